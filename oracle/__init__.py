@@ -1,0 +1,229 @@
+"""CPU oracle of the TPC CA + Kalman track finder -- TEST INFRASTRUCTURE.
+
+Plain, slow, obviously-correct reference (``oracle.cpp``, built with g++
+``-O2 -ffp-contract=off``).  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the product path
+never does.  It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpcca_oracle.so")
+NPAR = 36 + 36 + 36 * 64
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with g++ (no contraction, no fast-math)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", LIB_PATH + ".tmp", os.path.join(HERE, "oracle.cpp")]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_sectors", C.c_int32), ("n_rows", C.c_int32), ("row_x", C.POINTER(C.c_float)),
+                ("tan_half_angle", C.c_float), ("z_max", C.c_float), ("bz", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [("win_y", C.c_float), ("win_z", C.c_float), ("inv_var_y", C.c_float),
+                ("inv_var_z", C.c_float), ("link_cut", C.c_float), ("chi2_ext", C.c_float),
+                ("max_gap", C.c_int32), ("min_seed_hits", C.c_int32), ("min_hits", C.c_int32),
+                ("owned_num", C.c_int32), ("owned_den", C.c_int32), ("sin_max", C.c_float),
+                ("sigma_y", C.c_float), ("sigma_z", C.c_float), ("sigma_vertex", C.c_float),
+                ("sigma_tgl", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Result(C.Structure):
+    P64 = C.POINTER(C.c_int64)
+    _fields_ = [("n", C.c_int64), ("up", P64), ("dn", P64), ("cup", P64), ("cdn", P64),
+                ("n_starts", C.c_int64), ("starts", P64), ("n_seeds", C.c_int64),
+                ("seed_start", P64), ("seed_nhits", C.POINTER(C.c_int32)),
+                ("seed_key", C.POINTER(C.c_uint64)), ("seed_rlo", C.POINTER(C.c_int32)),
+                ("seed_rhi", C.POINTER(C.c_int32)), ("seed_hits", P64),
+                ("seed_state", C.POINTER(C.c_double)), ("n_tracks", C.c_int64),
+                ("trk_seed", P64), ("trk_sector", C.POINTER(C.c_int32)),
+                ("trk_xref", C.POINTER(C.c_double)), ("trk_p", C.POINTER(C.c_double)),
+                ("trk_cov", C.POINTER(C.c_double)), ("trk_chi2", C.POINTER(C.c_double)),
+                ("trk_ndf", C.POINTER(C.c_int32)), ("hit_off", P64), ("hit_ids", P64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_default_params.argtypes = [C.POINTER(Params)]
+        L.orc_transport.argtypes = [C.c_int, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    dp, dp, dp]
+        L.orc_transport.restype = C.c_int
+        L.orc_kf_update.argtypes = [C.c_int, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    dp, dp, dp]
+        L.orc_fit_hits.argtypes = [C.c_int, C.POINTER(Geometry), C.POINTER(Params), C.c_int32, dp, dp,
+                                   dp, C.c_double, dp, dp, dp]
+        L.orc_fit_hits.restype = C.c_int
+        L.orc_track.argtypes = [C.c_int, C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
+                                C.POINTER(C.c_int16), C.POINTER(C.c_uint8), C.POINTER(C.c_uint8),
+                                C.POINTER(C.POINTER(Result))]
+        L.orc_result_free.argtypes = [C.POINTER(Result)]
+        L.orc_calib_apply.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), dp, dp, dp,
+                                      dp, dp, dp]
+        L.orc_calib_chi2.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
+                                     C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64), dp, dp, C.POINTER(C.c_uint8), dp, dp,
+                                     C.POINTER(C.c_int64), dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct)) if a is not None else None
+
+
+def default_params() -> Params:
+    p = Params()
+    lib().orc_default_params(C.byref(p))
+    return p
+
+
+def make_geometry(geom):
+    """Geometry struct from a synth.Geometry; keeps the row table alive."""
+    rx = np.ascontiguousarray(geom.row_x, dtype=np.float32)
+    g = Geometry(geom.n_sectors, geom.n_rows, _ptr(rx, C.c_float), float(geom.tan_half_angle),
+                 float(geom.z_max), float(geom.bz))
+    g._keep = rx
+    return g
+
+
+def transport(p, cov, x0, x1, bz=0.5, sin_max=0.99, precision=64):
+    p = np.ascontiguousarray(p, dtype=np.float64); cov = np.ascontiguousarray(cov, dtype=np.float64)
+    op = np.zeros(5); oc = np.zeros(15); F = np.zeros(25)
+    ok = lib().orc_transport(precision, _ptr(p, C.c_double), _ptr(cov, C.c_double), x0, x1, bz,
+                             sin_max, _ptr(op, C.c_double), _ptr(oc, C.c_double), _ptr(F, C.c_double))
+    return bool(ok), op, oc, F.reshape(5, 5)
+
+
+def kf_update(p, cov, my, mz, vy, vz, precision=64):
+    p = np.ascontiguousarray(p, dtype=np.float64); cov = np.ascontiguousarray(cov, dtype=np.float64)
+    op = np.zeros(5); oc = np.zeros(15); c2 = C.c_double(0)
+    lib().orc_kf_update(precision, _ptr(p, C.c_double), _ptr(cov, C.c_double), my, mz, vy, vz,
+                        _ptr(op, C.c_double), _ptr(oc, C.c_double), C.byref(c2))
+    return op, oc, c2.value
+
+
+def fit_hits(geom, x, y, z, k0, params=None, precision=64):
+    g = make_geometry(geom)
+    P = params or default_params()
+    x = np.ascontiguousarray(x, dtype=np.float64); y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    p = np.zeros(5); cv = np.zeros(15); c2 = C.c_double(0)
+    ok = lib().orc_fit_hits(precision, C.byref(g), C.byref(P), len(x), _ptr(x, C.c_double),
+                            _ptr(y, C.c_double), _ptr(z, C.c_double), k0, _ptr(p, C.c_double),
+                            _ptr(cv, C.c_double), C.byref(c2))
+    return bool(ok), p, cv, c2.value
+
+
+def _arr(ptr, n, dtype):
+    if n == 0:
+        return np.zeros(0, dtype=dtype)
+    return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+
+def track(ev, precision=32, params=None, sector_mask=None, use64=False):
+    """Run the oracle pipeline on a synth.Event.  precision=32 rounds the
+    coordinates to FP32 and computes in FP32 (decision parity); 64 computes
+    in FP64 (from the FP64 coordinates if use64)."""
+    g = make_geometry(ev.geom)
+    P = params or default_params()
+    if use64:
+        x, y, z = ev.x64, ev.y64, ev.z64
+    else:
+        x, y, z = (ev.x.astype(np.float64), ev.y.astype(np.float64), ev.z.astype(np.float64))
+    x = np.ascontiguousarray(x); y = np.ascontiguousarray(y); z = np.ascontiguousarray(z)
+    row = np.ascontiguousarray(ev.row, dtype=np.int16)
+    sec = np.ascontiguousarray(ev.sector, dtype=np.uint8)
+    mask = None if sector_mask is None else np.ascontiguousarray(sector_mask, dtype=np.uint8)
+    out = C.POINTER(Result)()
+    lib().orc_track(precision, C.byref(g), C.byref(P), ev.n, _ptr(x, C.c_double), _ptr(y, C.c_double),
+                    _ptr(z, C.c_double), _ptr(row, C.c_int16), _ptr(sec, C.c_uint8),
+                    _ptr(mask, C.c_uint8) if mask is not None else None, C.byref(out))
+    r = out.contents
+    n, ns, nt, nr = r.n, r.n_seeds, r.n_tracks, ev.geom.n_rows
+    res = dict(
+        up=_arr(r.up, n, np.int64), dn=_arr(r.dn, n, np.int64),
+        cup=_arr(r.cup, n, np.int64), cdn=_arr(r.cdn, n, np.int64),
+        starts=_arr(r.starts, r.n_starts, np.int64),
+        seed_start=_arr(r.seed_start, ns, np.int64), seed_nhits=_arr(r.seed_nhits, ns, np.int32),
+        seed_key=_arr(r.seed_key, ns, np.uint64), seed_rlo=_arr(r.seed_rlo, ns, np.int32),
+        seed_rhi=_arr(r.seed_rhi, ns, np.int32),
+        seed_hits=_arr(r.seed_hits, ns * nr, np.int64).reshape(ns, nr),
+        seed_state=_arr(r.seed_state, ns * 20, np.float64).reshape(ns, 20),
+        trk_seed=_arr(r.trk_seed, nt, np.int64), sector=_arr(r.trk_sector, nt, np.int32),
+        x_ref=_arr(r.trk_xref, nt, np.float64), p=_arr(r.trk_p, 5 * nt, np.float64).reshape(nt, 5),
+        cov=_arr(r.trk_cov, 15 * nt, np.float64).reshape(nt, 15),
+        chi2=_arr(r.trk_chi2, nt, np.float64), ndf=_arr(r.trk_ndf, nt, np.int32),
+        hit_off=_arr(r.hit_off, nt + 1, np.int64), hit_ids=_arr(r.hit_ids, int(r.hit_off[nt]), np.int64),
+    )
+    lib().orc_result_free(out)
+    return res
+
+
+def calib_apply(ev_or_geom, sector, x, y, z, theta):
+    geom = getattr(ev_or_geom, 'geom', ev_or_geom)
+    g = make_geometry(geom)
+    sector = np.ascontiguousarray(sector, dtype=np.uint8)
+    x = np.ascontiguousarray(x, dtype=np.float64); y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    xo = np.zeros_like(x); zo = np.zeros_like(z)
+    lib().orc_calib_apply(C.byref(g), len(x), _ptr(sector, C.c_uint8), _ptr(x, C.c_double),
+                          _ptr(y, C.c_double), _ptr(z, C.c_double), _ptr(th, C.c_double),
+                          _ptr(xo, C.c_double), _ptr(zo, C.c_double))
+    return xo, zo
+
+
+def calib_chi2(geom, x, y, z, sector, hit_off, hit_ids, k0, theta, ext_tgl=None, use_vertex=None,
+               params=None, grad=False):
+    """Calibration objective chi2(theta) (and its exact FP64 gradient)."""
+    g = make_geometry(geom)
+    P = params or default_params()
+    x = np.ascontiguousarray(x, dtype=np.float64); y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    sector = np.ascontiguousarray(sector, dtype=np.uint8)
+    hit_off = np.ascontiguousarray(hit_off, dtype=np.int64)
+    hit_ids = np.ascontiguousarray(hit_ids, dtype=np.int64)
+    k0 = np.ascontiguousarray(k0, dtype=np.float64)
+    nt = len(hit_off) - 1
+    ext = None if ext_tgl is None else np.ascontiguousarray(ext_tgl, dtype=np.float64)
+    uv = None if use_vertex is None else np.ascontiguousarray(use_vertex, dtype=np.uint8)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    c2 = C.c_double(0); ndf = C.c_int64(0)
+    tc = np.zeros(nt)
+    gr = np.zeros(NPAR) if grad else None
+    lib().orc_calib_chi2(C.byref(g), C.byref(P), len(x), _ptr(x, C.c_double), _ptr(y, C.c_double),
+                         _ptr(z, C.c_double), _ptr(sector, C.c_uint8), nt, _ptr(hit_off, C.c_int64),
+                         _ptr(hit_ids, C.c_int64), _ptr(k0, C.c_double),
+                         _ptr(ext, C.c_double) if ext is not None else None,
+                         _ptr(uv, C.c_uint8) if uv is not None else None, _ptr(th, C.c_double),
+                         C.byref(c2), C.byref(ndf), _ptr(tc, C.c_double),
+                         _ptr(gr, C.c_double) if gr is not None else None)
+    if grad:
+        return c2.value, ndf.value, tc, gr
+    return c2.value, ndf.value, tc

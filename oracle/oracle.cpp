@@ -1,0 +1,865 @@
+// oracle.cpp -- plain CPU oracle of the per-sector TPC track finder.
+//
+// TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked
+// against.  It shares no code with the GPU path.  Linear scans over row
+// lists, no grids, no blocking, one tracklet at a time.
+//
+// The paper (Sec. "Track reconstruction in the TPC") fixes the structure:
+// cellular-automaton seeding of short chains of hits, then Kalman-filter
+// fitting and following, sectors processed independently, one worker per
+// cluster (seeding) and per track (following).  It states no constant and no
+// rule beyond that; every rule below is a reading, listed in the design
+// notes with its pin.  Units: cm, tesla, GeV.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no fast-math;
+// FP32 expressions are evaluated exactly as written, IEEE round-to-nearest).
+#include "tpcca_oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Reverse-mode tape scalar (FP64).  Every operation records its local
+// partial derivatives; backprop() accumulates adjoints in reverse order.
+struct Tape {
+  struct Node { int a, b; double da, db; };
+  std::vector<Node> nodes;
+  std::vector<double> adj;
+  int add(int a, double da, int b, double db) {
+    if (a < 0 && b < 0) return -1;
+    nodes.push_back({a, b, da, db});
+    return (int)nodes.size() - 1;
+  }
+  int leaf() { nodes.push_back({-1, -1, 0.0, 0.0}); return (int)nodes.size() - 1; }
+  void backprop(int out) {
+    adj.assign(nodes.size(), 0.0);
+    if (out < 0) return;
+    adj[out] = 1.0;
+    for (int i = out; i >= 0; --i) {
+      const Node& n = nodes[i];
+      if (adj[i] == 0.0) continue;
+      if (n.a >= 0) adj[n.a] += n.da * adj[i];
+      if (n.b >= 0) adj[n.b] += n.db * adj[i];
+    }
+  }
+  void clear() { nodes.clear(); adj.clear(); }
+};
+Tape* g_tape = nullptr;
+
+struct Var {
+  double v; int i;
+  Var() : v(0.0), i(-1) {}
+  Var(double x) : v(x), i(-1) {}                 // NOLINT: constants convert implicitly
+  static Var leaf(double x) { Var r(x); r.i = g_tape->leaf(); return r; }
+};
+inline Var mk(double v, int a, double da, int b, double db) {
+  Var r(v); r.i = g_tape ? g_tape->add(a, da, b, db) : -1; return r;
+}
+inline Var operator+(Var a, Var b) { return mk(a.v + b.v, a.i, 1.0, b.i, 1.0); }
+inline Var operator-(Var a, Var b) { return mk(a.v - b.v, a.i, 1.0, b.i, -1.0); }
+inline Var operator-(Var a) { return mk(-a.v, a.i, -1.0, -1, 0.0); }
+inline Var operator*(Var a, Var b) { return mk(a.v * b.v, a.i, b.v, b.i, a.v); }
+inline Var operator/(Var a, Var b) { double q = a.v / b.v; return mk(q, a.i, 1.0 / b.v, b.i, -q / b.v); }
+inline bool operator<(Var a, Var b) { return a.v < b.v; }
+inline bool operator<=(Var a, Var b) { return a.v <= b.v; }
+inline bool operator>(Var a, Var b) { return a.v > b.v; }
+inline bool operator==(Var a, Var b) { return a.v == b.v; }
+inline bool operator!=(Var a, Var b) { return a.v != b.v; }
+
+inline float Sqrt(float x) { return std::sqrt(x); }
+inline double Sqrt(double x) { return std::sqrt(x); }
+inline Var Sqrt(Var x) { double s = std::sqrt(x.v); return mk(s, x.i, 0.5 / s, -1, 0.0); }
+inline float Abs(float x) { return std::fabs(x); }
+inline double Abs(double x) { return std::fabs(x); }
+inline Var Abs(Var x) { return x.v < 0 ? -x : x; }
+inline double val(float x) { return x; }
+inline double val(double x) { return x; }
+inline double val(Var x) { return x.v; }
+
+// ---------------------------------------------------------------------------
+// Packed symmetric 5x5 covariance, upper triangle row by row.
+inline int ix(int i, int j) {
+  if (i > j) std::swap(i, j);
+  static const int base[5] = {0, 5, 9, 12, 14};
+  return base[i] + (j - i);
+}
+
+template <class R> struct Model {
+  R kfac;        // curvature per unit q/pT: -c * Bz
+  R sin_max;
+  R vy, vz;      // measurement variances
+};
+
+template <class R> Model<R> make_model(const orc_geometry& g, const orc_params& P) {
+  Model<R> m;
+  m.kfac = -R((double)2.99792458e-3) * R(g.bz);
+  m.sin_max = R(P.sin_max);
+  m.vy = R(P.sigma_y) * R(P.sigma_y);
+  m.vz = R(P.sigma_z) * R(P.sigma_z);
+  return m;
+}
+
+// Transport of state p = (y, z, s = sin phi, t = tan lambda, k = q/pT) from
+// the plane x0 to the plane x1 along a helix in a uniform field.  With the
+// signed curvature kap = kfac * k: s1 = s0 + kap*dx; the transverse chord
+// rises by dy = dx * (s0 + s1)/(c0 + c1) (tangent of the mean direction,
+// exact for a circle); the transverse arc is d * asin(u)/u with d the chord
+// length carrying the sign of dx (inward steps have negative path length)
+// and u = kap*d/2, asin(u)/u taken as its Maclaurin series to u^8; z
+// advances by t times the arc.  F is the exact Jacobian of these formulas;
+// the covariance becomes F C F^T (no process noise: no material).
+template <class R>
+bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr) {
+  R dx = x1 - x0;
+  if (dx == R(0.0)) {
+    if (Fout) { for (int i = 0; i < 25; ++i) Fout[i] = R(0.0); for (int i = 0; i < 5; ++i) Fout[i * 6] = R(1.0); }
+    return true;
+  }
+  const R A1 = R(1.0) / R(6.0), A2 = R(3.0) / R(40.0), A3 = R(5.0) / R(112.0), A4 = R(35.0) / R(1152.0);
+  const R B1 = R(1.0) / R(3.0), B2 = R(3.0) / R(10.0), B3 = R(15.0) / R(56.0), B4 = R(35.0) / R(144.0);
+  R kap = m.kfac * p[4];
+  R s0 = p[2];
+  R f = m.kfac * dx;                      // d s1 / d k
+  R s1 = s0 + kap * dx;
+  if (!(Abs(s1) < m.sin_max)) return false;
+  R c0 = Sqrt(R(1.0) - s0 * s0);
+  R c1 = Sqrt(R(1.0) - s1 * s1);
+  R ss = s0 + s1;
+  R cc = c0 + c1;
+  R tn = ss / cc;
+  R dy = dx * tn;
+  R d = Sqrt(dx * dx + dy * dy);          // chord length, signed like dx
+  if (dx < R(0.0)) d = -d;
+  R u = (kap * d) * R(0.5);
+  R u2 = u * u;
+  R g = R(1.0) + u2 * (A1 + u2 * (A2 + u2 * (A3 + u2 * A4)));
+  R gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));   // d(asin(u)/u)/du
+  R l = d * g;
+  R t0 = s0 / c0;
+  R t1 = s1 / c1;
+  R dtn_ds = (R(2.0) + tn * (t0 + t1)) / cc;
+  R dtn_dk = (f * (R(1.0) + tn * t1)) / cc;
+  R a = dx * dtn_ds;                       // d dy / d s0
+  R b = dx * dtn_dk;                       // d dy / d k
+  R dd_ds = (dy * a) / d;
+  R dd_dk = (dy * b) / d;
+  R du_ds = (kap * dd_ds) * R(0.5);
+  R du_dk = (m.kfac * d + kap * dd_dk) * R(0.5);
+  R dl_ds = dd_ds * g + (d * gp) * du_ds;
+  R dl_dk = dd_dk * g + (d * gp) * du_dk;
+  R t = p[3];
+  R c = t * dl_ds;                         // d z1 / d s0
+  R e = t * dl_dk;                         // d z1 / d k
+  p[0] = p[0] + dy;
+  p[1] = p[1] + t * l;
+  p[2] = s1;
+  // F = [[1,0,a,0,b],[0,1,c,l,e],[0,0,1,0,f],[0,0,0,1,0],[0,0,0,0,1]]
+  R C00 = C[0], C01 = C[1], C02 = C[2], C03 = C[3], C04 = C[4];
+  R C11 = C[5], C12 = C[6], C13 = C[7], C14 = C[8];
+  R C22 = C[9], C23 = C[10], C24 = C[11];
+  R C33 = C[12], C34 = C[13], C44 = C[14];
+  // T = F C (rows 0, 1, 2; rows 3 and 4 equal those of C)
+  R T00 = C00 + a * C02 + b * C04;
+  R T01 = C01 + a * C12 + b * C14;
+  R T02 = C02 + a * C22 + b * C24;
+  R T03 = C03 + a * C23 + b * C34;
+  R T04 = C04 + a * C24 + b * C44;
+  R T11 = C11 + c * C12 + l * C13 + e * C14;
+  R T12 = C12 + c * C22 + l * C23 + e * C24;
+  R T13 = C13 + c * C23 + l * C33 + e * C34;
+  R T14 = C14 + c * C24 + l * C34 + e * C44;
+  R T22 = C22 + f * C24;
+  R T23 = C23 + f * C34;
+  R T24 = C24 + f * C44;
+  // C' = T F^T
+  C[0] = T00 + a * T02 + b * T04;
+  C[1] = T01 + c * T02 + l * T03 + e * T04;
+  C[2] = T02 + f * T04;
+  C[3] = T03;
+  C[4] = T04;
+  C[5] = T11 + c * T12 + l * T13 + e * T14;
+  C[6] = T12 + f * T14;
+  C[7] = T13;
+  C[8] = T14;
+  C[9] = T22 + f * T24;
+  C[10] = T23;
+  C[11] = T24;
+  // C33, C34, C44 unchanged
+  if (Fout) {
+    for (int i = 0; i < 25; ++i) Fout[i] = R(0.0);
+    for (int i = 0; i < 5; ++i) Fout[i * 6] = R(1.0);
+    Fout[2] = a; Fout[4] = b; Fout[7] = c; Fout[8] = l; Fout[9] = e; Fout[14] = f;
+  }
+  return true;
+}
+
+// Kalman update with a (y, z) measurement, H = [I2 0], V = diag(vy, vz).
+template <class R>
+void kf_update(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
+  R r0 = my - p[0];
+  R r1 = mz - p[1];
+  R S00 = C[0] + vy;
+  R S01 = C[1];
+  R S11 = C[5] + vz;
+  R det = S00 * S11 - S01 * S01;
+  R I00 = S11 / det;
+  R I01 = (-S01) / det;
+  R I11 = S00 / det;
+  R row0[5], row1[5];
+  for (int j = 0; j < 5; ++j) { row0[j] = C[ix(0, j)]; row1[j] = C[ix(1, j)]; }
+  R K0[5], K1[5];
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = row0[i] * I00 + row1[i] * I01;
+    K1[i] = row0[i] * I01 + row1[i] * I11;
+  }
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+  for (int i = 0; i < 5; ++i)
+    for (int j = i; j < 5; ++j) C[ix(i, j)] = C[ix(i, j)] - (K0[i] * row0[j] + K1[i] * row1[j]);
+  chi2 = chi2 + (r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
+}
+
+// Kalman update with a scalar measurement of state component q.
+template <class R>
+void kf_update1(R p[5], R C[15], int q, R m, R v, R& chi2) {
+  R S = C[ix(q, q)] + v;
+  R rowq[5];
+  for (int j = 0; j < 5; ++j) rowq[j] = C[ix(q, j)];
+  R r = m - p[q];
+  R K[5];
+  for (int i = 0; i < 5; ++i) K[i] = rowq[i] / S;
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + K[i] * r;
+  for (int i = 0; i < 5; ++i)
+    for (int j = i; j < 5; ++j) C[ix(i, j)] = C[ix(i, j)] - K[i] * rowq[j];
+  chi2 = chi2 + (r * r) / S;
+}
+
+template <class R> void init_cov(R C[15], const orc_params& P) {
+  for (int i = 0; i < 15; ++i) C[i] = R(0.0);
+  C[0] = R(P.sigma_y) * R(P.sigma_y);
+  C[5] = R(P.sigma_z) * R(P.sigma_z);
+  C[9] = R(0.25);
+  C[12] = R(0.25);
+  C[14] = R(100.0);
+}
+
+// Direction from the chord between an inner hit (xi,yi,zi) and an outer hit
+// (xo,yo,zo): s = dy/rho, t = dz/rho with rho the transverse chord length.
+template <class R>
+void chord_dir(R xi, R yi, R zi, R xo, R yo, R zo, R& s, R& t) {
+  R dX = xo - xi, dY = yo - yi, dZ = zo - zi;
+  R rho = Sqrt(dX * dX + dY * dY);
+  s = dY / rho;
+  t = dZ / rho;
+}
+
+// Final fit of an ordered hit list (outermost first): state initialised at
+// the outermost hit, direction from the chord to the hit two positions
+// inward, q/pT from the prior k0; then transport + update hit by hit.
+template <class R>
+bool fit_hits(const Model<R>& m, const orc_params& P, int n, const R* x, const R* y, const R* z,
+              R k0, R p[5], R C[15], R& chi2, R& xcur) {
+  if (n < 3) return false;
+  R s, t;
+  chord_dir(x[2], y[2], z[2], x[0], y[0], z[0], s, t);
+  p[0] = y[0]; p[1] = z[0]; p[2] = s; p[3] = t; p[4] = k0;
+  init_cov(C, P);
+  chi2 = R(0.0);
+  if (!(Abs(s) < m.sin_max)) return false;
+  xcur = x[0];
+  for (int h = 1; h < n; ++h) {
+    if (!transport(p, C, xcur, x[h], m)) return false;
+    kf_update(p, C, y[h], z[h], m.vy, m.vz, chi2);
+    xcur = x[h];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// The per-sector pipeline.
+template <class R> struct Pipeline {
+  const orc_geometry& g;
+  const orc_params& P;
+  Model<R> m;
+  int64_t n;
+  std::vector<R> x, y, z;
+  std::vector<int> row, sec;
+  std::vector<R> X;                               // row planes
+  std::vector<std::vector<int64_t>> rows;         // ids per (sector,row), ascending id
+  std::vector<int64_t> up, dn, cup, cdn;
+
+  Pipeline(const orc_geometry& g_, const orc_params& P_) : g(g_), P(P_), m(make_model<R>(g_, P_)) {}
+
+  int ru(int s, int r) const { return s * g.n_rows + r; }
+
+  // Neighbour finding for a middle cluster i on row r (1 <= r <= n_rows-2):
+  // among down candidates d on row r-1 and up candidates u on row r+1 inside
+  // the (y, z) windows, the pair whose middle point deviates least from the
+  // straight chord d-u.  Score = ey^2/(1.5 sy^2) + ez^2/(1.5 sz^2) with
+  // (ey, ez) the deviation of i from the chord at x_i; accepted iff <= cut;
+  // ties broken by smaller up id, then smaller down id.
+  void find_neighbours(int64_t i) {
+    int s = sec[i], r = row[i];
+    up[i] = dn[i] = -1;
+    if (r < 1 || r > g.n_rows - 2) return;
+    const R WY = R(P.win_y), WZ = R(P.win_z), IWY = R(P.inv_var_y), IWZ = R(P.inv_var_z), CUT = R(P.link_cut);
+    bool have = false;
+    R bs = R(0.0);
+    int64_t bu = -1, bd = -1;
+    for (int64_t d : rows[ru(s, r - 1)]) {
+      if (!(Abs(y[d] - y[i]) <= WY && Abs(z[d] - z[i]) <= WZ)) continue;
+      for (int64_t u : rows[ru(s, r + 1)]) {
+        if (!(Abs(y[u] - y[i]) <= WY && Abs(z[u] - z[i]) <= WZ)) continue;
+        R w = (x[i] - x[d]) / (x[u] - x[d]);
+        R ey = y[i] - (y[d] + (y[u] - y[d]) * w);
+        R ez = z[i] - (z[d] + (z[u] - z[d]) * w);
+        R score = (ey * ey) * IWY + (ez * ez) * IWZ;
+        if (!(score <= CUT)) continue;
+        bool better = !have || score < bs || (score == bs && (u < bu || (u == bu && d < bd)));
+        if (better) { have = true; bs = score; bu = u; bd = d; }
+      }
+    }
+    if (have) { up[i] = bu; dn[i] = bd; }
+  }
+
+  // Search row r of sector s for the cluster closest to the predicted
+  // (y, z): d = dy^2/(Cyy+sy^2) + dz^2/(Czz+sz^2) <= chi2_ext, minimum
+  // (d, id).  Returns -1 if none.
+  int64_t search(int s, int r, const R p[5], const R C[15]) const {
+    R sy2 = C[0] + m.vy, sz2 = C[5] + m.vz;
+    R isy = R(1.0) / sy2, isz = R(1.0) / sz2;
+    const R CUT = R(P.chi2_ext);
+    int64_t best = -1;
+    R bd = R(0.0);
+    for (int64_t h : rows[ru(s, r)]) {
+      R dY = y[h] - p[0], dZ = z[h] - p[1];
+      R d = (dY * dY) * isy + (dZ * dZ) * isz;
+      if (!(d <= CUT)) continue;
+      if (best < 0 || d < bd || (d == bd && h < best)) { best = h; bd = d; }
+    }
+    return best;
+  }
+
+  bool accepted_here(int r, const R p[5]) const {
+    R lim = X[r] * R(g.tan_half_angle);
+    return !(Abs(p[0]) > lim || Abs(p[1]) > R(g.z_max));
+  }
+
+  struct Tracklet {
+    int64_t start = -1;
+    int32_t nhits = 0, rlo = 0, rhi = 0;
+    uint64_t key = 0;
+    std::vector<int64_t> hits;
+    R p[5], C[15];
+  };
+
+  // One following step on row r (used by both directions).  Returns false
+  // when following must stop.
+  bool follow_row(int s, int r, R p[5], R C[15], R& xc, int& rstate, Tracklet& T, int& gap,
+                  bool& wrote) {
+    wrote = false;
+    if (!transport(p, C, xc, X[r], m)) return false;
+    xc = X[r];
+    rstate = r;
+    if (!accepted_here(r, p)) return false;
+    int64_t h = search(s, r, p, C);
+    if (h >= 0) {
+      if (x[h] != X[r]) {
+        if (!transport(p, C, X[r], x[h], m)) return false;
+        xc = x[h];
+      }
+      R dummy = R(0.0);
+      kf_update(p, C, y[h], z[h], m.vy, m.vz, dummy);
+      T.hits[r] = h;
+      T.nhits++;
+      gap = 0;
+    } else {
+      T.hits[r] = -1;
+      gap++;
+    }
+    wrote = true;
+    return gap <= P.max_gap;
+  }
+
+  // Tracklet construction from a chain head (one independent unit).
+  Tracklet build(int64_t head) {
+    Tracklet T;
+    T.start = head;
+    T.hits.assign(g.n_rows, -1);
+    std::vector<int64_t> chain;
+    for (int64_t h = head; h >= 0; h = cup[h]) chain.push_back(h);
+    int s = sec[head], r0 = row[head];
+    T.rlo = T.rhi = r0;
+    // seed: position at the head, direction from the chord to the second successor
+    R p[5], C[15];
+    R sdir, tdir;
+    int64_t h0 = chain[0], h2 = chain[2];
+    chord_dir(x[h0], y[h0], z[h0], x[h2], y[h2], z[h2], sdir, tdir);
+    p[0] = y[h0]; p[1] = z[h0]; p[2] = sdir; p[3] = tdir; p[4] = R(0.0);
+    init_cov(C, P);
+    for (int i = 0; i < 5; ++i) T.p[i] = p[i];
+    for (int i = 0; i < 15; ++i) T.C[i] = C[i];
+    if (!(Abs(sdir) < m.sin_max)) { T.nhits = 0; return T; }
+    T.hits[r0] = h0;
+    T.nhits = 1;
+    R xc = x[h0];
+    R dummy = R(0.0);
+    for (size_t j = 1; j < chain.size(); ++j) {
+      int64_t h = chain[j];
+      if (!transport(p, C, xc, x[h], m)) { T.nhits = 0; T.hits.assign(g.n_rows, -1); return T; }
+      kf_update(p, C, y[h], z[h], m.vy, m.vz, dummy);
+      T.hits[row[h]] = h;
+      T.nhits++;
+      xc = x[h];
+    }
+    int rstate = row[chain.back()];
+    T.rhi = rstate;
+    // upward following
+    int gap = 0;
+    for (int r = rstate + 1; r < g.n_rows; ++r) {
+      bool wrote;
+      bool go = follow_row(s, r, p, C, xc, rstate, T, gap, wrote);
+      if (wrote) T.rhi = r;
+      if (!go) break;
+    }
+    // back to the head row without updates, then downward following
+    bool ok = true;
+    for (int r = rstate - 1; r >= r0; --r) {
+      if (!transport(p, C, xc, X[r], m)) { ok = false; break; }
+      xc = X[r];
+    }
+    if (ok) {
+      gap = 0;
+      int rs = r0;
+      for (int r = r0 - 1; r >= 0; --r) {
+        bool wrote;
+        bool go = follow_row(s, r, p, C, xc, rs, T, gap, wrote);
+        if (wrote) T.rlo = r;
+        if (!go) break;
+      }
+    }
+    for (int i = 0; i < 5; ++i) T.p[i] = p[i];
+    for (int i = 0; i < 15; ++i) T.C[i] = C[i];
+    // selection key: more hits first, then the lower start row, then the
+    // smaller start id (the start row makes equal-length tracklets grown from
+    // different chains of one track independent of the input order)
+    T.key = ((uint64_t)(uint32_t)T.nhits << 40) | ((uint64_t)(255 - r0) << 32) |
+            (uint64_t)(0xFFFFFFFFu - (uint32_t)head);
+    return T;
+  }
+};
+
+template <class R>
+orc_result* run_pipeline(const orc_geometry& g, const orc_params& P, int64_t n, const double* xin,
+                         const double* yin, const double* zin, const int16_t* rowin,
+                         const uint8_t* secin, const uint8_t* mask) {
+  Pipeline<R> pl(g, P);
+  pl.n = n;
+  pl.x.resize(n); pl.y.resize(n); pl.z.resize(n); pl.row.resize(n); pl.sec.resize(n);
+  pl.X.resize(g.n_rows);
+  for (int r = 0; r < g.n_rows; ++r) pl.X[r] = R(g.row_x[r]);
+  pl.rows.assign((size_t)g.n_sectors * g.n_rows, {});
+  for (int64_t i = 0; i < n; ++i) {
+    pl.x[i] = R(xin[i]); pl.y[i] = R(yin[i]); pl.z[i] = R(zin[i]);
+    pl.row[i] = rowin[i]; pl.sec[i] = secin[i];
+    if (mask && !mask[secin[i]]) continue;
+    pl.rows[pl.ru(secin[i], rowin[i])].push_back(i);        // ascending id by construction
+  }
+  pl.up.assign(n, -1); pl.dn.assign(n, -1); pl.cup.assign(n, -1); pl.cdn.assign(n, -1);
+  auto active = [&](int64_t i) { return !mask || mask[pl.sec[i]]; };
+  for (int64_t i = 0; i < n; ++i) if (active(i)) pl.find_neighbours(i);
+  // link cleaning: keep a link only if it is reciprocated (from the raw arrays)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t u = pl.up[i], d = pl.dn[i];
+    pl.cup[i] = (u >= 0 && pl.dn[u] == i) ? u : -1;
+    pl.cdn[i] = (d >= 0 && pl.up[d] == i) ? d : -1;
+  }
+  // start hits in (sector, row, id) order
+  std::vector<int64_t> starts;
+  for (const auto& lst : pl.rows)
+    for (int64_t i : lst)
+      if (pl.cup[i] >= 0 && pl.cdn[i] < 0) starts.push_back(i);
+  // seeds = heads of chains of at least min_seed_hits
+  std::vector<typename Pipeline<R>::Tracklet> tl;
+  for (int64_t h : starts) {
+    int L = 0;
+    for (int64_t q = h; q >= 0; q = pl.cup[q]) ++L;
+    if (L < P.min_seed_hits) continue;
+    tl.push_back(pl.build(h));
+  }
+  // selection: owner(h) = max key over the valid tracklets containing h
+  std::vector<uint64_t> owner(n, 0);
+  for (auto& T : tl) {
+    if (T.nhits < P.min_hits) continue;
+    for (int r = 0; r < g.n_rows; ++r) {
+      int64_t h = T.hits[r];
+      if (h >= 0) owner[h] = std::max(owner[h], T.key);
+    }
+  }
+  orc_result* res = (orc_result*)std::calloc(1, sizeof(orc_result));
+  res->n = n;
+  auto cp64 = [](const std::vector<int64_t>& v) {
+    int64_t* p = (int64_t*)std::malloc(sizeof(int64_t) * (v.size() + 1));
+    if (!v.empty()) std::memcpy(p, v.data(), sizeof(int64_t) * v.size());
+    return p;
+  };
+  res->up = cp64(pl.up); res->dn = cp64(pl.dn); res->cup = cp64(pl.cup); res->cdn = cp64(pl.cdn);
+  res->n_starts = (int64_t)starts.size(); res->starts = cp64(starts);
+  int64_t ns = (int64_t)tl.size();
+  res->n_seeds = ns;
+  res->seed_start = (int64_t*)std::malloc(sizeof(int64_t) * (ns + 1));
+  res->seed_nhits = (int32_t*)std::malloc(sizeof(int32_t) * (ns + 1));
+  res->seed_key = (uint64_t*)std::malloc(sizeof(uint64_t) * (ns + 1));
+  res->seed_rlo = (int32_t*)std::malloc(sizeof(int32_t) * (ns + 1));
+  res->seed_rhi = (int32_t*)std::malloc(sizeof(int32_t) * (ns + 1));
+  res->seed_hits = (int64_t*)std::malloc(sizeof(int64_t) * (ns * g.n_rows + 1));
+  res->seed_state = (double*)std::malloc(sizeof(double) * (ns * 20 + 1));
+  for (int64_t k = 0; k < ns; ++k) {
+    auto& T = tl[k];
+    res->seed_start[k] = T.start; res->seed_nhits[k] = T.nhits; res->seed_key[k] = T.key;
+    res->seed_rlo[k] = T.rlo; res->seed_rhi[k] = T.rhi;
+    for (int r = 0; r < g.n_rows; ++r) res->seed_hits[k * g.n_rows + r] = T.hits[r];
+    for (int i = 0; i < 5; ++i) res->seed_state[k * 20 + i] = val(T.p[i]);
+    for (int i = 0; i < 15; ++i) res->seed_state[k * 20 + 5 + i] = val(T.C[i]);
+  }
+  // acceptance and final fit
+  std::vector<int64_t> tseed, hoff{0}, hids;
+  std::vector<int32_t> tsec, tndf;
+  std::vector<double> txref, tp, tcov, tchi2;
+  for (int64_t k = 0; k < ns; ++k) {
+    auto& T = tl[k];
+    if (T.nhits < P.min_hits) continue;
+    std::vector<int64_t> own;                      // outermost first
+    for (int r = g.n_rows - 1; r >= 0; --r) {
+      int64_t h = T.hits[r];
+      if (h >= 0 && owner[h] == T.key) own.push_back(h);
+    }
+    int no = (int)own.size();
+    if (!(no >= P.min_hits && (int64_t)P.owned_den * no >= (int64_t)P.owned_num * T.nhits)) continue;
+    std::vector<R> hx(no), hy(no), hz(no);
+    for (int j = 0; j < no; ++j) { hx[j] = pl.x[own[j]]; hy[j] = pl.y[own[j]]; hz[j] = pl.z[own[j]]; }
+    R p[5], C[15], chi2, xcur;
+    if (!fit_hits(pl.m, P, no, hx.data(), hy.data(), hz.data(), T.p[4], p, C, chi2, xcur)) continue;
+    tseed.push_back(k);
+    tsec.push_back(pl.sec[T.start]);
+    txref.push_back(val(xcur));
+    for (int i = 0; i < 5; ++i) tp.push_back(val(p[i]));
+    for (int i = 0; i < 15; ++i) tcov.push_back(val(C[i]));
+    tchi2.push_back(val(chi2));
+    tndf.push_back(2 * no - 5);
+    for (int j = no - 1; j >= 0; --j) hids.push_back(own[j]);   // ascending row
+    hoff.push_back((int64_t)hids.size());
+  }
+  int64_t nt = (int64_t)tseed.size();
+  res->n_tracks = nt;
+  res->trk_seed = cp64(tseed);
+  res->trk_sector = (int32_t*)std::malloc(sizeof(int32_t) * (nt + 1));
+  res->trk_ndf = (int32_t*)std::malloc(sizeof(int32_t) * (nt + 1));
+  res->trk_xref = (double*)std::malloc(sizeof(double) * (nt + 1));
+  res->trk_chi2 = (double*)std::malloc(sizeof(double) * (nt + 1));
+  res->trk_p = (double*)std::malloc(sizeof(double) * (5 * nt + 1));
+  res->trk_cov = (double*)std::malloc(sizeof(double) * (15 * nt + 1));
+  for (int64_t t = 0; t < nt; ++t) {
+    res->trk_sector[t] = tsec[t]; res->trk_ndf[t] = tndf[t];
+    res->trk_xref[t] = txref[t]; res->trk_chi2[t] = tchi2[t];
+  }
+  if (nt) {
+    std::memcpy(res->trk_p, tp.data(), sizeof(double) * 5 * nt);
+    std::memcpy(res->trk_cov, tcov.data(), sizeof(double) * 15 * nt);
+  }
+  res->hit_off = cp64(hoff);
+  res->hit_ids = cp64(hids);
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// Calibration correction (applied to default-transformed clusters):
+//  drift: with side = +1 for A-side sectors (first half), -1 otherwise,
+//         side*z' = L - (1 + delta_s) * (L - side*z - tau_s);
+//  radial: x' = x + sum_ab c[s][a][b] B_a(xh) B_b(uh) with xh = (x - x_first)
+//         / (x_last - x_first), uh = (y/x + tanA)/(2 tanA), both clamped to
+//         [0, 1] and evaluated at the uncorrected (x, y).
+// B_a: the 8 clamped uniform cubic B-splines (knots 0,0,0,0,.2,.4,.6,.8,1,1,1,1).
+void bspline8(double u, double B[8]) {
+  static const double t[12] = {0, 0, 0, 0, 0.2, 0.4, 0.6, 0.8, 1, 1, 1, 1};
+  if (u < 0.0) u = 0.0;
+  if (u > 1.0) u = 1.0;
+  double N[11];
+  for (int i = 0; i < 11; ++i) N[i] = (t[i] <= u && u < t[i + 1]) ? 1.0 : 0.0;
+  if (u >= 1.0) N[7] = 1.0;
+  for (int p = 1; p <= 3; ++p) {
+    for (int i = 0; i < 11 - p; ++i) {
+      double a = (t[i + p] > t[i]) ? (u - t[i]) / (t[i + p] - t[i]) : 0.0;
+      double b = (t[i + p + 1] > t[i + 1]) ? (t[i + p + 1] - u) / (t[i + p + 1] - t[i + 1]) : 0.0;
+      N[i] = a * N[i] + b * N[i + 1];
+    }
+  }
+  for (int i = 0; i < 8; ++i) B[i] = N[i];
+}
+
+template <class R>
+void calib_point(const orc_geometry& g, int s, double x, double y, double z, const R* th, R& xo,
+                 R& zo) {
+  int half = g.n_sectors / 2;
+  double side = s < half ? 1.0 : -1.0;
+  double L = g.z_max;
+  const R& dl = th[s];
+  const R& tau = th[g.n_sectors + s];
+  zo = R(side) * (R(L) - (R(1.0) + dl) * (R(L - side * z) - tau));
+  double x0 = g.row_x[0], x1 = g.row_x[g.n_rows - 1];
+  double ta = g.tan_half_angle;
+  double Ba[8], Bb[8];
+  bspline8((x - x0) / (x1 - x0), Ba);
+  bspline8((y / x + ta) / (2.0 * ta), Bb);
+  const R* c = th + 2 * g.n_sectors + (size_t)s * 64;
+  R acc = R(x);
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b) {
+      double w = Ba[a] * Bb[b];
+      if (w != 0.0) acc = acc + c[a * 8 + b] * R(w);
+    }
+  xo = acc;
+}
+
+// Calibration objective of one track (see orc_calib_chi2).
+// Returns 0 if the hit fit fails, 1 if only the hits were used (vertex terms
+// off, or the transport to the beam axis left the sin(phi) range), 2 if the
+// vertex (and, if enabled, the external tan(lambda)) were added.
+template <class R>
+int track_objective(const orc_geometry& g, const orc_params& P, const Model<R>& m, int nh,
+                    const R* hx, const R* hy, const R* hz, R k0, bool use_vtx, bool use_ext,
+                    R ext_tgl, R& chi2) {
+  (void)g;
+  R p[5], C[15], xcur;
+  if (!fit_hits(m, P, nh, hx, hy, hz, k0, p, C, chi2, xcur)) return 0;
+  if (!use_vtx) return 1;
+  // sub-stepped transport to the beam axis at x = 0 (planes at multiples of 10 cm)
+  R q[5], Q[15];
+  for (int i = 0; i < 5; ++i) q[i] = p[i];
+  for (int i = 0; i < 15; ++i) Q[i] = C[i];
+  int mstep = (int)std::ceil(val(xcur) / 10.0) - 1;
+  R xc = xcur;
+  for (int k = mstep; k >= 0; --k) {
+    R xt = R(10.0 * k);
+    if (!transport(q, Q, xc, xt, m)) return 1;         // vertex terms skipped
+    xc = xt;
+  }
+  R sv2 = R(P.sigma_vertex) * R(P.sigma_vertex);
+  kf_update(q, Q, R(0.0), R(0.0), sv2, sv2, chi2);
+  if (use_ext) kf_update1(q, Q, 3, ext_tgl, R(P.sigma_tgl) * R(P.sigma_tgl), chi2);
+  return 2;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+void orc_default_params(orc_params* p) {
+  p->win_y = 2.0f;
+  p->win_z = 2.2f;
+  p->inv_var_y = (float)(1.0 / (1.5 * 0.1 * 0.1));
+  p->inv_var_z = (float)(1.0 / (1.5 * 0.15 * 0.15));
+  p->link_cut = 16.0f;
+  p->chi2_ext = 9.0f;
+  p->max_gap = 8;
+  p->min_seed_hits = 5;
+  p->min_hits = 10;
+  p->owned_num = 9;
+  p->owned_den = 10;
+  p->sin_max = 0.99f;
+  p->sigma_y = 0.1f;
+  p->sigma_z = 0.15f;
+  p->sigma_vertex = 0.01f;
+  p->sigma_tgl = 1e-3f;
+}
+
+int orc_transport(int precision, const double pin[5], const double Cin[15], double x0, double x1,
+                  double bz, double sin_max, double out_p[5], double out_C[15], double F[25]) {
+  orc_geometry g{};
+  g.bz = (float)bz;
+  orc_params P;
+  orc_default_params(&P);
+  P.sin_max = (float)sin_max;
+  if (precision == 32) {
+    Model<float> m = make_model<float>(g, P);
+    m.sin_max = (float)sin_max;
+    float p[5], C[15], Fl[25];
+    for (int i = 0; i < 5; ++i) p[i] = (float)pin[i];
+    for (int i = 0; i < 15; ++i) C[i] = (float)Cin[i];
+    if (!transport<float>(p, C, (float)x0, (float)x1, m, Fl)) return 0;
+    for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+    for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+    if (F) for (int i = 0; i < 25; ++i) F[i] = Fl[i];
+    return 1;
+  }
+  Model<double> m;
+  m.kfac = -2.99792458e-3 * bz;
+  m.sin_max = sin_max;
+  double p[5], C[15], Fl[25];
+  for (int i = 0; i < 5; ++i) p[i] = pin[i];
+  for (int i = 0; i < 15; ++i) C[i] = Cin[i];
+  if (!transport<double>(p, C, x0, x1, m, Fl)) return 0;
+  for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+  for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+  if (F) for (int i = 0; i < 25; ++i) F[i] = Fl[i];
+  return 1;
+}
+
+void orc_kf_update(int precision, const double pin[5], const double Cin[15], double my, double mz,
+                   double vy, double vz, double out_p[5], double out_C[15], double* dchi2) {
+  if (precision == 32) {
+    float p[5], C[15], c2 = 0.0f;
+    for (int i = 0; i < 5; ++i) p[i] = (float)pin[i];
+    for (int i = 0; i < 15; ++i) C[i] = (float)Cin[i];
+    kf_update<float>(p, C, (float)my, (float)mz, (float)vy, (float)vz, c2);
+    for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+    for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+    *dchi2 = c2;
+    return;
+  }
+  double p[5], C[15], c2 = 0.0;
+  for (int i = 0; i < 5; ++i) p[i] = pin[i];
+  for (int i = 0; i < 15; ++i) C[i] = Cin[i];
+  kf_update<double>(p, C, my, mz, vy, vz, c2);
+  for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+  for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+  *dchi2 = c2;
+}
+
+int orc_fit_hits(int precision, const orc_geometry* g, const orc_params* P, int32_t n,
+                 const double* x, const double* y, const double* z, double k0, double pout[5],
+                 double Cout[15], double* chi2out) {
+  if (precision == 32) {
+    Model<float> m = make_model<float>(*g, *P);
+    std::vector<float> hx(n), hy(n), hz(n);
+    for (int i = 0; i < n; ++i) { hx[i] = (float)x[i]; hy[i] = (float)y[i]; hz[i] = (float)z[i]; }
+    float p[5], C[15], c2, xc;
+    if (!fit_hits<float>(m, *P, n, hx.data(), hy.data(), hz.data(), (float)k0, p, C, c2, xc)) return 0;
+    for (int i = 0; i < 5; ++i) pout[i] = p[i];
+    for (int i = 0; i < 15; ++i) Cout[i] = C[i];
+    *chi2out = c2;
+    return 1;
+  }
+  Model<double> m;
+  m.kfac = -2.99792458e-3 * (double)g->bz;
+  m.sin_max = P->sin_max;
+  m.vy = (double)P->sigma_y * (double)P->sigma_y;
+  m.vz = (double)P->sigma_z * (double)P->sigma_z;
+  double p[5], C[15], c2, xc;
+  if (!fit_hits<double>(m, *P, n, x, y, z, k0, p, C, c2, xc)) return 0;
+  for (int i = 0; i < 5; ++i) pout[i] = p[i];
+  for (int i = 0; i < 15; ++i) Cout[i] = C[i];
+  *chi2out = c2;
+  return 1;
+}
+
+int orc_track(int precision, const orc_geometry* g, const orc_params* P, int64_t n, const double* x,
+              const double* y, const double* z, const int16_t* row, const uint8_t* sector,
+              const uint8_t* sector_mask, orc_result** out) {
+  if (precision == 32)
+    *out = run_pipeline<float>(*g, *P, n, x, y, z, row, sector, sector_mask);
+  else
+    *out = run_pipeline<double>(*g, *P, n, x, y, z, row, sector, sector_mask);
+  return 0;
+}
+
+void orc_result_free(orc_result* r) {
+  if (!r) return;
+  void* ptrs[] = {r->up, r->dn, r->cup, r->cdn, r->starts, r->seed_start, r->seed_nhits,
+                  r->seed_key, r->seed_rlo, r->seed_rhi, r->seed_hits, r->seed_state, r->trk_seed,
+                  r->trk_sector, r->trk_xref, r->trk_p, r->trk_cov, r->trk_chi2, r->trk_ndf,
+                  r->hit_off, r->hit_ids};
+  for (void* p : ptrs) std::free(p);
+  std::free(r);
+}
+
+void orc_calib_apply(const orc_geometry* g, int64_t n, const uint8_t* sector, const double* x,
+                     const double* y, const double* z, const double* theta, double* xo,
+                     double* zo) {
+  for (int64_t i = 0; i < n; ++i) calib_point<double>(*g, sector[i], x[i], y[i], z[i], theta, xo[i], zo[i]);
+}
+
+int orc_calib_chi2(const orc_geometry* g, const orc_params* P, int64_t n_clusters, const double* x,
+                   const double* y, const double* z, const uint8_t* sector, int64_t n_tracks,
+                   const int64_t* hit_off, const int64_t* hit_ids, const double* k0,
+                   const double* ext_tgl, const uint8_t* use_vertex, const double* theta,
+                   double* chi2_out, int64_t* ndf_out, double* trk_chi2, double* grad) {
+  (void)n_clusters;
+  const int npar = 2 * g->n_sectors + 64 * g->n_sectors;
+  if (grad) for (int i = 0; i < npar; ++i) grad[i] = 0.0;
+  double total = 0.0;
+  int64_t ndf = 0;
+  Tape tape;
+  for (int64_t t = 0; t < n_tracks; ++t) {
+    int64_t b = hit_off[t], e = hit_off[t + 1];
+    int nh = (int)(e - b);
+    bool uv = use_vertex && use_vertex[t];
+    bool ue = uv && ext_tgl != nullptr;
+    double c2v = 0.0;
+    int ok;
+    if (!grad) {
+      Model<double> m;
+      m.kfac = -2.99792458e-3 * (double)g->bz;
+      m.sin_max = P->sin_max;
+      m.vy = (double)P->sigma_y * (double)P->sigma_y;
+      m.vz = (double)P->sigma_z * (double)P->sigma_z;
+      std::vector<double> hx(nh), hy(nh), hz(nh);
+      for (int j = 0; j < nh; ++j) {                 // outermost first
+        int64_t c = hit_ids[e - 1 - j];
+        calib_point<double>(*g, sector[c], x[c], y[c], z[c], theta, hx[j], hz[j]);
+        hy[j] = y[c];
+      }
+      double c2 = 0.0;
+      ok = track_objective<double>(*g, *P, m, nh, hx.data(), hy.data(), hz.data(), k0[t], uv, ue,
+                                   ue ? ext_tgl[t] : 0.0, c2);
+      c2v = c2;
+    } else {
+      g_tape = &tape;
+      tape.clear();
+      int s = sector[hit_ids[b]];
+      std::vector<Var> th(npar);
+      for (int i = 0; i < npar; ++i) th[i] = Var(theta[i]);
+      std::vector<int> leaves;
+      auto mkleaf = [&](int i) { th[i] = Var::leaf(theta[i]); leaves.push_back(i); };
+      mkleaf(s);
+      mkleaf(g->n_sectors + s);
+      for (int k = 0; k < 64; ++k) mkleaf(2 * g->n_sectors + s * 64 + k);
+      Model<Var> m;
+      m.kfac = Var(-2.99792458e-3 * (double)g->bz);
+      m.sin_max = Var((double)P->sin_max);
+      m.vy = Var((double)P->sigma_y * (double)P->sigma_y);
+      m.vz = Var((double)P->sigma_z * (double)P->sigma_z);
+      std::vector<Var> hx(nh), hy(nh), hz(nh);
+      for (int j = 0; j < nh; ++j) {
+        int64_t c = hit_ids[e - 1 - j];
+        calib_point<Var>(*g, sector[c], x[c], y[c], z[c], th.data(), hx[j], hz[j]);
+        hy[j] = Var(y[c]);
+      }
+      Var c2(0.0);
+      ok = track_objective<Var>(*g, *P, m, nh, hx.data(), hy.data(), hz.data(), Var(k0[t]), uv, ue,
+                                Var(ue ? ext_tgl[t] : 0.0), c2);
+      c2v = c2.v;
+      if (ok) {
+        tape.backprop(c2.i);
+        for (int i : leaves) grad[i] += tape.adj[th[i].i];
+      }
+      g_tape = nullptr;
+    }
+    if (!ok) c2v = 0.0;
+    if (trk_chi2) trk_chi2[t] = c2v;
+    if (ok) {
+      total += c2v;
+      ndf += 2 * nh - 5 + (ok == 2 ? 2 + (ue ? 1 : 0) : 0);
+    }
+  }
+  *chi2_out = total;
+  *ndf_out = ndf;
+  return 0;
+}
+
+}  // extern "C"
