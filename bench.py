@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the TPC CA + Kalman track finder on one MI355X.
+
+Workload: the central-Pb-Pb-shaped event (36 sectors, 18,000 primaries +
+4,000 displaced secondaries, 5 % noise, 10 % merged-cluster doubling, ~3.8 M
+FP32 clusters), resident in HBM.  One step = one tpcca_track call: binning,
+neighbour finding, link cleaning, start hits, tracklet construction,
+selection and final fit, with the outputs complete on return.
+
+Prints one JSON line: clusters/s, ms per step, the roofline position of the
+dominant kernel (its algorithmic bytes per launch over its average duration,
+measured with HIP events on the library's stream inside the timed region),
+and the CPU oracle timed on a bounded sample of the same event.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cluster of each phase kernel ("Roofline").
+ALGO_BYTES_PER_CLUSTER = {
+    "rows": 55.0,        # read 15 B input + 4 B bucketed id; write 20 B canonical + 16 B grid entry
+    "links": 44.0,       # read 12 B own coordinates + ~2 x 16 B window candidates; write 8 B links
+    "tracklets": 44.0,   # chain coords + links, ~2 window candidates of 16 B, 4 B hit slot
+    "refit": 16.0,       # 12 B coordinates + 4 B owner check per fitted hit
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sectors", default="0,13,18")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the tracker shards by event and sector with no exchange, "
+              "and this build runs and reports the single-GPU share only (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1712_09434_amd import Tracker
+
+    dev = torch.device("cuda:0")
+    log("generating the central-Pb-Pb-shaped event")
+    ev = synth.make_config("C3")
+    n = ev.n
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    x, y, z, row, sec = t(ev.x), t(ev.y), t(ev.z), t(ev.row), t(ev.sector)
+    trk = Tracker.from_geometry(ev.geom)
+    log(f"{n} clusters resident; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        out = trk.track(x, y, z, row, sec)
+    torch.cuda.synchronize()
+    trk.set_phase_timing(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = trk.track(x, y, z, row, sec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases, calls = trk.phase_times()
+    ms = dt / args.steps * 1e3
+    value = n / (dt / args.steps)
+    n_tracks, n_hits = out.n_tracks, int(out.hit_id.numel())
+    log(f"{ms:.3f} ms/step, {value:.3e} clusters/s, {n_tracks} tracks; phases "
+        + ", ".join(f"{k}={v:.3f}" for k, v in phases.items()))
+
+    dom = max(ALGO_BYTES_PER_CLUSTER, key=lambda k: phases.get(k, 0.0))
+    dom_ms = phases[dom]
+    algo_bytes = ALGO_BYTES_PER_CLUSTER[dom] * n
+    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                "traffic": None, "kernel_ms": round(dom_ms, 4),
+                "algo_bytes_per_launch": algo_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        secs = [int(s) for s in args.cpu_sectors.split(",")]
+        mask = np.zeros(36, np.uint8); mask[secs] = 1
+        nsample = int(np.isin(ev.sector, secs).sum())
+        log(f"oracle (FP32, 1 thread) on sectors {secs}: {nsample} clusters")
+        t1 = time.perf_counter()
+        oracle.track(ev, precision=32, sector_mask=mask)
+        ct = time.perf_counter() - t1
+        cpu = {"value": nsample / ct, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+               "sample": f"C3 event sectors {secs} ({nsample} clusters), {ct:.1f} s single-threaded",
+               "host_cpu": _cpu_model()}
+        log(f"oracle {nsample / ct:.3e} clusters/s")
+
+    line = {
+        "metric": "clusters/sec tracked (central Pb-Pb-shaped event, 1 GPU)",
+        "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "C3 central-Pb-Pb-shaped event: 36 sectors, 159 rows, 18000 primaries "
+                               "+ 4000 secondaries, 5% noise, 10% doubling, seed 1003",
+                   "clusters": n, "tracks": n_tracks, "hits": n_hits},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phase_ms": {k: round(v, 4) for k, v in phases.items()},
+    }
+    trk.close()
+    print(json.dumps(line), flush=True)
+
+
+def _cpu_model():
+    try:
+        for l in open("/proc/cpuinfo"):
+            if l.startswith("model name"):
+                return l.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * tpcca.h -- C ABI of the MI355X (gfx950) TPC cellular-automaton + Kalman
+ * track finder.
+ *
+ * Source of the method: Rohr et al., "Online Reconstruction and Calibration
+ * with feed back loop in the ALICE High Level Trigger" (arXiv:1712.09434).
+ *   - Sec. "Track reconstruction in the TPC": a cellular automaton builds
+ *     short seeds (around 5 to 10 hits); a Kalman filter then fits and
+ *     follows them; one GPU thread per cluster during the cellular automaton
+ *     and one per track during following; sectors are processed individually
+ *     and their segments merged afterwards; several events share one GPU.
+ *   - Sec. "Approach for online calibration" and Sec. "Overview of HLT online
+ *     calibration": tracking consumes calibration-transformed clusters; the
+ *     calibration consumes default-transformed clusters joined to the tracks
+ *     by the unchanged cluster index, and feeds a new map back.
+ *   - Sec. "A flat data structure": tracks are shipped as flat, pointer-free
+ *     buffers; a TPC track carries at most one cluster per pad row (159).
+ *
+ * Conventions shared by every call:
+ *   - Lengths in cm, field in tesla, momenta in GeV.  Sector-local frame:
+ *     x along the sector centre line, y across it, z along the beam.
+ *   - A track state is p = (y, z, sin phi, tan lambda, q/pT) at the plane
+ *     x = x_ref; its covariance is the packed upper triangle of the 5x5
+ *     matrix, row by row (15 floats).
+ *   - Cluster ids are positions in the caller's input arrays (0-based, per
+ *     event).  They never change between tracking and calibration.
+ *   - Buffers are owned by the caller.  `mem` says whether the pointers of a
+ *     struct are host (TPCCA_MEM_HOST) or device (TPCCA_MEM_DEVICE) memory.
+ *     The library owns only the context and its device workspace, which
+ *     grows on demand and is released by tpcca_destroy.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Every call returns after the stream has finished the call's work, so
+ *     host and device outputs are valid on return.  One context per
+ *     concurrently used stream / host thread.
+ *   - Return codes: TPCCA_OK, or a negative TPCCA_E_* code; nothing aborts
+ *     and nothing throws across this boundary.  tpcca_last_error() gives the
+ *     message of the last failure on a context.
+ */
+#ifndef TPCCA_H
+#define TPCCA_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPCCA_OK 0
+#define TPCCA_E_INVALID (-1)   /* null pointer, bad size, NaN/inf coordinate, row or sector out of range */
+#define TPCCA_E_CAPACITY (-2)  /* outputs too small: required sizes written to n_tracks / n_hits */
+#define TPCCA_E_DEVICE (-3)    /* HIP runtime error */
+#define TPCCA_E_NOMEM (-4)     /* device workspace allocation failed */
+#define TPCCA_E_LIMIT (-5)     /* a pad row of one sector holds more than TPCCA_MAX_ROW_CLUSTERS clusters */
+
+#define TPCCA_MEM_HOST 0
+#define TPCCA_MEM_DEVICE 1
+
+#define TPCCA_MAX_ROW_CLUSTERS 8192
+#define TPCCA_NPAR_PER_SECTOR 66   /* drift scale, time offset, 8x8 radial map */
+
+typedef struct tpcca_ctx tpcca_ctx;
+
+/* Detector geometry (host memory).  n_sectors even: the first half are the
+ * z >= 0 (A-side) sectors, the second half the C-side ones.  row_x holds the
+ * n_rows pad-row plane positions, strictly increasing. */
+typedef struct {
+  int32_t n_sectors;        /* 36 */
+  int32_t n_rows;           /* 159, at most 255 */
+  const float* row_x;       /* [n_rows], cm */
+  float tan_half_angle;     /* tan of the sector half-opening angle (10 deg) */
+  float z_max;              /* drift length L, cm (250) */
+} tpcca_geometry;
+
+/* Uniform solenoid field along z. */
+typedef struct {
+  float bz_tesla;           /* 0.5 */
+} tpcca_field;
+
+/* Tunable constants.  The paper states none of them; the defaults are this
+ * library's reading (tpcca_default_params).  */
+typedef struct {
+  float win_y, win_z;        /* neighbour windows |dy| <= win_y, |dz| <= win_z (2.0, 2.2) */
+  float inv_var_y, inv_var_z;/* 1/(1.5 sigma^2) for the midpoint deviation score */
+  float link_cut;            /* accept a (down, up) pair iff score <= link_cut (16) */
+  float chi2_ext;            /* row search: dy^2/Syy + dz^2/Szz <= chi2_ext (9) */
+  int32_t max_gap;           /* stop following after more than max_gap empty rows (8) */
+  int32_t min_seed_hits;     /* minimum chain length of a seed (5) */
+  int32_t min_hits;          /* minimum hits of a tracklet and a track (10) */
+  int32_t owned_num, owned_den; /* accept iff owned_den*owned >= owned_num*n_hits (9, 10) */
+  float sin_max;             /* |sin phi| limit of every transport step (0.99) */
+  float sigma_y, sigma_z;    /* cluster errors (0.1, 0.15) */
+  float sigma_vertex;        /* primary-vertex pseudo-measurement error (0.01) */
+  float sigma_tgl;           /* external tan(lambda) error (1e-3) */
+} tpcca_params;
+
+/* Clusters of one event: structure of arrays, n entries each. */
+typedef struct {
+  int64_t n;
+  const float* x;           /* sector-local x (cm); the pad-row plane for an undistorted cluster */
+  const float* y;
+  const float* z;
+  const int16_t* row;       /* pad row, [0, n_rows) */
+  const uint8_t* sector;    /* [0, n_sectors) */
+  int32_t mem;              /* TPCCA_MEM_HOST or TPCCA_MEM_DEVICE */
+  void* stream;             /* hipStream_t the work is enqueued on */
+} tpcca_clusters;
+
+/* Track output of one event (flat, pointer-free as shipped), and the input
+ * of tpcca_refit_grad.  All arrays are caller-owned, in memory `mem`.
+ * Tracks are ordered by their start hit (sector, pad row, cluster id); the
+ * hits of a track are in ascending pad row. */
+typedef struct {
+  int64_t cap_tracks, cap_hits;   /* in: capacities of the arrays below */
+  int64_t n_tracks, n_hits;       /* out: counts (required sizes on TPCCA_E_CAPACITY) */
+  uint8_t* sector;                /* [cap_tracks] */
+  float* x_ref;                   /* [cap_tracks] x of the innermost hit */
+  float* p;                       /* [cap_tracks][5] state at x_ref */
+  float* cov;                     /* [cap_tracks][15] */
+  float* chi2;                    /* [cap_tracks] */
+  int32_t* ndf;                   /* [cap_tracks] 2*n_hits - 5 */
+  float* k_prior;                 /* [cap_tracks] q/pT at the end of following (optional, NULL = off) */
+  int32_t* hit_off;               /* [cap_tracks + 1] */
+  uint32_t* hit_id;               /* [cap_hits] cluster ids */
+  /* optional parity taps of the seeding steps (NULL = off), indexed by cluster id */
+  int32_t* dbg_up;                /* [n] raw up link (cluster id or -1) */
+  int32_t* dbg_dn;                /* [n] raw down link */
+  int32_t* dbg_cup;               /* [n] cleaned up link */
+  int32_t* dbg_cdn;               /* [n] cleaned down link */
+  uint32_t* dbg_start;            /* [n] start hits in (sector, row, id) order */
+  int64_t n_start;                /* out: number of start hits (valid if dbg_start) */
+  /* refit_grad inputs (ignored by tracking) */
+  const tpcca_clusters* clusters; /* default-transformed clusters hit_id refers to */
+  const float* ext_tgl;           /* [n_tracks] external tan(lambda) (NULL = none) */
+  const uint8_t* use_vertex;      /* [n_tracks] 1: add vertex + external terms */
+  int32_t mem;
+} tpcca_tracks;
+
+/* Calibration parameters theta (FP32): per sector drift-velocity scale
+ * delta, time offset tau (cm) and an 8x8 radial displacement map (cm). */
+typedef struct {
+  const float* drift_scale;       /* [n_sectors] */
+  const float* time_offset;       /* [n_sectors] */
+  const float* map;               /* [n_sectors][8][8] */
+  int32_t mem;
+} tpcca_calib;
+
+/* d chi2 / d theta (FP64, deterministic reduction over tracks). */
+typedef struct {
+  double chi2;                    /* out: total chi2 */
+  int64_t ndf;                    /* out */
+  double* d_drift_scale;          /* [n_sectors] */
+  double* d_time_offset;          /* [n_sectors] */
+  double* d_map;                  /* [n_sectors][8][8] */
+  int32_t mem;
+} tpcca_grad;
+
+/* Default constants (host call, no context needed). */
+void tpcca_default_params(tpcca_params* p);
+
+/* Create a context for one geometry and field (Sec. "Track reconstruction
+ * in the TPC": the tracker is configured once per run).  Copies the row
+ * table to the device.  Returns TPCCA_E_INVALID for a bad geometry
+ * (n_sectors not even, n_rows not in [3, 255], row_x not increasing,
+ * non-positive sizes), TPCCA_E_DEVICE if no HIP device is usable. */
+int tpcca_create(const tpcca_geometry* geom, const tpcca_field* field, tpcca_ctx** out);
+
+/* Replace the constants (validated: positive windows, cuts, sigmas,
+ * 0 < sin_max < 1, min_seed_hits >= 3, min_hits >= 3). */
+int tpcca_set_params(tpcca_ctx* ctx, const tpcca_params* p);
+int tpcca_get_params(const tpcca_ctx* ctx, tpcca_params* p);
+
+/* Track one event (Sec. "Track reconstruction in the TPC"): binning per
+ * (sector, pad row), neighbour finding on adjacent pad rows, link cleaning,
+ * start hits, Kalman tracklet construction, selection and final fit, every
+ * sector independent.  On TPCCA_E_CAPACITY the required sizes are in
+ * out->n_tracks / out->n_hits and nothing else is written. */
+int tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* clusters, tpcca_tracks* out);
+
+/* Track n_events events together (Sec. "Track reconstruction in the TPC":
+ * several events processed concurrently on one GPU to fill it).  Event e is
+ * described by events[e] and written to out[e]; the result of every event is
+ * identical to tpcca_track on that event alone.  All events must use the
+ * same stream.  If any event overflows, every out[e] gets its required sizes
+ * and nothing else is written. */
+int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* events,
+                      tpcca_tracks* out);
+
+/* Calibration objective and gradient (Sec. "Approach for online
+ * calibration"; Sec. "Overview of HLT online calibration"): apply the
+ * correction theta to the default-transformed clusters tracks->clusters,
+ * refit the fixed hit lists of `tracks` (outermost hit first, q/pT prior
+ * tracks->k_prior), add the primary vertex as a measured point and the
+ * external tan(lambda) where use_vertex is set, and return the total chi2,
+ * its ndf and d chi2/d theta (FP32 per track, FP64 deterministic reduction).
+ * tracks->hit_id / hit_off / k_prior / ext_tgl / use_vertex are read for
+ * tracks->n_tracks tracks; all of them, the clusters, calib and grad arrays
+ * must share one `mem` kind per struct. */
+int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_calib* calib,
+                     tpcca_grad* out);
+
+/* Debug tap of the last tpcca_track call (host memory): the tracklet of
+ * every seed (chain head with at least min_seed_hits links), in start
+ * order.  seed_hits is [cap][n_rows] cluster ids or -1; state is
+ * [cap][20] (p then cov after following).  Fails with TPCCA_E_CAPACITY if
+ * cap is too small (required size in *n_seeds). */
+int tpcca_debug_tracklets(tpcca_ctx* ctx, int64_t cap, int64_t* n_seeds, uint32_t* seed_start,
+                          int32_t* seed_nhits, int32_t* seed_hits, float* seed_state);
+
+/* Per-phase timing of tracking calls (HIP events recorded on the caller's
+ * stream between the kernels).  tpcca_set_phase_timing(ctx, 1) enables it
+ * and clears the accumulators; tpcca_phase_times writes up to cap phase
+ * names (static strings) and their accumulated milliseconds, and the number
+ * of timed calls; it returns the number of phases. */
+int tpcca_set_phase_timing(tpcca_ctx* ctx, int on);
+int tpcca_phase_times(const tpcca_ctx* ctx, int32_t cap, const char** names, double* total_ms,
+                      int64_t* calls);
+
+const char* tpcca_last_error(const tpcca_ctx* ctx);
+void tpcca_destroy(tpcca_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,127 @@
+"""ctypes mirror of include/tpcca.h and the loader of libtpcca.so.
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Importing this module does not need a GPU; calling into the library does.
+The loader raises if the library has not been built -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpcca.so")
+
+TPCCA_OK = 0
+TPCCA_E_INVALID = -1
+TPCCA_E_CAPACITY = -2
+TPCCA_E_DEVICE = -3
+TPCCA_E_NOMEM = -4
+TPCCA_E_LIMIT = -5
+TPCCA_MEM_HOST = 0
+TPCCA_MEM_DEVICE = 1
+TPCCA_MAX_ROW_CLUSTERS = 8192
+ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "E_NOMEM", -5: "E_LIMIT"}
+
+EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
+            "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
+            "tpcca_set_phase_timing", "tpcca_phase_times", "tpcca_last_error", "tpcca_destroy"]
+
+
+class tpcca_geometry(C.Structure):
+    _fields_ = [("n_sectors", C.c_int32), ("n_rows", C.c_int32), ("row_x", C.POINTER(C.c_float)),
+                ("tan_half_angle", C.c_float), ("z_max", C.c_float)]
+
+
+class tpcca_field(C.Structure):
+    _fields_ = [("bz_tesla", C.c_float)]
+
+
+class tpcca_params(C.Structure):
+    _fields_ = [("win_y", C.c_float), ("win_z", C.c_float), ("inv_var_y", C.c_float),
+                ("inv_var_z", C.c_float), ("link_cut", C.c_float), ("chi2_ext", C.c_float),
+                ("max_gap", C.c_int32), ("min_seed_hits", C.c_int32), ("min_hits", C.c_int32),
+                ("owned_num", C.c_int32), ("owned_den", C.c_int32), ("sin_max", C.c_float),
+                ("sigma_y", C.c_float), ("sigma_z", C.c_float), ("sigma_vertex", C.c_float),
+                ("sigma_tgl", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class tpcca_clusters(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("row", C.c_void_p), ("sector", C.c_void_p), ("mem", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class tpcca_tracks(C.Structure):
+    _fields_ = [("cap_tracks", C.c_int64), ("cap_hits", C.c_int64), ("n_tracks", C.c_int64),
+                ("n_hits", C.c_int64), ("sector", C.c_void_p), ("x_ref", C.c_void_p),
+                ("p", C.c_void_p), ("cov", C.c_void_p), ("chi2", C.c_void_p), ("ndf", C.c_void_p),
+                ("k_prior", C.c_void_p), ("hit_off", C.c_void_p), ("hit_id", C.c_void_p),
+                ("dbg_up", C.c_void_p), ("dbg_dn", C.c_void_p), ("dbg_cup", C.c_void_p),
+                ("dbg_cdn", C.c_void_p), ("dbg_start", C.c_void_p), ("n_start", C.c_int64),
+                ("clusters", C.POINTER(tpcca_clusters)), ("ext_tgl", C.c_void_p),
+                ("use_vertex", C.c_void_p), ("mem", C.c_int32)]
+
+
+class tpcca_calib(C.Structure):
+    _fields_ = [("drift_scale", C.c_void_p), ("time_offset", C.c_void_p), ("map", C.c_void_p),
+                ("mem", C.c_int32)]
+
+
+class tpcca_grad(C.Structure):
+    _fields_ = [("chi2", C.c_double), ("ndf", C.c_int64), ("d_drift_scale", C.c_void_p),
+                ("d_time_offset", C.c_void_p), ("d_map", C.c_void_p), ("mem", C.c_int32)]
+
+
+_lib = None
+
+
+class TpccaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libtpcca.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libtpcca.so not built ({path}); run __graft_entry__.build() or "
+                           f"python -m paper_1712_09434_amd.build")
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.tpcca_default_params.argtypes = [P(tpcca_params)]
+    L.tpcca_default_params.restype = None
+    L.tpcca_create.argtypes = [P(tpcca_geometry), P(tpcca_field), P(C.c_void_p)]
+    L.tpcca_set_params.argtypes = [C.c_void_p, P(tpcca_params)]
+    L.tpcca_get_params.argtypes = [C.c_void_p, P(tpcca_params)]
+    L.tpcca_track.argtypes = [C.c_void_p, P(tpcca_clusters), P(tpcca_tracks)]
+    L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]
+    L.tpcca_refit_grad.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]
+    L.tpcca_debug_tracklets.argtypes = [C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]
+    L.tpcca_set_phase_timing.argtypes = [C.c_void_p, C.c_int]
+    L.tpcca_set_phase_timing.restype = C.c_int
+    L.tpcca_phase_times.argtypes = [C.c_void_p, C.c_int32, P(C.c_char_p), P(C.c_double), P(C.c_int64)]
+    L.tpcca_phase_times.restype = C.c_int
+    L.tpcca_last_error.argtypes = [C.c_void_p]
+    L.tpcca_last_error.restype = C.c_char_p
+    L.tpcca_destroy.argtypes = [C.c_void_p]
+    L.tpcca_destroy.restype = None
+    for name in ("tpcca_create", "tpcca_set_params", "tpcca_get_params", "tpcca_track",
+                 "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def default_params() -> tpcca_params:
+    p = tpcca_params()
+    load().tpcca_default_params(C.byref(p))
+    return p

@@ -1,0 +1,144 @@
+// internal.hpp -- device workspace layout shared by the kernels and the host
+// runtime of libtpcca (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tpcca.h"
+#include "kf_device.hpp"
+
+namespace tpcca {
+
+constexpr int kMaxRow = TPCCA_MAX_ROW_CLUSTERS;   // clusters per (sector, row) handled in LDS
+constexpr int kMaxCells = kMaxRow / 2 + 1;        // grid cells per (sector, row)
+
+// Flags / counters in device memory.
+enum : int {
+  F_ERR = 0,        // error bits (below)
+  F_NSEEDS = 1,     // number of seeds
+  F_NSTARTS = 2,    // number of start hits
+  F_FITS = 3,       // 1 if every event's outputs fit their capacities
+  F_SEEDCTR = 4,    // work counter of the tracklet kernel
+  F_COUNT = 8
+};
+enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u };
+
+// Per-(event, sector, row) search grid: cells of a uniform 2-D (z, y) grid
+// over the row's bounding box; cell (iz, iy) = cell_base + iz * ny + iy.
+struct alignas(32) GridParams {
+  uint32_t cell_base;
+  uint32_t nz, ny;
+  float z0, y0, inv_bz, inv_by;
+  uint32_t pad;
+};
+
+struct EventIn {
+  const float* x;
+  const float* y;
+  const float* z;
+  const int16_t* row;
+  const uint8_t* sector;
+  int64_t base;     // first global cluster index of the event
+  int64_t n;
+};
+
+struct EventOut {
+  uint8_t* sector;
+  float* x_ref;
+  float* p;
+  float* cov;
+  float* chi2;
+  int32_t* ndf;
+  float* k_prior;
+  int32_t* hit_off;
+  uint32_t* hit_id;
+  int32_t* dbg_up;
+  int32_t* dbg_dn;
+  int32_t* dbg_cup;
+  int32_t* dbg_cdn;
+  uint32_t* dbg_start;
+  int64_t cap_tracks, cap_hits;
+};
+
+// Per-seed refit record (floats): x_ref, p[5], cov[15], chi2, k_prior.
+constexpr int kRf = 23;
+// Per-seed tracklet state (floats): p[5], cov[15].
+constexpr int kTl = 20;
+
+struct Ws {
+  // sizes
+  int E, S, R;          // events, sectors per event, rows
+  int64_t N;            // clusters (all events)
+  int64_t RU;           // row units = E * S * R
+  int64_t seed_cap;     // capacity of seed arrays (>= N / min_seed_hits)
+  int64_t nb;           // blocks of 256 over N
+  // tables
+  const EventIn* ev;
+  const EventOut* out;
+  const float* row_x;   // [R]
+  Model m;
+  tpcca_params P;
+  float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
+  uint32_t* flags;      // [F_COUNT]
+  // binning
+  uint32_t* ru_count;   // [RU]
+  uint32_t* ru_off;     // [RU + 1]
+  uint32_t* cell_cap;   // [RU] cells + 1 per row unit, then scanned -> cell base [RU + 1]
+  uint32_t* cell_base;  // [RU + 1]
+  GridParams* grid;     // [RU]
+  uint32_t* tmp;        // [N] global cluster index, bucketed by row unit
+  // canonical SoA: (event, sector, row, id) order
+  float* cx;
+  float* cy;
+  float* cz;
+  uint32_t* cid;        // event-local cluster id
+  uint32_t* cru;        // row unit
+  // grid-ordered copy for window searches: (y, z, x, canonical position)
+  float4* gbuf;         // [N]
+  uint32_t* cell_off;   // [N / 2 + 2 RU + 1]
+  // links (canonical positions)
+  int32_t* up;
+  int32_t* dn;
+  int32_t* cup;
+  int32_t* cdn;
+  uint8_t* flag;        // bit0 start, bit1 seed
+  uint32_t* blk_start;  // [nb + 1]
+  uint32_t* blk_seed;   // [nb + 1]
+  uint32_t* scan_tmp;   // scan partials
+  uint32_t* starts;     // [N / 2 + 1] canonical positions
+  uint32_t* seeds;      // [seed_cap]
+  uint32_t* seed_ev_off;   // [E + 1]
+  uint32_t* start_ev_off;  // [E + 1]
+  // tracklets
+  int32_t* tl_nhits;    // [seed_cap]
+  int32_t* tl_range;    // [seed_cap] rlo | rhi << 16
+  uint64_t* tl_key;     // [seed_cap]
+  float* tl_state;      // [seed_cap * kTl]
+  int32_t* tl_hits;     // [seed_cap * R]
+  uint64_t* owner;      // [N]
+  // selection / refit / output
+  float* rf;            // [seed_cap * kRf]
+  uint32_t* trk_flag;   // [seed_cap + 1] -> scanned in place
+  uint32_t* hit_cnt;    // [seed_cap + 1] -> scanned in place
+  int64_t* ev_res;      // [E * 4]: n_tracks, n_hits, n_start, fits
+};
+
+// Phase boundaries of one tracking call; events are recorded on the
+// caller's stream between the kernels when timing is enabled.
+enum Phase : int {
+  PH_ZERO = 0, PH_COUNT, PH_SCAN, PH_SCATTER, PH_ROWS, PH_LINKS, PH_CLEAN, PH_COMPACT,
+  PH_TRACKLETS, PH_OWNER, PH_REFIT, PH_OUTPUT, PH_N
+};
+static const char* const kPhaseNames[PH_N] = {
+    "zero", "count", "scan", "scatter", "rows", "links", "clean", "compact",
+    "tracklets", "owner", "refit", "output"};
+
+struct PhaseEvents {
+  hipEvent_t ev[PH_N + 1];
+};
+
+// Host-side launchers (tpcca_kernels.hip).
+hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe = nullptr);
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+}  // namespace tpcca

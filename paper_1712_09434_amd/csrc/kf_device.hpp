@@ -1,0 +1,159 @@
+// kf_device.hpp -- FP32 helix transport and Kalman update for gfx950.
+//
+// Track model (paper, Sec. "Track reconstruction in the TPC": Kalman-filter
+// fitting and following of cellular-automaton seeds): state
+// p = (y, z, s = sin phi, t = tan lambda, k = q/pT) on planes x = const of
+// a sector frame, uniform solenoid, no material.  Every expression below is
+// evaluated in exactly this order: the library is built with
+// -ffp-contract=off and correctly rounded FP32 division and square root, so
+// the integer decisions taken from these values (which cluster, which row,
+// stop or go) are reproducible on any IEEE implementation that evaluates
+// the same expressions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tpcca {
+
+struct Model {
+  float kfac;     // signed curvature per unit q/pT: -c Bz
+  float sin_max;
+  float vy, vz;   // cluster variances
+};
+
+// Packed upper-triangle index of a symmetric 5x5 matrix.
+__host__ __device__ constexpr int sym(int i, int j) {
+  return i <= j ? (i == 0 ? j : i == 1 ? 4 + j : i == 2 ? 7 + j : i == 3 ? 9 + j : 14)
+                : sym(j, i);
+}
+
+// One step of the helix from the plane x0 to the plane x1.  The sine of the
+// direction moves linearly (s1 = s0 + kap dx); the chord rises by
+// dx (s0 + s1)/(c0 + c1); the transverse path is the chord (signed like dx)
+// times asin(u)/u, u = kap d / 2, taken as its series through u^8; z moves
+// by t times that path.  The covariance becomes F C F^T with the exact
+// Jacobian F of these expressions.  Returns false, leaving p and C
+// untouched, if |s1| would reach sin_max.
+__device__ __forceinline__ bool transport(float p[5], float C[15], float x0, float x1,
+                                          const Model& m) {
+  const float dx = x1 - x0;
+  if (dx == 0.0f) return true;
+  const float A1 = 1.0f / 6.0f, A2 = 3.0f / 40.0f, A3 = 5.0f / 112.0f, A4 = 35.0f / 1152.0f;
+  const float B1 = 1.0f / 3.0f, B2 = 3.0f / 10.0f, B3 = 15.0f / 56.0f, B4 = 35.0f / 144.0f;
+  const float kap = m.kfac * p[4];
+  const float s0 = p[2];
+  const float f = m.kfac * dx;
+  const float s1 = s0 + kap * dx;
+  if (!(fabsf(s1) < m.sin_max)) return false;
+  const float c0 = sqrtf(1.0f - s0 * s0);
+  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float ss = s0 + s1;
+  const float cc = c0 + c1;
+  const float tn = ss / cc;
+  const float dy = dx * tn;
+  float d = sqrtf(dx * dx + dy * dy);
+  if (dx < 0.0f) d = -d;
+  const float u = (kap * d) * 0.5f;
+  const float u2 = u * u;
+  const float g = 1.0f + u2 * (A1 + u2 * (A2 + u2 * (A3 + u2 * A4)));
+  const float gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));
+  const float l = d * g;
+  const float t0 = s0 / c0;
+  const float t1 = s1 / c1;
+  const float dtn_ds = (2.0f + tn * (t0 + t1)) / cc;
+  const float dtn_dk = (f * (1.0f + tn * t1)) / cc;
+  const float a = dx * dtn_ds;
+  const float b = dx * dtn_dk;
+  const float dd_ds = (dy * a) / d;
+  const float dd_dk = (dy * b) / d;
+  const float du_ds = (kap * dd_ds) * 0.5f;
+  const float du_dk = (m.kfac * d + kap * dd_dk) * 0.5f;
+  const float dl_ds = dd_ds * g + (d * gp) * du_ds;
+  const float dl_dk = dd_dk * g + (d * gp) * du_dk;
+  const float t = p[3];
+  const float c = t * dl_ds;
+  const float e = t * dl_dk;
+  p[0] = p[0] + dy;
+  p[1] = p[1] + t * l;
+  p[2] = s1;
+  const float C00 = C[0], C01 = C[1], C02 = C[2], C03 = C[3], C04 = C[4];
+  const float C11 = C[5], C12 = C[6], C13 = C[7], C14 = C[8];
+  const float C22 = C[9], C23 = C[10], C24 = C[11];
+  const float C33 = C[12], C34 = C[13], C44 = C[14];
+  const float T00 = C00 + a * C02 + b * C04;
+  const float T01 = C01 + a * C12 + b * C14;
+  const float T02 = C02 + a * C22 + b * C24;
+  const float T03 = C03 + a * C23 + b * C34;
+  const float T04 = C04 + a * C24 + b * C44;
+  const float T11 = C11 + c * C12 + l * C13 + e * C14;
+  const float T12 = C12 + c * C22 + l * C23 + e * C24;
+  const float T13 = C13 + c * C23 + l * C33 + e * C34;
+  const float T14 = C14 + c * C24 + l * C34 + e * C44;
+  const float T22 = C22 + f * C24;
+  const float T23 = C23 + f * C34;
+  const float T24 = C24 + f * C44;
+  C[0] = T00 + a * T02 + b * T04;
+  C[1] = T01 + c * T02 + l * T03 + e * T04;
+  C[2] = T02 + f * T04;
+  C[3] = T03;
+  C[4] = T04;
+  C[5] = T11 + c * T12 + l * T13 + e * T14;
+  C[6] = T12 + f * T14;
+  C[7] = T13;
+  C[8] = T14;
+  C[9] = T22 + f * T24;
+  C[10] = T23;
+  C[11] = T24;
+  return true;
+}
+
+// Kalman update with the cluster (my, mz): H = [I2 0], V = diag(vy, vz).
+// Gain from the explicit 2x2 inverse of S = H C H^T + V; chi2 increment
+// r^T S^-1 r.
+__device__ __forceinline__ void update(float p[5], float C[15], float my, float mz,
+                                       const Model& m, float& chi2) {
+  const float r0 = my - p[0];
+  const float r1 = mz - p[1];
+  const float S00 = C[0] + m.vy;
+  const float S01 = C[1];
+  const float S11 = C[5] + m.vz;
+  const float det = S00 * S11 - S01 * S01;
+  const float I00 = S11 / det;
+  const float I01 = (-S01) / det;
+  const float I11 = S00 / det;
+  float row0[5], row1[5], K0[5], K1[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) { row0[j] = C[sym(0, j)]; row1[j] = C[sym(1, j)]; }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = row0[i] * I00 + row1[i] * I01;
+    K1[i] = row0[i] * I01 + row1[i] * I11;
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) C[sym(i, j)] = C[sym(i, j)] - (K0[i] * row0[j] + K1[i] * row1[j]);
+  chi2 = chi2 + (r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
+}
+
+__device__ __forceinline__ void init_cov(float C[15], float vy, float vz) {
+#pragma unroll
+  for (int i = 0; i < 15; ++i) C[i] = 0.0f;
+  C[0] = vy;
+  C[5] = vz;
+  C[9] = 0.25f;
+  C[12] = 0.25f;
+  C[14] = 100.0f;
+}
+
+// Direction of the chord from an inner to an outer point.
+__device__ __forceinline__ void chord_dir(float xi, float yi, float zi, float xo, float yo,
+                                          float zo, float& s, float& t) {
+  const float dX = xo - xi, dY = yo - yi, dZ = zo - zi;
+  const float rho = sqrtf(dX * dX + dY * dY);
+  s = dY / rho;
+  t = dZ / rho;
+}
+
+}  // namespace tpcca

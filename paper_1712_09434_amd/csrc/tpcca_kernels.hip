@@ -1,0 +1,785 @@
+// tpcca_kernels.hip -- the tracking path on gfx950.
+//
+// Paper, Sec. "Track reconstruction in the TPC": cellular-automaton seeding
+// with one thread per cluster, Kalman-filter following with one thread per
+// track, every sector independent.  Here every (event, sector) pair is an
+// independent unit, so one launch of each phase covers all events of a
+// batch.  Phases:
+//   a1 binning    count per (event, sector, row) -> scan -> bucket -> per
+//                 row: sort by id in LDS, canonical SoA, 2-D (z, y) grid
+//   a2 links      one lane per cluster, windows on the adjacent rows' grids
+//   a3/a4         reciprocal-link cleaning, start and seed flags, wave ballot
+//                 compaction in canonical (event, sector, row, id) order
+//   a5 tracklets  one lane per seed: chain fit, upward and downward
+//                 following with grid searches
+//   a6 selection  64-bit atomicMax ownership per cluster
+//   a7 final fit  outermost-to-innermost Kalman refit of the owned hits,
+//                 ordered compaction into the caller's flat buffers
+#include "internal.hpp"
+
+namespace tpcca {
+namespace {
+
+constexpr int TB = 256;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over a 256-thread block; *tot receives the block total.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* tot) {
+  __shared__ uint32_t s_w[TB / 64];
+  const uint32_t inc = wave_incl_scan(v);
+  const int wid = threadIdx.x >> 6;
+  if (lane_id() == 63) s_w[wid] = inc;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < TB / 64; ++i) {
+    const uint32_t t = s_w[i];
+    if (i < wid) base += t;
+    total += t;
+  }
+  __syncthreads();
+  *tot = total;
+  return base + inc - v;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// ---------------------------------------------------------------- utilities
+__global__ void k_fill(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) p[i] = v;
+}
+
+__global__ __launch_bounds__(TB) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                    uint32_t* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) if (base + j < n) s += in[base + j];
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(TB) void k_scan_parts(uint32_t* __restrict__ part, int64_t np) {
+  uint32_t carry = 0;
+  for (int64_t b = 0; b < np; b += TB) {
+    const int64_t i = b + threadIdx.x;
+    const uint32_t v = i < np ? part[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, &tot);
+    if (i < np) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) part[np] = carry;
+}
+
+__global__ __launch_bounds__(TB) void k_scan_down(const uint32_t* in, int64_t n,
+                                                  const uint32_t* __restrict__ part, int64_t np,
+                                                  uint32_t* out) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
+  uint32_t v[4], s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) { v[j] = base + j < n ? in[base + j] : 0u; s += v[j]; }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + (blockIdx.x < np ? part[blockIdx.x] : 0u);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) out[base + j] = ex;
+    ex += v[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[np];
+}
+
+// Exclusive scan of n values; out[n] receives the total (out may equal in).
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st) {
+  const int64_t np = (n + 1023) / 1024;
+  if (np > 0) k_scan_reduce<<<dim3((unsigned)np), dim3(TB), 0, st>>>(in, n, part);
+  k_scan_parts<<<1, TB, 0, st>>>(part, np);
+  k_scan_down<<<dim3((unsigned)(np > 0 ? np : 1)), dim3(TB), 0, st>>>(in, n, part, np, out);
+  return hipGetLastError();
+}
+
+inline unsigned blocks_for(int64_t n, int64_t cap = 1 << 16) {
+  int64_t b = (n + TB - 1) / TB;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+__device__ __forceinline__ int find_event(const Ws& w, int64_t g) {
+  int lo = 0, hi = w.E - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.ev[mid].base <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------- a1: binning
+__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int64_t& l,
+                                             uint32_t& ru) {
+  e = find_event(w, g);
+  const EventIn& E = w.ev[e];
+  l = g - E.base;
+  const float x = E.x[l], y = E.y[l], z = E.z[l];
+  const int r = E.row[l];
+  const int s = E.sector[l];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z)) || r < 0 || r >= w.R || s >= w.S) return false;
+  ru = ((uint32_t)e * (uint32_t)w.S + (uint32_t)s) * (uint32_t)w.R + (uint32_t)r;
+  return true;
+}
+
+__global__ __launch_bounds__(TB) void k_count(Ws w) {
+  for (int64_t g = (int64_t)blockIdx.x * TB + threadIdx.x; g < w.N; g += (int64_t)gridDim.x * TB) {
+    int e; int64_t l; uint32_t ru;
+    if (!read_cluster(w, g, e, l, ru)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
+    atomicAdd(&w.ru_count[ru], 1u);
+  }
+}
+
+// cells + 1 offsets per row unit
+__global__ void k_cell_caps(Ws w) {
+  for (int64_t ru = (int64_t)blockIdx.x * TB + threadIdx.x; ru < w.RU; ru += (int64_t)gridDim.x * TB)
+    w.cell_cap[ru] = (w.ru_count[ru] >> 1) + 2u;
+}
+
+__global__ __launch_bounds__(TB) void k_scatter(Ws w) {
+  for (int64_t g = (int64_t)blockIdx.x * TB + threadIdx.x; g < w.N; g += (int64_t)gridDim.x * TB) {
+    int e; int64_t l; uint32_t ru;
+    if (!read_cluster(w, g, e, l, ru)) continue;
+    const uint32_t k = atomicSub(&w.ru_count[ru], 1u) - 1u;
+    w.tmp[w.ru_off[ru] + k] = (uint32_t)g;
+  }
+}
+
+__device__ __forceinline__ uint32_t cell_coord(float v, float v0, float inv, uint32_t nc) {
+  float t = (v - v0) * inv;
+  t = fminf(fmaxf(t, 0.0f), (float)(nc - 1u));
+  return (uint32_t)t;
+}
+
+__device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float z) {
+  return cell_coord(z, G.z0, G.inv_bz, G.nz) * G.ny + cell_coord(y, G.y0, G.inv_by, G.ny);
+}
+
+// One block per row unit: ids sorted ascending in LDS (bitonic), canonical
+// SoA written in that order, then a uniform 2-D grid over the row's bounding
+// box with about two clusters per cell, filled by an LDS counting sort.
+__global__ __launch_bounds__(TB) void k_rows(Ws w) {
+  __shared__ uint32_t s_ids[kMaxRow];
+  __shared__ uint32_t s_hist[kMaxCells + 1];
+  __shared__ float s_red[4][TB / 64];
+  __shared__ GridParams s_gp;
+  const int64_t ru = blockIdx.x;
+  const uint32_t off = w.ru_off[ru];
+  const uint32_t n = w.ru_off[ru + 1] - off;
+  const uint32_t cbase = w.cell_base[ru];
+  const int e = (int)(ru / ((int64_t)w.S * w.R));
+  const EventIn E = w.ev[e];
+  const int tid = threadIdx.x;
+  if (n > (uint32_t)kMaxRow) {
+    if (tid == 0) {
+      atomicOr(&w.flags[F_ERR], ERR_LIMIT);
+      GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, 0u};
+      w.grid[ru] = G;
+      w.cell_off[cbase] = off;
+      w.cell_off[cbase + 1] = off;
+    }
+    const float nan = __int_as_float(0x7fc00000);
+    for (uint32_t k = tid; k < n; k += TB) {
+      w.cx[off + k] = nan; w.cy[off + k] = nan; w.cz[off + k] = nan;
+      w.cid[off + k] = 0u; w.cru[off + k] = (uint32_t)ru;
+    }
+    return;
+  }
+  uint32_t npad = 2;
+  while (npad < n) npad <<= 1;
+  for (uint32_t k = tid; k < npad; k += TB) s_ids[k] = k < n ? w.tmp[off + k] : 0xFFFFFFFFu;
+  __syncthreads();
+  for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < npad; i += TB) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = s_ids[i], b = s_ids[ixj];
+          const bool asc = (i & kk) == 0;
+          if ((a > b) == asc) { s_ids[i] = b; s_ids[ixj] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+  for (uint32_t k = tid; k < n; k += TB) {
+    const int64_t l = (int64_t)s_ids[k] - E.base;
+    const float x = E.x[l], y = E.y[l], z = E.z[l];
+    w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
+    w.cid[off + k] = (uint32_t)l; w.cru[off + k] = (uint32_t)ru;
+    ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
+    zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
+  }
+  if (lane_id() == 0) {
+    s_red[0][tid >> 6] = ymin; s_red[1][tid >> 6] = ymax; s_red[2][tid >> 6] = zmin; s_red[3][tid >> 6] = zmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < TB / 64; ++i) {
+      ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
+      zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
+    }
+    const uint32_t cap = (n >> 1) + 1u;
+    uint32_t nz = 1, ny = 1;
+    float dz = zmax - zmin, dy = ymax - ymin;
+    if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
+    if (n >= 4 && dz > 0.0f && dy > 0.0f) {
+      const float a = sqrtf((dz * dy) / (float)cap);
+      nz = (uint32_t)fminf(fmaxf(dz / a, 1.0f), (float)cap);
+      ny = (uint32_t)fminf(fmaxf(dy / a, 1.0f), (float)(cap / nz));
+    }
+    GridParams G;
+    G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
+    G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
+    G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
+    G.pad = 0u;
+    s_gp = G;
+    w.grid[ru] = G;
+  }
+  __syncthreads();
+  const GridParams G = s_gp;
+  const uint32_t nc = G.nz * G.ny;
+  for (uint32_t c = tid; c <= nc; c += TB) s_hist[c] = 0u;
+  __syncthreads();
+  for (uint32_t k = tid; k < n; k += TB) {
+    const int64_t l = (int64_t)s_ids[k] - E.base;
+    atomicAdd(&s_hist[cell_of(G, E.y[l], E.z[l])], 1u);
+  }
+  __syncthreads();
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nc; c0 += TB) {
+    const uint32_t c = c0 + tid;
+    const uint32_t v = c < nc ? s_hist[c] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, &tot) + carry;
+    if (c < nc) { s_hist[c] = ex; w.cell_off[cbase + c] = off + ex; }
+    carry += tot;
+  }
+  if (tid == 0) w.cell_off[cbase + nc] = off + n;
+  __syncthreads();
+  for (uint32_t k = tid; k < n; k += TB) {
+    const int64_t l = (int64_t)s_ids[k] - E.base;
+    const float x = E.x[l], y = E.y[l], z = E.z[l];
+    const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
+    w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
+  }
+}
+
+// Cell rectangle [iz0, iz1] x [iy0, iy1] covering |y - yq| <= wy, |z - zq| <= wz
+// (the margin absorbs the rounding of the bounds; the exact test is done per
+// candidate).
+struct CellBox { uint32_t iz0, iz1, iy0, iy1; };
+__device__ __forceinline__ CellBox cell_box(const GridParams& G, float yq, float zq, float wy, float wz) {
+  const float m = 1e-3f;
+  CellBox b;
+  b.iz0 = cell_coord(zq - wz - m, G.z0, G.inv_bz, G.nz);
+  b.iz1 = cell_coord(zq + wz + m, G.z0, G.inv_bz, G.nz);
+  b.iy0 = cell_coord(yq - wy - m, G.y0, G.inv_by, G.ny);
+  b.iy1 = cell_coord(yq + wy + m, G.y0, G.inv_by, G.ny);
+  return b;
+}
+
+// ---------------------------------------------------------- a2: neighbours
+// For the middle cluster i: the (down, up) pair on rows r-1 / r+1 inside the
+// windows minimising the deviation of i from the chord d-u, accepted iff the
+// score <= link_cut, ties by smaller up id then smaller down id (canonical
+// positions are ordered like ids within a row).
+__global__ __launch_bounds__(TB) void k_links(Ws w) {
+  const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (p >= w.N) return;
+  const uint32_t ru = w.cru[p];
+  const int r = (int)(ru % (uint32_t)w.R);
+  int32_t bu = -1, bd = -1;
+  if (r >= 1 && r <= w.R - 2) {
+    const float xi = w.cx[p], yi = w.cy[p], zi = w.cz[p];
+    const float WY = w.P.win_y, WZ = w.P.win_z, IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z;
+    const float CUT = w.P.link_cut;
+    const GridParams Gd = w.grid[ru - 1], Gu = w.grid[ru + 1];
+    const CellBox bdn = cell_box(Gd, yi, zi, WY, WZ);
+    const CellBox bup = cell_box(Gu, yi, zi, WY, WZ);
+    bool have = false;
+    float bs = 0.0f;
+    for (uint32_t izd = bdn.iz0; izd <= bdn.iz1; ++izd) {
+      const uint32_t cd0 = Gd.cell_base + izd * Gd.ny;
+      const uint32_t kd1 = w.cell_off[cd0 + bdn.iy1 + 1];
+      for (uint32_t kd = w.cell_off[cd0 + bdn.iy0]; kd < kd1; ++kd) {
+        const float4 D = w.gbuf[kd];
+        if (!(fabsf(D.x - yi) <= WY && fabsf(D.y - zi) <= WZ)) continue;
+        const int32_t pd = (int32_t)__float_as_uint(D.w);
+        for (uint32_t izu = bup.iz0; izu <= bup.iz1; ++izu) {
+          const uint32_t cu0 = Gu.cell_base + izu * Gu.ny;
+          const uint32_t ku1 = w.cell_off[cu0 + bup.iy1 + 1];
+          for (uint32_t ku = w.cell_off[cu0 + bup.iy0]; ku < ku1; ++ku) {
+            const float4 U = w.gbuf[ku];
+            if (!(fabsf(U.x - yi) <= WY && fabsf(U.y - zi) <= WZ)) continue;
+            const float wgt = (xi - D.z) / (U.z - D.z);
+            const float ey = yi - (D.x + (U.x - D.x) * wgt);
+            const float ez = zi - (D.y + (U.y - D.y) * wgt);
+            const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+            if (!(score <= CUT)) continue;
+            const int32_t pu = (int32_t)__float_as_uint(U.w);
+            const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
+            if (better) { have = true; bs = score; bu = pu; bd = pd; }
+          }
+        }
+      }
+    }
+  }
+  w.up[p] = bu;
+  w.dn[p] = bd;
+}
+
+// ------------------------------------------------------- a3/a4: clean/start
+// Keep a link only if reciprocated (from the raw arrays).  Start hit: kept up
+// link, no kept down link.  Seed: start hit whose chain reaches
+// min_seed_hits clusters.  Optional taps map positions to cluster ids.
+__global__ __launch_bounds__(TB) void k_clean(Ws w) {
+  __shared__ uint32_t s_cnt[2][TB / 64];
+  const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
+  bool start = false, seed = false;
+  if (p < w.N) {
+    const int32_t u = w.up[p], d = w.dn[p];
+    const int32_t cu = (u >= 0 && w.dn[u] == (int32_t)p) ? u : -1;
+    const int32_t cd = (d >= 0 && w.up[d] == (int32_t)p) ? d : -1;
+    w.cup[p] = cu;
+    w.cdn[p] = cd;
+    start = cu >= 0 && cd < 0;
+    if (start) {
+      int L = 2;
+      int32_t q = cu;
+      while (L < w.P.min_seed_hits) {
+        const int32_t nu = w.up[q];
+        if (nu < 0 || w.dn[nu] != q) break;
+        q = nu;
+        ++L;
+      }
+      seed = L >= w.P.min_seed_hits;
+    }
+    w.flag[p] = (uint8_t)((start ? 1 : 0) | (seed ? 2 : 0));
+    const int e = (int)(w.cru[p] / ((uint32_t)w.S * (uint32_t)w.R));
+    const EventOut& O = w.out[e];
+    const uint32_t id = w.cid[p];
+    if (O.dbg_up) O.dbg_up[id] = u >= 0 ? (int32_t)w.cid[u] : -1;
+    if (O.dbg_dn) O.dbg_dn[id] = d >= 0 ? (int32_t)w.cid[d] : -1;
+    if (O.dbg_cup) O.dbg_cup[id] = cu >= 0 ? (int32_t)w.cid[cu] : -1;
+    if (O.dbg_cdn) O.dbg_cdn[id] = cd >= 0 ? (int32_t)w.cid[cd] : -1;
+  }
+  const uint64_t bs = __ballot(start), bq = __ballot(seed);
+  if (lane_id() == 0) { s_cnt[0][threadIdx.x >> 6] = (uint32_t)__popcll(bs); s_cnt[1][threadIdx.x >> 6] = (uint32_t)__popcll(bq); }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (int i = 0; i < TB / 64; ++i) { a += s_cnt[0][i]; b += s_cnt[1][i]; }
+    w.blk_start[blockIdx.x] = a;
+    w.blk_seed[blockIdx.x] = b;
+  }
+}
+
+// Ordered compaction: block offset (scanned) + wave offset + ballot rank.
+__global__ __launch_bounds__(TB) void k_compact(Ws w) {
+  __shared__ uint32_t s_cnt[2][TB / 64];
+  const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
+  const uint8_t f = p < w.N ? w.flag[p] : (uint8_t)0;
+  const bool start = f & 1, seed = (f >> 1) & 1;
+  const uint64_t bs = __ballot(start), bq = __ballot(seed);
+  const int wid = threadIdx.x >> 6;
+  if (lane_id() == 0) { s_cnt[0][wid] = (uint32_t)__popcll(bs); s_cnt[1][wid] = (uint32_t)__popcll(bq); }
+  __syncthreads();
+  uint32_t os = w.blk_start[blockIdx.x], oq = w.blk_seed[blockIdx.x];
+  for (int i = 0; i < wid; ++i) { os += s_cnt[0][i]; oq += s_cnt[1][i]; }
+  const uint64_t lt = lanemask_lt();
+  if (start) w.starts[os + (uint32_t)__popcll(bs & lt)] = (uint32_t)p;
+  if (seed) w.seeds[oq + (uint32_t)__popcll(bq & lt)] = (uint32_t)p;
+}
+
+// Counts and per-event ranges of the start and seed lists.
+__global__ __launch_bounds__(TB) void k_ev_offsets(Ws w) {
+  const uint32_t ns = w.blk_seed[w.nb], nst = w.blk_start[w.nb];
+  if (threadIdx.x == 0) { w.flags[F_NSEEDS] = ns; w.flags[F_NSTARTS] = nst; }
+  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
+  for (int e = threadIdx.x; e <= w.E; e += TB) {
+    const uint32_t key = (uint32_t)e * per;
+    uint32_t lo = 0, hi = ns;
+    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.seeds[mid]] < key) lo = mid + 1; else hi = mid; }
+    w.seed_ev_off[e] = lo;
+    lo = 0; hi = nst;
+    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.starts[mid]] < key) lo = mid + 1; else hi = mid; }
+    w.start_ev_off[e] = lo;
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_start_tap(Ws w) {
+  const uint32_t nst = w.flags[F_NSTARTS];
+  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < nst; i += (int64_t)gridDim.x * TB) {
+    const uint32_t p = w.starts[i];
+    const int e = (int)(w.cru[p] / per);
+    const EventOut& O = w.out[e];
+    if (O.dbg_start) O.dbg_start[i - w.start_ev_off[e]] = w.cid[p];
+  }
+}
+
+// ----------------------------------------------------------- a5: tracklets
+struct Found { int32_t pos; float x, y, z; };
+
+// Closest cluster of row unit ru to the predicted (y, z):
+// d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
+__device__ __forceinline__ Found search_row(const Ws& w, uint32_t ru, const float p[5],
+                                            const float C[15]) {
+  const float sy2 = C[0] + w.m.vy, sz2 = C[5] + w.m.vz;
+  const float isy = 1.0f / sy2, isz = 1.0f / sz2;
+  const float CUT = w.P.chi2_ext;
+  const float wy = 3.0f * sqrtf(sy2) * 1.0001f, wz = 3.0f * sqrtf(sz2) * 1.0001f;
+  const GridParams G = w.grid[ru];
+  const CellBox b = cell_box(G, p[0], p[1], wy, wz);
+  Found best{-1, 0.f, 0.f, 0.f};
+  float bd = 0.0f;
+  for (uint32_t iz = b.iz0; iz <= b.iz1; ++iz) {
+    const uint32_t c0 = G.cell_base + iz * G.ny;
+    const uint32_t k1 = w.cell_off[c0 + b.iy1 + 1];
+    for (uint32_t k = w.cell_off[c0 + b.iy0]; k < k1; ++k) {
+      const float4 c = w.gbuf[k];
+      const float dY = c.x - p[0], dZ = c.y - p[1];
+      const float d = (dY * dY) * isy + (dZ * dZ) * isz;
+      if (!(d <= CUT)) continue;
+      const int32_t pos = (int32_t)__float_as_uint(c.w);
+      if (best.pos < 0 || d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
+    }
+  }
+  return best;
+}
+
+struct Acc { float tan_a, z_max; };
+
+__device__ __forceinline__ bool accepted(float X, const Acc& a, const float p[5]) {
+  const float lim = X * a.tan_a;
+  return !(fabsf(p[0]) > lim || fabsf(p[1]) > a.z_max);
+}
+
+// One following step on row r: transport to the row plane, acceptance,
+// search, (transport to the cluster's own x,) update.  Returns false when
+// following stops; *wrote tells whether the row slot was written.
+__device__ __forceinline__ bool follow_row(const Ws& w, const float* sX, const Acc& acc,
+                                           uint32_t rubase, int r, float p[5], float C[15],
+                                           float& xc, int& rstate, int32_t* hits, int& nhits,
+                                           int& gap, bool& wrote) {
+  wrote = false;
+  const float X = sX[r];
+  if (!transport(p, C, xc, X, w.m)) return false;
+  xc = X;
+  rstate = r;
+  if (!accepted(X, acc, p)) return false;
+  const Found h = search_row(w, rubase + (uint32_t)r, p, C);
+  if (h.pos >= 0) {
+    if (h.x != X) {
+      if (!transport(p, C, X, h.x, w.m)) return false;
+      xc = h.x;
+    }
+    float dummy = 0.0f;
+    update(p, C, h.y, h.z, w.m, dummy);
+    hits[r] = h.pos;
+    ++nhits;
+    gap = 0;
+  } else {
+    hits[r] = -1;
+    ++gap;
+  }
+  wrote = true;
+  return gap <= w.P.max_gap;
+}
+
+__global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
+  __shared__ float sX[256];
+  for (int r = threadIdx.x; r < w.R; r += TB) sX[r] = w.row_x[r];
+  __syncthreads();
+  const Acc acc{w.tan_a, w.z_max};
+  const uint32_t ns = w.flags[F_NSEEDS];
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
+    const int32_t h0 = (int32_t)w.seeds[s];
+    const uint32_t ru0 = w.cru[h0];
+    const int r0 = (int)(ru0 % (uint32_t)w.R);
+    const uint32_t rubase = ru0 - (uint32_t)r0;
+    int32_t* hits = w.tl_hits + s * w.R;
+    float* st = w.tl_state + s * kTl;
+    const int32_t h1 = w.cup[h0];
+    const int32_t h2 = w.cup[h1];
+    float p[5], C[15];
+    float sdir, tdir;
+    const float x0 = w.cx[h0], y0 = w.cy[h0], z0 = w.cz[h0];
+    chord_dir(x0, y0, z0, w.cx[h2], w.cy[h2], w.cz[h2], sdir, tdir);
+    p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
+    init_cov(C, w.m.vy, w.m.vz);
+    int nhits = 0, rlo = r0, rhi = r0;
+    bool ok = fabsf(sdir) < w.m.sin_max;
+    float xc = x0;
+    int rstate = r0;
+    if (ok) {
+      hits[r0] = h0;
+      nhits = 1;
+      float dummy = 0.0f;
+      for (int32_t h = h1; h >= 0; h = w.cup[h]) {
+        const float hx = w.cx[h];
+        if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
+        update(p, C, w.cy[h], w.cz[h], w.m, dummy);
+        ++rstate;
+        hits[rstate] = h;
+        ++nhits;
+        xc = hx;
+      }
+    }
+    if (!ok) {
+      nhits = 0;
+      rhi = rlo = r0;
+    } else {
+      rhi = rstate;
+      int gap = 0;
+      for (int r = rstate + 1; r < w.R; ++r) {
+        bool wrote;
+        const bool go = follow_row(w, sX, acc, rubase, r, p, C, xc, rstate, hits, nhits, gap, wrote);
+        if (wrote) rhi = r;
+        if (!go) break;
+      }
+      bool back = true;
+      for (int r = rstate - 1; r >= r0; --r) {
+        if (!transport(p, C, xc, sX[r], w.m)) { back = false; break; }
+        xc = sX[r];
+      }
+      if (back) {
+        gap = 0;
+        int rs = r0;
+        for (int r = r0 - 1; r >= 0; --r) {
+          bool wrote;
+          const bool go = follow_row(w, sX, acc, rubase, r, p, C, xc, rs, hits, nhits, gap, wrote);
+          if (wrote) rlo = r;
+          if (!go) break;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) st[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) st[5 + i] = C[i];
+    w.tl_nhits[s] = nhits;
+    w.tl_range[s] = rlo | (rhi << 16);
+    const uint32_t id = w.cid[h0];
+    w.tl_key[s] = ((uint64_t)(uint32_t)nhits << 40) | ((uint64_t)(255 - r0) << 32) |
+                  (uint64_t)(0xFFFFFFFFu - id);
+  }
+}
+
+// ----------------------------------------------------------- a6: selection
+__global__ __launch_bounds__(TB) void k_owner(Ws w) {
+  const uint32_t ns = w.flags[F_NSEEDS];
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
+    if (w.tl_nhits[s] < w.P.min_hits) continue;
+    const uint64_t key = w.tl_key[s];
+    const int32_t rg = w.tl_range[s];
+    const int rlo = rg & 0xFFFF, rhi = rg >> 16;
+    const int32_t* hits = w.tl_hits + s * w.R;
+    for (int r = rlo; r <= rhi; ++r) {
+      const int32_t h = hits[r];
+      if (h >= 0) atomicMax((unsigned long long*)&w.owner[h], (unsigned long long)key);
+    }
+  }
+}
+
+// ------------------------------------------------ a6/a7: accept + final fit
+__global__ __launch_bounds__(TB) void k_refit(Ws w) {
+  const uint32_t ns = w.flags[F_NSEEDS];
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
+    uint32_t okf = 0, cnt = 0;
+    if (s < ns && w.tl_nhits[s] >= w.P.min_hits) {
+      const int nh = w.tl_nhits[s];
+      const uint64_t key = w.tl_key[s];
+      const int32_t rg = w.tl_range[s];
+      const int rlo = rg & 0xFFFF, rhi = rg >> 16;
+      const int32_t* hits = w.tl_hits + s * w.R;
+      int32_t o[3] = {-1, -1, -1};
+      int r0 = -1;
+      for (int r = rhi; r >= rlo; --r) {
+        const int32_t h = hits[r];
+        if (h >= 0 && w.owner[h] == key) {
+          if (cnt < 3) { o[cnt] = h; if (cnt == 0) r0 = r; }
+          ++cnt;
+        }
+      }
+      const bool acc = (int)cnt >= w.P.min_hits &&
+                       (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh;
+      if (acc) {
+        float p[5], C[15], sdir, tdir;
+        const float xo = w.cx[o[0]], yo = w.cy[o[0]], zo = w.cz[o[0]];
+        chord_dir(w.cx[o[2]], w.cy[o[2]], w.cz[o[2]], xo, yo, zo, sdir, tdir);
+        const float kpr = w.tl_state[s * kTl + 4];
+        p[0] = yo; p[1] = zo; p[2] = sdir; p[3] = tdir; p[4] = kpr;
+        init_cov(C, w.m.vy, w.m.vz);
+        float chi2 = 0.0f;
+        bool ok = fabsf(sdir) < w.m.sin_max;
+        float xc = xo;
+        for (int r = r0 - 1; ok && r >= rlo; --r) {
+          const int32_t h = hits[r];
+          if (h < 0 || w.owner[h] != key) continue;
+          const float hx = w.cx[h];
+          if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
+          update(p, C, w.cy[h], w.cz[h], w.m, chi2);
+          xc = hx;
+        }
+        if (ok) {
+          float* rf = w.rf + s * kRf;
+          rf[0] = xc;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) rf[1 + i] = p[i];
+#pragma unroll
+          for (int i = 0; i < 15; ++i) rf[6 + i] = C[i];
+          rf[21] = chi2;
+          rf[22] = kpr;
+          okf = 1;
+        }
+      }
+    }
+    w.trk_flag[s] = okf;
+    w.hit_cnt[s] = okf ? cnt : 0u;
+  }
+}
+
+// Per-event totals and the capacity check.
+__global__ __launch_bounds__(TB) void k_totals(Ws w) {
+  __shared__ int s_fit;
+  if (threadIdx.x == 0) s_fit = 1;
+  __syncthreads();
+  for (int e = threadIdx.x; e < w.E; e += TB) {
+    const uint32_t b = w.seed_ev_off[e], en = w.seed_ev_off[e + 1];
+    const int64_t nt = (int64_t)w.trk_flag[en] - (int64_t)w.trk_flag[b];
+    const int64_t nh = (int64_t)w.hit_cnt[en] - (int64_t)w.hit_cnt[b];
+    w.ev_res[e * 4 + 0] = nt;
+    w.ev_res[e * 4 + 1] = nh;
+    w.ev_res[e * 4 + 2] = (int64_t)w.start_ev_off[e + 1] - (int64_t)w.start_ev_off[e];
+    const EventOut& O = w.out[e];
+    const bool fit = nt <= O.cap_tracks && nh <= O.cap_hits;
+    w.ev_res[e * 4 + 3] = fit ? 1 : 0;
+    if (!fit) atomicAnd(&s_fit, 0);
+  }
+  __syncthreads();
+  const bool go = s_fit && w.flags[F_ERR] == 0u;
+  if (threadIdx.x == 0) w.flags[F_FITS] = go ? 1u : 0u;
+  if (go)
+    for (int e = threadIdx.x; e < w.E; e += TB)
+      w.out[e].hit_off[w.ev_res[e * 4 + 0]] = (int32_t)w.ev_res[e * 4 + 1];
+}
+
+__global__ __launch_bounds__(TB) void k_write(Ws w) {
+  if (w.flags[F_FITS] == 0u) return;
+  const uint32_t ns = w.flags[F_NSEEDS];
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
+    const uint32_t t0 = w.trk_flag[s];
+    if (w.trk_flag[s + 1] == t0) continue;
+    const int32_t h0 = (int32_t)w.seeds[s];
+    const uint32_t vsec = w.cru[h0] / (uint32_t)w.R;
+    const int e = (int)(vsec / (uint32_t)w.S);
+    const EventOut& O = w.out[e];
+    const uint32_t sb = w.seed_ev_off[e];
+    const uint32_t j = t0 - w.trk_flag[sb];
+    const uint32_t o = w.hit_cnt[s] - w.hit_cnt[sb];
+    const uint32_t n = w.hit_cnt[s + 1] - w.hit_cnt[s];
+    const float* rf = w.rf + s * kRf;
+    O.sector[j] = (uint8_t)(vsec % (uint32_t)w.S);
+    O.x_ref[j] = rf[0];
+    for (int i = 0; i < 5; ++i) O.p[j * 5 + i] = rf[1 + i];
+    for (int i = 0; i < 15; ++i) O.cov[j * 15 + i] = rf[6 + i];
+    O.chi2[j] = rf[21];
+    O.ndf[j] = 2 * (int32_t)n - 5;
+    if (O.k_prior) O.k_prior[j] = rf[22];
+    O.hit_off[j] = (int32_t)o;
+    const uint64_t key = w.tl_key[s];
+    const int32_t rg = w.tl_range[s];
+    const int32_t* hits = w.tl_hits + s * w.R;
+    uint32_t k = o;
+    for (int r = rg & 0xFFFF; r <= (rg >> 16); ++r) {
+      const int32_t h = hits[r];
+      if (h >= 0 && w.owner[h] == key) O.hit_id[k++] = w.cid[h];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<blocks_for(n, 4096), TB, 0, st>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
+  hipError_t e;
+#define TPCCA_CHECK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+#define TPCCA_MARK(i) do { if (pe) TPCCA_CHECK(hipEventRecord(pe->ev[i], st)); } while (0)
+  TPCCA_MARK(PH_ZERO);
+  TPCCA_CHECK(fill_u32(w.flags, 0u, F_COUNT, st));
+  TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
+  TPCCA_CHECK(fill_u32((uint32_t*)w.owner, 0u, 2 * w.N, st));
+  TPCCA_MARK(PH_COUNT);
+  k_count<<<blocks_for(w.N), TB, 0, st>>>(w);
+  TPCCA_CHECK(hipGetLastError());
+  k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);
+  TPCCA_MARK(PH_SCAN);
+  TPCCA_CHECK(scan_u32(w.ru_count, w.ru_off, w.RU, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32(w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
+  TPCCA_MARK(PH_SCATTER);
+  k_scatter<<<blocks_for(w.N), TB, 0, st>>>(w);
+  TPCCA_MARK(PH_ROWS);
+  k_rows<<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  TPCCA_CHECK(hipGetLastError());
+  const unsigned nbN = (unsigned)w.nb;
+  TPCCA_MARK(PH_LINKS);
+  k_links<<<nbN, TB, 0, st>>>(w);
+  TPCCA_MARK(PH_CLEAN);
+  k_clean<<<nbN, TB, 0, st>>>(w);
+  TPCCA_MARK(PH_COMPACT);
+  TPCCA_CHECK(scan_u32(w.blk_start, w.blk_start, w.nb, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32(w.blk_seed, w.blk_seed, w.nb, w.scan_tmp, st));
+  k_compact<<<nbN, TB, 0, st>>>(w);
+  k_ev_offsets<<<1, TB, 0, st>>>(w);
+  k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
+  TPCCA_CHECK(hipGetLastError());
+  TPCCA_MARK(PH_TRACKLETS);
+  k_tracklets<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  TPCCA_CHECK(hipGetLastError());
+  TPCCA_MARK(PH_OWNER);
+  k_owner<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  TPCCA_MARK(PH_REFIT);
+  k_refit<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  TPCCA_MARK(PH_OUTPUT);
+  TPCCA_CHECK(scan_u32(w.trk_flag, w.trk_flag, w.seed_cap, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32(w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
+  k_totals<<<1, TB, 0, st>>>(w);
+  k_write<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  TPCCA_CHECK(hipGetLastError());
+  TPCCA_MARK(PH_N);
+#undef TPCCA_MARK
+#undef TPCCA_CHECK
+  return hipSuccess;
+}
+
+}  // namespace tpcca

@@ -1,0 +1,490 @@
+// tpcca_runtime.hip -- host side of libtpcca: the C ABI of include/tpcca.h.
+//
+// One context per geometry and stream user.  The context owns a single
+// device arena (grown on demand, never shrunk) that holds every
+// intermediate array of the tracking path, plus staging for host-memory
+// inputs and outputs.  Errors are reported by return code and message;
+// nothing throws or aborts across the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace tpcca;
+
+struct tpcca_ctx {
+  int device = 0;
+  int S = 0, R = 0;
+  float tan_a = 0.f, z_max = 0.f, bz = 0.f;
+  float* row_x_d = nullptr;
+  tpcca_params P{};
+  std::string err;
+  // arena
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  // staging for host-memory inputs / outputs
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
+  Ws w{};
+  // last tracking call (debug tap)
+  bool last_ok = false;
+  int64_t last_nseeds = 0;
+  // refit_grad scratch
+  char* gscratch = nullptr;
+  size_t gscratch_bytes = 0;
+  // phase timing
+  bool timing = false;
+  PhaseEvents pe{};
+  double phase_ms[PH_N] = {};
+  int64_t timed_calls = 0;
+};
+
+namespace {
+
+int fail(tpcca_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(tpcca_ctx* c, hipError_t e, const char* where) {
+  return fail(c, TPCCA_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+Model make_model(float bz, const tpcca_params& P) {
+  Model m;
+  m.kfac = -((float)2.99792458e-3) * bz;
+  m.sin_max = P.sin_max;
+  m.vy = P.sigma_y * P.sigma_y;
+  m.vz = P.sigma_z * P.sigma_z;
+  return m;
+}
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t off = 0;
+  template <class T> size_t take(int64_t n) { size_t o = off; off += al(sizeof(T) * (size_t)std::max<int64_t>(n, 1)); return o; }
+};
+
+// Lay out every workspace array for N clusters in E events.  With base ==
+// nullptr only the size is computed.
+size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed) {
+  Layout L;
+  w.E = E; w.S = S; w.R = R; w.N = N;
+  w.RU = (int64_t)E * S * R;
+  w.seed_cap = N / std::max(min_seed, 1) + 1;
+  w.nb = std::max<int64_t>(1, (N + 255) / 256);
+  const int64_t RU = w.RU, SC = w.seed_cap;
+  const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(RU, w.nb), SC) + 1;
+  size_t o_flags = L.take<uint32_t>(F_COUNT);
+  size_t o_ruc = L.take<uint32_t>(RU), o_ruo = L.take<uint32_t>(RU + 1);
+  size_t o_cc = L.take<uint32_t>(RU), o_cb = L.take<uint32_t>(RU + 1);
+  size_t o_grid = L.take<GridParams>(RU);
+  size_t o_tmp = L.take<uint32_t>(N);
+  size_t o_cx = L.take<float>(N), o_cy = L.take<float>(N), o_cz = L.take<float>(N);
+  size_t o_cid = L.take<uint32_t>(N), o_cru = L.take<uint32_t>(N);
+  size_t o_gbuf = L.take<float4>(N);
+  size_t o_coff = L.take<uint32_t>(N / 2 + 2 * RU + 1);
+  size_t o_up = L.take<int32_t>(N), o_dn = L.take<int32_t>(N), o_cup = L.take<int32_t>(N), o_cdn = L.take<int32_t>(N);
+  size_t o_flag = L.take<uint8_t>(N);
+  size_t o_bs = L.take<uint32_t>(w.nb + 1), o_bq = L.take<uint32_t>(w.nb + 1);
+  size_t o_scan = L.take<uint32_t>(scan_n / 1024 + 4);
+  size_t o_starts = L.take<uint32_t>(N / 2 + 1), o_seeds = L.take<uint32_t>(SC);
+  size_t o_seo = L.take<uint32_t>(E + 1), o_steo = L.take<uint32_t>(E + 1);
+  size_t o_tln = L.take<int32_t>(SC), o_tlr = L.take<int32_t>(SC);
+  size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * R);
+  size_t o_own = L.take<uint64_t>(N);
+  size_t o_rf = L.take<float>(SC * kRf);
+  size_t o_tf = L.take<uint32_t>(SC + 1), o_hc = L.take<uint32_t>(SC + 1);
+  size_t o_res = L.take<int64_t>((int64_t)E * 4);
+  size_t o_ev = L.take<EventIn>(E), o_out = L.take<EventOut>(E);
+  if (base) {
+    w.flags = (uint32_t*)(base + o_flags);
+    w.ru_count = (uint32_t*)(base + o_ruc); w.ru_off = (uint32_t*)(base + o_ruo);
+    w.cell_cap = (uint32_t*)(base + o_cc); w.cell_base = (uint32_t*)(base + o_cb);
+    w.grid = (GridParams*)(base + o_grid);
+    w.tmp = (uint32_t*)(base + o_tmp);
+    w.cx = (float*)(base + o_cx); w.cy = (float*)(base + o_cy); w.cz = (float*)(base + o_cz);
+    w.cid = (uint32_t*)(base + o_cid); w.cru = (uint32_t*)(base + o_cru);
+    w.gbuf = (float4*)(base + o_gbuf); w.cell_off = (uint32_t*)(base + o_coff);
+    w.up = (int32_t*)(base + o_up); w.dn = (int32_t*)(base + o_dn);
+    w.cup = (int32_t*)(base + o_cup); w.cdn = (int32_t*)(base + o_cdn);
+    w.flag = (uint8_t*)(base + o_flag);
+    w.blk_start = (uint32_t*)(base + o_bs); w.blk_seed = (uint32_t*)(base + o_bq);
+    w.scan_tmp = (uint32_t*)(base + o_scan);
+    w.starts = (uint32_t*)(base + o_starts); w.seeds = (uint32_t*)(base + o_seeds);
+    w.seed_ev_off = (uint32_t*)(base + o_seo); w.start_ev_off = (uint32_t*)(base + o_steo);
+    w.tl_nhits = (int32_t*)(base + o_tln); w.tl_range = (int32_t*)(base + o_tlr);
+    w.tl_key = (uint64_t*)(base + o_tlk); w.tl_state = (float*)(base + o_tls);
+    w.tl_hits = (int32_t*)(base + o_tlh);
+    w.owner = (uint64_t*)(base + o_own);
+    w.rf = (float*)(base + o_rf);
+    w.trk_flag = (uint32_t*)(base + o_tf); w.hit_cnt = (uint32_t*)(base + o_hc);
+    w.ev_res = (int64_t*)(base + o_res);
+    w.ev = (const EventIn*)(base + o_ev);
+    w.out = (const EventOut*)(base + o_out);
+  }
+  return L.off;
+}
+
+int ensure_arena(tpcca_ctx* c, size_t need) {
+  if (need <= c->arena_bytes) return TPCCA_OK;
+  if (c->arena) { (void)hipFree(c->arena); c->arena = nullptr; c->arena_bytes = 0; }
+  size_t want = need + need / 4;
+  hipError_t e = hipMalloc((void**)&c->arena, want);
+  if (e != hipSuccess) {
+    c->arena = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TPCCA_E_NOMEM, "device workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  c->arena_bytes = want;
+  return TPCCA_OK;
+}
+
+int ensure_stage(tpcca_ctx* c, size_t need) {
+  if (need <= c->stage_bytes) return TPCCA_OK;
+  if (c->stage) { (void)hipFree(c->stage); c->stage = nullptr; c->stage_bytes = 0; }
+  hipError_t e = hipMalloc((void**)&c->stage, need);
+  if (e != hipSuccess) {
+    c->stage = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TPCCA_E_NOMEM, "staging allocation failed");
+  }
+  c->stage_bytes = need;
+  return TPCCA_OK;
+}
+
+int check_params(const tpcca_params* p) {
+  if (!(p->win_y > 0 && p->win_z > 0 && p->inv_var_y > 0 && p->inv_var_z > 0 && p->link_cut > 0 &&
+        p->chi2_ext > 0 && p->max_gap >= 0 && p->min_seed_hits >= 3 && p->min_hits >= 3 &&
+        p->owned_num >= 0 && p->owned_den > 0 && p->sin_max > 0 && p->sin_max < 1 &&
+        p->sigma_y > 0 && p->sigma_z > 0 && p->sigma_vertex > 0 && p->sigma_tgl > 0))
+    return TPCCA_E_INVALID;
+  return TPCCA_OK;
+}
+
+struct HostOut {   // where host-memory outputs of an event are staged on the device
+  bool host = false;
+  int64_t tcap = 0, hcap = 0, n = 0;
+  size_t o_sector, o_xref, o_p, o_cov, o_chi2, o_ndf, o_kp, o_hoff, o_hid, o_up, o_dn, o_cup, o_cdn, o_start;
+};
+
+}  // namespace
+
+extern "C" {
+
+void tpcca_default_params(tpcca_params* p) {
+  if (!p) return;
+  p->win_y = 2.0f;
+  p->win_z = 2.2f;
+  p->inv_var_y = (float)(1.0 / (1.5 * 0.1 * 0.1));
+  p->inv_var_z = (float)(1.0 / (1.5 * 0.15 * 0.15));
+  p->link_cut = 16.0f;
+  p->chi2_ext = 9.0f;
+  p->max_gap = 8;
+  p->min_seed_hits = 5;
+  p->min_hits = 10;
+  p->owned_num = 9;
+  p->owned_den = 10;
+  p->sin_max = 0.99f;
+  p->sigma_y = 0.1f;
+  p->sigma_z = 0.15f;
+  p->sigma_vertex = 0.01f;
+  p->sigma_tgl = 1e-3f;
+}
+
+int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out) {
+  if (!out) return TPCCA_E_INVALID;
+  *out = nullptr;
+  if (!g || !f || !g->row_x) return TPCCA_E_INVALID;
+  if (g->n_sectors <= 0 || (g->n_sectors & 1) || g->n_sectors > 254 || g->n_rows < 3 || g->n_rows > 255)
+    return TPCCA_E_INVALID;
+  for (int r = 0; r < g->n_rows; ++r) {
+    if (!std::isfinite(g->row_x[r]) || g->row_x[r] <= 0.0f) return TPCCA_E_INVALID;
+    if (r > 0 && !(g->row_x[r] > g->row_x[r - 1])) return TPCCA_E_INVALID;
+  }
+  if (!(g->tan_half_angle > 0 && g->z_max > 0 && std::isfinite(f->bz_tesla))) return TPCCA_E_INVALID;
+  tpcca_ctx* c = new (std::nothrow) tpcca_ctx();
+  if (!c) return TPCCA_E_NOMEM;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { (void)hipGetLastError(); delete c; return TPCCA_E_DEVICE; }
+  c->S = g->n_sectors; c->R = g->n_rows;
+  c->tan_a = g->tan_half_angle; c->z_max = g->z_max; c->bz = f->bz_tesla;
+  tpcca_default_params(&c->P);
+  e = hipMalloc((void**)&c->row_x_d, sizeof(float) * g->n_rows);
+  if (e == hipSuccess) e = hipMemcpy(c->row_x_d, g->row_x, sizeof(float) * g->n_rows, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipGetLastError(); if (c->row_x_d) (void)hipFree(c->row_x_d); delete c; return TPCCA_E_DEVICE; }
+  *out = c;
+  return TPCCA_OK;
+}
+
+int tpcca_set_params(tpcca_ctx* c, const tpcca_params* p) {
+  if (!c || !p) return TPCCA_E_INVALID;
+  if (check_params(p) != TPCCA_OK) return fail(c, TPCCA_E_INVALID, "invalid parameter values");
+  c->P = *p;
+  return TPCCA_OK;
+}
+
+int tpcca_get_params(const tpcca_ctx* c, tpcca_params* p) {
+  if (!c || !p) return TPCCA_E_INVALID;
+  *p = c->P;
+  return TPCCA_OK;
+}
+
+const char* tpcca_last_error(const tpcca_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int tpcca_set_phase_timing(tpcca_ctx* c, int on) {
+  if (!c) return TPCCA_E_INVALID;
+  if (on && !c->pe.ev[0]) {
+    for (int i = 0; i <= PH_N; ++i) {
+      hipError_t e = hipEventCreate(&c->pe.ev[i]);
+      if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
+    }
+  }
+  c->timing = on != 0;
+  for (int i = 0; i < PH_N; ++i) c->phase_ms[i] = 0.0;
+  c->timed_calls = 0;
+  return TPCCA_OK;
+}
+
+int tpcca_phase_times(const tpcca_ctx* c, int32_t cap, const char** names, double* total_ms,
+                      int64_t* calls) {
+  if (!c) return TPCCA_E_INVALID;
+  if (calls) *calls = c->timed_calls;
+  for (int i = 0; i < PH_N && i < cap; ++i) {
+    if (names) names[i] = kPhaseNames[i];
+    if (total_ms) total_ms[i] = c->phase_ms[i];
+  }
+  return PH_N;
+}
+
+void tpcca_destroy(tpcca_ctx* c) {
+  if (!c) return;
+  for (int i = 0; i <= PH_N; ++i)
+    if (c->pe.ev[i]) (void)hipEventDestroy(c->pe.ev[i]);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->stage) (void)hipFree(c->stage);
+  if (c->gscratch) (void)hipFree(c->gscratch);
+  if (c->row_x_d) (void)hipFree(c->row_x_d);
+  delete c;
+}
+
+int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_tracks* out) {
+  if (!c) return TPCCA_E_INVALID;
+  c->last_ok = false;
+  if (E <= 0 || !ev || !out) return fail(c, TPCCA_E_INVALID, "need n_events > 0, events and outputs");
+  if (check_params(&c->P) != TPCCA_OK) return fail(c, TPCCA_E_INVALID, "invalid parameters");
+  hipStream_t st = (hipStream_t)ev[0].stream;
+  int64_t N = 0;
+  for (int e = 0; e < E; ++e) {
+    const tpcca_clusters& k = ev[e];
+    if (k.n < 0 || (k.n > 0 && (!k.x || !k.y || !k.z || !k.row || !k.sector)))
+      return fail(c, TPCCA_E_INVALID, "event " + std::to_string(e) + ": null array or negative size");
+    if (k.mem != TPCCA_MEM_HOST && k.mem != TPCCA_MEM_DEVICE) return fail(c, TPCCA_E_INVALID, "bad mem kind");
+    if (k.stream != ev[0].stream) return fail(c, TPCCA_E_INVALID, "all events must share one stream");
+    N += k.n;
+    const tpcca_tracks& o = out[e];
+    if (o.mem != TPCCA_MEM_HOST && o.mem != TPCCA_MEM_DEVICE) return fail(c, TPCCA_E_INVALID, "bad output mem kind");
+    if (o.cap_tracks < 0 || o.cap_hits < 0 || !o.hit_off)
+      return fail(c, TPCCA_E_INVALID, "event " + std::to_string(e) + ": negative capacity or null hit_off");
+    if (o.cap_tracks > 0 && (!o.sector || !o.x_ref || !o.p || !o.cov || !o.chi2 || !o.ndf))
+      return fail(c, TPCCA_E_INVALID, "event " + std::to_string(e) + ": null track array");
+    if (o.cap_hits > 0 && !o.hit_id) return fail(c, TPCCA_E_INVALID, "null hit_id");
+  }
+  if (N >= (int64_t)1 << 31) return fail(c, TPCCA_E_INVALID, "more than 2^31 clusters in one call");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+
+  Ws w{};
+  const size_t need = layout_ws(w, nullptr, N, E, c->S, c->R, c->P.min_seed_hits);
+  int rc = ensure_arena(c, need);
+  if (rc) return rc;
+  layout_ws(w, c->arena, N, E, c->S, c->R, c->P.min_seed_hits);
+  w.row_x = c->row_x_d;
+  w.m = make_model(c->bz, c->P);
+  w.P = c->P;
+  w.tan_a = c->tan_a;
+  w.z_max = c->z_max;
+
+  // staging: host inputs and host outputs
+  std::vector<HostOut> ho(E);
+  size_t soff = 0;
+  auto take = [&](size_t b) { size_t o = soff; soff += al(std::max<size_t>(b, 1)); return o; };
+  std::vector<size_t> in_off(E, 0);
+  for (int e = 0; e < E; ++e)
+    if (ev[e].mem == TPCCA_MEM_HOST && ev[e].n > 0) in_off[e] = take((size_t)ev[e].n * 15);
+  for (int e = 0; e < E; ++e) {
+    const tpcca_tracks& o = out[e];
+    HostOut& h = ho[e];
+    if (o.mem != TPCCA_MEM_HOST) continue;
+    h.host = true;
+    h.n = ev[e].n;
+    h.tcap = std::min<int64_t>(o.cap_tracks, ev[e].n / std::max(c->P.min_seed_hits, 1) + 1);
+    h.hcap = std::min<int64_t>(o.cap_hits, ev[e].n);
+    h.o_sector = take(h.tcap); h.o_xref = take(4 * h.tcap); h.o_p = take(20 * h.tcap);
+    h.o_cov = take(60 * h.tcap); h.o_chi2 = take(4 * h.tcap); h.o_ndf = take(4 * h.tcap);
+    h.o_kp = take(4 * h.tcap); h.o_hoff = take(4 * (h.tcap + 1)); h.o_hid = take(4 * h.hcap);
+    h.o_up = take(4 * h.n); h.o_dn = take(4 * h.n); h.o_cup = take(4 * h.n); h.o_cdn = take(4 * h.n);
+    h.o_start = take(4 * h.n);
+  }
+  if (soff > 0) { rc = ensure_stage(c, soff); if (rc) return rc; }
+  char* sb = c->stage;
+
+  std::vector<EventIn> ein(E);
+  std::vector<EventOut> eout(E);
+  int64_t base = 0;
+  for (int e = 0; e < E; ++e) {
+    const tpcca_clusters& k = ev[e];
+    EventIn& I = ein[e];
+    I.base = base; I.n = k.n;
+    if (k.mem == TPCCA_MEM_HOST && k.n > 0) {
+      char* p = sb + in_off[e];
+      he = hipMemcpyAsync(p, k.x, 4 * k.n, hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(p + 4 * k.n, k.y, 4 * k.n, hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(p + 8 * k.n, k.z, 4 * k.n, hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(p + 12 * k.n, k.row, 2 * k.n, hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(p + 14 * k.n, k.sector, k.n, hipMemcpyHostToDevice, st);
+      if (he != hipSuccess) return hip_fail(c, he, "input upload");
+      I.x = (const float*)p; I.y = (const float*)(p + 4 * k.n); I.z = (const float*)(p + 8 * k.n);
+      I.row = (const int16_t*)(p + 12 * k.n); I.sector = (const uint8_t*)(p + 14 * k.n);
+    } else {
+      I.x = k.x; I.y = k.y; I.z = k.z; I.row = k.row; I.sector = k.sector;
+    }
+    base += k.n;
+    const tpcca_tracks& o = out[e];
+    EventOut& O = eout[e];
+    O.cap_tracks = o.cap_tracks; O.cap_hits = o.cap_hits;
+    if (ho[e].host) {
+      const HostOut& h = ho[e];
+      O.cap_tracks = h.tcap; O.cap_hits = h.hcap;
+      O.sector = (uint8_t*)(sb + h.o_sector); O.x_ref = (float*)(sb + h.o_xref); O.p = (float*)(sb + h.o_p);
+      O.cov = (float*)(sb + h.o_cov); O.chi2 = (float*)(sb + h.o_chi2); O.ndf = (int32_t*)(sb + h.o_ndf);
+      O.k_prior = o.k_prior ? (float*)(sb + h.o_kp) : nullptr;
+      O.hit_off = (int32_t*)(sb + h.o_hoff); O.hit_id = (uint32_t*)(sb + h.o_hid);
+      O.dbg_up = o.dbg_up ? (int32_t*)(sb + h.o_up) : nullptr;
+      O.dbg_dn = o.dbg_dn ? (int32_t*)(sb + h.o_dn) : nullptr;
+      O.dbg_cup = o.dbg_cup ? (int32_t*)(sb + h.o_cup) : nullptr;
+      O.dbg_cdn = o.dbg_cdn ? (int32_t*)(sb + h.o_cdn) : nullptr;
+      O.dbg_start = o.dbg_start ? (uint32_t*)(sb + h.o_start) : nullptr;
+    } else {
+      O.sector = o.sector; O.x_ref = o.x_ref; O.p = o.p; O.cov = o.cov; O.chi2 = o.chi2; O.ndf = o.ndf;
+      O.k_prior = o.k_prior; O.hit_off = o.hit_off; O.hit_id = o.hit_id;
+      O.dbg_up = o.dbg_up; O.dbg_dn = o.dbg_dn; O.dbg_cup = o.dbg_cup; O.dbg_cdn = o.dbg_cdn;
+      O.dbg_start = o.dbg_start;
+    }
+  }
+  he = hipMemcpyAsync((void*)w.ev, ein.data(), sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout.data(), sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
+  if (he != hipSuccess) return hip_fail(c, he, "table upload");
+
+  he = run_pipeline(w, st, c->timing ? &c->pe : nullptr);
+  if (he != hipSuccess) return hip_fail(c, he, "kernel launch");
+  uint32_t flags[F_COUNT];
+  std::vector<int64_t> res((size_t)E * 4);
+  he = hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(res.data(), w.ev_res, sizeof(int64_t) * 4 * E, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "tracking");
+  if (c->timing) {
+    for (int i = 0; i < PH_N; ++i) {
+      float ms = 0.f;
+      he = hipEventElapsedTime(&ms, c->pe.ev[i], c->pe.ev[i + 1]);
+      if (he != hipSuccess) return hip_fail(c, he, "phase timing");
+      c->phase_ms[i] += ms;
+    }
+    c->timed_calls++;
+  }
+  if (flags[F_ERR] & ERR_INVALID) return fail(c, TPCCA_E_INVALID, "non-finite coordinate or row/sector out of range");
+  if (flags[F_ERR] & ERR_LIMIT)
+    return fail(c, TPCCA_E_LIMIT, "a pad row holds more than " + std::to_string(kMaxRow) + " clusters");
+  bool fits = true;
+  for (int e = 0; e < E; ++e) {
+    out[e].n_tracks = res[e * 4 + 0];
+    out[e].n_hits = res[e * 4 + 1];
+    out[e].n_start = res[e * 4 + 2];
+    fits &= res[e * 4 + 0] <= out[e].cap_tracks && res[e * 4 + 1] <= out[e].cap_hits;
+  }
+  c->last_ok = true;
+  c->last_nseeds = flags[F_NSEEDS];
+  c->w = w;
+  if (!fits || flags[F_FITS] == 0u) return fail(c, TPCCA_E_CAPACITY, "output capacity too small");
+  // host-memory outputs
+  for (int e = 0; e < E; ++e) {
+    if (!ho[e].host) continue;
+    const HostOut& h = ho[e];
+    tpcca_tracks& o = out[e];
+    const int64_t nt = o.n_tracks, nh = o.n_hits, n = h.n;
+    struct Cp { void* dst; size_t src; size_t bytes; };
+    std::vector<Cp> cps = {
+        {o.sector, h.o_sector, (size_t)nt}, {o.x_ref, h.o_xref, 4 * (size_t)nt}, {o.p, h.o_p, 20 * (size_t)nt},
+        {o.cov, h.o_cov, 60 * (size_t)nt}, {o.chi2, h.o_chi2, 4 * (size_t)nt}, {o.ndf, h.o_ndf, 4 * (size_t)nt},
+        {o.k_prior, h.o_kp, 4 * (size_t)nt}, {o.hit_off, h.o_hoff, 4 * (size_t)(nt + 1)},
+        {o.hit_id, h.o_hid, 4 * (size_t)nh}, {o.dbg_up, h.o_up, 4 * (size_t)n}, {o.dbg_dn, h.o_dn, 4 * (size_t)n},
+        {o.dbg_cup, h.o_cup, 4 * (size_t)n}, {o.dbg_cdn, h.o_cdn, 4 * (size_t)n},
+        {o.dbg_start, h.o_start, 4 * (size_t)o.n_start}};
+    for (const Cp& cp : cps) {
+      if (!cp.dst || cp.bytes == 0) continue;
+      he = hipMemcpyAsync(cp.dst, sb + cp.src, cp.bytes, hipMemcpyDeviceToHost, st);
+      if (he != hipSuccess) return hip_fail(c, he, "output download");
+    }
+  }
+  he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "output download");
+  return TPCCA_OK;
+}
+
+int tpcca_track(tpcca_ctx* c, const tpcca_clusters* k, tpcca_tracks* out) {
+  if (!c) return TPCCA_E_INVALID;
+  if (!k || !out) return fail(c, TPCCA_E_INVALID, "null clusters or output");
+  return tpcca_track_batch(c, 1, k, out);
+}
+
+int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t* seed_start,
+                          int32_t* seed_nhits, int32_t* seed_hits, float* seed_state) {
+  if (!c || !n_seeds) return TPCCA_E_INVALID;
+  if (!c->last_ok) return fail(c, TPCCA_E_INVALID, "no successful tracking call to inspect");
+  const Ws& w = c->w;
+  const int64_t ns = c->last_nseeds;
+  *n_seeds = ns;
+  if (cap < ns) return fail(c, TPCCA_E_CAPACITY, "seed capacity too small");
+  if (ns == 0) return TPCCA_OK;
+  std::vector<uint32_t> seeds(ns), cid(w.N);
+  std::vector<int32_t> nh(ns), hits((size_t)ns * w.R);
+  std::vector<float> state((size_t)ns * kTl);
+  hipError_t he = hipMemcpy(seeds.data(), w.seeds, 4 * ns, hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(cid.data(), w.cid, 4 * w.N, hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(nh.data(), w.tl_nhits, 4 * ns, hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(hits.data(), w.tl_hits, 4 * (size_t)ns * w.R, hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(state.data(), w.tl_state, 4 * (size_t)ns * kTl, hipMemcpyDeviceToHost);
+  std::vector<int32_t> rng(ns);
+  if (he == hipSuccess) he = hipMemcpy(rng.data(), w.tl_range, 4 * ns, hipMemcpyDeviceToHost);
+  if (he != hipSuccess) return hip_fail(c, he, "debug download");
+  for (int64_t s = 0; s < ns; ++s) {
+    if (seed_start) seed_start[s] = cid[seeds[s]];
+    if (seed_nhits) seed_nhits[s] = nh[s];
+    if (seed_hits) {
+      const int rlo = rng[s] & 0xFFFF, rhi = rng[s] >> 16;
+      for (int r = 0; r < w.R; ++r) {
+        const int32_t h = hits[(size_t)s * w.R + r];
+        seed_hits[(size_t)s * w.R + r] = (nh[s] > 0 && r >= rlo && r <= rhi && h >= 0) ? (int32_t)cid[h] : -1;
+      }
+    }
+    if (seed_state) std::memcpy(seed_state + (size_t)s * kTl, state.data() + (size_t)s * kTl, sizeof(float) * kTl);
+  }
+  return TPCCA_OK;
+}
+
+int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
+  (void)t; (void)cal; (void)g;
+  if (!c) return TPCCA_E_INVALID;
+  return fail(c, TPCCA_E_INVALID, "refit_grad: not available in this build");
+}
+
+}  // extern "C"

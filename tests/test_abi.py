@@ -1,0 +1,59 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, and its default constants equal the oracle's (the two
+define them independently)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tpcca.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpcca_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1712_09434_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1712_09434_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert "tpcca_track" in names and "tpcca_refit_grad" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1712_09434_amd import _abi
+    assert sorted(_abi.EXPORTED) == sorted(names)
+
+
+def test_default_params_match_oracle(lib, orc):
+    from paper_1712_09434_amd import _abi
+    a = _abi.default_params().as_dict()
+    b = orc.default_params().as_dict()
+    assert a == b
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1712_09434_amd import _abi
+    saved = _abi._lib
+    try:
+        _abi._lib = None
+        with pytest.raises(RuntimeError):
+            _abi.load(str(tmp_path / "nope.so"))
+    finally:
+        _abi._lib = saved
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    from paper_1712_09434_amd import _abi
+    ctx = ctypes.c_void_p()
+    assert lib.tpcca_create(None, None, ctypes.byref(ctx)) == _abi.TPCCA_E_INVALID
+    assert lib.tpcca_track(None, None, None) == _abi.TPCCA_E_INVALID
