@@ -152,6 +152,14 @@ typedef struct {
   int32_t mem;
 } tpcca_grad;
 
+/* Launch tuning (no effect on results).  ckpt_every: Kalman states kept
+ * every that many hit steps by the gradient's forward pass (1..160, default
+ * 12); tracklet_grid: workgroups of the tracklet kernel, 0 = automatic. */
+typedef struct {
+  int32_t ckpt_every;
+  int32_t tracklet_grid;
+} tpcca_tuning;
+
 /* Default constants (host call, no context needed). */
 void tpcca_default_params(tpcca_params* p);
 
@@ -203,6 +211,10 @@ int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_cal
  * cap is too small (required size in *n_seeds). */
 int tpcca_debug_tracklets(tpcca_ctx* ctx, int64_t cap, int64_t* n_seeds, uint32_t* seed_start,
                           int32_t* seed_nhits, int32_t* seed_hits, float* seed_state);
+
+/* Replace / read the launch tuning of a context (results never change). */
+int tpcca_set_tuning(tpcca_ctx* ctx, const tpcca_tuning* t);
+int tpcca_get_tuning(const tpcca_ctx* ctx, tpcca_tuning* t);
 
 /* Per-phase timing of tracking calls (HIP events recorded on the caller's
  * stream between the kernels).  tpcca_set_phase_timing(ctx, 1) enables it

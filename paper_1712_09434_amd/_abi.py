@@ -26,7 +26,8 @@ ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "
 
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
-            "tpcca_set_phase_timing", "tpcca_phase_times", "tpcca_last_error", "tpcca_destroy"]
+            "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
+            "tpcca_last_error", "tpcca_destroy"]
 
 
 class tpcca_geometry(C.Structure):
@@ -48,6 +49,10 @@ class tpcca_params(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class tpcca_tuning(C.Structure):
+    _fields_ = [("ckpt_every", C.c_int32), ("tracklet_grid", C.c_int32)]
 
 
 class tpcca_clusters(C.Structure):
@@ -106,6 +111,10 @@ def load(path: str = LIB_PATH):
     L.tpcca_refit_grad.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]
     L.tpcca_debug_tracklets.argtypes = [C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]
+    L.tpcca_set_tuning.argtypes = [C.c_void_p, P(tpcca_tuning)]
+    L.tpcca_set_tuning.restype = C.c_int
+    L.tpcca_get_tuning.argtypes = [C.c_void_p, P(tpcca_tuning)]
+    L.tpcca_get_tuning.restype = C.c_int
     L.tpcca_set_phase_timing.argtypes = [C.c_void_p, C.c_int]
     L.tpcca_set_phase_timing.restype = C.c_int
     L.tpcca_phase_times.argtypes = [C.c_void_p, C.c_int32, P(C.c_char_p), P(C.c_double), P(C.c_int64)]

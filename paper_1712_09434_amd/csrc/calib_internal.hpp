@@ -1,0 +1,50 @@
+// calib_internal.hpp -- workspace of the calibration gradient (not ABI).
+#pragma once
+#include "internal.hpp"
+
+namespace tpcca {
+
+constexpr int kPart = 68;                       // per-track partials: 66 parameters, chi2, pad
+constexpr int kNPar = TPCCA_NPAR_PER_SECTOR;    // 66 per sector
+constexpr int kChunk = 256;                     // tracks per first-level reduction chunk
+
+struct CalWs {
+  int S, R;
+  float L, x_first, x_span, tan_a;
+  Model m;
+  float sv2, st2;          // vertex and external tan(lambda) variances
+  int K;                   // checkpoint stride (hit steps)
+  int nck, nseg;           // checkpoints and segment slots per track
+  int64_t T, H, NC;        // tracks, hits, clusters
+  const int32_t* hit_off;
+  const uint32_t* hit_id;
+  const float* k_prior;
+  const float* ext_tgl;    // may be null
+  const uint8_t* use_vertex;  // may be null
+  const float* cx;
+  const float* cy;
+  const float* cz;
+  const uint8_t* csec;
+  const float* dl;
+  const float* tau;
+  const float* map;
+  float* hx;
+  float* hy;
+  float* hz;
+  float* gx;
+  float* gy;
+  float* gz;
+  float* part;             // [T][kPart]
+  int32_t* tflag;          // [T] 0 failed, 1 hits only, 2 with vertex terms
+  int32_t* tndf;           // [T]
+  float* ckpt;             // [T][nck][20]
+  float* seg;              // [T][nseg][20]
+  double* chunk;           // [nchunk][S*66 + 1]
+  double* out;             // [S*66 + 1]: per sector (delta, tau, map[64]), then chi2
+  unsigned long long* ndf_sum;
+  uint32_t* err;
+};
+
+hipError_t run_calib(const CalWs& c, hipStream_t st);
+
+}  // namespace tpcca

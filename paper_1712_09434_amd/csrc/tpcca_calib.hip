@@ -1,0 +1,617 @@
+// tpcca_calib.hip -- chi2(theta) of fixed hit lists and its gradient on gfx950.
+//
+// Paper, Sec. "Approach for online calibration" and Sec. "Overview of HLT
+// online calibration": the calibration runs on default-transformed clusters,
+// joined to the tracks by the unchanged cluster index, and feeds a new
+// transformation map back to tracking.  Here the map is a correction C_theta
+// (per-sector drift-velocity scale and time offset, an 8x8 cubic B-spline
+// radial displacement map per sector) and the feedback becomes gradient
+// descent on the total Kalman-refit chi2 of a frozen track set:
+//   1. calibrate the clusters of every hit (FP32);
+//   2. one lane per track: forward Kalman refit (outermost hit first, q/pT
+//      prior, then the primary vertex as a measured point and an external
+//      tan(lambda)), checkpointing the state every K steps; then a
+//      hand-written reverse sweep that recomputes each segment from its
+//      checkpoint and propagates adjoints through every update and transport
+//      (second derivatives of the transport by 3-direction dual numbers);
+//   3. per-track FP32 partial derivatives of the 66 parameters of its sector;
+//   4. FP64 reduction over tracks in a fixed order (no atomics on floats).
+#include <algorithm>
+
+#include "calib_internal.hpp"
+
+namespace tpcca {
+namespace {
+
+constexpr int TB = 256;
+
+// ------------------------------------------------------------ dual numbers
+struct D3 {
+  float v, d0, d1, d2;
+};
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
+__device__ __forceinline__ D3 operator-(D3 a) { return D3{-a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ D3 operator*(D3 a, D3 b) {
+  return D3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
+}
+__device__ __forceinline__ D3 operator*(D3 a, float b) { return D3{a.v * b, a.d0 * b, a.d1 * b, a.d2 * b}; }
+__device__ __forceinline__ D3 operator*(float b, D3 a) { return D3{b * a.v, b * a.d0, b * a.d1, b * a.d2}; }
+__device__ __forceinline__ D3 operator+(D3 a, float b) { return D3{a.v + b, a.d0, a.d1, a.d2}; }
+__device__ __forceinline__ D3 operator+(float b, D3 a) { return D3{b + a.v, a.d0, a.d1, a.d2}; }
+__device__ __forceinline__ D3 operator-(float b, D3 a) { return D3{b - a.v, -a.d0, -a.d1, -a.d2}; }
+__device__ __forceinline__ D3 operator/(D3 a, D3 b) {
+  const float q = a.v / b.v;
+  return D3{q, (a.d0 - q * b.d0) / b.v, (a.d1 - q * b.d1) / b.v, (a.d2 - q * b.d2) / b.v};
+}
+__device__ __forceinline__ D3 dsqrt(D3 a) {
+  const float s = sqrtf(a.v);
+  const float h = 0.5f / s;
+  return D3{s, a.d0 * h, a.d1 * h, a.d2 * h};
+}
+
+// The transport's scalar chain (same expressions as the tracking transport)
+// in dual numbers over (s0, k, dx): the chord rise dy, the path l and the
+// Jacobian entries a = d dy/d s0, b = d dy/d k, ls = d l/d s0,
+// lk = d l/d k, each with its derivatives along (s0, k, dx).
+struct TDer { D3 dy, l, a, b, ls, lk; };
+__device__ __forceinline__ TDer transport_duals(float s0v, float kv, float dxv, float kfac) {
+  const float A1 = 1.0f / 6.0f, A2 = 3.0f / 40.0f, A3 = 5.0f / 112.0f, A4 = 35.0f / 1152.0f;
+  const float B1 = 1.0f / 3.0f, B2 = 3.0f / 10.0f, B3 = 15.0f / 56.0f, B4 = 35.0f / 144.0f;
+  const D3 s0{s0v, 1.f, 0.f, 0.f}, k{kv, 0.f, 1.f, 0.f}, dx{dxv, 0.f, 0.f, 1.f};
+  const D3 kap = kfac * k;
+  const D3 f = kfac * dx;
+  TDer r;
+  const D3 s1 = s0 + kap * dx;
+  const D3 c0 = dsqrt(1.0f - s0 * s0);
+  const D3 c1 = dsqrt(1.0f - s1 * s1);
+  const D3 ss = s0 + s1, cc = c0 + c1;
+  const D3 tn = ss / cc;
+  r.dy = dx * tn;
+  D3 d = dsqrt(dx * dx + r.dy * r.dy);
+  if (dxv < 0.0f) d = -d;
+  const D3 u = (kap * d) * 0.5f;
+  const D3 u2 = u * u;
+  const D3 g = 1.0f + u2 * (A1 + u2 * (A2 + u2 * (A3 + u2 * A4)));
+  const D3 gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));
+  r.l = d * g;
+  const D3 t0 = s0 / c0, t1 = s1 / c1;
+  const D3 dtn_ds = (2.0f + tn * (t0 + t1)) / cc;
+  const D3 dtn_dk = (f * (1.0f + tn * t1)) / cc;
+  r.a = dx * dtn_ds;
+  r.b = dx * dtn_dk;
+  const D3 dd_ds = (r.dy * r.a) / d;
+  const D3 dd_dk = (r.dy * r.b) / d;
+  const D3 du_ds = (kap * dd_ds) * 0.5f;
+  const D3 du_dk = (kfac * d + kap * dd_dk) * 0.5f;
+  r.ls = dd_ds * g + (d * gp) * du_ds;
+  r.lk = dd_dk * g + (d * gp) * du_dk;
+  return r;
+}
+
+// ---------------------------------------------------------- small matrices
+__device__ __forceinline__ void unpack(const float c[15], float M[5][5]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) M[i][j] = c[sym(i, j)];
+}
+
+// Adjoint of the transport step x -> x + dx at pre-step state (P, C).
+// In: gP = d chi2/d P', G = d chi2/d C' (symmetric, packed).  Out: gP, G
+// replaced by the adjoints of (P, C); returns d chi2/d dx.
+__device__ float transport_adjoint(const float P[5], const float Cp[15], float dx, float kfac,
+                                   float gP[5], float G[15]) {
+  const TDer T = transport_duals(P[2], P[4], dx, kfac);
+  const float t = P[3];
+  const float kap = kfac * P[4];
+  float F[5][5] = {};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) F[i][i] = 1.0f;
+  F[0][2] = T.a.v; F[0][4] = T.b.v;
+  F[1][2] = t * T.ls.v; F[1][3] = T.l.v; F[1][4] = t * T.lk.v;
+  F[2][4] = kfac * dx;
+  float Cm[5][5], Gm[5][5];
+  unpack(Cp, Cm);
+  unpack(G, Gm);
+  // M = F C, N = G M; dF = 2 N (only the non-constant entries are needed)
+  float M[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s += F[i][k] * Cm[k][j];
+      M[i][j] = s;
+    }
+  auto N = [&](int i, int j) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s += Gm[i][k] * M[k][j];
+    return 2.0f * s;
+  };
+  const float dF02 = N(0, 2), dF04 = N(0, 4), dF12 = N(1, 2), dF13 = N(1, 3), dF14 = N(1, 4), dF24 = N(2, 4);
+  // new G = F^T G F
+  float GF[5][5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s += Gm[i][k] * F[k][j];
+      GF[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) s += F[k][i] * GF[k][j];
+      G[sym(i, j)] = s;
+    }
+  // state adjoint: F^T g, plus the dependence of F on (s0, t, k) and dx
+  float ng[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) s += F[i][j] * gP[i];
+    ng[j] = s;
+  }
+  ng[2] += dF02 * T.a.d0 + dF04 * T.b.d0 + dF12 * t * T.ls.d0 + dF13 * T.l.d0 + dF14 * t * T.lk.d0;
+  ng[4] += dF02 * T.a.d1 + dF04 * T.b.d1 + dF12 * t * T.ls.d1 + dF13 * T.l.d1 + dF14 * t * T.lk.d1;
+  ng[3] += dF12 * T.ls.v + dF14 * T.lk.v;
+  float gdx = dF02 * T.a.d2 + dF04 * T.b.d2 + dF12 * t * T.ls.d2 + dF13 * T.l.d2 + dF14 * t * T.lk.d2 +
+              dF24 * kfac;
+  gdx += gP[0] * T.dy.d2 + gP[1] * t * T.l.d2 + gP[2] * kap;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) gP[i] = ng[i];
+  return gdx;
+}
+
+// Adjoint of the (y, z) update at pre-update state (P, C) with measurement m.
+// Adds d chi2/d m to gm[2] and replaces (gP, G) by the adjoints of (P, C).
+__device__ void update_adjoint(const float P[5], const float Cp[15], float my, float mz, float vy,
+                               float vz, float gP[5], float G[15], float gm[2]) {
+  const float r0 = my - P[0], r1 = mz - P[1];
+  const float S00 = Cp[0] + vy, S01 = Cp[1], S11 = Cp[5] + vz;
+  const float det = S00 * S11 - S01 * S01;
+  const float W00 = S11 / det, W01 = -S01 / det, W11 = S00 / det;
+  float K[5][2];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const float c0 = Cp[sym(i, 0)], c1 = Cp[sym(i, 1)];
+    K[i][0] = c0 * W00 + c1 * W01;
+    K[i][1] = c0 * W01 + c1 * W11;
+  }
+  const float Wr0 = W00 * r0 + W01 * r1, Wr1 = W01 * r0 + W11 * r1;
+  float Ktg0 = 0.f, Ktg1 = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) { Ktg0 += K[i][0] * gP[i]; Ktg1 += K[i][1] * gP[i]; }
+  const float br0 = 2.0f * Wr0 + Ktg0, br1 = 2.0f * Wr1 + Ktg1;
+  float Gm[5][5];
+  unpack(G, Gm);
+  float GK[5][2];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) { a += Gm[i][k] * K[k][0]; b += Gm[i][k] * K[k][1]; }
+    GK[i][0] = a; GK[i][1] = b;
+  }
+  // bar S = -Wr Wr^T - sym(Ktg Wr^T) + K^T G K
+  float KGK00 = 0.f, KGK01 = 0.f, KGK11 = 0.f;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    KGK00 += K[k][0] * GK[k][0];
+    KGK01 += K[k][0] * GK[k][1];
+    KGK11 += K[k][1] * GK[k][1];
+  }
+  const float bS00 = -Wr0 * Wr0 - Ktg0 * Wr0 + KGK00;
+  const float bS11 = -Wr1 * Wr1 - Ktg1 * Wr1 + KGK11;
+  const float bS01 = -Wr0 * Wr1 - 0.5f * (Ktg0 * Wr1 + Ktg1 * Wr0) + KGK01;
+  // bar C = G - G K H - H^T K^T G + sym(g v^T) + H^T bar S H,  v = (Wr0, Wr1, 0, 0, 0)
+  const float v[5] = {Wr0, Wr1, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      float s = Gm[i][j];
+      if (j < 2) s -= GK[i][j];
+      if (i < 2) s -= GK[j][i];
+      s += 0.5f * (gP[i] * v[j] + v[i] * gP[j]);
+      if (i < 2 && j < 2) s += (i == 0 && j == 0) ? bS00 : (i == 1 && j == 1) ? bS11 : bS01;
+      G[sym(i, j)] = s;
+    }
+  gm[0] += br0;
+  gm[1] += br1;
+  gP[0] -= br0;
+  gP[1] -= br1;
+}
+
+// Adjoint of a scalar update of component q (measurement constant).
+__device__ void update1_adjoint(const float P[5], const float Cp[15], int q, float m, float var,
+                                float gP[5], float G[15]) {
+  const float S = Cp[sym(q, q)] + var;
+  const float W = 1.0f / S;
+  const float r = m - P[q];
+  float K[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) K[i] = Cp[sym(i, q)] * W;
+  const float Wr = W * r;
+  float Ktg = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) Ktg += K[i] * gP[i];
+  const float br = 2.0f * Wr + Ktg;
+  float Gm[5][5];
+  unpack(G, Gm);
+  float GK[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a += Gm[i][k] * K[k];
+    GK[i] = a;
+  }
+  float KGK = 0.f;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) KGK += K[k] * GK[k];
+  const float bS = -Wr * Wr - Ktg * Wr + KGK;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) {
+      float s = Gm[i][j];
+      if (j == q) s -= GK[i];
+      if (i == q) s -= GK[j];
+      const float vi = i == q ? Wr : 0.f, vj = j == q ? Wr : 0.f;
+      s += 0.5f * (gP[i] * vj + vi * gP[j]);
+      if (i == q && j == q) s += bS;
+      G[sym(i, j)] = s;
+    }
+  gP[q] -= br;
+}
+
+// Scalar update of component q (forward).
+__device__ __forceinline__ void update1(float p[5], float C[15], int q, float m, float var, float& chi2) {
+  const float S = C[sym(q, q)] + var;
+  float row[5], K[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) row[j] = C[sym(q, j)];
+  const float r = m - p[q];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) K[i] = row[i] / S;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + K[i] * r;
+#pragma unroll
+  for (int i = 0; i < 5; ++i)
+#pragma unroll
+    for (int j = i; j < 5; ++j) C[sym(i, j)] = C[sym(i, j)] - K[i] * row[j];
+  chi2 = chi2 + (r * r) / S;
+}
+
+__device__ __forceinline__ void save(float* dst, const float p[5], const float C[15]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) dst[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) dst[5 + i] = C[i];
+}
+__device__ __forceinline__ void load(const float* src, float p[5], float C[15]) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) p[i] = src[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) C[i] = src[5 + i];
+}
+
+// The 8 clamped uniform cubic B-splines (knots 0,0,0,0,.2,.4,.6,.8,1,1,1,1)
+// at u, by the Cox-de Boor recursion over the one non-empty span.
+__device__ __forceinline__ void bspline8(float u, float B[8]) {
+  u = fminf(fmaxf(u, 0.0f), 1.0f);
+  const float kn[12] = {0.f, 0.f, 0.f, 0.f, 0.2f, 0.4f, 0.6f, 0.8f, 1.f, 1.f, 1.f, 1.f};
+  int span = 3;
+#pragma unroll
+  for (int i = 4; i <= 7; ++i) if (u >= kn[i]) span = i;
+  float N[4] = {1.f, 0.f, 0.f, 0.f};
+  float left[4], right[4];
+#pragma unroll
+  for (int j = 1; j <= 3; ++j) {
+    left[j] = u - kn[span + 1 - j];
+    right[j] = kn[span + j] - u;
+    float saved = 0.f;
+#pragma unroll
+    for (int r = 0; r < j; ++r) {
+      const float den = right[r + 1] + left[j - r];
+      const float tmp = den != 0.f ? N[r] / den : 0.f;
+      N[r] = saved + right[r + 1] * tmp;
+      saved = left[j - r] * tmp;
+    }
+    N[j] = saved;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) B[i] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) B[span - 3 + j] = N[j];
+}
+
+// ------------------------------------------------------- 1. calibrate hits
+__global__ __launch_bounds__(TB) void k_cal_hits(CalWs c) {
+  for (int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x; j < c.H; j += (int64_t)gridDim.x * TB) {
+    const uint32_t id = c.hit_id[j];
+    c.gx[j] = 0.f; c.gy[j] = 0.f; c.gz[j] = 0.f;
+    if ((int64_t)id >= c.NC) { atomicOr(c.err, 1u); c.hx[j] = c.hy[j] = c.hz[j] = 0.f; continue; }
+    const int s = c.csec[id];
+    if (s >= c.S) { atomicOr(c.err, 1u); c.hx[j] = c.hy[j] = c.hz[j] = 0.f; continue; }
+    const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
+    const float side = s < c.S / 2 ? 1.0f : -1.0f;
+    const float dl = c.dl[s], tau = c.tau[s];
+    c.hz[j] = side * (c.L - (1.0f + dl) * ((c.L - side * z) - tau));
+    float Ba[8], Bb[8];
+    bspline8((x - c.x_first) / c.x_span, Ba);
+    bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
+    const float* cm = c.map + s * 64;
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      float ra = 0.f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) ra += cm[a * 8 + b] * Bb[b];
+      acc += Ba[a] * ra;
+    }
+    c.hx[j] = x + acc;
+    c.hy[j] = y;
+  }
+}
+
+// ------------------------------------------- 2. forward + reverse per track
+__global__ __launch_bounds__(TB) void k_cal_adjoint(CalWs c) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < c.T; t += (int64_t)gridDim.x * TB) {
+    const int32_t b0 = c.hit_off[t];
+    const int nh = c.hit_off[t + 1] - b0;
+    float* part = c.part + t * kPart;
+    c.tflag[t] = 0;
+    c.tndf[t] = 0;
+    part[66] = 0.f;
+    if (nh < 3 || nh > c.R) { if (nh > c.R || nh < 0) atomicOr(c.err, 2u); continue; }
+    // k-th processed hit (outermost first) is hit index jk(k)
+    auto jk = [&](int k) { return (int64_t)b0 + nh - 1 - k; };
+    const Model& m = c.m;
+    float p[5], C[15];
+    float sdir, tdir;
+    const int64_t j0 = jk(0), j2 = jk(2);
+    chord_dir(c.hx[j2], c.hy[j2], c.hz[j2], c.hx[j0], c.hy[j0], c.hz[j0], sdir, tdir);
+    p[0] = c.hy[j0]; p[1] = c.hz[j0]; p[2] = sdir; p[3] = tdir; p[4] = c.k_prior[t];
+    init_cov(C, m.vy, m.vz);
+    if (!(fabsf(sdir) < m.sin_max)) continue;
+    float* ck = c.ckpt + t * (int64_t)c.nck * 20;
+    float* sg = c.seg + t * (int64_t)c.nseg * 20;
+    float chi2 = 0.f;
+    bool ok = true;
+    float xc = c.hx[j0];
+    for (int k = 1; k < nh; ++k) {
+      if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
+      const int64_t j = jk(k);
+      const float hx = c.hx[j];
+      if (!transport(p, C, xc, hx, m)) { ok = false; break; }
+      update(p, C, c.hy[j], c.hz[j], m, chi2);
+      xc = hx;
+    }
+    if (!ok) continue;
+    // vertex and external tan(lambda)
+    const bool uv = c.use_vertex && c.use_vertex[t];
+    const bool ue = uv && c.ext_tgl;
+    int flag = 1;
+    int nsub = 0;
+    float last_p[5], last_C[15];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) last_p[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) last_C[i] = C[i];
+    const float x_last = xc;
+    if (uv) {
+      nsub = (int)ceilf(x_last / 10.0f);
+      bool vok = nsub <= c.nseg - 2 && nsub >= 1;
+      float q[5], Q[15];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) q[i] = p[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) Q[i] = C[i];
+      float xv = x_last;
+      for (int s = 0; vok && s < nsub; ++s) {
+        const float xt = 10.0f * (float)(nsub - 1 - s);
+        if (!transport(q, Q, xv, xt, m)) { vok = false; break; }
+        xv = xt;
+      }
+      if (vok) {
+        float c2 = chi2;
+        update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, c2);
+        if (ue) update1(q, Q, 3, c.ext_tgl[t], c.st2, c2);
+        chi2 = c2;
+        flag = 2;
+      }
+    }
+    c.tflag[t] = flag;
+    c.tndf[t] = 2 * nh - 5 + (flag == 2 ? 2 + (ue ? 1 : 0) : 0);
+    part[66] = chi2;
+    // ---------------------------------------------------------- reverse
+    float gP[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, G[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) G[i] = 0.f;
+    if (flag == 2) {
+      // recompute the tail, keeping each pre-step state
+      float q[5], Q[15];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) q[i] = last_p[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) Q[i] = last_C[i];
+      float xv = x_last;
+      for (int s = 0; s < nsub; ++s) {
+        save(sg + s * 20, q, Q);
+        const float xt = 10.0f * (float)(nsub - 1 - s);
+        transport(q, Q, xv, xt, m);
+        xv = xt;
+      }
+      save(sg + nsub * 20, q, Q);                    // before the vertex update
+      if (ue) {
+        float dummy = 0.f;
+        update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, dummy);
+        update1_adjoint(q, Q, 3, c.ext_tgl[t], c.st2, gP, G);
+        load(sg + nsub * 20, q, Q);
+      }
+      float gm[2] = {0.f, 0.f};
+      update_adjoint(q, Q, 0.0f, 0.0f, c.sv2, c.sv2, gP, G, gm);
+      for (int s = nsub - 1; s >= 0; --s) {
+        load(sg + s * 20, q, Q);
+        const float xf = s == 0 ? x_last : 10.0f * (float)(nsub - s);
+        const float xt = 10.0f * (float)(nsub - 1 - s);
+        const float gdx = transport_adjoint(q, Q, xt - xf, m.kfac, gP, G);
+        if (s == 0) c.gx[jk(nh - 1)] -= gdx;
+      }
+    }
+    // hit steps, segment by segment from the last
+    const int nsteps = nh - 1;
+    for (int sgi = (nsteps - 1) / c.K; sgi >= 0; --sgi) {
+      const int k1 = 1 + sgi * c.K;
+      const int k2 = min(nsteps, k1 + c.K - 1);
+      float q[5], Q[15];
+      load(ck + sgi * 20, q, Q);
+      float xv = c.hx[jk(k1 - 1)];
+      float dummy = 0.f;
+      for (int k = k1; k <= k2; ++k) {
+        save(sg + (k - k1) * 20, q, Q);
+        const int64_t j = jk(k);
+        const float hx = c.hx[j];
+        transport(q, Q, xv, hx, m);
+        update(q, Q, c.hy[j], c.hz[j], m, dummy);
+        xv = hx;
+      }
+      for (int k = k2; k >= k1; --k) {
+        const int64_t j = jk(k), jp = jk(k - 1);
+        float a[5], A[15];
+        load(sg + (k - k1) * 20, a, A);
+        const float xf = c.hx[jp], xt = c.hx[j];
+        float b[5], B[15];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) b[i] = a[i];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) B[i] = A[i];
+        transport(b, B, xf, xt, m);
+        float gm[2] = {0.f, 0.f};
+        update_adjoint(b, B, c.hy[j], c.hz[j], m.vy, m.vz, gP, G, gm);
+        c.gy[j] += gm[0];
+        c.gz[j] += gm[1];
+        const float gdx = transport_adjoint(a, A, xt - xf, m.kfac, gP, G);
+        c.gx[j] += gdx;
+        c.gx[jp] -= gdx;
+      }
+    }
+    // initial state: (y, z) of the outermost hit, direction from the chord
+    {
+      c.gy[j0] += gP[0];
+      c.gz[j0] += gP[1];
+      const float dX = c.hx[j0] - c.hx[j2], dY = c.hy[j0] - c.hy[j2], dZ = c.hz[j0] - c.hz[j2];
+      const float rho = sqrtf(dX * dX + dY * dY);
+      const float r3 = rho * rho * rho;
+      const float gs = gP[2], gt = gP[3];
+      const float gdX = gs * (-dY * dX / r3) + gt * (-dZ * dX / r3);
+      const float gdY = gs * (dX * dX / r3) + gt * (-dZ * dY / r3);
+      const float gdZ = gt / rho;
+      c.gx[j0] += gdX; c.gx[j2] -= gdX;
+      c.gy[j0] += gdY; c.gy[j2] -= gdY;
+      c.gz[j0] += gdZ; c.gz[j2] -= gdZ;
+    }
+  }
+}
+
+// ------------------------------------------ 3. per-track parameter partials
+// One wave per track: lane l owns map coefficient (l / 8, l % 8); lanes 0
+// and 1 also own the drift scale and the time offset.  Sums run over the
+// track's hits in order (FP32).
+__global__ __launch_bounds__(64) void k_cal_partials(CalWs c) {
+  const int64_t t = blockIdx.x;
+  const int l = threadIdx.x;
+  float* part = c.part + t * kPart;
+  const int32_t b0 = c.hit_off[t];
+  const int nh = c.hit_off[t + 1] - b0;
+  float acc = 0.f, accd = 0.f;
+  if (c.tflag[t] > 0) {
+    const int s = c.csec[c.hit_id[b0]];
+    const float side = s < c.S / 2 ? 1.0f : -1.0f;
+    const float dl = c.dl[s], tau = c.tau[s];
+    const int a = l >> 3, b = l & 7;
+    for (int i = 0; i < nh; ++i) {
+      const int64_t j = b0 + i;
+      const uint32_t id = c.hit_id[j];
+      const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
+      float Ba[8], Bb[8];
+      bspline8((x - c.x_first) / c.x_span, Ba);
+      bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
+      acc += c.gx[j] * (Ba[a] * Bb[b]);
+      if (l == 0) accd += c.gz[j] * (-side * ((c.L - side * z) - tau));
+      if (l == 1) accd += c.gz[j] * (side * (1.0f + dl));
+    }
+  }
+  part[2 + l] = acc;
+  if (l < 2) part[l] = accd;
+}
+
+// --------------------------------------------- 4. FP64 fixed-order reduction
+// chunk[ch][s*66 + p] = sum over the tracks of chunk ch (ascending) in sector s
+// of part[t][p]; chunk[ch][S*66] = sum of the chunk's chi2.
+__global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
+  __shared__ int s_sec[kChunk];
+  const int64_t t0 = (int64_t)blockIdx.x * kChunk;
+  const int64_t nt = (c.T - t0) < kChunk ? (c.T - t0) : (int64_t)kChunk;
+  for (int i = threadIdx.x; i < kChunk; i += TB) {
+    int s = -1;
+    if (i < nt && c.tflag[t0 + i] > 0) s = c.csec[c.hit_id[c.hit_off[t0 + i]]];
+    s_sec[i] = s;
+  }
+  __syncthreads();
+  const int nq = c.S * kNPar + 1;
+  double* out = c.chunk + (int64_t)blockIdx.x * nq;
+  for (int q = threadIdx.x; q < nq; q += TB) {
+    double acc = 0.0;
+    if (q == c.S * kNPar) {
+      for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) acc += (double)c.part[(t0 + i) * kPart + 66];
+    } else {
+      const int s = q / kNPar, p = q % kNPar;
+      for (int i = 0; i < nt; ++i) if (s_sec[i] == s) acc += (double)c.part[(t0 + i) * kPart + p];
+    }
+    out[q] = acc;
+  }
+  for (int i = threadIdx.x; i < nt; i += TB)
+    if (c.tflag[t0 + i] > 0) atomicAdd(c.ndf_sum, (unsigned long long)c.tndf[t0 + i]);
+}
+
+__global__ __launch_bounds__(TB) void k_cal_final(CalWs c, int64_t nchunk) {
+  const int nq = c.S * kNPar + 1;
+  for (int q = blockIdx.x * TB + threadIdx.x; q < nq; q += gridDim.x * TB) {
+    double acc = 0.0;
+    for (int64_t ch = 0; ch < nchunk; ++ch) acc += c.chunk[ch * nq + q];
+    c.out[q] = acc;
+  }
+}
+
+__global__ void k_cal_zero(CalWs c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) { *c.ndf_sum = 0ull; *c.err = 0u; }
+}
+
+}  // namespace
+
+hipError_t run_calib(const CalWs& c, hipStream_t st) {
+  k_cal_zero<<<1, 64, 0, st>>>(c);
+  const unsigned bh = (unsigned)std::min<int64_t>(std::max<int64_t>((c.H + TB - 1) / TB, 1), 65536);
+  k_cal_hits<<<bh, TB, 0, st>>>(c);
+  const unsigned bt = (unsigned)std::min<int64_t>(std::max<int64_t>((c.T + TB - 1) / TB, 1), 65536);
+  k_cal_adjoint<<<bt, TB, 0, st>>>(c);
+  if (c.T > 0) k_cal_partials<<<dim3((unsigned)c.T), 64, 0, st>>>(c);
+  const int64_t nchunk = (c.T + kChunk - 1) / kChunk;
+  if (nchunk > 0) k_cal_chunks<<<dim3((unsigned)nchunk), TB, 0, st>>>(c);
+  k_cal_final<<<dim3((unsigned)((c.S * kNPar + 1 + TB - 1) / TB)), TB, 0, st>>>(c, nchunk);
+  return hipGetLastError();
+}
+
+}  // namespace tpcca

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "calib_internal.hpp"
 #include "internal.hpp"
 
 using namespace tpcca;
@@ -39,6 +40,8 @@ struct tpcca_ctx {
   // refit_grad scratch
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
+  // tuning
+  tpcca_tuning tune{12, 0};
   // phase timing
   bool timing = false;
   PhaseEvents pe{};
@@ -481,10 +484,176 @@ int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t*
   return TPCCA_OK;
 }
 
+int tpcca_set_tuning(tpcca_ctx* c, const tpcca_tuning* t) {
+  if (!c || !t) return TPCCA_E_INVALID;
+  if (t->ckpt_every < 1 || t->ckpt_every > 160 || t->tracklet_grid < 0)
+    return fail(c, TPCCA_E_INVALID, "invalid tuning values");
+  c->tune = *t;
+  return TPCCA_OK;
+}
+
+int tpcca_get_tuning(const tpcca_ctx* c, tpcca_tuning* t) {
+  if (!c || !t) return TPCCA_E_INVALID;
+  *t = c->tune;
+  return TPCCA_OK;
+}
+
 int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
-  (void)t; (void)cal; (void)g;
   if (!c) return TPCCA_E_INVALID;
-  return fail(c, TPCCA_E_INVALID, "refit_grad: not available in this build");
+  if (!t || !cal || !g || !t->clusters) return fail(c, TPCCA_E_INVALID, "null tracks, clusters, calib or grad");
+  const tpcca_clusters& k = *t->clusters;
+  const int64_t T = t->n_tracks, NC = k.n;
+  const int S = c->S;
+  if (T < 0 || NC < 0) return fail(c, TPCCA_E_INVALID, "negative sizes");
+  if (T > 0 && (!t->hit_off || !t->hit_id || !t->k_prior)) return fail(c, TPCCA_E_INVALID, "null hit_off/hit_id/k_prior");
+  if (NC > 0 && (!k.x || !k.y || !k.z || !k.sector)) return fail(c, TPCCA_E_INVALID, "null cluster arrays");
+  if (!cal->drift_scale || !cal->time_offset || !cal->map) return fail(c, TPCCA_E_INVALID, "null calibration arrays");
+  if (!g->d_drift_scale || !g->d_time_offset || !g->d_map) return fail(c, TPCCA_E_INVALID, "null gradient arrays");
+  for (int mk : {t->mem, k.mem, cal->mem, g->mem})
+    if (mk != TPCCA_MEM_HOST && mk != TPCCA_MEM_DEVICE) return fail(c, TPCCA_E_INVALID, "bad mem kind");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+  hipStream_t st = (hipStream_t)k.stream;
+  // number of hits
+  int32_t H32 = 0;
+  if (T > 0) {
+    if (t->mem == TPCCA_MEM_HOST) {
+      H32 = t->hit_off[T];
+      if (t->hit_off[0] != 0) return fail(c, TPCCA_E_INVALID, "hit_off[0] must be 0");
+    } else {
+      int32_t ends[2];
+      he = hipMemcpyAsync(&ends[0], t->hit_off, 4, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(&ends[1], t->hit_off + T, 4, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
+      if (ends[0] != 0) return fail(c, TPCCA_E_INVALID, "hit_off[0] must be 0");
+      H32 = ends[1];
+    }
+  }
+  const int64_t H = H32;
+  if (H < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
+  const int K = c->tune.ckpt_every;
+  const int nck = (c->R - 1 + K - 1) / K + 1;
+  const int nseg = std::max(K, 28);
+  const int64_t nchunk = (T + kChunk - 1) / kChunk;
+  const int nq = S * kNPar + 1;
+  // scratch layout
+  Layout L;
+  size_t o_hx = L.take<float>(H), o_hy = L.take<float>(H), o_hz = L.take<float>(H);
+  size_t o_gx = L.take<float>(H), o_gy = L.take<float>(H), o_gz = L.take<float>(H);
+  size_t o_part = L.take<float>(T * kPart);
+  size_t o_tf = L.take<int32_t>(T), o_tn = L.take<int32_t>(T);
+  size_t o_ck = L.take<float>(T * nck * 20), o_sg = L.take<float>(T * nseg * 20);
+  size_t o_chunk = L.take<double>(nchunk * nq), o_out = L.take<double>(nq);
+  size_t o_ndf = L.take<unsigned long long>(1), o_err = L.take<uint32_t>(1);
+  // staged copies of host inputs
+  const bool th = t->mem == TPCCA_MEM_HOST, kh = k.mem == TPCCA_MEM_HOST, ch = cal->mem == TPCCA_MEM_HOST;
+  size_t o_off = 0, o_ids = 0, o_kp = 0, o_ext = 0, o_uv = 0, o_cx = 0, o_cy = 0, o_cz = 0, o_cs = 0, o_th = 0;
+  if (th) {
+    o_off = L.take<int32_t>(T + 1); o_ids = L.take<uint32_t>(H); o_kp = L.take<float>(T);
+    o_ext = L.take<float>(T); o_uv = L.take<uint8_t>(T);
+  }
+  if (kh) { o_cx = L.take<float>(NC); o_cy = L.take<float>(NC); o_cz = L.take<float>(NC); o_cs = L.take<uint8_t>(NC); }
+  if (ch) o_th = L.take<float>(S * 66);
+  if (L.off > c->gscratch_bytes) {
+    if (c->gscratch) { (void)hipFree(c->gscratch); c->gscratch = nullptr; c->gscratch_bytes = 0; }
+    he = hipMalloc((void**)&c->gscratch, L.off + L.off / 4);
+    if (he != hipSuccess) { c->gscratch = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "gradient scratch allocation failed"); }
+    c->gscratch_bytes = L.off + L.off / 4;
+  }
+  char* b = c->gscratch;
+  CalWs w{};
+  w.S = S; w.R = c->R; w.L = c->z_max; w.tan_a = c->tan_a;
+  w.m = make_model(c->bz, c->P);
+  w.sv2 = c->P.sigma_vertex * c->P.sigma_vertex;
+  w.st2 = c->P.sigma_tgl * c->P.sigma_tgl;
+  w.K = K; w.nck = nck; w.nseg = nseg;
+  w.T = T; w.H = H; w.NC = NC;
+  {
+    // x_first and x_span of the map's radial coordinate
+    std::vector<float> rx(c->R);
+    he = hipMemcpy(rx.data(), c->row_x_d, sizeof(float) * c->R, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return hip_fail(c, he, "row table");
+    w.x_first = rx[0];
+    w.x_span = rx[c->R - 1] - rx[0];
+  }
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0 || !src) return hipSuccess;
+    return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  he = hipSuccess;
+  if (th) {
+    if (he == hipSuccess) he = up(o_off, t->hit_off, 4 * (T + 1));
+    if (he == hipSuccess) he = up(o_ids, t->hit_id, 4 * H);
+    if (he == hipSuccess) he = up(o_kp, t->k_prior, 4 * T);
+    if (he == hipSuccess) he = up(o_ext, t->ext_tgl, 4 * T);
+    if (he == hipSuccess) he = up(o_uv, t->use_vertex, T);
+    w.hit_off = (const int32_t*)(b + o_off); w.hit_id = (const uint32_t*)(b + o_ids);
+    w.k_prior = (const float*)(b + o_kp);
+    w.ext_tgl = t->ext_tgl ? (const float*)(b + o_ext) : nullptr;
+    w.use_vertex = t->use_vertex ? (const uint8_t*)(b + o_uv) : nullptr;
+  } else {
+    w.hit_off = t->hit_off; w.hit_id = t->hit_id; w.k_prior = t->k_prior;
+    w.ext_tgl = t->ext_tgl; w.use_vertex = t->use_vertex;
+  }
+  if (kh) {
+    if (he == hipSuccess) he = up(o_cx, k.x, 4 * NC);
+    if (he == hipSuccess) he = up(o_cy, k.y, 4 * NC);
+    if (he == hipSuccess) he = up(o_cz, k.z, 4 * NC);
+    if (he == hipSuccess) he = up(o_cs, k.sector, NC);
+    w.cx = (const float*)(b + o_cx); w.cy = (const float*)(b + o_cy); w.cz = (const float*)(b + o_cz);
+    w.csec = (const uint8_t*)(b + o_cs);
+  } else {
+    w.cx = k.x; w.cy = k.y; w.cz = k.z; w.csec = k.sector;
+  }
+  if (ch) {
+    if (he == hipSuccess) he = up(o_th, cal->drift_scale, 4 * S);
+    if (he == hipSuccess) he = up(o_th + 4 * S, cal->time_offset, 4 * S);
+    if (he == hipSuccess) he = up(o_th + 8 * S, cal->map, 4 * 64 * S);
+    w.dl = (const float*)(b + o_th); w.tau = (const float*)(b + o_th + 4 * S);
+    w.map = (const float*)(b + o_th + 8 * S);
+  } else {
+    w.dl = cal->drift_scale; w.tau = cal->time_offset; w.map = cal->map;
+  }
+  if (he != hipSuccess) return hip_fail(c, he, "input upload");
+  w.hx = (float*)(b + o_hx); w.hy = (float*)(b + o_hy); w.hz = (float*)(b + o_hz);
+  w.gx = (float*)(b + o_gx); w.gy = (float*)(b + o_gy); w.gz = (float*)(b + o_gz);
+  w.part = (float*)(b + o_part); w.tflag = (int32_t*)(b + o_tf); w.tndf = (int32_t*)(b + o_tn);
+  w.ckpt = (float*)(b + o_ck); w.seg = (float*)(b + o_sg);
+  w.chunk = (double*)(b + o_chunk); w.out = (double*)(b + o_out);
+  w.ndf_sum = (unsigned long long*)(b + o_ndf); w.err = (uint32_t*)(b + o_err);
+  he = run_calib(w, st);
+  if (he != hipSuccess) return hip_fail(c, he, "gradient kernels");
+  std::vector<double> out(nq);
+  unsigned long long ndf = 0;
+  uint32_t err = 0;
+  he = hipMemcpyAsync(out.data(), w.out, sizeof(double) * nq, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(&ndf, w.ndf_sum, 8, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(&err, w.err, 4, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "gradient");
+  if (err & 1u) return fail(c, TPCCA_E_INVALID, "hit id or sector out of range");
+  if (err & 2u) return fail(c, TPCCA_E_INVALID, "a track has more hits than pad rows");
+  std::vector<double> gd(S), gt(S), gm((size_t)S * 64);
+  for (int s = 0; s < S; ++s) {
+    gd[s] = out[s * kNPar + 0];
+    gt[s] = out[s * kNPar + 1];
+    for (int q = 0; q < 64; ++q) gm[(size_t)s * 64 + q] = out[s * kNPar + 2 + q];
+  }
+  g->chi2 = out[S * kNPar];
+  g->ndf = (int64_t)ndf;
+  if (g->mem == TPCCA_MEM_HOST) {
+    std::memcpy(g->d_drift_scale, gd.data(), 8 * S);
+    std::memcpy(g->d_time_offset, gt.data(), 8 * S);
+    std::memcpy(g->d_map, gm.data(), 8 * 64 * (size_t)S);
+  } else {
+    he = hipMemcpyAsync(g->d_drift_scale, gd.data(), 8 * S, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(g->d_time_offset, gt.data(), 8 * S, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(g->d_map, gm.data(), 8 * 64 * (size_t)S, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(c, he, "gradient download");
+  }
+  return TPCCA_OK;
 }
 
 }  // extern "C"
