@@ -42,6 +42,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sectors", default="0,13,18")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
+    ap.add_argument("--batch-reps", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -106,6 +109,9 @@ def main():
                "host_cpu": _cpu_model()}
         log(f"oracle {nsample / ct:.3e} clusters/s")
 
+    batch = None if args.no_batch else batch_leg(args, Tracker, dev)
+    grad = None if args.no_grad else grad_leg(Tracker, dev)
+
     line = {
         "metric": "clusters/sec tracked (central Pb-Pb-shaped event, 1 GPU)",
         "value": value, "unit": "clusters/s", "n_gpus": 1, "steps": args.steps,
@@ -117,9 +123,112 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
+        "batch": batch,
+        "grad": grad,
     }
     trk.close()
     print(json.dumps(line), flush=True)
+
+
+def _to_dev(ev, dev):
+    import numpy as np
+    import torch
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    return t(ev.x), t(ev.y), t(ev.z), t(ev.row), t(ev.sector)
+
+
+def batch_leg(args, Tracker, dev):
+    """64 events of lognormal multiplicity: one tpcca_track_batch call vs 64
+    back-to-back tpcca_track calls on the same stream (both with the tuned
+    launch setting)."""
+    import torch
+
+    import synth
+    from paper_1712_09434_amd import autotune
+
+    log("generating the 64-event batch")
+    evs = [synth.make_config("C4", e) for e in range(64)]
+    n = sum(e.n for e in evs)
+    side = torch.cuda.Stream(dev)
+    with torch.cuda.stream(side):
+        tens = [_to_dev(e, dev) for e in evs]
+        trk = Tracker.from_geometry(evs[0].geom)
+        tuned = autotune.autotune(trk, tens, reps=2, cache=None, log=log)
+        best = tuned["best"]
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        t_batch = timed(lambda: trk.track_batch(tens), args.batch_reps)
+
+        def seq():
+            for e in tens:
+                trk.track(*e)
+
+        # the sequential baseline gets its own best setting among the same candidates
+        seq_best = None
+        for g in sorted({0, best["tracklet_grid"]}):
+            for u in (0, 1):
+                trk.set_tuning(tracklet_grid=g, use_graph=u)
+                t = timed(seq, args.batch_reps)
+                if seq_best is None or t < seq_best[0]:
+                    seq_best = (t, g, u)
+        trk.close()
+    t_seq = seq_best[0]
+    log(f"batch: {n} clusters in 64 events: batched {t_batch * 1e3:.2f} ms, "
+        f"sequential {t_seq * 1e3:.2f} ms, gain {t_seq / t_batch:.2f}")
+    return {"events": 64, "clusters": n, "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
+            "gain": t_seq / t_batch, "batched_clusters_per_s": n / t_batch,
+            "batched_tuning": {"tracklet_grid": best["tracklet_grid"], "use_graph": best["use_graph"]},
+            "sequential_tuning": {"tracklet_grid": seq_best[1], "use_graph": seq_best[2]}}
+
+
+def grad_leg(Tracker, dev):
+    """Time tpcca_refit_grad on the tracks of one miscalibrated full event
+    (tracks with >= 40 hits, chi2/ndf <= 4 and a first hit within the first 11
+    pad rows; vertex and external tan(lambda) terms on)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1712_09434_amd import FitTracks
+
+    ev = synth.make_config("C5", 0)
+    cl = _to_dev(ev, dev)
+    trk = Tracker.from_geometry(ev.geom)
+    out = trk.track(*cl)
+    nh = (out.hit_off[1:] - out.hit_off[:-1]).cpu().numpy()
+    q = (out.chi2 / out.ndf).cpu().numpy()
+    off = out.hit_off.cpu().numpy()
+    ids = out.hit_id.cpu().numpy()
+    inner_row = ev.row[ids[off[:-1]]]
+    keep = np.nonzero((nh >= 40) & (q <= 4.0) & (inner_row <= 10))[0]
+    lists = [ids[off[t]:off[t + 1]] for t in keep]
+    hoff = np.concatenate([[0], np.cumsum([len(l) for l in lists])]).astype(np.int32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    fit = FitTracks(clusters=cl, hit_off=d(hoff), hit_id=d(np.concatenate(lists).astype(np.int32)),
+                    k_prior=out.k_prior[torch.from_numpy(keep).to(dev)].contiguous(),
+                    ext_tgl=out.p[torch.from_numpy(keep).to(dev), 3].contiguous(),
+                    use_vertex=torch.ones(len(keep), dtype=torch.uint8, device=dev))
+    th = torch.zeros(36 * 66, dtype=torch.float32, device=dev)
+    trk.refit_grad(fit, th)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        trk.refit_grad(fit, th)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    trk.close()
+    log(f"grad: {len(keep)} tracks, {int(hoff[-1])} hits, {dt * 1e3:.3f} ms per refit_grad")
+    return {"tracks": int(len(keep)), "hits": int(hoff[-1]), "ms_per_call": dt * 1e3,
+            "params": 36 * 66}
 
 
 def _cpu_model():

@@ -154,10 +154,14 @@ typedef struct {
 
 /* Launch tuning (no effect on results).  ckpt_every: Kalman states kept
  * every that many hit steps by the gradient's forward pass (1..160, default
- * 12); tracklet_grid: workgroups of the tracklet kernel, 0 = automatic. */
+ * 12); tracklet_grid: workgroups of the persistent tracklet kernel, 0 =
+ * automatic; use_graph: 1 = capture the kernel sequence of a tracking call
+ * in a hipGraph the first time a workspace shape is seen on a non-null
+ * stream and replay it afterwards (default 0). */
 typedef struct {
   int32_t ckpt_every;
   int32_t tracklet_grid;
+  int32_t use_graph;
 } tpcca_tuning;
 
 /* Default constants (host call, no context needed). */

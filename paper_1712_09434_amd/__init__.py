@@ -5,4 +5,5 @@ loads it and marshals torch tensors into its C ABI (``include/tpcca.h``).
 There is no CPU fallback: calls fail if the library is not built.
 """
 from ._abi import TpccaError, default_params, load  # noqa: F401
-from .tracker import Tracker, Tracks  # noqa: F401
+from .tracker import FitTracks, Tracker, Tracks  # noqa: F401
+from .calib import Chi2Refit, calibrate  # noqa: F401

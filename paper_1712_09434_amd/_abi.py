@@ -52,7 +52,7 @@ class tpcca_params(C.Structure):
 
 
 class tpcca_tuning(C.Structure):
-    _fields_ = [("ckpt_every", C.c_int32), ("tracklet_grid", C.c_int32)]
+    _fields_ = [("ckpt_every", C.c_int32), ("tracklet_grid", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class tpcca_clusters(C.Structure):

@@ -31,9 +31,10 @@ struct CalWs {
   float* hx;
   float* hy;
   float* hz;
-  float* gx;
+  float* gx;               // [H] dx-derivative of the step ending at the hit
   float* gy;
   float* gz;
+  float* gpt;              // [H] x-adjoint point terms (seed chord, vertex hop)
   float* part;             // [T][kPart]
   int32_t* tflag;          // [T] 0 failed, 1 hits only, 2 with vertex terms
   int32_t* tndf;           // [T]

@@ -21,7 +21,7 @@ enum : int {
   F_SEEDCTR = 4,    // work counter of the tracklet kernel
   F_COUNT = 8
 };
-enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u };
+enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u, ERR_STUCK = 4u };
 
 // Per-(event, sector, row) search grid: cells of a uniform 2-D (z, y) grid
 // over the row's bounding box; cell (iz, iy) = cell_base + iz * ny + iy.
@@ -79,6 +79,7 @@ struct Ws {
   Model m;
   tpcca_params P;
   float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
+  int tracklet_grid;    // workgroups of the tracklet kernel (0 = automatic)
   uint32_t* flags;      // [F_COUNT]
   // binning
   uint32_t* ru_count;   // [RU]
@@ -116,6 +117,11 @@ struct Ws {
   float* tl_state;      // [seed_cap * kTl]
   int32_t* tl_hits;     // [seed_cap * R]
   uint64_t* owner;      // [N]
+  int32_t* tl_own;      // [seed_cap * R] owned hits of accepted tracklets, outermost first
+  uint32_t* acc_flag;   // [seed_cap + 1]
+  uint32_t* acc_off;    // [seed_cap + 1] scanned acc_flag
+  uint32_t* acc_list;   // [seed_cap] accepted seeds
+  uint32_t* own_cnt;    // [seed_cap] owned hits of accepted and fitted tracklets
   // selection / refit / output
   float* rf;            // [seed_cap * kRf]
   uint32_t* trk_flag;   // [seed_cap + 1] -> scanned in place

@@ -33,7 +33,7 @@ __host__ __device__ constexpr int sym(int i, int j) {
 // by t times that path.  The covariance becomes F C F^T with the exact
 // Jacobian F of these expressions.  Returns false, leaving p and C
 // untouched, if |s1| would reach sin_max.
-__device__ __forceinline__ bool transport(float p[5], float C[15], float x0, float x1,
+__host__ __device__ __forceinline__ bool transport(float p[5], float C[15], float x0, float x1,
                                           const Model& m) {
   const float dx = x1 - x0;
   if (dx == 0.0f) return true;
@@ -109,7 +109,7 @@ __device__ __forceinline__ bool transport(float p[5], float C[15], float x0, flo
 // Kalman update with the cluster (my, mz): H = [I2 0], V = diag(vy, vz).
 // Gain from the explicit 2x2 inverse of S = H C H^T + V; chi2 increment
 // r^T S^-1 r.
-__device__ __forceinline__ void update(float p[5], float C[15], float my, float mz,
+__host__ __device__ __forceinline__ void update(float p[5], float C[15], float my, float mz,
                                        const Model& m, float& chi2) {
   const float r0 = my - p[0];
   const float r1 = mz - p[1];
@@ -137,7 +137,7 @@ __device__ __forceinline__ void update(float p[5], float C[15], float my, float 
   chi2 = chi2 + (r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
 }
 
-__device__ __forceinline__ void init_cov(float C[15], float vy, float vz) {
+__host__ __device__ __forceinline__ void init_cov(float C[15], float vy, float vz) {
 #pragma unroll
   for (int i = 0; i < 15; ++i) C[i] = 0.0f;
   C[0] = vy;
@@ -148,7 +148,7 @@ __device__ __forceinline__ void init_cov(float C[15], float vy, float vz) {
 }
 
 // Direction of the chord from an inner to an outer point.
-__device__ __forceinline__ void chord_dir(float xi, float yi, float zi, float xo, float yo,
+__host__ __device__ __forceinline__ void chord_dir(float xi, float yi, float zi, float xo, float yo,
                                           float zo, float& s, float& t) {
   const float dX = xo - xi, dY = yo - yi, dZ = zo - zi;
   const float rho = sqrtf(dX * dX + dY * dY);

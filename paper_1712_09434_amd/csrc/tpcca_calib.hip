@@ -29,22 +29,22 @@ constexpr int TB = 256;
 struct D3 {
   float v, d0, d1, d2;
 };
-__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
-__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
-__device__ __forceinline__ D3 operator-(D3 a) { return D3{-a.v, -a.d0, -a.d1, -a.d2}; }
-__device__ __forceinline__ D3 operator*(D3 a, D3 b) {
+__host__ __device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.v + b.v, a.d0 + b.d0, a.d1 + b.d1, a.d2 + b.d2}; }
+__host__ __device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.v - b.v, a.d0 - b.d0, a.d1 - b.d1, a.d2 - b.d2}; }
+__host__ __device__ __forceinline__ D3 operator-(D3 a) { return D3{-a.v, -a.d0, -a.d1, -a.d2}; }
+__host__ __device__ __forceinline__ D3 operator*(D3 a, D3 b) {
   return D3{a.v * b.v, a.d0 * b.v + a.v * b.d0, a.d1 * b.v + a.v * b.d1, a.d2 * b.v + a.v * b.d2};
 }
-__device__ __forceinline__ D3 operator*(D3 a, float b) { return D3{a.v * b, a.d0 * b, a.d1 * b, a.d2 * b}; }
-__device__ __forceinline__ D3 operator*(float b, D3 a) { return D3{b * a.v, b * a.d0, b * a.d1, b * a.d2}; }
-__device__ __forceinline__ D3 operator+(D3 a, float b) { return D3{a.v + b, a.d0, a.d1, a.d2}; }
-__device__ __forceinline__ D3 operator+(float b, D3 a) { return D3{b + a.v, a.d0, a.d1, a.d2}; }
-__device__ __forceinline__ D3 operator-(float b, D3 a) { return D3{b - a.v, -a.d0, -a.d1, -a.d2}; }
-__device__ __forceinline__ D3 operator/(D3 a, D3 b) {
+__host__ __device__ __forceinline__ D3 operator*(D3 a, float b) { return D3{a.v * b, a.d0 * b, a.d1 * b, a.d2 * b}; }
+__host__ __device__ __forceinline__ D3 operator*(float b, D3 a) { return D3{b * a.v, b * a.d0, b * a.d1, b * a.d2}; }
+__host__ __device__ __forceinline__ D3 operator+(D3 a, float b) { return D3{a.v + b, a.d0, a.d1, a.d2}; }
+__host__ __device__ __forceinline__ D3 operator+(float b, D3 a) { return D3{b + a.v, a.d0, a.d1, a.d2}; }
+__host__ __device__ __forceinline__ D3 operator-(float b, D3 a) { return D3{b - a.v, -a.d0, -a.d1, -a.d2}; }
+__host__ __device__ __forceinline__ D3 operator/(D3 a, D3 b) {
   const float q = a.v / b.v;
   return D3{q, (a.d0 - q * b.d0) / b.v, (a.d1 - q * b.d1) / b.v, (a.d2 - q * b.d2) / b.v};
 }
-__device__ __forceinline__ D3 dsqrt(D3 a) {
+__host__ __device__ __forceinline__ D3 dsqrt(D3 a) {
   const float s = sqrtf(a.v);
   const float h = 0.5f / s;
   return D3{s, a.d0 * h, a.d1 * h, a.d2 * h};
@@ -55,7 +55,7 @@ __device__ __forceinline__ D3 dsqrt(D3 a) {
 // Jacobian entries a = d dy/d s0, b = d dy/d k, ls = d l/d s0,
 // lk = d l/d k, each with its derivatives along (s0, k, dx).
 struct TDer { D3 dy, l, a, b, ls, lk; };
-__device__ __forceinline__ TDer transport_duals(float s0v, float kv, float dxv, float kfac) {
+__host__ __device__ __forceinline__ TDer transport_duals(float s0v, float kv, float dxv, float kfac) {
   const float A1 = 1.0f / 6.0f, A2 = 3.0f / 40.0f, A3 = 5.0f / 112.0f, A4 = 35.0f / 1152.0f;
   const float B1 = 1.0f / 3.0f, B2 = 3.0f / 10.0f, B3 = 15.0f / 56.0f, B4 = 35.0f / 144.0f;
   const D3 s0{s0v, 1.f, 0.f, 0.f}, k{kv, 0.f, 1.f, 0.f}, dx{dxv, 0.f, 0.f, 1.f};
@@ -90,7 +90,7 @@ __device__ __forceinline__ TDer transport_duals(float s0v, float kv, float dxv, 
 }
 
 // ---------------------------------------------------------- small matrices
-__device__ __forceinline__ void unpack(const float c[15], float M[5][5]) {
+__host__ __device__ __forceinline__ void unpack(const float c[15], float M[5][5]) {
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
@@ -100,7 +100,7 @@ __device__ __forceinline__ void unpack(const float c[15], float M[5][5]) {
 // Adjoint of the transport step x -> x + dx at pre-step state (P, C).
 // In: gP = d chi2/d P', G = d chi2/d C' (symmetric, packed).  Out: gP, G
 // replaced by the adjoints of (P, C); returns d chi2/d dx.
-__device__ float transport_adjoint(const float P[5], const float Cp[15], float dx, float kfac,
+__host__ __device__ float transport_adjoint(const float P[5], const float Cp[15], float dx, float kfac,
                                    float gP[5], float G[15]) {
   const TDer T = transport_duals(P[2], P[4], dx, kfac);
   const float t = P[3];
@@ -174,7 +174,7 @@ __device__ float transport_adjoint(const float P[5], const float Cp[15], float d
 
 // Adjoint of the (y, z) update at pre-update state (P, C) with measurement m.
 // Adds d chi2/d m to gm[2] and replaces (gP, G) by the adjoints of (P, C).
-__device__ void update_adjoint(const float P[5], const float Cp[15], float my, float mz, float vy,
+__host__ __device__ void update_adjoint(const float P[5], const float Cp[15], float my, float mz, float vy,
                                float vz, float gP[5], float G[15], float gm[2]) {
   const float r0 = my - P[0], r1 = mz - P[1];
   const float S00 = Cp[0] + vy, S01 = Cp[1], S11 = Cp[5] + vz;
@@ -233,7 +233,7 @@ __device__ void update_adjoint(const float P[5], const float Cp[15], float my, f
 }
 
 // Adjoint of a scalar update of component q (measurement constant).
-__device__ void update1_adjoint(const float P[5], const float Cp[15], int q, float m, float var,
+__host__ __device__ void update1_adjoint(const float P[5], const float Cp[15], int q, float m, float var,
                                 float gP[5], float G[15]) {
   const float S = Cp[sym(q, q)] + var;
   const float W = 1.0f / S;
@@ -276,7 +276,7 @@ __device__ void update1_adjoint(const float P[5], const float Cp[15], int q, flo
 }
 
 // Scalar update of component q (forward).
-__device__ __forceinline__ void update1(float p[5], float C[15], int q, float m, float var, float& chi2) {
+__host__ __device__ __forceinline__ void update1(float p[5], float C[15], int q, float m, float var, float& chi2) {
   const float S = C[sym(q, q)] + var;
   float row[5], K[5];
 #pragma unroll
@@ -293,13 +293,13 @@ __device__ __forceinline__ void update1(float p[5], float C[15], int q, float m,
   chi2 = chi2 + (r * r) / S;
 }
 
-__device__ __forceinline__ void save(float* dst, const float p[5], const float C[15]) {
+__host__ __device__ __forceinline__ void save(float* dst, const float p[5], const float C[15]) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) dst[i] = p[i];
 #pragma unroll
   for (int i = 0; i < 15; ++i) dst[5 + i] = C[i];
 }
-__device__ __forceinline__ void load(const float* src, float p[5], float C[15]) {
+__host__ __device__ __forceinline__ void load(const float* src, float p[5], float C[15]) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) p[i] = src[i];
 #pragma unroll
@@ -308,7 +308,7 @@ __device__ __forceinline__ void load(const float* src, float p[5], float C[15]) 
 
 // The 8 clamped uniform cubic B-splines (knots 0,0,0,0,.2,.4,.6,.8,1,1,1,1)
 // at u, by the Cox-de Boor recursion over the one non-empty span.
-__device__ __forceinline__ void bspline8(float u, float B[8]) {
+__host__ __device__ __forceinline__ void bspline8(float u, float B[8]) {
   u = fminf(fmaxf(u, 0.0f), 1.0f);
   const float kn[12] = {0.f, 0.f, 0.f, 0.f, 0.2f, 0.4f, 0.6f, 0.8f, 1.f, 1.f, 1.f, 1.f};
   int span = 3;
@@ -337,225 +337,254 @@ __device__ __forceinline__ void bspline8(float u, float B[8]) {
 }
 
 // ------------------------------------------------------- 1. calibrate hits
-__global__ __launch_bounds__(TB) void k_cal_hits(CalWs c) {
-  for (int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x; j < c.H; j += (int64_t)gridDim.x * TB) {
-    const uint32_t id = c.hit_id[j];
-    c.gx[j] = 0.f; c.gy[j] = 0.f; c.gz[j] = 0.f;
-    if ((int64_t)id >= c.NC) { atomicOr(c.err, 1u); c.hx[j] = c.hy[j] = c.hz[j] = 0.f; continue; }
-    const int s = c.csec[id];
-    if (s >= c.S) { atomicOr(c.err, 1u); c.hx[j] = c.hy[j] = c.hz[j] = 0.f; continue; }
-    const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
-    const float side = s < c.S / 2 ? 1.0f : -1.0f;
-    const float dl = c.dl[s], tau = c.tau[s];
-    c.hz[j] = side * (c.L - (1.0f + dl) * ((c.L - side * z) - tau));
-    float Ba[8], Bb[8];
-    bspline8((x - c.x_first) / c.x_span, Ba);
-    bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
-    const float* cm = c.map + s * 64;
-    float acc = 0.f;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      float ra = 0.f;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) ra += cm[a * 8 + b] * Bb[b];
-      acc += Ba[a] * ra;
-    }
-    c.hx[j] = x + acc;
-    c.hy[j] = y;
+__host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
+  const uint32_t id = c.hit_id[j];
+  c.gx[j] = 0.f; c.gy[j] = 0.f; c.gz[j] = 0.f; c.gpt[j] = 0.f;
+  if ((int64_t)id >= c.NC || c.csec[id] >= c.S) {
+#ifdef __HIP_DEVICE_COMPILE__
+    atomicOr(c.err, 1u);
+#else
+    *c.err |= 1u;
+#endif
+    c.hx[j] = c.hy[j] = c.hz[j] = 0.f;
+    return;
   }
+  const int s = c.csec[id];
+  const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
+  const float side = s < c.S / 2 ? 1.0f : -1.0f;
+  const float dl = c.dl[s], tau = c.tau[s];
+  c.hz[j] = side * (c.L - (1.0f + dl) * ((c.L - side * z) - tau));
+  float Ba[8], Bb[8];
+  bspline8((x - c.x_first) / c.x_span, Ba);
+  bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
+  const float* cm = c.map + s * 64;
+  float acc = 0.f;
+  for (int a = 0; a < 8; ++a) {
+    float ra = 0.f;
+    for (int b = 0; b < 8; ++b) ra += cm[a * 8 + b] * Bb[b];
+    acc += Ba[a] * ra;
+  }
+  c.hx[j] = x + acc;
+  c.hy[j] = y;
+}
+
+__global__ __launch_bounds__(TB) void k_cal_hits(CalWs c) {
+  for (int64_t j = (int64_t)blockIdx.x * TB + threadIdx.x; j < c.H; j += (int64_t)gridDim.x * TB) calib_hit(c, j);
 }
 
 // ------------------------------------------- 2. forward + reverse per track
-__global__ __launch_bounds__(TB) void k_cal_adjoint(CalWs c) {
-  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < c.T; t += (int64_t)gridDim.x * TB) {
-    const int32_t b0 = c.hit_off[t];
-    const int nh = c.hit_off[t + 1] - b0;
-    float* part = c.part + t * kPart;
-    c.tflag[t] = 0;
-    c.tndf[t] = 0;
-    part[66] = 0.f;
-    if (nh < 3 || nh > c.R) { if (nh > c.R || nh < 0) atomicOr(c.err, 2u); continue; }
-    // k-th processed hit (outermost first) is hit index jk(k)
-    auto jk = [&](int k) { return (int64_t)b0 + nh - 1 - k; };
-    const Model& m = c.m;
-    float p[5], C[15];
-    float sdir, tdir;
-    const int64_t j0 = jk(0), j2 = jk(2);
-    chord_dir(c.hx[j2], c.hy[j2], c.hz[j2], c.hx[j0], c.hy[j0], c.hz[j0], sdir, tdir);
-    p[0] = c.hy[j0]; p[1] = c.hz[j0]; p[2] = sdir; p[3] = tdir; p[4] = c.k_prior[t];
-    init_cov(C, m.vy, m.vz);
-    if (!(fabsf(sdir) < m.sin_max)) continue;
-    float* ck = c.ckpt + t * (int64_t)c.nck * 20;
-    float* sg = c.seg + t * (int64_t)c.nseg * 20;
-    float chi2 = 0.f;
-    bool ok = true;
-    float xc = c.hx[j0];
-    for (int k = 1; k < nh; ++k) {
-      if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
-      const int64_t j = jk(k);
-      const float hx = c.hx[j];
-      if (!transport(p, C, xc, hx, m)) { ok = false; break; }
-      update(p, C, c.hy[j], c.hz[j], m, chi2);
-      xc = hx;
+#ifdef __HIP_DEVICE_COMPILE__
+#define SET_ERR(c, v) atomicOr((c).err, (v))
+#else
+#define SET_ERR(c, v) (*(c).err |= (v))
+#endif
+
+// Forward refit with checkpoints, then the reverse sweep, for track t.
+__host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
+  const int32_t b0 = c.hit_off[t];
+  const int nh = c.hit_off[t + 1] - b0;
+  float* part = c.part + t * kPart;
+  c.tflag[t] = 0;
+  c.tndf[t] = 0;
+  part[66] = 0.f;
+  if (b0 < 0 || nh < 0 || nh > c.R || (int64_t)b0 + nh > c.H) { SET_ERR(c, 2u); return; }
+  if (nh < 3) return;
+  // k-th processed hit (outermost first) is hit index jk(k)
+  auto jk = [&](int k) { return (int64_t)b0 + nh - 1 - k; };
+  const Model& m = c.m;
+  float p[5], C[15];
+  float sdir, tdir;
+  const int64_t j0 = jk(0), j2 = jk(2);
+  chord_dir(c.hx[j2], c.hy[j2], c.hz[j2], c.hx[j0], c.hy[j0], c.hz[j0], sdir, tdir);
+  p[0] = c.hy[j0]; p[1] = c.hz[j0]; p[2] = sdir; p[3] = tdir; p[4] = c.k_prior[t];
+  init_cov(C, m.vy, m.vz);
+  if (!(fabsf(sdir) < m.sin_max)) return;
+  float* ck = c.ckpt + t * (int64_t)c.nck * 20;
+  float* sg = c.seg + t * (int64_t)c.nseg * 20;
+  float chi2 = 0.f;
+  bool ok = true;
+  float xc = c.hx[j0];
+  for (int k = 1; k < nh; ++k) {
+    if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
+    const int64_t j = jk(k);
+    const float hx = c.hx[j];
+    if (!transport(p, C, xc, hx, m)) { ok = false; break; }
+    update(p, C, c.hy[j], c.hz[j], m, chi2);
+    xc = hx;
+  }
+  if (!ok) return;
+  // vertex and external tan(lambda)
+  const bool uv = c.use_vertex && c.use_vertex[t];
+  const bool ue = uv && c.ext_tgl;
+  int flag = 1;
+  int nsub = 0;
+  float last_p[5], last_C[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) last_p[i] = p[i];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) last_C[i] = C[i];
+  const float x_last = xc;
+  if (uv) {
+    nsub = (int)ceilf(x_last / 10.0f);
+    bool vok = nsub <= c.nseg - 2 && nsub >= 1;
+    float q[5], Q[15];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) q[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Q[i] = C[i];
+    float xv = x_last;
+    for (int s = 0; vok && s < nsub; ++s) {
+      const float xt = 10.0f * (float)(nsub - 1 - s);
+      if (!transport(q, Q, xv, xt, m)) { vok = false; break; }
+      xv = xt;
     }
-    if (!ok) continue;
-    // vertex and external tan(lambda)
-    const bool uv = c.use_vertex && c.use_vertex[t];
-    const bool ue = uv && c.ext_tgl;
-    int flag = 1;
-    int nsub = 0;
-    float last_p[5], last_C[15];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) last_p[i] = p[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) last_C[i] = C[i];
-    const float x_last = xc;
-    if (uv) {
-      nsub = (int)ceilf(x_last / 10.0f);
-      bool vok = nsub <= c.nseg - 2 && nsub >= 1;
-      float q[5], Q[15];
-#pragma unroll
-      for (int i = 0; i < 5; ++i) q[i] = p[i];
-#pragma unroll
-      for (int i = 0; i < 15; ++i) Q[i] = C[i];
-      float xv = x_last;
-      for (int s = 0; vok && s < nsub; ++s) {
-        const float xt = 10.0f * (float)(nsub - 1 - s);
-        if (!transport(q, Q, xv, xt, m)) { vok = false; break; }
-        xv = xt;
-      }
-      if (vok) {
-        float c2 = chi2;
-        update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, c2);
-        if (ue) update1(q, Q, 3, c.ext_tgl[t], c.st2, c2);
-        chi2 = c2;
-        flag = 2;
-      }
-    }
-    c.tflag[t] = flag;
-    c.tndf[t] = 2 * nh - 5 + (flag == 2 ? 2 + (ue ? 1 : 0) : 0);
-    part[66] = chi2;
-    // ---------------------------------------------------------- reverse
-    float gP[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, G[15];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) G[i] = 0.f;
-    if (flag == 2) {
-      // recompute the tail, keeping each pre-step state
-      float q[5], Q[15];
-#pragma unroll
-      for (int i = 0; i < 5; ++i) q[i] = last_p[i];
-#pragma unroll
-      for (int i = 0; i < 15; ++i) Q[i] = last_C[i];
-      float xv = x_last;
-      for (int s = 0; s < nsub; ++s) {
-        save(sg + s * 20, q, Q);
-        const float xt = 10.0f * (float)(nsub - 1 - s);
-        transport(q, Q, xv, xt, m);
-        xv = xt;
-      }
-      save(sg + nsub * 20, q, Q);                    // before the vertex update
-      if (ue) {
-        float dummy = 0.f;
-        update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, dummy);
-        update1_adjoint(q, Q, 3, c.ext_tgl[t], c.st2, gP, G);
-        load(sg + nsub * 20, q, Q);
-      }
-      float gm[2] = {0.f, 0.f};
-      update_adjoint(q, Q, 0.0f, 0.0f, c.sv2, c.sv2, gP, G, gm);
-      for (int s = nsub - 1; s >= 0; --s) {
-        load(sg + s * 20, q, Q);
-        const float xf = s == 0 ? x_last : 10.0f * (float)(nsub - s);
-        const float xt = 10.0f * (float)(nsub - 1 - s);
-        const float gdx = transport_adjoint(q, Q, xt - xf, m.kfac, gP, G);
-        if (s == 0) c.gx[jk(nh - 1)] -= gdx;
-      }
-    }
-    // hit steps, segment by segment from the last
-    const int nsteps = nh - 1;
-    for (int sgi = (nsteps - 1) / c.K; sgi >= 0; --sgi) {
-      const int k1 = 1 + sgi * c.K;
-      const int k2 = min(nsteps, k1 + c.K - 1);
-      float q[5], Q[15];
-      load(ck + sgi * 20, q, Q);
-      float xv = c.hx[jk(k1 - 1)];
-      float dummy = 0.f;
-      for (int k = k1; k <= k2; ++k) {
-        save(sg + (k - k1) * 20, q, Q);
-        const int64_t j = jk(k);
-        const float hx = c.hx[j];
-        transport(q, Q, xv, hx, m);
-        update(q, Q, c.hy[j], c.hz[j], m, dummy);
-        xv = hx;
-      }
-      for (int k = k2; k >= k1; --k) {
-        const int64_t j = jk(k), jp = jk(k - 1);
-        float a[5], A[15];
-        load(sg + (k - k1) * 20, a, A);
-        const float xf = c.hx[jp], xt = c.hx[j];
-        float b[5], B[15];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) b[i] = a[i];
-#pragma unroll
-        for (int i = 0; i < 15; ++i) B[i] = A[i];
-        transport(b, B, xf, xt, m);
-        float gm[2] = {0.f, 0.f};
-        update_adjoint(b, B, c.hy[j], c.hz[j], m.vy, m.vz, gP, G, gm);
-        c.gy[j] += gm[0];
-        c.gz[j] += gm[1];
-        const float gdx = transport_adjoint(a, A, xt - xf, m.kfac, gP, G);
-        c.gx[j] += gdx;
-        c.gx[jp] -= gdx;
-      }
-    }
-    // initial state: (y, z) of the outermost hit, direction from the chord
-    {
-      c.gy[j0] += gP[0];
-      c.gz[j0] += gP[1];
-      const float dX = c.hx[j0] - c.hx[j2], dY = c.hy[j0] - c.hy[j2], dZ = c.hz[j0] - c.hz[j2];
-      const float rho = sqrtf(dX * dX + dY * dY);
-      const float r3 = rho * rho * rho;
-      const float gs = gP[2], gt = gP[3];
-      const float gdX = gs * (-dY * dX / r3) + gt * (-dZ * dX / r3);
-      const float gdY = gs * (dX * dX / r3) + gt * (-dZ * dY / r3);
-      const float gdZ = gt / rho;
-      c.gx[j0] += gdX; c.gx[j2] -= gdX;
-      c.gy[j0] += gdY; c.gy[j2] -= gdY;
-      c.gz[j0] += gdZ; c.gz[j2] -= gdZ;
+    if (vok) {
+      float c2 = chi2;
+      update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, c2);
+      if (ue) update1(q, Q, 3, c.ext_tgl[t], c.st2, c2);
+      chi2 = c2;
+      flag = 2;
     }
   }
+  c.tflag[t] = flag;
+  c.tndf[t] = 2 * nh - 5 + (flag == 2 ? 2 + (ue ? 1 : 0) : 0);
+  part[66] = chi2;
+  // ---------------------------------------------------------- reverse
+  float gP[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, G[15];
+#pragma unroll
+  for (int i = 0; i < 15; ++i) G[i] = 0.f;
+  if (flag == 2) {
+    // recompute the tail, keeping each pre-step state
+    float q[5], Q[15];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) q[i] = last_p[i];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Q[i] = last_C[i];
+    float xv = x_last;
+    for (int s = 0; s < nsub; ++s) {
+      save(sg + s * 20, q, Q);
+      const float xt = 10.0f * (float)(nsub - 1 - s);
+      transport(q, Q, xv, xt, m);
+      xv = xt;
+    }
+    save(sg + nsub * 20, q, Q);                    // before the vertex update
+    if (ue) {
+      float dummy = 0.f;
+      update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, dummy);
+      update1_adjoint(q, Q, 3, c.ext_tgl[t], c.st2, gP, G);
+      load(sg + nsub * 20, q, Q);
+    }
+    float gm[2] = {0.f, 0.f};
+    update_adjoint(q, Q, 0.0f, 0.0f, c.sv2, c.sv2, gP, G, gm);
+    for (int s = nsub - 1; s >= 0; --s) {
+      load(sg + s * 20, q, Q);
+      const float xf = s == 0 ? x_last : 10.0f * (float)(nsub - s);
+      const float xt = 10.0f * (float)(nsub - 1 - s);
+      const float gdx = transport_adjoint(q, Q, xt - xf, m.kfac, gP, G);
+      if (s == 0) c.gpt[jk(nh - 1)] -= gdx;
+    }
+  }
+  // hit steps, segment by segment from the last
+  const int nsteps = nh - 1;
+  for (int sgi = (nsteps - 1) / c.K; sgi >= 0; --sgi) {
+    const int k1 = 1 + sgi * c.K;
+    const int k2 = min(nsteps, k1 + c.K - 1);
+    float q[5], Q[15];
+    load(ck + sgi * 20, q, Q);
+    float xv = c.hx[jk(k1 - 1)];
+    float dummy = 0.f;
+    for (int k = k1; k <= k2; ++k) {
+      save(sg + (k - k1) * 20, q, Q);
+      const int64_t j = jk(k);
+      const float hx = c.hx[j];
+      transport(q, Q, xv, hx, m);
+      update(q, Q, c.hy[j], c.hz[j], m, dummy);
+      xv = hx;
+    }
+    for (int k = k2; k >= k1; --k) {
+      const int64_t j = jk(k), jp = jk(k - 1);
+      float a[5], A[15];
+      load(sg + (k - k1) * 20, a, A);
+      const float xf = c.hx[jp], xt = c.hx[j];
+      float b[5], B[15];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) b[i] = a[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) B[i] = A[i];
+      transport(b, B, xf, xt, m);
+      float gm[2] = {0.f, 0.f};
+      update_adjoint(b, B, c.hy[j], c.hz[j], m.vy, m.vz, gP, G, gm);
+      c.gy[j] += gm[0];
+      c.gz[j] += gm[1];
+      // the step's dx-derivative is kept whole (at the hit it ends on); the
+      // map partials weight it by the change of the basis product between
+      // its two hits, which avoids forming the difference of two large,
+      // nearly equal step derivatives per hit
+      c.gx[j] = transport_adjoint(a, A, xt - xf, m.kfac, gP, G);
+    }
+  }
+  // initial state: (y, z) of the outermost hit, direction from the chord
+  {
+    c.gy[j0] += gP[0];
+    c.gz[j0] += gP[1];
+    const float dX = c.hx[j0] - c.hx[j2], dY = c.hy[j0] - c.hy[j2], dZ = c.hz[j0] - c.hz[j2];
+    const float rho = sqrtf(dX * dX + dY * dY);
+    const float r3 = rho * rho * rho;
+    const float gs = gP[2], gt = gP[3];
+    const float gdX = gs * (-dY * dX / r3) + gt * (-dZ * dX / r3);
+    const float gdY = gs * (dX * dX / r3) + gt * (-dZ * dY / r3);
+    const float gdZ = gt / rho;
+    c.gpt[j0] += gdX; c.gpt[j2] -= gdX;
+    c.gy[j0] += gdY; c.gy[j2] -= gdY;
+    c.gz[j0] += gdZ; c.gz[j2] -= gdZ;
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_cal_adjoint(CalWs c) {
+  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < c.T; t += (int64_t)gridDim.x * TB) adjoint_track(c, t);
 }
 
 // ------------------------------------------ 3. per-track parameter partials
 // One wave per track: lane l owns map coefficient (l / 8, l % 8); lanes 0
 // and 1 also own the drift scale and the time offset.  Sums run over the
 // track's hits in order (FP32).
-__global__ __launch_bounds__(64) void k_cal_partials(CalWs c) {
-  const int64_t t = blockIdx.x;
-  const int l = threadIdx.x;
+__host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) {
   float* part = c.part + t * kPart;
   const int32_t b0 = c.hit_off[t];
   const int nh = c.hit_off[t + 1] - b0;
   float acc = 0.f, accd = 0.f;
   if (c.tflag[t] > 0) {
-    const int s = c.csec[c.hit_id[b0]];
+    const uint32_t id0 = c.hit_id[b0];
+    int s = (int64_t)id0 < c.NC ? c.csec[id0] : 0;
+    if (s >= c.S) s = 0;   // flagged as an error by k_cal_hits
     const float side = s < c.S / 2 ? 1.0f : -1.0f;
     const float dl = c.dl[s], tau = c.tau[s];
     const int a = l >> 3, b = l & 7;
-    for (int i = 0; i < nh; ++i) {
+    // basis product at hit i+1 (the next hit outward), carried down the loop
+    float w_next = 0.f;
+    for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
       const uint32_t id = c.hit_id[j];
-      const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
-      float Ba[8], Bb[8];
-      bspline8((x - c.x_first) / c.x_span, Ba);
-      bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
-      acc += c.gx[j] * (Ba[a] * Bb[b]);
-      if (l == 0) accd += c.gz[j] * (-side * ((c.L - side * z) - tau));
-      if (l == 1) accd += c.gz[j] * (side * (1.0f + dl));
+      float wj = 0.f;
+      if ((int64_t)id < c.NC) {
+        const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
+        float Ba[8], Bb[8];
+        bspline8((x - c.x_first) / c.x_span, Ba);
+        bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
+        wj = Ba[a] * Bb[b];
+        if (l == 0) accd += c.gz[j] * (-side * ((c.L - side * z) - tau));
+        if (l == 1) accd += c.gz[j] * (side * (1.0f + dl));
+      }
+      if (i < nh - 1) acc += c.gx[j] * (wj - w_next);
+      acc += c.gpt[j] * wj;
+      w_next = wj;
     }
   }
   part[2 + l] = acc;
   if (l < 2) part[l] = accd;
 }
+
+__global__ __launch_bounds__(64) void k_cal_partials(CalWs c) { partials_lane(c, blockIdx.x, threadIdx.x); }
 
 // --------------------------------------------- 4. FP64 fixed-order reduction
 // chunk[ch][s*66 + p] = sum over the tracks of chunk ch (ascending) in sector s
@@ -566,7 +595,10 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
   const int64_t nt = (c.T - t0) < kChunk ? (c.T - t0) : (int64_t)kChunk;
   for (int i = threadIdx.x; i < kChunk; i += TB) {
     int s = -1;
-    if (i < nt && c.tflag[t0 + i] > 0) s = c.csec[c.hit_id[c.hit_off[t0 + i]]];
+    if (i < nt && c.tflag[t0 + i] > 0) {
+      const uint32_t id = c.hit_id[c.hit_off[t0 + i]];
+      s = (int64_t)id < c.NC ? c.csec[id] : 0;
+    }
     s_sec[i] = s;
   }
   __syncthreads();
@@ -602,6 +634,13 @@ __global__ void k_cal_zero(CalWs c) {
 }  // namespace
 
 hipError_t run_calib(const CalWs& c, hipStream_t st) {
+  // every array the kernels touch must be set before anything is launched
+  const void* need[] = {c.hit_off, c.hit_id, c.k_prior, c.cx, c.cy, c.cz, c.csec, c.dl, c.tau, c.map,
+                        c.hx, c.hy, c.hz, c.gx, c.gy, c.gz, c.gpt, c.part, c.tflag, c.tndf, c.ckpt,
+                        c.seg, c.chunk, c.out, c.ndf_sum, c.err};
+  for (const void* p : need)
+    if (!p) return hipErrorInvalidValue;
+  if (c.K < 1 || c.nseg < c.K || c.nseg < 28 || c.nck < (c.R - 1 + c.K - 1) / c.K + 1) return hipErrorInvalidValue;
   k_cal_zero<<<1, 64, 0, st>>>(c);
   const unsigned bh = (unsigned)std::min<int64_t>(std::max<int64_t>((c.H + TB - 1) / TB, 1), 65536);
   k_cal_hits<<<bh, TB, 0, st>>>(c);

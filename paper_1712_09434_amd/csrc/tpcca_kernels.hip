@@ -264,10 +264,9 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   const uint32_t nc = G.nz * G.ny;
   for (uint32_t c = tid; c <= nc; c += TB) s_hist[c] = 0u;
   __syncthreads();
-  for (uint32_t k = tid; k < n; k += TB) {
-    const int64_t l = (int64_t)s_ids[k] - E.base;
-    atomicAdd(&s_hist[cell_of(G, E.y[l], E.z[l])], 1u);
-  }
+  // the canonical entries were written by this same thread (same k stride):
+  // re-read them, coalesced, instead of gathering from the input again
+  for (uint32_t k = tid; k < n; k += TB) atomicAdd(&s_hist[cell_of(G, w.cy[off + k], w.cz[off + k])], 1u);
   __syncthreads();
   uint32_t carry = 0;
   for (uint32_t c0 = 0; c0 < nc; c0 += TB) {
@@ -281,8 +280,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   if (tid == 0) w.cell_off[cbase + nc] = off + n;
   __syncthreads();
   for (uint32_t k = tid; k < n; k += TB) {
-    const int64_t l = (int64_t)s_ids[k] - E.base;
-    const float x = E.x[l], y = E.y[l], z = E.z[l];
+    const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
     const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
     w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
   }
@@ -306,50 +304,89 @@ __device__ __forceinline__ CellBox cell_box(const GridParams& G, float yq, float
 // For the middle cluster i: the (down, up) pair on rows r-1 / r+1 inside the
 // windows minimising the deviation of i from the chord d-u, accepted iff the
 // score <= link_cut, ties by smaller up id then smaller down id (canonical
-// positions are ordered like ids within a row).
-__global__ __launch_bounds__(TB) void k_links(Ws w) {
-  const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (p >= w.N) return;
-  const uint32_t ru = w.cru[p];
-  const int r = (int)(ru % (uint32_t)w.R);
-  int32_t bu = -1, bd = -1;
-  if (r >= 1 && r <= w.R - 2) {
-    const float xi = w.cx[p], yi = w.cy[p], zi = w.cz[p];
-    const float WY = w.P.win_y, WZ = w.P.win_z, IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z;
-    const float CUT = w.P.link_cut;
-    const GridParams Gd = w.grid[ru - 1], Gu = w.grid[ru + 1];
-    const CellBox bdn = cell_box(Gd, yi, zi, WY, WZ);
-    const CellBox bup = cell_box(Gu, yi, zi, WY, WZ);
-    bool have = false;
-    float bs = 0.0f;
-    for (uint32_t izd = bdn.iz0; izd <= bdn.iz1; ++izd) {
-      const uint32_t cd0 = Gd.cell_base + izd * Gd.ny;
-      const uint32_t kd1 = w.cell_off[cd0 + bdn.iy1 + 1];
-      for (uint32_t kd = w.cell_off[cd0 + bdn.iy0]; kd < kd1; ++kd) {
-        const float4 D = w.gbuf[kd];
-        if (!(fabsf(D.x - yi) <= WY && fabsf(D.y - zi) <= WZ)) continue;
-        const int32_t pd = (int32_t)__float_as_uint(D.w);
-        for (uint32_t izu = bup.iz0; izu <= bup.iz1; ++izu) {
-          const uint32_t cu0 = Gu.cell_base + izu * Gu.ny;
-          const uint32_t ku1 = w.cell_off[cu0 + bup.iy1 + 1];
-          for (uint32_t ku = w.cell_off[cu0 + bup.iy0]; ku < ku1; ++ku) {
-            const float4 U = w.gbuf[ku];
-            if (!(fabsf(U.x - yi) <= WY && fabsf(U.y - zi) <= WZ)) continue;
-            const float wgt = (xi - D.z) / (U.z - D.z);
-            const float ey = yi - (D.x + (U.x - D.x) * wgt);
-            const float ez = zi - (D.y + (U.y - D.y) * wgt);
-            const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
-            if (!(score <= CUT)) continue;
-            const int32_t pu = (int32_t)__float_as_uint(U.w);
-            const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
-            if (better) { have = true; bs = score; bu = pu; bd = pd; }
-          }
+// positions are ordered like ids within a row).  D/U: the grid-ordered
+// entries of the two rows; Dc/Uc: their cell start offsets (index into D/U).
+template <class F4, class U32>
+__device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float zi,
+                                          const GridParams& Gd, F4 D4, U32 Dc,
+                                          const GridParams& Gu, F4 U4, U32 Uc,
+                                          int32_t& bu, int32_t& bd) {
+  const float WY = w.P.win_y, WZ = w.P.win_z, IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z;
+  const float CUT = w.P.link_cut;
+  const CellBox bdn = cell_box(Gd, yi, zi, WY, WZ);
+  const CellBox bup = cell_box(Gu, yi, zi, WY, WZ);
+  bool have = false;
+  float bs = 0.0f;
+  bu = -1; bd = -1;
+  for (uint32_t izd = bdn.iz0; izd <= bdn.iz1; ++izd) {
+    const uint32_t cd0 = izd * Gd.ny;
+    const uint32_t kd1 = Dc[cd0 + bdn.iy1 + 1];
+    for (uint32_t kd = Dc[cd0 + bdn.iy0]; kd < kd1; ++kd) {
+      const float4 D = D4[kd];
+      if (!(fabsf(D.x - yi) <= WY && fabsf(D.y - zi) <= WZ)) continue;
+      const int32_t pd = (int32_t)__float_as_uint(D.w);
+      for (uint32_t izu = bup.iz0; izu <= bup.iz1; ++izu) {
+        const uint32_t cu0 = izu * Gu.ny;
+        const uint32_t ku1 = Uc[cu0 + bup.iy1 + 1];
+        for (uint32_t ku = Uc[cu0 + bup.iy0]; ku < ku1; ++ku) {
+          const float4 U = U4[ku];
+          if (!(fabsf(U.x - yi) <= WY && fabsf(U.y - zi) <= WZ)) continue;
+          const float wgt = (xi - D.z) / (U.z - D.z);
+          const float ey = yi - (D.x + (U.x - D.x) * wgt);
+          const float ez = zi - (D.y + (U.y - D.y) * wgt);
+          const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+          if (!(score <= CUT)) continue;
+          const int32_t pu = (int32_t)__float_as_uint(U.w);
+          const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
+          if (better) { have = true; bs = score; bu = pu; bd = pd; }
         }
       }
     }
   }
-  w.up[p] = bu;
-  w.dn[p] = bd;
+}
+
+constexpr uint32_t kSlab = 1024;   // clusters of one row staged in LDS
+
+// One block per row unit: the grids of rows r-1 and r+1 (entries and cell
+// offsets) are staged in LDS when each holds at most kSlab clusters; every
+// window search of the row's clusters then reads LDS only.
+__global__ __launch_bounds__(TB) void k_links(Ws w) {
+  __shared__ float4 s_d[kSlab], s_u[kSlab];
+  __shared__ uint32_t s_cd[kSlab / 2 + 2], s_cu[kSlab / 2 + 2];
+  const int64_t ru = blockIdx.x;
+  const int r = (int)(ru % w.R);
+  const uint32_t off = w.ru_off[ru];
+  const uint32_t n = w.ru_off[ru + 1] - off;
+  if (n == 0) return;
+  if (r < 1 || r > w.R - 2) {
+    for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
+    return;
+  }
+  const uint32_t offd = w.ru_off[ru - 1], nd = off - offd;
+  const uint32_t offu = w.ru_off[ru + 1], nu = w.ru_off[ru + 2] - offu;
+  const GridParams Gd = w.grid[ru - 1], Gu = w.grid[ru + 1];
+  const bool lds = nd <= kSlab && nu <= kSlab;
+  if (lds) {
+    const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
+    for (uint32_t i = threadIdx.x; i < nd; i += TB) s_d[i] = w.gbuf[offd + i];
+    for (uint32_t i = threadIdx.x; i < nu; i += TB) s_u[i] = w.gbuf[offu + i];
+    for (uint32_t i = threadIdx.x; i <= ncd; i += TB) s_cd[i] = w.cell_off[Gd.cell_base + i] - offd;
+    for (uint32_t i = threadIdx.x; i <= ncu; i += TB) s_cu[i] = w.cell_off[Gu.cell_base + i] - offu;
+    __syncthreads();
+  }
+  for (uint32_t k = threadIdx.x; k < n; k += TB) {
+    const uint32_t p = off + k;
+    const float xi = w.cx[p], yi = w.cy[p], zi = w.cz[p];
+    int32_t bu, bd;
+    if (lds)
+      find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint32_t*)s_cd, Gu, (const float4*)s_u,
+                (const uint32_t*)s_cu, bu, bd);
+    else
+      find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
+                w.cell_off + Gu.cell_base, bu, bd);
+    w.up[p] = bu;
+    w.dn[p] = bd;
+  }
 }
 
 // ------------------------------------------------------- a3/a4: clean/start
@@ -479,37 +516,16 @@ __device__ __forceinline__ bool accepted(float X, const Acc& a, const float p[5]
   return !(fabsf(p[0]) > lim || fabsf(p[1]) > a.z_max);
 }
 
-// One following step on row r: transport to the row plane, acceptance,
-// search, (transport to the cluster's own x,) update.  Returns false when
-// following stops; *wrote tells whether the row slot was written.
-__device__ __forceinline__ bool follow_row(const Ws& w, const float* sX, const Acc& acc,
-                                           uint32_t rubase, int r, float p[5], float C[15],
-                                           float& xc, int& rstate, int32_t* hits, int& nhits,
-                                           int& gap, bool& wrote) {
-  wrote = false;
-  const float X = sX[r];
-  if (!transport(p, C, xc, X, w.m)) return false;
-  xc = X;
-  rstate = r;
-  if (!accepted(X, acc, p)) return false;
-  const Found h = search_row(w, rubase + (uint32_t)r, p, C);
-  if (h.pos >= 0) {
-    if (h.x != X) {
-      if (!transport(p, C, X, h.x, w.m)) return false;
-      xc = h.x;
-    }
-    float dummy = 0.0f;
-    update(p, C, h.y, h.z, w.m, dummy);
-    hits[r] = h.pos;
-    ++nhits;
-    gap = 0;
-  } else {
-    hits[r] = -1;
-    ++gap;
-  }
-  wrote = true;
-  return gap <= w.P.max_gap;
-}
+// Tracklet construction as a per-lane state machine: every loop iteration
+// advances each lane by one row step, whatever phase it is in, so the lanes
+// of a wave stay converged on the common transport.  Phases:
+//   CHAIN  fit the next cluster of the seed's chain (no search);
+//   UP     transport to the next row plane, acceptance, search, update;
+//   BACK   transport row by row back to the seed's first row, no updates;
+//   DOWN   as UP, downward from the row below the seed.
+// A lane that finishes writes its tracklet and takes the next seed from a
+// device counter (one atomic per wave).
+enum : int { ST_CHAIN = 0, ST_UP = 1, ST_BACK = 2, ST_DOWN = 3, ST_DONE = 4, ST_IDLE = 5 };
 
 __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   __shared__ float sX[256];
@@ -517,76 +533,157 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   __syncthreads();
   const Acc acc{w.tan_a, w.z_max};
   const uint32_t ns = w.flags[F_NSEEDS];
-  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
-    const int32_t h0 = (int32_t)w.seeds[s];
-    const uint32_t ru0 = w.cru[h0];
-    const int r0 = (int)(ru0 % (uint32_t)w.R);
-    const uint32_t rubase = ru0 - (uint32_t)r0;
-    int32_t* hits = w.tl_hits + s * w.R;
-    float* st = w.tl_state + s * kTl;
-    const int32_t h1 = w.cup[h0];
-    const int32_t h2 = w.cup[h1];
-    float p[5], C[15];
-    float sdir, tdir;
-    const float x0 = w.cx[h0], y0 = w.cy[h0], z0 = w.cz[h0];
-    chord_dir(x0, y0, z0, w.cx[h2], w.cy[h2], w.cz[h2], sdir, tdir);
-    p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
-    init_cov(C, w.m.vy, w.m.vz);
-    int nhits = 0, rlo = r0, rhi = r0;
-    bool ok = fabsf(sdir) < w.m.sin_max;
-    float xc = x0;
-    int rstate = r0;
-    if (ok) {
-      hits[r0] = h0;
-      nhits = 1;
-      float dummy = 0.0f;
-      for (int32_t h = h1; h >= 0; h = w.cup[h]) {
-        const float hx = w.cx[h];
-        if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
-        update(p, C, w.cy[h], w.cz[h], w.m, dummy);
-        ++rstate;
-        hits[rstate] = h;
-        ++nhits;
-        xc = hx;
-      }
+  const int R = w.R;
+  int phase = ST_IDLE;
+  int64_t s = -1;
+  int32_t* hits = nullptr;
+  int32_t h0 = 0, nxt = -1;
+  int r0 = 0, r = 0, rstate = 0, rlo = 0, rhi = 0, nhits = 0, gap = 0;
+  uint32_t rubase = 0;
+  float p[5], C[15], xc = 0.f;
+  uint32_t iters = 0;
+  while (true) {
+    // every lane's steps are bounded (rows only move one way per phase), so
+    // this cap is never reached by a correct kernel; it turns a defect into
+    // an error instead of a hang
+    if (++iters > (1u << 22)) { atomicOr(&w.flags[F_ERR], ERR_STUCK); break; }
+    // finished lanes publish their tracklet and take new seeds
+    if (phase == ST_DONE) {
+      float* st = w.tl_state + s * kTl;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) st[i] = p[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) st[5 + i] = C[i];
+      w.tl_nhits[s] = nhits;
+      w.tl_range[s] = rlo | (rhi << 16);
+      w.tl_key[s] = ((uint64_t)(uint32_t)nhits << 40) | ((uint64_t)(255 - r0) << 32) |
+                    (uint64_t)(0xFFFFFFFFu - w.cid[h0]);
+      phase = ST_IDLE;
     }
-    if (!ok) {
-      nhits = 0;
-      rhi = rlo = r0;
-    } else {
-      rhi = rstate;
-      int gap = 0;
-      for (int r = rstate + 1; r < w.R; ++r) {
-        bool wrote;
-        const bool go = follow_row(w, sX, acc, rubase, r, p, C, xc, rstate, hits, nhits, gap, wrote);
-        if (wrote) rhi = r;
-        if (!go) break;
-      }
-      bool back = true;
-      for (int r = rstate - 1; r >= r0; --r) {
-        if (!transport(p, C, xc, sX[r], w.m)) { back = false; break; }
-        xc = sX[r];
-      }
-      if (back) {
-        gap = 0;
-        int rs = r0;
-        for (int r = r0 - 1; r >= 0; --r) {
-          bool wrote;
-          const bool go = follow_row(w, sX, acc, rubase, r, p, C, xc, rs, hits, nhits, gap, wrote);
-          if (wrote) rlo = r;
-          if (!go) break;
+    const bool want = phase == ST_IDLE && s != -2;
+    const uint64_t wm = __ballot(want);
+    if (wm) {
+      uint32_t base = 0;
+      const int leader = __ffsll((unsigned long long)wm) - 1;
+      if (lane_id() == leader) base = atomicAdd(&w.flags[F_SEEDCTR], (uint32_t)__popcll(wm));
+      base = __shfl(base, leader, 64);
+      if (want) {
+        const uint32_t mine = base + (uint32_t)__popcll(wm & lanemask_lt());
+        if (mine >= ns) {
+          s = -2;   // no more work for this lane
+        } else {
+          s = mine;
+          h0 = (int32_t)w.seeds[s];
+          const uint32_t ru0 = w.cru[h0];
+          r0 = (int)(ru0 % (uint32_t)R);
+          rubase = ru0 - (uint32_t)r0;
+          hits = w.tl_hits + s * R;
+          const int32_t h1 = w.cup[h0];
+          const int32_t h2 = w.cup[h1];
+          float sdir, tdir;
+          const float x0 = w.cx[h0], y0 = w.cy[h0], z0 = w.cz[h0];
+          chord_dir(x0, y0, z0, w.cx[h2], w.cy[h2], w.cz[h2], sdir, tdir);
+          p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
+          init_cov(C, w.m.vy, w.m.vz);
+          rlo = rhi = rstate = r0;
+          xc = x0;
+          if (fabsf(sdir) < w.m.sin_max) {
+            hits[r0] = h0;
+            nhits = 1;
+            nxt = h1;
+            phase = ST_CHAIN;
+          } else {
+            nhits = 0;
+            phase = ST_DONE;
+          }
         }
       }
     }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) st[i] = p[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) st[5 + i] = C[i];
-    w.tl_nhits[s] = nhits;
-    w.tl_range[s] = rlo | (rhi << 16);
-    const uint32_t id = w.cid[h0];
-    w.tl_key[s] = ((uint64_t)(uint32_t)nhits << 40) | ((uint64_t)(255 - r0) << 32) |
-                  (uint64_t)(0xFFFFFFFFu - id);
+    if (__ballot(phase != ST_IDLE) == 0ull) break;
+    if (phase == ST_DONE || phase == ST_IDLE) continue;
+    // one row step
+    if (phase == ST_CHAIN) {
+      const float hx = w.cx[nxt];
+      if (!transport(p, C, xc, hx, w.m)) {
+        nhits = 0; rlo = rhi = r0; phase = ST_DONE;
+      } else {
+        float dummy = 0.0f;
+        update(p, C, w.cy[nxt], w.cz[nxt], w.m, dummy);
+        ++rstate;
+        hits[rstate] = nxt;
+        ++nhits;
+        xc = hx;
+        nxt = w.cup[nxt];
+        if (nxt < 0) {
+          rhi = rstate;
+          gap = 0;
+          r = rstate + 1;
+          phase = r < R ? ST_UP : ST_BACK;
+          if (phase == ST_BACK) r = rstate - 1;
+        }
+      }
+    } else if (phase == ST_BACK) {
+      if (!transport(p, C, xc, sX[r], w.m)) {
+        phase = ST_DONE;
+      } else {
+        xc = sX[r];
+        --r;
+        if (r < r0) {
+          gap = 0;
+          r = r0 - 1;
+          phase = r >= 0 ? ST_DOWN : ST_DONE;
+        }
+      }
+    } else {   // ST_UP or ST_DOWN
+      const float X = sX[r];
+      bool go = transport(p, C, xc, X, w.m);
+      bool wrote = false;
+      if (go) {
+        xc = X;
+        rstate = r;
+        go = accepted(X, acc, p);
+        if (go) {
+          const Found h = search_row(w, rubase + (uint32_t)r, p, C);
+          if (h.pos >= 0) {
+            if (h.x != X) {
+              go = transport(p, C, X, h.x, w.m);
+              if (go) xc = h.x;
+            }
+            if (go) {
+              float dummy = 0.0f;
+              update(p, C, h.y, h.z, w.m, dummy);
+              hits[r] = h.pos;
+              ++nhits;
+              gap = 0;
+              wrote = true;
+            }
+          } else {
+            hits[r] = -1;
+            ++gap;
+            wrote = true;
+          }
+          if (wrote) go = gap <= w.P.max_gap;
+        }
+      }
+      if (phase == ST_UP) {
+        if (wrote) rhi = r;
+        if (go && r + 1 < R) {
+          ++r;
+        } else {
+          r = rstate - 1;
+          if (r >= r0) {
+            phase = ST_BACK;
+          } else {
+            gap = 0;
+            r = r0 - 1;
+            phase = r >= 0 ? ST_DOWN : ST_DONE;
+          }
+        }
+      } else {
+        if (wrote) rlo = r;
+        if (go && r - 1 >= 0) --r; else phase = ST_DONE;
+      }
+    }
   }
 }
 
@@ -601,66 +698,98 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
     const int32_t* hits = w.tl_hits + s * w.R;
     for (int r = rlo; r <= rhi; ++r) {
       const int32_t h = hits[r];
-      if (h >= 0) atomicMax((unsigned long long*)&w.owner[h], (unsigned long long)key);
+      // owners only grow: a value already >= key (even a stale one) makes the atomic a no-op
+      if (h >= 0 && w.owner[h] < key) atomicMax((unsigned long long*)&w.owner[h], (unsigned long long)key);
     }
   }
 }
 
 // ------------------------------------------------ a6/a7: accept + final fit
-__global__ __launch_bounds__(TB) void k_refit(Ws w) {
+// Acceptance: count the hits a tracklet owns (outermost first), keep them as
+// a compact list tl_own[s][0..cnt) and flag the tracklet if it owns at least
+// min_hits and owned_num/owned_den of its hits.
+__global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const uint32_t ns = w.flags[F_NSEEDS];
   for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
-    uint32_t okf = 0, cnt = 0;
+    uint32_t acc = 0, cnt = 0;
     if (s < ns && w.tl_nhits[s] >= w.P.min_hits) {
       const int nh = w.tl_nhits[s];
       const uint64_t key = w.tl_key[s];
       const int32_t rg = w.tl_range[s];
       const int rlo = rg & 0xFFFF, rhi = rg >> 16;
       const int32_t* hits = w.tl_hits + s * w.R;
-      int32_t o[3] = {-1, -1, -1};
-      int r0 = -1;
+      int32_t* own = w.tl_own + s * w.R;
       for (int r = rhi; r >= rlo; --r) {
         const int32_t h = hits[r];
-        if (h >= 0 && w.owner[h] == key) {
-          if (cnt < 3) { o[cnt] = h; if (cnt == 0) r0 = r; }
-          ++cnt;
-        }
+        if (h >= 0 && w.owner[h] == key) own[cnt++] = h;
       }
-      const bool acc = (int)cnt >= w.P.min_hits &&
-                       (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh;
-      if (acc) {
-        float p[5], C[15], sdir, tdir;
-        const float xo = w.cx[o[0]], yo = w.cy[o[0]], zo = w.cz[o[0]];
-        chord_dir(w.cx[o[2]], w.cy[o[2]], w.cz[o[2]], xo, yo, zo, sdir, tdir);
-        const float kpr = w.tl_state[s * kTl + 4];
-        p[0] = yo; p[1] = zo; p[2] = sdir; p[3] = tdir; p[4] = kpr;
-        init_cov(C, w.m.vy, w.m.vz);
-        float chi2 = 0.0f;
-        bool ok = fabsf(sdir) < w.m.sin_max;
-        float xc = xo;
-        for (int r = r0 - 1; ok && r >= rlo; --r) {
-          const int32_t h = hits[r];
-          if (h < 0 || w.owner[h] != key) continue;
-          const float hx = w.cx[h];
-          if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
-          update(p, C, w.cy[h], w.cz[h], w.m, chi2);
-          xc = hx;
-        }
-        if (ok) {
-          float* rf = w.rf + s * kRf;
-          rf[0] = xc;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) rf[1 + i] = p[i];
-#pragma unroll
-          for (int i = 0; i < 15; ++i) rf[6 + i] = C[i];
-          rf[21] = chi2;
-          rf[22] = kpr;
-          okf = 1;
-        }
-      }
+      acc = ((int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
     }
-    w.trk_flag[s] = okf;
-    w.hit_cnt[s] = okf ? cnt : 0u;
+    w.acc_flag[s] = acc;
+    w.own_cnt[s] = acc ? cnt : 0u;
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_acc_list(Ws w) {
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
+    const uint32_t a = w.acc_off[s];
+    if (w.acc_off[s + 1] != a) w.acc_list[a] = (uint32_t)s;
+  }
+}
+
+// Final fit of every accepted tracklet (dense over the accepted list):
+// outermost owned hit first, direction from the chord to the hit two
+// positions inward, q/pT prior from following; the next hit's coordinates
+// are loaded while the current step computes.
+__global__ __launch_bounds__(TB) void k_refit(Ws w) {
+  const uint32_t na = w.acc_off[w.seed_cap];
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < na; i += (int64_t)gridDim.x * TB) {
+    const int64_t s = w.acc_list[i];
+    const int32_t* own = w.tl_own + s * w.R;
+    const uint32_t cnt = w.own_cnt[s];
+    float p[5], C[15], sdir, tdir;
+    const int32_t o0 = own[0], o2 = own[2];
+    const float xo = w.cx[o0], yo = w.cy[o0], zo = w.cz[o0];
+    chord_dir(w.cx[o2], w.cy[o2], w.cz[o2], xo, yo, zo, sdir, tdir);
+    const float kpr = w.tl_state[s * kTl + 4];
+    p[0] = yo; p[1] = zo; p[2] = sdir; p[3] = tdir; p[4] = kpr;
+    init_cov(C, w.m.vy, w.m.vz);
+    float chi2 = 0.0f;
+    bool ok = fabsf(sdir) < w.m.sin_max;
+    float xc = xo;
+    int32_t hn = own[1];
+    float nx = w.cx[hn], ny = w.cy[hn], nz = w.cz[hn];
+    for (uint32_t k = 1; ok && k < cnt; ++k) {
+      const float hx = nx, hy = ny, hz = nz;
+      if (k + 1 < cnt) {
+        hn = own[k + 1];
+        nx = w.cx[hn]; ny = w.cy[hn]; nz = w.cz[hn];
+      }
+      if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
+      update(p, C, hy, hz, w.m, chi2);
+      xc = hx;
+    }
+    if (ok) {
+      float* rf = w.rf + s * kRf;
+      rf[0] = xc;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) rf[1 + q] = p[q];
+#pragma unroll
+      for (int q = 0; q < 15; ++q) rf[6 + q] = C[q];
+      rf[21] = chi2;
+      rf[22] = kpr;
+    } else {
+      w.own_cnt[s] = 0u;          // a failed fit produces no track
+    }
+  }
+}
+
+// Output flags of every seed: accepted and fitted.
+__global__ __launch_bounds__(TB) void k_trk_flags(Ws w) {
+  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
+    const uint32_t c = w.own_cnt[s];
+    w.trk_flag[s] = c > 0 ? 1u : 0u;
+    w.hit_cnt[s] = c;
   }
 }
 
@@ -712,18 +841,21 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
     O.ndf[j] = 2 * (int32_t)n - 5;
     if (O.k_prior) O.k_prior[j] = rf[22];
     O.hit_off[j] = (int32_t)o;
-    const uint64_t key = w.tl_key[s];
-    const int32_t rg = w.tl_range[s];
-    const int32_t* hits = w.tl_hits + s * w.R;
-    uint32_t k = o;
-    for (int r = rg & 0xFFFF; r <= (rg >> 16); ++r) {
-      const int32_t h = hits[r];
-      if (h >= 0 && w.owner[h] == key) O.hit_id[k++] = w.cid[h];
-    }
+    const int32_t* own = w.tl_own + s * w.R;
+    for (uint32_t q = 0; q < n; ++q) O.hit_id[o + q] = w.cid[own[n - 1 - q]];
   }
 }
 
 }  // namespace
+
+// Persistent grid of the tracklet kernel: enough waves to cover every seed
+// of the largest event set at once, capped by the machine (256 CUs x 8
+// waves of 64 lanes), or the tuned value.
+unsigned tracklet_grid(const Ws& w) {
+  if (w.tracklet_grid > 0) return (unsigned)w.tracklet_grid;
+  const int64_t cap = 256 * 8 * 64 / TB;
+  return blocks_for(w.seed_cap, cap);
+}
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -753,7 +885,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(hipGetLastError());
   const unsigned nbN = (unsigned)w.nb;
   TPCCA_MARK(PH_LINKS);
-  k_links<<<nbN, TB, 0, st>>>(w);
+  k_links<<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_CLEAN);
   k_clean<<<nbN, TB, 0, st>>>(w);
   TPCCA_MARK(PH_COMPACT);
@@ -764,12 +896,16 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_TRACKLETS);
-  k_tracklets<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_OWNER);
   k_owner<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
-  k_refit<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_accept<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
+  k_acc_list<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);
+  k_trk_flags<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   TPCCA_MARK(PH_OUTPUT);
   TPCCA_CHECK(scan_u32(w.trk_flag, w.trk_flag, w.seed_cap, w.scan_tmp, st));
   TPCCA_CHECK(scan_u32(w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));

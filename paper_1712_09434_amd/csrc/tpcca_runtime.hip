@@ -41,7 +41,18 @@ struct tpcca_ctx {
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
   // tuning
-  tpcca_tuning tune{12, 0};
+  tpcca_tuning tune{12, 0, 0};
+  // captured tracking graph and the workspace shape it was captured for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphKey {
+    int64_t N = -1;
+    int E = 0;
+    char* arena = nullptr;
+    hipStream_t st = nullptr;
+    tpcca_params P{};
+    int tracklet_grid = 0;
+  } gkey;
   // phase timing
   bool timing = false;
   PhaseEvents pe{};
@@ -104,6 +115,9 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_tln = L.take<int32_t>(SC), o_tlr = L.take<int32_t>(SC);
   size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * R);
   size_t o_own = L.take<uint64_t>(N);
+  size_t o_tlo = L.take<int32_t>(SC * R);
+  size_t o_acf = L.take<uint32_t>(SC + 1), o_aco = L.take<uint32_t>(SC + 1);
+  size_t o_acl = L.take<uint32_t>(SC), o_occ = L.take<uint32_t>(SC + 1);
   size_t o_rf = L.take<float>(SC * kRf);
   size_t o_tf = L.take<uint32_t>(SC + 1), o_hc = L.take<uint32_t>(SC + 1);
   size_t o_res = L.take<int64_t>((int64_t)E * 4);
@@ -128,6 +142,9 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.tl_key = (uint64_t*)(base + o_tlk); w.tl_state = (float*)(base + o_tls);
     w.tl_hits = (int32_t*)(base + o_tlh);
     w.owner = (uint64_t*)(base + o_own);
+    w.tl_own = (int32_t*)(base + o_tlo);
+    w.acc_flag = (uint32_t*)(base + o_acf); w.acc_off = (uint32_t*)(base + o_aco);
+    w.acc_list = (uint32_t*)(base + o_acl); w.own_cnt = (uint32_t*)(base + o_occ);
     w.rf = (float*)(base + o_rf);
     w.trk_flag = (uint32_t*)(base + o_tf); w.hit_cnt = (uint32_t*)(base + o_hc);
     w.ev_res = (int64_t*)(base + o_res);
@@ -270,6 +287,8 @@ int tpcca_phase_times(const tpcca_ctx* c, int32_t cap, const char** names, doubl
 
 void tpcca_destroy(tpcca_ctx* c) {
   if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (int i = 0; i <= PH_N; ++i)
     if (c->pe.ev[i]) (void)hipEventDestroy(c->pe.ev[i]);
   if (c->arena) (void)hipFree(c->arena);
@@ -315,6 +334,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   w.P = c->P;
   w.tan_a = c->tan_a;
   w.z_max = c->z_max;
+  w.tracklet_grid = c->tune.tracklet_grid;
 
   // staging: host inputs and host outputs
   std::vector<HostOut> ho(E);
@@ -387,8 +407,30 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout.data(), sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
   if (he != hipSuccess) return hip_fail(c, he, "table upload");
 
-  he = run_pipeline(w, st, c->timing ? &c->pe : nullptr);
-  if (he != hipSuccess) return hip_fail(c, he, "kernel launch");
+  if (c->tune.use_graph && !c->timing && st != nullptr) {
+    const bool same = c->gexec && c->gkey.N == N && c->gkey.E == E && c->gkey.arena == c->arena &&
+                      c->gkey.st == st && c->gkey.tracklet_grid == c->tune.tracklet_grid &&
+                      std::memcmp(&c->gkey.P, &c->P, sizeof(tpcca_params)) == 0;
+    if (!same) {
+      if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+      if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+      he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+      if (he != hipSuccess) return hip_fail(c, he, "graph capture");
+      hipError_t le = run_pipeline(w, st, nullptr);
+      he = hipStreamEndCapture(st, &c->graph);
+      if (le != hipSuccess) return hip_fail(c, le, "kernel launch (capture)");
+      if (he != hipSuccess) return hip_fail(c, he, "graph capture");
+      he = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
+      if (he != hipSuccess) { c->gexec = nullptr; return hip_fail(c, he, "graph instantiate"); }
+      c->gkey.N = N; c->gkey.E = E; c->gkey.arena = c->arena; c->gkey.st = st;
+      c->gkey.P = c->P; c->gkey.tracklet_grid = c->tune.tracklet_grid;
+    }
+    he = hipGraphLaunch(c->gexec, st);
+    if (he != hipSuccess) return hip_fail(c, he, "graph launch");
+  } else {
+    he = run_pipeline(w, st, c->timing ? &c->pe : nullptr);
+    if (he != hipSuccess) return hip_fail(c, he, "kernel launch");
+  }
   uint32_t flags[F_COUNT];
   std::vector<int64_t> res((size_t)E * 4);
   he = hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, st);
@@ -404,6 +446,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
     }
     c->timed_calls++;
   }
+  if (flags[F_ERR] & ERR_STUCK) return fail(c, TPCCA_E_DEVICE, "tracklet kernel exceeded its iteration bound");
   if (flags[F_ERR] & ERR_INVALID) return fail(c, TPCCA_E_INVALID, "non-finite coordinate or row/sector out of range");
   if (flags[F_ERR] & ERR_LIMIT)
     return fail(c, TPCCA_E_LIMIT, "a pad row holds more than " + std::to_string(kMaxRow) + " clusters");
@@ -486,7 +529,7 @@ int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t*
 
 int tpcca_set_tuning(tpcca_ctx* c, const tpcca_tuning* t) {
   if (!c || !t) return TPCCA_E_INVALID;
-  if (t->ckpt_every < 1 || t->ckpt_every > 160 || t->tracklet_grid < 0)
+  if (t->ckpt_every < 1 || t->ckpt_every > 160 || t->tracklet_grid < 0 || t->use_graph < 0 || t->use_graph > 1)
     return fail(c, TPCCA_E_INVALID, "invalid tuning values");
   c->tune = *t;
   return TPCCA_OK;
@@ -540,7 +583,7 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   // scratch layout
   Layout L;
   size_t o_hx = L.take<float>(H), o_hy = L.take<float>(H), o_hz = L.take<float>(H);
-  size_t o_gx = L.take<float>(H), o_gy = L.take<float>(H), o_gz = L.take<float>(H);
+  size_t o_gx = L.take<float>(H), o_gy = L.take<float>(H), o_gz = L.take<float>(H), o_gpt = L.take<float>(H);
   size_t o_part = L.take<float>(T * kPart);
   size_t o_tf = L.take<int32_t>(T), o_tn = L.take<int32_t>(T);
   size_t o_ck = L.take<float>(T * nck * 20), o_sg = L.take<float>(T * nseg * 20);
@@ -618,6 +661,7 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   if (he != hipSuccess) return hip_fail(c, he, "input upload");
   w.hx = (float*)(b + o_hx); w.hy = (float*)(b + o_hy); w.hz = (float*)(b + o_hz);
   w.gx = (float*)(b + o_gx); w.gy = (float*)(b + o_gy); w.gz = (float*)(b + o_gz);
+  w.gpt = (float*)(b + o_gpt);
   w.part = (float*)(b + o_part); w.tflag = (int32_t*)(b + o_tf); w.tndf = (int32_t*)(b + o_tn);
   w.ckpt = (float*)(b + o_ck); w.seg = (float*)(b + o_sg);
   w.chunk = (double*)(b + o_chunk); w.out = (double*)(b + o_out);

@@ -53,6 +53,23 @@ class Tracks:
         return int(self.x_ref.shape[0])
 
 
+@dataclass
+class FitTracks:
+    """Fixed hit lists for tpcca_refit_grad: the clusters (default
+    transformation), CSR hit lists in ascending pad row, the q/pT prior, the
+    external tan(lambda) and the vertex flags (tensors on one device)."""
+    clusters: tuple
+    hit_off: torch.Tensor
+    hit_id: torch.Tensor
+    k_prior: torch.Tensor
+    ext_tgl: Optional[torch.Tensor]
+    use_vertex: Optional[torch.Tensor]
+
+    @property
+    def n_tracks(self) -> int:
+        return int(self.hit_off.shape[0]) - 1
+
+
 class Tracker:
     """tpcca_create / tpcca_track / tpcca_track_batch / tpcca_refit_grad."""
 
@@ -160,6 +177,44 @@ class Tracker:
             outs.append(o)
         _check(self.L, self.ctx, self.L.tpcca_track_batch(self.ctx, E, cls, sts))
         return [self._slice(sts[e], outs[e], int(events[e][0].shape[0])) for e in range(E)]
+
+    # ----------------------------------------------------------- calibration
+    def set_tuning(self, ckpt_every: int = 12, tracklet_grid: int = 0, use_graph: int = 0):
+        t = A.tpcca_tuning(int(ckpt_every), int(tracklet_grid), int(use_graph))
+        _check(self.L, self.ctx, self.L.tpcca_set_tuning(self.ctx, C.byref(t)))
+
+    def refit_grad(self, fit: "FitTracks", theta: torch.Tensor):
+        """Total chi2, ndf and d chi2/d theta (float64, flat layout
+        [drift_scale(S), time_offset(S), map(S*64)]) of the fixed hit lists in
+        `fit` under the calibration theta (flat float32, same layout)."""
+        S = self.n_sectors
+        th = theta.detach().to(torch.float32).contiguous()
+        dev = th.device
+        grad = torch.empty(S * 66, dtype=torch.float64, device=dev)
+        cl = self.clusters_struct(*fit.clusters)
+        st = A.tpcca_tracks()
+        st.n_tracks = fit.n_tracks
+        st.hit_off = _ptr(fit.hit_off)
+        st.hit_id = _ptr(fit.hit_id)
+        st.k_prior = _ptr(fit.k_prior)
+        st.ext_tgl = _ptr(fit.ext_tgl)
+        st.use_vertex = _ptr(fit.use_vertex)
+        st.clusters = C.pointer(cl)
+        st.mem = _mem(fit.hit_off)
+        cal = A.tpcca_calib(_ptr(th), C.c_void_p(th.data_ptr() + 4 * S), C.c_void_p(th.data_ptr() + 8 * S),
+                            _mem(th))
+        g = A.tpcca_grad()
+        g.d_drift_scale = _ptr(grad)
+        g.d_time_offset = C.c_void_p(grad.data_ptr() + 8 * S)
+        g.d_map = C.c_void_p(grad.data_ptr() + 16 * S)
+        g.mem = _mem(grad)
+        _check(self.L, self.ctx, self.L.tpcca_refit_grad(self.ctx, C.byref(st), C.byref(cal), C.byref(g)))
+        return float(g.chi2), int(g.ndf), grad
+
+    def get_tuning(self) -> A.tpcca_tuning:
+        t = A.tpcca_tuning()
+        _check(self.L, self.ctx, self.L.tpcca_get_tuning(self.ctx, C.byref(t)))
+        return t
 
     def set_phase_timing(self, on: bool = True):
         _check(self.L, self.ctx, self.L.tpcca_set_phase_timing(self.ctx, 1 if on else 0))

@@ -1,0 +1,63 @@
+"""Calibration as gradient descent on the GPU (the paper's feedback loop,
+Sec. "Approach for online calibration"): Adam on the correction theta,
+through the torch.autograd.Function around tpcca_refit_grad, recovers an
+injected miscalibration; the optimiser state checkpoints and resumes."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from calibset import calib_subset
+
+pytestmark = pytest.mark.gpu
+S = 36
+NEV = int(os.environ.get("TPCCA_CALIB_EVENTS", "10"))
+
+
+@pytest.fixture(scope="module")
+def dataset():
+    from paper_1712_09434_amd import FitTracks, Tracker
+    dev = torch.device("cuda:0")
+    trk = Tracker.from_geometry(synth.default_geometry())
+    cols = [[] for _ in range(5)]
+    offs, ids, k0s, exts = [0], [], [], []
+    base = 0
+    for e in range(NEV):
+        ev = synth.make_config("C5", e)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        out = trk.track(t(ev.x), t(ev.y), t(ev.z), t(ev.row), t(ev.sector))
+        off = out.hit_off.cpu().numpy().astype(np.int64)
+        hid = out.hit_id.cpu().numpy().astype(np.int64)
+        cs = calib_subset(ev, off, hid, out.sector.cpu().numpy(), out.chi2.cpu().numpy(),
+                          out.ndf.cpu().numpy(), out.k_prior.cpu().numpy())
+        for L, a in zip(cols, (ev.x, ev.y, ev.z, ev.row, ev.sector)):
+            L.append(a)
+        for k in range(len(cs["k0"])):
+            h = cs["hit_ids"][cs["hit_off"][k]:cs["hit_off"][k + 1]] + base
+            ids.append(h)
+            offs.append(offs[-1] + len(h))
+        k0s.append(cs["k0"]); exts.append(cs["ext_tgl"])
+        base += ev.n
+    cat = lambda a, dt: torch.from_numpy(np.ascontiguousarray(np.concatenate(a)).astype(dt)).to(dev)
+    cl = (cat(cols[0], np.float32), cat(cols[1], np.float32), cat(cols[2], np.float32),
+          cat(cols[3], np.int16), cat(cols[4], np.uint8))
+    fit = FitTracks(clusters=cl, hit_off=torch.tensor(offs, dtype=torch.int32, device=dev),
+                    hit_id=cat(ids, np.int32), k_prior=cat(k0s, np.float32), ext_tgl=cat(exts, np.float32),
+                    use_vertex=torch.ones(len(offs) - 1, dtype=torch.uint8, device=dev))
+    hid = np.concatenate(ids)
+    x = np.concatenate(cols[0]).astype(float)[hid]
+    y = np.concatenate(cols[1]).astype(float)[hid]
+    sec = np.concatenate(cols[4])[hid].astype(int)
+    print(f"[gpu] calibration set: {NEV} events, {fit.n_tracks} tracks, {offs[-1]} hits", flush=True)
+    yield trk, fit, synth.draw_theta().flat(), (x, y, sec)
+    trk.close()
+
+
+def radial_map(theta, pts):
+    x, y, sec = pts
+    ta = np.tan(np.deg2rad(10.0))
+    Ba = synth.bspline_basis((x - 85.0) / 162.0)
+    Bb = synth.bspline_basis((y / x + ta) / (2 * ta))
+    return np.einsum("na,nab,nb->n", Ba, theta[72:].reshape(S, 8, 8)[sec], Bb)

@@ -191,3 +191,43 @@ def test_row_limit(tracker):
     sec = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
     rc, _ = _raw_track(tracker, x, y, z, row, sec, 100, n)
     assert rc == A.TPCCA_E_LIMIT
+
+
+def test_graph_replay_matches_eager(tracker):
+    """Captured tracking graph: every replay equals the eager call, with eager
+    GPU work and synchronisations between replays."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        evs = [synth.make_config("C1"), synth.make_event(seed=21, n_primaries=400, noise=0.03)]
+        tens = [to_dev(e) for e in evs]
+        tracker.set_tuning(use_graph=0)
+        eager = [tracker.track(*t) for t in tens]
+        tracker.set_tuning(use_graph=1)
+        try:
+            for rep in range(3):
+                for e, t in enumerate(tens):
+                    out = tracker.track(*t)
+                    junk = t[0] * 2.0 + 1.0          # eager work between replays
+                    torch.cuda.synchronize()
+                    for k in ("hit_off", "hit_id", "p", "cov", "chi2", "sector"):
+                        assert torch.equal(getattr(out, k), getattr(eager[e], k)), (rep, e, k)
+                    del junk
+            batch = tracker.track_batch(tens)
+            batch2 = tracker.track_batch(tens)
+            for e in range(len(tens)):
+                assert torch.equal(batch[e].hit_id, eager[e].hit_id)
+                assert torch.equal(batch2[e].p, eager[e].p)
+        finally:
+            tracker.set_tuning(use_graph=0)
+
+
+def test_tracklet_grid_does_not_change_results(tracker):
+    ev = synth.make_config("C2")
+    t = to_dev(ev)
+    ref = tracker.track(*t)
+    for g in (1, 7, 256, 4096):
+        tracker.set_tuning(tracklet_grid=g)
+        out = tracker.track(*t)
+        for k in ("hit_off", "hit_id", "p"):
+            assert torch.equal(getattr(out, k), getattr(ref, k)), (g, k)
+    tracker.set_tuning(tracklet_grid=0)
