@@ -45,7 +45,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run device copies of this many MiB (calibrates PMC byte counters)")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the tracker shards by event and sector with no exchange, "
@@ -128,6 +133,23 @@ def main():
     }
     trk.close()
     print(json.dumps(line), flush=True)
+
+
+def copy_probe(mib: int, reps: int = 5):
+    """A plain device-to-device copy of `mib` MiB, `reps` times: each copy
+    reads and writes exactly mib MiB, which scales FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_mib": mib, "reps": reps, "ms_per_copy": dt * 1e3,
+                      "GBps": 2 * mib * (1 << 20) / dt / 1e9}), flush=True)
 
 
 def _to_dev(ev, dev):

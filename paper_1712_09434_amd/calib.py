@@ -50,27 +50,95 @@ def from_theta(theta: torch.Tensor, n_sectors: int, drift_length: float,
     return torch.cat([d / drift_unit, theta[S:2 * S] - drift_length * d, theta[2 * S:]])
 
 
+def sector_hessian(tracker: Tracker, fit: FitTracks, theta0: torch.Tensor,
+                   steps=(2e-4, 0.01, 0.01)) -> torch.Tensor:
+    """Per-sector 66x66 Hessian blocks of chi2 at theta0 by central
+    differences of the library gradient.  Parameters of different sectors
+    never share a track, so perturbing parameter p of every sector at once
+    gives column p of all blocks: 2 x 66 gradient evaluations.
+    steps: perturbation of (drift scale, time offset [cm], map [cm])."""
+    S = tracker.n_sectors
+    dev = theta0.device
+    th0 = theta0.to(torch.float64)
+    H = torch.zeros(S, 66, 66, dtype=torch.float64, device=dev)
+
+    def sp(v):   # [S*66] layout -> [S, 66]
+        return torch.cat([v[:S, None], v[S:2 * S, None], v[2 * S:].reshape(S, 64)], dim=1)
+
+    def flat(a):
+        return torch.cat([a[:, 0], a[:, 1], a[:, 2:].reshape(-1)])
+
+    for q in range(66):
+        h = steps[0] if q == 0 else steps[1] if q == 1 else steps[2]
+        e = torch.zeros(S, 66, dtype=torch.float64, device=dev)
+        e[:, q] = h
+        _, _, gp = tracker.refit_grad(fit, (th0 + flat(e)).to(torch.float32))
+        _, _, gm = tracker.refit_grad(fit, (th0 - flat(e)).to(torch.float32))
+        H[:, :, q] = (sp(gp) - sp(gm)) / (2.0 * h)
+    return 0.5 * (H + H.transpose(1, 2))
+
+
+def whitening(H: torch.Tensor, floor: float = 1e-9):
+    """Symmetric square roots W = H^(1/2) and W^-1 per block (eigenvalues
+    floored at floor * the block's largest)."""
+    w, V = torch.linalg.eigh(H)
+    w = torch.clamp(w, min=floor * w.max(dim=1, keepdim=True).values)
+    r = torch.sqrt(w)
+    W = V @ torch.diag_embed(r) @ V.transpose(1, 2)
+    Wi = V @ torch.diag_embed(1.0 / r) @ V.transpose(1, 2)
+    return W, Wi
+
+
 def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 0.02),
               theta0: Optional[torch.Tensor] = None, betas=(0.9, 0.999), drift_length: float = 250.0,
-              callback: Optional[Callable] = None, state: Optional[dict] = None):
-    """Adam on theta from theta0 (default 0) in the variables of to_theta.
-    lr = learning rates of the (drift scale [1e-3], drift offset [cm],
-    map [cm]) groups.  Returns (theta, history, state); `state` (step,
-    moments, variables) allows a resume from a checkpoint."""
+              callback: Optional[Callable] = None, state: Optional[dict] = None,
+              precondition: bool = False, lr_white: float = 10.0):
+    """Adam on theta from theta0 (default 0).
+
+    Without preconditioning the variables are those of to_theta and
+    lr = learning rates of the (drift scale [1e-3], drift offset [cm], map
+    [cm]) groups.  With precondition=True the per-sector Hessian blocks at
+    theta0 are estimated once (sector_hessian) and Adam runs on
+    u = H^(1/2) (theta - theta0), where chi2 is locally isotropic, with the
+    single learning rate lr_white.  Returns (theta, history, state); `state`
+    (step, moments, variables, whitening) allows a resume from a checkpoint."""
     S = tracker.n_sectors
     dev = fit.hit_off.device
     if state is None:
         th0 = torch.zeros(S * 66, dtype=torch.float64, device=dev) if theta0 is None else (
             theta0.to(torch.float64).to(dev))
-        u0 = from_theta(th0, S, drift_length)
-        state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0))
-    lr_vec = torch.empty(S * 66, dtype=torch.float64, device=dev)
-    lr_vec[:S] = lr[0]; lr_vec[S:2 * S] = lr[1]; lr_vec[2 * S:] = lr[2]
+        if precondition:
+            H = sector_hessian(tracker, fit, th0)
+            W, Wi = whitening(H)
+            u0 = torch.zeros(S * 66, dtype=torch.float64, device=dev)
+            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0), W=W, Wi=Wi, th0=th0)
+        else:
+            u0 = from_theta(th0, S, drift_length)
+            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0))
+    white = "Wi" in state
+
+    def sp(v):
+        return torch.cat([v[:S, None], v[S:2 * S, None], v[2 * S:].reshape(S, 64)], dim=1)
+
+    def flat(a):
+        return torch.cat([a[:, 0], a[:, 1], a[:, 2:].reshape(-1)])
+
+    def theta_of(u):
+        if white:
+            du = (state["Wi"] @ u.reshape(S, 66, 1)).reshape(S, 66)
+            return state["th0"] + flat(du)
+        return to_theta(u, S, drift_length)
+
+    if white:
+        lr_vec = torch.full((S * 66,), float(lr_white), dtype=torch.float64, device=dev)
+    else:
+        lr_vec = torch.empty(S * 66, dtype=torch.float64, device=dev)
+        lr_vec[:S] = lr[0]; lr_vec[S:2 * S] = lr[1]; lr_vec[2 * S:] = lr[2]
     b1, b2 = betas
     hist = []
     for _ in range(steps):
         u = state["u"].clone().requires_grad_(True)
-        chi2 = Chi2Refit.apply(to_theta(u, S, drift_length), tracker, fit)
+        chi2 = Chi2Refit.apply(theta_of(u), tracker, fit)
         chi2.backward()
         gu = u.grad.detach()
         state["step"] += 1
@@ -83,15 +151,16 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
         hist.append(float(chi2))
         if callback:
             callback(t, float(chi2), state)
-    return to_theta(state["u"], S, drift_length).detach(), hist, state
+    return theta_of(state["u"]).detach(), hist, state
 
 
 def save_state(path: str, state: dict) -> None:
-    np.savez(path, step=state["step"], u=state["u"].cpu().numpy(), m=state["m"].cpu().numpy(),
-             v=state["v"].cpu().numpy())
+    arrays = {k: v.cpu().numpy() for k, v in state.items() if isinstance(v, torch.Tensor)}
+    np.savez(path, step=state["step"], **arrays)
 
 
 def load_state(path: str, device) -> dict:
     z = np.load(path)
-    t = lambda a: torch.from_numpy(a).to(torch.float64).to(device)
-    return dict(step=int(z["step"]), u=t(z["u"]), m=t(z["m"]), v=t(z["v"]))
+    st = {k: torch.from_numpy(z[k]).to(torch.float64).to(device) for k in z.files if k != "step"}
+    st["step"] = int(z["step"])
+    return st

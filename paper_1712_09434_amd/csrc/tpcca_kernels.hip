@@ -140,12 +140,33 @@ __device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int
   return true;
 }
 
+// Binning histograms are privatised in LDS per chunk of kChunk clusters: the
+// bins are the row units of the event of the chunk's first cluster (a chunk
+// that reaches into the next events sends those clusters straight to the
+// global counters).  Count: one global atomic per non-empty bin.  Scatter:
+// one global range reservation per non-empty bin, then LDS ranks.
+constexpr int kChunkCl = 8192;
+constexpr int kLdsBins = 8192;
+
 __global__ __launch_bounds__(TB) void k_count(Ws w) {
-  for (int64_t g = (int64_t)blockIdx.x * TB + threadIdx.x; g < w.N; g += (int64_t)gridDim.x * TB) {
+  __shared__ uint32_t s_h[kLdsBins];
+  const int64_t c0 = (int64_t)blockIdx.x * kChunkCl;
+  const int64_t c1 = c0 + kChunkCl < w.N ? c0 + kChunkCl : w.N;
+  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
+  const bool lds = per <= (uint32_t)kLdsBins;
+  const uint32_t rb = (uint32_t)find_event(w, c0) * per;
+  if (lds) for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
+  __syncthreads();
+  for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
     int e; int64_t l; uint32_t ru;
     if (!read_cluster(w, g, e, l, ru)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
-    atomicAdd(&w.ru_count[ru], 1u);
+    if (lds && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
+    else atomicAdd(&w.ru_count[ru], 1u);
   }
+  __syncthreads();
+  if (lds)
+    for (uint32_t b = threadIdx.x; b < per; b += TB)
+      if (s_h[b]) atomicAdd(&w.ru_count[rb + b], s_h[b]);
 }
 
 // cells + 1 offsets per row unit
@@ -154,11 +175,33 @@ __global__ void k_cell_caps(Ws w) {
     w.cell_cap[ru] = (w.ru_count[ru] >> 1) + 2u;
 }
 
+// ru_count is reused as the global fill cursor (zeroed after the scans).
 __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
-  for (int64_t g = (int64_t)blockIdx.x * TB + threadIdx.x; g < w.N; g += (int64_t)gridDim.x * TB) {
+  __shared__ uint32_t s_h[kLdsBins];
+  const int64_t c0 = (int64_t)blockIdx.x * kChunkCl;
+  const int64_t c1 = c0 + kChunkCl < w.N ? c0 + kChunkCl : w.N;
+  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
+  const bool lds = per <= (uint32_t)kLdsBins;
+  const uint32_t rb = (uint32_t)find_event(w, c0) * per;
+  if (lds) {
+    for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
+    __syncthreads();
+    for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
+      int e; int64_t l; uint32_t ru;
+      if (!read_cluster(w, g, e, l, ru)) continue;
+      if (ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < per; b += TB) {
+      const uint32_t n = s_h[b];
+      s_h[b] = n ? atomicAdd(&w.ru_count[rb + b], n) : 0u;
+    }
+    __syncthreads();
+  }
+  for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
     int e; int64_t l; uint32_t ru;
     if (!read_cluster(w, g, e, l, ru)) continue;
-    const uint32_t k = atomicSub(&w.ru_count[ru], 1u) - 1u;
+    const uint32_t k = (lds && ru - rb < per) ? atomicAdd(&s_h[ru - rb], 1u) : atomicAdd(&w.ru_count[ru], 1u);
     w.tmp[w.ru_off[ru] + k] = (uint32_t)g;
   }
 }
@@ -872,14 +915,16 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
   TPCCA_CHECK(fill_u32((uint32_t*)w.owner, 0u, 2 * w.N, st));
   TPCCA_MARK(PH_COUNT);
-  k_count<<<blocks_for(w.N), TB, 0, st>>>(w);
+  const unsigned nchunk = (unsigned)((w.N + kChunkCl - 1) / kChunkCl > 0 ? (w.N + kChunkCl - 1) / kChunkCl : 1);
+  k_count<<<nchunk, TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_SCAN);
   TPCCA_CHECK(scan_u32(w.ru_count, w.ru_off, w.RU, w.scan_tmp, st));
   TPCCA_CHECK(scan_u32(w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
+  TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
   TPCCA_MARK(PH_SCATTER);
-  k_scatter<<<blocks_for(w.N), TB, 0, st>>>(w);
+  k_scatter<<<nchunk, TB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
   k_rows<<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());

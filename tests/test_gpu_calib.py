@@ -14,6 +14,7 @@ from calibset import calib_subset
 pytestmark = pytest.mark.gpu
 S = 36
 NEV = int(os.environ.get("TPCCA_CALIB_EVENTS", "10"))
+LR = (0.5, 0.02, 0.02)   # Adam learning rates: drift scale [1e-3], drift offset [cm], map [cm]
 
 
 @pytest.fixture(scope="module")
@@ -61,3 +62,36 @@ def radial_map(theta, pts):
     Ba = synth.bspline_basis((x - 85.0) / 162.0)
     Bb = synth.bspline_basis((y / x + ta) / (2 * ta))
     return np.einsum("na,nab,nb->n", Ba, theta[72:].reshape(S, 8, 8)[sec], Bb)
+
+
+def recovery_metrics(theta, theta_star, pts):
+    d = np.abs(theta[:S] - theta_star[:S]).max()
+    t = np.abs(theta[S:2 * S] - theta_star[S:2 * S]).max()
+    rs = radial_map(theta_star, pts)
+    r = np.sqrt(np.mean((radial_map(theta, pts) - rs) ** 2) / np.mean(rs ** 2))
+    return d, t, r
+
+
+def test_adam_recovers_injected_miscalibration(dataset):
+    from paper_1712_09434_amd import calibrate
+    trk, fit, theta_star, pts = dataset
+    theta, hist, _ = calibrate(trk, fit, steps=50, lr=LR)
+    d, t, r = recovery_metrics(theta.cpu().numpy(), theta_star, pts)
+    print(f"[gpu] adam: chi2 {hist[0]:.0f} -> {hist[-1]:.0f}; max|d-d*| {d:.2e}, max|tau-tau*| {t:.4f}, "
+          f"map rms rel {r:.3f}", flush=True)
+    assert hist[-1] < hist[0]
+    assert d <= 0.2 * 2e-3          # 0.2 of the injected spread of the drift scale
+    assert t <= 0.2 * 0.1           # 0.2 of the injected spread of the time offset (cm)
+    assert r <= 0.2                 # radial map: 20 % of the injected RMS at the cluster positions
+
+
+def test_resume_from_checkpoint(dataset, tmp_path):
+    from paper_1712_09434_amd.calib import calibrate, load_state, save_state
+    trk, fit, theta_star, pts = dataset
+    _, h_all, st_all = calibrate(trk, fit, steps=6, lr=LR)
+    _, h1, st1 = calibrate(trk, fit, steps=3, lr=LR)
+    save_state(str(tmp_path / "adam.npz"), st1)
+    st2 = load_state(str(tmp_path / "adam.npz"), fit.hit_off.device)
+    _, h2, st2 = calibrate(trk, fit, steps=3, lr=LR, state=st2)
+    assert h1 + h2 == h_all
+    assert torch.equal(st2["u"], st_all["u"])
