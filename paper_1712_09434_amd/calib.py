@@ -10,6 +10,8 @@ computed in the same call.  ``calibrate`` runs Adam on theta.
 """
 from __future__ import annotations
 
+import math
+
 from typing import Callable, Optional
 
 import numpy as np
@@ -89,33 +91,38 @@ def whitening(H: torch.Tensor, floor: float = 1e-9):
     return W, Wi
 
 
+def default_prior_sigma(n_sectors: int = 36, device=None) -> torch.Tensor:
+    """Expected spread of the miscalibration: drift scale 2e-3, time offset
+    0.1 cm, map coefficients 0.3/sqrt(3) cm (the sd of U(-0.3, 0.3))."""
+    s = torch.empty(n_sectors * 66, dtype=torch.float64, device=device)
+    s[:n_sectors] = 2e-3
+    s[n_sectors:2 * n_sectors] = 0.1
+    s[2 * n_sectors:] = 0.3 / math.sqrt(3.0)
+    return s
+
+
 def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 0.02),
               theta0: Optional[torch.Tensor] = None, betas=(0.9, 0.999), drift_length: float = 250.0,
               callback: Optional[Callable] = None, state: Optional[dict] = None,
-              precondition: bool = False, lr_white: float = 10.0):
+              precondition: bool = False, lr_white: float = 30.0, lr_final: float = 0.1,
+              prior_sigma: Optional[torch.Tensor] = None):
     """Adam on theta from theta0 (default 0).
+
+    Loss: the refit chi2 and, if prior_sigma is given, a Gaussian prior
+    sum((theta / prior_sigma)^2) on the size of the miscalibration (a MAP
+    estimate: directions the tracks cannot see stay near zero instead of
+    drifting).
 
     Without preconditioning the variables are those of to_theta and
     lr = learning rates of the (drift scale [1e-3], drift offset [cm], map
-    [cm]) groups.  With precondition=True the per-sector Hessian blocks at
-    theta0 are estimated once (sector_hessian) and Adam runs on
-    u = H^(1/2) (theta - theta0), where chi2 is locally isotropic, with the
-    single learning rate lr_white.  Returns (theta, history, state); `state`
+    [cm]) groups.  With precondition=True the per-sector Hessian blocks of
+    the loss at theta0 are estimated once (sector_hessian plus the prior's
+    curvature) and Adam runs on u = H^(1/2) (theta - theta0), where the loss
+    is locally isotropic, with a step size decaying from lr_white to lr_final
+    (half cosine over `steps`).  Returns (theta, history, state); `state`
     (step, moments, variables, whitening) allows a resume from a checkpoint."""
     S = tracker.n_sectors
     dev = fit.hit_off.device
-    if state is None:
-        th0 = torch.zeros(S * 66, dtype=torch.float64, device=dev) if theta0 is None else (
-            theta0.to(torch.float64).to(dev))
-        if precondition:
-            H = sector_hessian(tracker, fit, th0)
-            W, Wi = whitening(H)
-            u0 = torch.zeros(S * 66, dtype=torch.float64, device=dev)
-            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0), W=W, Wi=Wi, th0=th0)
-        else:
-            u0 = from_theta(th0, S, drift_length)
-            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0))
-    white = "Wi" in state
 
     def sp(v):
         return torch.cat([v[:S, None], v[S:2 * S, None], v[2 * S:].reshape(S, 64)], dim=1)
@@ -123,23 +130,40 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
     def flat(a):
         return torch.cat([a[:, 0], a[:, 1], a[:, 2:].reshape(-1)])
 
+    if state is None:
+        th0 = torch.zeros(S * 66, dtype=torch.float64, device=dev) if theta0 is None else (
+            theta0.to(torch.float64).to(dev))
+        if precondition:
+            H = sector_hessian(tracker, fit, th0)
+            if prior_sigma is not None:
+                H = H + torch.diag_embed(sp(2.0 / prior_sigma.to(dev) ** 2))
+            W, Wi = whitening(H)
+            u0 = torch.zeros(S * 66, dtype=torch.float64, device=dev)
+            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0), W=W, Wi=Wi, th0=th0,
+                         total=torch.tensor(float(steps)))
+        else:
+            u0 = from_theta(th0, S, drift_length)
+            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0))
+    white = "Wi" in state
+
     def theta_of(u):
         if white:
             du = (state["Wi"] @ u.reshape(S, 66, 1)).reshape(S, 66)
             return state["th0"] + flat(du)
         return to_theta(u, S, drift_length)
 
-    if white:
-        lr_vec = torch.full((S * 66,), float(lr_white), dtype=torch.float64, device=dev)
-    else:
+    if not white:
         lr_vec = torch.empty(S * 66, dtype=torch.float64, device=dev)
         lr_vec[:S] = lr[0]; lr_vec[S:2 * S] = lr[1]; lr_vec[2 * S:] = lr[2]
     b1, b2 = betas
     hist = []
     for _ in range(steps):
         u = state["u"].clone().requires_grad_(True)
-        chi2 = Chi2Refit.apply(theta_of(u), tracker, fit)
-        chi2.backward()
+        theta = theta_of(u)
+        loss = Chi2Refit.apply(theta, tracker, fit)
+        if prior_sigma is not None:
+            loss = loss + ((theta / prior_sigma.to(dev)) ** 2).sum()
+        loss.backward()
         gu = u.grad.detach()
         state["step"] += 1
         t = state["step"]
@@ -147,10 +171,15 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
         state["v"] = b2 * state["v"] + (1 - b2) * gu * gu
         mh = state["m"] / (1 - b1 ** t)
         vh = state["v"] / (1 - b2 ** t)
-        state["u"] = state["u"] - lr_vec * mh / (torch.sqrt(vh) + 1e-12)
-        hist.append(float(chi2))
+        if white:
+            frac = min(1.0, (t - 1) / max(float(state["total"]) - 1.0, 1.0))
+            rate = lr_final + 0.5 * (lr_white - lr_final) * (1.0 + math.cos(math.pi * frac))
+            state["u"] = state["u"] - rate * mh / (torch.sqrt(vh) + 1e-12)
+        else:
+            state["u"] = state["u"] - lr_vec * mh / (torch.sqrt(vh) + 1e-12)
+        hist.append(float(loss))
         if callback:
-            callback(t, float(chi2), state)
+            callback(t, float(loss), state)
     return theta_of(state["u"]).detach(), hist, state
 
 

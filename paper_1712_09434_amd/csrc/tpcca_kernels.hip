@@ -527,20 +527,32 @@ struct Found { int32_t pos; float x, y, z; };
 
 // Closest cluster of row unit ru to the predicted (y, z):
 // d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
-__device__ __forceinline__ Found search_row(const Ws& w, uint32_t ru, const float p[5],
+__device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, const float p[5],
                                             const float C[15]) {
   const float sy2 = C[0] + w.m.vy, sz2 = C[5] + w.m.vz;
   const float isy = 1.0f / sy2, isz = 1.0f / sz2;
   const float CUT = w.P.chi2_ext;
   const float wy = 3.0f * sqrtf(sy2) * 1.0001f, wz = 3.0f * sqrtf(sz2) * 1.0001f;
-  const GridParams G = w.grid[ru];
   const CellBox b = cell_box(G, p[0], p[1], wy, wz);
   Found best{-1, 0.f, 0.f, 0.f};
   float bd = 0.0f;
-  for (uint32_t iz = b.iz0; iz <= b.iz1; ++iz) {
-    const uint32_t c0 = G.cell_base + iz * G.ny;
-    const uint32_t k1 = w.cell_off[c0 + b.iy1 + 1];
-    for (uint32_t k = w.cell_off[c0 + b.iy0]; k < k1; ++k) {
+  // issue the cell-range loads of the first two z rows of the box together
+  const uint32_t nzr = b.iz1 - b.iz0 + 1;
+  const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
+  const uint32_t c0b = c0a + G.ny;
+  uint32_t ka0 = w.cell_off[c0a + b.iy0], ka1 = w.cell_off[c0a + b.iy1 + 1];
+  uint32_t kb0 = 0, kb1 = 0;
+  if (nzr > 1) { kb0 = w.cell_off[c0b + b.iy0]; kb1 = w.cell_off[c0b + b.iy1 + 1]; }
+  for (uint32_t iz = 0; iz < nzr; ++iz) {
+    uint32_t k0, k1;
+    if (iz == 0) { k0 = ka0; k1 = ka1; }
+    else if (iz == 1) { k0 = kb0; k1 = kb1; }
+    else {
+      const uint32_t c0 = G.cell_base + (b.iz0 + iz) * G.ny;
+      k0 = w.cell_off[c0 + b.iy0];
+      k1 = w.cell_off[c0 + b.iy1 + 1];
+    }
+    for (uint32_t k = k0; k < k1; ++k) {
       const float4 c = w.gbuf[k];
       const float dY = c.x - p[0], dZ = c.y - p[1];
       const float d = (dY * dY) * isy + (dZ * dZ) * isz;
@@ -679,6 +691,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
       }
     } else {   // ST_UP or ST_DOWN
       const float X = sX[r];
+      const GridParams G = w.grid[rubase + (uint32_t)r];   // in flight during the transport
       bool go = transport(p, C, xc, X, w.m);
       bool wrote = false;
       if (go) {
@@ -686,7 +699,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
         rstate = r;
         go = accepted(X, acc, p);
         if (go) {
-          const Found h = search_row(w, rubase + (uint32_t)r, p, C);
+          const Found h = search_row(w, G, p, C);
           if (h.pos >= 0) {
             if (h.x != X) {
               go = transport(p, C, X, h.x, w.m);
@@ -891,13 +904,12 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
 
 }  // namespace
 
-// Persistent grid of the tracklet kernel: enough waves to cover every seed
-// of the largest event set at once, capped by the machine (256 CUs x 8
-// waves of 64 lanes), or the tuned value.
+// Persistent grid of the tracklet kernel: by default one lane per possible
+// seed (lanes that find the counter exhausted leave at once), so no seed
+// waits for another; or the tuned value.
 unsigned tracklet_grid(const Ws& w) {
   if (w.tracklet_grid > 0) return (unsigned)w.tracklet_grid;
-  const int64_t cap = 256 * 8 * 64 / TB;
-  return blocks_for(w.seed_cap, cap);
+  return blocks_for(w.seed_cap, 1 << 16);
 }
 
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
