@@ -6,4 +6,4 @@ There is no CPU fallback: calls fail if the library is not built.
 """
 from ._abi import TpccaError, default_params, load  # noqa: F401
 from .tracker import FitTracks, Tracker, Tracks  # noqa: F401
-from .calib import Chi2Refit, calibrate  # noqa: F401
+from .calib import Chi2Refit, calibrate, calibrate_newton  # noqa: F401

@@ -6,7 +6,9 @@ transformation used by tracking).
 ``Chi2Refit`` is a torch.autograd.Function whose forward calls
 tpcca_refit_grad (total Kalman-refit chi2 of a frozen track set under the
 correction theta) and whose backward returns the gradient the library
-computed in the same call.  ``calibrate`` runs Adam on theta.
+computed in the same call.  ``calibrate`` runs Adam on theta;
+``calibrate_newton`` takes damped Newton steps on the per-sector Hessian
+blocks (the MAP estimate under a Gaussian prior on the miscalibration).
 """
 from __future__ import annotations
 
@@ -53,12 +55,16 @@ def from_theta(theta: torch.Tensor, n_sectors: int, drift_length: float,
 
 
 def sector_hessian(tracker: Tracker, fit: FitTracks, theta0: torch.Tensor,
-                   steps=(2e-4, 0.01, 0.01)) -> torch.Tensor:
+                   steps=(1e-3, 0.05, 0.1)) -> torch.Tensor:
     """Per-sector 66x66 Hessian blocks of chi2 at theta0 by central
     differences of the library gradient.  Parameters of different sectors
     never share a track, so perturbing parameter p of every sector at once
     gives column p of all blocks: 2 x 66 gradient evaluations.
-    steps: perturbation of (drift scale, time offset [cm], map [cm])."""
+    steps: perturbation of (drift scale, time offset [cm], map [cm]); the
+    chi2 is close to quadratic in theta (cluster positions move linearly
+    with it), so steps of about half the expected miscalibration keep the
+    truncation error small while the FP32 rounding of the gradient is
+    divided by a large step."""
     S = tracker.n_sectors
     dev = theta0.device
     th0 = theta0.to(torch.float64)
@@ -181,6 +187,65 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
         if callback:
             callback(t, float(loss), state)
     return theta_of(state["u"]).detach(), hist, state
+
+
+def _blocks(v: torch.Tensor, S: int) -> torch.Tensor:
+    return torch.cat([v[:S, None], v[S:2 * S, None], v[2 * S:].reshape(S, 64)], dim=1)
+
+
+def _flat(a: torch.Tensor) -> torch.Tensor:
+    return torch.cat([a[:, 0], a[:, 1], a[:, 2:].reshape(-1)])
+
+
+def map_objective(tracker: Tracker, fit: FitTracks, theta: torch.Tensor, prior_sigma: torch.Tensor):
+    """(chi2 + sum((theta / sigma)^2), its gradient) at theta (FP64)."""
+    chi2, _, g = tracker.refit_grad(fit, theta.to(torch.float32))
+    th = theta.to(torch.float64)
+    return chi2 + float(((th / prior_sigma) ** 2).sum()), g + 2.0 * th / prior_sigma ** 2
+
+
+def calibrate_newton(tracker: Tracker, fit: FitTracks, iters: int = 4, prior_sigma: Optional[torch.Tensor] = None,
+                     theta0: Optional[torch.Tensor] = None, rehess: bool = True, max_halvings: int = 8,
+                     callback: Optional[Callable] = None):
+    """MAP calibration by damped Newton steps.
+
+    Loss f = chi2(theta) + sum((theta / prior_sigma)^2).  Every iteration
+    takes the per-sector Hessian blocks (sector_hessian, recomputed at the
+    current theta when rehess, else kept from theta0), clamps the chi2 part
+    to be positive semi-definite per block (eigenvalues < 0 -> 0, so the
+    prior alone sets the curvature of directions the tracks do not see),
+    solves for the Newton step and halves it until f decreases.  Returns
+    (theta, history of f)."""
+    S = tracker.n_sectors
+    dev = fit.hit_off.device
+    sig = (default_prior_sigma(S, dev) if prior_sigma is None else prior_sigma.to(dev)).to(torch.float64)
+    th = torch.zeros(S * 66, dtype=torch.float64, device=dev) if theta0 is None else theta0.to(torch.float64).to(dev)
+    f, g = map_objective(tracker, fit, th, sig)
+    hist = [f]
+    curv = torch.diag_embed(_blocks(2.0 / sig ** 2, S))
+    H = None
+    for it in range(iters):
+        if H is None or rehess:
+            Hc = sector_hessian(tracker, fit, th)
+            w, V = torch.linalg.eigh(Hc)
+            Hc = V @ torch.diag_embed(torch.clamp(w, min=0.0)) @ V.transpose(1, 2)
+            H = Hc + curv
+        step = -torch.linalg.solve(H, _blocks(g, S).unsqueeze(2)).squeeze(2)
+        step = _flat(step)
+        a = 1.0
+        for _ in range(max_halvings + 1):
+            tn = th + a * step
+            fn, gn = map_objective(tracker, fit, tn, sig)
+            if math.isfinite(fn) and fn < f:
+                break
+            a *= 0.5
+        else:
+            break                      # no decrease along the step: converged to rounding
+        th, f, g = tn, fn, gn
+        hist.append(f)
+        if callback:
+            callback(it + 1, f, th, a)
+    return th, hist
 
 
 def save_state(path: str, state: dict) -> None:

@@ -87,7 +87,7 @@ struct Ws {
   uint32_t* cell_cap;   // [RU] cells + 1 per row unit, then scanned -> cell base [RU + 1]
   uint32_t* cell_base;  // [RU + 1]
   GridParams* grid;     // [RU]
-  uint32_t* tmp;        // [N] global cluster index, bucketed by row unit
+  float4* tmp4;         // [N] (x, y, z, event-local id bits), bucketed by row unit
   // canonical SoA: (event, sector, row, id) order
   float* cx;
   float* cy;
@@ -101,6 +101,7 @@ struct Ws {
   int32_t* up;
   int32_t* dn;
   int32_t* cup;
+  float4* cpk;          // [N] (x, y, z, cleaned up-link bits): one load per chain step
   int32_t* cdn;
   uint8_t* flag;        // bit0 start, bit1 seed
   uint32_t* blk_start;  // [nb + 1]

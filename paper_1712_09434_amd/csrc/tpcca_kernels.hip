@@ -127,8 +127,8 @@ __device__ __forceinline__ int find_event(const Ws& w, int64_t g) {
 }
 
 // ------------------------------------------------------------- a1: binning
-__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int64_t& l,
-                                             uint32_t& ru) {
+__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int64_t& l, uint32_t& ru,
+                                             float4& v) {
   e = find_event(w, g);
   const EventIn& E = w.ev[e];
   l = g - E.base;
@@ -137,6 +137,7 @@ __device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int
   const int s = E.sector[l];
   if (!(isfinite(x) && isfinite(y) && isfinite(z)) || r < 0 || r >= w.R || s >= w.S) return false;
   ru = ((uint32_t)e * (uint32_t)w.S + (uint32_t)s) * (uint32_t)w.R + (uint32_t)r;
+  v = make_float4(x, y, z, __uint_as_float((uint32_t)l));
   return true;
 }
 
@@ -158,8 +159,8 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
   if (lds) for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
   __syncthreads();
   for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int e; int64_t l; uint32_t ru;
-    if (!read_cluster(w, g, e, l, ru)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
+    int e; int64_t l; uint32_t ru; float4 v;
+    if (!read_cluster(w, g, e, l, ru, v)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
     if (lds && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
     else atomicAdd(&w.ru_count[ru], 1u);
   }
@@ -176,6 +177,9 @@ __global__ void k_cell_caps(Ws w) {
 }
 
 // ru_count is reused as the global fill cursor (zeroed after the scans).
+// Each cluster travels with its coordinates and event-local id, so the row
+// kernel reads its row unit contiguously instead of gathering from the
+// (arbitrarily ordered) input.
 __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
   __shared__ uint32_t s_h[kLdsBins];
   const int64_t c0 = (int64_t)blockIdx.x * kChunkCl;
@@ -187,8 +191,8 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
     for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
     __syncthreads();
     for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-      int e; int64_t l; uint32_t ru;
-      if (!read_cluster(w, g, e, l, ru)) continue;
+      int e; int64_t l; uint32_t ru; float4 v;
+      if (!read_cluster(w, g, e, l, ru, v)) continue;
       if (ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
     }
     __syncthreads();
@@ -199,10 +203,10 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
     __syncthreads();
   }
   for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int e; int64_t l; uint32_t ru;
-    if (!read_cluster(w, g, e, l, ru)) continue;
+    int e; int64_t l; uint32_t ru; float4 v;
+    if (!read_cluster(w, g, e, l, ru, v)) continue;
     const uint32_t k = (lds && ru - rb < per) ? atomicAdd(&s_h[ru - rb], 1u) : atomicAdd(&w.ru_count[ru], 1u);
-    w.tmp[w.ru_off[ru] + k] = (uint32_t)g;
+    w.tmp4[w.ru_off[ru] + k] = v;
   }
 }
 
@@ -216,20 +220,22 @@ __device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float 
   return cell_coord(z, G.z0, G.inv_bz, G.nz) * G.ny + cell_coord(y, G.y0, G.inv_by, G.ny);
 }
 
-// One block per row unit: ids sorted ascending in LDS (bitonic), canonical
-// SoA written in that order, then a uniform 2-D grid over the row's bounding
-// box with about two clusters per cell, filled by an LDS counting sort.
+// One block per row unit: the row unit's (x, y, z, id) entries sorted by id
+// in LDS (bitonic on the ids, carrying the entry's slot), canonical SoA
+// written in that order, then a uniform 2-D grid over the row's bounding box
+// with about two clusters per cell, filled by an LDS counting sort.
 __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   __shared__ uint32_t s_ids[kMaxRow];
-  __shared__ uint32_t s_hist[kMaxCells + 1];
+  // slots (16 bit) during the sort, then the cell histogram
+  __shared__ uint32_t s_aux[(kMaxCells + 1) > kMaxRow / 2 ? (kMaxCells + 1) : kMaxRow / 2];
   __shared__ float s_red[4][TB / 64];
   __shared__ GridParams s_gp;
+  uint16_t* s_slot = (uint16_t*)s_aux;
+  uint32_t* s_hist = s_aux;
   const int64_t ru = blockIdx.x;
   const uint32_t off = w.ru_off[ru];
   const uint32_t n = w.ru_off[ru + 1] - off;
   const uint32_t cbase = w.cell_base[ru];
-  const int e = (int)(ru / ((int64_t)w.S * w.R));
-  const EventIn E = w.ev[e];
   const int tid = threadIdx.x;
   if (n > (uint32_t)kMaxRow) {
     if (tid == 0) {
@@ -239,16 +245,23 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
       w.cell_off[cbase] = off;
       w.cell_off[cbase + 1] = off;
     }
+    // every per-position array still gets a defined entry (its own position
+    // in the grid copy), so later kernels stay in bounds until the error is
+    // reported
     const float nan = __int_as_float(0x7fc00000);
     for (uint32_t k = tid; k < n; k += TB) {
       w.cx[off + k] = nan; w.cy[off + k] = nan; w.cz[off + k] = nan;
       w.cid[off + k] = 0u; w.cru[off + k] = (uint32_t)ru;
+      w.gbuf[off + k] = make_float4(nan, nan, nan, __uint_as_float(off + k));
     }
     return;
   }
   uint32_t npad = 2;
   while (npad < n) npad <<= 1;
-  for (uint32_t k = tid; k < npad; k += TB) s_ids[k] = k < n ? w.tmp[off + k] : 0xFFFFFFFFu;
+  for (uint32_t k = tid; k < npad; k += TB) {
+    s_ids[k] = k < n ? __float_as_uint(w.tmp4[off + k].w) : 0xFFFFFFFFu;
+    s_slot[k] = (uint16_t)k;
+  }
   __syncthreads();
   for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
     for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
@@ -257,7 +270,10 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         if (ixj > i) {
           const uint32_t a = s_ids[i], b = s_ids[ixj];
           const bool asc = (i & kk) == 0;
-          if ((a > b) == asc) { s_ids[i] = b; s_ids[ixj] = a; }
+          if ((a > b) == asc) {
+            s_ids[i] = b; s_ids[ixj] = a;
+            const uint16_t t = s_slot[i]; s_slot[i] = s_slot[ixj]; s_slot[ixj] = t;
+          }
         }
       }
       __syncthreads();
@@ -265,10 +281,10 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   }
   float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
   for (uint32_t k = tid; k < n; k += TB) {
-    const int64_t l = (int64_t)s_ids[k] - E.base;
-    const float x = E.x[l], y = E.y[l], z = E.z[l];
+    const float4 v = w.tmp4[off + s_slot[k]];
+    const float x = v.x, y = v.y, z = v.z;
     w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
-    w.cid[off + k] = (uint32_t)l; w.cru[off + k] = (uint32_t)ru;
+    w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
     ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
   }
 #pragma unroll
@@ -389,19 +405,72 @@ __device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float
 }
 
 constexpr uint32_t kSlab = 1024;   // clusters of one row staged in LDS
+constexpr int kCand = 16;          // passing candidates per side kept per lane
+
+// Window scan of one row's box: indices (into D4) of the entries within the
+// windows, at most kCand; returns the count, or kCand + 1 on overflow.
+template <class F4, class U32>
+__device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float yi, float zi, float WY,
+                                       float WZ, uint16_t* out) {
+  const CellBox b = cell_box(G, yi, zi, WY, WZ);
+  int n = 0;
+  for (uint32_t iz = b.iz0; iz <= b.iz1; ++iz) {
+    const uint32_t c0 = iz * G.ny;
+    const uint32_t k1 = Dc[c0 + b.iy1 + 1];
+    for (uint32_t k = Dc[c0 + b.iy0]; k < k1; ++k) {
+      const float4 D = D4[k];
+      if (!(fabsf(D.x - yi) <= WY && fabsf(D.y - zi) <= WZ)) continue;
+      if (n < kCand) out[n] = (uint16_t)k;
+      ++n;
+    }
+  }
+  return n <= kCand ? n : kCand + 1;
+}
+
+// Pairs from the two candidate lists, same arithmetic and tie-break as find_pair.
+template <class F4>
+__device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
+                                          int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
+                                          int32_t& bd) {
+  const float IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z, CUT = w.P.link_cut;
+  bool have = false;
+  float bs = 0.0f;
+  bu = -1; bd = -1;
+  for (int i = 0; i < nd; ++i) {
+    const float4 D = D4[ld[i]];
+    const int32_t pd = (int32_t)__float_as_uint(D.w);
+    for (int j = 0; j < nu; ++j) {
+      const float4 U = U4[lu[j]];
+      const float wgt = (xi - D.z) / (U.z - D.z);
+      const float ey = yi - (D.x + (U.x - D.x) * wgt);
+      const float ez = zi - (D.y + (U.y - D.y) * wgt);
+      const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+      if (!(score <= CUT)) continue;
+      const int32_t pu = (int32_t)__float_as_uint(U.w);
+      const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
+      if (better) { have = true; bs = score; bu = pu; bd = pd; }
+    }
+  }
+}
 
 // One block per row unit: the grids of rows r-1 and r+1 (entries and cell
-// offsets) are staged in LDS when each holds at most kSlab clusters; every
-// window search of the row's clusters then reads LDS only.
+// offsets) are staged in LDS when each holds at most kSlab clusters.  Lanes
+// take the row's clusters in grid (cell) order, so the lanes of a wave are
+// spatial neighbours with similar candidate counts.  A lane first collects
+// the down and up candidates inside the windows (two flat scans), then
+// scores the pairs; nested scanning would make a wave run the product of its
+// lanes' largest candidate counts.  Results do not depend on the order.
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
   __shared__ float4 s_d[kSlab], s_u[kSlab];
   __shared__ uint32_t s_cd[kSlab / 2 + 2], s_cu[kSlab / 2 + 2];
+  __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const int64_t ru = blockIdx.x;
   const int r = (int)(ru % w.R);
   const uint32_t off = w.ru_off[ru];
   const uint32_t n = w.ru_off[ru + 1] - off;
   if (n == 0) return;
-  if (r < 1 || r > w.R - 2) {
+  // edge rows have no links; an over-full row unit (reported as an error) gets none either
+  if (r < 1 || r > w.R - 2 || n > (uint32_t)kMaxRow) {
     for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
     return;
   }
@@ -417,16 +486,26 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     for (uint32_t i = threadIdx.x; i <= ncu; i += TB) s_cu[i] = w.cell_off[Gu.cell_base + i] - offu;
     __syncthreads();
   }
+  uint16_t* ld = s_ld + kCand * threadIdx.x;
+  uint16_t* lu = s_lu + kCand * threadIdx.x;
+  const float WY = w.P.win_y, WZ = w.P.win_z;
   for (uint32_t k = threadIdx.x; k < n; k += TB) {
-    const uint32_t p = off + k;
-    const float xi = w.cx[p], yi = w.cy[p], zi = w.cz[p];
-    int32_t bu, bd;
-    if (lds)
-      find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint32_t*)s_cd, Gu, (const float4*)s_u,
-                (const uint32_t*)s_cu, bu, bd);
-    else
+    const float4 me = w.gbuf[off + k];
+    const uint32_t p = __float_as_uint(me.w);
+    const float xi = me.z, yi = me.x, zi = me.y;
+    int32_t bu = -1, bd = -1;
+    if (lds) {
+      const int cd = collect(Gd, (const float4*)s_d, (const uint32_t*)s_cd, yi, zi, WY, WZ, ld);
+      const int cu = cd > 0 ? collect(Gu, (const float4*)s_u, (const uint32_t*)s_cu, yi, zi, WY, WZ, lu) : 0;
+      if (cd <= kCand && cu <= kCand)
+        best_pair(w, xi, yi, zi, (const float4*)s_d, ld, cd, (const float4*)s_u, lu, cu, bu, bd);
+      else
+        find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint32_t*)s_cd, Gu, (const float4*)s_u,
+                  (const uint32_t*)s_cu, bu, bd);
+    } else {
       find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
                 w.cell_off + Gu.cell_base, bu, bd);
+    }
     w.up[p] = bu;
     w.dn[p] = bd;
   }
@@ -446,6 +525,7 @@ __global__ __launch_bounds__(TB) void k_clean(Ws w) {
     const int32_t cd = (d >= 0 && w.up[d] == (int32_t)p) ? d : -1;
     w.cup[p] = cu;
     w.cdn[p] = cd;
+    w.cpk[p] = make_float4(w.cx[p], w.cy[p], w.cz[p], __int_as_float(cu));
     start = cu >= 0 && cd < 0;
     if (start) {
       int L = 2;
@@ -633,11 +713,13 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
           r0 = (int)(ru0 % (uint32_t)R);
           rubase = ru0 - (uint32_t)r0;
           hits = w.tl_hits + s * R;
-          const int32_t h1 = w.cup[h0];
-          const int32_t h2 = w.cup[h1];
+          const float4 a0 = w.cpk[h0];
+          const int32_t h1 = __float_as_int(a0.w);
+          const int32_t h2 = __float_as_int(w.cpk[h1].w);
+          const float4 a2 = w.cpk[h2];
           float sdir, tdir;
-          const float x0 = w.cx[h0], y0 = w.cy[h0], z0 = w.cz[h0];
-          chord_dir(x0, y0, z0, w.cx[h2], w.cy[h2], w.cz[h2], sdir, tdir);
+          const float x0 = a0.x, y0 = a0.y, z0 = a0.z;
+          chord_dir(x0, y0, z0, a2.x, a2.y, a2.z, sdir, tdir);
           p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
           init_cov(C, w.m.vy, w.m.vz);
           rlo = rhi = rstate = r0;
@@ -656,19 +738,64 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     }
     if (__ballot(phase != ST_IDLE) == 0ull) break;
     if (phase == ST_DONE || phase == ST_IDLE) continue;
-    // one row step
-    if (phase == ST_CHAIN) {
-      const float hx = w.cx[nxt];
-      if (!transport(p, C, xc, hx, w.m)) {
+    // one row step: every active lane transports once (the target plane
+    // depends on the phase), then the phase's own work follows
+    const bool chain = phase == ST_CHAIN;
+    const bool search = phase == ST_UP || phase == ST_DOWN;
+    float X, my = 0.0f, mz = 0.0f;
+    int32_t cnx = -1;
+    GridParams G;
+    if (chain) {
+      const float4 c = w.cpk[nxt];
+      X = c.x; my = c.y; mz = c.z; cnx = __float_as_int(c.w);
+    } else {
+      X = sX[r];
+    }
+    if (search) G = w.grid[rubase + (uint32_t)r];
+    bool go = transport(p, C, xc, X, w.m);
+    bool upd = false, wrote = false;
+    if (chain) {
+      upd = go;
+    } else if (search && go) {
+      xc = X;
+      rstate = r;
+      go = accepted(X, acc, p);
+      if (go) {
+        const Found h = search_row(w, G, p, C);
+        if (h.pos >= 0) {
+          if (h.x != X) {
+            go = transport(p, C, X, h.x, w.m);
+            if (go) xc = h.x;
+          }
+          if (go) {
+            my = h.y; mz = h.z;
+            upd = true;
+            hits[r] = h.pos;
+            ++nhits;
+            gap = 0;
+            wrote = true;
+          }
+        } else {
+          hits[r] = -1;
+          ++gap;
+          wrote = true;
+        }
+        if (wrote) go = gap <= w.P.max_gap;
+      }
+    }
+    if (upd) {
+      float dummy = 0.0f;
+      update(p, C, my, mz, w.m, dummy);
+    }
+    if (chain) {
+      if (!go) {
         nhits = 0; rlo = rhi = r0; phase = ST_DONE;
       } else {
-        float dummy = 0.0f;
-        update(p, C, w.cy[nxt], w.cz[nxt], w.m, dummy);
         ++rstate;
         hits[rstate] = nxt;
         ++nhits;
-        xc = hx;
-        nxt = w.cup[nxt];
+        xc = X;
+        nxt = cnx;
         if (nxt < 0) {
           rhi = rstate;
           gap = 0;
@@ -678,10 +805,10 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
         }
       }
     } else if (phase == ST_BACK) {
-      if (!transport(p, C, xc, sX[r], w.m)) {
+      if (!go) {
         phase = ST_DONE;
       } else {
-        xc = sX[r];
+        xc = X;
         --r;
         if (r < r0) {
           gap = 0;
@@ -689,70 +816,41 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
           phase = r >= 0 ? ST_DOWN : ST_DONE;
         }
       }
-    } else {   // ST_UP or ST_DOWN
-      const float X = sX[r];
-      const GridParams G = w.grid[rubase + (uint32_t)r];   // in flight during the transport
-      bool go = transport(p, C, xc, X, w.m);
-      bool wrote = false;
-      if (go) {
-        xc = X;
-        rstate = r;
-        go = accepted(X, acc, p);
-        if (go) {
-          const Found h = search_row(w, G, p, C);
-          if (h.pos >= 0) {
-            if (h.x != X) {
-              go = transport(p, C, X, h.x, w.m);
-              if (go) xc = h.x;
-            }
-            if (go) {
-              float dummy = 0.0f;
-              update(p, C, h.y, h.z, w.m, dummy);
-              hits[r] = h.pos;
-              ++nhits;
-              gap = 0;
-              wrote = true;
-            }
-          } else {
-            hits[r] = -1;
-            ++gap;
-            wrote = true;
-          }
-          if (wrote) go = gap <= w.P.max_gap;
-        }
-      }
-      if (phase == ST_UP) {
-        if (wrote) rhi = r;
-        if (go && r + 1 < R) {
-          ++r;
-        } else {
-          r = rstate - 1;
-          if (r >= r0) {
-            phase = ST_BACK;
-          } else {
-            gap = 0;
-            r = r0 - 1;
-            phase = r >= 0 ? ST_DOWN : ST_DONE;
-          }
-        }
+    } else if (phase == ST_UP) {
+      if (wrote) rhi = r;
+      if (go && r + 1 < R) {
+        ++r;
       } else {
-        if (wrote) rlo = r;
-        if (go && r - 1 >= 0) --r; else phase = ST_DONE;
+        r = rstate - 1;
+        if (r >= r0) {
+          phase = ST_BACK;
+        } else {
+          gap = 0;
+          r = r0 - 1;
+          phase = r >= 0 ? ST_DOWN : ST_DONE;
+        }
       }
+    } else {
+      if (wrote) rlo = r;
+      if (go && r - 1 >= 0) --r; else phase = ST_DONE;
     }
   }
 }
 
 // ----------------------------------------------------------- a6: selection
+// One wave per tracklet: the lanes cover consecutive rows of its hit list,
+// so the list is read in whole cache lines.
 __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   const uint32_t ns = w.flags[F_NSEEDS];
-  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (TB / 64);
+  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < ns; s += nw) {
     if (w.tl_nhits[s] < w.P.min_hits) continue;
     const uint64_t key = w.tl_key[s];
     const int32_t rg = w.tl_range[s];
     const int rlo = rg & 0xFFFF, rhi = rg >> 16;
     const int32_t* hits = w.tl_hits + s * w.R;
-    for (int r = rlo; r <= rhi; ++r) {
+    for (int r = rlo + lane; r <= rhi; r += 64) {
       const int32_t h = hits[r];
       // owners only grow: a value already >= key (even a stale one) makes the atomic a no-op
       if (h >= 0 && w.owner[h] < key) atomicMax((unsigned long long*)&w.owner[h], (unsigned long long)key);
@@ -763,10 +861,13 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
 // ------------------------------------------------ a6/a7: accept + final fit
 // Acceptance: count the hits a tracklet owns (outermost first), keep them as
 // a compact list tl_own[s][0..cnt) and flag the tracklet if it owns at least
-// min_hits and owned_num/owned_den of its hits.
+// min_hits and owned_num/owned_den of its hits.  One wave per tracklet: 64
+// rows per pass from the outermost down, compacted with a ballot.
 __global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const uint32_t ns = w.flags[F_NSEEDS];
-  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (TB / 64);
+  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < w.seed_cap; s += nw) {
     uint32_t acc = 0, cnt = 0;
     if (s < ns && w.tl_nhits[s] >= w.P.min_hits) {
       const int nh = w.tl_nhits[s];
@@ -775,14 +876,21 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
       const int rlo = rg & 0xFFFF, rhi = rg >> 16;
       const int32_t* hits = w.tl_hits + s * w.R;
       int32_t* own = w.tl_own + s * w.R;
-      for (int r = rhi; r >= rlo; --r) {
-        const int32_t h = hits[r];
-        if (h >= 0 && w.owner[h] == key) own[cnt++] = h;
+      for (int rb = rhi; rb >= rlo; rb -= 64) {
+        const int r = rb - lane;
+        int32_t h = -1;
+        if (r >= rlo) h = hits[r];
+        const bool mine = h >= 0 && w.owner[h] == key;
+        const uint64_t m = __ballot(mine);
+        if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h;
+        cnt += (uint32_t)__popcll(m);
       }
       acc = ((int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
     }
-    w.acc_flag[s] = acc;
-    w.own_cnt[s] = acc ? cnt : 0u;
+    if (lane == 0) {
+      w.acc_flag[s] = acc;
+      w.own_cnt[s] = acc ? cnt : 0u;
+    }
   }
 }
 
@@ -805,8 +913,9 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
     const uint32_t cnt = w.own_cnt[s];
     float p[5], C[15], sdir, tdir;
     const int32_t o0 = own[0], o2 = own[2];
-    const float xo = w.cx[o0], yo = w.cy[o0], zo = w.cz[o0];
-    chord_dir(w.cx[o2], w.cy[o2], w.cz[o2], xo, yo, zo, sdir, tdir);
+    const float4 c0 = w.cpk[o0], c2 = w.cpk[o2];
+    const float xo = c0.x, yo = c0.y, zo = c0.z;
+    chord_dir(c2.x, c2.y, c2.z, xo, yo, zo, sdir, tdir);
     const float kpr = w.tl_state[s * kTl + 4];
     p[0] = yo; p[1] = zo; p[2] = sdir; p[3] = tdir; p[4] = kpr;
     init_cov(C, w.m.vy, w.m.vz);
@@ -814,12 +923,14 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
     bool ok = fabsf(sdir) < w.m.sin_max;
     float xc = xo;
     int32_t hn = own[1];
-    float nx = w.cx[hn], ny = w.cy[hn], nz = w.cz[hn];
+    float4 cn = w.cpk[hn];
+    float nx = cn.x, ny = cn.y, nz = cn.z;
     for (uint32_t k = 1; ok && k < cnt; ++k) {
       const float hx = nx, hy = ny, hz = nz;
       if (k + 1 < cnt) {
         hn = own[k + 1];
-        nx = w.cx[hn]; ny = w.cy[hn]; nz = w.cz[hn];
+        cn = w.cpk[hn];
+        nx = cn.x; ny = cn.y; nz = cn.z;
       }
       if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
       update(p, C, hy, hz, w.m, chi2);
@@ -956,9 +1067,9 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_OWNER);
-  k_owner<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_owner<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
-  k_accept<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_accept<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
   k_acc_list<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);

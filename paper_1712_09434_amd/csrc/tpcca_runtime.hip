@@ -101,12 +101,13 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_ruc = L.take<uint32_t>(RU), o_ruo = L.take<uint32_t>(RU + 1);
   size_t o_cc = L.take<uint32_t>(RU), o_cb = L.take<uint32_t>(RU + 1);
   size_t o_grid = L.take<GridParams>(RU);
-  size_t o_tmp = L.take<uint32_t>(N);
+  size_t o_tmp = L.take<float4>(N);
   size_t o_cx = L.take<float>(N), o_cy = L.take<float>(N), o_cz = L.take<float>(N);
   size_t o_cid = L.take<uint32_t>(N), o_cru = L.take<uint32_t>(N);
   size_t o_gbuf = L.take<float4>(N);
   size_t o_coff = L.take<uint32_t>(N / 2 + 2 * RU + 1);
   size_t o_up = L.take<int32_t>(N), o_dn = L.take<int32_t>(N), o_cup = L.take<int32_t>(N), o_cdn = L.take<int32_t>(N);
+  size_t o_cpk = L.take<float4>(N);
   size_t o_flag = L.take<uint8_t>(N);
   size_t o_bs = L.take<uint32_t>(w.nb + 1), o_bq = L.take<uint32_t>(w.nb + 1);
   size_t o_scan = L.take<uint32_t>(scan_n / 1024 + 4);
@@ -127,12 +128,13 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.ru_count = (uint32_t*)(base + o_ruc); w.ru_off = (uint32_t*)(base + o_ruo);
     w.cell_cap = (uint32_t*)(base + o_cc); w.cell_base = (uint32_t*)(base + o_cb);
     w.grid = (GridParams*)(base + o_grid);
-    w.tmp = (uint32_t*)(base + o_tmp);
+    w.tmp4 = (float4*)(base + o_tmp);
     w.cx = (float*)(base + o_cx); w.cy = (float*)(base + o_cy); w.cz = (float*)(base + o_cz);
     w.cid = (uint32_t*)(base + o_cid); w.cru = (uint32_t*)(base + o_cru);
     w.gbuf = (float4*)(base + o_gbuf); w.cell_off = (uint32_t*)(base + o_coff);
     w.up = (int32_t*)(base + o_up); w.dn = (int32_t*)(base + o_dn);
     w.cup = (int32_t*)(base + o_cup); w.cdn = (int32_t*)(base + o_cdn);
+    w.cpk = (float4*)(base + o_cpk);
     w.flag = (uint8_t*)(base + o_flag);
     w.blk_start = (uint32_t*)(base + o_bs); w.blk_seed = (uint32_t*)(base + o_bq);
     w.scan_tmp = (uint32_t*)(base + o_scan);
