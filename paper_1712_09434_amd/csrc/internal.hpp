@@ -18,8 +18,8 @@ enum : int {
   F_NSEEDS = 1,     // number of seeds
   F_NSTARTS = 2,    // number of start hits
   F_FITS = 3,       // 1 if every event's outputs fit their capacities
-  F_SEEDCTR = 4,    // work counter of the tracklet kernel
-  F_COUNT = 8
+  F_SEEDCTR = 8,    // work counters of the tracklet kernel, one per seed range (8)
+  F_COUNT = 16
 };
 enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u, ERR_STUCK = 4u };
 

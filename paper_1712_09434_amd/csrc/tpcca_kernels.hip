@@ -21,6 +21,7 @@ namespace tpcca {
 namespace {
 
 constexpr int TB = 256;
+constexpr int kXcd = 8;   // accelerator complex dies (each with its own L2) of the chip
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -115,6 +116,13 @@ inline unsigned blocks_for(int64_t n, int64_t cap = 1 << 16) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (unsigned)b;
+}
+
+// A multiple of kXcd workgroups (at most 2^14) for kernels that split their
+// work by XCD.
+inline unsigned xcd_blocks(int64_t n) {
+  const int64_t b = blocks_for(n, 1 << 14);
+  return (unsigned)((b + kXcd - 1) / kXcd * kXcd);
 }
 
 __device__ __forceinline__ int find_event(const Ws& w, int64_t g) {
@@ -659,7 +667,9 @@ __device__ __forceinline__ bool accepted(float X, const Acc& a, const float p[5]
 //   BACK   transport row by row back to the seed's first row, no updates;
 //   DOWN   as UP, downward from the row below the seed.
 // A lane that finishes writes its tracklet and takes the next seed from a
-// device counter (one atomic per wave).
+// device counter (one atomic per wave).  The seed list is split into kXcd
+// contiguous ranges with a counter each; a workgroup starts on the range of
+// its XCD and moves on to the others once that one is used up.
 enum : int { ST_CHAIN = 0, ST_UP = 1, ST_BACK = 2, ST_DOWN = 3, ST_DONE = 4, ST_IDLE = 5 };
 
 __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
@@ -677,6 +687,9 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   uint32_t rubase = 0;
   float p[5], C[15], xc = 0.f;
   uint32_t iters = 0;
+  // seed range of this workgroup's XCD (workgroups are dispatched to the
+  // XCDs round-robin), so that each XCD's L2 holds the grids of its sectors
+  int rx = (int)(blockIdx.x % kXcd), tries = 0;
   while (true) {
     // every lane's steps are bounded (rows only move one way per phase), so
     // this cap is never reached by a correct kernel; it turns a defect into
@@ -695,45 +708,59 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
                     (uint64_t)(0xFFFFFFFFu - w.cid[h0]);
       phase = ST_IDLE;
     }
-    const bool want = phase == ST_IDLE && s != -2;
-    const uint64_t wm = __ballot(want);
-    if (wm) {
-      uint32_t base = 0;
-      const int leader = __ffsll((unsigned long long)wm) - 1;
-      if (lane_id() == leader) base = atomicAdd(&w.flags[F_SEEDCTR], (uint32_t)__popcll(wm));
-      base = __shfl(base, leader, 64);
-      if (want) {
-        const uint32_t mine = base + (uint32_t)__popcll(wm & lanemask_lt());
-        if (mine >= ns) {
-          s = -2;   // no more work for this lane
-        } else {
-          s = mine;
-          h0 = (int32_t)w.seeds[s];
-          const uint32_t ru0 = w.cru[h0];
-          r0 = (int)(ru0 % (uint32_t)R);
-          rubase = ru0 - (uint32_t)r0;
-          hits = w.tl_hits + s * R;
-          const float4 a0 = w.cpk[h0];
-          const int32_t h1 = __float_as_int(a0.w);
-          const int32_t h2 = __float_as_int(w.cpk[h1].w);
-          const float4 a2 = w.cpk[h2];
-          float sdir, tdir;
-          const float x0 = a0.x, y0 = a0.y, z0 = a0.z;
-          chord_dir(x0, y0, z0, a2.x, a2.y, a2.z, sdir, tdir);
-          p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
-          init_cov(C, w.m.vy, w.m.vz);
-          rlo = rhi = rstate = r0;
-          xc = x0;
-          if (fabsf(sdir) < w.m.sin_max) {
-            hits[r0] = h0;
-            nhits = 1;
-            nxt = h1;
-            phase = ST_CHAIN;
-          } else {
-            nhits = 0;
-            phase = ST_DONE;
+    bool want = phase == ST_IDLE && s != -2;
+    uint64_t wm = __ballot(want);
+    while (wm) {
+      const uint32_t lo = (uint32_t)(((uint64_t)ns * (uint32_t)rx) / kXcd);
+      const uint32_t hi = (uint32_t)(((uint64_t)ns * (uint32_t)(rx + 1)) / kXcd);
+      uint32_t* ctr = &w.flags[F_SEEDCTR + rx];
+      // a fresh (L2-bypassing) read first: exhausted ranges cost no atomic
+      uint32_t base = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (base < hi - lo) {
+        const int leader = __ffsll((unsigned long long)wm) - 1;
+        if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(wm));
+        base = __shfl(base, leader, 64);
+        if (want) {
+          const uint64_t mine = (uint64_t)lo + base + (uint32_t)__popcll(wm & lanemask_lt());
+          if (mine < hi) {
+            want = false;
+            s = (int64_t)mine;
+            h0 = (int32_t)w.seeds[s];
+            const uint32_t ru0 = w.cru[h0];
+            r0 = (int)(ru0 % (uint32_t)R);
+            rubase = ru0 - (uint32_t)r0;
+            hits = w.tl_hits + s * R;
+            const float4 a0 = w.cpk[h0];
+            const int32_t h1 = __float_as_int(a0.w);
+            const int32_t h2 = __float_as_int(w.cpk[h1].w);
+            const float4 a2 = w.cpk[h2];
+            float sdir, tdir;
+            const float x0 = a0.x, y0 = a0.y, z0 = a0.z;
+            chord_dir(x0, y0, z0, a2.x, a2.y, a2.z, sdir, tdir);
+            p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
+            init_cov(C, w.m.vy, w.m.vz);
+            rlo = rhi = rstate = r0;
+            xc = x0;
+            if (fabsf(sdir) < w.m.sin_max) {
+              hits[r0] = h0;
+              nhits = 1;
+              nxt = h1;
+              phase = ST_CHAIN;
+            } else {
+              nhits = 0;
+              phase = ST_DONE;
+            }
           }
         }
+      }
+      wm = __ballot(want);
+      if (wm) {
+        // this range is used up: take seeds from the next one
+        if (++tries >= kXcd) {
+          if (want) s = -2;   // every range is used up: no more work for this lane
+          break;
+        }
+        rx = (rx + 1) % kXcd;
       }
     }
     if (__ballot(phase != ST_IDLE) == 0ull) break;
@@ -838,13 +865,26 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
 }
 
 // ----------------------------------------------------------- a6: selection
-// One wave per tracklet: the lanes cover consecutive rows of its hit list,
-// so the list is read in whole cache lines.
+// Tracklets of one XCD's seed range (the ranges of the tracklet kernel) are
+// handled by the workgroups dispatched to that XCD, one wave per tracklet.
+struct XcdWaves { int64_t lo, hi, first, stride; };
+__device__ __forceinline__ XcdWaves xcd_waves(uint32_t ns) {
+  const uint32_t x = blockIdx.x % kXcd;
+  XcdWaves r;
+  r.lo = (int64_t)(((uint64_t)ns * x) / kXcd);
+  r.hi = (int64_t)(((uint64_t)ns * (x + 1)) / kXcd);
+  r.first = r.lo + (int64_t)(blockIdx.x / kXcd) * (TB / 64) + (threadIdx.x >> 6);
+  r.stride = (int64_t)(gridDim.x / kXcd) * (TB / 64);
+  return r;
+}
+
+// Ownership: the lanes of a wave cover consecutive rows of the tracklet's
+// hit list, so the list is read in whole cache lines.
 __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   const uint32_t ns = w.flags[F_NSEEDS];
   const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * (TB / 64);
-  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < ns; s += nw) {
+  const XcdWaves X = xcd_waves(ns);
+  for (int64_t s = X.first; s < X.hi; s += X.stride) {
     if (w.tl_nhits[s] < w.P.min_hits) continue;
     const uint64_t key = w.tl_key[s];
     const int32_t rg = w.tl_range[s];
@@ -866,10 +906,10 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
 __global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const uint32_t ns = w.flags[F_NSEEDS];
   const int lane = lane_id();
-  const int64_t nw = (int64_t)gridDim.x * (TB / 64);
-  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < w.seed_cap; s += nw) {
+  const XcdWaves X = xcd_waves(ns);
+  for (int64_t s = X.first; s < X.hi; s += X.stride) {
     uint32_t acc = 0, cnt = 0;
-    if (s < ns && w.tl_nhits[s] >= w.P.min_hits) {
+    if (w.tl_nhits[s] >= w.P.min_hits) {
       const int nh = w.tl_nhits[s];
       const uint64_t key = w.tl_key[s];
       const int32_t rg = w.tl_range[s];
@@ -891,6 +931,12 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
       w.acc_flag[s] = acc;
       w.own_cnt[s] = acc ? cnt : 0u;
     }
+  }
+  // slots past the seed count (scanned with the others)
+  for (int64_t s = (int64_t)ns + (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap;
+       s += (int64_t)gridDim.x * TB) {
+    w.acc_flag[s] = 0u;
+    w.own_cnt[s] = 0u;
   }
 }
 
@@ -1067,9 +1113,9 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_OWNER);
-  k_owner<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
+  k_owner<<<xcd_blocks(w.seed_cap * 64), TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
-  k_accept<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
+  k_accept<<<xcd_blocks(w.seed_cap * 64), TB, 0, st>>>(w);
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
   k_acc_list<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);
