@@ -615,6 +615,10 @@ struct Found { int32_t pos; float x, y, z; };
 
 // Closest cluster of row unit ru to the predicted (y, z):
 // d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
+// The cell ranges of the box's first two z rows are read together, then
+// their entries in chunks of eight loads issued before any is tested, so a
+// step waits for memory twice rather than once per candidate.  The result
+// does not depend on the order the candidates are visited in.
 __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, const float p[5],
                                             const float C[15]) {
   const float sy2 = C[0] + w.m.vy, sz2 = C[5] + w.m.vz;
@@ -624,29 +628,44 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   const CellBox b = cell_box(G, p[0], p[1], wy, wz);
   Found best{-1, 0.f, 0.f, 0.f};
   float bd = 0.0f;
-  // issue the cell-range loads of the first two z rows of the box together
+  auto consider = [&](const float4& c) {
+    const float dY = c.x - p[0], dZ = c.y - p[1];
+    const float d = (dY * dY) * isy + (dZ * dZ) * isz;
+    if (!(d <= CUT)) return;
+    const int32_t pos = (int32_t)__float_as_uint(c.w);
+    if (best.pos < 0 || d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
+  };
   const uint32_t nzr = b.iz1 - b.iz0 + 1;
   const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
   const uint32_t c0b = c0a + G.ny;
-  uint32_t ka0 = w.cell_off[c0a + b.iy0], ka1 = w.cell_off[c0a + b.iy1 + 1];
+  const uint32_t ka0 = w.cell_off[c0a + b.iy0], ka1 = w.cell_off[c0a + b.iy1 + 1];
   uint32_t kb0 = 0, kb1 = 0;
   if (nzr > 1) { kb0 = w.cell_off[c0b + b.iy0]; kb1 = w.cell_off[c0b + b.iy1 + 1]; }
-  for (uint32_t iz = 0; iz < nzr; ++iz) {
-    uint32_t k0, k1;
-    if (iz == 0) { k0 = ka0; k1 = ka1; }
-    else if (iz == 1) { k0 = kb0; k1 = kb1; }
-    else {
-      const uint32_t c0 = G.cell_base + (b.iz0 + iz) * G.ny;
-      k0 = w.cell_off[c0 + b.iy0];
-      k1 = w.cell_off[c0 + b.iy1 + 1];
+  // entries of the two ranges as one sequence t = 0 .. na + nb - 1
+  const uint32_t na = ka1 - ka0, nt = na + (kb1 - kb0);
+  constexpr uint32_t kChunk = 8;
+  for (uint32_t t0 = 0; t0 < nt; t0 += kChunk) {
+    float4 c[kChunk];
+#pragma unroll
+    for (uint32_t j = 0; j < kChunk; ++j) {
+      const uint32_t t = t0 + j;
+      if (t < nt) c[j] = w.gbuf[t < na ? ka0 + t : kb0 + (t - na)];
     }
-    for (uint32_t k = k0; k < k1; ++k) {
-      const float4 c = w.gbuf[k];
-      const float dY = c.x - p[0], dZ = c.y - p[1];
-      const float d = (dY * dY) * isy + (dZ * dZ) * isz;
-      if (!(d <= CUT)) continue;
-      const int32_t pos = (int32_t)__float_as_uint(c.w);
-      if (best.pos < 0 || d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
+#pragma unroll
+    for (uint32_t j = 0; j < kChunk; ++j)
+      if (t0 + j < nt) consider(c[j]);
+  }
+  for (uint32_t iz = 2; iz < nzr; ++iz) {
+    const uint32_t cz = G.cell_base + (b.iz0 + iz) * G.ny;
+    const uint32_t k0 = w.cell_off[cz + b.iy0], k1 = w.cell_off[cz + b.iy1 + 1];
+    for (uint32_t k = k0; k < k1; k += 4) {
+      float4 c[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if (k + j < k1) c[j] = w.gbuf[k + j];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if (k + j < k1) consider(c[j]);
     }
   }
   return best;
