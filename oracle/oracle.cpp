@@ -23,6 +23,10 @@
 
 namespace {
 
+// Longest transport (in pad rows) on the way back from the last row reached
+// upward to the seed's first row.
+constexpr int kBackRows = 32;
+
 // ---------------------------------------------------------------------------
 // Reverse-mode tape scalar (FP64).  Every operation records its local
 // partial derivatives; backprop() accumulates adjoints in reverse order.
@@ -426,9 +430,12 @@ template <class R> struct Pipeline {
       if (wrote) T.rhi = r;
       if (!go) break;
     }
-    // back to the head row without updates, then downward following
+    // back to the head row without updates, in transports of at most
+    // kBackRows rows (no measurement in between, and without material a
+    // helix step composes exactly), then downward following
     bool ok = true;
-    for (int r = rstate - 1; r >= r0; --r) {
+    for (int r = rstate; r > r0;) {
+      r = std::max(r0, r - kBackRows);
       if (!transport(p, C, xc, X[r], m)) { ok = false; break; }
       xc = X[r];
     }

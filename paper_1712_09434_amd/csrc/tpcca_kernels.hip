@@ -22,6 +22,7 @@ namespace {
 
 constexpr int TB = 256;
 constexpr int kXcd = 8;   // accelerator complex dies (each with its own L2) of the chip
+constexpr int kBackRows = 32;   // longest transport (rows) back to a seed's first row
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -424,12 +425,20 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
   int n = 0;
   for (uint32_t iz = b.iz0; iz <= b.iz1; ++iz) {
     const uint32_t c0 = iz * G.ny;
-    const uint32_t k1 = Dc[c0 + b.iy1 + 1];
-    for (uint32_t k = Dc[c0 + b.iy0]; k < k1; ++k) {
-      const float4 D = D4[k];
-      if (!(fabsf(D.x - yi) <= WY && fabsf(D.y - zi) <= WZ)) continue;
-      if (n < kCand) out[n] = (uint16_t)k;
-      ++n;
+    const uint32_t k0 = Dc[c0 + b.iy0], k1 = Dc[c0 + b.iy1 + 1];
+    // four entries read before any is tested
+    for (uint32_t k = k0; k < k1; k += 4) {
+      float4 D[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j)
+        if (k + j < k1) D[j] = D4[k + j];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; ++j) {
+        if (k + j < k1 && fabsf(D[j].x - yi) <= WY && fabsf(D[j].y - zi) <= WZ) {
+          if (n < kCand) out[n] = (uint16_t)(k + j);
+          ++n;
+        }
+      }
     }
   }
   return n <= kCand ? n : kCand + 1;
@@ -683,7 +692,8 @@ __device__ __forceinline__ bool accepted(float X, const Acc& a, const float p[5]
 // of a wave stay converged on the common transport.  Phases:
 //   CHAIN  fit the next cluster of the seed's chain (no search);
 //   UP     transport to the next row plane, acceptance, search, update;
-//   BACK   transport row by row back to the seed's first row, no updates;
+//   BACK   transport back to the seed's first row, at most kBackRows rows
+//          per step, no updates;
 //   DOWN   as UP, downward from the row below the seed.
 // A lane that finishes writes its tracklet and takes the next seed from a
 // device counter (one atomic per wave).  The seed list is split into kXcd
@@ -847,7 +857,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
           gap = 0;
           r = rstate + 1;
           phase = r < R ? ST_UP : ST_BACK;
-          if (phase == ST_BACK) r = rstate - 1;
+          if (phase == ST_BACK) r = max(r0, rstate - kBackRows);
         }
       }
     } else if (phase == ST_BACK) {
@@ -855,11 +865,12 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
         phase = ST_DONE;
       } else {
         xc = X;
-        --r;
-        if (r < r0) {
+        if (r == r0) {
           gap = 0;
           r = r0 - 1;
           phase = r >= 0 ? ST_DOWN : ST_DONE;
+        } else {
+          r = max(r0, r - kBackRows);
         }
       }
     } else if (phase == ST_UP) {
@@ -867,8 +878,8 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
       if (go && r + 1 < R) {
         ++r;
       } else {
-        r = rstate - 1;
-        if (r >= r0) {
+        if (rstate > r0) {
+          r = max(r0, rstate - kBackRows);
           phase = ST_BACK;
         } else {
           gap = 0;
@@ -987,16 +998,24 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
     float chi2 = 0.0f;
     bool ok = fabsf(sdir) < w.m.sin_max;
     float xc = xo;
-    int32_t hn = own[1];
-    float4 cn = w.cpk[hn];
-    float nx = cn.x, ny = cn.y, nz = cn.z;
+    // hit records are read four steps ahead of their use and hit indices
+    // eight steps ahead (register rings), so loads overlap the filter steps
+    float4 q0, q1, q2, q3;
+    int32_t j0 = -1, j1 = -1, j2 = -1, j3 = -1;
+    q0 = w.cpk[own[1]];
+    if (2 < cnt) q1 = w.cpk[own[2]];
+    if (3 < cnt) q2 = w.cpk[own[3]];
+    if (4 < cnt) q3 = w.cpk[own[4]];
+    if (5 < cnt) j0 = own[5];
+    if (6 < cnt) j1 = own[6];
+    if (7 < cnt) j2 = own[7];
+    if (8 < cnt) j3 = own[8];
     for (uint32_t k = 1; ok && k < cnt; ++k) {
-      const float hx = nx, hy = ny, hz = nz;
-      if (k + 1 < cnt) {
-        hn = own[k + 1];
-        cn = w.cpk[hn];
-        nx = cn.x; ny = cn.y; nz = cn.z;
-      }
+      const float hx = q0.x, hy = q0.y, hz = q0.z;
+      q0 = q1; q1 = q2; q2 = q3;
+      if (k + 4 < cnt) q3 = w.cpk[j0];
+      j0 = j1; j1 = j2; j2 = j3;
+      if (k + 8 < cnt) j3 = own[k + 8];
       if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
       update(p, C, hy, hz, w.m, chi2);
       xc = hx;
@@ -1050,10 +1069,14 @@ __global__ __launch_bounds__(TB) void k_totals(Ws w) {
       w.out[e].hit_off[w.ev_res[e * 4 + 0]] = (int32_t)w.ev_res[e * 4 + 1];
 }
 
+// One wave per track: scalars spread over the lanes, the hit list written
+// in whole cache lines (innermost first).
 __global__ __launch_bounds__(TB) void k_write(Ws w) {
   if (w.flags[F_FITS] == 0u) return;
   const uint32_t ns = w.flags[F_NSEEDS];
-  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < ns; s += (int64_t)gridDim.x * TB) {
+  const int lane = lane_id();
+  const int64_t nw = (int64_t)gridDim.x * (TB / 64);
+  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < ns; s += nw) {
     const uint32_t t0 = w.trk_flag[s];
     if (w.trk_flag[s + 1] == t0) continue;
     const int32_t h0 = (int32_t)w.seeds[s];
@@ -1065,16 +1088,16 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
     const uint32_t o = w.hit_cnt[s] - w.hit_cnt[sb];
     const uint32_t n = w.hit_cnt[s + 1] - w.hit_cnt[s];
     const float* rf = w.rf + s * kRf;
-    O.sector[j] = (uint8_t)(vsec % (uint32_t)w.S);
-    O.x_ref[j] = rf[0];
-    for (int i = 0; i < 5; ++i) O.p[j * 5 + i] = rf[1 + i];
-    for (int i = 0; i < 15; ++i) O.cov[j * 15 + i] = rf[6 + i];
-    O.chi2[j] = rf[21];
-    O.ndf[j] = 2 * (int32_t)n - 5;
-    if (O.k_prior) O.k_prior[j] = rf[22];
-    O.hit_off[j] = (int32_t)o;
+    if (lane < 5) O.p[j * 5 + lane] = rf[1 + lane];
+    else if (lane < 20) O.cov[j * 15 + (lane - 5)] = rf[6 + (lane - 5)];
+    else if (lane == 20) O.x_ref[j] = rf[0];
+    else if (lane == 21) O.chi2[j] = rf[21];
+    else if (lane == 22) { if (O.k_prior) O.k_prior[j] = rf[22]; }
+    else if (lane == 23) O.sector[j] = (uint8_t)(vsec % (uint32_t)w.S);
+    else if (lane == 24) O.ndf[j] = 2 * (int32_t)n - 5;
+    else if (lane == 25) O.hit_off[j] = (int32_t)o;
     const int32_t* own = w.tl_own + s * w.R;
-    for (uint32_t q = 0; q < n; ++q) O.hit_id[o + q] = w.cid[own[n - 1 - q]];
+    for (uint32_t q = lane; q < n; q += 64) O.hit_id[o + q] = w.cid[own[n - 1 - q]];
   }
 }
 
@@ -1143,7 +1166,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(scan_u32(w.trk_flag, w.trk_flag, w.seed_cap, w.scan_tmp, st));
   TPCCA_CHECK(scan_u32(w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
   k_totals<<<1, TB, 0, st>>>(w);
-  k_write<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
+  k_write<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_N);
 #undef TPCCA_MARK
