@@ -110,6 +110,7 @@ struct Ws {
   uint32_t* starts;     // [N / 2 + 1] canonical positions
   uint32_t* seeds;      // [seed_cap]
   uint32_t* seed_ev_off;   // [E + 1]
+  uint32_t* seed_su_off;   // [E * S + 1] seeds per (event, sector)
   uint32_t* start_ev_off;  // [E + 1]
   // tracklets
   int32_t* tl_nhits;    // [seed_cap]

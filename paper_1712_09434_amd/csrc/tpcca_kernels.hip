@@ -444,7 +444,10 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
   return n <= kCand ? n : kCand + 1;
 }
 
-// Pairs from the two candidate lists, same arithmetic and tie-break as find_pair.
+// Pairs from the two candidate lists, same arithmetic and tie-break as
+// find_pair.  The up candidates are read four at a time; the interpolation
+// weight depends only on the two x coordinates, so the quotient of the
+// previous pair is reused when they repeat (clusters on their row planes).
 template <class F4>
 __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
@@ -453,19 +456,32 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
   bool have = false;
   float bs = 0.0f;
   bu = -1; bd = -1;
+  float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
+  bool wk = false;
   for (int i = 0; i < nd; ++i) {
     const float4 D = D4[ld[i]];
     const int32_t pd = (int32_t)__float_as_uint(D.w);
-    for (int j = 0; j < nu; ++j) {
-      const float4 U = U4[lu[j]];
-      const float wgt = (xi - D.z) / (U.z - D.z);
-      const float ey = yi - (D.x + (U.x - D.x) * wgt);
-      const float ez = zi - (D.y + (U.y - D.y) * wgt);
-      const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
-      if (!(score <= CUT)) continue;
-      const int32_t pu = (int32_t)__float_as_uint(U.w);
-      const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
-      if (better) { have = true; bs = score; bu = pu; bd = pd; }
+    for (int j0 = 0; j0 < nu; j0 += 4) {
+      float4 U[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j0 + j < nu) U[j] = U4[lu[j0 + j]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j0 + j >= nu) continue;
+        if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
+          wq = (xi - D.z) / (U[j].z - D.z);
+          wx_d = D.z; wx_u = U[j].z; wk = true;
+        }
+        const float wgt = wq;
+        const float ey = yi - (D.x + (U[j].x - D.x) * wgt);
+        const float ez = zi - (D.y + (U[j].y - D.y) * wgt);
+        const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+        if (!(score <= CUT)) continue;
+        const int32_t pu = (int32_t)__float_as_uint(U[j].w);
+        const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
+        if (better) { have = true; bs = score; bu = pu; bd = pd; }
+      }
     }
   }
 }
@@ -605,6 +621,12 @@ __global__ __launch_bounds__(TB) void k_ev_offsets(Ws w) {
     lo = 0; hi = nst;
     while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.starts[mid]] < key) lo = mid + 1; else hi = mid; }
     w.start_ev_off[e] = lo;
+  }
+  for (int u = threadIdx.x; u <= w.E * w.S; u += TB) {
+    const uint32_t key = (uint32_t)u * (uint32_t)w.R;
+    uint32_t lo = 0, hi = ns;
+    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.seeds[mid]] < key) lo = mid + 1; else hi = mid; }
+    w.seed_su_off[u] = lo;
   }
 }
 
@@ -908,23 +930,44 @@ __device__ __forceinline__ XcdWaves xcd_waves(uint32_t ns) {
   return r;
 }
 
-// Ownership: the lanes of a wave cover consecutive rows of the tracklet's
-// hit list, so the list is read in whole cache lines.
+// Ownership by bands of kBandRows pad rows of one (event, sector): tracklets
+// of different sectors never share a cluster, so the workgroup of a band
+// scans its sector's tracklets (four lanes per tracklet, one per row) and
+// takes the key maximum of each of the band's clusters with LDS atomics,
+// then writes the band's owners out in order.  A band with more than
+// kBandCap clusters uses global atomics on the (zeroed) owner array instead.
+constexpr int kBandRows = 4;
+constexpr int kBandCap = 6144;
+
 __global__ __launch_bounds__(TB) void k_owner(Ws w) {
-  const uint32_t ns = w.flags[F_NSEEDS];
-  const int lane = lane_id();
-  const XcdWaves X = xcd_waves(ns);
-  for (int64_t s = X.first; s < X.hi; s += X.stride) {
-    if (w.tl_nhits[s] < w.P.min_hits) continue;
-    const uint64_t key = w.tl_key[s];
+  __shared__ unsigned long long s_own[kBandCap];
+  const int nband = (w.R + kBandRows - 1) / kBandRows;
+  const int64_t su = blockIdx.x / nband;
+  const int r_lo = (int)(blockIdx.x % nband) * kBandRows;
+  const int r_hi = min(r_lo + kBandRows, w.R) - 1;
+  const uint32_t c0 = w.ru_off[su * w.R + r_lo], c1 = w.ru_off[su * w.R + r_hi + 1];
+  const uint32_t nc = c1 - c0;
+  const bool lds = nc <= (uint32_t)kBandCap;
+  if (lds)
+    for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
+  __syncthreads();
+  const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
+  const int q = threadIdx.x % kBandRows;
+  const int r = r_lo + q;
+  for (uint32_t sb = s0; sb < s1; sb += TB / kBandRows) {
+    const uint32_t s = sb + threadIdx.x / kBandRows;
+    if (s >= s1 || r > r_hi) continue;
     const int32_t rg = w.tl_range[s];
-    const int rlo = rg & 0xFFFF, rhi = rg >> 16;
-    const int32_t* hits = w.tl_hits + s * w.R;
-    for (int r = rlo + lane; r <= rhi; r += 64) {
-      const int32_t h = hits[r];
-      // owners only grow: a value already >= key (even a stale one) makes the atomic a no-op
-      if (h >= 0 && w.owner[h] < key) atomicMax((unsigned long long*)&w.owner[h], (unsigned long long)key);
-    }
+    if (r < (rg & 0xFFFF) || r > (rg >> 16) || w.tl_nhits[s] < w.P.min_hits) continue;
+    const int32_t h = w.tl_hits[(int64_t)s * w.R + r];
+    if (h < 0) continue;
+    const unsigned long long key = w.tl_key[s];
+    if (lds) atomicMax(&s_own[(uint32_t)h - c0], key);
+    else if (w.owner[h] < key) atomicMax((unsigned long long*)&w.owner[h], key);
+  }
+  if (lds) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nc; i += TB) w.owner[c0 + i] = s_own[i];
   }
 }
 
@@ -1155,7 +1198,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_OWNER);
-  k_owner<<<xcd_blocks(w.seed_cap * 64), TB, 0, st>>>(w);
+  k_owner<<<(unsigned)((int64_t)w.E * w.S * ((w.R + kBandRows - 1) / kBandRows)), TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
   k_accept<<<xcd_blocks(w.seed_cap * 64), TB, 0, st>>>(w);
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));

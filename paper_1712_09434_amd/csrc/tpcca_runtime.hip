@@ -113,6 +113,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_scan = L.take<uint32_t>(scan_n / 1024 + 4);
   size_t o_starts = L.take<uint32_t>(N / 2 + 1), o_seeds = L.take<uint32_t>(SC);
   size_t o_seo = L.take<uint32_t>(E + 1), o_steo = L.take<uint32_t>(E + 1);
+  size_t o_ssu = L.take<uint32_t>((int64_t)E * S + 1);
   size_t o_tln = L.take<int32_t>(SC), o_tlr = L.take<int32_t>(SC);
   size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * R);
   size_t o_own = L.take<uint64_t>(N);
@@ -140,6 +141,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.scan_tmp = (uint32_t*)(base + o_scan);
     w.starts = (uint32_t*)(base + o_starts); w.seeds = (uint32_t*)(base + o_seeds);
     w.seed_ev_off = (uint32_t*)(base + o_seo); w.start_ev_off = (uint32_t*)(base + o_steo);
+    w.seed_su_off = (uint32_t*)(base + o_ssu);
     w.tl_nhits = (int32_t*)(base + o_tln); w.tl_range = (int32_t*)(base + o_tlr);
     w.tl_key = (uint64_t*)(base + o_tlk); w.tl_state = (float*)(base + o_tls);
     w.tl_hits = (int32_t*)(base + o_tlh);
