@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per cluster of each phase kernel ("Roofline").
 ALGO_BYTES_PER_CLUSTER = {
-    "rows": 55.0,        # read 15 B input + 4 B bucketed id; write 20 B canonical + 16 B grid entry
+    "rows": 52.0,        # read 16 B bucketed (x, y, z, id); write 20 B canonical + 16 B grid entry
     "links": 44.0,       # read 12 B own coordinates + ~2 x 16 B window candidates; write 8 B links
     "tracklets": 44.0,   # chain coords + links, ~2 window candidates of 16 B, 4 B hit slot
     "refit": 16.0,       # 12 B coordinates + 4 B owner check per fitted hit
@@ -47,9 +47,14 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run device copies of this many MiB (calibrates PMC byte counters)")
+    ap.add_argument("--pmc-summary", default="",
+                    help="only summarise rocprofv3 output under this folder into profiles/")
     args = ap.parse_args()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -96,7 +101,7 @@ def main():
     achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                "traffic": None, "kernel_ms": round(dom_ms, 4),
+                "traffic": measured_traffic(f"k_{dom}"), "kernel_ms": round(dom_ms, 4),
                 "algo_bytes_per_launch": algo_bytes}
 
     cpu = None
@@ -133,6 +138,121 @@ def main():
     }
     trk.close()
     print(json.dumps(line), flush=True)
+
+
+KERNEL_SOURCES = ("paper_1712_09434_amd/csrc/tpcca_kernels.hip", "paper_1712_09434_amd/csrc/kf_device.hpp",
+                  "paper_1712_09434_amd/csrc/internal.hpp")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tracking_c3_traffic.md")
+PMC_BENCH_CMD = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-grad"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = next(json.loads(l[len("record: "):]) for l in f if l.startswith("record: "))
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def pmc_summary(folder: str):
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the benchmark,
+    scaled by what the same counters read for a plain copy of 1 GiB, written
+    to profiles/tracking_c3_traffic.md with the kernel-source hash."""
+    import csv, glob, re
+    from collections import defaultdict
+
+    def load(sub):
+        out = defaultdict(list)
+        for f in glob.glob(os.path.join(folder, sub, "**", "*counter_collection*.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("tpcca::(anonymous namespace)::", ""))
+                out[name].append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = load("pmc_fetch"), load("pmc_write")
+    cf, cw = load("pmc_copy_fetch"), load("pmc_copy_write")
+    big = lambda d: max(max(v) for v in d.values())
+    kib = 1024 * 1024
+    sf, sw = kib / big(cf), kib / big(cw)
+    mean = lambda v: sum(v) / len(v)
+    rows, rec = [], {}
+    for k in sorted(set(fetch) | set(write), key=lambda k: -mean(fetch.get(k, [0]))):
+        if not k.startswith("k_"):
+            continue
+        f, w = mean(fetch.get(k, [0.0])), mean(write.get(k, [0.0]))
+        b = (f * sf + w * sw) * 1024
+        rec[k] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": round(b)}
+        rows.append(f"| {k} | {f:,.0f} | {w:,.0f} | {b / 1e6:,.1f} |")
+    record = {"workload": "C3", "source_sha256": kernel_source_hash(), "fetch_scale": round(sf, 4),
+              "write_scale": round(sw, 4), "kernels": rec}
+    text = f"""# HBM traffic per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
+
+Commands (from the repository root on the GPU box, `TMPDIR=/tmp`):
+
+    rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_fetch -o fetch -- {PMC_BENCH_CMD}
+    rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_write -o write -- {PMC_BENCH_CMD}
+    rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_copy_fetch -o cfetch -- python3 bench.py --copy-probe-mib 1024
+    rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_copy_write -o cwrite -- python3 bench.py --copy-probe-mib 1024
+    python3 bench.py --pmc-summary <out>
+
+Scale: a plain 1 GiB device copy reads as {big(cf):,.0f} KiB of FETCH_SIZE and {big(cw):,.0f} KiB of
+WRITE_SIZE, so fetch counts are multiplied by {sf:.4f} and write counts by {sw:.4f}.  Values are
+means over the profiled dispatches (6 calls).
+
+| Kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled HBM MB/launch |
+|---|---|---|---|
+""" + "\n".join(rows) + f"""
+
+The record below is read by `bench.py` (roofline `traffic`) only while the kernel sources hash to
+`source_sha256`.
+
+record: {json.dumps(record)}
+"""
+    os.makedirs(os.path.dirname(TRAFFIC_RECORD), exist_ok=True)
+    with open(TRAFFIC_RECORD, "w") as f:
+        f.write(text)
+    print(text)
+    stats = glob.glob(os.path.join(folder, "prof_c3", "**", "*kernel_stats.csv"), recursive=True)
+    if stats:
+        lines = []
+        tot = 0.0
+        for r in csv.DictReader(open(stats[0])):
+            name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+            lines.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+            tot += float(r["TotalDurationNs"])
+        body = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in lines[:24])
+        text2 = f"""# Kernel trace, central-Pb-Pb-shaped event (3.81 M clusters, one tpcca_track call per step)
+
+Command (from the repository root on the GPU box, `TMPDIR=/tmp`):
+
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_c3 -o c3 -- {PMC_BENCH_CMD}
+    python3 bench.py --pmc-summary <out>
+
+6 tracking calls (1 warm-up + 5 timed); average duration per dispatch.  Kernel sources
+sha256 `{kernel_source_hash()}`.
+
+| Kernel | Calls | Average µs | % of GPU time |
+|---|---|---|---|
+{body}
+"""
+        with open(os.path.join(ROOT, "profiles", "tracking_c3_kernel_trace.md"), "w") as f:
+            f.write(text2)
+        print(text2)
 
 
 def copy_probe(mib: int, reps: int = 5):

@@ -954,16 +954,30 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
   const int q = threadIdx.x % kBandRows;
   const int r = r_lo + q;
-  for (uint32_t sb = s0; sb < s1; sb += TB / kBandRows) {
-    const uint32_t s = sb + threadIdx.x / kBandRows;
-    if (s >= s1 || r > r_hi) continue;
-    const int32_t rg = w.tl_range[s];
-    if (r < (rg & 0xFFFF) || r > (rg >> 16) || w.tl_nhits[s] < w.P.min_hits) continue;
-    const int32_t h = w.tl_hits[(int64_t)s * w.R + r];
-    if (h < 0) continue;
-    const unsigned long long key = w.tl_key[s];
-    if (lds) atomicMax(&s_own[(uint32_t)h - c0], key);
-    else if (w.owner[h] < key) atomicMax((unsigned long long*)&w.owner[h], key);
+  constexpr uint32_t kPer = TB / kBandRows;   // tracklets per pass
+  constexpr int kUn = 2;                      // passes whose loads are issued together
+  for (uint32_t sb = s0; sb < s1; sb += kPer * kUn) {
+    int32_t rg[kUn], nh[kUn], hh[kUn];
+    unsigned long long key[kUn];
+    bool ok[kUn];
+    // every load of a tracklet depends only on its index: issue them all first
+#pragma unroll
+    for (int u = 0; u < kUn; ++u) {
+      const uint32_t s = sb + u * kPer + threadIdx.x / kBandRows;
+      ok[u] = s < s1 && r <= r_hi;
+      const uint32_t sc = ok[u] ? s : s0;
+      rg[u] = w.tl_range[sc];
+      nh[u] = w.tl_nhits[sc];
+      hh[u] = w.tl_hits[(int64_t)sc * w.R + (r <= r_hi ? r : r_lo)];
+      key[u] = w.tl_key[sc];
+    }
+#pragma unroll
+    for (int u = 0; u < kUn; ++u) {
+      if (!ok[u] || r < (rg[u] & 0xFFFF) || r > (rg[u] >> 16) || nh[u] < w.P.min_hits || hh[u] < 0) continue;
+      const int32_t h = hh[u];
+      if (lds) atomicMax(&s_own[(uint32_t)h - c0], key[u]);
+      else if (w.owner[h] < key[u]) atomicMax((unsigned long long*)&w.owner[h], key[u]);
+    }
   }
   if (lds) {
     __syncthreads();
