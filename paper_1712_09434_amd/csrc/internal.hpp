@@ -10,7 +10,14 @@
 namespace tpcca {
 
 constexpr int kMaxRow = TPCCA_MAX_ROW_CLUSTERS;   // clusters per (sector, row) handled in LDS
-constexpr int kMaxCells = kMaxRow / 2 + 1;        // grid cells per (sector, row)
+constexpr int kMaxCells = kMaxRow / 2 + 1;        // grid cells per (sector, row), at most
+
+// Cells of a row unit's search grid for n clusters: about two per cluster
+// (window searches then scan ~2 candidates), capped at kMaxCells.
+__host__ __device__ inline uint32_t grid_cells(uint32_t n) {
+  const uint32_t c = 2u * n + 1u;
+  return c < (uint32_t)kMaxCells ? c : (uint32_t)kMaxCells;
+}
 
 // Flags / counters in device memory.
 enum : int {
@@ -96,7 +103,7 @@ struct Ws {
   uint32_t* cru;        // row unit
   // grid-ordered copy for window searches: (y, z, x, canonical position)
   float4* gbuf;         // [N]
-  uint32_t* cell_off;   // [N / 2 + 2 RU + 1]
+  uint32_t* cell_off;   // [2 N + 2 RU + 1] (grid_cells + 1 per row unit)
   // links (canonical positions)
   int32_t* up;
   int32_t* dn;

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
 // cells + 1 offsets per row unit
 __global__ void k_cell_caps(Ws w) {
   for (int64_t ru = (int64_t)blockIdx.x * TB + threadIdx.x; ru < w.RU; ru += (int64_t)gridDim.x * TB)
-    w.cell_cap[ru] = (w.ru_count[ru] >> 1) + 2u;
+    w.cell_cap[ru] = grid_cells(w.ru_count[ru]) + 1u;
 }
 
 // ru_count is reused as the global fill cursor (zeroed after the scans).
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
       ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
       zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
     }
-    const uint32_t cap = (n >> 1) + 1u;
+    const uint32_t cap = grid_cells(n);
     uint32_t nz = 1, ny = 1;
     float dz = zmax - zmin, dy = ymax - ymin;
     if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
@@ -413,7 +413,7 @@ __device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float
   }
 }
 
-constexpr uint32_t kSlab = 1024;   // clusters of one row staged in LDS
+constexpr uint32_t kSlab = 896;    // clusters of one row staged in LDS (3 workgroups per CU fit)
 constexpr int kCand = 16;          // passing candidates per side kept per lane
 
 // Window scan of one row's box: indices (into D4) of the entries within the
@@ -495,7 +495,9 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
 // lanes' largest candidate counts.  Results do not depend on the order.
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
   __shared__ float4 s_d[kSlab], s_u[kSlab];
-  __shared__ uint32_t s_cd[kSlab / 2 + 2], s_cu[kSlab / 2 + 2];
+  // cell offsets relative to the slab (< kSlab): 16 bit; a row of <= kSlab
+  // clusters has at most 2 kSlab + 1 cells
+  __shared__ uint16_t s_cd[2 * kSlab + 2], s_cu[2 * kSlab + 2];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const int64_t ru = blockIdx.x;
   const int r = (int)(ru % w.R);
@@ -515,8 +517,8 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
     for (uint32_t i = threadIdx.x; i < nd; i += TB) s_d[i] = w.gbuf[offd + i];
     for (uint32_t i = threadIdx.x; i < nu; i += TB) s_u[i] = w.gbuf[offu + i];
-    for (uint32_t i = threadIdx.x; i <= ncd; i += TB) s_cd[i] = w.cell_off[Gd.cell_base + i] - offd;
-    for (uint32_t i = threadIdx.x; i <= ncu; i += TB) s_cu[i] = w.cell_off[Gu.cell_base + i] - offu;
+    for (uint32_t i = threadIdx.x; i <= ncd; i += TB) s_cd[i] = (uint16_t)(w.cell_off[Gd.cell_base + i] - offd);
+    for (uint32_t i = threadIdx.x; i <= ncu; i += TB) s_cu[i] = (uint16_t)(w.cell_off[Gu.cell_base + i] - offu);
     __syncthreads();
   }
   uint16_t* ld = s_ld + kCand * threadIdx.x;
@@ -528,13 +530,13 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     const float xi = me.z, yi = me.x, zi = me.y;
     int32_t bu = -1, bd = -1;
     if (lds) {
-      const int cd = collect(Gd, (const float4*)s_d, (const uint32_t*)s_cd, yi, zi, WY, WZ, ld);
-      const int cu = cd > 0 ? collect(Gu, (const float4*)s_u, (const uint32_t*)s_cu, yi, zi, WY, WZ, lu) : 0;
+      const int cd = collect(Gd, (const float4*)s_d, (const uint16_t*)s_cd, yi, zi, WY, WZ, ld);
+      const int cu = cd > 0 ? collect(Gu, (const float4*)s_u, (const uint16_t*)s_cu, yi, zi, WY, WZ, lu) : 0;
       if (cd <= kCand && cu <= kCand)
         best_pair(w, xi, yi, zi, (const float4*)s_d, ld, cd, (const float4*)s_u, lu, cu, bu, bd);
       else
-        find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint32_t*)s_cd, Gu, (const float4*)s_u,
-                  (const uint32_t*)s_cu, bu, bd);
+        find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint16_t*)s_cd, Gu, (const float4*)s_u,
+                  (const uint16_t*)s_cu, bu, bd);
     } else {
       find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
                 w.cell_off + Gu.cell_base, bu, bd);
