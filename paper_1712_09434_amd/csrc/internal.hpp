@@ -75,6 +75,7 @@ constexpr int kTl = 20;
 struct Ws {
   // sizes
   int E, S, R;          // events, sectors per event, rows
+  int Rh;               // stride of a tracklet's hit slots: R rounded up to 4 (16-byte groups)
   int64_t N;            // clusters (all events)
   int64_t RU;           // row units = E * S * R
   int64_t seed_cap;     // capacity of seed arrays (>= N / min_seed_hits)

@@ -740,6 +740,29 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   uint32_t rubase = 0;
   float p[5], C[15], xc = 0.f;
   uint32_t iters = 0;
+  // hit slots are written through a four-row buffer (rows are visited in
+  // order within a phase), one 16-byte store per full group of four rows
+  int32_t wb0 = 0, wb1 = 0, wb2 = 0, wb3 = 0;
+  int wbase = -1;
+  uint32_t wmask = 0;
+  auto flush = [&]() {
+    if (wmask == 0xFu) {
+      *(int4*)(hits + wbase) = make_int4(wb0, wb1, wb2, wb3);
+    } else if (wmask) {
+      if (wmask & 1u) hits[wbase] = wb0;
+      if (wmask & 2u) hits[wbase + 1] = wb1;
+      if (wmask & 4u) hits[wbase + 2] = wb2;
+      if (wmask & 8u) hits[wbase + 3] = wb3;
+    }
+    wmask = 0;
+  };
+  auto put = [&](int row, int32_t v) {
+    const int b = row & ~3;
+    if (b != wbase) { flush(); wbase = b; }
+    const int q = row & 3;
+    if (q == 0) wb0 = v; else if (q == 1) wb1 = v; else if (q == 2) wb2 = v; else wb3 = v;
+    wmask |= 1u << q;
+  };
   // seed range of this workgroup's XCD (workgroups are dispatched to the
   // XCDs round-robin), so that each XCD's L2 holds the grids of its sectors
   int rx = (int)(blockIdx.x % kXcd), tries = 0;
@@ -750,6 +773,8 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     if (++iters > (1u << 22)) { atomicOr(&w.flags[F_ERR], ERR_STUCK); break; }
     // finished lanes publish their tracklet and take new seeds
     if (phase == ST_DONE) {
+      flush();
+      wbase = -1;
       float* st = w.tl_state + s * kTl;
 #pragma unroll
       for (int i = 0; i < 5; ++i) st[i] = p[i];
@@ -782,7 +807,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
             const uint32_t ru0 = w.cru[h0];
             r0 = (int)(ru0 % (uint32_t)R);
             rubase = ru0 - (uint32_t)r0;
-            hits = w.tl_hits + s * R;
+            hits = w.tl_hits + s * w.Rh;
             const float4 a0 = w.cpk[h0];
             const int32_t h1 = __float_as_int(a0.w);
             const int32_t h2 = __float_as_int(w.cpk[h1].w);
@@ -795,7 +820,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
             rlo = rhi = rstate = r0;
             xc = x0;
             if (fabsf(sdir) < w.m.sin_max) {
-              hits[r0] = h0;
+              put(r0, h0);
               nhits = 1;
               nxt = h1;
               phase = ST_CHAIN;
@@ -850,13 +875,13 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
           if (go) {
             my = h.y; mz = h.z;
             upd = true;
-            hits[r] = h.pos;
+            put(r, h.pos);
             ++nhits;
             gap = 0;
             wrote = true;
           }
         } else {
-          hits[r] = -1;
+          put(r, -1);
           ++gap;
           wrote = true;
         }
@@ -872,7 +897,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
         nhits = 0; rlo = rhi = r0; phase = ST_DONE;
       } else {
         ++rstate;
-        hits[rstate] = nxt;
+        put(rstate, nxt);
         ++nhits;
         xc = X;
         nxt = cnx;
@@ -970,7 +995,7 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
       const uint32_t sc = ok[u] ? s : s0;
       rg[u] = w.tl_range[sc];
       nh[u] = w.tl_nhits[sc];
-      hh[u] = w.tl_hits[(int64_t)sc * w.R + (r <= r_hi ? r : r_lo)];
+      hh[u] = w.tl_hits[(int64_t)sc * w.Rh + (r <= r_hi ? r : r_lo)];
       key[u] = w.tl_key[sc];
     }
 #pragma unroll
@@ -1003,15 +1028,25 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
       const uint64_t key = w.tl_key[s];
       const int32_t rg = w.tl_range[s];
       const int rlo = rg & 0xFFFF, rhi = rg >> 16;
-      const int32_t* hits = w.tl_hits + s * w.R;
+      const int32_t* hits = w.tl_hits + s * w.Rh;
       int32_t* own = w.tl_own + s * w.R;
-      for (int rb = rhi; rb >= rlo; rb -= 64) {
-        const int r = rb - lane;
-        int32_t h = -1;
-        if (r >= rlo) h = hits[r];
-        const bool mine = h >= 0 && w.owner[h] == key;
+      // a list spans at most four passes of 64 rows (<= 255 rows): read all
+      // hit slots, then all their owners, then compact pass by pass
+      constexpr int kPass = 4;
+      int32_t h[kPass];
+      uint64_t o[kPass];
+#pragma unroll
+      for (int c = 0; c < kPass; ++c) {
+        const int r = rhi - lane - 64 * c;
+        h[c] = r >= rlo ? hits[r] : -1;
+      }
+#pragma unroll
+      for (int c = 0; c < kPass; ++c) o[c] = h[c] >= 0 ? w.owner[h[c]] : 0ull;
+#pragma unroll
+      for (int c = 0; c < kPass; ++c) {
+        const bool mine = h[c] >= 0 && o[c] == key;
         const uint64_t m = __ballot(mine);
-        if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h;
+        if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h[c];
         cnt += (uint32_t)__popcll(m);
       }
       acc = ((int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
