@@ -265,36 +265,104 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
     }
     return;
   }
-  uint32_t npad = 2;
-  while (npad < n) npad <<= 1;
-  for (uint32_t k = tid; k < npad; k += TB) {
-    s_ids[k] = k < n ? __float_as_uint(w.tmp4[off + k].w) : 0xFFFFFFFFu;
-    s_slot[k] = (uint16_t)k;
-  }
-  __syncthreads();
-  for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
-    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tid; i < npad; i += TB) {
-        const uint32_t ixj = i ^ j;
-        if (ixj > i) {
-          const uint32_t a = s_ids[i], b = s_ids[ixj];
-          const bool asc = (i & kk) == 0;
-          if ((a > b) == asc) {
-            s_ids[i] = b; s_ids[ixj] = a;
-            const uint16_t t = s_slot[i]; s_slot[i] = s_slot[ixj]; s_slot[ixj] = t;
+  // Rows of up to 4 TB clusters (all but extreme ones) are sorted in
+  // registers: thread t holds sorted positions 4t .. 4t+3; bitonic stages
+  // whose partner is in the same thread swap registers, partners in the
+  // same wave come by shuffles, and only the stages across waves (partner
+  // distance >= 256) go through LDS.  Their coordinates then stay in
+  // registers for the grid passes.
+  const bool fast = n <= 4u * TB;
+  uint32_t K[4], V[4];
+  float px[4], py[4], pz[4];
+  float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+  if (fast) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * tid + k;
+      K[k] = i < n ? __float_as_uint(w.tmp4[off + i].w) : 0xFFFFFFFFu;
+      V[k] = i;
+    }
+    auto cs = [&](int k0, int k1, uint32_t kk) {   // registers k0 < k1 of this thread
+      const bool asc = ((4u * tid + k0) & kk) == 0;
+      if (asc ? K[k0] > K[k1] : K[k0] < K[k1]) {
+        const uint32_t t = K[k0]; K[k0] = K[k1]; K[k1] = t;
+        const uint32_t u = V[k0]; V[k0] = V[k1]; V[k1] = u;
+      }
+    };
+    for (uint32_t kk = 2; kk <= 4u * TB; kk <<= 1) {
+      for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+        if (j == 1) {
+          cs(0, 1, kk); cs(2, 3, kk);
+        } else if (j == 2) {
+          cs(0, 2, kk); cs(1, 3, kk);
+        } else {
+          uint32_t O[4], OV[4];
+          if (j < 256) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              O[k] = (uint32_t)__shfl_xor((int)K[k], (int)(j >> 2), 64);
+              OV[k] = (uint32_t)__shfl_xor((int)V[k], (int)(j >> 2), 64);
+            }
+          } else {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { s_ids[4u * tid + k] = K[k]; s_slot[4u * tid + k] = (uint16_t)V[k]; }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { O[k] = s_ids[(4u * tid + k) ^ j]; OV[k] = s_slot[(4u * tid + k) ^ j]; }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t i = 4u * tid + k;
+            const bool lower = (i & j) == 0, asc = (i & kk) == 0;
+            const uint32_t lo = lower ? K[k] : O[k], hi = lower ? O[k] : K[k];
+            if (asc ? lo > hi : lo < hi) { K[k] = O[k]; V[k] = OV[k]; }
           }
         }
       }
-      __syncthreads();
     }
-  }
-  float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
-  for (uint32_t k = tid; k < n; k += TB) {
-    const float4 v = w.tmp4[off + s_slot[k]];
-    const float x = v.x, y = v.y, z = v.z;
-    w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
-    w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
-    ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * tid + k;
+      if (i < n) {
+        const float4 v = w.tmp4[off + V[k]];
+        px[k] = v.x; py[k] = v.y; pz[k] = v.z;
+        w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
+        w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
+        ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+      }
+    }
+  } else {
+    uint32_t npad = 2;
+    while (npad < n) npad <<= 1;
+    for (uint32_t k = tid; k < npad; k += TB) {
+      s_ids[k] = k < n ? __float_as_uint(w.tmp4[off + k].w) : 0xFFFFFFFFu;
+      s_slot[k] = (uint16_t)k;
+    }
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+      for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+        for (uint32_t i = tid; i < npad; i += TB) {
+          const uint32_t ixj = i ^ j;
+          if (ixj > i) {
+            const uint32_t a = s_ids[i], b = s_ids[ixj];
+            const bool asc = (i & kk) == 0;
+            if ((a > b) == asc) {
+              s_ids[i] = b; s_ids[ixj] = a;
+              const uint16_t t = s_slot[i]; s_slot[i] = s_slot[ixj]; s_slot[ixj] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (uint32_t k = tid; k < n; k += TB) {
+      const float4 v = w.tmp4[off + s_slot[k]];
+      const float x = v.x, y = v.y, z = v.z;
+      w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
+      w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
+      ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
+    }
   }
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
@@ -332,9 +400,15 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   const uint32_t nc = G.nz * G.ny;
   for (uint32_t c = tid; c <= nc; c += TB) s_hist[c] = 0u;
   __syncthreads();
-  // the canonical entries were written by this same thread (same k stride):
-  // re-read them, coalesced, instead of gathering from the input again
-  for (uint32_t k = tid; k < n; k += TB) atomicAdd(&s_hist[cell_of(G, w.cy[off + k], w.cz[off + k])], 1u);
+  if (fast) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4u * tid + k < n) atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
+  } else {
+    // the canonical entries were written by this same thread (same k
+    // stride): re-read them, coalesced
+    for (uint32_t k = tid; k < n; k += TB) atomicAdd(&s_hist[cell_of(G, w.cy[off + k], w.cz[off + k])], 1u);
+  }
   __syncthreads();
   uint32_t carry = 0;
   for (uint32_t c0 = 0; c0 < nc; c0 += TB) {
@@ -347,10 +421,21 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   }
   if (tid == 0) w.cell_off[cbase + nc] = off + n;
   __syncthreads();
-  for (uint32_t k = tid; k < n; k += TB) {
-    const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
-    const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
-    w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
+  if (fast) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * tid + k;
+      if (i < n) {
+        const uint32_t slot = atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
+        w.gbuf[off + slot] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
+      }
+    }
+  } else {
+    for (uint32_t k = tid; k < n; k += TB) {
+      const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
+      const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
+      w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
+    }
   }
 }
 
