@@ -18,7 +18,7 @@ import torch
 from .tracker import Tracker
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
-GRIDS = (0, 256, 512, 1024, 2048)
+GRIDS = (0, 512, 768, 1024, 2048)
 
 
 def _key(n_clusters: int, n_events: int) -> str:

@@ -23,6 +23,7 @@ namespace {
 constexpr int TB = 256;
 constexpr int kXcd = 8;   // accelerator complex dies (each with its own L2) of the chip
 constexpr int kBackRows = 32;   // longest transport (rows) back to a seed's first row
+constexpr int kRefillMin = 16;  // waiting lanes that make a wave take new seeds
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -233,10 +234,16 @@ __device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float 
 // in LDS (bitonic on the ids, carrying the entry's slot), canonical SoA
 // written in that order, then a uniform 2-D grid over the row's bounding box
 // with about two clusters per cell, filled by an LDS counting sort.
+// Two instantiations: row units of up to 4 TB clusters (small LDS, so many
+// workgroups share a CU) and larger ones (LDS for kMaxRow ids); each launch
+// covers every row unit and skips those of the other size.
+template <bool kLarge>
 __global__ __launch_bounds__(TB) void k_rows(Ws w) {
-  __shared__ uint32_t s_ids[kMaxRow];
+  constexpr uint32_t kIds = kLarge ? (uint32_t)kMaxRow : 4u * TB;
+  constexpr uint32_t kCells = kLarge ? (uint32_t)kMaxCells : 2u * 4u * TB + 1u;   // grid_cells(n) bound
+  __shared__ uint32_t s_ids[kIds];
   // slots (16 bit) during the sort, then the cell histogram
-  __shared__ uint32_t s_aux[(kMaxCells + 1) > kMaxRow / 2 ? (kMaxCells + 1) : kMaxRow / 2];
+  __shared__ uint32_t s_aux[(kCells + 1) > kIds / 2 ? (kCells + 1) : kIds / 2];
   __shared__ float s_red[4][TB / 64];
   __shared__ GridParams s_gp;
   uint16_t* s_slot = (uint16_t*)s_aux;
@@ -246,6 +253,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   const uint32_t n = w.ru_off[ru + 1] - off;
   const uint32_t cbase = w.cell_base[ru];
   const int tid = threadIdx.x;
+  if (kLarge != (n > 4u * TB)) return;
   if (n > (uint32_t)kMaxRow) {
     if (tid == 0) {
       atomicOr(&w.flags[F_ERR], ERR_LIMIT);
@@ -271,7 +279,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   // same wave come by shuffles, and only the stages across waves (partner
   // distance >= 256) go through LDS.  Their coordinates then stay in
   // registers for the grid passes.
-  const bool fast = n <= 4u * TB;
+  const bool fast = !kLarge;
   uint32_t K[4], V[4];
   float px[4], py[4], pz[4];
   float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
@@ -289,7 +297,11 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         const uint32_t u = V[k0]; V[k0] = V[k1]; V[k1] = u;
       }
     };
-    for (uint32_t kk = 2; kk <= 4u * TB; kk <<= 1) {
+    // stages up to the row's power-of-two size only: the entries past it are
+    // all padding (equal maxima), already in order
+    uint32_t npad = 2;
+    while (npad < n) npad <<= 1;
+    for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
       for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
         if (j == 1) {
           cs(0, 1, kk); cs(2, 3, kk);
@@ -578,11 +590,18 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
 // the down and up candidates inside the windows (two flat scans), then
 // scores the pairs; nested scanning would make a wave run the product of its
 // lanes' largest candidate counts.  Results do not depend on the order.
+//
+// Two instantiations: neighbour rows of up to kSmallSlab clusters (small LDS,
+// twice the workgroups per CU) and the rest; each launch covers every row
+// unit and skips those of the other kind.
+constexpr uint32_t kSmallSlab = 256;
+
+template <uint32_t kS>
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
-  __shared__ float4 s_d[kSlab], s_u[kSlab];
-  // cell offsets relative to the slab (< kSlab): 16 bit; a row of <= kSlab
-  // clusters has at most 2 kSlab + 1 cells
-  __shared__ uint16_t s_cd[2 * kSlab + 2], s_cu[2 * kSlab + 2];
+  __shared__ float4 s_d[kS], s_u[kS];
+  // cell offsets relative to the slab (< kS): 16 bit; a row of <= kS
+  // clusters has at most 2 kS + 1 cells
+  __shared__ uint16_t s_cd[2 * kS + 2], s_cu[2 * kS + 2];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const int64_t ru = blockIdx.x;
   const int r = (int)(ru % w.R);
@@ -591,13 +610,16 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   if (n == 0) return;
   // edge rows have no links; an over-full row unit (reported as an error) gets none either
   if (r < 1 || r > w.R - 2 || n > (uint32_t)kMaxRow) {
-    for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
+    if (kS == kSlab)   // (written by one of the two instantiations)
+      for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
     return;
   }
   const uint32_t offd = w.ru_off[ru - 1], nd = off - offd;
   const uint32_t offu = w.ru_off[ru + 1], nu = w.ru_off[ru + 2] - offu;
+  const bool small = nd <= kSmallSlab && nu <= kSmallSlab;
+  if (small != (kS == kSmallSlab)) return;
   const GridParams Gd = w.grid[ru - 1], Gu = w.grid[ru + 1];
-  const bool lds = nd <= kSlab && nu <= kSlab;
+  const bool lds = nd <= kS && nu <= kS;
   if (lds) {
     const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
     for (uint32_t i = threadIdx.x; i < nd; i += TB) s_d[i] = w.gbuf[offd + i];
@@ -695,25 +717,26 @@ __global__ __launch_bounds__(TB) void k_compact(Ws w) {
   if (seed) w.seeds[oq + (uint32_t)__popcll(bq & lt)] = (uint32_t)p;
 }
 
-// Counts and per-event ranges of the start and seed lists.
+// Counts and per-event (and, for seeds, per-sector) ranges of the start and
+// seed lists: entry i of a list writes the boundaries between its
+// predecessor's unit and its own (all entries in parallel).
 __global__ __launch_bounds__(TB) void k_ev_offsets(Ws w) {
   const uint32_t ns = w.blk_seed[w.nb], nst = w.blk_start[w.nb];
-  if (threadIdx.x == 0) { w.flags[F_NSEEDS] = ns; w.flags[F_NSTARTS] = nst; }
-  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
-  for (int e = threadIdx.x; e <= w.E; e += TB) {
-    const uint32_t key = (uint32_t)e * per;
-    uint32_t lo = 0, hi = ns;
-    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.seeds[mid]] < key) lo = mid + 1; else hi = mid; }
-    w.seed_ev_off[e] = lo;
-    lo = 0; hi = nst;
-    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.starts[mid]] < key) lo = mid + 1; else hi = mid; }
-    w.start_ev_off[e] = lo;
+  const int64_t g0 = (int64_t)blockIdx.x * TB + threadIdx.x, gs = (int64_t)gridDim.x * TB;
+  if (g0 == 0) { w.flags[F_NSEEDS] = ns; w.flags[F_NSTARTS] = nst; }
+  const int64_t nsu = (int64_t)w.E * w.S;
+  for (int64_t i = g0; i <= ns; i += gs) {
+    const int64_t cur = i < ns ? (int64_t)(w.cru[w.seeds[i]] / (uint32_t)w.R) : nsu;
+    const int64_t prev = i > 0 ? (int64_t)(w.cru[w.seeds[i - 1]] / (uint32_t)w.R) : -1;
+    for (int64_t u = prev + 1; u <= cur; ++u) w.seed_su_off[u] = (uint32_t)i;
+    const int64_t ce = i < ns ? cur / w.S : w.E, pe = i > 0 ? prev / w.S : -1;
+    for (int64_t e = pe + 1; e <= ce; ++e) w.seed_ev_off[e] = (uint32_t)i;
   }
-  for (int u = threadIdx.x; u <= w.E * w.S; u += TB) {
-    const uint32_t key = (uint32_t)u * (uint32_t)w.R;
-    uint32_t lo = 0, hi = ns;
-    while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (w.cru[w.seeds[mid]] < key) lo = mid + 1; else hi = mid; }
-    w.seed_su_off[u] = lo;
+  const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
+  for (int64_t i = g0; i <= nst; i += gs) {
+    const int64_t ce = i < nst ? (int64_t)(w.cru[w.starts[i]] / per) : w.E;
+    const int64_t pe = i > 0 ? (int64_t)(w.cru[w.starts[i - 1]] / per) : -1;
+    for (int64_t e = pe + 1; e <= ce; ++e) w.start_ev_off[e] = (uint32_t)i;
   }
 }
 
@@ -816,6 +839,9 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   __syncthreads();
   const Acc acc{w.tan_a, w.z_max};
   const uint32_t ns = w.flags[F_NSEEDS];
+  // when the lanes of the lower workgroups already outnumber the seeds they
+  // take (and, by refills, finish) them all: this one has nothing to do
+  if ((int64_t)blockIdx.x * TB >= (int64_t)ns) return;
   const int R = w.R;
   int phase = ST_IDLE;
   int64_t s = -1;
@@ -873,6 +899,9 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     }
     bool want = phase == ST_IDLE && s != -2;
     uint64_t wm = __ballot(want);
+    // refills stall the whole wave (counter, atomic, seed set-up): take new
+    // seeds only once a quarter of the lanes wait, or no lane is working
+    if (__popcll(wm) < kRefillMin && __ballot(phase != ST_IDLE) != 0ull) wm = 0ull;
     while (wm) {
       const uint32_t lo = (uint32_t)(((uint64_t)ns * (uint32_t)rx) / kXcd);
       const uint32_t hi = (uint32_t)(((uint64_t)ns * (uint32_t)(rx + 1)) / kXcd);
@@ -1282,9 +1311,8 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
 
 }  // namespace
 
-// Persistent grid of the tracklet kernel: by default one lane per possible
-// seed (lanes that find the counter exhausted leave at once), so no seed
-// waits for another; or the tuned value.
+// Persistent grid of the tracklet kernel: one lane per possible seed (the
+// workgroups past the actual seed count leave at once), or the tuned value.
 unsigned tracklet_grid(const Ws& w) {
   if (w.tracklet_grid > 0) return (unsigned)w.tracklet_grid;
   return blocks_for(w.seed_cap, 1 << 16);
@@ -1316,18 +1344,20 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_SCATTER);
   k_scatter<<<nchunk, TB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
-  k_rows<<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_rows<false><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_rows<true><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   const unsigned nbN = (unsigned)w.nb;
   TPCCA_MARK(PH_LINKS);
-  k_links<<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_links<kSmallSlab><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_links<kSlab><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_CLEAN);
   k_clean<<<nbN, TB, 0, st>>>(w);
   TPCCA_MARK(PH_COMPACT);
   TPCCA_CHECK(scan_u32(w.blk_start, w.blk_start, w.nb, w.scan_tmp, st));
   TPCCA_CHECK(scan_u32(w.blk_seed, w.blk_seed, w.nb, w.scan_tmp, st));
   k_compact<<<nbN, TB, 0, st>>>(w);
-  k_ev_offsets<<<1, TB, 0, st>>>(w);
+  k_ev_offsets<<<blocks_for(w.N / 2 + 2, 4096), TB, 0, st>>>(w);
   k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_TRACKLETS);

@@ -231,3 +231,40 @@ def test_tracklet_grid_does_not_change_results(tracker):
         for k in ("hit_off", "hit_id", "p"):
             assert torch.equal(getattr(out, k), getattr(ref, k)), (g, k)
     tracker.set_tuning(tracklet_grid=0)
+
+
+def _with_patches(ev, patches, seed):
+    """Copy of `ev` with uniform clusters added in (row, n, y range, z range)
+    patches of sector 0, on the row planes."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    xs, ys, zs, rows = [ev.x], [ev.y], [ev.z], [ev.row]
+    for r, n, (y0, y1), (z0, z1) in patches:
+        xs.append(np.full(n, ev.geom.row_x[r], np.float32))
+        ys.append(rng.uniform(y0, y1, n).astype(np.float32))
+        zs.append(rng.uniform(z0, z1, n).astype(np.float32))
+        rows.append(np.full(n, r, np.int16))
+    extra = sum(p[1] for p in patches)
+    cat = np.concatenate
+    return dataclasses.replace(
+        ev, x=cat(xs), y=cat(ys), z=cat(zs), row=cat(rows), sector=cat([ev.sector, np.zeros(extra, np.uint8)]),
+        x64=cat(xs).astype(np.float64), y64=cat(ys).astype(np.float64), z64=cat(zs).astype(np.float64),
+        truth_track=cat([ev.truth_track, np.full(extra, -1, np.int32)]),
+        truth_double=cat([ev.truth_double, np.zeros(extra, bool)]))
+
+
+def test_dense_rows_take_the_fallback_paths(tracker, orc):
+    """Rows above the register-sort size (1024), above the neighbour slab
+    (896), a 4-row band above the LDS ownership capacity (6144), and windows
+    with more than 16 candidates per side in an LDS-staged row: every
+    fallback path still matches the oracle."""
+    ev = synth.make_event(seed=31, n_primaries=150, noise=0.01, single_sector=True)
+    patches = [(r, 1600, (-10.0, 10.0), (40.0, 120.0)) for r in (40, 41, 42, 43)]
+    patches += [(r, 650, (-6.0, 6.0), (150.0, 180.0)) for r in (80, 81, 82)]
+    ev = _with_patches(ev, patches, seed=32)
+    print(f"[gpu] dense rows n={ev.n}", flush=True)
+    out = tracker.track(*to_dev(ev), taps=True)
+    tl = tracker.debug_tracklets()
+    ref = orc.track(ev, precision=32)
+    compare(ev, out, tl, ref)
+    assert out.n_tracks > 0
