@@ -1058,19 +1058,6 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
 }
 
 // ----------------------------------------------------------- a6: selection
-// Tracklets of one XCD's seed range (the ranges of the tracklet kernel) are
-// handled by the workgroups dispatched to that XCD, one wave per tracklet.
-struct XcdWaves { int64_t lo, hi, first, stride; };
-__device__ __forceinline__ XcdWaves xcd_waves(uint32_t ns) {
-  const uint32_t x = blockIdx.x % kXcd;
-  XcdWaves r;
-  r.lo = (int64_t)(((uint64_t)ns * x) / kXcd);
-  r.hi = (int64_t)(((uint64_t)ns * (x + 1)) / kXcd);
-  r.first = r.lo + (int64_t)(blockIdx.x / kXcd) * (TB / 64) + (threadIdx.x >> 6);
-  r.stride = (int64_t)(gridDim.x / kXcd) * (TB / 64);
-  return r;
-}
-
 // Ownership by bands of kBandRows pad rows of one (event, sector): tracklets
 // of different sectors never share a cluster, so the workgroup of a band
 // scans its sector's tracklets (four lanes per tracklet, one per row) and
@@ -1092,32 +1079,39 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   if (lds)
     for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
   __syncthreads();
+  // one thread per tracklet: the band's four hit slots are one aligned
+  // 16-byte load (the slot stride is a multiple of four rows)
+  static_assert(kBandRows == 4, "one int4 of hit slots per band");
   const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
-  const int q = threadIdx.x % kBandRows;
-  const int r = r_lo + q;
-  constexpr uint32_t kPer = TB / kBandRows;   // tracklets per pass
-  constexpr int kUn = 2;                      // passes whose loads are issued together
-  for (uint32_t sb = s0; sb < s1; sb += kPer * kUn) {
-    int32_t rg[kUn], nh[kUn], hh[kUn];
+  constexpr int kUn = 2;   // passes whose loads are issued together
+  for (uint32_t sb = s0; sb < s1; sb += TB * kUn) {
+    int32_t rg[kUn], nh[kUn];
+    int4 hh[kUn];
     unsigned long long key[kUn];
     bool ok[kUn];
-    // every load of a tracklet depends only on its index: issue them all first
 #pragma unroll
     for (int u = 0; u < kUn; ++u) {
-      const uint32_t s = sb + u * kPer + threadIdx.x / kBandRows;
-      ok[u] = s < s1 && r <= r_hi;
+      const uint32_t s = sb + u * TB + threadIdx.x;
+      ok[u] = s < s1;
       const uint32_t sc = ok[u] ? s : s0;
       rg[u] = w.tl_range[sc];
       nh[u] = w.tl_nhits[sc];
-      hh[u] = w.tl_hits[(int64_t)sc * w.Rh + (r <= r_hi ? r : r_lo)];
+      hh[u] = *(const int4*)(w.tl_hits + (int64_t)sc * w.Rh + r_lo);
       key[u] = w.tl_key[sc];
     }
 #pragma unroll
     for (int u = 0; u < kUn; ++u) {
-      if (!ok[u] || r < (rg[u] & 0xFFFF) || r > (rg[u] >> 16) || nh[u] < w.P.min_hits || hh[u] < 0) continue;
-      const int32_t h = hh[u];
-      if (lds) atomicMax(&s_own[(uint32_t)h - c0], key[u]);
-      else if (w.owner[h] < key[u]) atomicMax((unsigned long long*)&w.owner[h], key[u]);
+      if (!ok[u] || nh[u] < w.P.min_hits) continue;
+      const int rlo = rg[u] & 0xFFFF, rhi = rg[u] >> 16;
+      const int32_t hq[4] = {hh[u].x, hh[u].y, hh[u].z, hh[u].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r_lo + q;
+        const int32_t h = hq[q];
+        if (r > r_hi || r < rlo || r > rhi || h < 0) continue;
+        if (lds) atomicMax(&s_own[(uint32_t)h - c0], key[u]);
+        else if (w.owner[h] < key[u]) atomicMax((unsigned long long*)&w.owner[h], key[u]);
+      }
     }
   }
   if (lds) {
@@ -1132,10 +1126,16 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
 // min_hits and owned_num/owned_den of its hits.  One wave per tracklet: 64
 // rows per pass from the outermost down, compacted with a ballot.
 __global__ __launch_bounds__(TB) void k_accept(Ws w) {
+  // half a wave (32 lanes) per tracklet, two tracklets per wave in flight;
+  // the tracklets of one XCD's seed range go to that XCD's workgroups
   const uint32_t ns = w.flags[F_NSEEDS];
-  const int lane = lane_id();
-  const XcdWaves X = xcd_waves(ns);
-  for (int64_t s = X.first; s < X.hi; s += X.stride) {
+  const int lane = lane_id(), hl = lane & 31;
+  const uint64_t half = (lane < 32) ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull;
+  const uint32_t x = blockIdx.x % kXcd;
+  const int64_t lo = (int64_t)(((uint64_t)ns * x) / kXcd), hi = (int64_t)(((uint64_t)ns * (x + 1)) / kXcd);
+  const int64_t first = lo + (int64_t)(blockIdx.x / kXcd) * (TB / 32) + (threadIdx.x >> 5);
+  const int64_t stride = (int64_t)(gridDim.x / kXcd) * (TB / 32);
+  for (int64_t s = first; s < hi; s += stride) {
     uint32_t acc = 0, cnt = 0;
     if (w.tl_nhits[s] >= w.P.min_hits) {
       const int nh = w.tl_nhits[s];
@@ -1144,14 +1144,14 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
       const int rlo = rg & 0xFFFF, rhi = rg >> 16;
       const int32_t* hits = w.tl_hits + s * w.Rh;
       int32_t* own = w.tl_own + s * w.R;
-      // a list spans at most four passes of 64 rows (<= 255 rows): read all
+      // a list spans at most eight passes of 32 rows (<= 255 rows): read all
       // hit slots, then all their owners, then compact pass by pass
-      constexpr int kPass = 4;
+      constexpr int kPass = 8;
       int32_t h[kPass];
       uint64_t o[kPass];
 #pragma unroll
       for (int c = 0; c < kPass; ++c) {
-        const int r = rhi - lane - 64 * c;
+        const int r = rhi - hl - 32 * c;
         h[c] = r >= rlo ? hits[r] : -1;
       }
 #pragma unroll
@@ -1159,13 +1159,13 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
 #pragma unroll
       for (int c = 0; c < kPass; ++c) {
         const bool mine = h[c] >= 0 && o[c] == key;
-        const uint64_t m = __ballot(mine);
+        const uint64_t m = __ballot(mine) & half;
         if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h[c];
         cnt += (uint32_t)__popcll(m);
       }
       acc = ((int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
     }
-    if (lane == 0) {
+    if (hl == 0) {
       w.acc_flag[s] = acc;
       w.own_cnt[s] = acc ? cnt : 0u;
     }
@@ -1366,7 +1366,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_OWNER);
   k_owner<<<(unsigned)((int64_t)w.E * w.S * ((w.R + kBandRows - 1) / kBandRows)), TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
-  k_accept<<<xcd_blocks(w.seed_cap * 64), TB, 0, st>>>(w);
+  k_accept<<<xcd_blocks(w.seed_cap * 32), TB, 0, st>>>(w);
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
   k_acc_list<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);
