@@ -181,6 +181,7 @@ def pmc_summary(folder: str):
         for f in glob.glob(os.path.join(folder, sub, "**", "*counter_collection*.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
                 name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("tpcca::(anonymous namespace)::", ""))
+                name = re.sub(r"^void ", "", name)
                 out[name].append(float(r["Counter_Value"]))
         return out
 
@@ -233,6 +234,7 @@ record: {json.dumps(record)}
         tot = 0.0
         for r in csv.DictReader(open(stats[0])):
             name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+            name = re.sub(r"^void ", "", name)
             lines.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
             tot += float(r["TotalDurationNs"])
         body = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in lines[:24])
