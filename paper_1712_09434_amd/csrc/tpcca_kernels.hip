@@ -605,21 +605,33 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const int64_t ru = blockIdx.x;
   const int r = (int)(ru % w.R);
-  const uint32_t off = w.ru_off[ru];
-  const uint32_t n = w.ru_off[ru + 1] - off;
+  const bool inner = r >= 1 && r <= w.R - 2;
+  // every row offset and both neighbour grids in one round of loads
+  const int64_t rdn = inner ? ru - 1 : ru, rup = inner ? ru + 1 : ru;
+  const uint32_t offd = w.ru_off[rdn], off = w.ru_off[ru], offu = w.ru_off[ru + 1];
+  const uint32_t endu = w.ru_off[inner ? ru + 2 : ru + 1];
+  const GridParams Gd = w.grid[rdn], Gu = w.grid[rup];
+  const uint32_t n = offu - off;
   if (n == 0) return;
   // edge rows have no links; an over-full row unit (reported as an error) gets none either
-  if (r < 1 || r > w.R - 2 || n > (uint32_t)kMaxRow) {
+  if (!inner || n > (uint32_t)kMaxRow) {
     if (kS == kSlab)   // (written by one of the two instantiations)
       for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
     return;
   }
-  const uint32_t offd = w.ru_off[ru - 1], nd = off - offd;
-  const uint32_t offu = w.ru_off[ru + 1], nu = w.ru_off[ru + 2] - offu;
+  const uint32_t nd = off - offd, nu = endu - offu;
   const bool small = nd <= kSmallSlab && nu <= kSmallSlab;
   if (small != (kS == kSmallSlab)) return;
-  const GridParams Gd = w.grid[ru - 1], Gu = w.grid[ru + 1];
   const bool lds = nd <= kS && nu <= kS;
+  // this thread's own clusters (grid order) for its first rounds, read now
+  // so that they arrive with the staged rows
+  constexpr int kOwn = 4;
+  float4 mine[kOwn];
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i) {
+    const uint32_t k = threadIdx.x + TB * i;
+    if (k < n) mine[i] = w.gbuf[off + k];
+  }
   if (lds) {
     const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
     for (uint32_t i = threadIdx.x; i < nd; i += TB) s_d[i] = w.gbuf[offd + i];
@@ -631,8 +643,7 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   uint16_t* ld = s_ld + kCand * threadIdx.x;
   uint16_t* lu = s_lu + kCand * threadIdx.x;
   const float WY = w.P.win_y, WZ = w.P.win_z;
-  for (uint32_t k = threadIdx.x; k < n; k += TB) {
-    const float4 me = w.gbuf[off + k];
+  auto link = [&](const float4& me) {
     const uint32_t p = __float_as_uint(me.w);
     const float xi = me.z, yi = me.x, zi = me.y;
     int32_t bu = -1, bd = -1;
@@ -650,7 +661,11 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     }
     w.up[p] = bu;
     w.dn[p] = bd;
-  }
+  };
+#pragma unroll
+  for (int i = 0; i < kOwn; ++i)
+    if (threadIdx.x + TB * i < n) link(mine[i]);
+  for (uint32_t k = threadIdx.x + TB * kOwn; k < n; k += TB) link(w.gbuf[off + k]);
 }
 
 // ------------------------------------------------------- a3/a4: clean/start
