@@ -268,3 +268,15 @@ def test_dense_rows_take_the_fallback_paths(tracker, orc):
     ref = orc.track(ev, precision=32)
     compare(ev, out, tl, ref)
     assert out.n_tracks > 0
+
+
+def test_batch_of_uneven_events_matches_oracle(tracker, orc):
+    """Several events of the batching workload (lognormal multiplicity) in one
+    call, each compared with the oracle in full."""
+    evs = [synth.make_config("C4", e) for e in range(6)]
+    evs = sorted(evs, key=lambda e: e.n)[:4]          # the four smallest, for the oracle's sake
+    print("[gpu] batch sizes", [e.n for e in evs], flush=True)
+    batch = tracker.track_batch([to_dev(e) for e in evs], taps=True)
+    for ev, out in zip(evs, batch):
+        ref = orc.track(ev, precision=32)
+        compare(ev, out, None, ref)
