@@ -88,7 +88,6 @@ struct Ws {
   tpcca_params P;
   float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
   int tracklet_grid;    // workgroups of the tracklet kernel (0 = automatic)
-  int n_cu;             // compute units of the device
   uint32_t* flags;      // [F_COUNT]
   // binning
   uint32_t* ru_count;   // [RU]

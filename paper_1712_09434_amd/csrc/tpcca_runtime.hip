@@ -22,7 +22,6 @@ using namespace tpcca;
 
 struct tpcca_ctx {
   int device = 0;
-  int n_cu = 0;       // compute units of the device
   int S = 0, R = 0;
   float tan_a = 0.f, z_max = 0.f, bz = 0.f;
   float* row_x_d = nullptr;
@@ -240,7 +239,6 @@ int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out)
   tpcca_ctx* c = new (std::nothrow) tpcca_ctx();
   if (!c) return TPCCA_E_NOMEM;
   hipError_t e = hipGetDevice(&c->device);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) { (void)hipGetLastError(); delete c; return TPCCA_E_DEVICE; }
   c->S = g->n_sectors; c->R = g->n_rows;
   c->tan_a = g->tan_half_angle; c->z_max = g->z_max; c->bz = f->bz_tesla;
@@ -342,7 +340,6 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   w.tan_a = c->tan_a;
   w.z_max = c->z_max;
   w.tracklet_grid = c->tune.tracklet_grid;
-  w.n_cu = c->n_cu;
 
   // staging: host inputs and host outputs
   std::vector<HostOut> ho(E);
