@@ -1292,14 +1292,16 @@ __global__ __launch_bounds__(TB) void k_totals(Ws w) {
       w.out[e].hit_off[w.ev_res[e * 4 + 0]] = (int32_t)w.ev_res[e * 4 + 1];
 }
 
-// One wave per track: scalars spread over the lanes, the hit list written
-// in whole cache lines (innermost first).
+// One wave per accepted tracklet (the ordered accepted list; those whose
+// fit failed are skipped): scalars spread over the lanes, the hit list
+// written in whole cache lines (innermost first).
 __global__ __launch_bounds__(TB) void k_write(Ws w) {
   if (w.flags[F_FITS] == 0u) return;
-  const uint32_t ns = w.flags[F_NSEEDS];
+  const uint32_t na = w.acc_off[w.seed_cap];
   const int lane = lane_id();
   const int64_t nw = (int64_t)gridDim.x * (TB / 64);
-  for (int64_t s = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); s < ns; s += nw) {
+  for (int64_t i = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); i < na; i += nw) {
+    const int64_t s = w.acc_list[i];
     const uint32_t t0 = w.trk_flag[s];
     if (w.trk_flag[s + 1] == t0) continue;
     const int32_t h0 = (int32_t)w.seeds[s];
@@ -1390,7 +1392,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(scan_u32(w.trk_flag, w.trk_flag, w.seed_cap, w.scan_tmp, st));
   TPCCA_CHECK(scan_u32(w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
   k_totals<<<1, TB, 0, st>>>(w);
-  k_write<<<blocks_for(w.seed_cap * 64, 1 << 14), TB, 0, st>>>(w);
+  k_write<<<blocks_for(w.seed_cap * 16, 1 << 13), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_N);
 #undef TPCCA_MARK
