@@ -542,9 +542,11 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
 }
 
 // Pairs from the two candidate lists, same arithmetic and tie-break as
-// find_pair.  The up candidates are read four at a time; the interpolation
-// weight depends only on the two x coordinates, so the quotient of the
-// previous pair is reused when they repeat (clusters on their row planes).
+// find_pair.  The up candidates are read into registers once (kCand slots,
+// LDS occupancy leaves room for them), so the pair loop touches LDS only for
+// the down candidates; the interpolation weight depends only on the two x
+// coordinates, so the quotient of the previous pair is reused when they
+// repeat (clusters on their row planes).
 template <class F4>
 __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
@@ -555,30 +557,31 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
   bu = -1; bd = -1;
   float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
   bool wk = false;
+  uint32_t ui[kCand];
+#pragma unroll
+  for (int j = 0; j < kCand; ++j) ui[j] = j < nu ? lu[j] : 0u;
+  float4 U[kCand];
+#pragma unroll
+  for (int j = 0; j < kCand; ++j)
+    if (j < nu) U[j] = U4[ui[j]];
   for (int i = 0; i < nd; ++i) {
     const float4 D = D4[ld[i]];
     const int32_t pd = (int32_t)__float_as_uint(D.w);
-    for (int j0 = 0; j0 < nu; j0 += 4) {
-      float4 U[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (j0 + j < nu) U[j] = U4[lu[j0 + j]];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (j0 + j >= nu) continue;
-        if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
-          wq = (xi - D.z) / (U[j].z - D.z);
-          wx_d = D.z; wx_u = U[j].z; wk = true;
-        }
-        const float wgt = wq;
-        const float ey = yi - (D.x + (U[j].x - D.x) * wgt);
-        const float ez = zi - (D.y + (U[j].y - D.y) * wgt);
-        const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
-        if (!(score <= CUT)) continue;
-        const int32_t pu = (int32_t)__float_as_uint(U[j].w);
-        const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
-        if (better) { have = true; bs = score; bu = pu; bd = pd; }
+    for (int j = 0; j < kCand; ++j) {
+      if (j >= nu) continue;
+      if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
+        wq = (xi - D.z) / (U[j].z - D.z);
+        wx_d = D.z; wx_u = U[j].z; wk = true;
       }
+      const float wgt = wq;
+      const float ey = yi - (D.x + (U[j].x - D.x) * wgt);
+      const float ez = zi - (D.y + (U[j].y - D.y) * wgt);
+      const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+      if (!(score <= CUT)) continue;
+      const int32_t pu = (int32_t)__float_as_uint(U[j].w);
+      const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
+      if (better) { have = true; bs = score; bu = pu; bd = pd; }
     }
   }
 }
