@@ -81,6 +81,12 @@ inline Var Sqrt(Var x) { double s = std::sqrt(x.v); return mk(s, x.i, 0.5 / s, -
 inline float Abs(float x) { return std::fabs(x); }
 inline double Abs(double x) { return std::fabs(x); }
 inline Var Abs(Var x) { return x.v < 0 ? -x : x; }
+// Fused multiply-add a*b + c with one rounding (the FP32 parity mode takes it
+// at exactly the places the GPU code does); on the tape an ordinary product
+// and sum.
+inline float Fma(float a, float b, float c) { return std::fma(a, b, c); }
+inline double Fma(double a, double b, double c) { return std::fma(a, b, c); }
+inline Var Fma(Var a, Var b, Var c) { return a * b + c; }
 inline double val(float x) { return x; }
 inline double val(double x) { return x; }
 inline double val(Var x) { return x.v; }
@@ -129,38 +135,38 @@ bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr
   R kap = m.kfac * p[4];
   R s0 = p[2];
   R f = m.kfac * dx;                      // d s1 / d k
-  R s1 = s0 + kap * dx;
+  R s1 = Fma(kap, dx, s0);
   if (!(Abs(s1) < m.sin_max)) return false;
-  R c0 = Sqrt(R(1.0) - s0 * s0);
-  R c1 = Sqrt(R(1.0) - s1 * s1);
+  R c0 = Sqrt(Fma(-s0, s0, R(1.0)));
+  R c1 = Sqrt(Fma(-s1, s1, R(1.0)));
   R ss = s0 + s1;
   R cc = c0 + c1;
   R tn = ss / cc;
   R dy = dx * tn;
-  R d = Sqrt(dx * dx + dy * dy);          // chord length, signed like dx
+  R d = Sqrt(Fma(dx, dx, dy * dy));       // chord length, signed like dx
   if (dx < R(0.0)) d = -d;
   R u = (kap * d) * R(0.5);
   R u2 = u * u;
-  R g = R(1.0) + u2 * (A1 + u2 * (A2 + u2 * (A3 + u2 * A4)));
-  R gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));   // d(asin(u)/u)/du
+  R g = Fma(u2, Fma(u2, Fma(u2, Fma(u2, A4, A3), A2), A1), R(1.0));
+  R gp = u * Fma(u2, Fma(u2, Fma(u2, B4, B3), B2), B1);   // d(asin(u)/u)/du
   R l = d * g;
   R t0 = s0 / c0;
   R t1 = s1 / c1;
-  R dtn_ds = (R(2.0) + tn * (t0 + t1)) / cc;
-  R dtn_dk = (f * (R(1.0) + tn * t1)) / cc;
+  R dtn_ds = Fma(tn, t0 + t1, R(2.0)) / cc;
+  R dtn_dk = (f * Fma(tn, t1, R(1.0))) / cc;
   R a = dx * dtn_ds;                       // d dy / d s0
   R b = dx * dtn_dk;                       // d dy / d k
   R dd_ds = (dy * a) / d;
   R dd_dk = (dy * b) / d;
   R du_ds = (kap * dd_ds) * R(0.5);
-  R du_dk = (m.kfac * d + kap * dd_dk) * R(0.5);
-  R dl_ds = dd_ds * g + (d * gp) * du_ds;
-  R dl_dk = dd_dk * g + (d * gp) * du_dk;
+  R du_dk = Fma(m.kfac, d, kap * dd_dk) * R(0.5);
+  R dl_ds = Fma(dd_ds, g, (d * gp) * du_ds);
+  R dl_dk = Fma(dd_dk, g, (d * gp) * du_dk);
   R t = p[3];
   R c = t * dl_ds;                         // d z1 / d s0
   R e = t * dl_dk;                         // d z1 / d k
   p[0] = p[0] + dy;
-  p[1] = p[1] + t * l;
+  p[1] = Fma(t, l, p[1]);
   p[2] = s1;
   // F = [[1,0,a,0,b],[0,1,c,l,e],[0,0,1,0,f],[0,0,0,1,0],[0,0,0,0,1]]
   R C00 = C[0], C01 = C[1], C02 = C[2], C03 = C[3], C04 = C[4];
@@ -168,29 +174,29 @@ bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr
   R C22 = C[9], C23 = C[10], C24 = C[11];
   R C33 = C[12], C34 = C[13], C44 = C[14];
   // T = F C (rows 0, 1, 2; rows 3 and 4 equal those of C)
-  R T00 = C00 + a * C02 + b * C04;
-  R T01 = C01 + a * C12 + b * C14;
-  R T02 = C02 + a * C22 + b * C24;
-  R T03 = C03 + a * C23 + b * C34;
-  R T04 = C04 + a * C24 + b * C44;
-  R T11 = C11 + c * C12 + l * C13 + e * C14;
-  R T12 = C12 + c * C22 + l * C23 + e * C24;
-  R T13 = C13 + c * C23 + l * C33 + e * C34;
-  R T14 = C14 + c * C24 + l * C34 + e * C44;
-  R T22 = C22 + f * C24;
-  R T23 = C23 + f * C34;
-  R T24 = C24 + f * C44;
+  R T00 = Fma(b, C04, Fma(a, C02, C00));
+  R T01 = Fma(b, C14, Fma(a, C12, C01));
+  R T02 = Fma(b, C24, Fma(a, C22, C02));
+  R T03 = Fma(b, C34, Fma(a, C23, C03));
+  R T04 = Fma(b, C44, Fma(a, C24, C04));
+  R T11 = Fma(e, C14, Fma(l, C13, Fma(c, C12, C11)));
+  R T12 = Fma(e, C24, Fma(l, C23, Fma(c, C22, C12)));
+  R T13 = Fma(e, C34, Fma(l, C33, Fma(c, C23, C13)));
+  R T14 = Fma(e, C44, Fma(l, C34, Fma(c, C24, C14)));
+  R T22 = Fma(f, C24, C22);
+  R T23 = Fma(f, C34, C23);
+  R T24 = Fma(f, C44, C24);
   // C' = T F^T
-  C[0] = T00 + a * T02 + b * T04;
-  C[1] = T01 + c * T02 + l * T03 + e * T04;
-  C[2] = T02 + f * T04;
+  C[0] = Fma(b, T04, Fma(a, T02, T00));
+  C[1] = Fma(e, T04, Fma(l, T03, Fma(c, T02, T01)));
+  C[2] = Fma(f, T04, T02);
   C[3] = T03;
   C[4] = T04;
-  C[5] = T11 + c * T12 + l * T13 + e * T14;
-  C[6] = T12 + f * T14;
+  C[5] = Fma(e, T14, Fma(l, T13, Fma(c, T12, T11)));
+  C[6] = Fma(f, T14, T12);
   C[7] = T13;
   C[8] = T14;
-  C[9] = T22 + f * T24;
+  C[9] = Fma(f, T24, T22);
   C[10] = T23;
   C[11] = T24;
   // C33, C34, C44 unchanged
@@ -210,7 +216,7 @@ void kf_update(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
   R S00 = C[0] + vy;
   R S01 = C[1];
   R S11 = C[5] + vz;
-  R det = S00 * S11 - S01 * S01;
+  R det = Fma(S00, S11, -(S01 * S01));
   R I00 = S11 / det;
   R I01 = (-S01) / det;
   R I11 = S00 / det;
@@ -218,13 +224,13 @@ void kf_update(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
   for (int j = 0; j < 5; ++j) { row0[j] = C[ix(0, j)]; row1[j] = C[ix(1, j)]; }
   R K0[5], K1[5];
   for (int i = 0; i < 5; ++i) {
-    K0[i] = row0[i] * I00 + row1[i] * I01;
-    K1[i] = row0[i] * I01 + row1[i] * I11;
+    K0[i] = Fma(row1[i], I01, row0[i] * I00);
+    K1[i] = Fma(row1[i], I11, row0[i] * I01);
   }
-  for (int i = 0; i < 5; ++i) p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + Fma(K1[i], r1, K0[i] * r0);
   for (int i = 0; i < 5; ++i)
-    for (int j = i; j < 5; ++j) C[ix(i, j)] = C[ix(i, j)] - (K0[i] * row0[j] + K1[i] * row1[j]);
-  chi2 = chi2 + (r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
+    for (int j = i; j < 5; ++j) C[ix(i, j)] = C[ix(i, j)] - Fma(K1[i], row1[j], K0[i] * row0[j]);
+  chi2 = chi2 + Fma(r1, Fma(I11, r1, I01 * r0), r0 * Fma(I01, r1, I00 * r0));
 }
 
 // Kalman update with a scalar measurement of state component q.
@@ -256,7 +262,7 @@ template <class R> void init_cov(R C[15], const orc_params& P) {
 template <class R>
 void chord_dir(R xi, R yi, R zi, R xo, R yo, R zo, R& s, R& t) {
   R dX = xo - xi, dY = yo - yi, dZ = zo - zi;
-  R rho = Sqrt(dX * dX + dY * dY);
+  R rho = Sqrt(Fma(dX, dX, dY * dY));
   s = dY / rho;
   t = dZ / rho;
 }
@@ -319,9 +325,9 @@ template <class R> struct Pipeline {
       for (int64_t u : rows[ru(s, r + 1)]) {
         if (!(Abs(y[u] - y[i]) <= WY && Abs(z[u] - z[i]) <= WZ)) continue;
         R w = (x[i] - x[d]) / (x[u] - x[d]);
-        R ey = y[i] - (y[d] + (y[u] - y[d]) * w);
-        R ez = z[i] - (z[d] + (z[u] - z[d]) * w);
-        R score = (ey * ey) * IWY + (ez * ez) * IWZ;
+        R ey = y[i] - Fma(y[u] - y[d], w, y[d]);
+        R ez = z[i] - Fma(z[u] - z[d], w, z[d]);
+        R score = Fma(ez * ez, IWZ, (ey * ey) * IWY);
         if (!(score <= CUT)) continue;
         bool better = !have || score < bs || (score == bs && (u < bu || (u == bu && d < bd)));
         if (better) { have = true; bs = score; bu = u; bd = d; }
@@ -341,7 +347,7 @@ template <class R> struct Pipeline {
     R bd = R(0.0);
     for (int64_t h : rows[ru(s, r)]) {
       R dY = y[h] - p[0], dZ = z[h] - p[1];
-      R d = (dY * dY) * isy + (dZ * dZ) * isz;
+      R d = Fma(dZ * dZ, isz, (dY * dY) * isy);
       if (!(d <= CUT)) continue;
       if (best < 0 || d < bd || (d == bd && h < best)) { best = h; bd = d; }
     }

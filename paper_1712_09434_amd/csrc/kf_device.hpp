@@ -5,7 +5,8 @@
 // p = (y, z, s = sin phi, t = tan lambda, k = q/pT) on planes x = const of
 // a sector frame, uniform solenoid, no material.  Every expression below is
 // evaluated in exactly this order: the library is built with
-// -ffp-contract=off and correctly rounded FP32 division and square root, so
+// -ffp-contract=off and correctly rounded FP32 division and square root, and
+// fused multiply-adds (one rounding) appear only where fmaf is written, so
 // the integer decisions taken from these values (which cluster, which row,
 // stop or go) are reproducible on any IEEE implementation that evaluates
 // the same expressions.
@@ -42,65 +43,65 @@ __host__ __device__ __forceinline__ bool transport(float p[5], float C[15], floa
   const float kap = m.kfac * p[4];
   const float s0 = p[2];
   const float f = m.kfac * dx;
-  const float s1 = s0 + kap * dx;
+  const float s1 = fmaf(kap, dx, s0);
   if (!(fabsf(s1) < m.sin_max)) return false;
-  const float c0 = sqrtf(1.0f - s0 * s0);
-  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float c0 = sqrtf(fmaf(-s0, s0, 1.0f));
+  const float c1 = sqrtf(fmaf(-s1, s1, 1.0f));
   const float ss = s0 + s1;
   const float cc = c0 + c1;
   const float tn = ss / cc;
   const float dy = dx * tn;
-  float d = sqrtf(dx * dx + dy * dy);
+  float d = sqrtf(fmaf(dx, dx, dy * dy));
   if (dx < 0.0f) d = -d;
   const float u = (kap * d) * 0.5f;
   const float u2 = u * u;
-  const float g = 1.0f + u2 * (A1 + u2 * (A2 + u2 * (A3 + u2 * A4)));
-  const float gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));
+  const float g = fmaf(u2, fmaf(u2, fmaf(u2, fmaf(u2, A4, A3), A2), A1), 1.0f);
+  const float gp = u * fmaf(u2, fmaf(u2, fmaf(u2, B4, B3), B2), B1);
   const float l = d * g;
   const float t0 = s0 / c0;
   const float t1 = s1 / c1;
-  const float dtn_ds = (2.0f + tn * (t0 + t1)) / cc;
-  const float dtn_dk = (f * (1.0f + tn * t1)) / cc;
+  const float dtn_ds = fmaf(tn, t0 + t1, 2.0f) / cc;
+  const float dtn_dk = (f * fmaf(tn, t1, 1.0f)) / cc;
   const float a = dx * dtn_ds;
   const float b = dx * dtn_dk;
   const float dd_ds = (dy * a) / d;
   const float dd_dk = (dy * b) / d;
   const float du_ds = (kap * dd_ds) * 0.5f;
-  const float du_dk = (m.kfac * d + kap * dd_dk) * 0.5f;
-  const float dl_ds = dd_ds * g + (d * gp) * du_ds;
-  const float dl_dk = dd_dk * g + (d * gp) * du_dk;
+  const float du_dk = fmaf(m.kfac, d, kap * dd_dk) * 0.5f;
+  const float dl_ds = fmaf(dd_ds, g, (d * gp) * du_ds);
+  const float dl_dk = fmaf(dd_dk, g, (d * gp) * du_dk);
   const float t = p[3];
   const float c = t * dl_ds;
   const float e = t * dl_dk;
   p[0] = p[0] + dy;
-  p[1] = p[1] + t * l;
+  p[1] = fmaf(t, l, p[1]);
   p[2] = s1;
   const float C00 = C[0], C01 = C[1], C02 = C[2], C03 = C[3], C04 = C[4];
   const float C11 = C[5], C12 = C[6], C13 = C[7], C14 = C[8];
   const float C22 = C[9], C23 = C[10], C24 = C[11];
   const float C33 = C[12], C34 = C[13], C44 = C[14];
-  const float T00 = C00 + a * C02 + b * C04;
-  const float T01 = C01 + a * C12 + b * C14;
-  const float T02 = C02 + a * C22 + b * C24;
-  const float T03 = C03 + a * C23 + b * C34;
-  const float T04 = C04 + a * C24 + b * C44;
-  const float T11 = C11 + c * C12 + l * C13 + e * C14;
-  const float T12 = C12 + c * C22 + l * C23 + e * C24;
-  const float T13 = C13 + c * C23 + l * C33 + e * C34;
-  const float T14 = C14 + c * C24 + l * C34 + e * C44;
-  const float T22 = C22 + f * C24;
-  const float T23 = C23 + f * C34;
-  const float T24 = C24 + f * C44;
-  C[0] = T00 + a * T02 + b * T04;
-  C[1] = T01 + c * T02 + l * T03 + e * T04;
-  C[2] = T02 + f * T04;
+  const float T00 = fmaf(b, C04, fmaf(a, C02, C00));
+  const float T01 = fmaf(b, C14, fmaf(a, C12, C01));
+  const float T02 = fmaf(b, C24, fmaf(a, C22, C02));
+  const float T03 = fmaf(b, C34, fmaf(a, C23, C03));
+  const float T04 = fmaf(b, C44, fmaf(a, C24, C04));
+  const float T11 = fmaf(e, C14, fmaf(l, C13, fmaf(c, C12, C11)));
+  const float T12 = fmaf(e, C24, fmaf(l, C23, fmaf(c, C22, C12)));
+  const float T13 = fmaf(e, C34, fmaf(l, C33, fmaf(c, C23, C13)));
+  const float T14 = fmaf(e, C44, fmaf(l, C34, fmaf(c, C24, C14)));
+  const float T22 = fmaf(f, C24, C22);
+  const float T23 = fmaf(f, C34, C23);
+  const float T24 = fmaf(f, C44, C24);
+  C[0] = fmaf(b, T04, fmaf(a, T02, T00));
+  C[1] = fmaf(e, T04, fmaf(l, T03, fmaf(c, T02, T01)));
+  C[2] = fmaf(f, T04, T02);
   C[3] = T03;
   C[4] = T04;
-  C[5] = T11 + c * T12 + l * T13 + e * T14;
-  C[6] = T12 + f * T14;
+  C[5] = fmaf(e, T14, fmaf(l, T13, fmaf(c, T12, T11)));
+  C[6] = fmaf(f, T14, T12);
   C[7] = T13;
   C[8] = T14;
-  C[9] = T22 + f * T24;
+  C[9] = fmaf(f, T24, T22);
   C[10] = T23;
   C[11] = T24;
   return true;
@@ -116,7 +117,7 @@ __host__ __device__ __forceinline__ void update(float p[5], float C[15], float m
   const float S00 = C[0] + m.vy;
   const float S01 = C[1];
   const float S11 = C[5] + m.vz;
-  const float det = S00 * S11 - S01 * S01;
+  const float det = fmaf(S00, S11, -(S01 * S01));
   const float I00 = S11 / det;
   const float I01 = (-S01) / det;
   const float I11 = S00 / det;
@@ -125,16 +126,16 @@ __host__ __device__ __forceinline__ void update(float p[5], float C[15], float m
   for (int j = 0; j < 5; ++j) { row0[j] = C[sym(0, j)]; row1[j] = C[sym(1, j)]; }
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
-    K0[i] = row0[i] * I00 + row1[i] * I01;
-    K1[i] = row0[i] * I01 + row1[i] * I11;
+    K0[i] = fmaf(row1[i], I01, row0[i] * I00);
+    K1[i] = fmaf(row1[i], I11, row0[i] * I01);
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) p[i] = p[i] + (K0[i] * r0 + K1[i] * r1);
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + fmaf(K1[i], r1, K0[i] * r0);
 #pragma unroll
   for (int i = 0; i < 5; ++i)
 #pragma unroll
-    for (int j = i; j < 5; ++j) C[sym(i, j)] = C[sym(i, j)] - (K0[i] * row0[j] + K1[i] * row1[j]);
-  chi2 = chi2 + (r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1));
+    for (int j = i; j < 5; ++j) C[sym(i, j)] = C[sym(i, j)] - fmaf(K1[i], row1[j], K0[i] * row0[j]);
+  chi2 = chi2 + fmaf(r1, fmaf(I11, r1, I01 * r0), r0 * fmaf(I01, r1, I00 * r0));
 }
 
 __host__ __device__ __forceinline__ void init_cov(float C[15], float vy, float vz) {
@@ -151,7 +152,7 @@ __host__ __device__ __forceinline__ void init_cov(float C[15], float vy, float v
 __host__ __device__ __forceinline__ void chord_dir(float xi, float yi, float zi, float xo, float yo,
                                           float zo, float& s, float& t) {
   const float dX = xo - xi, dY = yo - yi, dZ = zo - zi;
-  const float rho = sqrtf(dX * dX + dY * dY);
+  const float rho = sqrtf(fmaf(dX, dX, dY * dY));
   s = dY / rho;
   t = dZ / rho;
 }

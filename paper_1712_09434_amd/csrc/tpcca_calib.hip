@@ -528,7 +528,7 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     c.gy[j0] += gP[0];
     c.gz[j0] += gP[1];
     const float dX = c.hx[j0] - c.hx[j2], dY = c.hy[j0] - c.hy[j2], dZ = c.hz[j0] - c.hz[j2];
-    const float rho = sqrtf(dX * dX + dY * dY);
+    const float rho = sqrtf(fmaf(dX, dX, dY * dY));   // as the forward chord_dir
     const float r3 = rho * rho * rho;
     const float gs = gP[2], gt = gP[3];
     const float gdX = gs * (-dY * dX / r3) + gt * (-dZ * dX / r3);

@@ -497,9 +497,9 @@ __device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float
           const float4 U = U4[ku];
           if (!(fabsf(U.x - yi) <= WY && fabsf(U.y - zi) <= WZ)) continue;
           const float wgt = (xi - D.z) / (U.z - D.z);
-          const float ey = yi - (D.x + (U.x - D.x) * wgt);
-          const float ez = zi - (D.y + (U.y - D.y) * wgt);
-          const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+          const float ey = yi - fmaf(U.x - D.x, wgt, D.x);
+          const float ez = zi - fmaf(U.y - D.y, wgt, D.y);
+          const float score = fmaf(ez * ez, IWZ, (ey * ey) * IWY);
           if (!(score <= CUT)) continue;
           const int32_t pu = (int32_t)__float_as_uint(U.w);
           const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
@@ -575,9 +575,9 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
         wx_d = D.z; wx_u = U[j].z; wk = true;
       }
       const float wgt = wq;
-      const float ey = yi - (D.x + (U[j].x - D.x) * wgt);
-      const float ez = zi - (D.y + (U[j].y - D.y) * wgt);
-      const float score = (ey * ey) * IWY + (ez * ez) * IWZ;
+      const float ey = yi - fmaf(U[j].x - D.x, wgt, D.x);
+      const float ez = zi - fmaf(U[j].y - D.y, wgt, D.y);
+      const float score = fmaf(ez * ez, IWZ, (ey * ey) * IWY);
       if (!(score <= CUT)) continue;
       const int32_t pu = (int32_t)__float_as_uint(U[j].w);
       const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
@@ -789,7 +789,7 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   float bd = 0.0f;
   auto consider = [&](const float4& c) {
     const float dY = c.x - p[0], dZ = c.y - p[1];
-    const float d = (dY * dY) * isy + (dZ * dZ) * isz;
+    const float d = fmaf(dZ * dZ, isz, (dY * dY) * isy);
     if (!(d <= CUT)) return;
     const int32_t pos = (int32_t)__float_as_uint(c.w);
     if (best.pos < 0 || d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
