@@ -234,6 +234,100 @@ __device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float 
 // in LDS (bitonic on the ids, carrying the entry's slot), canonical SoA
 // written in that order, then a uniform 2-D grid over the row's bounding box
 // with about two clusters per cell, filled by an LDS counting sort.
+// Ordering of LDS accesses between the lanes of one wave (the wave's LDS
+// operations complete in order; this waits for them and keeps the compiler
+// from moving accesses across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row units of at most 64 clusters (most units of small events): one wave
+// each, four per workgroup, no workgroup barrier.  Lane k holds the k-th
+// entry: the ids are sorted by a bitonic network over lane shuffles, the
+// coordinates follow by a gather from the lane that held them; the grid is
+// built as in k_rows with a per-wave LDS histogram.  Same results as k_rows.
+constexpr uint32_t kTiny = 64;
+
+__global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
+  __shared__ uint32_t s_h[TB / 64][2 * kTiny + 2];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int64_t ru = (int64_t)blockIdx.x * (TB / 64) + wv;
+  if (ru >= w.RU) return;
+  const uint32_t off = w.ru_off[ru];
+  const uint32_t n = w.ru_off[ru + 1] - off;
+  if (n > kTiny) return;
+  const uint32_t cbase = w.cell_base[ru];
+  uint32_t* hist = s_h[wv];
+  float x0 = 0.f, y0 = 0.f, z0 = 0.f;
+  uint32_t key = 0xFFFFFFFFu, slot = (uint32_t)lane;
+  if ((uint32_t)lane < n) {
+    const float4 v = w.tmp4[off + lane];
+    x0 = v.x; y0 = v.y; z0 = v.z; key = __float_as_uint(v.w);
+  }
+  uint32_t npad = 2;
+  while (npad < n) npad <<= 1;
+  for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)key, (int)j, 64);
+      const uint32_t os = (uint32_t)__shfl_xor((int)slot, (int)j, 64);
+      const bool lower = ((uint32_t)lane & j) == 0, asc = ((uint32_t)lane & kk) == 0;
+      const uint32_t lo = lower ? key : o, hi = lower ? o : key;
+      if (asc ? lo > hi : lo < hi) { key = o; slot = os; }
+    }
+  }
+  const float x = __shfl(x0, (int)slot, 64), y = __shfl(y0, (int)slot, 64), z = __shfl(z0, (int)slot, 64);
+  const bool mine = (uint32_t)lane < n;
+  if (mine) {
+    w.cx[off + lane] = x; w.cy[off + lane] = y; w.cz[off + lane] = z;
+    w.cid[off + lane] = key; w.cru[off + lane] = (uint32_t)ru;
+  }
+  float ymin = mine ? y : INFINITY, ymax = mine ? y : -INFINITY;
+  float zmin = mine ? z : INFINITY, zmax = mine ? z : -INFINITY;
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
+    zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
+  }
+  // grid parameters: every lane computes the same values, lane 0 stores them
+  const uint32_t cap = grid_cells(n);
+  uint32_t nz = 1, ny = 1;
+  float dz = zmax - zmin, dy = ymax - ymin;
+  if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
+  if (n >= 4 && dz > 0.0f && dy > 0.0f) {
+    const float a = sqrtf((dz * dy) / (float)cap);
+    nz = (uint32_t)fminf(fmaxf(dz / a, 1.0f), (float)cap);
+    ny = (uint32_t)fminf(fmaxf(dy / a, 1.0f), (float)(cap / nz));
+  }
+  GridParams G;
+  G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
+  G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
+  G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
+  G.pad = 0u;
+  if (lane == 0) w.grid[ru] = G;
+  const uint32_t nc = nz * ny;
+  for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
+  wave_sync();
+  const uint32_t cell = mine ? cell_of(G, y, z) : 0u;
+  if (mine) atomicAdd(&hist[cell], 1u);
+  wave_sync();
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nc; c0 += 64) {
+    const uint32_t c = c0 + lane;
+    const uint32_t v = c < nc ? hist[c] : 0u;
+    const uint32_t inc = wave_incl_scan(v);
+    if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = off + carry + inc - v; }
+    carry += (uint32_t)__shfl((int)inc, 63, 64);
+  }
+  if (lane == 0) w.cell_off[cbase + nc] = off + n;
+  wave_sync();
+  if (mine) {
+    const uint32_t pos = atomicAdd(&hist[cell], 1u);
+    w.gbuf[off + pos] = make_float4(y, z, x, __uint_as_float(off + lane));
+  }
+}
+
 // Two instantiations: row units of up to 4 TB clusters (small LDS, so many
 // workgroups share a CU) and larger ones (LDS for kMaxRow ids); each launch
 // covers every row unit and skips those of the other size.
@@ -253,7 +347,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   const uint32_t n = w.ru_off[ru + 1] - off;
   const uint32_t cbase = w.cell_base[ru];
   const int tid = threadIdx.x;
-  if (kLarge != (n > 4u * TB)) return;
+  if (kLarge != (n > 4u * TB) || n <= kTiny) return;   // (k_rows_tiny takes units of <= kTiny)
   if (n > (uint32_t)kMaxRow) {
     if (tid == 0) {
       atomicOr(&w.flags[F_ERR], ERR_LIMIT);
@@ -594,19 +688,25 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
 // scores the pairs; nested scanning would make a wave run the product of its
 // lanes' largest candidate counts.  Results do not depend on the order.
 //
-// Two instantiations: neighbour rows of up to kSmallSlab clusters (small LDS,
-// twice the workgroups per CU) and the rest; each launch covers every row
-// unit and skips those of the other kind.
+// Three instantiations by the size of the neighbour rows: up to kTiny
+// clusters (one wave per row unit, four per workgroup, wave-level ordering),
+// up to kSmallSlab (workgroup per row unit, half the LDS) and the rest
+// (896-cluster slab); each launch covers every row unit and skips those of
+// the other kinds.
 constexpr uint32_t kSmallSlab = 256;
 
-template <uint32_t kS>
+template <uint32_t kS, uint32_t kG>
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
-  __shared__ float4 s_d[kS], s_u[kS];
+  constexpr uint32_t kNG = TB / kG;   // row units per workgroup
+  constexpr int kClass = kS == kTiny ? 0 : kS == kSmallSlab ? 1 : 2;
+  __shared__ float4 s_d[kNG][kS], s_u[kNG][kS];
   // cell offsets relative to the slab (< kS): 16 bit; a row of <= kS
   // clusters has at most 2 kS + 1 cells
-  __shared__ uint16_t s_cd[2 * kS + 2], s_cu[2 * kS + 2];
+  __shared__ uint16_t s_cd[kNG][2 * kS + 2], s_cu[kNG][2 * kS + 2];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
-  const int64_t ru = blockIdx.x;
+  const uint32_t g = threadIdx.x / kG, gt = threadIdx.x % kG;
+  const int64_t ru = (int64_t)blockIdx.x * kNG + g;
+  if (ru >= w.RU) return;
   const int r = (int)(ru % w.R);
   const bool inner = r >= 1 && r <= w.R - 2;
   // every row offset and both neighbour grids in one round of loads
@@ -618,30 +718,34 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   if (n == 0) return;
   // edge rows have no links; an over-full row unit (reported as an error) gets none either
   if (!inner || n > (uint32_t)kMaxRow) {
-    if (kS == kSlab)   // (written by one of the two instantiations)
-      for (uint32_t k = threadIdx.x; k < n; k += TB) { w.up[off + k] = -1; w.dn[off + k] = -1; }
+    if (kClass == 2)   // (written by one of the instantiations)
+      for (uint32_t k = gt; k < n; k += kG) { w.up[off + k] = -1; w.dn[off + k] = -1; }
     return;
   }
   const uint32_t nd = off - offd, nu = endu - offu;
-  const bool small = nd <= kSmallSlab && nu <= kSmallSlab;
-  if (small != (kS == kSmallSlab)) return;
+  const int cls = (nd <= kTiny && nu <= kTiny) ? 0 : (nd <= kSmallSlab && nu <= kSmallSlab) ? 1 : 2;
+  if (cls != kClass) return;
   const bool lds = nd <= kS && nu <= kS;
+  float4* sd = s_d[g];
+  float4* su = s_u[g];
+  uint16_t* scd = s_cd[g];
+  uint16_t* scu = s_cu[g];
   // this thread's own clusters (grid order) for its first rounds, read now
   // so that they arrive with the staged rows
   constexpr int kOwn = 4;
   float4 mine[kOwn];
 #pragma unroll
   for (int i = 0; i < kOwn; ++i) {
-    const uint32_t k = threadIdx.x + TB * i;
+    const uint32_t k = gt + kG * i;
     if (k < n) mine[i] = w.gbuf[off + k];
   }
   if (lds) {
     const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
-    for (uint32_t i = threadIdx.x; i < nd; i += TB) s_d[i] = w.gbuf[offd + i];
-    for (uint32_t i = threadIdx.x; i < nu; i += TB) s_u[i] = w.gbuf[offu + i];
-    for (uint32_t i = threadIdx.x; i <= ncd; i += TB) s_cd[i] = (uint16_t)(w.cell_off[Gd.cell_base + i] - offd);
-    for (uint32_t i = threadIdx.x; i <= ncu; i += TB) s_cu[i] = (uint16_t)(w.cell_off[Gu.cell_base + i] - offu);
-    __syncthreads();
+    for (uint32_t i = gt; i < nd; i += kG) sd[i] = w.gbuf[offd + i];
+    for (uint32_t i = gt; i < nu; i += kG) su[i] = w.gbuf[offu + i];
+    for (uint32_t i = gt; i <= ncd; i += kG) scd[i] = (uint16_t)(w.cell_off[Gd.cell_base + i] - offd);
+    for (uint32_t i = gt; i <= ncu; i += kG) scu[i] = (uint16_t)(w.cell_off[Gu.cell_base + i] - offu);
+    if (kG == TB) __syncthreads(); else wave_sync();
   }
   uint16_t* ld = s_ld + kCand * threadIdx.x;
   uint16_t* lu = s_lu + kCand * threadIdx.x;
@@ -651,13 +755,13 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     const float xi = me.z, yi = me.x, zi = me.y;
     int32_t bu = -1, bd = -1;
     if (lds) {
-      const int cd = collect(Gd, (const float4*)s_d, (const uint16_t*)s_cd, yi, zi, WY, WZ, ld);
-      const int cu = cd > 0 ? collect(Gu, (const float4*)s_u, (const uint16_t*)s_cu, yi, zi, WY, WZ, lu) : 0;
+      const int cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
+      const int cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
       if (cd <= kCand && cu <= kCand)
-        best_pair(w, xi, yi, zi, (const float4*)s_d, ld, cd, (const float4*)s_u, lu, cu, bu, bd);
+        best_pair(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
       else
-        find_pair(w, xi, yi, zi, Gd, (const float4*)s_d, (const uint16_t*)s_cd, Gu, (const float4*)s_u,
-                  (const uint16_t*)s_cu, bu, bd);
+        find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
+                  (const uint16_t*)scu, bu, bd);
     } else {
       find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
                 w.cell_off + Gu.cell_base, bu, bd);
@@ -667,8 +771,8 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   };
 #pragma unroll
   for (int i = 0; i < kOwn; ++i)
-    if (threadIdx.x + TB * i < n) link(mine[i]);
-  for (uint32_t k = threadIdx.x + TB * kOwn; k < n; k += TB) link(w.gbuf[off + k]);
+    if (gt + kG * i < n) link(mine[i]);
+  for (uint32_t k = gt + kG * kOwn; k < n; k += kG) link(w.gbuf[off + k]);
 }
 
 // ------------------------------------------------------- a3/a4: clean/start
@@ -1364,13 +1468,15 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_SCATTER);
   k_scatter<<<nchunk, TB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
+  k_rows_tiny<<<(unsigned)((w.RU + TB / 64 - 1) / (TB / 64)), TB, 0, st>>>(w);
   k_rows<false><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   k_rows<true><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   const unsigned nbN = (unsigned)w.nb;
   TPCCA_MARK(PH_LINKS);
-  k_links<kSmallSlab><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
-  k_links<kSlab><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_links<kTiny, 64><<<(unsigned)((w.RU + TB / 64 - 1) / (TB / 64)), TB, 0, st>>>(w);
+  k_links<kSmallSlab, TB><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_links<kSlab, TB><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_CLEAN);
   k_clean<<<nbN, TB, 0, st>>>(w);
   TPCCA_MARK(PH_COMPACT);
