@@ -49,6 +49,16 @@ struct EventIn {
   int64_t n;
 };
 
+// Binning chunk: kChunkCl consecutive clusters of one event (the last chunk
+// of an event is shorter; unused table entries are empty).
+constexpr int kChunkCl = 8192;
+struct ChunkIn {
+  int64_t c0, c1;   // global cluster range
+  int32_t e;        // event
+  int32_t pad;
+};
+inline int64_t chunk_cap(int64_t N, int E) { return N / kChunkCl + E + 1; }
+
 struct EventOut {
   uint8_t* sector;
   float* x_ref;
@@ -89,6 +99,7 @@ struct Ws {
   float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
   int tracklet_grid;    // workgroups of the tracklet kernel (0 = automatic)
   uint32_t* flags;      // [F_COUNT]
+  const ChunkIn* chunk; // [chunk_cap(N, E)] binning chunks, empty entries past the last
   // binning
   uint32_t* ru_count;   // [RU]
   uint32_t* ru_off;     // [RU + 1]

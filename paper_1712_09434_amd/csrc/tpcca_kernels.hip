@@ -127,19 +127,9 @@ inline unsigned xcd_blocks(int64_t n) {
   return (unsigned)((b + kXcd - 1) / kXcd * kXcd);
 }
 
-__device__ __forceinline__ int find_event(const Ws& w, int64_t g) {
-  int lo = 0, hi = w.E - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (w.ev[mid].base <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // ------------------------------------------------------------- a1: binning
-__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int64_t& l, uint32_t& ru,
+__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int e, int64_t& l, uint32_t& ru,
                                              float4& v) {
-  e = find_event(w, g);
   const EventIn& E = w.ev[e];
   l = g - E.base;
   const float x = E.x[l], y = E.y[l], z = E.z[l];
@@ -151,25 +141,25 @@ __device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int& e, int
   return true;
 }
 
-// Binning histograms are privatised in LDS per chunk of kChunk clusters: the
-// bins are the row units of the event of the chunk's first cluster (a chunk
-// that reaches into the next events sends those clusters straight to the
-// global counters).  Count: one global atomic per non-empty bin.  Scatter:
+// Binning histograms are privatised in LDS per chunk (up to kChunkCl
+// clusters of one event, from the host's chunk table): the bins are the
+// event's row units.  Count: one global atomic per non-empty bin.  Scatter:
 // one global range reservation per non-empty bin, then LDS ranks.
-constexpr int kChunkCl = 8192;
 constexpr int kLdsBins = 8192;
 
 __global__ __launch_bounds__(TB) void k_count(Ws w) {
   __shared__ uint32_t s_h[kLdsBins];
-  const int64_t c0 = (int64_t)blockIdx.x * kChunkCl;
-  const int64_t c1 = c0 + kChunkCl < w.N ? c0 + kChunkCl : w.N;
+  const ChunkIn ch = w.chunk[blockIdx.x];
+  if (ch.c0 >= ch.c1) return;
+  const int64_t c0 = ch.c0, c1 = ch.c1;
+  const int e = ch.e;
   const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
   const bool lds = per <= (uint32_t)kLdsBins;
-  const uint32_t rb = (uint32_t)find_event(w, c0) * per;
+  const uint32_t rb = (uint32_t)e * per;
   if (lds) for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
   __syncthreads();
   for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int e; int64_t l; uint32_t ru; float4 v;
+    int64_t l; uint32_t ru; float4 v;
     if (!read_cluster(w, g, e, l, ru, v)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
     if (lds && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
     else atomicAdd(&w.ru_count[ru], 1u);
@@ -192,16 +182,18 @@ __global__ void k_cell_caps(Ws w) {
 // (arbitrarily ordered) input.
 __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
   __shared__ uint32_t s_h[kLdsBins];
-  const int64_t c0 = (int64_t)blockIdx.x * kChunkCl;
-  const int64_t c1 = c0 + kChunkCl < w.N ? c0 + kChunkCl : w.N;
+  const ChunkIn ch = w.chunk[blockIdx.x];
+  if (ch.c0 >= ch.c1) return;
+  const int64_t c0 = ch.c0, c1 = ch.c1;
+  const int e = ch.e;
   const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
   const bool lds = per <= (uint32_t)kLdsBins;
-  const uint32_t rb = (uint32_t)find_event(w, c0) * per;
+  const uint32_t rb = (uint32_t)e * per;
   if (lds) {
     for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
     __syncthreads();
     for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-      int e; int64_t l; uint32_t ru; float4 v;
+      int64_t l; uint32_t ru; float4 v;
       if (!read_cluster(w, g, e, l, ru, v)) continue;
       if (ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
     }
@@ -213,7 +205,7 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
     __syncthreads();
   }
   for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int e; int64_t l; uint32_t ru; float4 v;
+    int64_t l; uint32_t ru; float4 v;
     if (!read_cluster(w, g, e, l, ru, v)) continue;
     const uint32_t k = (lds && ru - rb < per) ? atomicAdd(&s_h[ru - rb], 1u) : atomicAdd(&w.ru_count[ru], 1u);
     w.tmp4[w.ru_off[ru] + k] = v;
@@ -1457,7 +1449,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
   TPCCA_CHECK(fill_u32((uint32_t*)w.owner, 0u, 2 * w.N, st));
   TPCCA_MARK(PH_COUNT);
-  const unsigned nchunk = (unsigned)((w.N + kChunkCl - 1) / kChunkCl > 0 ? (w.N + kChunkCl - 1) / kChunkCl : 1);
+  const unsigned nchunk = (unsigned)chunk_cap(w.N, w.E);
   k_count<<<nchunk, TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);

@@ -125,6 +125,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_tf = L.take<uint32_t>(SC + 1), o_hc = L.take<uint32_t>(SC + 1);
   size_t o_res = L.take<int64_t>((int64_t)E * 4);
   size_t o_ev = L.take<EventIn>(E), o_out = L.take<EventOut>(E);
+  size_t o_chunk = L.take<ChunkIn>(chunk_cap(N, E));
   if (base) {
     w.flags = (uint32_t*)(base + o_flags);
     w.ru_count = (uint32_t*)(base + o_ruc); w.ru_off = (uint32_t*)(base + o_ruo);
@@ -154,6 +155,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.trk_flag = (uint32_t*)(base + o_tf); w.hit_cnt = (uint32_t*)(base + o_hc);
     w.ev_res = (int64_t*)(base + o_res);
     w.ev = (const EventIn*)(base + o_ev);
+    w.chunk = (const ChunkIn*)(base + o_chunk);
     w.out = (const EventOut*)(base + o_out);
   }
   return L.off;
@@ -408,7 +410,17 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
       O.dbg_start = o.dbg_start;
     }
   }
-  he = hipMemcpyAsync((void*)w.ev, ein.data(), sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
+  // binning chunks never span two events (the table has a fixed length for
+  // given N and E, so a captured graph stays valid; surplus entries are empty)
+  std::vector<ChunkIn> chunks((size_t)chunk_cap(w.N, E), ChunkIn{0, 0, 0, 0});
+  {
+    size_t q = 0;
+    for (int e = 0; e < E; ++e)
+      for (int64_t c0 = ein[e].base; c0 < ein[e].base + ein[e].n; c0 += kChunkCl)
+        chunks[q++] = ChunkIn{c0, std::min<int64_t>(c0 + kChunkCl, ein[e].base + ein[e].n), e, 0};
+  }
+  he = hipMemcpyAsync((void*)w.chunk, chunks.data(), sizeof(ChunkIn) * chunks.size(), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.ev, ein.data(), sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
   if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout.data(), sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
   if (he != hipSuccess) return hip_fail(c, he, "table upload");
 
