@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per cluster of each phase kernel ("Roofline").
+# Algorithmic bytes per cluster of each phase kernel: what the kernel must read and write per cluster.
 ALGO_BYTES_PER_CLUSTER = {
     "rows": 52.0,        # read 16 B bucketed (x, y, z, id); write 20 B canonical + 16 B grid entry
     "links": 44.0,       # read 12 B own coordinates + ~2 x 16 B window candidates; write 8 B links
@@ -59,7 +59,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the tracker shards by event and sector with no exchange, "
-              "and this build runs and reports the single-GPU share only (use --gpus 1).",
+              "and this benchmark runs and reports the single-GPU share only (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -203,7 +203,7 @@ def pmc_summary(folder: str):
               "write_scale": round(sw, 4), "kernels": rec}
     text = f"""# HBM traffic per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
 
-Commands (from the repository root on the GPU box, `TMPDIR=/tmp`):
+Commands (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
     rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_fetch -o fetch -- {PMC_BENCH_CMD}
     rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_write -o write -- {PMC_BENCH_CMD}
@@ -240,7 +240,7 @@ record: {json.dumps(record)}
         body = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in lines[:24])
         text2 = f"""# Kernel trace, central-Pb-Pb-shaped event (3.81 M clusters, one tpcca_track call per step)
 
-Command (from the repository root on the GPU box, `TMPDIR=/tmp`):
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
     rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_c3 -o c3 -- {PMC_BENCH_CMD}
     python3 bench.py --pmc-summary <out>

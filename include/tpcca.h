@@ -5,7 +5,7 @@
  * Source of the method: Rohr et al., "Online Reconstruction and Calibration
  * with feed back loop in the ALICE High Level Trigger" (arXiv:1712.09434).
  *   - Sec. "Track reconstruction in the TPC": a cellular automaton builds
- *     short seeds (around 5 to 10 hits); a Kalman filter then fits and
+ *     seeds of a handful of hits (five to ten); a Kalman filter then fits and
  *     follows them; one GPU thread per cluster during the cellular automaton
  *     and one per track during following; sectors are processed individually
  *     and their segments merged afterwards; several events share one GPU.
