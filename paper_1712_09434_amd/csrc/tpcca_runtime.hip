@@ -33,6 +33,12 @@ struct tpcca_ctx {
   // staging for host-memory inputs / outputs
   char* stage = nullptr;
   size_t stage_bytes = 0;
+  // pinned host memory for the per-call tables and the result words, so
+  // their copies are asynchronous
+  char* hpin = nullptr;
+  size_t hpin_bytes = 0;
+  bool hpin_busy = false;         // copies from/to it may still be queued (a call failed midway)
+  hipStream_t hpin_stream = nullptr;
   Ws w{};
   // last tracking call (debug tap)
   bool last_ok = false;
@@ -175,6 +181,20 @@ int ensure_arena(tpcca_ctx* c, size_t need) {
   return TPCCA_OK;
 }
 
+int ensure_pinned(tpcca_ctx* c, size_t need) {
+  if (need <= c->hpin_bytes) return TPCCA_OK;
+  if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; c->hpin_bytes = 0; }
+  const size_t want = need + need / 2;
+  hipError_t e = hipHostMalloc((void**)&c->hpin, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    c->hpin = nullptr;
+    (void)hipGetLastError();
+    return fail(c, TPCCA_E_NOMEM, "pinned host allocation failed");
+  }
+  c->hpin_bytes = want;
+  return TPCCA_OK;
+}
+
 int ensure_stage(tpcca_ctx* c, size_t need) {
   if (need <= c->stage_bytes) return TPCCA_OK;
   if (c->stage) { (void)hipFree(c->stage); c->stage = nullptr; c->stage_bytes = 0; }
@@ -300,6 +320,7 @@ void tpcca_destroy(tpcca_ctx* c) {
     if (c->pe.ev[i]) (void)hipEventDestroy(c->pe.ev[i]);
   if (c->arena) (void)hipFree(c->arena);
   if (c->stage) (void)hipFree(c->stage);
+  if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->gscratch) (void)hipFree(c->gscratch);
   if (c->row_x_d) (void)hipFree(c->row_x_d);
   delete c;
@@ -367,8 +388,24 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   if (soff > 0) { rc = ensure_stage(c, soff); if (rc) return rc; }
   char* sb = c->stage;
 
-  std::vector<EventIn> ein(E);
-  std::vector<EventOut> eout(E);
+  // per-call tables and result words in pinned host memory (a call that
+  // failed after queueing copies may have left them in flight)
+  if (c->hpin_busy) {
+    (void)hipStreamSynchronize(c->hpin_stream);
+    (void)hipGetLastError();
+    c->hpin_busy = false;
+  }
+  const size_t nchunk = (size_t)chunk_cap(N, E);
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t p_ein = 0, p_eout = al(p_ein + sizeof(EventIn) * E), p_chunk = al(p_eout + sizeof(EventOut) * E);
+  const size_t p_flags = al(p_chunk + sizeof(ChunkIn) * nchunk), p_res = al(p_flags + sizeof(uint32_t) * F_COUNT);
+  rc = ensure_pinned(c, p_res + sizeof(int64_t) * 4 * E);
+  if (rc) return rc;
+  EventIn* ein = (EventIn*)(c->hpin + p_ein);
+  EventOut* eout = (EventOut*)(c->hpin + p_eout);
+  ChunkIn* chunks = (ChunkIn*)(c->hpin + p_chunk);
+  uint32_t* flags = (uint32_t*)(c->hpin + p_flags);
+  int64_t* res = (int64_t*)(c->hpin + p_res);
   int64_t base = 0;
   for (int e = 0; e < E; ++e) {
     const tpcca_clusters& k = ev[e];
@@ -412,16 +449,18 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   }
   // binning chunks never span two events (the table has a fixed length for
   // given N and E, so a captured graph stays valid; surplus entries are empty)
-  std::vector<ChunkIn> chunks((size_t)chunk_cap(w.N, E), ChunkIn{0, 0, 0, 0});
   {
     size_t q = 0;
     for (int e = 0; e < E; ++e)
       for (int64_t c0 = ein[e].base; c0 < ein[e].base + ein[e].n; c0 += kChunkCl)
         chunks[q++] = ChunkIn{c0, std::min<int64_t>(c0 + kChunkCl, ein[e].base + ein[e].n), e, 0};
+    for (; q < nchunk; ++q) chunks[q] = ChunkIn{0, 0, 0, 0};
   }
-  he = hipMemcpyAsync((void*)w.chunk, chunks.data(), sizeof(ChunkIn) * chunks.size(), hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.ev, ein.data(), sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout.data(), sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
+  c->hpin_busy = true;
+  c->hpin_stream = st;
+  he = hipMemcpyAsync((void*)w.chunk, chunks, sizeof(ChunkIn) * nchunk, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.ev, ein, sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout, sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
   if (he != hipSuccess) return hip_fail(c, he, "table upload");
 
   if (c->tune.use_graph && !c->timing && st != nullptr) {
@@ -448,12 +487,11 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
     he = run_pipeline(w, st, c->timing ? &c->pe : nullptr);
     if (he != hipSuccess) return hip_fail(c, he, "kernel launch");
   }
-  uint32_t flags[F_COUNT];
-  std::vector<int64_t> res((size_t)E * 4);
-  he = hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(res.data(), w.ev_res, sizeof(int64_t) * 4 * E, hipMemcpyDeviceToHost, st);
+  he = hipMemcpyAsync(flags, w.flags, sizeof(uint32_t) * F_COUNT, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(res, w.ev_res, sizeof(int64_t) * 4 * E, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return hip_fail(c, he, "tracking");
+  c->hpin_busy = false;
   if (c->timing) {
     for (int i = 0; i < PH_N; ++i) {
       float ms = 0.f;
