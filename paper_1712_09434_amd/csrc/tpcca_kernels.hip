@@ -1182,7 +1182,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
 // takes the key maximum of each of the band's clusters with LDS atomics,
 // then writes the band's owners out in order.  A band with more than
 // kBandCap clusters uses global atomics on the (zeroed) owner array instead.
-constexpr int kBandRows = 4;
+constexpr int kBandRows = 8;
 constexpr int kBandCap = 6144;
 
 __global__ __launch_bounds__(TB) void k_owner(Ws w) {
@@ -1197,14 +1197,14 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   if (lds)
     for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
   __syncthreads();
-  // one thread per tracklet: the band's four hit slots are one aligned
-  // 16-byte load (the slot stride is a multiple of four rows)
-  static_assert(kBandRows == 4, "one int4 of hit slots per band");
+  // one thread per tracklet: the band's eight hit slots are two aligned
+  // 16-byte loads (the slot stride is a multiple of four rows)
+  static_assert(kBandRows == 8, "two int4 of hit slots per band");
   const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
   constexpr int kUn = 2;   // passes whose loads are issued together
   for (uint32_t sb = s0; sb < s1; sb += TB * kUn) {
     int32_t rg[kUn], nh[kUn];
-    int4 hh[kUn];
+    int4 hh[kUn], hh2[kUn];
     unsigned long long key[kUn];
     bool ok[kUn];
 #pragma unroll
@@ -1215,15 +1215,16 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
       rg[u] = w.tl_range[sc];
       nh[u] = w.tl_nhits[sc];
       hh[u] = *(const int4*)(w.tl_hits + (int64_t)sc * w.Rh + r_lo);
+      hh2[u] = r_lo + 4 < w.Rh ? *(const int4*)(w.tl_hits + (int64_t)sc * w.Rh + r_lo + 4) : make_int4(-1, -1, -1, -1);
       key[u] = w.tl_key[sc];
     }
 #pragma unroll
     for (int u = 0; u < kUn; ++u) {
       if (!ok[u] || nh[u] < w.P.min_hits) continue;
       const int rlo = rg[u] & 0xFFFF, rhi = rg[u] >> 16;
-      const int32_t hq[4] = {hh[u].x, hh[u].y, hh[u].z, hh[u].w};
+      const int32_t hq[8] = {hh[u].x, hh[u].y, hh[u].z, hh[u].w, hh2[u].x, hh2[u].y, hh2[u].z, hh2[u].w};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const int r = r_lo + q;
         const int32_t h = hq[q];
         if (r > r_hi || r < rlo || r > rhi || h < 0) continue;
