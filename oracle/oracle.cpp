@@ -141,7 +141,8 @@ bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr
   R c1 = Sqrt(Fma(-s1, s1, R(1.0)));
   R ss = s0 + s1;
   R cc = c0 + c1;
-  R tn = ss / cc;
+  R icc = R(1.0) / cc;                    // shared denominator: one division, then products
+  R tn = ss * icc;
   R dy = dx * tn;
   R d = Sqrt(Fma(dx, dx, dy * dy));       // chord length, signed like dx
   if (dx < R(0.0)) d = -d;
@@ -152,12 +153,13 @@ bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr
   R l = d * g;
   R t0 = s0 / c0;
   R t1 = s1 / c1;
-  R dtn_ds = Fma(tn, t0 + t1, R(2.0)) / cc;
-  R dtn_dk = (f * Fma(tn, t1, R(1.0))) / cc;
+  R dtn_ds = Fma(tn, t0 + t1, R(2.0)) * icc;
+  R dtn_dk = (f * Fma(tn, t1, R(1.0))) * icc;
   R a = dx * dtn_ds;                       // d dy / d s0
   R b = dx * dtn_dk;                       // d dy / d k
-  R dd_ds = (dy * a) / d;
-  R dd_dk = (dy * b) / d;
+  R id = R(1.0) / d;
+  R dd_ds = (dy * a) * id;
+  R dd_dk = (dy * b) * id;
   R du_ds = (kap * dd_ds) * R(0.5);
   R du_dk = Fma(m.kfac, d, kap * dd_dk) * R(0.5);
   R dl_ds = Fma(dd_ds, g, (d * gp) * du_ds);
@@ -217,9 +219,10 @@ void kf_update(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
   R S01 = C[1];
   R S11 = C[5] + vz;
   R det = Fma(S00, S11, -(S01 * S01));
-  R I00 = S11 / det;
-  R I01 = (-S01) / det;
-  R I11 = S00 / det;
+  R idet = R(1.0) / det;
+  R I00 = S11 * idet;
+  R I01 = (-S01) * idet;
+  R I11 = S00 * idet;
   R row0[5], row1[5];
   for (int j = 0; j < 5; ++j) { row0[j] = C[ix(0, j)]; row1[j] = C[ix(1, j)]; }
   R K0[5], K1[5];
@@ -263,8 +266,9 @@ template <class R>
 void chord_dir(R xi, R yi, R zi, R xo, R yo, R zo, R& s, R& t) {
   R dX = xo - xi, dY = yo - yi, dZ = zo - zi;
   R rho = Sqrt(Fma(dX, dX, dY * dY));
-  s = dY / rho;
-  t = dZ / rho;
+  R irho = R(1.0) / rho;
+  s = dY * irho;
+  t = dZ * irho;
 }
 
 // Final fit of an ordered hit list (outermost first): state initialised at

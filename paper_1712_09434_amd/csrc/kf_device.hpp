@@ -49,7 +49,8 @@ __host__ __device__ __forceinline__ bool transport(float p[5], float C[15], floa
   const float c1 = sqrtf(fmaf(-s1, s1, 1.0f));
   const float ss = s0 + s1;
   const float cc = c0 + c1;
-  const float tn = ss / cc;
+  const float icc = 1.0f / cc;   // shared denominator: one division, then products
+  const float tn = ss * icc;
   const float dy = dx * tn;
   float d = sqrtf(fmaf(dx, dx, dy * dy));
   if (dx < 0.0f) d = -d;
@@ -60,12 +61,13 @@ __host__ __device__ __forceinline__ bool transport(float p[5], float C[15], floa
   const float l = d * g;
   const float t0 = s0 / c0;
   const float t1 = s1 / c1;
-  const float dtn_ds = fmaf(tn, t0 + t1, 2.0f) / cc;
-  const float dtn_dk = (f * fmaf(tn, t1, 1.0f)) / cc;
+  const float dtn_ds = fmaf(tn, t0 + t1, 2.0f) * icc;
+  const float dtn_dk = (f * fmaf(tn, t1, 1.0f)) * icc;
   const float a = dx * dtn_ds;
   const float b = dx * dtn_dk;
-  const float dd_ds = (dy * a) / d;
-  const float dd_dk = (dy * b) / d;
+  const float id = 1.0f / d;
+  const float dd_ds = (dy * a) * id;
+  const float dd_dk = (dy * b) * id;
   const float du_ds = (kap * dd_ds) * 0.5f;
   const float du_dk = fmaf(m.kfac, d, kap * dd_dk) * 0.5f;
   const float dl_ds = fmaf(dd_ds, g, (d * gp) * du_ds);
@@ -118,9 +120,10 @@ __host__ __device__ __forceinline__ void update(float p[5], float C[15], float m
   const float S01 = C[1];
   const float S11 = C[5] + m.vz;
   const float det = fmaf(S00, S11, -(S01 * S01));
-  const float I00 = S11 / det;
-  const float I01 = (-S01) / det;
-  const float I11 = S00 / det;
+  const float idet = 1.0f / det;
+  const float I00 = S11 * idet;
+  const float I01 = (-S01) * idet;
+  const float I11 = S00 * idet;
   float row0[5], row1[5], K0[5], K1[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) { row0[j] = C[sym(0, j)]; row1[j] = C[sym(1, j)]; }
@@ -153,8 +156,9 @@ __host__ __device__ __forceinline__ void chord_dir(float xi, float yi, float zi,
                                           float zo, float& s, float& t) {
   const float dX = xo - xi, dY = yo - yi, dZ = zo - zi;
   const float rho = sqrtf(fmaf(dX, dX, dY * dY));
-  s = dY / rho;
-  t = dZ / rho;
+  const float irho = 1.0f / rho;
+  s = dY * irho;
+  t = dZ * irho;
 }
 
 }  // namespace tpcca
