@@ -41,7 +41,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sectors", default="0,13,18")
+    ap.add_argument("--cpu-sectors", default="0,13,18",
+                    help="sectors of the single-threaded oracle sample")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the multi-threaded oracle sample (0: the usable cores, at most 16)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -106,18 +109,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        secs = [int(s) for s in args.cpu_sectors.split(",")]
-        mask = np.zeros(36, np.uint8); mask[secs] = 1
-        nsample = int(np.isin(ev.sector, secs).sum())
-        log(f"oracle (FP32, 1 thread) on sectors {secs}: {nsample} clusters")
-        t1 = time.perf_counter()
-        oracle.track(ev, precision=32, sector_mask=mask)
-        ct = time.perf_counter() - t1
-        cpu = {"value": nsample / ct, "unit": "clusters/s", "cores": 1, "kind": "oracle",
-               "sample": f"C3 event sectors {secs} ({nsample} clusters), {ct:.1f} s single-threaded",
-               "host_cpu": _cpu_model()}
-        log(f"oracle {nsample / ct:.3e} clusters/s")
+        cpu = cpu_baseline(ev, args)
 
     batch = None if args.no_batch else batch_leg(args, Tracker, dev)
     grad = None if args.no_grad else grad_leg(Tracker, dev)
@@ -374,6 +366,51 @@ def grad_leg(Tracker, dev):
     return {"tracks": int(len(keep)), "hits": int(hoff[-1]), "ms_per_call": dt * 1e3,
             "params": 36 * 66}
 
+
+
+def cpu_baseline(ev, args):
+    """The oracle as written (FP32 mode), timed on host cores on a bounded
+    sample of the same event: (i) single-threaded on a few sectors, (ii) one
+    sector per thread on T threads at once (sectors are independent, so the
+    event's work splits over them without change).  The reported value is
+    (ii); cores = T."""
+    import concurrent.futures
+    import numpy as np
+    import oracle
+    ns = int(ev.geom.n_sectors)
+
+    def one(secs):
+        mask = np.zeros(ns, np.uint8)
+        mask[list(secs)] = 1
+        oracle.track(ev, precision=32, sector_mask=mask)
+
+    secs1 = [int(s) for s in args.cpu_sectors.split(",")]
+    n1 = int(np.isin(ev.sector, secs1).sum())
+    log(f"oracle (FP32, 1 thread) on sectors {secs1}: {n1} clusters")
+    t1 = time.perf_counter()
+    one(secs1)
+    c1 = time.perf_counter() - t1
+    log(f"oracle 1 thread {n1 / c1:.3e} clusters/s")
+
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    T = args.cpu_threads or max(1, min(16, avail))
+    T = min(T, ns)
+    secsT = sorted({int(round(v)) for v in np.linspace(0, ns - 1, T)})
+    nT = int(np.isin(ev.sector, secsT).sum())
+    log(f"oracle (FP32, {len(secsT)} threads, one sector each) on sectors {secsT}: {nT} clusters")
+    tT = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(secsT)) as pool:
+        list(pool.map(lambda s: one([s]), secsT))
+    cT = time.perf_counter() - tT
+    log(f"oracle {len(secsT)} threads {nT / cT:.3e} clusters/s")
+    return {"value": nT / cT, "unit": "clusters/s", "cores": len(secsT), "kind": "oracle",
+            "sample": (f"C3 event: sectors {secsT} ({nT} clusters), one sector per thread on "
+                       f"{len(secsT)} threads, {cT:.1f} s wall; single-threaded on sectors {secs1} "
+                       f"({n1} clusters) {c1:.1f} s"),
+            "single_thread_value": n1 / c1, "host_cpu": _cpu_model()}
 
 def _cpu_model():
     try:
