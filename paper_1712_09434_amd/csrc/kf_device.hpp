@@ -22,9 +22,13 @@ struct Model {
 };
 
 // Packed upper-triangle index of a symmetric 5x5 matrix.
+// (Not recursive, so that unrolled loops fold it to a constant: a swap by
+// recursion was left as a runtime loop with indexed register reads.)
+__host__ __device__ constexpr int sym_upper(int i, int j) {
+  return i == 0 ? j : i == 1 ? 4 + j : i == 2 ? 7 + j : i == 3 ? 9 + j : 14;
+}
 __host__ __device__ constexpr int sym(int i, int j) {
-  return i <= j ? (i == 0 ? j : i == 1 ? 4 + j : i == 2 ? 7 + j : i == 3 ? 9 + j : 14)
-                : sym(j, i);
+  return i <= j ? sym_upper(i, j) : sym_upper(j, i);
 }
 
 // One step of the helix from the plane x0 to the plane x1.  The sine of the

@@ -638,11 +638,8 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
                                           int32_t& bd) {
   const float IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z, CUT = w.P.link_cut;
-  bool have = false;
-  float bs = 0.0f;
   bu = -1; bd = -1;
-  float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
-  bool wk = false;
+  if (nu == 0) return;
   uint32_t ui[kCand];
 #pragma unroll
   for (int j = 0; j < kCand; ++j) ui[j] = j < nu ? lu[j] : 0u;
@@ -650,26 +647,53 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
 #pragma unroll
   for (int j = 0; j < kCand; ++j)
     if (j < nu) U[j] = U4[ui[j]];
+  // (bs, bu, bd) starts at (CUT, INT32_MAX, INT32_MAX): the first pair with
+  // score <= CUT replaces it, later ones must beat the best so far (a NaN
+  // score fails every comparison)
+  float bs = CUT;
+  int32_t ku = INT32_MAX, kd = INT32_MAX;
+  auto take = [&](float score, int32_t pu, int32_t pd) {
+    if (score < bs || (score == bs && (pu < ku || (pu == ku && pd < kd)))) { bs = score; ku = pu; kd = pd; }
+  };
+  // the interpolation quotient (xi - xd)/(xu - xd) only changes with the x
+  // coordinates: when all up candidates share one x it is taken once per
+  // down x, else per pair whenever either x differs from the last quotient's
+  bool same_xu = true;
+#pragma unroll
+  for (int j = 1; j < kCand; ++j)
+    if (j < nu && U[j].z != U[0].z) same_xu = false;
+  float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
+  bool wk = false;
   for (int i = 0; i < nd; ++i) {
     const float4 D = D4[ld[i]];
     const int32_t pd = (int32_t)__float_as_uint(D.w);
-#pragma unroll
-    for (int j = 0; j < kCand; ++j) {
-      if (j >= nu) continue;
-      if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
-        wq = (xi - D.z) / (U[j].z - D.z);
-        wx_d = D.z; wx_u = U[j].z; wk = true;
+    if (same_xu) {
+      if (!(wk && D.z == wx_d)) {
+        wq = (xi - D.z) / (U[0].z - D.z);
+        wx_d = D.z; wx_u = U[0].z; wk = true;
       }
-      const float wgt = wq;
-      const float ey = yi - fmaf(U[j].x - D.x, wgt, D.x);
-      const float ez = zi - fmaf(U[j].y - D.y, wgt, D.y);
-      const float score = fmaf(ez * ez, IWZ, (ey * ey) * IWY);
-      if (!(score <= CUT)) continue;
-      const int32_t pu = (int32_t)__float_as_uint(U[j].w);
-      const bool better = !have || score < bs || (score == bs && (pu < bu || (pu == bu && pd < bd)));
-      if (better) { have = true; bs = score; bu = pu; bd = pd; }
+#pragma unroll
+      for (int j = 0; j < kCand; ++j) {
+        if (j >= nu) continue;
+        const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
+        const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
+        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kCand; ++j) {
+        if (j >= nu) continue;
+        if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
+          wq = (xi - D.z) / (U[j].z - D.z);
+          wx_d = D.z; wx_u = U[j].z; wk = true;
+        }
+        const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
+        const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
+        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
+      }
     }
   }
+  if (ku != INT32_MAX) { bu = ku; bd = kd; }
 }
 
 // One block per row unit: the grids of rows r-1 and r+1 (entries and cell
@@ -885,14 +909,16 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   const float wy = 3.0f * __builtin_amdgcn_sqrtf(sy2) * 1.0001f;
   const float wz = 3.0f * __builtin_amdgcn_sqrtf(sz2) * 1.0001f;
   const CellBox b = cell_box(G, p[0], p[1], wy, wz);
-  Found best{-1, 0.f, 0.f, 0.f};
-  float bd = 0.0f;
+  // (bd, pos) starts at (CUT, INT32_MAX): the first candidate with d <= CUT
+  // replaces it, later ones must beat the best so far, so no separate test
+  // of the cut (a NaN distance fails every comparison)
+  Found best{INT32_MAX, 0.f, 0.f, 0.f};
+  float bd = CUT;
   auto consider = [&](const float4& c) {
     const float dY = c.x - p[0], dZ = c.y - p[1];
     const float d = fmaf(dZ * dZ, isz, (dY * dY) * isy);
-    if (!(d <= CUT)) return;
     const int32_t pos = (int32_t)__float_as_uint(c.w);
-    if (best.pos < 0 || d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
+    if (d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
   };
   const uint32_t nzr = b.iz1 - b.iz0 + 1;
   const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
@@ -927,6 +953,7 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
         if (k + j < k1) consider(c[j]);
     }
   }
+  if (best.pos == INT32_MAX) best.pos = -1;
   return best;
 }
 
