@@ -12,10 +12,11 @@ namespace tpcca {
 constexpr int kMaxRow = TPCCA_MAX_ROW_CLUSTERS;   // clusters per (sector, row) handled in LDS
 constexpr int kMaxCells = kMaxRow / 2 + 1;        // grid cells per (sector, row), at most
 
-// Cells of a row unit's search grid for n clusters: about two per cluster
-// (window searches then scan ~2 candidates), capped at kMaxCells.
+// Cells of a row unit's search grid for n clusters: kCellsPerCluster per
+// cluster (window searches then scan ~2 candidates), capped at kMaxCells.
+constexpr uint32_t kCellsPerCluster = 2;
 __host__ __device__ inline uint32_t grid_cells(uint32_t n) {
-  const uint32_t c = 2u * n + 1u;
+  const uint32_t c = kCellsPerCluster * n + 1u;
   return c < (uint32_t)kMaxCells ? c : (uint32_t)kMaxCells;
 }
 
@@ -115,7 +116,7 @@ struct Ws {
   uint32_t* cru;        // row unit
   // grid-ordered copy for window searches: (y, z, x, canonical position)
   float4* gbuf;         // [N]
-  uint32_t* cell_off;   // [2 N + 2 RU + 1] (grid_cells + 1 per row unit)
+  uint32_t* cell_off;   // [kCellsPerCluster N + 2 RU + 1] (grid_cells + 1 per row unit)
   // links (canonical positions)
   int32_t* up;
   int32_t* dn;

@@ -243,7 +243,7 @@ __device__ __forceinline__ void wave_sync() {
 constexpr uint32_t kTiny = 64;
 
 __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
-  __shared__ uint32_t s_h[TB / 64][2 * kTiny + 2];
+  __shared__ uint32_t s_h[TB / 64][kCellsPerCluster * kTiny + 2];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int64_t ru = (int64_t)blockIdx.x * (TB / 64) + wv;
   if (ru >= w.RU) return;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
 template <bool kLarge>
 __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   constexpr uint32_t kIds = kLarge ? (uint32_t)kMaxRow : 4u * TB;
-  constexpr uint32_t kCells = kLarge ? (uint32_t)kMaxCells : 2u * 4u * TB + 1u;   // grid_cells(n) bound
+  constexpr uint32_t kCells = kLarge ? (uint32_t)kMaxCells : kCellsPerCluster * 4u * TB + 1u;   // grid_cells(n) bound
   __shared__ uint32_t s_ids[kIds];
   // slots (16 bit) during the sort, then the cell histogram
   __shared__ uint32_t s_aux[(kCells + 1) > kIds / 2 ? (kCells + 1) : kIds / 2];
@@ -717,8 +717,8 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   constexpr int kClass = kS == kTiny ? 0 : kS == kSmallSlab ? 1 : 2;
   __shared__ float4 s_d[kNG][kS], s_u[kNG][kS];
   // cell offsets relative to the slab (< kS): 16 bit; a row of <= kS
-  // clusters has at most 2 kS + 1 cells
-  __shared__ uint16_t s_cd[kNG][2 * kS + 2], s_cu[kNG][2 * kS + 2];
+  // clusters has at most kCellsPerCluster kS + 1 cells
+  __shared__ uint16_t s_cd[kNG][kCellsPerCluster * kS + 2], s_cu[kNG][kCellsPerCluster * kS + 2];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const uint32_t g = threadIdx.x / kG, gt = threadIdx.x % kG;
   const int64_t ru = (int64_t)blockIdx.x * kNG + g;
@@ -996,6 +996,8 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   uint32_t rubase = 0;
   float p[5], C[15], xc = 0.f;
   uint32_t iters = 0;
+  // the record of the next chain cluster (nxt), loaded one step ahead
+  float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
   // hit slots are written through a four-row buffer (rows are visited in
   // order within a phase), one 16-byte store per full group of four rows
   int32_t wb0 = 0, wb1 = 0, wb2 = 0, wb3 = 0;
@@ -1016,7 +1018,12 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     const int b = row & ~3;
     if (b != wbase) { flush(); wbase = b; }
     const int q = row & 3;
-    if (q == 0) wb0 = v; else if (q == 1) wb1 = v; else if (q == 2) wb2 = v; else wb3 = v;
+    // value selects, not a store through a selected pointer: the latter
+    // would put the buffer in scratch memory
+    wb0 = q == 0 ? v : wb0;
+    wb1 = q == 1 ? v : wb1;
+    wb2 = q == 2 ? v : wb2;
+    wb3 = q == 3 ? v : wb3;
     wmask |= 1u << q;
   };
   // seed range of this workgroup's XCD (workgroups are dispatched to the
@@ -1069,7 +1076,8 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
             hits = w.tl_hits + s * w.Rh;
             const float4 a0 = w.cpk[h0];
             const int32_t h1 = __float_as_int(a0.w);
-            const int32_t h2 = __float_as_int(w.cpk[h1].w);
+            const float4 a1 = w.cpk[h1];
+            const int32_t h2 = __float_as_int(a1.w);
             const float4 a2 = w.cpk[h2];
             float sdir, tdir;
             const float x0 = a0.x, y0 = a0.y, z0 = a0.z;
@@ -1082,6 +1090,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
               put(r0, h0);
               nhits = 1;
               nxt = h1;
+              cn = a1;
               phase = ST_CHAIN;
             } else {
               nhits = 0;
@@ -1110,8 +1119,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     int32_t cnx = -1;
     GridParams G;
     if (chain) {
-      const float4 c = w.cpk[nxt];
-      X = c.x; my = c.y; mz = c.z; cnx = __float_as_int(c.w);
+      X = cn.x; my = cn.y; mz = cn.z; cnx = __float_as_int(cn.w);
     } else {
       X = sX[r];
     }
@@ -1199,6 +1207,9 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
       if (wrote) rlo = r;
       if (go && r - 1 >= 0) --r; else phase = ST_DONE;
     }
+    // the next chain record, loaded now so that it is there when the next
+    // step's transport needs its plane
+    if (phase == ST_CHAIN) cn = w.cpk[nxt];
   }
 }
 

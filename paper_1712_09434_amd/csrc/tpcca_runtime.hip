@@ -112,7 +112,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_cx = L.take<float>(N), o_cy = L.take<float>(N), o_cz = L.take<float>(N);
   size_t o_cid = L.take<uint32_t>(N), o_cru = L.take<uint32_t>(N);
   size_t o_gbuf = L.take<float4>(N);
-  size_t o_coff = L.take<uint32_t>(2 * N + 2 * RU + 1);
+  size_t o_coff = L.take<uint32_t>(kCellsPerCluster * N + 2 * RU + 1);
   size_t o_up = L.take<int32_t>(N), o_dn = L.take<int32_t>(N), o_cup = L.take<int32_t>(N), o_cdn = L.take<int32_t>(N);
   size_t o_cpk = L.take<float4>(N);
   size_t o_flag = L.take<uint8_t>(N);
