@@ -151,8 +151,9 @@ bool transport(R p[5], R C[15], R x0, R x1, const Model<R>& m, R* Fout = nullptr
   R g = Fma(u2, Fma(u2, Fma(u2, Fma(u2, A4, A3), A2), A1), R(1.0));
   R gp = u * Fma(u2, Fma(u2, Fma(u2, B4, B3), B2), B1);   // d(asin(u)/u)/du
   R l = d * g;
-  R t0 = s0 / c0;
-  R t1 = s1 / c1;
+  R i01 = R(1.0) / (c0 * c1);              // the two tangents share one division
+  R t0 = (s0 * c1) * i01;
+  R t1 = (s1 * c0) * i01;
   R dtn_ds = Fma(tn, t0 + t1, R(2.0)) * icc;
   R dtn_dk = (f * Fma(tn, t1, R(1.0))) * icc;
   R a = dx * dtn_ds;                       // d dy / d s0

@@ -31,6 +31,27 @@ __host__ __device__ constexpr int sym(int i, int j) {
   return i <= j ? sym_upper(i, j) : sym_upper(j, i);
 }
 
+// Correctly rounded square root of a finite x that is 0, negative (NaN
+// result) or >= 2^-96: the hardware root is within one ulp, and the signs of
+// the fused residuals x - s' s of its two neighbours s' pick the rounded
+// result.  This is the standard correction without the rescaling of tiny
+// inputs, which the callers' arguments never need: 1 - s^2 (one fused
+// rounding) for a float s is <= 0 or >= 2^-23 - 2^-48.  (The host build of
+// this header, used to run the calibration code on the CPU, takes the
+// library square root, which is correctly rounded too.)
+__host__ __device__ __forceinline__ float sqrt_rn_normal(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+  const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+  float r = fmaf(-sm, s, x) <= 0.0f ? sm : s;
+  r = fmaf(-sp, s, x) > 0.0f ? sp : r;
+  return r;
+#else
+  return sqrtf(x);
+#endif
+}
+
 // One step of the helix from the plane x0 to the plane x1.  The sine of the
 // direction moves linearly (s1 = s0 + kap dx); the chord rises by
 // dx (s0 + s1)/(c0 + c1); the transverse path is the chord (signed like dx)
@@ -49,8 +70,8 @@ __host__ __device__ __forceinline__ bool transport(float p[5], float C[15], floa
   const float f = m.kfac * dx;
   const float s1 = fmaf(kap, dx, s0);
   if (!(fabsf(s1) < m.sin_max)) return false;
-  const float c0 = sqrtf(fmaf(-s0, s0, 1.0f));
-  const float c1 = sqrtf(fmaf(-s1, s1, 1.0f));
+  const float c0 = sqrt_rn_normal(fmaf(-s0, s0, 1.0f));
+  const float c1 = sqrt_rn_normal(fmaf(-s1, s1, 1.0f));
   const float ss = s0 + s1;
   const float cc = c0 + c1;
   const float icc = 1.0f / cc;   // shared denominator: one division, then products
@@ -63,8 +84,9 @@ __host__ __device__ __forceinline__ bool transport(float p[5], float C[15], floa
   const float g = fmaf(u2, fmaf(u2, fmaf(u2, fmaf(u2, A4, A3), A2), A1), 1.0f);
   const float gp = u * fmaf(u2, fmaf(u2, fmaf(u2, B4, B3), B2), B1);
   const float l = d * g;
-  const float t0 = s0 / c0;
-  const float t1 = s1 / c1;
+  const float i01 = 1.0f / (c0 * c1);   // the two tangents share one division
+  const float t0 = (s0 * c1) * i01;
+  const float t1 = (s1 * c0) * i01;
   const float dtn_ds = fmaf(tn, t0 + t1, 2.0f) * icc;
   const float dtn_dk = (f * fmaf(tn, t1, 1.0f)) * icc;
   const float a = dx * dtn_ds;
