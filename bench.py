@@ -247,6 +247,46 @@ sha256 `{kernel_source_hash()}`.
         with open(os.path.join(ROOT, "profiles", "tracking_c3_kernel_trace.md"), "w") as f:
             f.write(text2)
         print(text2)
+        sq = defaultdict(lambda: defaultdict(float))
+        ncalls = defaultdict(int)
+        for fn in glob.glob(os.path.join(folder, "pmc_sq", "**", "*counter_collection*.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("tpcca::(anonymous namespace)::", ""))
+                name = re.sub(r"^void ", "", name)
+                sq[name][r["Counter_Name"]] += float(r["Counter_Value"])
+                if r["Counter_Name"] == "SQ_WAVES":
+                    ncalls[name] += 1
+        if sq:
+            avg_us = {n: a for n, _, a, _ in lines}
+            simds, clock_ghz = 256 * 4, 2.4
+            rows3 = []
+            for n in sorted(sq, key=lambda k: -avg_us.get(k, 0.0)):
+                c = ncalls[n] or 1
+                valu = sq[n]["SQ_INSTS_VALU"] / c
+                issue_us = valu * 4 / simds / (clock_ghz * 1e3)
+                d = avg_us.get(n, 0.0)
+                if d < 20.0:
+                    continue
+                rows3.append(f"| {n} | {sq[n]['SQ_WAVES'] / c:,.0f} | {valu / 1e6:,.1f} | "
+                             f"{sq[n]['SQ_INSTS_LDS'] / c / 1e6:,.2f} | {issue_us:,.1f} | {d:,.1f} | {issue_us / d:.2f} |")
+            text3 = f"""# SQ counters per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
+
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS -f csv -d <out>/pmc_sq -o sq -- {PMC_BENCH_CMD}
+    python3 bench.py --pmc-summary <out>
+
+Per dispatch (means over the profiled calls).  VALU issue time = wave-64 VALU instructions x 4
+cycles / (1,024 SIMDs x 2.4 GHz): the time the kernel would take if every SIMD issued one of its
+VALU instructions every 4 cycles.  Its ratio to the traced duration is the kernel's VALU issue
+utilisation.  Kernel sources sha256 `{kernel_source_hash()}`.
+
+| Kernel | Waves | VALU (M wave-instr.) | LDS (M wave-instr.) | VALU issue µs | Traced µs | Issue / traced |
+|---|---|---|---|---|---|---|
+""" + "\n".join(rows3) + "\n"
+            with open(os.path.join(ROOT, "profiles", "tracking_c3_sq_counters.md"), "w") as f:
+                f.write(text3)
+            print(text3)
 
 
 def copy_probe(mib: int, reps: int = 5):
