@@ -128,17 +128,47 @@ inline unsigned xcd_blocks(int64_t n) {
 }
 
 // ------------------------------------------------------------- a1: binning
-__device__ __forceinline__ bool read_cluster(const Ws& w, int64_t g, int e, int64_t& l, uint32_t& ru,
-                                             float4& v) {
-  const EventIn& E = w.ev[e];
-  l = g - E.base;
-  const float x = E.x[l], y = E.y[l], z = E.z[l];
-  const int r = E.row[l];
-  const int s = E.sector[l];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z)) || r < 0 || r >= w.R || s >= w.S) return false;
-  ru = ((uint32_t)e * (uint32_t)w.S + (uint32_t)s) * (uint32_t)w.R + (uint32_t)r;
-  v = make_float4(x, y, z, __uint_as_float((uint32_t)l));
+// Raw fields of one input cluster, then its validation and row unit.  The
+// binning kernels take kGroup clusters per thread at a time and issue all
+// their loads before the first is used.
+struct RawCl { float x, y, z; int r, s; };
+
+__device__ __forceinline__ RawCl load_cluster(const EventIn& E, int64_t l) {
+  return RawCl{E.x[l], E.y[l], E.z[l], (int)E.row[l], (int)E.sector[l]};
+}
+
+__device__ __forceinline__ bool check_cluster(const Ws& w, const RawCl& c, int e, int64_t l, uint32_t& ru,
+                                              float4& v) {
+  if (!(isfinite(c.x) && isfinite(c.y) && isfinite(c.z)) || c.r < 0 || c.r >= w.R || c.s >= w.S) return false;
+  ru = ((uint32_t)e * (uint32_t)w.S + (uint32_t)c.s) * (uint32_t)w.R + (uint32_t)c.r;
+  v = make_float4(c.x, c.y, c.z, __uint_as_float((uint32_t)l));
   return true;
+}
+
+constexpr int kGroup = 4;
+
+// f(ok, ru, v) for every cluster of the chunk [c0, c1) of event e taken by
+// this thread (stride TB), kGroup at a time.
+template <class F>
+__device__ __forceinline__ void for_chunk(const Ws& w, int64_t c0, int64_t c1, int e, F&& f) {
+  const EventIn& E = w.ev[e];
+  for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += (int64_t)kGroup * TB) {
+    RawCl c[kGroup];
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      const int64_t g = g0 + (int64_t)k * TB;
+      if (g < c1) c[k] = load_cluster(E, g - E.base);
+    }
+#pragma unroll
+    for (int k = 0; k < kGroup; ++k) {
+      const int64_t g = g0 + (int64_t)k * TB;
+      if (g >= c1) continue;
+      uint32_t ru = 0;
+      float4 v;
+      const bool ok = check_cluster(w, c[k], e, g - E.base, ru, v);
+      f(ok, ru, v);
+    }
+  }
 }
 
 // Binning histograms are privatised in LDS per chunk (up to kChunkCl
@@ -158,12 +188,11 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
   const uint32_t rb = (uint32_t)e * per;
   if (lds) for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
   __syncthreads();
-  for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int64_t l; uint32_t ru; float4 v;
-    if (!read_cluster(w, g, e, l, ru, v)) { atomicOr(&w.flags[F_ERR], ERR_INVALID); continue; }
+  for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4&) {
+    if (!ok) { atomicOr(&w.flags[F_ERR], ERR_INVALID); return; }
     if (lds && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
     else atomicAdd(&w.ru_count[ru], 1u);
-  }
+  });
   __syncthreads();
   if (lds)
     for (uint32_t b = threadIdx.x; b < per; b += TB)
@@ -192,24 +221,32 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
   if (lds) {
     for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
     __syncthreads();
-    for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-      int64_t l; uint32_t ru; float4 v;
-      if (!read_cluster(w, g, e, l, ru, v)) continue;
-      if (ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
-    }
+    for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4&) {
+      if (ok && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
+    });
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < per; b += TB) {
-      const uint32_t n = s_h[b];
-      s_h[b] = n ? atomicAdd(&w.ru_count[rb + b], n) : 0u;
+    // range reservations: the returning atomics of a thread's bins are all
+    // issued before their results are stored
+    constexpr int kPer = kLdsBins / TB;
+    uint32_t got[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t b = threadIdx.x + (uint32_t)i * TB;
+      const uint32_t n = b < per ? s_h[b] : 0u;
+      got[i] = n ? atomicAdd(&w.ru_count[rb + b], n) : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const uint32_t b = threadIdx.x + (uint32_t)i * TB;
+      if (b < per) s_h[b] = got[i];
     }
     __syncthreads();
   }
-  for (int64_t g = c0 + threadIdx.x; g < c1; g += TB) {
-    int64_t l; uint32_t ru; float4 v;
-    if (!read_cluster(w, g, e, l, ru, v)) continue;
+  for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4& v) {
+    if (!ok) return;
     const uint32_t k = (lds && ru - rb < per) ? atomicAdd(&s_h[ru - rb], 1u) : atomicAdd(&w.ru_count[ru], 1u);
     w.tmp4[w.ru_off[ru] + k] = v;
-  }
+  });
 }
 
 __device__ __forceinline__ uint32_t cell_coord(float v, float v0, float inv, uint32_t nc) {
@@ -1294,10 +1331,11 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const int64_t stride = (int64_t)(gridDim.x / kXcd) * (TB / 32);
   for (int64_t s = first; s < hi; s += stride) {
     uint32_t acc = 0, cnt = 0;
-    if (w.tl_nhits[s] >= w.P.min_hits) {
-      const int nh = w.tl_nhits[s];
-      const uint64_t key = w.tl_key[s];
-      const int32_t rg = w.tl_range[s];
+    // the three are loaded together (one memory round trip)
+    const int nh = w.tl_nhits[s];
+    const uint64_t key = w.tl_key[s];
+    const int32_t rg = w.tl_range[s];
+    if (nh >= w.P.min_hits) {
       const int rlo = rg & 0xFFFF, rhi = rg >> 16;
       const int32_t* hits = w.tl_hits + s * w.Rh;
       int32_t* own = w.tl_own + s * w.R;
