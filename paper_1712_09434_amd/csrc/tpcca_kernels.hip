@@ -752,10 +752,13 @@ template <uint32_t kS, uint32_t kG>
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
   constexpr uint32_t kNG = TB / kG;   // row units per workgroup
   constexpr int kClass = kS == kTiny ? 0 : kS == kSmallSlab ? 1 : 2;
-  __shared__ float4 s_d[kNG][kS], s_u[kNG][kS];
+  // one spare slot at the end of each array takes the staging stores of
+  // slots past a row's end (never read)
+  constexpr uint32_t kSpareE = kS, kSpareC = kCellsPerCluster * kS + 2;
+  __shared__ float4 s_d[kNG][kS + 1], s_u[kNG][kS + 1];
   // cell offsets relative to the slab (< kS): 16 bit; a row of <= kS
   // clusters has at most kCellsPerCluster kS + 1 cells
-  __shared__ uint16_t s_cd[kNG][kCellsPerCluster * kS + 2], s_cu[kNG][kCellsPerCluster * kS + 2];
+  __shared__ uint16_t s_cd[kNG][kSpareC + 1], s_cu[kNG][kSpareC + 1];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const uint32_t g = threadIdx.x / kG, gt = threadIdx.x % kG;
   const int64_t ru = (int64_t)blockIdx.x * kNG + g;
@@ -790,14 +793,33 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
 #pragma unroll
   for (int i = 0; i < kOwn; ++i) {
     const uint32_t k = gt + kG * i;
-    if (k < n) mine[i] = w.gbuf[off + k];
+    mine[i] = w.gbuf[off + (k < n ? k : 0u)];   // (used only if k < n)
   }
   if (lds) {
+    // all of a thread's staging loads are issued before the first LDS store
+    // (one memory round trip instead of one per loop iteration); slots past
+    // a row's end load an entry known to exist (this row's first entry, the
+    // row's first cell offset) and store it to the spare slot, so that
+    // neither the loads nor the stores need a branch
+    constexpr int kE = (int)((kS + kG - 1) / kG);                          // entries per thread
+    constexpr int kC = (int)((kCellsPerCluster * kS + 1 + kG) / kG);      // cell offsets per thread
     const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
-    for (uint32_t i = gt; i < nd; i += kG) sd[i] = w.gbuf[offd + i];
-    for (uint32_t i = gt; i < nu; i += kG) su[i] = w.gbuf[offu + i];
-    for (uint32_t i = gt; i <= ncd; i += kG) scd[i] = (uint16_t)(w.cell_off[Gd.cell_base + i] - offd);
-    for (uint32_t i = gt; i <= ncu; i += kG) scu[i] = (uint16_t)(w.cell_off[Gu.cell_base + i] - offu);
+#pragma unroll
+    for (int j = 0; j < kE; ++j) {
+      const uint32_t i = gt + kG * (uint32_t)j;
+      const float4 a = w.gbuf[i < nd ? offd + i : off];
+      const float4 b = w.gbuf[i < nu ? offu + i : off];
+      sd[i < nd ? i : kSpareE] = a;
+      su[i < nu ? i : kSpareE] = b;
+    }
+#pragma unroll
+    for (int j = 0; j < kC; ++j) {
+      const uint32_t i = gt + kG * (uint32_t)j;
+      const uint32_t a = w.cell_off[Gd.cell_base + (i <= ncd ? i : 0u)];
+      const uint32_t b = w.cell_off[Gu.cell_base + (i <= ncu ? i : 0u)];
+      scd[i <= ncd ? i : kSpareC] = (uint16_t)(a - offd);
+      scu[i <= ncu ? i : kSpareC] = (uint16_t)(b - offu);
+    }
     if (kG == TB) __syncthreads(); else wave_sync();
   }
   uint16_t* ld = s_ld + kCand * threadIdx.x;
