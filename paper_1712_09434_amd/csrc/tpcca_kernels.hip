@@ -859,12 +859,17 @@ __global__ __launch_bounds__(TB) void k_clean(Ws w) {
   const int64_t p = (int64_t)blockIdx.x * TB + threadIdx.x;
   bool start = false, seed = false;
   if (p < w.N) {
+    // independent loads first, then both reciprocity gathers together
+    // (a missing link reads the cluster's own entry, which is not used)
     const int32_t u = w.up[p], d = w.dn[p];
-    const int32_t cu = (u >= 0 && w.dn[u] == (int32_t)p) ? u : -1;
-    const int32_t cd = (d >= 0 && w.up[d] == (int32_t)p) ? d : -1;
+    const float x = w.cx[p], y = w.cy[p], z = w.cz[p];
+    const int32_t du = w.dn[u >= 0 ? u : (int32_t)p];
+    const int32_t ud = w.up[d >= 0 ? d : (int32_t)p];
+    const int32_t cu = (u >= 0 && du == (int32_t)p) ? u : -1;
+    const int32_t cd = (d >= 0 && ud == (int32_t)p) ? d : -1;
     w.cup[p] = cu;
     w.cdn[p] = cd;
-    w.cpk[p] = make_float4(w.cx[p], w.cy[p], w.cz[p], __int_as_float(cu));
+    w.cpk[p] = make_float4(x, y, z, __int_as_float(cu));
     start = cu >= 0 && cd < 0;
     if (start) {
       int L = 2;
