@@ -1358,35 +1358,35 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const int64_t stride = (int64_t)(gridDim.x / kXcd) * (TB / 32);
   for (int64_t s = first; s < hi; s += stride) {
     uint32_t acc = 0, cnt = 0;
-    // the three are loaded together (one memory round trip)
+    // the three are loaded together (one memory round trip): no branch
+    // around the rest, whose loads and stores are predicated on ok instead
     const int nh = w.tl_nhits[s];
     const uint64_t key = w.tl_key[s];
     const int32_t rg = w.tl_range[s];
-    if (nh >= w.P.min_hits) {
-      const int rlo = rg & 0xFFFF, rhi = rg >> 16;
-      const int32_t* hits = w.tl_hits + s * w.Rh;
-      int32_t* own = w.tl_own + s * w.R;
-      // a list spans at most eight passes of 32 rows (<= 255 rows): read all
-      // hit slots, then all their owners, then compact pass by pass
-      constexpr int kPass = 8;
-      int32_t h[kPass];
-      uint64_t o[kPass];
+    const bool ok = nh >= w.P.min_hits;
+    const int rlo = rg & 0xFFFF, rhi = rg >> 16;
+    const int32_t* hits = w.tl_hits + s * w.Rh;
+    int32_t* own = w.tl_own + s * w.R;
+    // a list spans at most eight passes of 32 rows (<= 255 rows): read all
+    // hit slots, then all their owners, then compact pass by pass
+    constexpr int kPass = 8;
+    int32_t h[kPass];
+    uint64_t o[kPass];
 #pragma unroll
-      for (int c = 0; c < kPass; ++c) {
-        const int r = rhi - hl - 32 * c;
-        h[c] = r >= rlo ? hits[r] : -1;
-      }
-#pragma unroll
-      for (int c = 0; c < kPass; ++c) o[c] = h[c] >= 0 ? w.owner[h[c]] : 0ull;
-#pragma unroll
-      for (int c = 0; c < kPass; ++c) {
-        const bool mine = h[c] >= 0 && o[c] == key;
-        const uint64_t m = __ballot(mine) & half;
-        if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h[c];
-        cnt += (uint32_t)__popcll(m);
-      }
-      acc = ((int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
+    for (int c = 0; c < kPass; ++c) {
+      const int r = rhi - hl - 32 * c;
+      h[c] = (ok && r >= rlo) ? hits[r] : -1;
     }
+#pragma unroll
+    for (int c = 0; c < kPass; ++c) o[c] = h[c] >= 0 ? w.owner[h[c]] : 0ull;
+#pragma unroll
+    for (int c = 0; c < kPass; ++c) {
+      const bool mine = h[c] >= 0 && o[c] == key;
+      const uint64_t m = __ballot(mine) & half;
+      if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h[c];
+      cnt += (uint32_t)__popcll(m);
+    }
+    acc = (ok && (int)cnt >= w.P.min_hits && (int64_t)w.P.owned_den * cnt >= (int64_t)w.P.owned_num * nh) ? 1u : 0u;
     if (hl == 0) {
       w.acc_flag[s] = acc;
       w.own_cnt[s] = acc ? cnt : 0u;
