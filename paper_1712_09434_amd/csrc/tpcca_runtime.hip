@@ -290,8 +290,11 @@ const char* tpcca_last_error(const tpcca_ctx* c) { return c ? c->err.c_str() : "
 int tpcca_set_phase_timing(tpcca_ctx* c, int on) {
   if (!c) return TPCCA_E_INVALID;
   if (on && !c->pe.ev[0]) {
+    // timing only (read after the call's stream synchronisation): no
+    // system-scope fence, so recording an event between two kernels does not
+    // write back and invalidate the caches under the next one
     for (int i = 0; i <= PH_N; ++i) {
-      hipError_t e = hipEventCreate(&c->pe.ev[i]);
+      hipError_t e = hipEventCreateWithFlags(&c->pe.ev[i], hipEventDisableSystemFence);
       if (e != hipSuccess) return hip_fail(c, e, "hipEventCreate");
     }
   }

@@ -280,3 +280,35 @@ def test_batch_of_uneven_events_matches_oracle(tracker, orc):
     for ev, out in zip(evs, batch):
         ref = orc.track(ev, precision=32)
         compare(ev, out, None, ref)
+
+
+def test_event_above_2_22_clusters(tracker, orc):
+    """An event of more than 2^22 clusters (ids past 22 bits, noise added to
+    sectors 1-12 of the headline event): the sampled sectors still match the
+    oracle."""
+    import dataclasses
+    ev = synth.make_config("C3")
+    extra = (1 << 22) - ev.n + 20000
+    rng = np.random.default_rng(77)
+    g = ev.geom
+    sec = rng.integers(1, 13, extra).astype(np.uint8)          # noise in sectors 1..12 only
+    row = rng.integers(0, g.n_rows, extra).astype(np.int16)
+    x = np.asarray(g.row_x, np.float32)[row]
+    y = (rng.uniform(-1.0, 1.0, extra) * x * np.float32(g.tan_half_angle)).astype(np.float32)
+    z = rng.uniform(-0.98, 0.98, extra).astype(np.float32) * np.float32(g.z_max)
+    cat = np.concatenate
+    big = dataclasses.replace(
+        ev, x=cat([ev.x, x]), y=cat([ev.y, y]), z=cat([ev.z, z]), row=cat([ev.row, row]),
+        sector=cat([ev.sector, sec]), x64=cat([ev.x64, x.astype(np.float64)]),
+        y64=cat([ev.y64, y.astype(np.float64)]), z64=cat([ev.z64, z.astype(np.float64)]),
+        truth_track=cat([ev.truth_track, np.full(extra, -1, np.int32)]),
+        truth_double=cat([ev.truth_double, np.zeros(extra, bool)]))
+    assert big.n >= 1 << 22
+    print(f"[gpu] event above 2^22 clusters n={big.n}", flush=True)
+    out = tracker.track(*to_dev(big), taps=True)
+    tl = tracker.debug_tracklets()
+    sectors = [0, 5, 13]
+    mask = np.zeros(36, np.uint8); mask[sectors] = 1
+    ref = orc.track(big, precision=32, sector_mask=mask)
+    compare(big, out, tl, ref, sectors=sectors)
+    assert out.n_tracks > 0
