@@ -1429,26 +1429,38 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
     bool ok = fabsf(sdir) < w.m.sin_max;
     float xc = xo;
     // hit records are read four steps ahead of their use and hit indices
-    // eight steps ahead (register rings), so loads overlap the filter steps
-    float4 q0, q1, q2, q3;
-    int32_t j0 = -1, j1 = -1, j2 = -1, j3 = -1;
-    q0 = w.cpk[own[1]];
-    if (2 < cnt) q1 = w.cpk[own[2]];
-    if (3 < cnt) q2 = w.cpk[own[3]];
-    if (4 < cnt) q3 = w.cpk[own[4]];
-    if (5 < cnt) j0 = own[5];
-    if (6 < cnt) j1 = own[6];
-    if (7 < cnt) j2 = own[7];
-    if (8 < cnt) j3 = own[8];
-    for (uint32_t k = 1; ok && k < cnt; ++k) {
-      const float hx = q0.x, hy = q0.y, hz = q0.z;
-      q0 = q1; q1 = q2; q2 = q3;
-      if (k + 4 < cnt) q3 = w.cpk[j0];
-      j0 = j1; j1 = j2; j2 = j3;
-      if (k + 8 < cnt) j3 = own[k + 8];
-      if (!transport(p, C, xc, hx, w.m)) { ok = false; break; }
-      update(p, C, hy, hz, w.m, chi2);
-      xc = hx;
+    // eight steps ahead, so loads overlap the filter steps.  The loop is
+    // unrolled by four with one register slot per step: a slot is refilled
+    // right after its use, and no register moves (which would wait for the
+    // loads in flight) rotate the slots.
+    float4 q0 = w.cpk[own[1]];
+    float4 q1 = w.cpk[2 < cnt ? own[2] : o0];
+    float4 q2 = w.cpk[3 < cnt ? own[3] : o0];
+    float4 q3 = w.cpk[4 < cnt ? own[4] : o0];
+    int32_t j0 = own[5 < cnt ? 5u : 0u], j1 = own[6 < cnt ? 6u : 0u];
+    int32_t j2 = own[7 < cnt ? 7u : 0u], j3 = own[8 < cnt ? 8u : 0u];
+    // (past the list's end a slot is refilled from the first hit, never
+    // used: loads made by every step, whether its hit exists or not, leave
+    // no register to merge after them)
+    // The refill is issued after the step's arithmetic, when the slot's old
+    // value is dead, so it lands in the same registers.
+    auto step = [&](float4& q, int32_t& j, uint32_t k) {
+      if (ok && k < cnt) {
+        if (transport(p, C, xc, q.x, w.m)) {
+          update(p, C, q.y, q.z, w.m, chi2);
+          xc = q.x;
+        } else {
+          ok = false;
+        }
+      }
+      q = w.cpk[k + 4 < cnt ? j : o0];
+      j = own[k + 8 < cnt ? k + 8 : 0u];
+    };
+    for (uint32_t k = 1; ok && k < cnt; k += 4) {
+      step(q0, j0, k);
+      step(q1, j1, k + 1);
+      step(q2, j2, k + 2);
+      step(q3, j3, k + 3);
     }
     if (ok) {
       float* rf = w.rf + s * kRf;
