@@ -35,6 +35,10 @@ struct CalWs {
   float* gy;
   float* gz;
   float* gpt;              // [H] x-adjoint point terms (seed chord, vertex hop)
+  float4* bva;             // [H] the four non-zero x-direction B-splines at the hit
+  float4* bvb;             // [H] the four non-zero y/x-direction B-splines at the hit
+  int32_t* bsp;            // [H] index of the first of each four: x in bits 0-7, y/x in 8-15
+  float* dzt;              // [H] drift term (L - side z) - tau of the hit (0 if invalid)
   float* part;             // [T][kPart]
   int32_t* tflag;          // [T] 0 failed, 1 hits only, 2 with vertex terms
   int32_t* tndf;           // [T]

@@ -307,14 +307,15 @@ __host__ __device__ __forceinline__ void load(const float* src, float p[5], floa
 }
 
 // The 8 clamped uniform cubic B-splines (knots 0,0,0,0,.2,.4,.6,.8,1,1,1,1)
-// at u, by the Cox-de Boor recursion over the one non-empty span.
-__host__ __device__ __forceinline__ void bspline8(float u, float B[8]) {
+// at u, by the Cox-de Boor recursion over the one non-empty span: the four
+// non-zero ones are B[span - 3 .. span] = N[0 .. 3]; returns span - 3.
+__host__ __device__ __forceinline__ int bspline4(float u, float N[4]) {
   u = fminf(fmaxf(u, 0.0f), 1.0f);
   const float kn[12] = {0.f, 0.f, 0.f, 0.f, 0.2f, 0.4f, 0.6f, 0.8f, 1.f, 1.f, 1.f, 1.f};
   int span = 3;
 #pragma unroll
   for (int i = 4; i <= 7; ++i) if (u >= kn[i]) span = i;
-  float N[4] = {1.f, 0.f, 0.f, 0.f};
+  N[0] = 1.f; N[1] = 0.f; N[2] = 0.f; N[3] = 0.f;
   float left[4], right[4];
 #pragma unroll
   for (int j = 1; j <= 3; ++j) {
@@ -330,10 +331,7 @@ __host__ __device__ __forceinline__ void bspline8(float u, float B[8]) {
     }
     N[j] = saved;
   }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) B[i] = 0.f;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) B[span - 3 + j] = N[j];
+  return span - 3;
 }
 
 // ------------------------------------------------------- 1. calibrate hits
@@ -347,16 +345,30 @@ __host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
     *c.err |= 1u;
 #endif
     c.hx[j] = c.hy[j] = c.hz[j] = 0.f;
+    c.bva[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    c.bvb[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    c.bsp[j] = 0;
+    c.dzt[j] = 0.f;
     return;
   }
   const int s = c.csec[id];
   const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
   const float side = s < c.S / 2 ? 1.0f : -1.0f;
   const float dl = c.dl[s], tau = c.tau[s];
-  c.hz[j] = side * (c.L - (1.0f + dl) * ((c.L - side * z) - tau));
+  const float drift = (c.L - side * z) - tau;
+  c.hz[j] = side * (c.L - (1.0f + dl) * drift);
+  c.dzt[j] = drift;
+  float Na[4], Nb[4];
+  const int fa = bspline4((x - c.x_first) / c.x_span, Na);
+  const int fb = bspline4((y / x + c.tan_a) / (2.0f * c.tan_a), Nb);
+  c.bva[j] = make_float4(Na[0], Na[1], Na[2], Na[3]);
+  c.bvb[j] = make_float4(Nb[0], Nb[1], Nb[2], Nb[3]);
+  c.bsp[j] = fa | (fb << 8);
   float Ba[8], Bb[8];
-  bspline8((x - c.x_first) / c.x_span, Ba);
-  bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { Ba[i] = 0.f; Bb[i] = 0.f; }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { Ba[fa + i] = Na[i]; Bb[fb + i] = Nb[i]; }
   const float* cm = c.map + s * 64;
   float acc = 0.f;
   for (int a = 0; a < 8; ++a) {
@@ -558,22 +570,23 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     int s = (int64_t)id0 < c.NC ? c.csec[id0] : 0;
     if (s >= c.S) s = 0;   // flagged as an error by k_cal_hits
     const float side = s < c.S / 2 ? 1.0f : -1.0f;
-    const float dl = c.dl[s], tau = c.tau[s];
+    const float dl = c.dl[s];
     const int a = l >> 3, b = l & 7;
+    // this lane's basis product at each hit from the four non-zero values
+    // of each direction stored per hit (the same floats as the full basis);
+    // the hit's records are the same for every lane of the track
+    auto pick = [](const float4& v, int k) {
+      return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : k == 3 ? v.w : 0.f;
+    };
     // basis product at hit i+1 (the next hit outward), carried down the loop
     float w_next = 0.f;
     for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
-      const uint32_t id = c.hit_id[j];
-      float wj = 0.f;
-      if ((int64_t)id < c.NC) {
-        const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
-        float Ba[8], Bb[8];
-        bspline8((x - c.x_first) / c.x_span, Ba);
-        bspline8((y / x + c.tan_a) / (2.0f * c.tan_a), Bb);
-        wj = Ba[a] * Bb[b];
-        if (l == 0) accd += c.gz[j] * (-side * ((c.L - side * z) - tau));
-        if (l == 1) accd += c.gz[j] * (side * (1.0f + dl));
+      const int32_t sp = c.bsp[j];
+      const float wj = pick(c.bva[j], a - (sp & 0xFF)) * pick(c.bvb[j], b - (sp >> 8));
+      if (l < 2 && (int64_t)c.hit_id[j] < c.NC) {
+        if (l == 0) accd += c.gz[j] * (-side * c.dzt[j]);
+        else accd += c.gz[j] * (side * (1.0f + dl));
       }
       if (i < nh - 1) acc += c.gx[j] * (wj - w_next);
       acc += c.gpt[j] * wj;
@@ -636,7 +649,8 @@ __global__ void k_cal_zero(CalWs c) {
 hipError_t run_calib(const CalWs& c, hipStream_t st) {
   // every array the kernels touch must be set before anything is launched
   const void* need[] = {c.hit_off, c.hit_id, c.k_prior, c.cx, c.cy, c.cz, c.csec, c.dl, c.tau, c.map,
-                        c.hx, c.hy, c.hz, c.gx, c.gy, c.gz, c.gpt, c.part, c.tflag, c.tndf, c.ckpt,
+                        c.hx, c.hy, c.hz, c.gx, c.gy, c.gz, c.gpt, c.bva, c.bvb, c.bsp, c.dzt,
+                        c.part, c.tflag, c.tndf, c.ckpt,
                         c.seg, c.chunk, c.out, c.ndf_sum, c.err};
   for (const void* p : need)
     if (!p) return hipErrorInvalidValue;

@@ -642,6 +642,8 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   Layout L;
   size_t o_hx = L.take<float>(H), o_hy = L.take<float>(H), o_hz = L.take<float>(H);
   size_t o_gx = L.take<float>(H), o_gy = L.take<float>(H), o_gz = L.take<float>(H), o_gpt = L.take<float>(H);
+  size_t o_bva = L.take<float4>(H), o_bvb = L.take<float4>(H), o_bsp = L.take<int32_t>(H);
+  size_t o_dzt = L.take<float>(H);
   size_t o_part = L.take<float>(T * kPart);
   size_t o_tf = L.take<int32_t>(T), o_tn = L.take<int32_t>(T);
   size_t o_ck = L.take<float>(T * nck * 20), o_sg = L.take<float>(T * nseg * 20);
@@ -720,6 +722,8 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   w.hx = (float*)(b + o_hx); w.hy = (float*)(b + o_hy); w.hz = (float*)(b + o_hz);
   w.gx = (float*)(b + o_gx); w.gy = (float*)(b + o_gy); w.gz = (float*)(b + o_gz);
   w.gpt = (float*)(b + o_gpt);
+  w.bva = (float4*)(b + o_bva); w.bvb = (float4*)(b + o_bvb); w.bsp = (int32_t*)(b + o_bsp);
+  w.dzt = (float*)(b + o_dzt);
   w.part = (float*)(b + o_part); w.tflag = (int32_t*)(b + o_tf); w.tndf = (int32_t*)(b + o_tn);
   w.ckpt = (float*)(b + o_ck); w.seg = (float*)(b + o_sg);
   w.chunk = (double*)(b + o_chunk); w.out = (double*)(b + o_out);

@@ -50,13 +50,16 @@ int main(int argc, char** argv) {
   c.hit_off = hoff.data(); c.hit_id = hid.data(); c.k_prior = kp.data(); c.ext_tgl = ext.data();
   c.use_vertex = uv.data(); c.cx = cx.data(); c.cy = cy.data(); c.cz = cz.data(); c.csec = cs.data();
   c.dl = th.data(); c.tau = th.data() + 36; c.map = th.data() + 72;
-  std::vector<float> hx(c.H), hy(c.H), hz(c.H), gx(c.H), gy(c.H), gz(c.H), gpt(c.H);
+  std::vector<float> hx(c.H), hy(c.H), hz(c.H), gx(c.H), gy(c.H), gz(c.H), gpt(c.H), dzt(c.H);
+  std::vector<float4> bva(c.H), bvb(c.H);
+  std::vector<int32_t> bsp(c.H);
   std::vector<float> part(c.T * kPart), ck(c.T * c.nck * 20), sg(c.T * c.nseg * 20);
   std::vector<int32_t> tf(c.T), tn(c.T);
   uint32_t err = 0;
   unsigned long long ndf = 0;
   c.hx = hx.data(); c.hy = hy.data(); c.hz = hz.data(); c.gx = gx.data(); c.gy = gy.data();
   c.gz = gz.data(); c.gpt = gpt.data(); c.part = part.data(); c.tflag = tf.data(); c.tndf = tn.data();
+  c.bva = bva.data(); c.bvb = bvb.data(); c.bsp = bsp.data(); c.dzt = dzt.data();
   c.ckpt = ck.data(); c.seg = sg.data(); c.err = &err; c.ndf_sum = &ndf;
   for (int64_t j = 0; j < c.H; ++j) calib_hit(c, j);
   for (int64_t t = 0; t < c.T; ++t) adjoint_track(c, t);
