@@ -10,6 +10,7 @@
 namespace tpcca {
 
 constexpr int kMaxRow = TPCCA_MAX_ROW_CLUSTERS;   // clusters per (sector, row) handled in LDS
+constexpr int kMaxSectors = 254;                  // sectors of a geometry, at most
 constexpr int kMaxCells = kMaxRow / 2 + 1;        // grid cells per (sector, row), at most
 
 // Cells of a row unit's search grid for n clusters: kCellsPerCluster per

@@ -416,12 +416,15 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   float chi2 = 0.f;
   bool ok = true;
   float xc = c.hx[j0];
+  // each step's hit is loaded one step ahead (the last step reloads its own)
+  float nx = c.hx[jk(1)], ny = c.hy[jk(1)], nz = c.hz[jk(1)];
   for (int k = 1; k < nh; ++k) {
     if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
-    const int64_t j = jk(k);
-    const float hx = c.hx[j];
+    const float hx = nx, hy = ny, hz = nz;
+    const int64_t jn = jk(k + 1 < nh ? k + 1 : k);
+    nx = c.hx[jn]; ny = c.hy[jn]; nz = c.hz[jn];
     if (!transport(p, C, xc, hx, m)) { ok = false; break; }
-    update(p, C, c.hy[j], c.hz[j], m, chi2);
+    update(p, C, hy, hz, m, chi2);
     xc = hx;
   }
   if (!ok) return;
@@ -505,19 +508,28 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     load(ck + sgi * 20, q, Q);
     float xv = c.hx[jk(k1 - 1)];
     float dummy = 0.f;
+    float nx = c.hx[jk(k1)], ny = c.hy[jk(k1)], nz = c.hz[jk(k1)];
     for (int k = k1; k <= k2; ++k) {
       save(sg + (k - k1) * 20, q, Q);
-      const int64_t j = jk(k);
-      const float hx = c.hx[j];
+      const float hx = nx, hy = ny, hz = nz;
+      const int64_t jn = jk(k < k2 ? k + 1 : k);
+      nx = c.hx[jn]; ny = c.hy[jn]; nz = c.hz[jn];
       transport(q, Q, xv, hx, m);
-      update(q, Q, c.hy[j], c.hz[j], m, dummy);
+      update(q, Q, hy, hz, m, dummy);
       xv = hx;
     }
+    // the hit values of the step are loaded one step ahead; gy and gz of a
+    // hit are still zero (set with the calibrated hits) when its step is
+    // reached, each hit ending one step, so they are written, not updated
+    float xt_n = c.hx[jk(k2)], yt_n = c.hy[jk(k2)], zt_n = c.hz[jk(k2)], xf_n = c.hx[jk(k2 - 1)];
     for (int k = k2; k >= k1; --k) {
-      const int64_t j = jk(k), jp = jk(k - 1);
+      const int64_t j = jk(k);
       float a[5], A[15];
       load(sg + (k - k1) * 20, a, A);
-      const float xf = c.hx[jp], xt = c.hx[j];
+      const float xt = xt_n, yt = yt_n, zt = zt_n, xf = xf_n;
+      // the next step (k - 1) ends on hit k - 1 and starts from hit k - 2
+      const int64_t jq = jk(k - 1), jr = jk(k >= 2 ? k - 2 : 0);
+      xt_n = xf; yt_n = c.hy[jq]; zt_n = c.hz[jq]; xf_n = c.hx[jr];
       float b[5], B[15];
 #pragma unroll
       for (int i = 0; i < 5; ++i) b[i] = a[i];
@@ -525,9 +537,9 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
       for (int i = 0; i < 15; ++i) B[i] = A[i];
       transport(b, B, xf, xt, m);
       float gm[2] = {0.f, 0.f};
-      update_adjoint(b, B, c.hy[j], c.hz[j], m.vy, m.vz, gP, G, gm);
-      c.gy[j] += gm[0];
-      c.gz[j] += gm[1];
+      update_adjoint(b, B, yt, zt, m.vy, m.vz, gP, G, gm);
+      c.gy[j] = 0.0f + gm[0];
+      c.gz[j] = 0.0f + gm[1];
       // the step's dx-derivative is kept whole (at the hit it ends on); the
       // map partials weight it by the change of the basis product between
       // its two hits, which avoids forming the difference of two large,
@@ -604,6 +616,11 @@ __global__ __launch_bounds__(64) void k_cal_partials(CalWs c) { partials_lane(c,
 // of part[t][p]; chunk[ch][S*66] = sum of the chunk's chi2.
 __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
   __shared__ int s_sec[kChunk];
+  // the chunk's tracks listed by sector, ascending within each (counting
+  // sort by one thread: kChunk entries), so that each sum visits only its
+  // sector's tracks, in the same order as a scan of the whole chunk
+  __shared__ int s_list[kChunk];
+  __shared__ int s_first[kMaxSectors + 1], s_fill[kMaxSectors];
   const int64_t t0 = (int64_t)blockIdx.x * kChunk;
   const int64_t nt = (c.T - t0) < kChunk ? (c.T - t0) : (int64_t)kChunk;
   for (int i = threadIdx.x; i < kChunk; i += TB) {
@@ -611,8 +628,17 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
     if (i < nt && c.tflag[t0 + i] > 0) {
       const uint32_t id = c.hit_id[c.hit_off[t0 + i]];
       s = (int64_t)id < c.NC ? c.csec[id] : 0;
+      if (s >= c.S) s = 0;   // flagged as an error by k_cal_hits
     }
     s_sec[i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q <= c.S; ++q) s_first[q] = 0;
+    for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) ++s_first[s_sec[i] + 1];
+    for (int q = 0; q < c.S; ++q) s_first[q + 1] += s_first[q];
+    for (int q = 0; q < c.S; ++q) s_fill[q] = s_first[q];
+    for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) s_list[s_fill[s_sec[i]]++] = i;
   }
   __syncthreads();
   const int nq = c.S * kNPar + 1;
@@ -623,7 +649,7 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
       for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) acc += (double)c.part[(t0 + i) * kPart + 66];
     } else {
       const int s = q / kNPar, p = q % kNPar;
-      for (int i = 0; i < nt; ++i) if (s_sec[i] == s) acc += (double)c.part[(t0 + i) * kPart + p];
+      for (int k = s_first[s]; k < s_first[s + 1]; ++k) acc += (double)c.part[(t0 + s_list[k]) * kPart + p];
     }
     out[q] = acc;
   }

@@ -251,7 +251,7 @@ int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out)
   if (!out) return TPCCA_E_INVALID;
   *out = nullptr;
   if (!g || !f || !g->row_x) return TPCCA_E_INVALID;
-  if (g->n_sectors <= 0 || (g->n_sectors & 1) || g->n_sectors > 254 || g->n_rows < 3 || g->n_rows > 255)
+  if (g->n_sectors <= 0 || (g->n_sectors & 1) || g->n_sectors > kMaxSectors || g->n_rows < 3 || g->n_rows > 255)
     return TPCCA_E_INVALID;
   for (int r = 0; r < g->n_rows; ++r) {
     if (!std::isfinite(g->row_x[r]) || g->row_x[r] <= 0.0f) return TPCCA_E_INVALID;
