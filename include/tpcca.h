@@ -154,7 +154,10 @@ typedef struct {
 
 /* Launch tuning (no effect on results).  ckpt_every: Kalman states kept
  * every that many hit steps by the gradient's forward pass (1..160, default
- * 12); tracklet_grid: workgroups of the persistent tracklet kernel, 0 =
+ * 160); the reverse sweep recomputes the states of each segment but the last
+ * from its checkpoint, so at the default (at least a track's step count) no
+ * state is recomputed, for 188 x 80 bytes of state per track;
+ * tracklet_grid: workgroups of the persistent tracklet kernel, 0 =
  * automatic; use_graph: 1 = capture the kernel sequence of a tracking call
  * in a hipGraph the first time a workspace shape is seen on a non-null
  * stream and replay it afterwards (default 0). */

@@ -7,6 +7,7 @@ namespace tpcca {
 constexpr int kPart = 68;                       // per-track partials: 66 parameters, chi2, pad
 constexpr int kNPar = TPCCA_NPAR_PER_SECTOR;    // 66 per sector
 constexpr int kChunk = 256;                     // tracks per first-level reduction chunk
+constexpr int kTail = 28;                       // state slots of the steps to the vertex (<= kTail - 2 steps)
 
 struct CalWs {
   int S, R;
@@ -14,7 +15,8 @@ struct CalWs {
   Model m;
   float sv2, st2;          // vertex and external tan(lambda) variances
   int K;                   // checkpoint stride (hit steps)
-  int nck, nseg;           // checkpoints and segment slots per track
+  int nck, nseg;           // checkpoints and state slots per track: K for a segment of hit
+                           // steps, then kTail for the steps to the vertex
   int64_t T, H, NC;        // tracks, hits, clusters
   const int32_t* hit_off;
   const uint32_t* hit_id;

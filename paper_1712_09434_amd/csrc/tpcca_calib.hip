@@ -413,13 +413,19 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   if (!(fabsf(sdir) < m.sin_max)) return;
   float* ck = c.ckpt + t * (int64_t)c.nck * 20;
   float* sg = c.seg + t * (int64_t)c.nseg * 20;
+  float* tl = sg + (int64_t)c.K * 20;   // the steps to the vertex
   float chi2 = 0.f;
   bool ok = true;
   float xc = c.hx[j0];
+  // the reverse sweep starts with the last segment of steps: its pre-step
+  // states are kept here, so that segment is not recomputed (with K >= the
+  // step count there is one segment and no recomputation at all)
+  const int k1_last = 1 + ((nh - 2) / c.K) * c.K;
   // each step's hit is loaded one step ahead (the last step reloads its own)
   float nx = c.hx[jk(1)], ny = c.hy[jk(1)], nz = c.hz[jk(1)];
   for (int k = 1; k < nh; ++k) {
     if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
+    if (k >= k1_last) save(sg + (k - k1_last) * 20, p, C);
     const float hx = nx, hy = ny, hz = nz;
     const int64_t jn = jk(k + 1 < nh ? k + 1 : k);
     nx = c.hx[jn]; ny = c.hy[jn]; nz = c.hz[jn];
@@ -441,7 +447,7 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   const float x_last = xc;
   if (uv) {
     nsub = (int)ceilf(x_last / 10.0f);
-    bool vok = nsub <= c.nseg - 2 && nsub >= 1;
+    bool vok = nsub <= kTail - 2 && nsub >= 1;
     float q[5], Q[15];
 #pragma unroll
     for (int i = 0; i < 5; ++i) q[i] = p[i];
@@ -477,22 +483,22 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     for (int i = 0; i < 15; ++i) Q[i] = last_C[i];
     float xv = x_last;
     for (int s = 0; s < nsub; ++s) {
-      save(sg + s * 20, q, Q);
+      save(tl + s * 20, q, Q);
       const float xt = 10.0f * (float)(nsub - 1 - s);
       transport(q, Q, xv, xt, m);
       xv = xt;
     }
-    save(sg + nsub * 20, q, Q);                    // before the vertex update
+    save(tl + nsub * 20, q, Q);                    // before the vertex update
     if (ue) {
       float dummy = 0.f;
       update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, dummy);
       update1_adjoint(q, Q, 3, c.ext_tgl[t], c.st2, gP, G);
-      load(sg + nsub * 20, q, Q);
+      load(tl + nsub * 20, q, Q);
     }
     float gm[2] = {0.f, 0.f};
     update_adjoint(q, Q, 0.0f, 0.0f, c.sv2, c.sv2, gP, G, gm);
     for (int s = nsub - 1; s >= 0; --s) {
-      load(sg + s * 20, q, Q);
+      load(tl + s * 20, q, Q);
       const float xf = s == 0 ? x_last : 10.0f * (float)(nsub - s);
       const float xt = 10.0f * (float)(nsub - 1 - s);
       const float gdx = transport_adjoint(q, Q, xt - xf, m.kfac, gP, G);
@@ -509,7 +515,7 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     float xv = c.hx[jk(k1 - 1)];
     float dummy = 0.f;
     float nx = c.hx[jk(k1)], ny = c.hy[jk(k1)], nz = c.hz[jk(k1)];
-    for (int k = k1; k <= k2; ++k) {
+    for (int k = k1; k <= k2 && k1 != k1_last; ++k) {
       save(sg + (k - k1) * 20, q, Q);
       const float hx = nx, hy = ny, hz = nz;
       const int64_t jn = jk(k < k2 ? k + 1 : k);
@@ -522,10 +528,17 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     // hit are still zero (set with the calibrated hits) when its step is
     // reached, each hit ending one step, so they are written, not updated
     float xt_n = c.hx[jk(k2)], yt_n = c.hy[jk(k2)], zt_n = c.hz[jk(k2)], xf_n = c.hx[jk(k2 - 1)];
+    // the saved state of the step is loaded one step ahead as well
+    float a_n[5], A_n[15];
+    load(sg + (k2 - k1) * 20, a_n, A_n);
     for (int k = k2; k >= k1; --k) {
       const int64_t j = jk(k);
       float a[5], A[15];
-      load(sg + (k - k1) * 20, a, A);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) a[i] = a_n[i];
+#pragma unroll
+      for (int i = 0; i < 15; ++i) A[i] = A_n[i];
+      load(sg + (k > k1 ? k - 1 - k1 : 0) * 20, a_n, A_n);
       const float xt = xt_n, yt = yt_n, zt = zt_n, xf = xf_n;
       // the next step (k - 1) ends on hit k - 1 and starts from hit k - 2
       const int64_t jq = jk(k - 1), jr = jk(k >= 2 ? k - 2 : 0);
@@ -680,7 +693,7 @@ hipError_t run_calib(const CalWs& c, hipStream_t st) {
                         c.seg, c.chunk, c.out, c.ndf_sum, c.err};
   for (const void* p : need)
     if (!p) return hipErrorInvalidValue;
-  if (c.K < 1 || c.nseg < c.K || c.nseg < 28 || c.nck < (c.R - 1 + c.K - 1) / c.K + 1) return hipErrorInvalidValue;
+  if (c.K < 1 || c.nseg < c.K + kTail || c.nck < (c.R - 1 + c.K - 1) / c.K + 1) return hipErrorInvalidValue;
   k_cal_zero<<<1, 64, 0, st>>>(c);
   const unsigned bh = (unsigned)std::min<int64_t>(std::max<int64_t>((c.H + TB - 1) / TB, 1), 65536);
   k_cal_hits<<<bh, TB, 0, st>>>(c);

@@ -47,7 +47,7 @@ struct tpcca_ctx {
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
   // tuning
-  tpcca_tuning tune{12, 0, 0};
+  tpcca_tuning tune{160, 0, 0};
   // captured tracking graph and the workspace shape it was captured for
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -635,7 +635,7 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   if (H < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
   const int K = c->tune.ckpt_every;
   const int nck = (c->R - 1 + K - 1) / K + 1;
-  const int nseg = std::max(K, 28);
+  const int nseg = K + kTail;
   const int64_t nchunk = (T + kChunk - 1) / kChunk;
   const int nq = S * kNPar + 1;
   // scratch layout

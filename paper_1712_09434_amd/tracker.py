@@ -179,7 +179,7 @@ class Tracker:
         return [self._slice(sts[e], outs[e], int(events[e][0].shape[0])) for e in range(E)]
 
     # ----------------------------------------------------------- calibration
-    def set_tuning(self, ckpt_every: int = 12, tracklet_grid: int = 0, use_graph: int = 0):
+    def set_tuning(self, ckpt_every: int = 160, tracklet_grid: int = 0, use_graph: int = 0):
         t = A.tpcca_tuning(int(ckpt_every), int(tracklet_grid), int(use_graph))
         _check(self.L, self.ctx, self.L.tpcca_set_tuning(self.ctx, C.byref(t)))
 

@@ -87,7 +87,7 @@ def test_checkpoint_stride_does_not_change_results(setup):
             ref = (c2, g)
         else:
             assert c2 == ref[0] and torch.equal(g, ref[1]), K
-    trk.set_tuning(ckpt_every=12)
+    trk.set_tuning(ckpt_every=160)
 
 
 def test_deterministic_and_host_mode(setup):
