@@ -605,6 +605,7 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     };
     // basis product at hit i+1 (the next hit outward), carried down the loop
     float w_next = 0.f;
+#pragma unroll 4
     for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
       const int32_t sp = c.bsp[j];
@@ -629,11 +630,11 @@ __global__ __launch_bounds__(64) void k_cal_partials(CalWs c) { partials_lane(c,
 // of part[t][p]; chunk[ch][S*66] = sum of the chunk's chi2.
 __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
   __shared__ int s_sec[kChunk];
-  // the chunk's tracks listed by sector, ascending within each (counting
-  // sort by one thread: kChunk entries), so that each sum visits only its
-  // sector's tracks, in the same order as a scan of the whole chunk
+  // the chunk's tracks listed by sector, ascending within each, so that
+  // each sum visits only its sector's tracks, in the same order as a scan
+  // of the whole chunk
   __shared__ int s_list[kChunk];
-  __shared__ int s_first[kMaxSectors + 1], s_fill[kMaxSectors];
+  __shared__ int s_first[kMaxSectors + 1];
   const int64_t t0 = (int64_t)blockIdx.x * kChunk;
   const int64_t nt = (c.T - t0) < kChunk ? (c.T - t0) : (int64_t)kChunk;
   for (int i = threadIdx.x; i < kChunk; i += TB) {
@@ -646,12 +647,30 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
     s_sec[i] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 0; q <= c.S; ++q) s_first[q] = 0;
-    for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) ++s_first[s_sec[i] + 1];
+  // each entry's rank among the earlier entries of its sector (broadcast
+  // LDS reads), the sectors' counts, their prefix, then the lists
+  for (int q = threadIdx.x; q <= c.S; q += TB) s_first[q] = 0;
+  __syncthreads();
+  int rank[kChunk / TB];
+#pragma unroll
+  for (int u = 0; u < kChunk / TB; ++u) {
+    const int i = threadIdx.x + u * TB;
+    const int si = s_sec[i];
+    int rk = 0;
+    if (si >= 0) {
+      for (int k = 0; k < i; ++k) rk += s_sec[k] == si ? 1 : 0;
+      atomicAdd(&s_first[si + 1], 1);
+    }
+    rank[u] = rk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
     for (int q = 0; q < c.S; ++q) s_first[q + 1] += s_first[q];
-    for (int q = 0; q < c.S; ++q) s_fill[q] = s_first[q];
-    for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) s_list[s_fill[s_sec[i]]++] = i;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kChunk / TB; ++u) {
+    const int i = threadIdx.x + u * TB;
+    if (s_sec[i] >= 0) s_list[s_first[s_sec[i]] + rank[u]] = i;
   }
   __syncthreads();
   const int nq = c.S * kNPar + 1;
