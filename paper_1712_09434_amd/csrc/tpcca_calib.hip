@@ -363,7 +363,7 @@ __host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
   const int fb = bspline4((y / x + c.tan_a) / (2.0f * c.tan_a), Nb);
   c.bva[j] = make_float4(Na[0], Na[1], Na[2], Na[3]);
   c.bvb[j] = make_float4(Nb[0], Nb[1], Nb[2], Nb[3]);
-  c.bsp[j] = fa | (fb << 8);
+  c.bsp[j] = fa | (fb << 8) | (1 << 16);
   float Ba[8], Bb[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) { Ba[i] = 0.f; Bb[i] = 0.f; }
@@ -599,23 +599,31 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     const int a = l >> 3, b = l & 7;
     // this lane's basis product at each hit from the four non-zero values
     // of each direction stored per hit (the same floats as the full basis);
-    // the hit's records are the same for every lane of the track
+    // the hit's records are the same for every lane of the track and are
+    // all read before any is used, the sums take their terms by selects
+    // component k of v (0 outside 0..3) as a sum of products with 0 / 1:
+    // exact for the finite, non-negative basis values, and every component
+    // is read, so the record's loads are not split across branches
     auto pick = [](const float4& v, int k) {
-      return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : k == 3 ? v.w : 0.f;
+      const float e0 = k == 0 ? 1.f : 0.f, e1 = k == 1 ? 1.f : 0.f;
+      const float e2 = k == 2 ? 1.f : 0.f, e3 = k == 3 ? 1.f : 0.f;
+      return ((e0 * v.x + e1 * v.y) + e2 * v.z) + e3 * v.w;
     };
+    const float kd = l == 0 ? -side : side * (1.0f + dl);
     // basis product at hit i+1 (the next hit outward), carried down the loop
     float w_next = 0.f;
 #pragma unroll 4
     for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
       const int32_t sp = c.bsp[j];
-      const float wj = pick(c.bva[j], a - (sp & 0xFF)) * pick(c.bvb[j], b - (sp >> 8));
-      if (l < 2 && (int64_t)c.hit_id[j] < c.NC) {
-        if (l == 0) accd += c.gz[j] * (-side * c.dzt[j]);
-        else accd += c.gz[j] * (side * (1.0f + dl));
-      }
-      if (i < nh - 1) acc += c.gx[j] * (wj - w_next);
-      acc += c.gpt[j] * wj;
+      const float4 va = c.bva[j], vb = c.bvb[j];
+      const float gxj = c.gx[j], gpj = c.gpt[j], gzj = c.gz[j], dz = c.dzt[j];
+      const float wj = pick(va, a - (sp & 0xFF)) * pick(vb, b - ((sp >> 8) & 0xFF));
+      // drift scale (lane 0) and time offset (lane 1), valid hits only
+      const float td = l == 0 ? dz : 1.0f;
+      if (l < 2 && (sp >> 16) != 0) accd += gzj * (kd * td);
+      if (i < nh - 1) acc += gxj * (wj - w_next);
+      acc += gpj * wj;
       w_next = wj;
     }
   }
