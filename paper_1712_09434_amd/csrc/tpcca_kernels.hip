@@ -63,8 +63,68 @@ __global__ void k_fill(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) p[i] = v;
 }
 
-__global__ __launch_bounds__(TB) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
-                                                    uint32_t* __restrict__ part) {
+// Exclusive scans, out[n] = total (out may equal in).  Up to two arrays of
+// the same length are scanned by the same launches (blockIdx.y selects the
+// array): one workgroup each when n <= kScanSmall, else reduce / partials /
+// down-sweep over tiles of 1024.
+struct ScanArgs {
+  const uint32_t* in[2];
+  uint32_t* out[2];
+};
+constexpr int kScanNT = 1024;                        // threads of a one-workgroup scan
+constexpr int64_t kScanSmall = 4 * 4 * kScanNT;      // at most four tiles of 4 x kScanNT
+
+// Exclusive scan over a kScanNT-thread block; *tot receives the block total.
+__device__ uint32_t block_excl_scan_big(uint32_t v, uint32_t* tot) {
+  __shared__ uint32_t s_w[kScanNT / 64];
+  const uint32_t inc = wave_incl_scan(v);
+  const int wid = threadIdx.x >> 6;
+  if (lane_id() == 63) s_w[wid] = inc;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kScanNT / 64; ++i) {
+    const uint32_t t = s_w[i];
+    if (i < wid) base += t;
+    total += t;
+  }
+  __syncthreads();
+  *tot = total;
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_small(ScanArgs a, int64_t n) {
+  const uint32_t* in = a.in[blockIdx.x];
+  uint32_t* out = a.out[blockIdx.x];
+  const uint32_t n32 = (uint32_t)n;   // n <= kScanSmall
+  // tiles of four coalesced values per thread with a running carry; past
+  // the end a thread reads element 0 and drops it (no branch around loads)
+  uint32_t carry = 0;
+  for (uint32_t t0 = 0; t0 < n32; t0 += 4u * kScanNT) {
+    const uint32_t base = t0 + 4u * threadIdx.x;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t x = in[base + j < n32 ? base + j : 0u];
+      v[j] = base + j < n32 ? x : 0u;
+      sum += v[j];
+    }
+    uint32_t tot;
+    uint32_t ex = carry + block_excl_scan_big(sum, &tot);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      if (base + j < n32) out[base + j] = ex;
+      ex += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n32] = carry;
+}
+
+__global__ __launch_bounds__(TB) void k_scan_reduce(ScanArgs a, int64_t n, uint32_t* __restrict__ part,
+                                                    int64_t pstride) {
+  const uint32_t* in = a.in[blockIdx.y];
+  part += blockIdx.y * pstride;
   const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   uint32_t s = 0;
 #pragma unroll
@@ -74,7 +134,8 @@ __global__ __launch_bounds__(TB) void k_scan_reduce(const uint32_t* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(TB) void k_scan_parts(uint32_t* __restrict__ part, int64_t np) {
+__global__ __launch_bounds__(TB) void k_scan_parts(uint32_t* __restrict__ part, int64_t np, int64_t pstride) {
+  part += blockIdx.x * pstride;
   uint32_t carry = 0;
   for (int64_t b = 0; b < np; b += TB) {
     const int64_t i = b + threadIdx.x;
@@ -87,9 +148,11 @@ __global__ __launch_bounds__(TB) void k_scan_parts(uint32_t* __restrict__ part, 
   if (threadIdx.x == 0) part[np] = carry;
 }
 
-__global__ __launch_bounds__(TB) void k_scan_down(const uint32_t* in, int64_t n,
-                                                  const uint32_t* __restrict__ part, int64_t np,
-                                                  uint32_t* out) {
+__global__ __launch_bounds__(TB) void k_scan_down(ScanArgs a, int64_t n, const uint32_t* __restrict__ part,
+                                                  int64_t np, int64_t pstride) {
+  const uint32_t* in = a.in[blockIdx.y];
+  uint32_t* out = a.out[blockIdx.y];
+  part += blockIdx.y * pstride;
   const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   uint32_t v[4], s = 0;
 #pragma unroll
@@ -104,13 +167,30 @@ __global__ __launch_bounds__(TB) void k_scan_down(const uint32_t* in, int64_t n,
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[np];
 }
 
-// Exclusive scan of n values; out[n] receives the total (out may equal in).
-hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st) {
+// Exclusive scans of narr (1 or 2) arrays of n values; part holds
+// 2 (n / 1024 + 2) values.
+hipError_t scan_arrays(ScanArgs a, int narr, int64_t n, uint32_t* part, hipStream_t st) {
+  if (n <= kScanSmall) {
+    k_scan_small<<<dim3((unsigned)narr), dim3(kScanNT), 0, st>>>(a, n);
+    return hipGetLastError();
+  }
   const int64_t np = (n + 1023) / 1024;
-  if (np > 0) k_scan_reduce<<<dim3((unsigned)np), dim3(TB), 0, st>>>(in, n, part);
-  k_scan_parts<<<1, TB, 0, st>>>(part, np);
-  k_scan_down<<<dim3((unsigned)(np > 0 ? np : 1)), dim3(TB), 0, st>>>(in, n, part, np, out);
+  const int64_t ps = np + 2;
+  k_scan_reduce<<<dim3((unsigned)np, (unsigned)narr), dim3(TB), 0, st>>>(a, n, part, ps);
+  k_scan_parts<<<dim3((unsigned)narr), TB, 0, st>>>(part, np, ps);
+  k_scan_down<<<dim3((unsigned)np, (unsigned)narr), dim3(TB), 0, st>>>(a, n, part, np, ps);
   return hipGetLastError();
+}
+
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st) {
+  ScanArgs a{{in, in}, {out, out}};
+  return scan_arrays(a, 1, n, part, st);
+}
+
+hipError_t scan_u32x2(const uint32_t* in0, uint32_t* out0, const uint32_t* in1, uint32_t* out1, int64_t n,
+                      uint32_t* part, hipStream_t st) {
+  ScanArgs a{{in0, in1}, {out0, out1}};
+  return scan_arrays(a, 2, n, part, st);
 }
 
 inline unsigned blocks_for(int64_t n, int64_t cap = 1 << 16) {
@@ -1574,8 +1654,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(hipGetLastError());
   k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_SCAN);
-  TPCCA_CHECK(scan_u32(w.ru_count, w.ru_off, w.RU, w.scan_tmp, st));
-  TPCCA_CHECK(scan_u32(w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32x2(w.ru_count, w.ru_off, w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
   TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
   TPCCA_MARK(PH_SCATTER);
   k_scatter<<<nchunk, TB, 0, st>>>(w);
@@ -1592,8 +1671,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_CLEAN);
   k_clean<<<nbN, TB, 0, st>>>(w);
   TPCCA_MARK(PH_COMPACT);
-  TPCCA_CHECK(scan_u32(w.blk_start, w.blk_start, w.nb, w.scan_tmp, st));
-  TPCCA_CHECK(scan_u32(w.blk_seed, w.blk_seed, w.nb, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32x2(w.blk_start, w.blk_start, w.blk_seed, w.blk_seed, w.nb, w.scan_tmp, st));
   k_compact<<<nbN, TB, 0, st>>>(w);
   k_ev_offsets<<<blocks_for(w.N / 2 + 2, 4096), TB, 0, st>>>(w);
   k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
@@ -1610,8 +1688,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);
   k_trk_flags<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   TPCCA_MARK(PH_OUTPUT);
-  TPCCA_CHECK(scan_u32(w.trk_flag, w.trk_flag, w.seed_cap, w.scan_tmp, st));
-  TPCCA_CHECK(scan_u32(w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
+  TPCCA_CHECK(scan_u32x2(w.trk_flag, w.trk_flag, w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
   k_totals<<<1, TB, 0, st>>>(w);
   k_write<<<blocks_for(w.seed_cap * 16, 1 << 13), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());

@@ -117,7 +117,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_cpk = L.take<float4>(N);
   size_t o_flag = L.take<uint8_t>(N);
   size_t o_bs = L.take<uint32_t>(w.nb + 1), o_bq = L.take<uint32_t>(w.nb + 1);
-  size_t o_scan = L.take<uint32_t>(scan_n / 1024 + 4);
+  size_t o_scan = L.take<uint32_t>(2 * (scan_n / 1024 + 2) + 4);
   size_t o_starts = L.take<uint32_t>(N / 2 + 1), o_seeds = L.take<uint32_t>(SC);
   size_t o_seo = L.take<uint32_t>(E + 1), o_steo = L.take<uint32_t>(E + 1);
   size_t o_ssu = L.take<uint32_t>((int64_t)E * S + 1);
