@@ -1376,8 +1376,13 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   const uint32_t c0 = w.ru_off[su * w.R + r_lo], c1 = w.ru_off[su * w.R + r_hi + 1];
   const uint32_t nc = c1 - c0;
   const bool lds = nc <= (uint32_t)kBandCap;
+  // every cluster lies in one band, whose workgroup alone writes its owner
+  // entries: here (LDS maxima copied out at the end) or, for bands above
+  // the LDS capacity, by global atomics on entries this workgroup clears
   if (lds)
     for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
+  else
+    for (uint32_t i = threadIdx.x; i < nc; i += TB) w.owner[c0 + i] = 0ull;
   __syncthreads();
   // one thread per tracklet: the band's eight hit slots are two aligned
   // 16-byte loads (the slot stride is a multiple of four rows)
@@ -1647,7 +1652,6 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_ZERO);
   TPCCA_CHECK(fill_u32(w.flags, 0u, F_COUNT, st));
   TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
-  TPCCA_CHECK(fill_u32((uint32_t*)w.owner, 0u, 2 * w.N, st));
   TPCCA_MARK(PH_COUNT);
   const unsigned nchunk = (unsigned)chunk_cap(w.N, w.E);
   k_count<<<nchunk, TB, 0, st>>>(w);
