@@ -104,7 +104,10 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   w.nb = std::max<int64_t>(1, (N + 255) / 256);
   const int64_t RU = w.RU, SC = w.seed_cap;
   const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(RU, w.nb), SC) + 1;
+  // flags, then the per-event results: one download after the pipeline
+  // (the host staging buffer repeats this placement)
   size_t o_flags = L.take<uint32_t>(F_COUNT);
+  size_t o_res = L.take<int64_t>((int64_t)E * 4);
   size_t o_ruc = L.take<uint32_t>(RU), o_ruo = L.take<uint32_t>(RU + 1);
   size_t o_cc = L.take<uint32_t>(RU), o_cb = L.take<uint32_t>(RU + 1);
   size_t o_grid = L.take<GridParams>(RU);
@@ -129,7 +132,8 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_acl = L.take<uint32_t>(SC), o_occ = L.take<uint32_t>(SC + 1);
   size_t o_rf = L.take<float>(SC * kRf);
   size_t o_tf = L.take<uint32_t>(SC + 1), o_hc = L.take<uint32_t>(SC + 1);
-  size_t o_res = L.take<int64_t>((int64_t)E * 4);
+  // event, output and chunk tables back to back: one upload per call (the
+  // host staging buffer repeats this placement)
   size_t o_ev = L.take<EventIn>(E), o_out = L.take<EventOut>(E);
   size_t o_chunk = L.take<ChunkIn>(chunk_cap(N, E));
   if (base) {
@@ -461,9 +465,8 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   }
   c->hpin_busy = true;
   c->hpin_stream = st;
-  he = hipMemcpyAsync((void*)w.chunk, chunks, sizeof(ChunkIn) * nchunk, hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.ev, ein, sizeof(EventIn) * E, hipMemcpyHostToDevice, st);
-  if (he == hipSuccess) he = hipMemcpyAsync((void*)w.out, eout, sizeof(EventOut) * E, hipMemcpyHostToDevice, st);
+  // the three tables in one copy: same placement on both sides
+  he = hipMemcpyAsync((void*)w.ev, ein, p_chunk + sizeof(ChunkIn) * nchunk, hipMemcpyHostToDevice, st);
   if (he != hipSuccess) return hip_fail(c, he, "table upload");
 
   if (c->tune.use_graph && !c->timing && st != nullptr) {
@@ -490,8 +493,8 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
     he = run_pipeline(w, st, c->timing ? &c->pe : nullptr);
     if (he != hipSuccess) return hip_fail(c, he, "kernel launch");
   }
-  he = hipMemcpyAsync(flags, w.flags, sizeof(uint32_t) * F_COUNT, hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(res, w.ev_res, sizeof(int64_t) * 4 * E, hipMemcpyDeviceToHost, st);
+  // flags and per-event results in one copy: same placement on both sides
+  he = hipMemcpyAsync(flags, w.flags, (p_res - p_flags) + sizeof(int64_t) * 4 * E, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return hip_fail(c, he, "tracking");
   c->hpin_busy = false;
