@@ -105,6 +105,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                 "traffic": measured_traffic(f"k_{dom}"), "kernel_ms": round(dom_ms, 4),
+                "valu_issue_frac": measured_valu_issue(f"k_{dom}"),
                 "algo_bytes_per_launch": algo_bytes}
 
     cpu = None
@@ -159,6 +160,27 @@ def measured_traffic(kernel: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["bytes_per_launch"]
+
+
+def measured_valu_issue(kernel: str):
+    """VALU issue time over traced duration of `kernel` from the committed
+    SQ-counter summary, or None if there is none or the kernel sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "tracking_c3_sq_counters.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    if f"sha256 `{kernel_source_hash()}`" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if cells and cells[0] == kernel and len(cells) >= 7:
+            try:
+                return float(cells[6])
+            except ValueError:
+                return None
+    return None
 
 
 def pmc_summary(folder: str):
