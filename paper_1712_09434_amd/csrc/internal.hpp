@@ -100,6 +100,7 @@ struct Ws {
   tpcca_params P;
   float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
   int tracklet_grid;    // workgroups of the tracklet kernel (0 = automatic)
+  int taps;             // 1 if some event of the call asks for link or start-hit taps
   uint32_t* flags;      // [F_COUNT]
   const ChunkIn* chunk; // [chunk_cap(N, E)] binning chunks, empty entries past the last
   // binning

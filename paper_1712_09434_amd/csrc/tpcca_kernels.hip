@@ -963,13 +963,15 @@ __global__ __launch_bounds__(TB) void k_clean(Ws w) {
       seed = L >= w.P.min_seed_hits;
     }
     w.flag[p] = (uint8_t)((start ? 1 : 0) | (seed ? 2 : 0));
-    const int e = (int)(w.cru[p] / ((uint32_t)w.S * (uint32_t)w.R));
-    const EventOut& O = w.out[e];
-    const uint32_t id = w.cid[p];
-    if (O.dbg_up) O.dbg_up[id] = u >= 0 ? (int32_t)w.cid[u] : -1;
-    if (O.dbg_dn) O.dbg_dn[id] = d >= 0 ? (int32_t)w.cid[d] : -1;
-    if (O.dbg_cup) O.dbg_cup[id] = cu >= 0 ? (int32_t)w.cid[cu] : -1;
-    if (O.dbg_cdn) O.dbg_cdn[id] = cd >= 0 ? (int32_t)w.cid[cd] : -1;
+    if (w.taps) {
+      const int e = (int)(w.cru[p] / ((uint32_t)w.S * (uint32_t)w.R));
+      const EventOut& O = w.out[e];
+      const uint32_t id = w.cid[p];
+      if (O.dbg_up) O.dbg_up[id] = u >= 0 ? (int32_t)w.cid[u] : -1;
+      if (O.dbg_dn) O.dbg_dn[id] = d >= 0 ? (int32_t)w.cid[d] : -1;
+      if (O.dbg_cup) O.dbg_cup[id] = cu >= 0 ? (int32_t)w.cid[cu] : -1;
+      if (O.dbg_cdn) O.dbg_cdn[id] = cd >= 0 ? (int32_t)w.cid[cd] : -1;
+    }
   }
   const uint64_t bs = __ballot(start), bq = __ballot(seed);
   if (lane_id() == 0) { s_cnt[0][threadIdx.x >> 6] = (uint32_t)__popcll(bs); s_cnt[1][threadIdx.x >> 6] = (uint32_t)__popcll(bq); }
@@ -1678,7 +1680,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(scan_u32x2(w.blk_start, w.blk_start, w.blk_seed, w.blk_seed, w.nb, w.scan_tmp, st));
   k_compact<<<nbN, TB, 0, st>>>(w);
   k_ev_offsets<<<blocks_for(w.N / 2 + 2, 4096), TB, 0, st>>>(w);
-  k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
+  if (w.taps) k_start_tap<<<blocks_for(w.N / 2 + 1, 2048), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_TRACKLETS);
   k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);

@@ -58,6 +58,7 @@ struct tpcca_ctx {
     hipStream_t st = nullptr;
     tpcca_params P{};
     int tracklet_grid = 0;
+    int taps = 0;
   } gkey;
   // phase timing
   bool timing = false;
@@ -370,6 +371,9 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   w.tan_a = c->tan_a;
   w.z_max = c->z_max;
   w.tracklet_grid = c->tune.tracklet_grid;
+  w.taps = 0;
+  for (int e = 0; e < E; ++e)
+    if (out[e].dbg_up || out[e].dbg_dn || out[e].dbg_cup || out[e].dbg_cdn || out[e].dbg_start) w.taps = 1;
 
   // staging: host inputs and host outputs
   std::vector<HostOut> ho(E);
@@ -472,6 +476,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   if (c->tune.use_graph && !c->timing && st != nullptr) {
     const bool same = c->gexec && c->gkey.N == N && c->gkey.E == E && c->gkey.arena == c->arena &&
                       c->gkey.st == st && c->gkey.tracklet_grid == c->tune.tracklet_grid &&
+                      c->gkey.taps == w.taps &&
                       std::memcmp(&c->gkey.P, &c->P, sizeof(tpcca_params)) == 0;
     if (!same) {
       if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
@@ -485,7 +490,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
       he = hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0);
       if (he != hipSuccess) { c->gexec = nullptr; return hip_fail(c, he, "graph instantiate"); }
       c->gkey.N = N; c->gkey.E = E; c->gkey.arena = c->arena; c->gkey.st = st;
-      c->gkey.P = c->P; c->gkey.tracklet_grid = c->tune.tracklet_grid;
+      c->gkey.P = c->P; c->gkey.tracklet_grid = c->tune.tracklet_grid; c->gkey.taps = w.taps;
     }
     he = hipGraphLaunch(c->gexec, st);
     if (he != hipSuccess) return hip_fail(c, he, "graph launch");
