@@ -63,6 +63,14 @@ __global__ void k_fill(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) p[i] = v;
 }
 
+// Two ranges cleared by one launch.
+__global__ void k_zero2(uint32_t* __restrict__ p, int64_t n, uint32_t* __restrict__ q, int64_t m) {
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n + m; i += (int64_t)gridDim.x * TB) {
+    if (i < n) p[i] = 0u;
+    else q[i - n] = 0u;
+  }
+}
+
 // Exclusive scans, out[n] = total (out may equal in).  Up to two arrays of
 // the same length are scanned by the same launches (blockIdx.y selects the
 // array): one workgroup each when n <= kScanSmall, else reduce / partials /
@@ -119,6 +127,43 @@ __global__ __launch_bounds__(kScanNT) void k_scan_small(ScanArgs a, int64_t n) {
     carry += tot;
   }
   if (threadIdx.x == 0) out[n32] = carry;
+}
+
+// Row-unit offsets in one workgroup (RU <= kScanSmall): scans the counts
+// into ru_off and the cell capacities (grid_cells(count) + 1, computed here)
+// into cell_base, then clears the counts for their second use as the
+// scatter's fill cursors.
+__global__ __launch_bounds__(kScanNT) void k_scan_rows(Ws w) {
+  const uint32_t n32 = (uint32_t)w.RU;
+  uint32_t carry0 = 0, carry1 = 0;
+  for (uint32_t t0 = 0; t0 < n32; t0 += 4u * kScanNT) {
+    const uint32_t base = t0 + 4u * threadIdx.x;
+    uint32_t v0[4], v1[4], s0 = 0, s1 = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t x = w.ru_count[base + j < n32 ? base + j : 0u];
+      v0[j] = base + j < n32 ? x : 0u;
+      v1[j] = base + j < n32 ? grid_cells(x) + 1u : 0u;
+      s0 += v0[j];
+      s1 += v1[j];
+    }
+    uint32_t tot0, tot1;
+    uint32_t e0 = carry0 + block_excl_scan_big(s0, &tot0);
+    uint32_t e1 = carry1 + block_excl_scan_big(s1, &tot1);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      if (base + j < n32) {
+        w.ru_off[base + j] = e0;
+        w.cell_base[base + j] = e1;
+        w.ru_count[base + j] = 0u;
+      }
+      e0 += v0[j];
+      e1 += v1[j];
+    }
+    carry0 += tot0;
+    carry1 += tot1;
+  }
+  if (threadIdx.x == 0) { w.ru_off[n32] = carry0; w.cell_base[n32] = carry1; }
 }
 
 __global__ __launch_bounds__(TB) void k_scan_reduce(ScanArgs a, int64_t n, uint32_t* __restrict__ part,
@@ -1652,16 +1697,21 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
 #define TPCCA_CHECK(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
 #define TPCCA_MARK(i) do { if (pe) TPCCA_CHECK(hipEventRecord(pe->ev[i], st)); } while (0)
   TPCCA_MARK(PH_ZERO);
-  TPCCA_CHECK(fill_u32(w.flags, 0u, F_COUNT, st));
-  TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
+  k_zero2<<<blocks_for(F_COUNT + w.RU, 4096), TB, 0, st>>>(w.flags, F_COUNT, w.ru_count, w.RU);
+  TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_COUNT);
   const unsigned nchunk = (unsigned)chunk_cap(w.N, w.E);
   k_count<<<nchunk, TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
-  k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);
   TPCCA_MARK(PH_SCAN);
-  TPCCA_CHECK(scan_u32x2(w.ru_count, w.ru_off, w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
-  TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
+  if (w.RU <= kScanSmall) {
+    k_scan_rows<<<1, kScanNT, 0, st>>>(w);
+    TPCCA_CHECK(hipGetLastError());
+  } else {
+    k_cell_caps<<<blocks_for(w.RU), TB, 0, st>>>(w);
+    TPCCA_CHECK(scan_u32x2(w.ru_count, w.ru_off, w.cell_cap, w.cell_base, w.RU, w.scan_tmp, st));
+    TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
+  }
   TPCCA_MARK(PH_SCATTER);
   k_scatter<<<nchunk, TB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
