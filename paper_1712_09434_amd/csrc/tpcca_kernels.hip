@@ -78,7 +78,11 @@ __global__ void k_zero2(uint32_t* __restrict__ p, int64_t n, uint32_t* __restric
 struct ScanArgs {
   const uint32_t* in[2];
   uint32_t* out[2];
+  int ind[2];   // 1: scan the indicator (value > 0) of the input instead of the value
 };
+__device__ __forceinline__ uint32_t scan_in(const ScanArgs& a, int y, uint32_t v) {
+  return a.ind[y] ? (v > 0u ? 1u : 0u) : v;
+}
 constexpr int kScanNT = 1024;                        // threads of a one-workgroup scan
 constexpr int64_t kScanSmall = 4 * 4 * kScanNT;      // at most four tiles of 4 x kScanNT
 
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(kScanNT) void k_scan_small(ScanArgs a, int64_t n) {
     uint32_t v[4], sum = 0;
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) {
-      const uint32_t x = in[base + j < n32 ? base + j : 0u];
+      const uint32_t x = scan_in(a, blockIdx.x, in[base + j < n32 ? base + j : 0u]);
       v[j] = base + j < n32 ? x : 0u;
       sum += v[j];
     }
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(TB) void k_scan_reduce(ScanArgs a, int64_t n, uint3
   const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   uint32_t s = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) if (base + j < n) s += in[base + j];
+  for (int j = 0; j < 4; ++j) if (base + j < n) s += scan_in(a, blockIdx.y, in[base + j]);
   uint32_t tot;
   block_excl_scan(s, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(TB) void k_scan_down(ScanArgs a, int64_t n, const u
   const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x * 4;
   uint32_t v[4], s = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) { v[j] = base + j < n ? in[base + j] : 0u; s += v[j]; }
+  for (int j = 0; j < 4; ++j) { v[j] = base + j < n ? scan_in(a, blockIdx.y, in[base + j]) : 0u; s += v[j]; }
   uint32_t tot;
   uint32_t ex = block_excl_scan(s, &tot) + (blockIdx.x < np ? part[blockIdx.x] : 0u);
 #pragma unroll
@@ -228,13 +232,14 @@ hipError_t scan_arrays(ScanArgs a, int narr, int64_t n, uint32_t* part, hipStrea
 }
 
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st) {
-  ScanArgs a{{in, in}, {out, out}};
+  ScanArgs a{{in, in}, {out, out}, {0, 0}};
   return scan_arrays(a, 1, n, part, st);
 }
 
+// ind0: the first array is scanned as the indicator of its values.
 hipError_t scan_u32x2(const uint32_t* in0, uint32_t* out0, const uint32_t* in1, uint32_t* out1, int64_t n,
-                      uint32_t* part, hipStream_t st) {
-  ScanArgs a{{in0, in1}, {out0, out1}};
+                      uint32_t* part, hipStream_t st, int ind0 = 0) {
+  ScanArgs a{{in0, in1}, {out0, out1}, {ind0, 0}};
   return scan_arrays(a, 2, n, part, st);
 }
 
@@ -1609,14 +1614,6 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
   }
 }
 
-// Output flags of every seed: accepted and fitted.
-__global__ __launch_bounds__(TB) void k_trk_flags(Ws w) {
-  for (int64_t s = (int64_t)blockIdx.x * TB + threadIdx.x; s < w.seed_cap; s += (int64_t)gridDim.x * TB) {
-    const uint32_t c = w.own_cnt[s];
-    w.trk_flag[s] = c > 0 ? 1u : 0u;
-    w.hit_cnt[s] = c;
-  }
-}
 
 // Per-event totals and the capacity check.
 __global__ __launch_bounds__(TB) void k_totals(Ws w) {
@@ -1742,9 +1739,10 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
   k_acc_list<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   k_refit<<<blocks_for(w.seed_cap / 4 + 1, 4096), TB, 0, st>>>(w);
-  k_trk_flags<<<blocks_for(w.seed_cap, 4096), TB, 0, st>>>(w);
   TPCCA_MARK(PH_OUTPUT);
-  TPCCA_CHECK(scan_u32x2(w.trk_flag, w.trk_flag, w.hit_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st));
+  // track offsets (indicator of a fitted track) and hit offsets (owned
+  // count) from the owned counts, by the same launches
+  TPCCA_CHECK(scan_u32x2(w.own_cnt, w.trk_flag, w.own_cnt, w.hit_cnt, w.seed_cap, w.scan_tmp, st, 1));
   k_totals<<<1, TB, 0, st>>>(w);
   k_write<<<blocks_for(w.seed_cap * 16, 1 << 13), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
