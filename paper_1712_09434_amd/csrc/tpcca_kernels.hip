@@ -1650,16 +1650,22 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
   const int64_t nw = (int64_t)gridDim.x * (TB / 64);
   for (int64_t i = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6); i < na; i += nw) {
     const int64_t s = w.acc_list[i];
-    const uint32_t t0 = w.trk_flag[s];
-    if (w.trk_flag[s + 1] == t0) continue;
+    // everything indexed by s in one round trip
+    const uint32_t t0 = w.trk_flag[s], t1 = w.trk_flag[s + 1];
+    const uint32_t c0 = w.hit_cnt[s], c1 = w.hit_cnt[s + 1];
     const int32_t h0 = (int32_t)w.seeds[s];
+    if (t1 == t0) continue;
     const uint32_t vsec = w.cru[h0] / (uint32_t)w.R;
     const int e = (int)(vsec / (uint32_t)w.S);
     const EventOut& O = w.out[e];
-    const uint32_t sb = w.seed_ev_off[e];
-    const uint32_t j = t0 - w.trk_flag[sb];
-    const uint32_t o = w.hit_cnt[s] - w.hit_cnt[sb];
-    const uint32_t n = w.hit_cnt[s + 1] - w.hit_cnt[s];
+    // offsets within the event (a single event starts at zero)
+    uint32_t j = t0, o = c0;
+    if (w.E > 1) {
+      const uint32_t sb = w.seed_ev_off[e];
+      j = t0 - w.trk_flag[sb];
+      o = c0 - w.hit_cnt[sb];
+    }
+    const uint32_t n = c1 - c0;
     const float* rf = w.rf + s * kRf;
     if (lane < 5) O.p[j * 5 + lane] = rf[1 + lane];
     else if (lane < 20) O.cov[j * 15 + (lane - 5)] = rf[6 + (lane - 5)];
