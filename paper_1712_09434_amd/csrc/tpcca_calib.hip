@@ -577,8 +577,12 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   }
 }
 
-__global__ __launch_bounds__(TB) void k_cal_adjoint(CalWs c) {
-  for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < c.T; t += (int64_t)gridDim.x * TB) adjoint_track(c, t);
+// One lane per track, one wave per workgroup: a call has a few thousand
+// tracks, so this spreads their waves over as many compute units (and their
+// vector memory paths) as there are waves, rather than four to a unit.
+constexpr int TA = 64;
+__global__ __launch_bounds__(TA) void k_cal_adjoint(CalWs c) {
+  for (int64_t t = (int64_t)blockIdx.x * TA + threadIdx.x; t < c.T; t += (int64_t)gridDim.x * TA) adjoint_track(c, t);
 }
 
 // ------------------------------------------ 3. per-track parameter partials
@@ -724,8 +728,8 @@ hipError_t run_calib(const CalWs& c, hipStream_t st) {
   k_cal_zero<<<1, 64, 0, st>>>(c);
   const unsigned bh = (unsigned)std::min<int64_t>(std::max<int64_t>((c.H + TB - 1) / TB, 1), 65536);
   k_cal_hits<<<bh, TB, 0, st>>>(c);
-  const unsigned bt = (unsigned)std::min<int64_t>(std::max<int64_t>((c.T + TB - 1) / TB, 1), 65536);
-  k_cal_adjoint<<<bt, TB, 0, st>>>(c);
+  const unsigned bt = (unsigned)std::min<int64_t>(std::max<int64_t>((c.T + TA - 1) / TA, 1), 65536);
+  k_cal_adjoint<<<bt, TA, 0, st>>>(c);
   if (c.T > 0) k_cal_partials<<<dim3((unsigned)c.T), 64, 0, st>>>(c);
   const int64_t nchunk = (c.T + kChunk - 1) / kChunk;
   if (nchunk > 0) k_cal_chunks<<<dim3((unsigned)nchunk), TB, 0, st>>>(c);
