@@ -156,7 +156,8 @@ typedef struct {
  * every that many hit steps by the gradient's forward pass (1..160, default
  * 160); the reverse sweep recomputes the states of each segment but the last
  * from its checkpoint, so at the default (at least a track's step count) no
- * state is recomputed, for 188 x 80 bytes of state per track;
+ * state is recomputed, for 348 x 80 bytes of state per track (each hit
+ * step keeps its state before and after the transport);
  * tracklet_grid: workgroups of the persistent tracklet kernel, 0 =
  * automatic; use_graph: 1 = capture the kernel sequence of a tracking call
  * in a hipGraph the first time a workspace shape is seen on a non-null

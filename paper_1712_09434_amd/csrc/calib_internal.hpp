@@ -15,8 +15,9 @@ struct CalWs {
   Model m;
   float sv2, st2;          // vertex and external tan(lambda) variances
   int K;                   // checkpoint stride (hit steps)
-  int nck, nseg;           // checkpoints and state slots per track: K for a segment of hit
-                           // steps, then kTail for the steps to the vertex
+  int nck, nseg;           // checkpoints and state slots per track: 2K for a segment of hit
+                           // steps (each step's state before and after its transport),
+                           // then kTail for the steps to the vertex
   int64_t T, H, NC;        // tracks, hits, clusters
   const int32_t* hit_off;
   const uint32_t* hit_id;

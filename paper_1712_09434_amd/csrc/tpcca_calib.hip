@@ -413,7 +413,9 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   if (!(fabsf(sdir) < m.sin_max)) return;
   float* ck = c.ckpt + t * (int64_t)c.nck * 20;
   float* sg = c.seg + t * (int64_t)c.nseg * 20;
-  float* tl = sg + (int64_t)c.K * 20;   // the steps to the vertex
+  // a hit step's slot holds its state before and after the transport, so
+  // the reverse sweep takes the transported state as kept, not recomputed
+  float* tl = sg + (int64_t)c.K * 40;   // the steps to the vertex
   float chi2 = 0.f;
   bool ok = true;
   float xc = c.hx[j0];
@@ -425,11 +427,12 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   float nx = c.hx[jk(1)], ny = c.hy[jk(1)], nz = c.hz[jk(1)];
   for (int k = 1; k < nh; ++k) {
     if ((k - 1) % c.K == 0) save(ck + ((k - 1) / c.K) * 20, p, C);
-    if (k >= k1_last) save(sg + (k - k1_last) * 20, p, C);
+    if (k >= k1_last) save(sg + (k - k1_last) * 40, p, C);
     const float hx = nx, hy = ny, hz = nz;
     const int64_t jn = jk(k + 1 < nh ? k + 1 : k);
     nx = c.hx[jn]; ny = c.hy[jn]; nz = c.hz[jn];
     if (!transport(p, C, xc, hx, m)) { ok = false; break; }
+    if (k >= k1_last) save(sg + (k - k1_last) * 40 + 20, p, C);
     update(p, C, hy, hz, m, chi2);
     xc = hx;
   }
@@ -516,11 +519,12 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     float dummy = 0.f;
     float nx = c.hx[jk(k1)], ny = c.hy[jk(k1)], nz = c.hz[jk(k1)];
     for (int k = k1; k <= k2 && k1 != k1_last; ++k) {
-      save(sg + (k - k1) * 20, q, Q);
+      save(sg + (k - k1) * 40, q, Q);
       const float hx = nx, hy = ny, hz = nz;
       const int64_t jn = jk(k < k2 ? k + 1 : k);
       nx = c.hx[jn]; ny = c.hy[jn]; nz = c.hz[jn];
       transport(q, Q, xv, hx, m);
+      save(sg + (k - k1) * 40 + 20, q, Q);
       update(q, Q, hy, hz, m, dummy);
       xv = hx;
     }
@@ -528,27 +532,23 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     // hit are still zero (set with the calibrated hits) when its step is
     // reached, each hit ending one step, so they are written, not updated
     float xt_n = c.hx[jk(k2)], yt_n = c.hy[jk(k2)], zt_n = c.hz[jk(k2)], xf_n = c.hx[jk(k2 - 1)];
-    // the saved state of the step is loaded one step ahead as well
-    float a_n[5], A_n[15];
-    load(sg + (k2 - k1) * 20, a_n, A_n);
+    // the saved states of the step are loaded one step ahead as well
+    float a_n[5], A_n[15], b_n[5], B_n[15];
+    load(sg + (k2 - k1) * 40, a_n, A_n);
+    load(sg + (k2 - k1) * 40 + 20, b_n, B_n);
     for (int k = k2; k >= k1; --k) {
       const int64_t j = jk(k);
-      float a[5], A[15];
+      float a[5], A[15], b[5], B[15];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) a[i] = a_n[i];
+      for (int i = 0; i < 5; ++i) { a[i] = a_n[i]; b[i] = b_n[i]; }
 #pragma unroll
-      for (int i = 0; i < 15; ++i) A[i] = A_n[i];
-      load(sg + (k > k1 ? k - 1 - k1 : 0) * 20, a_n, A_n);
+      for (int i = 0; i < 15; ++i) { A[i] = A_n[i]; B[i] = B_n[i]; }
+      load(sg + (k > k1 ? k - 1 - k1 : 0) * 40, a_n, A_n);
+      load(sg + (k > k1 ? k - 1 - k1 : 0) * 40 + 20, b_n, B_n);
       const float xt = xt_n, yt = yt_n, zt = zt_n, xf = xf_n;
       // the next step (k - 1) ends on hit k - 1 and starts from hit k - 2
       const int64_t jq = jk(k - 1), jr = jk(k >= 2 ? k - 2 : 0);
       xt_n = xf; yt_n = c.hy[jq]; zt_n = c.hz[jq]; xf_n = c.hx[jr];
-      float b[5], B[15];
-#pragma unroll
-      for (int i = 0; i < 5; ++i) b[i] = a[i];
-#pragma unroll
-      for (int i = 0; i < 15; ++i) B[i] = A[i];
-      transport(b, B, xf, xt, m);
       float gm[2] = {0.f, 0.f};
       update_adjoint(b, B, yt, zt, m.vy, m.vz, gP, G, gm);
       c.gy[j] = 0.0f + gm[0];
@@ -724,7 +724,7 @@ hipError_t run_calib(const CalWs& c, hipStream_t st) {
                         c.seg, c.chunk, c.out, c.ndf_sum, c.err};
   for (const void* p : need)
     if (!p) return hipErrorInvalidValue;
-  if (c.K < 1 || c.nseg < c.K + kTail || c.nck < (c.R - 1 + c.K - 1) / c.K + 1) return hipErrorInvalidValue;
+  if (c.K < 1 || c.nseg < 2 * c.K + kTail || c.nck < (c.R - 1 + c.K - 1) / c.K + 1) return hipErrorInvalidValue;
   k_cal_zero<<<1, 64, 0, st>>>(c);
   const unsigned bh = (unsigned)std::min<int64_t>(std::max<int64_t>((c.H + TB - 1) / TB, 1), 65536);
   k_cal_hits<<<bh, TB, 0, st>>>(c);

@@ -643,7 +643,7 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   if (H < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
   const int K = c->tune.ckpt_every;
   const int nck = (c->R - 1 + K - 1) / K + 1;
-  const int nseg = K + kTail;
+  const int nseg = 2 * K + kTail;
   const int64_t nchunk = (T + kChunk - 1) / kChunk;
   const int nq = S * kNPar + 1;
   // scratch layout

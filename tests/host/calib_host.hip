@@ -45,7 +45,7 @@ int main(int argc, char** argv) {
   c.m.kfac = -((float)2.99792458e-3) * 0.5f;
   c.m.sin_max = 0.99f; c.m.vy = 0.1f * 0.1f; c.m.vz = 0.15f * 0.15f;
   c.sv2 = 0.01f * 0.01f; c.st2 = 1e-3f * 1e-3f;
-  c.K = K; c.nck = (c.R - 1 + K - 1) / K + 1; c.nseg = K + kTail;
+  c.K = K; c.nck = (c.R - 1 + K - 1) / K + 1; c.nseg = 2 * K + kTail;
   c.T = (int64_t)hoff.size() - 1; c.H = (int64_t)hid.size(); c.NC = (int64_t)cx.size();
   c.hit_off = hoff.data(); c.hit_id = hid.data(); c.k_prior = kp.data(); c.ext_tgl = ext.data();
   c.use_vertex = uv.data(); c.cx = cx.data(); c.cy = cy.data(); c.cz = cz.data(); c.csec = cs.data();
