@@ -208,7 +208,9 @@ int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* ev
  * its ndf and d chi2/d theta (FP32 per track, FP64 deterministic reduction).
  * tracks->hit_id / hit_off / k_prior / ext_tgl / use_vertex are read for
  * tracks->n_tracks tracks; all of them, the clusters, calib and grad arrays
- * must share one `mem` kind per struct. */
+ * must share one `mem` kind per struct.  Device gradient arrays are written
+ * by the kernels, so after an error found on the device (a hit id or sector
+ * out of range, more hits than pad rows) they may hold partial values. */
 int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_calib* calib,
                      tpcca_grad* out);
 

@@ -49,6 +49,9 @@ struct CalWs {
   float* seg;              // [T][nseg][20]
   double* chunk;           // [nchunk][S*66 + 1]
   double* out;             // [S*66 + 1]: per sector (delta, tau, map[64]), then chi2
+  double* g_dl;            // device gradient outputs [S], [S], [S][64]; null for host outputs
+  double* g_tau;
+  double* g_map;
   unsigned long long* ndf_sum;
   uint32_t* err;
 };

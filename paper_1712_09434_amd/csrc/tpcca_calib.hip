@@ -707,6 +707,12 @@ __global__ __launch_bounds__(TB) void k_cal_final(CalWs c, int64_t nchunk) {
     double acc = 0.0;
     for (int64_t ch = 0; ch < nchunk; ++ch) acc += c.chunk[ch * nq + q];
     c.out[q] = acc;
+    if (c.g_dl && q < nq - 1) {
+      const int s = q / kNPar, p = q - s * kNPar;
+      if (p == 0) c.g_dl[s] = acc;
+      else if (p == 1) c.g_tau[s] = acc;
+      else c.g_map[(int64_t)s * 64 + (p - 2)] = acc;
+    }
   }
 }
 

@@ -25,6 +25,7 @@ struct tpcca_ctx {
   int S = 0, R = 0;
   float tan_a = 0.f, z_max = 0.f, bz = 0.f;
   float* row_x_d = nullptr;
+  float row_x_first = 0.f, row_x_last = 0.f;   // the map's radial range
   tpcca_params P{};
   std::string err;
   // arena
@@ -270,6 +271,8 @@ int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out)
   c->S = g->n_sectors; c->R = g->n_rows;
   c->tan_a = g->tan_half_angle; c->z_max = g->z_max; c->bz = f->bz_tesla;
   tpcca_default_params(&c->P);
+  c->row_x_first = g->row_x[0];
+  c->row_x_last = g->row_x[g->n_rows - 1];
   e = hipMalloc((void**)&c->row_x_d, sizeof(float) * g->n_rows);
   if (e == hipSuccess) e = hipMemcpy(c->row_x_d, g->row_x, sizeof(float) * g->n_rows, hipMemcpyHostToDevice);
   if (e != hipSuccess) { (void)hipGetLastError(); if (c->row_x_d) (void)hipFree(c->row_x_d); delete c; return TPCCA_E_DEVICE; }
@@ -623,6 +626,17 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   hipError_t he = hipSetDevice(c->device);
   if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
   hipStream_t st = (hipStream_t)k.stream;
+  // the hit count and the results are read back through pinned host memory
+  // (a call that failed after queueing copies may have left them in flight)
+  if (c->hpin_busy) {
+    (void)hipStreamSynchronize(c->hpin_stream);
+    (void)hipGetLastError();
+    c->hpin_busy = false;
+  }
+  const int nq = S * kNPar + 1;
+  const size_t r_bytes = al(sizeof(double) * nq) + al(sizeof(unsigned long long)) + sizeof(uint32_t);
+  int rc = ensure_pinned(c, r_bytes);
+  if (rc != TPCCA_OK) return rc;
   // number of hits
   int32_t H32 = 0;
   if (T > 0) {
@@ -630,11 +644,14 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
       H32 = t->hit_off[T];
       if (t->hit_off[0] != 0) return fail(c, TPCCA_E_INVALID, "hit_off[0] must be 0");
     } else {
-      int32_t ends[2];
+      int32_t* ends = (int32_t*)c->hpin;
+      c->hpin_busy = true;
+      c->hpin_stream = st;
       he = hipMemcpyAsync(&ends[0], t->hit_off, 4, hipMemcpyDeviceToHost, st);
       if (he == hipSuccess) he = hipMemcpyAsync(&ends[1], t->hit_off + T, 4, hipMemcpyDeviceToHost, st);
       if (he == hipSuccess) he = hipStreamSynchronize(st);
       if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
+      c->hpin_busy = false;
       if (ends[0] != 0) return fail(c, TPCCA_E_INVALID, "hit_off[0] must be 0");
       H32 = ends[1];
     }
@@ -645,7 +662,6 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   const int nck = (c->R - 1 + K - 1) / K + 1;
   const int nseg = 2 * K + kTail;
   const int64_t nchunk = (T + kChunk - 1) / kChunk;
-  const int nq = S * kNPar + 1;
   // scratch layout
   Layout L;
   size_t o_hx = L.take<float>(H), o_hy = L.take<float>(H), o_hz = L.take<float>(H);
@@ -680,14 +696,8 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   w.st2 = c->P.sigma_tgl * c->P.sigma_tgl;
   w.K = K; w.nck = nck; w.nseg = nseg;
   w.T = T; w.H = H; w.NC = NC;
-  {
-    // x_first and x_span of the map's radial coordinate
-    std::vector<float> rx(c->R);
-    he = hipMemcpy(rx.data(), c->row_x_d, sizeof(float) * c->R, hipMemcpyDeviceToHost);
-    if (he != hipSuccess) return hip_fail(c, he, "row table");
-    w.x_first = rx[0];
-    w.x_span = rx[c->R - 1] - rx[0];
-  }
+  w.x_first = c->row_x_first;
+  w.x_span = c->row_x_last - c->row_x_first;
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0 || !src) return hipSuccess;
     return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, st);
@@ -736,36 +746,30 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   w.ckpt = (float*)(b + o_ck); w.seg = (float*)(b + o_sg);
   w.chunk = (double*)(b + o_chunk); w.out = (double*)(b + o_out);
   w.ndf_sum = (unsigned long long*)(b + o_ndf); w.err = (uint32_t*)(b + o_err);
+  // device gradient arrays are written by the reduction itself
+  if (g->mem == TPCCA_MEM_DEVICE) { w.g_dl = g->d_drift_scale; w.g_tau = g->d_time_offset; w.g_map = g->d_map; }
   he = run_calib(w, st);
   if (he != hipSuccess) return hip_fail(c, he, "gradient kernels");
-  std::vector<double> out(nq);
-  unsigned long long ndf = 0;
-  uint32_t err = 0;
-  he = hipMemcpyAsync(out.data(), w.out, sizeof(double) * nq, hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(&ndf, w.ndf_sum, 8, hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(&err, w.err, 4, hipMemcpyDeviceToHost, st);
+  // sums, ndf and the error word in one copy (adjacent in the layout)
+  c->hpin_busy = true;
+  c->hpin_stream = st;
+  he = hipMemcpyAsync(c->hpin, w.out, r_bytes, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return hip_fail(c, he, "gradient");
+  c->hpin_busy = false;
+  const double* out = (const double*)c->hpin;
+  const unsigned long long ndf = *(const unsigned long long*)(c->hpin + (o_ndf - o_out));
+  const uint32_t err = *(const uint32_t*)(c->hpin + (o_err - o_out));
   if (err & 1u) return fail(c, TPCCA_E_INVALID, "hit id or sector out of range");
   if (err & 2u) return fail(c, TPCCA_E_INVALID, "a track has more hits than pad rows");
-  std::vector<double> gd(S), gt(S), gm((size_t)S * 64);
-  for (int s = 0; s < S; ++s) {
-    gd[s] = out[s * kNPar + 0];
-    gt[s] = out[s * kNPar + 1];
-    for (int q = 0; q < 64; ++q) gm[(size_t)s * 64 + q] = out[s * kNPar + 2 + q];
-  }
   g->chi2 = out[S * kNPar];
   g->ndf = (int64_t)ndf;
   if (g->mem == TPCCA_MEM_HOST) {
-    std::memcpy(g->d_drift_scale, gd.data(), 8 * S);
-    std::memcpy(g->d_time_offset, gt.data(), 8 * S);
-    std::memcpy(g->d_map, gm.data(), 8 * 64 * (size_t)S);
-  } else {
-    he = hipMemcpyAsync(g->d_drift_scale, gd.data(), 8 * S, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipMemcpyAsync(g->d_time_offset, gt.data(), 8 * S, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipMemcpyAsync(g->d_map, gm.data(), 8 * 64 * (size_t)S, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) return hip_fail(c, he, "gradient download");
+    for (int s = 0; s < S; ++s) {
+      g->d_drift_scale[s] = out[s * kNPar + 0];
+      g->d_time_offset[s] = out[s * kNPar + 1];
+      for (int q = 0; q < 64; ++q) g->d_map[(size_t)s * 64 + q] = out[s * kNPar + 2 + q];
+    }
   }
   return TPCCA_OK;
 }
