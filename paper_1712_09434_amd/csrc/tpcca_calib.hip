@@ -616,7 +616,7 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     const float kd = l == 0 ? -side : side * (1.0f + dl);
     // basis product at hit i+1 (the next hit outward), carried down the loop
     float w_next = 0.f;
-#pragma unroll 4
+#pragma unroll 8
     for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
       const int32_t sp = c.bsp[j];
@@ -687,13 +687,35 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
   __syncthreads();
   const int nq = c.S * kNPar + 1;
   double* out = c.chunk + (int64_t)blockIdx.x * nq;
+  // the terms are loaded kU at a time (indices clamped into the list) and
+  // added one by one in list order, so the loads of a batch are in flight
+  // together while the sum is the same as the plain sequential loop
+  constexpr int kU = 16;
   for (int q = threadIdx.x; q < nq; q += TB) {
     double acc = 0.0;
     if (q == c.S * kNPar) {
-      for (int i = 0; i < nt; ++i) if (s_sec[i] >= 0) acc += (double)c.part[(t0 + i) * kPart + 66];
+      for (int i = 0; i < nt; i += kU) {
+        float v[kU];
+        bool ok[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int iu = i + u < nt ? i + u : i;
+          ok[u] = i + u < nt && s_sec[iu] >= 0;
+          v[u] = c.part[(t0 + iu) * kPart + 66];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc = ok[u] ? acc + (double)v[u] : acc;
+      }
     } else {
       const int s = q / kNPar, p = q % kNPar;
-      for (int k = s_first[s]; k < s_first[s + 1]; ++k) acc += (double)c.part[(t0 + s_list[k]) * kPart + p];
+      const int k0 = s_first[s], k1 = s_first[s + 1];
+      for (int k = k0; k < k1; k += kU) {
+        float v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = c.part[(t0 + s_list[k + u < k1 ? k + u : k]) * kPart + p];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc = k + u < k1 ? acc + (double)v[u] : acc;
+      }
     }
     out[q] = acc;
   }
