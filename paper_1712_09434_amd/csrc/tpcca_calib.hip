@@ -647,7 +647,9 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
   // of the whole chunk
   __shared__ int s_list[kChunk];
   __shared__ int s_first[kMaxSectors + 1];
+  __shared__ unsigned long long s_ndf;
   const int64_t t0 = (int64_t)blockIdx.x * kChunk;
+  if (threadIdx.x == 0) s_ndf = 0ull;
   const int64_t nt = (c.T - t0) < kChunk ? (c.T - t0) : (int64_t)kChunk;
   for (int i = threadIdx.x; i < kChunk; i += TB) {
     int s = -1;
@@ -719,8 +721,13 @@ __global__ __launch_bounds__(TB) void k_cal_chunks(CalWs c) {
     }
     out[q] = acc;
   }
+  // ndf: the chunk's integer sum first, then one global atomic per chunk
+  unsigned long long nd = 0ull;
   for (int i = threadIdx.x; i < nt; i += TB)
-    if (c.tflag[t0 + i] > 0) atomicAdd(c.ndf_sum, (unsigned long long)c.tndf[t0 + i]);
+    if (c.tflag[t0 + i] > 0) nd += (unsigned long long)c.tndf[t0 + i];
+  if (nd) atomicAdd(&s_ndf, nd);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_ndf) atomicAdd(c.ndf_sum, s_ndf);
 }
 
 __global__ __launch_bounds__(TB) void k_cal_final(CalWs c, int64_t nchunk) {
