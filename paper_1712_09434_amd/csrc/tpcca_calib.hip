@@ -442,11 +442,6 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
   const bool ue = uv && c.ext_tgl;
   int flag = 1;
   int nsub = 0;
-  float last_p[5], last_C[15];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) last_p[i] = p[i];
-#pragma unroll
-  for (int i = 0; i < 15; ++i) last_C[i] = C[i];
   const float x_last = xc;
   if (uv) {
     nsub = (int)ceilf(x_last / 10.0f);
@@ -456,13 +451,16 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
     for (int i = 0; i < 5; ++i) q[i] = p[i];
 #pragma unroll
     for (int i = 0; i < 15; ++i) Q[i] = C[i];
+    // each pre-step state of the tail is kept for the reverse sweep
     float xv = x_last;
     for (int s = 0; vok && s < nsub; ++s) {
+      save(tl + s * 20, q, Q);
       const float xt = 10.0f * (float)(nsub - 1 - s);
       if (!transport(q, Q, xv, xt, m)) { vok = false; break; }
       xv = xt;
     }
     if (vok) {
+      save(tl + nsub * 20, q, Q);                  // before the vertex update
       float c2 = chi2;
       update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, c2);
       if (ue) update1(q, Q, 3, c.ext_tgl[t], c.st2, c2);
@@ -478,20 +476,9 @@ __host__ __device__ inline void adjoint_track(const CalWs& c, int64_t t) {
 #pragma unroll
   for (int i = 0; i < 15; ++i) G[i] = 0.f;
   if (flag == 2) {
-    // recompute the tail, keeping each pre-step state
+    // the tail's states were kept by the forward pass
     float q[5], Q[15];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) q[i] = last_p[i];
-#pragma unroll
-    for (int i = 0; i < 15; ++i) Q[i] = last_C[i];
-    float xv = x_last;
-    for (int s = 0; s < nsub; ++s) {
-      save(tl + s * 20, q, Q);
-      const float xt = 10.0f * (float)(nsub - 1 - s);
-      transport(q, Q, xv, xt, m);
-      xv = xt;
-    }
-    save(tl + nsub * 20, q, Q);                    // before the vertex update
+    load(tl + nsub * 20, q, Q);
     if (ue) {
       float dummy = 0.f;
       update(q, Q, 0.0f, 0.0f, Model{m.kfac, m.sin_max, c.sv2, c.sv2}, dummy);
