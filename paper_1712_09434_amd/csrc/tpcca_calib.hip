@@ -364,17 +364,18 @@ __host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
   c.bva[j] = make_float4(Na[0], Na[1], Na[2], Na[3]);
   c.bvb[j] = make_float4(Nb[0], Nb[1], Nb[2], Nb[3]);
   c.bsp[j] = fa | (fb << 8) | (1 << 16);
-  float Ba[8], Bb[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) { Ba[i] = 0.f; Bb[i] = 0.f; }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) { Ba[fa + i] = Na[i]; Bb[fb + i] = Nb[i]; }
-  const float* cm = c.map + s * 64;
+  // sum over a of B_a (sum over b of c_ab B_b), both in ascending order,
+  // over the 4 x 4 window where the basis is non-zero: the terms left out
+  // are products with an exact zero, and adding a zero to these sums (which
+  // start at +0 and so are never -0) leaves them unchanged for a finite map
+  const float* cm = c.map + s * 64 + fa * 8 + fb;
   float acc = 0.f;
-  for (int a = 0; a < 8; ++a) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
     float ra = 0.f;
-    for (int b = 0; b < 8; ++b) ra += cm[a * 8 + b] * Bb[b];
-    acc += Ba[a] * ra;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ra += cm[i * 8 + k] * Nb[k];
+    acc += Na[i] * ra;
   }
   c.hx[j] = x + acc;
   c.hy[j] = y;
