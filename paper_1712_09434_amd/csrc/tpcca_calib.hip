@@ -40,9 +40,12 @@ __host__ __device__ __forceinline__ D3 operator*(float b, D3 a) { return D3{b * 
 __host__ __device__ __forceinline__ D3 operator+(D3 a, float b) { return D3{a.v + b, a.d0, a.d1, a.d2}; }
 __host__ __device__ __forceinline__ D3 operator+(float b, D3 a) { return D3{b + a.v, a.d0, a.d1, a.d2}; }
 __host__ __device__ __forceinline__ D3 operator-(float b, D3 a) { return D3{b - a.v, -a.d0, -a.d1, -a.d2}; }
+// The value is the rounded quotient; the three derivative parts share one
+// reciprocal of the denominator (each within an ulp of its own quotient).
 __host__ __device__ __forceinline__ D3 operator/(D3 a, D3 b) {
   const float q = a.v / b.v;
-  return D3{q, (a.d0 - q * b.d0) / b.v, (a.d1 - q * b.d1) / b.v, (a.d2 - q * b.d2) / b.v};
+  const float r = 1.0f / b.v;
+  return D3{q, (a.d0 - q * b.d0) * r, (a.d1 - q * b.d1) * r, (a.d2 - q * b.d2) * r};
 }
 __host__ __device__ __forceinline__ D3 dsqrt(D3 a) {
   const float s = sqrtf(a.v);
