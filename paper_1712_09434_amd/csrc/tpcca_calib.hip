@@ -40,11 +40,12 @@ __host__ __device__ __forceinline__ D3 operator*(float b, D3 a) { return D3{b * 
 __host__ __device__ __forceinline__ D3 operator+(D3 a, float b) { return D3{a.v + b, a.d0, a.d1, a.d2}; }
 __host__ __device__ __forceinline__ D3 operator+(float b, D3 a) { return D3{b + a.v, a.d0, a.d1, a.d2}; }
 __host__ __device__ __forceinline__ D3 operator-(float b, D3 a) { return D3{b - a.v, -a.d0, -a.d1, -a.d2}; }
-// The value is the rounded quotient; the three derivative parts share one
-// reciprocal of the denominator (each within an ulp of its own quotient).
+// The value and the three derivative parts share one reciprocal of the
+// denominator (each within an ulp of its own quotient; these duals feed
+// the adjoint only, never a state or a decision).
 __host__ __device__ __forceinline__ D3 operator/(D3 a, D3 b) {
-  const float q = a.v / b.v;
   const float r = 1.0f / b.v;
+  const float q = a.v * r;
   return D3{q, (a.d0 - q * b.d0) * r, (a.d1 - q * b.d1) * r, (a.d2 - q * b.d2) * r};
 }
 __host__ __device__ __forceinline__ D3 dsqrt(D3 a) {
@@ -182,7 +183,8 @@ __host__ __device__ void update_adjoint(const float P[5], const float Cp[15], fl
   const float r0 = my - P[0], r1 = mz - P[1];
   const float S00 = Cp[0] + vy, S01 = Cp[1], S11 = Cp[5] + vz;
   const float det = S00 * S11 - S01 * S01;
-  const float W00 = S11 / det, W01 = -S01 / det, W11 = S00 / det;
+  const float idet = 1.0f / det;
+  const float W00 = S11 * idet, W01 = -S01 * idet, W11 = S00 * idet;
   float K[5][2];
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
