@@ -48,14 +48,26 @@ __host__ __device__ __forceinline__ D3 operator/(D3 a, D3 b) {
   const float q = a.v * r;
   return D3{q, (a.d0 - q * b.d0) * r, (a.d1 - q * b.d1) * r, (a.d2 - q * b.d2) * r};
 }
+// Square root of a dual: the hardware root on the device (within an ulp;
+// these duals feed the adjoint only), the library root on the host.
 __host__ __device__ __forceinline__ D3 dsqrt(D3 a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float s = __builtin_amdgcn_sqrtf(a.v);
+#else
   const float s = sqrtf(a.v);
+#endif
   const float h = 0.5f / s;
   return D3{s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
+// Reciprocal of a dual, for a denominator shared by several quotients.
+__host__ __device__ __forceinline__ D3 dinv(D3 b) {
+  const float r = 1.0f / b.v;
+  const float m = -(r * r);
+  return D3{r, m * b.d0, m * b.d1, m * b.d2};
+}
 
-// The transport's scalar chain (same expressions as the tracking transport)
-// in dual numbers over (s0, k, dx): the chord rise dy, the path l and the
+// The transport's scalar chain (the tracking transport's expressions, its
+// quotients by shared reciprocals) in dual numbers over (s0, k, dx): the chord rise dy, the path l and the
 // Jacobian entries a = d dy/d s0, b = d dy/d k, ls = d l/d s0,
 // lk = d l/d k, each with its derivatives along (s0, k, dx).
 struct TDer { D3 dy, l, a, b, ls, lk; };
@@ -70,7 +82,8 @@ __host__ __device__ __forceinline__ TDer transport_duals(float s0v, float kv, fl
   const D3 c0 = dsqrt(1.0f - s0 * s0);
   const D3 c1 = dsqrt(1.0f - s1 * s1);
   const D3 ss = s0 + s1, cc = c0 + c1;
-  const D3 tn = ss / cc;
+  const D3 icc = dinv(cc);
+  const D3 tn = ss * icc;
   r.dy = dx * tn;
   D3 d = dsqrt(dx * dx + r.dy * r.dy);
   if (dxv < 0.0f) d = -d;
@@ -80,12 +93,13 @@ __host__ __device__ __forceinline__ TDer transport_duals(float s0v, float kv, fl
   const D3 gp = u * (B1 + u2 * (B2 + u2 * (B3 + u2 * B4)));
   r.l = d * g;
   const D3 t0 = s0 / c0, t1 = s1 / c1;
-  const D3 dtn_ds = (2.0f + tn * (t0 + t1)) / cc;
-  const D3 dtn_dk = (f * (1.0f + tn * t1)) / cc;
+  const D3 dtn_ds = (2.0f + tn * (t0 + t1)) * icc;
+  const D3 dtn_dk = (f * (1.0f + tn * t1)) * icc;
   r.a = dx * dtn_ds;
   r.b = dx * dtn_dk;
-  const D3 dd_ds = (r.dy * r.a) / d;
-  const D3 dd_dk = (r.dy * r.b) / d;
+  const D3 id = dinv(d);
+  const D3 dd_ds = (r.dy * r.a) * id;
+  const D3 dd_dk = (r.dy * r.b) * id;
   const D3 du_ds = (kap * dd_ds) * 0.5f;
   const D3 du_dk = (kfac * d + kap * dd_dk) * 0.5f;
   r.ls = dd_ds * g + (d * gp) * du_ds;
