@@ -10,8 +10,9 @@
 //   1. calibrate the clusters of every hit (FP32);
 //   2. one lane per track: forward Kalman refit (outermost hit first, q/pT
 //      prior, then the primary vertex as a measured point and an external
-//      tan(lambda)), checkpointing the state every K steps; then a
-//      hand-written reverse sweep that recomputes each segment from its
+//      tan(lambda)), checkpointing the state every K steps and keeping the
+//      last segment's and the vertex steps' states; then a hand-written
+//      reverse sweep that recomputes each earlier segment from its
 //      checkpoint and propagates adjoints through every update and transport
 //      (second derivatives of the transport by 3-direction dual numbers);
 //   3. per-track FP32 partial derivatives of the 66 parameters of its sector;
