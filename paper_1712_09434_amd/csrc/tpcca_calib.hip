@@ -49,15 +49,17 @@ __host__ __device__ __forceinline__ D3 operator/(D3 a, D3 b) {
   const float q = a.v * r;
   return D3{q, (a.d0 - q * b.d0) * r, (a.d1 - q * b.d1) * r, (a.d2 - q * b.d2) * r};
 }
-// Square root of a dual: the hardware root on the device (within an ulp;
-// these duals feed the adjoint only), the library root on the host.
+// Square root of a dual: the hardware root and reciprocal root on the
+// device (each within an ulp; these duals feed the adjoint only), the
+// library root and a division on the host.
 __host__ __device__ __forceinline__ D3 dsqrt(D3 a) {
 #if defined(__HIP_DEVICE_COMPILE__)
   const float s = __builtin_amdgcn_sqrtf(a.v);
+  const float h = 0.5f * __builtin_amdgcn_rsqf(a.v);
 #else
   const float s = sqrtf(a.v);
-#endif
   const float h = 0.5f / s;
+#endif
   return D3{s, a.d0 * h, a.d1 * h, a.d2 * h};
 }
 // Reciprocal of a dual, for a denominator shared by several quotients.
