@@ -76,6 +76,7 @@ def lib():
         L.orc_transport.restype = C.c_int
         L.orc_kf_update.argtypes = [C.c_int, dp, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                     dp, dp, dp]
+        L.orc_kf_update1.argtypes = [C.c_int, dp, dp, C.c_int, C.c_double, C.c_double, dp, dp, dp]
         L.orc_fit_hits.argtypes = [C.c_int, C.POINTER(Geometry), C.POINTER(Params), C.c_int32, dp, dp,
                                    dp, C.c_double, dp, dp, dp]
         L.orc_fit_hits.restype = C.c_int
@@ -125,6 +126,15 @@ def kf_update(p, cov, my, mz, vy, vz, precision=64):
     op = np.zeros(5); oc = np.zeros(15); c2 = C.c_double(0)
     lib().orc_kf_update(precision, _ptr(p, C.c_double), _ptr(cov, C.c_double), my, mz, vy, vz,
                         _ptr(op, C.c_double), _ptr(oc, C.c_double), C.byref(c2))
+    return op, oc, c2.value
+
+
+def kf_update1(p, cov, q, m, v, precision=64):
+    """Scalar-measurement update of state component q (value m, variance v)."""
+    p = np.ascontiguousarray(p, dtype=np.float64); cov = np.ascontiguousarray(cov, dtype=np.float64)
+    op = np.zeros(5); oc = np.zeros(15); c2 = C.c_double(0)
+    lib().orc_kf_update1(precision, _ptr(p, C.c_double), _ptr(cov, C.c_double), int(q), m, v,
+                         _ptr(op, C.c_double), _ptr(oc, C.c_double), C.byref(c2))
     return op, oc, c2.value
 
 

@@ -749,6 +749,27 @@ void orc_kf_update(int precision, const double pin[5], const double Cin[15], dou
   *dchi2 = c2;
 }
 
+void orc_kf_update1(int precision, const double pin[5], const double Cin[15], int q, double m,
+                    double v, double out_p[5], double out_C[15], double* dchi2) {
+  if (precision == 32) {
+    float p[5], C[15], c2 = 0.0f;
+    for (int i = 0; i < 5; ++i) p[i] = (float)pin[i];
+    for (int i = 0; i < 15; ++i) C[i] = (float)Cin[i];
+    kf_update1<float>(p, C, q, (float)m, (float)v, c2);
+    for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+    for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+    *dchi2 = c2;
+    return;
+  }
+  double p[5], C[15], c2 = 0.0;
+  for (int i = 0; i < 5; ++i) p[i] = pin[i];
+  for (int i = 0; i < 15; ++i) C[i] = Cin[i];
+  kf_update1<double>(p, C, q, m, v, c2);
+  for (int i = 0; i < 5; ++i) out_p[i] = p[i];
+  for (int i = 0; i < 15; ++i) out_C[i] = C[i];
+  *dchi2 = c2;
+}
+
 int orc_fit_hits(int precision, const orc_geometry* g, const orc_params* P, int32_t n,
                  const double* x, const double* y, const double* z, double k0, double pout[5],
                  double Cout[15], double* chi2out) {

@@ -64,6 +64,12 @@ int orc_transport(int precision, const double p[5], const double C[15], double x
 void orc_kf_update(int precision, const double p[5], const double C[15], double my, double mz,
                    double vy, double vz, double out_p[5], double out_C[15], double* dchi2);
 
+/* One Kalman update with a scalar measurement m of state component q
+ * (0..4) with variance v (the external tan(lambda) of the calibration
+ * objective).  Writes the filtered state, covariance and chi2 increment. */
+void orc_kf_update1(int precision, const double p[5], const double C[15], int q, double m,
+                    double v, double out_p[5], double out_C[15], double* dchi2);
+
 /* Final fit of an ordered hit list (outermost first): the track refit of the
  * selection step.  Returns 1 on success. */
 int orc_fit_hits(int precision, const orc_geometry* g, const orc_params* P, int32_t n,
