@@ -222,6 +222,18 @@ int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_cal
 int tpcca_debug_tracklets(tpcca_ctx* ctx, int64_t cap, int64_t* n_seeds, uint32_t* seed_start,
                           int32_t* seed_nhits, int32_t* seed_hits, float* seed_state);
 
+/* Test tap of the FP32 arithmetic the bit-exact decisions rest on (the
+ * library's reading of the paper's tracking: integer decisions taken from
+ * FP32 values that any IEEE implementation of the same expressions
+ * reproduces).  Evaluates, elementwise on the device with the tracking
+ * kernels' compile flags, op 0: the correctly rounded square root used for
+ * cosines (argument 0, negative, or >= 2^-96), 1: a[i] / b[i], 2: 1 / a[i],
+ * 3: the correctly rounded sqrtf(a[i]).  a, b, out are device arrays of n
+ * floats (b only for op 1), owned by the caller; work is enqueued on
+ * `stream` and finished on return.  TPCCA_E_INVALID for a bad op, size or
+ * null pointer, TPCCA_E_DEVICE for a HIP error.  No context needed. */
+int tpcca_debug_fp32(int32_t op, int64_t n, const float* a, const float* b, float* out, void* stream);
+
 /* Replace / read the launch tuning of a context (results never change). */
 int tpcca_set_tuning(tpcca_ctx* ctx, const tpcca_tuning* t);
 int tpcca_get_tuning(const tpcca_ctx* ctx, tpcca_tuning* t);

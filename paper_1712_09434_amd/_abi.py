@@ -27,7 +27,7 @@ ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
-            "tpcca_last_error", "tpcca_destroy"]
+            "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32"]
 
 
 class tpcca_geometry(C.Structure):
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
     L.tpcca_last_error.restype = C.c_char_p
     L.tpcca_destroy.argtypes = [C.c_void_p]
     L.tpcca_destroy.restype = None
+    L.tpcca_debug_fp32.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.tpcca_debug_fp32.restype = C.c_int
     for name in ("tpcca_create", "tpcca_set_params", "tpcca_get_params", "tpcca_track",
                  "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets"):
         getattr(L, name).restype = C.c_int

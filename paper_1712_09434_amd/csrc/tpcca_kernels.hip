@@ -1689,6 +1689,30 @@ unsigned tracklet_grid(const Ws& w) {
   return blocks_for(w.seed_cap, 1 << 16);
 }
 
+namespace {
+// FP32 building blocks of the bit-exact contract, elementwise, compiled with
+// the flags of the tracking kernels: op 0 sqrt_rn_normal(a), 1 a / b,
+// 2 1 / a, 3 sqrtf(a).
+__global__ __launch_bounds__(TB) void k_fp32_probe(int op, int64_t n, const float* __restrict__ a,
+                                                   const float* __restrict__ b, float* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+    const float x = a[i];
+    float r;
+    if (op == 0) r = sqrt_rn_normal(x);
+    else if (op == 1) r = x / b[i];
+    else if (op == 2) r = 1.0f / x;
+    else r = sqrtf(x);
+    out[i] = r;
+  }
+}
+}  // namespace
+
+hipError_t fp32_probe(int op, int64_t n, const float* a, const float* b, float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fp32_probe<<<blocks_for(n, 1 << 14), TB, 0, st>>>(op, n, a, b, out);
+  return hipGetLastError();
+}
+
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_fill<<<blocks_for(n, 4096), TB, 0, st>>>(p, v, n);

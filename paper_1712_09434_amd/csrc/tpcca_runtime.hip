@@ -596,6 +596,16 @@ int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t*
   return TPCCA_OK;
 }
 
+int tpcca_debug_fp32(int32_t op, int64_t n, const float* a, const float* b, float* out, void* stream) {
+  if (op < 0 || op > 3 || n < 0) return TPCCA_E_INVALID;
+  if (n > 0 && (!a || !out || (op == 1 && !b))) return TPCCA_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t he = fp32_probe(op, n, a, b, out, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) { (void)hipGetLastError(); return TPCCA_E_DEVICE; }
+  return TPCCA_OK;
+}
+
 int tpcca_set_tuning(tpcca_ctx* c, const tpcca_tuning* t) {
   if (!c || !t) return TPCCA_E_INVALID;
   if (t->ckpt_every < 1 || t->ckpt_every > 160 || t->tracklet_grid < 0 || t->use_graph < 0 || t->use_graph > 1)

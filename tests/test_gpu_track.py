@@ -4,9 +4,9 @@ Bar (FP32 both sides, same expressions, no contraction):
   * raw and cleaned neighbour links, start hits, tracklet hit lists and
     final hit lists: bit-exact;
   * track parameters, covariance, chi2: |a - b| <= 1e-4 * max(|b|, floor).
-C1 and C2 are compared whole; C3 (the headline event, in the launch
-configuration the benchmark times) is compared on sampled sectors that the
-oracle processes one by one.
+C1 and C2 are compared whole; C3 (the headline event) is compared whole,
+sector by sector (the oracle takes one sector per host thread), with the
+taps on and in the launch configuration the benchmark times.
 """
 import ctypes as C
 
@@ -89,15 +89,59 @@ def test_parity_full_event(tracker, orc, cfg):
     print(f"[gpu] {cfg}: {out.n_tracks} tracks, exact-parameter fraction {exact:.4f}", flush=True)
 
 
-def test_parity_c3_sampled_sectors(tracker, orc):
+def host(out):
+    """The tracks with every tensor copied to host memory once."""
+    import dataclasses
+    taps = {k: v.cpu() for k, v in out.taps.items()} if out.taps else out.taps
+    return dataclasses.replace(out, **{f.name: getattr(out, f.name).cpu() for f in dataclasses.fields(out)
+                                       if f.name != "taps"}, taps=taps)
+
+
+def oracle_by_sector(orc, ev, sectors, threads=16):
+    """The oracle on each sector alone (sectors are independent), one sector
+    per host thread; returns {sector: result}."""
+    import concurrent.futures
+
+    def one(s):
+        mask = np.zeros(ev.geom.n_sectors, np.uint8)
+        mask[s] = 1
+        return s, orc.track(ev, precision=32, sector_mask=mask)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as pool:
+        return dict(pool.map(one, sectors))
+
+
+@pytest.fixture(scope="module")
+def c3_reference(orc):
     ev = synth.make_config("C3")
-    print(f"[gpu] parity C3 n={ev.n}", flush=True)
-    out = tracker.track(*to_dev(ev), taps=True)
+    print(f"[gpu] oracle on the 36 sectors of C3 n={ev.n}", flush=True)
+    return ev, oracle_by_sector(orc, ev, range(ev.geom.n_sectors))
+
+
+def test_parity_c3_whole_event(tracker, c3_reference):
+    """The headline event, every sector: links, starts, tracklets and tracks."""
+    ev, refs = c3_reference
+    print(f"[gpu] parity C3 whole event (taps on) n={ev.n}", flush=True)
+    out = host(tracker.track(*to_dev(ev), taps=True))
     tl = tracker.debug_tracklets()
-    sectors = [0, 13, 18, 35]
-    mask = np.zeros(36, np.uint8); mask[sectors] = 1
-    ref = orc.track(ev, precision=32, sector_mask=mask)
-    compare(ev, out, tl, ref, sectors=sectors)
+    for s, ref in refs.items():
+        compare(ev, out, tl, ref, sectors=[s])
+    assert out.n_tracks == sum(len(r["x_ref"]) for r in refs.values())
+
+
+def test_parity_c3_timed_configuration(tracker, c3_reference):
+    """The call the benchmark times (no taps, default tuning, phase timing
+    on): final tracks of every sector equal the oracle's."""
+    ev, refs = c3_reference
+    print(f"[gpu] parity C3 whole event (taps off) n={ev.n}", flush=True)
+    tracker.set_phase_timing(True)
+    try:
+        out = host(tracker.track(*to_dev(ev)))
+    finally:
+        tracker.set_phase_timing(False)
+    for s, ref in refs.items():
+        compare(ev, out, None, ref, sectors=[s], check_taps=False)
+    assert out.n_tracks == sum(len(r["x_ref"]) for r in refs.values())
 
 
 def test_deterministic_repeat(tracker):
