@@ -48,7 +48,9 @@ extern "C" {
 #define TPCCA_E_CAPACITY (-2)  /* outputs too small: required sizes written to n_tracks / n_hits */
 #define TPCCA_E_DEVICE (-3)    /* HIP runtime error */
 #define TPCCA_E_NOMEM (-4)     /* device workspace allocation failed */
-#define TPCCA_E_LIMIT (-5)     /* a pad row of one sector holds more than TPCCA_MAX_ROW_CLUSTERS clusters */
+#define TPCCA_E_LIMIT (-5)     /* a fixed limit exceeded: a pad row of one sector holds more than
+                                  TPCCA_MAX_ROW_CLUSTERS clusters, or a call needs more than the
+                                  static scratch of tpcca_refit_grad_noalloc */
 
 #define TPCCA_MEM_HOST 0
 #define TPCCA_MEM_DEVICE 1
@@ -213,6 +215,32 @@ int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* ev
  * out of range, more hits than pad rows) they may hold partial values. */
 int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_calib* calib,
                      tpcca_grad* out);
+
+/* tpcca_refit_grad for callers that cannot allocate memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, bit for bit, but its scratch is a
+ * static device array of TPCCA_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends, and the call makes
+ * no device or pinned-host allocation (it does synchronise the stream and
+ * read the hit count and the result words into host stack memory).
+ * Differences from tpcca_refit_grad:
+ *   - tracks, clusters, calib and grad must all be device memory
+ *     (TPCCA_MEM_DEVICE), else TPCCA_E_INVALID;
+ *   - the checkpoint stride is the largest one up to the tuned ckpt_every
+ *     whose workspace fits the scratch (results do not depend on it); if
+ *     none fits, TPCCA_E_LIMIT and nothing runs.  Per track the workspace
+ *     is 68 bytes per hit plus 5.5 KB (stride 9-12) to 28 KB (stride 160)
+ *     of kept states: for tracks of 130 hits the scratch holds about 3,600
+ *     of them at stride 160 and about 9,300 at the most compact stride;
+ *   - every call on a GPU, from any context, uses that GPU's one array:
+ *     calls that overlap in time on one GPU (two streams, two threads)
+ *     race and give wrong results.  The array keeps the last call's
+ *     contents; each call clears what it needs cleared itself;
+ *   - TPCCA_E_DEVICE if the array's device address could not be found
+ *     when the context was created. */
+#define TPCCA_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int tpcca_refit_grad_noalloc(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_calib* calib,
+                             tpcca_grad* out);
 
 /* Debug tap of the last tpcca_track call (host memory): the tracklet of
  * every seed (chain head with at least min_seed_hits links), in start

@@ -22,12 +22,13 @@ TPCCA_E_LIMIT = -5
 TPCCA_MEM_HOST = 0
 TPCCA_MEM_DEVICE = 1
 TPCCA_MAX_ROW_CLUSTERS = 8192
+TPCCA_NOALLOC_SCRATCH_BYTES = 128 << 20
 ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "E_NOMEM", -5: "E_LIMIT"}
 
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
-            "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32"]
+            "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc"]
 
 
 class tpcca_geometry(C.Structure):
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
     L.tpcca_track.argtypes = [C.c_void_p, P(tpcca_clusters), P(tpcca_tracks)]
     L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]
     L.tpcca_refit_grad.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]
+    L.tpcca_refit_grad_noalloc.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]
     L.tpcca_debug_tracklets.argtypes = [C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]
     L.tpcca_set_tuning.argtypes = [C.c_void_p, P(tpcca_tuning)]
@@ -126,7 +128,8 @@ def load(path: str = LIB_PATH):
     L.tpcca_debug_fp32.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.tpcca_debug_fp32.restype = C.c_int
     for name in ("tpcca_create", "tpcca_set_params", "tpcca_get_params", "tpcca_track",
-                 "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets"):
+                 "tpcca_track_batch", "tpcca_refit_grad", "tpcca_refit_grad_noalloc",
+                 "tpcca_debug_tracklets"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,39 @@
 #include "internal.hpp"
 
 using namespace tpcca;
+
+namespace {
+
+// Scratch of tpcca_refit_grad_noalloc, which allocates nothing: a file-scope
+// device array.  Each GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code `scratch` names only a
+// host-side stand-in: every host use goes through the device address that
+// hipGetSymbolAddress returned for the GPU (scratch_address).
+constexpr size_t kNoAllocScratchBytes = (size_t)TPCCA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev`, looked up once per device with
+// that device current (the caller has made it current).
+hipError_t scratch_address(int dev, char** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 
 struct tpcca_ctx {
   int device = 0;
@@ -47,6 +81,10 @@ struct tpcca_ctx {
   // refit_grad scratch
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
+  // device address of the static scratch of tpcca_refit_grad_noalloc on
+  // this context's GPU (null, with the reason, if the lookup failed)
+  char* noalloc_scratch = nullptr;
+  std::string noalloc_err;
   // tuning
   tpcca_tuning tune{160, 0, 0};
   // captured tracking graph and the workspace shape it was captured for
@@ -276,6 +314,14 @@ int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out)
   e = hipMalloc((void**)&c->row_x_d, sizeof(float) * g->n_rows);
   if (e == hipSuccess) e = hipMemcpy(c->row_x_d, g->row_x, sizeof(float) * g->n_rows, hipMemcpyHostToDevice);
   if (e != hipSuccess) { (void)hipGetLastError(); if (c->row_x_d) (void)hipFree(c->row_x_d); delete c; return TPCCA_E_DEVICE; }
+  // the static scratch of the allocation-free gradient: its address on this
+  // device (the device is current); only that entry point needs it
+  e = scratch_address(c->device, &c->noalloc_scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->noalloc_scratch = nullptr;
+    c->noalloc_err = hipGetErrorString(e);
+  }
   *out = c;
   return TPCCA_OK;
 }
@@ -620,19 +666,155 @@ int tpcca_get_tuning(const tpcca_ctx* c, tpcca_tuning* t) {
   return TPCCA_OK;
 }
 
-int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
-  if (!c) return TPCCA_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Where the arrays of one gradient call live in its scratch (byte offsets
+// from the scratch base), for T tracks, H hits, NC clusters, S sectors, R
+// pad rows and checkpoint stride K; host inputs get staged copies.
+struct GradLayout {
+  int K = 0, nck = 0, nseg = 0;
+  size_t o_hx = 0, o_hy = 0, o_hz = 0, o_gx = 0, o_gy = 0, o_gz = 0, o_gpt = 0;
+  size_t o_bva = 0, o_bvb = 0, o_bsp = 0, o_dzt = 0;
+  size_t o_part = 0, o_tf = 0, o_tn = 0, o_ck = 0, o_sg = 0, o_chunk = 0, o_out = 0, o_ndf = 0, o_err = 0;
+  size_t o_off = 0, o_ids = 0, o_kp = 0, o_ext = 0, o_uv = 0;
+  size_t o_cx = 0, o_cy = 0, o_cz = 0, o_cs = 0, o_th = 0;
+  size_t bytes = 0;
+};
+
+GradLayout grad_layout(int64_t T, int64_t H, int64_t NC, int S, int R, int K, bool th, bool kh, bool ch) {
+  GradLayout g;
+  g.K = K;
+  g.nck = (R - 1 + K - 1) / K + 1;
+  g.nseg = 2 * K + kTail;
+  const int nq = S * kNPar + 1;
+  const int64_t nchunk = (T + kChunk - 1) / kChunk;
+  Layout L;
+  g.o_hx = L.take<float>(H); g.o_hy = L.take<float>(H); g.o_hz = L.take<float>(H);
+  g.o_gx = L.take<float>(H); g.o_gy = L.take<float>(H); g.o_gz = L.take<float>(H); g.o_gpt = L.take<float>(H);
+  g.o_bva = L.take<float4>(H); g.o_bvb = L.take<float4>(H); g.o_bsp = L.take<int32_t>(H);
+  g.o_dzt = L.take<float>(H);
+  g.o_part = L.take<float>(T * kPart);
+  g.o_tf = L.take<int32_t>(T); g.o_tn = L.take<int32_t>(T);
+  g.o_ck = L.take<float>(T * g.nck * 20); g.o_sg = L.take<float>(T * g.nseg * 20);
+  // the total chi2 (last entry of out), ndf and the error word are read
+  // back together: keep them adjacent
+  g.o_chunk = L.take<double>(nchunk * nq); g.o_out = L.take<double>(nq);
+  g.o_ndf = L.take<unsigned long long>(1); g.o_err = L.take<uint32_t>(1);
+  if (th) {
+    g.o_off = L.take<int32_t>(T + 1); g.o_ids = L.take<uint32_t>(H); g.o_kp = L.take<float>(T);
+    g.o_ext = L.take<float>(T); g.o_uv = L.take<uint8_t>(T);
+  }
+  if (kh) { g.o_cx = L.take<float>(NC); g.o_cy = L.take<float>(NC); g.o_cz = L.take<float>(NC); g.o_cs = L.take<uint8_t>(NC); }
+  if (ch) g.o_th = L.take<float>(S * 66);
+  g.bytes = L.off;
+  return g;
+}
+
+// Argument checks shared by the gradient entry points.
+int grad_args(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, const tpcca_grad* g) {
   if (!t || !cal || !g || !t->clusters) return fail(c, TPCCA_E_INVALID, "null tracks, clusters, calib or grad");
   const tpcca_clusters& k = *t->clusters;
   const int64_t T = t->n_tracks, NC = k.n;
-  const int S = c->S;
   if (T < 0 || NC < 0) return fail(c, TPCCA_E_INVALID, "negative sizes");
+  if (T >= ((int64_t)1 << 31) || NC >= ((int64_t)1 << 32)) return fail(c, TPCCA_E_INVALID, "too many tracks or clusters");
   if (T > 0 && (!t->hit_off || !t->hit_id || !t->k_prior)) return fail(c, TPCCA_E_INVALID, "null hit_off/hit_id/k_prior");
   if (NC > 0 && (!k.x || !k.y || !k.z || !k.sector)) return fail(c, TPCCA_E_INVALID, "null cluster arrays");
   if (!cal->drift_scale || !cal->time_offset || !cal->map) return fail(c, TPCCA_E_INVALID, "null calibration arrays");
   if (!g->d_drift_scale || !g->d_time_offset || !g->d_map) return fail(c, TPCCA_E_INVALID, "null gradient arrays");
   for (int mk : {t->mem, k.mem, cal->mem, g->mem})
     if (mk != TPCCA_MEM_HOST && mk != TPCCA_MEM_DEVICE) return fail(c, TPCCA_E_INVALID, "bad mem kind");
+  return TPCCA_OK;
+}
+
+// Bind the workspace of a gradient call to scratch base b (laid out by gl)
+// and to the caller's arrays; host inputs are copied into the scratch on
+// stream st.
+hipError_t grad_bind(const tpcca_ctx* c, CalWs& w, char* b, const GradLayout& gl, const tpcca_tracks* t,
+                     const tpcca_calib* cal, const tpcca_grad* g, int64_t H, hipStream_t st) {
+  const tpcca_clusters& k = *t->clusters;
+  const int S = c->S;
+  const int64_t T = t->n_tracks, NC = k.n;
+  w = CalWs{};
+  w.S = S; w.R = c->R; w.L = c->z_max; w.tan_a = c->tan_a;
+  w.m = make_model(c->bz, c->P);
+  w.sv2 = c->P.sigma_vertex * c->P.sigma_vertex;
+  w.st2 = c->P.sigma_tgl * c->P.sigma_tgl;
+  w.K = gl.K; w.nck = gl.nck; w.nseg = gl.nseg;
+  w.T = T; w.H = H; w.NC = NC;
+  w.x_first = c->row_x_first;
+  w.x_span = c->row_x_last - c->row_x_first;
+  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0 || !src) return hipSuccess;
+    return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  hipError_t he = hipSuccess;
+  if (t->mem == TPCCA_MEM_HOST) {
+    if (he == hipSuccess) he = up(gl.o_off, t->hit_off, 4 * (T + 1));
+    if (he == hipSuccess) he = up(gl.o_ids, t->hit_id, 4 * H);
+    if (he == hipSuccess) he = up(gl.o_kp, t->k_prior, 4 * T);
+    if (he == hipSuccess) he = up(gl.o_ext, t->ext_tgl, 4 * T);
+    if (he == hipSuccess) he = up(gl.o_uv, t->use_vertex, T);
+    w.hit_off = (const int32_t*)(b + gl.o_off); w.hit_id = (const uint32_t*)(b + gl.o_ids);
+    w.k_prior = (const float*)(b + gl.o_kp);
+    w.ext_tgl = t->ext_tgl ? (const float*)(b + gl.o_ext) : nullptr;
+    w.use_vertex = t->use_vertex ? (const uint8_t*)(b + gl.o_uv) : nullptr;
+  } else {
+    w.hit_off = t->hit_off; w.hit_id = t->hit_id; w.k_prior = t->k_prior;
+    w.ext_tgl = t->ext_tgl; w.use_vertex = t->use_vertex;
+  }
+  if (k.mem == TPCCA_MEM_HOST) {
+    if (he == hipSuccess) he = up(gl.o_cx, k.x, 4 * NC);
+    if (he == hipSuccess) he = up(gl.o_cy, k.y, 4 * NC);
+    if (he == hipSuccess) he = up(gl.o_cz, k.z, 4 * NC);
+    if (he == hipSuccess) he = up(gl.o_cs, k.sector, NC);
+    w.cx = (const float*)(b + gl.o_cx); w.cy = (const float*)(b + gl.o_cy); w.cz = (const float*)(b + gl.o_cz);
+    w.csec = (const uint8_t*)(b + gl.o_cs);
+  } else {
+    w.cx = k.x; w.cy = k.y; w.cz = k.z; w.csec = k.sector;
+  }
+  if (cal->mem == TPCCA_MEM_HOST) {
+    if (he == hipSuccess) he = up(gl.o_th, cal->drift_scale, 4 * S);
+    if (he == hipSuccess) he = up(gl.o_th + 4 * S, cal->time_offset, 4 * S);
+    if (he == hipSuccess) he = up(gl.o_th + 8 * S, cal->map, 4 * 64 * S);
+    w.dl = (const float*)(b + gl.o_th); w.tau = (const float*)(b + gl.o_th + 4 * S);
+    w.map = (const float*)(b + gl.o_th + 8 * S);
+  } else {
+    w.dl = cal->drift_scale; w.tau = cal->time_offset; w.map = cal->map;
+  }
+  w.hx = (float*)(b + gl.o_hx); w.hy = (float*)(b + gl.o_hy); w.hz = (float*)(b + gl.o_hz);
+  w.gx = (float*)(b + gl.o_gx); w.gy = (float*)(b + gl.o_gy); w.gz = (float*)(b + gl.o_gz);
+  w.gpt = (float*)(b + gl.o_gpt);
+  w.bva = (float4*)(b + gl.o_bva); w.bvb = (float4*)(b + gl.o_bvb); w.bsp = (int32_t*)(b + gl.o_bsp);
+  w.dzt = (float*)(b + gl.o_dzt);
+  w.part = (float*)(b + gl.o_part); w.tflag = (int32_t*)(b + gl.o_tf); w.tndf = (int32_t*)(b + gl.o_tn);
+  w.ckpt = (float*)(b + gl.o_ck); w.seg = (float*)(b + gl.o_sg);
+  w.chunk = (double*)(b + gl.o_chunk); w.out = (double*)(b + gl.o_out);
+  w.ndf_sum = (unsigned long long*)(b + gl.o_ndf); w.err = (uint32_t*)(b + gl.o_err);
+  // device gradient arrays are written by the reduction itself
+  if (g->mem == TPCCA_MEM_DEVICE) { w.g_dl = g->d_drift_scale; w.g_tau = g->d_time_offset; w.g_map = g->d_map; }
+  return he;
+}
+
+// The error word of a finished gradient call.
+int grad_err(tpcca_ctx* c, uint32_t err) {
+  if (err & 1u) return fail(c, TPCCA_E_INVALID, "hit id or sector out of range");
+  if (err & 2u) return fail(c, TPCCA_E_INVALID, "a track has more hits than pad rows");
+  return TPCCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
+  if (!c) return TPCCA_E_INVALID;
+  int rc = grad_args(c, t, cal, g);
+  if (rc != TPCCA_OK) return rc;
+  const tpcca_clusters& k = *t->clusters;
+  const int64_t T = t->n_tracks, NC = k.n;
+  const int S = c->S;
   hipError_t he = hipSetDevice(c->device);
   if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
   hipStream_t st = (hipStream_t)k.stream;
@@ -645,7 +827,7 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   }
   const int nq = S * kNPar + 1;
   const size_t r_bytes = al(sizeof(double) * nq) + al(sizeof(unsigned long long)) + sizeof(uint32_t);
-  int rc = ensure_pinned(c, r_bytes);
+  rc = ensure_pinned(c, r_bytes);
   if (rc != TPCCA_OK) return rc;
   // number of hits
   int32_t H32 = 0;
@@ -668,96 +850,17 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   }
   const int64_t H = H32;
   if (H < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
-  const int K = c->tune.ckpt_every;
-  const int nck = (c->R - 1 + K - 1) / K + 1;
-  const int nseg = 2 * K + kTail;
-  const int64_t nchunk = (T + kChunk - 1) / kChunk;
-  // scratch layout
-  Layout L;
-  size_t o_hx = L.take<float>(H), o_hy = L.take<float>(H), o_hz = L.take<float>(H);
-  size_t o_gx = L.take<float>(H), o_gy = L.take<float>(H), o_gz = L.take<float>(H), o_gpt = L.take<float>(H);
-  size_t o_bva = L.take<float4>(H), o_bvb = L.take<float4>(H), o_bsp = L.take<int32_t>(H);
-  size_t o_dzt = L.take<float>(H);
-  size_t o_part = L.take<float>(T * kPart);
-  size_t o_tf = L.take<int32_t>(T), o_tn = L.take<int32_t>(T);
-  size_t o_ck = L.take<float>(T * nck * 20), o_sg = L.take<float>(T * nseg * 20);
-  size_t o_chunk = L.take<double>(nchunk * nq), o_out = L.take<double>(nq);
-  size_t o_ndf = L.take<unsigned long long>(1), o_err = L.take<uint32_t>(1);
-  // staged copies of host inputs
-  const bool th = t->mem == TPCCA_MEM_HOST, kh = k.mem == TPCCA_MEM_HOST, ch = cal->mem == TPCCA_MEM_HOST;
-  size_t o_off = 0, o_ids = 0, o_kp = 0, o_ext = 0, o_uv = 0, o_cx = 0, o_cy = 0, o_cz = 0, o_cs = 0, o_th = 0;
-  if (th) {
-    o_off = L.take<int32_t>(T + 1); o_ids = L.take<uint32_t>(H); o_kp = L.take<float>(T);
-    o_ext = L.take<float>(T); o_uv = L.take<uint8_t>(T);
-  }
-  if (kh) { o_cx = L.take<float>(NC); o_cy = L.take<float>(NC); o_cz = L.take<float>(NC); o_cs = L.take<uint8_t>(NC); }
-  if (ch) o_th = L.take<float>(S * 66);
-  if (L.off > c->gscratch_bytes) {
+  const GradLayout gl = grad_layout(T, H, NC, S, c->R, c->tune.ckpt_every, t->mem == TPCCA_MEM_HOST,
+                                    k.mem == TPCCA_MEM_HOST, cal->mem == TPCCA_MEM_HOST);
+  if (gl.bytes > c->gscratch_bytes) {
     if (c->gscratch) { (void)hipFree(c->gscratch); c->gscratch = nullptr; c->gscratch_bytes = 0; }
-    he = hipMalloc((void**)&c->gscratch, L.off + L.off / 4);
+    he = hipMalloc((void**)&c->gscratch, gl.bytes + gl.bytes / 4);
     if (he != hipSuccess) { c->gscratch = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "gradient scratch allocation failed"); }
-    c->gscratch_bytes = L.off + L.off / 4;
+    c->gscratch_bytes = gl.bytes + gl.bytes / 4;
   }
-  char* b = c->gscratch;
   CalWs w{};
-  w.S = S; w.R = c->R; w.L = c->z_max; w.tan_a = c->tan_a;
-  w.m = make_model(c->bz, c->P);
-  w.sv2 = c->P.sigma_vertex * c->P.sigma_vertex;
-  w.st2 = c->P.sigma_tgl * c->P.sigma_tgl;
-  w.K = K; w.nck = nck; w.nseg = nseg;
-  w.T = T; w.H = H; w.NC = NC;
-  w.x_first = c->row_x_first;
-  w.x_span = c->row_x_last - c->row_x_first;
-  auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
-    if (bytes == 0 || !src) return hipSuccess;
-    return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, st);
-  };
-  he = hipSuccess;
-  if (th) {
-    if (he == hipSuccess) he = up(o_off, t->hit_off, 4 * (T + 1));
-    if (he == hipSuccess) he = up(o_ids, t->hit_id, 4 * H);
-    if (he == hipSuccess) he = up(o_kp, t->k_prior, 4 * T);
-    if (he == hipSuccess) he = up(o_ext, t->ext_tgl, 4 * T);
-    if (he == hipSuccess) he = up(o_uv, t->use_vertex, T);
-    w.hit_off = (const int32_t*)(b + o_off); w.hit_id = (const uint32_t*)(b + o_ids);
-    w.k_prior = (const float*)(b + o_kp);
-    w.ext_tgl = t->ext_tgl ? (const float*)(b + o_ext) : nullptr;
-    w.use_vertex = t->use_vertex ? (const uint8_t*)(b + o_uv) : nullptr;
-  } else {
-    w.hit_off = t->hit_off; w.hit_id = t->hit_id; w.k_prior = t->k_prior;
-    w.ext_tgl = t->ext_tgl; w.use_vertex = t->use_vertex;
-  }
-  if (kh) {
-    if (he == hipSuccess) he = up(o_cx, k.x, 4 * NC);
-    if (he == hipSuccess) he = up(o_cy, k.y, 4 * NC);
-    if (he == hipSuccess) he = up(o_cz, k.z, 4 * NC);
-    if (he == hipSuccess) he = up(o_cs, k.sector, NC);
-    w.cx = (const float*)(b + o_cx); w.cy = (const float*)(b + o_cy); w.cz = (const float*)(b + o_cz);
-    w.csec = (const uint8_t*)(b + o_cs);
-  } else {
-    w.cx = k.x; w.cy = k.y; w.cz = k.z; w.csec = k.sector;
-  }
-  if (ch) {
-    if (he == hipSuccess) he = up(o_th, cal->drift_scale, 4 * S);
-    if (he == hipSuccess) he = up(o_th + 4 * S, cal->time_offset, 4 * S);
-    if (he == hipSuccess) he = up(o_th + 8 * S, cal->map, 4 * 64 * S);
-    w.dl = (const float*)(b + o_th); w.tau = (const float*)(b + o_th + 4 * S);
-    w.map = (const float*)(b + o_th + 8 * S);
-  } else {
-    w.dl = cal->drift_scale; w.tau = cal->time_offset; w.map = cal->map;
-  }
+  he = grad_bind(c, w, c->gscratch, gl, t, cal, g, H, st);
   if (he != hipSuccess) return hip_fail(c, he, "input upload");
-  w.hx = (float*)(b + o_hx); w.hy = (float*)(b + o_hy); w.hz = (float*)(b + o_hz);
-  w.gx = (float*)(b + o_gx); w.gy = (float*)(b + o_gy); w.gz = (float*)(b + o_gz);
-  w.gpt = (float*)(b + o_gpt);
-  w.bva = (float4*)(b + o_bva); w.bvb = (float4*)(b + o_bvb); w.bsp = (int32_t*)(b + o_bsp);
-  w.dzt = (float*)(b + o_dzt);
-  w.part = (float*)(b + o_part); w.tflag = (int32_t*)(b + o_tf); w.tndf = (int32_t*)(b + o_tn);
-  w.ckpt = (float*)(b + o_ck); w.seg = (float*)(b + o_sg);
-  w.chunk = (double*)(b + o_chunk); w.out = (double*)(b + o_out);
-  w.ndf_sum = (unsigned long long*)(b + o_ndf); w.err = (uint32_t*)(b + o_err);
-  // device gradient arrays are written by the reduction itself
-  if (g->mem == TPCCA_MEM_DEVICE) { w.g_dl = g->d_drift_scale; w.g_tau = g->d_time_offset; w.g_map = g->d_map; }
   he = run_calib(w, st);
   if (he != hipSuccess) return hip_fail(c, he, "gradient kernels");
   // sums, ndf and the error word in one copy (adjacent in the layout)
@@ -768,10 +871,10 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   if (he != hipSuccess) return hip_fail(c, he, "gradient");
   c->hpin_busy = false;
   const double* out = (const double*)c->hpin;
-  const unsigned long long ndf = *(const unsigned long long*)(c->hpin + (o_ndf - o_out));
-  const uint32_t err = *(const uint32_t*)(c->hpin + (o_err - o_out));
-  if (err & 1u) return fail(c, TPCCA_E_INVALID, "hit id or sector out of range");
-  if (err & 2u) return fail(c, TPCCA_E_INVALID, "a track has more hits than pad rows");
+  const unsigned long long ndf = *(const unsigned long long*)(c->hpin + (gl.o_ndf - gl.o_out));
+  const uint32_t err = *(const uint32_t*)(c->hpin + (gl.o_err - gl.o_out));
+  rc = grad_err(c, err);
+  if (rc != TPCCA_OK) return rc;
   g->chi2 = out[S * kNPar];
   g->ndf = (int64_t)ndf;
   if (g->mem == TPCCA_MEM_HOST) {
@@ -781,6 +884,71 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
       for (int q = 0; q < 64; ++q) g->d_map[(size_t)s * 64 + q] = out[s * kNPar + 2 + q];
     }
   }
+  return TPCCA_OK;
+}
+
+int tpcca_refit_grad_noalloc(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
+  if (!c) return TPCCA_E_INVALID;
+  int rc = grad_args(c, t, cal, g);
+  if (rc != TPCCA_OK) return rc;
+  const tpcca_clusters& k = *t->clusters;
+  if (t->mem != TPCCA_MEM_DEVICE || k.mem != TPCCA_MEM_DEVICE || cal->mem != TPCCA_MEM_DEVICE ||
+      g->mem != TPCCA_MEM_DEVICE)
+    return fail(c, TPCCA_E_INVALID, "the allocation-free gradient takes device memory only");
+  if (!c->noalloc_scratch)
+    return fail(c, TPCCA_E_DEVICE, "the device address of the static gradient scratch is unknown: " + c->noalloc_err);
+  const int64_t T = t->n_tracks, NC = k.n;
+  const int S = c->S;
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+  hipStream_t st = (hipStream_t)k.stream;
+  // the hit count, read into host stack memory
+  int32_t ends[2] = {0, 0};
+  if (T > 0) {
+    he = hipMemcpyAsync(&ends[0], t->hit_off, 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(&ends[1], t->hit_off + T, 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
+    if (ends[0] != 0) return fail(c, TPCCA_E_INVALID, "hit_off[0] must be 0");
+    if (ends[1] < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
+  }
+  const int64_t H = ends[1];
+  // the largest checkpoint stride up to the tuned one whose layout fits
+  // (results do not depend on the stride)
+  GradLayout gl;
+  int K = c->tune.ckpt_every;
+  for (; K >= 1; --K) {
+    gl = grad_layout(T, H, NC, S, c->R, K, false, false, false);
+    if (gl.bytes <= kNoAllocScratchBytes) break;
+  }
+  if (K < 1)
+    return fail(c, TPCCA_E_LIMIT, std::to_string(T) + " tracks with " + std::to_string(H) +
+                                      " hits need more than the " + std::to_string(kNoAllocScratchBytes >> 20) +
+                                      " MiB of static gradient scratch at every checkpoint stride");
+  CalWs w{};
+  he = grad_bind(c, w, c->noalloc_scratch, gl, t, cal, g, H, st);
+  if (he != hipSuccess) return hip_fail(c, he, "workspace");
+  he = run_calib(w, st);
+  if (he != hipSuccess) return hip_fail(c, he, "gradient kernels");
+  // the total chi2 (last entry of out), ndf and the error word are adjacent
+  const size_t from = gl.o_out + sizeof(double) * (size_t)(S * kNPar);
+  const size_t span = gl.o_err + sizeof(uint32_t) - from;
+  alignas(8) unsigned char res[1024];
+  static_assert(sizeof(double) + 256 + 256 + sizeof(uint32_t) <= sizeof(res), "result words");
+  if (span > sizeof(res)) return fail(c, TPCCA_E_DEVICE, "result layout");
+  he = hipMemcpyAsync(res, c->noalloc_scratch + from, span, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "gradient");
+  double chi2;
+  unsigned long long ndf;
+  uint32_t err;
+  std::memcpy(&chi2, res, sizeof(double));
+  std::memcpy(&ndf, res + (gl.o_ndf - from), sizeof(ndf));
+  std::memcpy(&err, res + (gl.o_err - from), sizeof(err));
+  rc = grad_err(c, err);
+  if (rc != TPCCA_OK) return rc;
+  g->chi2 = chi2;
+  g->ndf = (int64_t)ndf;
   return TPCCA_OK;
 }
 

@@ -187,6 +187,15 @@ class Tracker:
         """Total chi2, ndf and d chi2/d theta (float64, flat layout
         [drift_scale(S), time_offset(S), map(S*64)]) of the fixed hit lists in
         `fit` under the calibration theta (flat float32, same layout)."""
+        return self._refit_grad(self.L.tpcca_refit_grad, fit, theta)
+
+    def refit_grad_noalloc(self, fit: "FitTracks", theta: torch.Tensor):
+        """refit_grad through tpcca_refit_grad_noalloc: the library allocates
+        nothing (its scratch is a static device array); every tensor must be
+        on the GPU.  The gradient tensor is allocated here, by the caller."""
+        return self._refit_grad(self.L.tpcca_refit_grad_noalloc, fit, theta)
+
+    def _refit_grad(self, entry, fit: "FitTracks", theta: torch.Tensor):
         S = self.n_sectors
         th = theta.detach().to(torch.float32).contiguous()
         dev = th.device
@@ -208,7 +217,7 @@ class Tracker:
         g.d_time_offset = C.c_void_p(grad.data_ptr() + 8 * S)
         g.d_map = C.c_void_p(grad.data_ptr() + 16 * S)
         g.mem = _mem(grad)
-        _check(self.L, self.ctx, self.L.tpcca_refit_grad(self.ctx, C.byref(st), C.byref(cal), C.byref(g)))
+        _check(self.L, self.ctx, entry(self.ctx, C.byref(st), C.byref(cal), C.byref(g)))
         return float(g.chi2), int(g.ndf), grad
 
     def get_tuning(self) -> A.tpcca_tuning:
