@@ -151,8 +151,19 @@ typedef struct {
   double* d_drift_scale;          /* [n_sectors] */
   double* d_time_offset;          /* [n_sectors] */
   double* d_map;                  /* [n_sectors][8][8] */
+  int32_t* track_flag;            /* [n_tracks] optional (NULL = off): per-track status, see
+                                     TPCCA_TRK_* */
   int32_t mem;
 } tpcca_grad;
+
+/* Per-track status of a gradient call (track_flag): the low two bits say
+ * what entered chi2, the next bit whether the track lies outside the
+ * accuracy domain of the FP32 per-track gradient. */
+#define TPCCA_TRK_NOT_FITTED 0    /* fewer than 3 hits, or a transport reached |sin phi| >= sin_max */
+#define TPCCA_TRK_HITS 1          /* the hits only (no vertex requested, or its transport refused) */
+#define TPCCA_TRK_VERTEX 2        /* the hits, the vertex and (if given) the external tan(lambda) */
+#define TPCCA_TRK_SHORT 4         /* fewer than TPCCA_GRAD_MIN_HITS hits (see tpcca_refit_grad) */
+#define TPCCA_GRAD_MIN_HITS 40
 
 /* Launch tuning (no effect on results).  ckpt_every: Kalman states kept
  * every that many hit steps by the gradient's forward pass (1..160, default
@@ -212,7 +223,22 @@ int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* ev
  * tracks->n_tracks tracks; all of them, the clusters, calib and grad arrays
  * must share one `mem` kind per struct.  Device gradient arrays are written
  * by the kernels, so after an error found on the device (a hit id or sector
- * out of range, more hits than pad rows) they may hold partial values. */
+ * out of range, more hits than pad rows) they may hold partial values.
+ *
+ * Accuracy.  Each track is refitted and differentiated in FP32; the first
+ * TPCCA_GRAD_C2_UPDATES Kalman updates of a refit, where the nearly
+ * diffuse prior makes C - K H C cancel most digits of C, compute the gain
+ * and the covariance update in compensated two-float arithmetic (FP32
+ * operations only).  For tracks of at least TPCCA_GRAD_MIN_HITS hits the
+ * gradient over a calibration set then agrees with exact arithmetic to
+ * about 1e-4 (relative, per parameter group).  Shorter tracks are
+ * ill-conditioned in FP32: their map gradient is a sum of large per-hit
+ * terms that nearly cancel (a common shift of the hits along the track is
+ * absorbed by its parameters), and for short, strongly curved segments or
+ * long extrapolations to the vertex single tracks can be off by percents.
+ * They are computed and summed like the others and reported with
+ * TPCCA_TRK_SHORT in track_flag; a calibration set should leave them out. */
+#define TPCCA_GRAD_C2_UPDATES 3
 int tpcca_refit_grad(tpcca_ctx* ctx, const tpcca_tracks* tracks, const tpcca_calib* calib,
                      tpcca_grad* out);
 

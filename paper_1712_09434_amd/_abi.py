@@ -23,6 +23,9 @@ TPCCA_MEM_HOST = 0
 TPCCA_MEM_DEVICE = 1
 TPCCA_MAX_ROW_CLUSTERS = 8192
 TPCCA_NOALLOC_SCRATCH_BYTES = 128 << 20
+TPCCA_TRK_NOT_FITTED, TPCCA_TRK_HITS, TPCCA_TRK_VERTEX, TPCCA_TRK_SHORT = 0, 1, 2, 4
+TPCCA_GRAD_MIN_HITS = 40
+TPCCA_GRAD_C2_UPDATES = 3
 ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "E_NOMEM", -5: "E_LIMIT"}
 
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
@@ -80,7 +83,8 @@ class tpcca_calib(C.Structure):
 
 class tpcca_grad(C.Structure):
     _fields_ = [("chi2", C.c_double), ("ndf", C.c_int64), ("d_drift_scale", C.c_void_p),
-                ("d_time_offset", C.c_void_p), ("d_map", C.c_void_p), ("mem", C.c_int32)]
+                ("d_time_offset", C.c_void_p), ("d_map", C.c_void_p), ("track_flag", C.c_void_p),
+                ("mem", C.c_int32)]
 
 
 _lib = None

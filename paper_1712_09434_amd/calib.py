@@ -121,12 +121,21 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
 
     Without preconditioning the variables are those of to_theta and
     lr = learning rates of the (drift scale [1e-3], drift offset [cm], map
-    [cm]) groups.  With precondition=True the per-sector Hessian blocks of
-    the loss at theta0 are estimated once (sector_hessian plus the prior's
-    curvature) and Adam runs on u = H^(1/2) (theta - theta0), where the loss
-    is locally isotropic, with a step size decaying from lr_white to lr_final
-    (half cosine over `steps`).  Returns (theta, history, state); `state`
-    (step, moments, variables, whitening) allows a resume from a checkpoint."""
+    [cm]) groups.  With a preconditioner the per-sector Hessian blocks of the
+    loss at theta0 are estimated once (sector_hessian plus the prior's
+    curvature) and Adam runs on linear coordinates u of theta - theta0 with a
+    step size decaying from lr_white to lr_final (half cosine over `steps`):
+      precondition=True or "white": u = H^(1/2) (theta - theta0), where the
+        loss is locally isotropic;
+      precondition="eigen": u = V^T D^-1 (theta - theta0) with D the prior
+        spread (prior_sigma, required) and V the eigenvectors of D H D: the
+        prior-scaled parameters rotated so that each coordinate is an
+        independent quadratic to second order.  Adam's per-coordinate
+        normalisation then moves every coordinate at the same rate in units
+        of the expected miscalibration, so one step-size schedule suits
+        strongly and weakly measured directions alike.
+    Returns (theta, history, state); `state` (step, moments, variables,
+    coordinate map) allows a resume from a checkpoint."""
     S = tracker.n_sectors
     dev = fit.hit_off.device
 
@@ -143,18 +152,26 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
             H = sector_hessian(tracker, fit, th0)
             if prior_sigma is not None:
                 H = H + torch.diag_embed(sp(2.0 / prior_sigma.to(dev) ** 2))
-            W, Wi = whitening(H)
+            if precondition == "eigen":
+                if prior_sigma is None:
+                    raise ValueError('precondition="eigen" needs prior_sigma')
+                d = sp(prior_sigma.to(dev).to(torch.float64))             # [S, 66]
+                A = d.unsqueeze(2) * H * d.unsqueeze(1)
+                _, V = torch.linalg.eigh(0.5 * (A + A.transpose(1, 2)))
+                R = d.unsqueeze(2) * V                                    # theta - theta0 = R u
+            else:
+                _, R = whitening(H)
             u0 = torch.zeros(S * 66, dtype=torch.float64, device=dev)
-            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0), W=W, Wi=Wi, th0=th0,
+            state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0), R=R, th0=th0,
                          total=torch.tensor(float(steps)))
         else:
             u0 = from_theta(th0, S, drift_length)
             state = dict(step=0, u=u0, m=torch.zeros_like(u0), v=torch.zeros_like(u0))
-    white = "Wi" in state
+    white = "R" in state
 
     def theta_of(u):
         if white:
-            du = (state["Wi"] @ u.reshape(S, 66, 1)).reshape(S, 66)
+            du = (state["R"] @ u.reshape(S, 66, 1)).reshape(S, 66)
             return state["th0"] + flat(du)
         return to_theta(u, S, drift_length)
 
@@ -183,7 +200,7 @@ def calibrate(tracker: Tracker, fit: FitTracks, steps: int = 50, lr=(0.5, 0.02, 
             state["u"] = state["u"] - rate * mh / (torch.sqrt(vh) + 1e-12)
         else:
             state["u"] = state["u"] - lr_vec * mh / (torch.sqrt(vh) + 1e-12)
-        hist.append(float(loss))
+        hist.append(float(loss.detach()))
         if callback:
             callback(t, float(loss), state)
     return theta_of(state["u"]).detach(), hist, state

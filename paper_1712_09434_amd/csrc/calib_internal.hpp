@@ -8,6 +8,8 @@ constexpr int kPart = 68;                       // per-track partials: 66 parame
 constexpr int kNPar = TPCCA_NPAR_PER_SECTOR;    // 66 per sector
 constexpr int kChunk = 256;                     // tracks per first-level reduction chunk
 constexpr int kTail = 28;                       // state slots of the steps to the vertex (<= kTail - 2 steps)
+constexpr int kFirstC2 = TPCCA_GRAD_C2_UPDATES;   // hit updates 1..kFirstC2 of a refit in two-float arithmetic
+constexpr int kMinAccurateHits = TPCCA_GRAD_MIN_HITS;
 
 struct CalWs {
   int S, R;
@@ -45,6 +47,7 @@ struct CalWs {
   float* part;             // [T][kPart]
   int32_t* tflag;          // [T] 0 failed, 1 hits only, 2 with vertex terms
   int32_t* tndf;           // [T]
+  int32_t* flag_out;       // [T] per-track status for the caller (may be null)
   float* ckpt;             // [T][nck][20]
   float* seg;              // [T][nseg][20]
   double* chunk;           // [nchunk][S*66 + 1]

@@ -680,10 +680,12 @@ struct GradLayout {
   size_t o_part = 0, o_tf = 0, o_tn = 0, o_ck = 0, o_sg = 0, o_chunk = 0, o_out = 0, o_ndf = 0, o_err = 0;
   size_t o_off = 0, o_ids = 0, o_kp = 0, o_ext = 0, o_uv = 0;
   size_t o_cx = 0, o_cy = 0, o_cz = 0, o_cs = 0, o_th = 0;
+  size_t o_flag = 0;       // staged per-track flags for a host track_flag
   size_t bytes = 0;
 };
 
-GradLayout grad_layout(int64_t T, int64_t H, int64_t NC, int S, int R, int K, bool th, bool kh, bool ch) {
+GradLayout grad_layout(int64_t T, int64_t H, int64_t NC, int S, int R, int K, bool th, bool kh, bool ch,
+                       bool fh) {
   GradLayout g;
   g.K = K;
   g.nck = (R - 1 + K - 1) / K + 1;
@@ -708,6 +710,7 @@ GradLayout grad_layout(int64_t T, int64_t H, int64_t NC, int S, int R, int K, bo
   }
   if (kh) { g.o_cx = L.take<float>(NC); g.o_cy = L.take<float>(NC); g.o_cz = L.take<float>(NC); g.o_cs = L.take<uint8_t>(NC); }
   if (ch) g.o_th = L.take<float>(S * 66);
+  if (fh) g.o_flag = L.take<int32_t>(T);
   g.bytes = L.off;
   return g;
 }
@@ -792,8 +795,13 @@ hipError_t grad_bind(const tpcca_ctx* c, CalWs& w, char* b, const GradLayout& gl
   w.ckpt = (float*)(b + gl.o_ck); w.seg = (float*)(b + gl.o_sg);
   w.chunk = (double*)(b + gl.o_chunk); w.out = (double*)(b + gl.o_out);
   w.ndf_sum = (unsigned long long*)(b + gl.o_ndf); w.err = (uint32_t*)(b + gl.o_err);
-  // device gradient arrays are written by the reduction itself
-  if (g->mem == TPCCA_MEM_DEVICE) { w.g_dl = g->d_drift_scale; w.g_tau = g->d_time_offset; w.g_map = g->d_map; }
+  // device gradient arrays and flags are written by the kernels themselves
+  if (g->mem == TPCCA_MEM_DEVICE) {
+    w.g_dl = g->d_drift_scale; w.g_tau = g->d_time_offset; w.g_map = g->d_map;
+    w.flag_out = g->track_flag;
+  } else if (g->track_flag) {
+    w.flag_out = (int32_t*)(b + gl.o_flag);
+  }
   return he;
 }
 
@@ -851,7 +859,8 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   const int64_t H = H32;
   if (H < 0) return fail(c, TPCCA_E_INVALID, "negative hit count");
   const GradLayout gl = grad_layout(T, H, NC, S, c->R, c->tune.ckpt_every, t->mem == TPCCA_MEM_HOST,
-                                    k.mem == TPCCA_MEM_HOST, cal->mem == TPCCA_MEM_HOST);
+                                    k.mem == TPCCA_MEM_HOST, cal->mem == TPCCA_MEM_HOST,
+                                    g->mem == TPCCA_MEM_HOST && g->track_flag);
   if (gl.bytes > c->gscratch_bytes) {
     if (c->gscratch) { (void)hipFree(c->gscratch); c->gscratch = nullptr; c->gscratch_bytes = 0; }
     he = hipMalloc((void**)&c->gscratch, gl.bytes + gl.bytes / 4);
@@ -867,6 +876,8 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
   c->hpin_busy = true;
   c->hpin_stream = st;
   he = hipMemcpyAsync(c->hpin, w.out, r_bytes, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess && g->mem == TPCCA_MEM_HOST && g->track_flag && T > 0)
+    he = hipMemcpyAsync(g->track_flag, w.flag_out, sizeof(int32_t) * (size_t)T, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return hip_fail(c, he, "gradient");
   c->hpin_busy = false;
@@ -918,7 +929,7 @@ int tpcca_refit_grad_noalloc(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_ca
   GradLayout gl;
   int K = c->tune.ckpt_every;
   for (; K >= 1; --K) {
-    gl = grad_layout(T, H, NC, S, c->R, K, false, false, false);
+    gl = grad_layout(T, H, NC, S, c->R, K, false, false, false, false);
     if (gl.bytes <= kNoAllocScratchBytes) break;
   }
   if (K < 1)

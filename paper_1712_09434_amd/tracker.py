@@ -183,23 +183,26 @@ class Tracker:
         t = A.tpcca_tuning(int(ckpt_every), int(tracklet_grid), int(use_graph))
         _check(self.L, self.ctx, self.L.tpcca_set_tuning(self.ctx, C.byref(t)))
 
-    def refit_grad(self, fit: "FitTracks", theta: torch.Tensor):
+    def refit_grad(self, fit: "FitTracks", theta: torch.Tensor, flags: bool = False):
         """Total chi2, ndf and d chi2/d theta (float64, flat layout
         [drift_scale(S), time_offset(S), map(S*64)]) of the fixed hit lists in
-        `fit` under the calibration theta (flat float32, same layout)."""
-        return self._refit_grad(self.L.tpcca_refit_grad, fit, theta)
+        `fit` under the calibration theta (flat float32, same layout).  With
+        flags=True a fourth item holds the per-track status (int32,
+        TPCCA_TRK_* bits)."""
+        return self._refit_grad(self.L.tpcca_refit_grad, fit, theta, flags)
 
-    def refit_grad_noalloc(self, fit: "FitTracks", theta: torch.Tensor):
+    def refit_grad_noalloc(self, fit: "FitTracks", theta: torch.Tensor, flags: bool = False):
         """refit_grad through tpcca_refit_grad_noalloc: the library allocates
         nothing (its scratch is a static device array); every tensor must be
         on the GPU.  The gradient tensor is allocated here, by the caller."""
-        return self._refit_grad(self.L.tpcca_refit_grad_noalloc, fit, theta)
+        return self._refit_grad(self.L.tpcca_refit_grad_noalloc, fit, theta, flags)
 
-    def _refit_grad(self, entry, fit: "FitTracks", theta: torch.Tensor):
+    def _refit_grad(self, entry, fit: "FitTracks", theta: torch.Tensor, flags: bool = False):
         S = self.n_sectors
         th = theta.detach().to(torch.float32).contiguous()
         dev = th.device
         grad = torch.empty(S * 66, dtype=torch.float64, device=dev)
+        tflag = torch.empty(max(fit.n_tracks, 1), dtype=torch.int32, device=dev) if flags else None
         cl = self.clusters_struct(*fit.clusters)
         st = A.tpcca_tracks()
         st.n_tracks = fit.n_tracks
@@ -216,8 +219,11 @@ class Tracker:
         g.d_drift_scale = _ptr(grad)
         g.d_time_offset = C.c_void_p(grad.data_ptr() + 8 * S)
         g.d_map = C.c_void_p(grad.data_ptr() + 16 * S)
+        g.track_flag = _ptr(tflag)
         g.mem = _mem(grad)
         _check(self.L, self.ctx, entry(self.ctx, C.byref(st), C.byref(cal), C.byref(g)))
+        if flags:
+            return float(g.chi2), int(g.ndf), grad, tflag[:fit.n_tracks]
         return float(g.chi2), int(g.ndf), grad
 
     def get_tuning(self) -> A.tpcca_tuning:

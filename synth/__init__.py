@@ -7,6 +7,6 @@ injected miscalibration.  It contains none of the tracker's arithmetic and is
 shared by the oracle tests and the GPU path as the one source of inputs.
 """
 from .events import (  # noqa: F401
-    Geometry, Event, CalibTheta, default_geometry, make_event, make_config,
+    Geometry, Event, CalibTheta, default_geometry, make_event, make_config, make_configs,
     bspline_basis, draw_theta, CONFIGS,
 )

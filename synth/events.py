@@ -102,18 +102,19 @@ def bspline_basis(u: np.ndarray) -> np.ndarray:
     u = np.clip(np.asarray(u, dtype=np.float64), 0.0, 1.0)
     n = u.shape[0]
     m = len(t) - 1
-    N = np.zeros((n, m))
+    # one row per basis function (contiguous), transposed at the end
+    N = np.zeros((m, n))
     for i in range(m):
-        N[:, i] = (t[i] <= u) & (u < t[i + 1])
-    N[u >= 1.0, 7] = 1.0           # right end belongs to the last non-empty span
+        N[i] = (t[i] <= u) & (u < t[i + 1])
+    N[7, u >= 1.0] = 1.0           # right end belongs to the last non-empty span
     for p in range(1, 4):
-        M = np.zeros((n, m - p))
+        M = np.zeros((m - p, n))
         for i in range(m - p):
             a = (u - t[i]) / (t[i + p] - t[i]) if t[i + p] > t[i] else 0.0
             b = (t[i + p + 1] - u) / (t[i + p + 1] - t[i + 1]) if t[i + p + 1] > t[i + 1] else 0.0
-            M[:, i] = a * N[:, i] + b * N[:, i + 1]
+            M[i] = a * N[i] + b * N[i + 1]
         N = M
-    return N[:, :8]
+    return np.ascontiguousarray(N[:8].T)
 
 
 def draw_theta(seed: int = 1005999, sd_delta=2e-3, sd_tau=0.1, amp=0.3) -> CalibTheta:
@@ -313,6 +314,33 @@ CONFIGS = {
     # central-Pb-Pb-shaped event, ~3 M clusters
     'C3': dict(seed=1003, n_primaries=18000, n_secondaries=4000, noise=0.05, doubling=0.10),
 }
+
+
+def _make_indexed(args):
+    name, index = args
+    return make_config(name, index)
+
+
+def make_configs(name: str, indices, workers: int = 8) -> list:
+    """make_config(name, i) for every i of `indices`, in order, generated in
+    up to `workers` worker processes (events are independent; a miscalibrated
+    event costs seconds in the FP64 fixed-point inverse of the calibration).
+    Workers use the 'spawn' start method, so they never inherit a GPU
+    context; a script that calls this needs the usual __main__ guard."""
+    import concurrent.futures
+    import multiprocessing
+    import os
+    indices = list(indices)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(workers, avail, len(indices)))
+    if workers == 1:
+        return [make_config(name, i) for i in indices]
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as pool:
+        return list(pool.map(_make_indexed, [(name, i) for i in indices]))
 
 
 def make_config(name: str, index: int = 0, **over) -> Event:

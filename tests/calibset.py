@@ -1,12 +1,11 @@
 """Frozen calibration track subset built from a tracked event and its truth.
 
-Truth-matched primaries with at least `min_hits` hits, chi2/ndf <= 4 at the
-default calibration, and a segment that starts within the first
-`max_inner_row` + 1 pad rows (it comes straight from the vertex: segments of
-low-momentum tracks that enter a sector from its neighbour need a long,
-strongly curved extrapolation to the vertex, where the FP32 refit adjoint
-loses precision).  Each carries its q/pT prior (the tracklet's final q/pT),
-the external tan(lambda) and the vertex flag.
+Truth-matched primaries with at least `min_hits` hits (the library's FP32
+gradient is accurate to about 1e-4 from 40 hits on) and chi2/ndf <= 4 at the
+default calibration, whatever pad row their segment starts on (optionally
+only segments starting within the first `max_inner_row` + 1 rows).  Each
+carries its q/pT prior (the tracklet's final q/pT), the external tan(lambda)
+and the vertex flag.
 """
 import numpy as np
 
@@ -14,14 +13,14 @@ import truth
 
 
 def calib_subset(ev, hit_off, hit_ids, sectors, chi2, ndf, k_prior, min_hits=40, max_q=4.0,
-                 max_tracks=None, max_inner_row=10):
+                 max_tracks=None, max_inner_row=None):
     m = truth.match_tracks(ev, hit_off, hit_ids, sectors)
     keep = []
     for t in range(len(hit_off) - 1):
         n = hit_off[t + 1] - hit_off[t]
         if m[t] < 0 or n < min_hits or chi2[t] / ndf[t] > max_q:
             continue
-        if ev.row[hit_ids[hit_off[t]]] > max_inner_row:
+        if max_inner_row is not None and ev.row[hit_ids[hit_off[t]]] > max_inner_row:
             continue
         if not ev.tracks['primary'][m[t] // 64]:
             continue
