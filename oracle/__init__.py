@@ -86,6 +86,9 @@ def lib():
         L.orc_result_free.argtypes = [C.POINTER(Result)]
         L.orc_calib_apply.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), dp, dp, dp,
                                       dp, dp, dp]
+        fp = C.POINTER(C.c_float)
+        L.orc_calib_apply32.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), fp, fp, fp,
+                                        fp, fp, fp]
         L.orc_calib_chi2.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
                                      C.POINTER(C.c_uint8), C.c_int64, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), dp, dp, C.POINTER(C.c_uint8), dp, dp,
@@ -156,16 +159,26 @@ def _arr(ptr, n, dtype):
     return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
 
 
-def track(ev, precision=32, params=None, sector_mask=None, use64=False):
+def track(ev, precision=32, params=None, sector_mask=None, use64=False, theta=None):
     """Run the oracle pipeline on a synth.Event.  precision=32 rounds the
     coordinates to FP32 and computes in FP32 (decision parity); 64 computes
-    in FP64 (from the FP64 coordinates if use64)."""
+    in FP64 (from the FP64 coordinates if use64).  With a calibration theta
+    (flat [drift scale, time offset, map]) the clusters are corrected first:
+    in FP32 by calib_apply32 (the tracker's input correction) for
+    precision=32, in FP64 by calib_apply otherwise."""
     g = make_geometry(ev.geom)
     P = params or default_params()
     if use64:
         x, y, z = ev.x64, ev.y64, ev.z64
     else:
         x, y, z = (ev.x.astype(np.float64), ev.y.astype(np.float64), ev.z.astype(np.float64))
+    if theta is not None:
+        if precision == 32:
+            xf, zf = calib_apply32(ev.geom, ev.sector, x.astype(np.float32), y.astype(np.float32),
+                                   z.astype(np.float32), theta)
+            x, z = xf.astype(np.float64), zf.astype(np.float64)
+        else:
+            x, z = calib_apply(ev.geom, ev.sector, x, y, z, np.asarray(theta, np.float64))
     x = np.ascontiguousarray(x); y = np.ascontiguousarray(y); z = np.ascontiguousarray(z)
     row = np.ascontiguousarray(ev.row, dtype=np.int16)
     sec = np.ascontiguousarray(ev.sector, dtype=np.uint8)
@@ -206,6 +219,21 @@ def calib_apply(ev_or_geom, sector, x, y, z, theta):
     lib().orc_calib_apply(C.byref(g), len(x), _ptr(sector, C.c_uint8), _ptr(x, C.c_double),
                           _ptr(y, C.c_double), _ptr(z, C.c_double), _ptr(th, C.c_double),
                           _ptr(xo, C.c_double), _ptr(zo, C.c_double))
+    return xo, zo
+
+
+def calib_apply32(ev_or_geom, sector, x, y, z, theta):
+    """The FP32 input correction of the tracker (float32 in, float32 out)."""
+    geom = getattr(ev_or_geom, 'geom', ev_or_geom)
+    g = make_geometry(geom)
+    sector = np.ascontiguousarray(sector, dtype=np.uint8)
+    x = np.ascontiguousarray(x, dtype=np.float32); y = np.ascontiguousarray(y, dtype=np.float32)
+    z = np.ascontiguousarray(z, dtype=np.float32)
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    xo = np.zeros_like(x); zo = np.zeros_like(z)
+    lib().orc_calib_apply32(C.byref(g), len(x), _ptr(sector, C.c_uint8), _ptr(x, C.c_float),
+                            _ptr(y, C.c_float), _ptr(z, C.c_float), _ptr(th, C.c_float),
+                            _ptr(xo, C.c_float), _ptr(zo, C.c_float))
     return xo, zo
 
 

@@ -643,6 +643,61 @@ void calib_point(const orc_geometry& g, int s, double x, double y, double z, con
   xo = acc;
 }
 
+// The same correction as the tracker applies it to its FP32 input, every
+// operation rounded to FP32 in this order (no contraction):
+//   z' = z + side (tau - delta (D - tau)),  D = L - side z
+//        (side z' = L - (1 + delta)(D - tau) rearranged so that the small
+//        correction is added to z: theta = 0 leaves z unchanged);
+//   x' = x + sum_a Na[a] (sum_b c[fa + a][fb + b] Nb[b])  over the four
+//        non-zero basis functions of each direction, ascending indices,
+//        each sum starting at +0;
+// with the basis values from de Boor's triangular recursion on the knot
+// span of the clamped argument.
+static void bspline_nonzero32(float u, int& first, float N[4]) {
+  static const float U[12] = {0.f, 0.f, 0.f, 0.f, 0.2f, 0.4f, 0.6f, 0.8f, 1.f, 1.f, 1.f, 1.f};
+  u = std::min(std::max(u, 0.0f), 1.0f);
+  int i = 3;                              // span: U[i] <= u < U[i+1]; the last one for u = 1
+  while (i < 7 && u >= U[i + 1]) ++i;
+  float left[4], right[4];
+  N[0] = 1.0f;
+  for (int j = 1; j <= 3; ++j) {
+    left[j] = u - U[i + 1 - j];
+    right[j] = U[i + j] - u;
+    float saved = 0.0f;
+    for (int r = 0; r < j; ++r) {
+      const float temp = N[r] / (right[r + 1] + left[j - r]);
+      N[r] = saved + right[r + 1] * temp;
+      saved = left[j - r] * temp;
+    }
+    N[j] = saved;
+  }
+  first = i - 3;
+}
+
+void calib_point32(const orc_geometry& g, int s, float x, float y, float z, const float* th, float& xo,
+                   float& zo) {
+  const int S = g.n_sectors;
+  const float side = s < S / 2 ? 1.0f : -1.0f;
+  const float L = g.z_max;
+  const float dl = th[s], tau = th[S + s];
+  const float D = L - side * z;
+  zo = z + side * (tau - dl * (D - tau));
+  const float xf = g.row_x[0], xl = g.row_x[g.n_rows - 1];
+  const float ta = g.tan_half_angle;
+  float Na[4], Nb[4];
+  int fa, fb;
+  bspline_nonzero32((x - xf) / (xl - xf), fa, Na);
+  bspline_nonzero32((y / x + ta) / (2.0f * ta), fb, Nb);
+  const float* c = th + 2 * S + (size_t)s * 64;
+  float d = 0.0f;
+  for (int a = 0; a < 4; ++a) {
+    float inner = 0.0f;
+    for (int b = 0; b < 4; ++b) inner = inner + c[(fa + a) * 8 + (fb + b)] * Nb[b];
+    d = d + Na[a] * inner;
+  }
+  xo = x + d;
+}
+
 // Calibration objective of one track (see orc_calib_chi2).
 // Returns 0 if the hit fit fails, 1 if only the hits were used (vertex terms
 // off, or the transport to the beam axis left the sin(phi) range), 2 if the
@@ -821,6 +876,11 @@ void orc_calib_apply(const orc_geometry* g, int64_t n, const uint8_t* sector, co
                      const double* y, const double* z, const double* theta, double* xo,
                      double* zo) {
   for (int64_t i = 0; i < n; ++i) calib_point<double>(*g, sector[i], x[i], y[i], z[i], theta, xo[i], zo[i]);
+}
+
+void orc_calib_apply32(const orc_geometry* g, int64_t n, const uint8_t* sector, const float* x,
+                       const float* y, const float* z, const float* theta, float* xo, float* zo) {
+  for (int64_t i = 0; i < n; ++i) calib_point32(*g, sector[i], x[i], y[i], z[i], theta, xo[i], zo[i]);
 }
 
 int orc_calib_chi2(const orc_geometry* g, const orc_params* P, int64_t n_clusters, const double* x,

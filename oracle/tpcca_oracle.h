@@ -115,6 +115,12 @@ void orc_calib_apply(const orc_geometry* g, int64_t n, const uint8_t* sector, co
                      const double* y, const double* z, const double* theta, double* xo,
                      double* zo);
 
+/* The same correction in FP32 as the tracker applies it to its input
+ * (corrections added to the coordinates; see calib_point32 for the order of
+ * operations).  theta in FP32, same layout. */
+void orc_calib_apply32(const orc_geometry* g, int64_t n, const uint8_t* sector, const float* x,
+                       const float* y, const float* z, const float* theta, float* xo, float* zo);
+
 /* chi2(theta) of fixed hit lists: refit over the hits (outermost first), then
  * optionally the primary vertex as a measured point and an external
  * tan(lambda).  hit_ids[hit_off[t]..hit_off[t+1]) index the clusters in
