@@ -451,15 +451,45 @@ def grad_leg(Tracker, dev, n_events=20):
     sig = default_prior_sigma(36, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, hist, _ = calibrate(trk, fit, steps=50, precondition="eigen", lr_white=0.6, lr_final=1e-3,
-                           betas=(0.8, 0.999), prior_sigma=sig)
+    theta, hist, _ = calibrate(trk, fit, steps=50, precondition="eigen", lr_white=0.6, lr_final=1e-3,
+                               betas=(0.8, 0.999), prior_sigma=sig)
     torch.cuda.synchronize()
     t_adam = time.perf_counter() - t0
     log(f"grad: 50 Adam steps (after a 132-call Hessian) in {t_adam:.3f} s; objective {hist[0]:.0f} -> {hist[-1]:.0f}")
+    # the feedback: the calibration found is installed in front of tracking
+    cal_map = calib_map_leg(trk, evs[0], theta, dev)
     trk.close()
     return {"workload": f"{n_events} miscalibrated full events (5000 primaries, 2% noise, seeds 1005000+)",
             "tracks": T, "hits": H, "ms_per_call": dt * 1e3, "tracks_per_s": T / dt, "hits_per_s": H / dt,
-            "params": 36 * 66, "adam50_s": t_adam, "adam50_gradient_calls": 132 + 50}
+            "params": 36 * 66, "adam50_s": t_adam, "adam50_gradient_calls": 132 + 50, "calib_map": cal_map}
+
+
+def calib_map_leg(trk, ev, theta, dev, reps=20):
+    """Tracking of one miscalibrated full event without and with the
+    calibration installed in front of binning (tpcca_set_calib): time per
+    call and of the binning scatter (where the correction runs)."""
+    import torch
+    cl = _to_dev(ev, dev)
+    res = {}
+    for name, th in (("uncorrected", None), ("corrected", theta)):
+        trk.set_calib(th)
+        for _ in range(3):
+            trk.track(*cl)
+        trk.set_phase_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            trk.track(*cl)
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) / reps * 1e3, trk.phase_times()[0]["scatter"])
+        trk.set_phase_timing(False)
+    trk.set_calib(None)
+    out = {"clusters": int(ev.n), "ms_uncorrected": res["uncorrected"][0], "ms_corrected": res["corrected"][0],
+           "scatter_ms_uncorrected": res["uncorrected"][1], "scatter_ms_corrected": res["corrected"][1]}
+    log(f"calibration map: {ev.n} clusters, {out['ms_uncorrected']:.3f} ms uncorrected, "
+        f"{out['ms_corrected']:.3f} ms with the map (scatter {out['scatter_ms_uncorrected']:.4f} -> "
+        f"{out['scatter_ms_corrected']:.4f} ms)")
+    return out
 
 
 def cpu_baseline(ev, args):

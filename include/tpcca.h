@@ -203,6 +203,25 @@ int tpcca_get_params(const tpcca_ctx* ctx, tpcca_params* p);
  * out->n_tracks / out->n_hits and nothing else is written. */
 int tpcca_track(tpcca_ctx* ctx, const tpcca_clusters* clusters, tpcca_tracks* out);
 
+/* Install (or, with calib = NULL, remove) a calibration correction of the
+ * tracking input (Sec. "Track reconstruction in the TPC": components
+ * chained on the GPU so that no data crosses PCIe between them; Sec.
+ * "Approach for online calibration": tracking consumes calibration-
+ * transformed clusters, the calibration feeds a new map back).  While
+ * installed, every tracking call of the context corrects each cluster of
+ * sector s on the device, inside binning, before anything else reads it:
+ *   z' = z + side (tau_s - delta_s (D - tau_s)),  D = L - side z,
+ *   x' = x + sum_a Na (sum_b c_s[a][b] Nb)  (four non-zero cubic B-splines of
+ *        each direction at the uncorrected (x, y), as tpcca_refit_grad),
+ * in FP32 in exactly this order (side = +1 for the first half of the
+ * sectors, -1 otherwise; L = z_max); the pad row is kept.  The library
+ * copies theta (host or device memory per calib->mem, read synchronously:
+ * device arrays must be complete) into its own device buffer; later changes
+ * of the caller's arrays have no effect until the next call.  Returns
+ * TPCCA_E_INVALID for null arrays, a bad mem kind or a non-finite value,
+ * TPCCA_E_NOMEM if the buffer cannot be allocated. */
+int tpcca_set_calib(tpcca_ctx* ctx, const tpcca_calib* calib);
+
 /* Track n_events events together (Sec. "Track reconstruction in the TPC":
  * several events processed concurrently on one GPU to fill it).  Event e is
  * described by events[e] and written to out[e]; the result of every event is

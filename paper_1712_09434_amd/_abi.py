@@ -31,7 +31,8 @@ ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
-            "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc"]
+            "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc",
+            "tpcca_set_calib"]
 
 
 class tpcca_geometry(C.Structure):
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.tpcca_set_params.argtypes = [C.c_void_p, P(tpcca_params)]
     L.tpcca_get_params.argtypes = [C.c_void_p, P(tpcca_params)]
     L.tpcca_track.argtypes = [C.c_void_p, P(tpcca_clusters), P(tpcca_tracks)]
+    L.tpcca_set_calib.argtypes = [C.c_void_p, P(tpcca_calib)]
+    L.tpcca_set_calib.restype = C.c_int
     L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]
     L.tpcca_refit_grad.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]
     L.tpcca_refit_grad_noalloc.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_calib), P(tpcca_grad)]

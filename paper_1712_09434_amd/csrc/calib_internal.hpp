@@ -1,5 +1,6 @@
 // calib_internal.hpp -- workspace of the calibration gradient (not ABI).
 #pragma once
+#include "calib_device.hpp"
 #include "internal.hpp"
 
 namespace tpcca {
@@ -13,7 +14,7 @@ constexpr int kMinAccurateHits = TPCCA_GRAD_MIN_HITS;
 
 struct CalWs {
   int S, R;
-  float L, x_first, x_span, tan_a;
+  CalGeo geo;              // the correction's geometry (drift length, radial range, sector angle)
   Model m;
   float sv2, st2;          // vertex and external tan(lambda) variances
   int K;                   // checkpoint stride (hit steps)

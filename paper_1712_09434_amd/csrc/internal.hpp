@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/tpcca.h"
+#include "calib_device.hpp"
 #include "kf_device.hpp"
 
 namespace tpcca {
@@ -101,6 +102,8 @@ struct Ws {
   float tan_a, z_max;   // acceptance: |y| <= x tan_a, |z| <= z_max
   int tracklet_grid;    // workgroups of the tracklet kernel (0 = automatic)
   int taps;             // 1 if some event of the call asks for link or start-hit taps
+  const float* cal;     // installed calibration [S delta][S tau][S][8][8] (device), or null
+  CalGeo cal_geo;       // geometry of the correction
   uint32_t* flags;      // [F_COUNT]
   const ChunkIn* chunk; // [chunk_cap(N, E)] binning chunks, empty entries past the last
   // binning

@@ -409,34 +409,6 @@ __host__ __device__ __forceinline__ void load(const float* src, float p[5], floa
   for (int i = 0; i < 15; ++i) C[i] = src[5 + i];
 }
 
-// The 8 clamped uniform cubic B-splines (knots 0,0,0,0,.2,.4,.6,.8,1,1,1,1)
-// at u, by the Cox-de Boor recursion over the one non-empty span: the four
-// non-zero ones are B[span - 3 .. span] = N[0 .. 3]; returns span - 3.
-__host__ __device__ __forceinline__ int bspline4(float u, float N[4]) {
-  u = fminf(fmaxf(u, 0.0f), 1.0f);
-  const float kn[12] = {0.f, 0.f, 0.f, 0.f, 0.2f, 0.4f, 0.6f, 0.8f, 1.f, 1.f, 1.f, 1.f};
-  int span = 3;
-#pragma unroll
-  for (int i = 4; i <= 7; ++i) if (u >= kn[i]) span = i;
-  N[0] = 1.f; N[1] = 0.f; N[2] = 0.f; N[3] = 0.f;
-  float left[4], right[4];
-#pragma unroll
-  for (int j = 1; j <= 3; ++j) {
-    left[j] = u - kn[span + 1 - j];
-    right[j] = kn[span + j] - u;
-    float saved = 0.f;
-#pragma unroll
-    for (int r = 0; r < j; ++r) {
-      const float den = right[r + 1] + left[j - r];
-      const float tmp = den != 0.f ? N[r] / den : 0.f;
-      N[r] = saved + right[r + 1] * tmp;
-      saved = left[j - r] * tmp;
-    }
-    N[j] = saved;
-  }
-  return span - 3;
-}
-
 // ------------------------------------------------------- 1. calibrate hits
 __host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
   const uint32_t id = c.hit_id[j];
@@ -456,31 +428,13 @@ __host__ __device__ inline void calib_hit(const CalWs& c, int64_t j) {
   }
   const int s = c.csec[id];
   const float x = c.cx[id], y = c.cy[id], z = c.cz[id];
-  const float side = s < c.S / 2 ? 1.0f : -1.0f;
-  const float dl = c.dl[s], tau = c.tau[s];
-  const float drift = (c.L - side * z) - tau;
-  c.hz[j] = side * (c.L - (1.0f + dl) * drift);
-  c.dzt[j] = drift;
-  float Na[4], Nb[4];
-  const int fa = bspline4((x - c.x_first) / c.x_span, Na);
-  const int fb = bspline4((y / x + c.tan_a) / (2.0f * c.tan_a), Nb);
-  c.bva[j] = make_float4(Na[0], Na[1], Na[2], Na[3]);
-  c.bvb[j] = make_float4(Nb[0], Nb[1], Nb[2], Nb[3]);
-  c.bsp[j] = fa | (fb << 8) | (1 << 16);
-  // sum over a of B_a (sum over b of c_ab B_b), both in ascending order,
-  // over the 4 x 4 window where the basis is non-zero: the terms left out
-  // are products with an exact zero, and adding a zero to these sums (which
-  // start at +0 and so are never -0) leaves them unchanged for a finite map
-  const float* cm = c.map + s * 64 + fa * 8 + fb;
-  float acc = 0.f;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    float ra = 0.f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ra += cm[i * 8 + k] * Nb[k];
-    acc += Na[i] * ra;
-  }
-  c.hx[j] = x + acc;
+  const Corrected k = correct_cluster(c.geo, c.dl[s], c.tau[s], c.map + s * 64, s, x, y, z);
+  c.hz[j] = k.z;
+  c.dzt[j] = k.drift;
+  c.bva[j] = make_float4(k.Na[0], k.Na[1], k.Na[2], k.Na[3]);
+  c.bvb[j] = make_float4(k.Nb[0], k.Nb[1], k.Nb[2], k.Nb[3]);
+  c.bsp[j] = k.fa | (k.fb << 8) | (1 << 16);
+  c.hx[j] = k.x;
   c.hy[j] = y;
 }
 

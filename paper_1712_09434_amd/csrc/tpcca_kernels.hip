@@ -375,7 +375,18 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
   for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4& v) {
     if (!ok) return;
     const uint32_t k = (lds && ru - rb < per) ? atomicAdd(&s_h[ru - rb], 1u) : atomicAdd(&w.ru_count[ru], 1u);
-    w.tmp4[w.ru_off[ru] + k] = v;
+    float4 o = v;
+    if (w.cal) {
+      // the installed calibration, applied on the way into the row buckets:
+      // every later step sees only corrected clusters (the row is kept)
+      const int s = (int)((ru / (uint32_t)w.R) % (uint32_t)w.S);
+      const int S = w.S;
+      const Corrected c = correct_cluster(w.cal_geo, w.cal[s], w.cal[S + s], w.cal + 2 * S + s * 64, s, v.x,
+                                          v.y, v.z);
+      o.x = c.x;
+      o.z = c.z;
+    }
+    w.tmp4[w.ru_off[ru] + k] = o;
   });
 }
 

@@ -81,6 +81,9 @@ struct tpcca_ctx {
   // refit_grad scratch
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
+  // installed calibration of the tracking input (device, 66 S floats), or off
+  float* cal_d = nullptr;
+  bool cal_on = false;
   // device address of the static scratch of tpcca_refit_grad_noalloc on
   // this context's GPU (null, with the reason, if the lookup failed)
   char* noalloc_scratch = nullptr;
@@ -98,6 +101,7 @@ struct tpcca_ctx {
     tpcca_params P{};
     int tracklet_grid = 0;
     int taps = 0;
+    const float* cal = nullptr;
   } gkey;
   // phase timing
   bool timing = false;
@@ -127,6 +131,12 @@ Model make_model(float bz, const tpcca_params& P) {
 }
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The geometry of the calibration correction of a context.
+CalGeo cal_geo(const tpcca_ctx* c) {
+  return CalGeo{c->S, c->z_max, c->row_x_first, c->row_x_last - c->row_x_first, c->tan_a};
+}
+
 
 struct Layout {
   size_t off = 0;
@@ -339,6 +349,32 @@ int tpcca_get_params(const tpcca_ctx* c, tpcca_params* p) {
   return TPCCA_OK;
 }
 
+int tpcca_set_calib(tpcca_ctx* c, const tpcca_calib* cal) {
+  if (!c) return TPCCA_E_INVALID;
+  if (!cal) { c->cal_on = false; return TPCCA_OK; }
+  if (!cal->drift_scale || !cal->time_offset || !cal->map) return fail(c, TPCCA_E_INVALID, "null calibration arrays");
+  if (cal->mem != TPCCA_MEM_HOST && cal->mem != TPCCA_MEM_DEVICE) return fail(c, TPCCA_E_INVALID, "bad mem kind");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+  const int S = c->S;
+  std::vector<float> th((size_t)S * 66);
+  const hipMemcpyKind k = cal->mem == TPCCA_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+  he = hipMemcpy(th.data(), cal->drift_scale, sizeof(float) * S, k);
+  if (he == hipSuccess) he = hipMemcpy(th.data() + S, cal->time_offset, sizeof(float) * S, k);
+  if (he == hipSuccess) he = hipMemcpy(th.data() + 2 * S, cal->map, sizeof(float) * 64 * S, k);
+  if (he != hipSuccess) return hip_fail(c, he, "calibration read");
+  for (float v : th)
+    if (!std::isfinite(v)) return fail(c, TPCCA_E_INVALID, "non-finite calibration value");
+  if (!c->cal_d) {
+    he = hipMalloc((void**)&c->cal_d, sizeof(float) * th.size());
+    if (he != hipSuccess) { c->cal_d = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "calibration buffer allocation failed"); }
+  }
+  he = hipMemcpy(c->cal_d, th.data(), sizeof(float) * th.size(), hipMemcpyHostToDevice);
+  if (he != hipSuccess) return hip_fail(c, he, "calibration upload");
+  c->cal_on = true;
+  return TPCCA_OK;
+}
+
 const char* tpcca_last_error(const tpcca_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
 int tpcca_set_phase_timing(tpcca_ctx* c, int on) {
@@ -379,6 +415,7 @@ void tpcca_destroy(tpcca_ctx* c) {
   if (c->stage) (void)hipFree(c->stage);
   if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->gscratch) (void)hipFree(c->gscratch);
+  if (c->cal_d) (void)hipFree(c->cal_d);
   if (c->row_x_d) (void)hipFree(c->row_x_d);
   delete c;
 }
@@ -420,6 +457,8 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   w.tan_a = c->tan_a;
   w.z_max = c->z_max;
   w.tracklet_grid = c->tune.tracklet_grid;
+  w.cal = c->cal_on ? c->cal_d : nullptr;
+  w.cal_geo = cal_geo(c);
   w.taps = 0;
   for (int e = 0; e < E; ++e)
     if (out[e].dbg_up || out[e].dbg_dn || out[e].dbg_cup || out[e].dbg_cdn || out[e].dbg_start) w.taps = 1;
@@ -525,7 +564,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
   if (c->tune.use_graph && !c->timing && st != nullptr) {
     const bool same = c->gexec && c->gkey.N == N && c->gkey.E == E && c->gkey.arena == c->arena &&
                       c->gkey.st == st && c->gkey.tracklet_grid == c->tune.tracklet_grid &&
-                      c->gkey.taps == w.taps &&
+                      c->gkey.taps == w.taps && c->gkey.cal == w.cal &&
                       std::memcmp(&c->gkey.P, &c->P, sizeof(tpcca_params)) == 0;
     if (!same) {
       if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
@@ -540,6 +579,7 @@ int tpcca_track_batch(tpcca_ctx* c, int32_t E, const tpcca_clusters* ev, tpcca_t
       if (he != hipSuccess) { c->gexec = nullptr; return hip_fail(c, he, "graph instantiate"); }
       c->gkey.N = N; c->gkey.E = E; c->gkey.arena = c->arena; c->gkey.st = st;
       c->gkey.P = c->P; c->gkey.tracklet_grid = c->tune.tracklet_grid; c->gkey.taps = w.taps;
+      c->gkey.cal = w.cal;
     }
     he = hipGraphLaunch(c->gexec, st);
     if (he != hipSuccess) return hip_fail(c, he, "graph launch");
@@ -740,14 +780,13 @@ hipError_t grad_bind(const tpcca_ctx* c, CalWs& w, char* b, const GradLayout& gl
   const int S = c->S;
   const int64_t T = t->n_tracks, NC = k.n;
   w = CalWs{};
-  w.S = S; w.R = c->R; w.L = c->z_max; w.tan_a = c->tan_a;
+  w.S = S; w.R = c->R;
+  w.geo = cal_geo(c);
   w.m = make_model(c->bz, c->P);
   w.sv2 = c->P.sigma_vertex * c->P.sigma_vertex;
   w.st2 = c->P.sigma_tgl * c->P.sigma_tgl;
   w.K = gl.K; w.nck = gl.nck; w.nseg = gl.nseg;
   w.T = T; w.H = H; w.NC = NC;
-  w.x_first = c->row_x_first;
-  w.x_span = c->row_x_last - c->row_x_first;
   auto up = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0 || !src) return hipSuccess;
     return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, st);

@@ -113,6 +113,22 @@ class Tracker:
         _check(self.L, self.ctx, self.L.tpcca_get_params(self.ctx, C.byref(p)))
         return p
 
+    # ----------------------------------------------------------- calibration
+    def set_calib(self, theta: Optional[torch.Tensor]):
+        """Install the calibration theta (flat float32 [drift_scale(S),
+        time_offset(S), map(S*64)], host or device) as the correction of the
+        tracking input, or remove it (None)."""
+        if theta is None:
+            _check(self.L, self.ctx, self.L.tpcca_set_calib(self.ctx, None))
+            return
+        S = self.n_sectors
+        th = theta.detach().to(torch.float32).contiguous()
+        if th.numel() != S * 66:
+            raise ValueError(f"theta needs {S * 66} values")
+        cal = A.tpcca_calib(_ptr(th), C.c_void_p(th.data_ptr() + 4 * S), C.c_void_p(th.data_ptr() + 8 * S),
+                            _mem(th))
+        _check(self.L, self.ctx, self.L.tpcca_set_calib(self.ctx, C.byref(cal)))
+
     # -------------------------------------------------------------- tracking
     @staticmethod
     def clusters_struct(x, y, z, row, sector) -> A.tpcca_clusters:

@@ -39,9 +39,8 @@ int main(int argc, char** argv) {
   auto th = rd<float>(d, "theta");
   auto rx = rd<float>(d, "row_x");
   CalWs c{};
-  c.S = 36; c.R = (int)rx.size(); c.L = 250.0f;
-  c.x_first = rx[0]; c.x_span = rx[c.R - 1] - rx[0];
-  c.tan_a = (float)std::tan(10.0 * M_PI / 180.0);
+  c.S = 36; c.R = (int)rx.size();
+  c.geo = CalGeo{36, 250.0f, rx[0], rx[c.R - 1] - rx[0], (float)std::tan(10.0 * M_PI / 180.0)};
   c.m.kfac = -((float)2.99792458e-3) * 0.5f;
   c.m.sin_max = 0.99f; c.m.vy = 0.1f * 0.1f; c.m.vz = 0.15f * 0.15f;
   c.sv2 = 0.01f * 0.01f; c.st2 = 1e-3f * 1e-3f;
