@@ -91,6 +91,9 @@ typedef struct {
   float sigma_y, sigma_z;    /* cluster errors (0.1, 0.15) */
   float sigma_vertex;        /* primary-vertex pseudo-measurement error (0.01) */
   float sigma_tgl;           /* external tan(lambda) error (1e-3) */
+  float chi2_merge;          /* segment merging: a pair's match chi2 at most this (50) */
+  float merge_dist;          /* segment merging: outer hit of the inner segment within this
+                                transverse and z distance of the inner hit of the outer one (20 cm) */
 } tpcca_params;
 
 /* Clusters of one event: structure of arrays, n entries each. */

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("max_gap", C.c_int32), ("min_seed_hits", C.c_int32), ("min_hits", C.c_int32),
                 ("owned_num", C.c_int32), ("owned_den", C.c_int32), ("sin_max", C.c_float),
                 ("sigma_y", C.c_float), ("sigma_z", C.c_float), ("sigma_vertex", C.c_float),
-                ("sigma_tgl", C.c_float)]
+                ("sigma_tgl", C.c_float), ("chi2_merge", C.c_float), ("merge_dist", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,6 +86,13 @@ def lib():
         L.orc_result_free.argtypes = [C.POINTER(Result)]
         L.orc_calib_apply.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), dp, dp, dp,
                                       dp, dp, dp]
+        i32p = C.POINTER(C.c_int32)
+        i64p = C.POINTER(C.c_int64)
+        L.orc_rotate.argtypes = [C.c_int, C.c_double, dp, dp, C.c_double, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.orc_rotate.restype = C.c_int
+        L.orc_merge.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
+                                C.POINTER(C.c_int16), C.c_int64, i32p, dp, dp, dp, dp, i64p, i64p,
+                                i32p, i32p, dp, dp, i32p, dp, dp, C.POINTER(C.POINTER(Result))]
         fp = C.POINTER(C.c_float)
         L.orc_calib_apply32.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), fp, fp, fp,
                                         fp, fp, fp]
@@ -204,6 +211,54 @@ def track(ev, precision=32, params=None, sector_mask=None, use64=False, theta=No
         chi2=_arr(r.trk_chi2, nt, np.float64), ndf=_arr(r.trk_ndf, nt, np.int32),
         hit_off=_arr(r.hit_off, nt + 1, np.int64), hit_ids=_arr(r.hit_ids, int(r.hit_off[nt]), np.int64),
     )
+    lib().orc_result_free(out)
+    return res
+
+
+def rotate(x, p, cov, dalpha, bz=0.5, sin_max=0.99, precision=64):
+    """State at plane x turned into a frame rotated by dalpha about z:
+    (ok, new x, p, cov, Jacobian)."""
+    p = np.ascontiguousarray(p, dtype=np.float64); cov = np.ascontiguousarray(cov, dtype=np.float64)
+    ox = C.c_double(0); op = np.zeros(5); oc = np.zeros(15); J = np.zeros(25)
+    ok = lib().orc_rotate(precision, float(x), _ptr(p, C.c_double), _ptr(cov, C.c_double), float(dalpha), bz,
+                          sin_max, C.byref(ox), _ptr(op, C.c_double), _ptr(oc, C.c_double), _ptr(J, C.c_double))
+    return bool(ok), ox.value, op, oc, J.reshape(5, 5)
+
+
+def merge(ev, seg, params=None):
+    """The sector merger on the segments `seg` of event `ev` (a track()
+    result: sector, x_ref, p, cov, chi2, hit_off, hit_ids).  Returns the
+    links, the per-segment best candidates with their chi2 and second-best
+    chi2, and the merged tracks (head = index of the innermost segment)."""
+    g = make_geometry(ev.geom)
+    P = params or default_params()
+    x = np.ascontiguousarray(ev.x, dtype=np.float64); y = np.ascontiguousarray(ev.y, dtype=np.float64)
+    z = np.ascontiguousarray(ev.z, dtype=np.float64)
+    row = np.ascontiguousarray(ev.row, dtype=np.int16)
+    ns = len(seg['x_ref'])
+    sec = np.ascontiguousarray(seg['sector'], dtype=np.int32)
+    xr = np.ascontiguousarray(seg['x_ref'], dtype=np.float64)
+    sp = np.ascontiguousarray(seg['p'], dtype=np.float64)
+    sc = np.ascontiguousarray(seg['cov'], dtype=np.float64)
+    sx2 = np.ascontiguousarray(seg['chi2'], dtype=np.float64)
+    so = np.ascontiguousarray(seg['hit_off'], dtype=np.int64)
+    si = np.ascontiguousarray(seg['hit_ids'], dtype=np.int64)
+    link = np.zeros(ns, np.int32); bi = np.zeros(ns, np.int32); bo = np.zeros(ns, np.int32)
+    ci = np.zeros(ns); ci2 = np.zeros(ns); co = np.zeros(ns); co2 = np.zeros(ns)
+    out = C.POINTER(Result)()
+    i32 = lambda a: _ptr(a, C.c_int32)
+    f64 = lambda a: _ptr(a, C.c_double)
+    lib().orc_merge(C.byref(g), C.byref(P), ev.n, f64(x), f64(y), f64(z), _ptr(row, C.c_int16), ns, i32(sec),
+                    f64(xr), f64(sp), f64(sc), f64(sx2), _ptr(so, C.c_int64), _ptr(si, C.c_int64), i32(link),
+                    i32(bi), f64(ci), f64(ci2), i32(bo), f64(co), f64(co2), C.byref(out))
+    r = out.contents
+    nt = r.n_tracks
+    res = dict(link=link, best_in=bi, chi_in=ci, chi_in2=ci2, best_out=bo, chi_out=co, chi_out2=co2,
+               head=_arr(r.trk_seed, nt, np.int64), sector=_arr(r.trk_sector, nt, np.int32),
+               x_ref=_arr(r.trk_xref, nt, np.float64), p=_arr(r.trk_p, 5 * nt, np.float64).reshape(nt, 5),
+               cov=_arr(r.trk_cov, 15 * nt, np.float64).reshape(nt, 15),
+               chi2=_arr(r.trk_chi2, nt, np.float64), ndf=_arr(r.trk_ndf, nt, np.int32),
+               hit_off=_arr(r.hit_off, nt + 1, np.int64), hit_ids=_arr(r.hit_ids, int(r.hit_off[nt]), np.int64))
     lib().orc_result_free(out)
     return res
 

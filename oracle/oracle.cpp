@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 namespace {
@@ -595,6 +596,305 @@ orc_result* run_pipeline(const orc_geometry& g, const orc_params& P, int64_t n, 
 }
 
 // ---------------------------------------------------------------------------
+// Sector track merger.  The paper processes the TPC sectors independently
+// and merges their track segments afterwards (Sec. "Track reconstruction in
+// the TPC"); its rules are not given, so every rule below is a reading.
+//
+// Rotation of a state from the frame of one sector into a frame turned by
+// dalpha about z (ca = cos dalpha, sa = sin dalpha).  The point (x, y) of
+// the track becomes (x ca + y sa, -x sa + y ca); the direction angle drops
+// by dalpha, so s' = s ca - c sa with c = +sqrt(1 - s^2) (tracks move
+// outward in x); z, tan(lambda) and q/pT are unchanged.  The new state
+// lives on the plane x' of the rotated point.  Its covariance is J C J^T
+// with J the Jacobian at that fixed plane: a shift dy of the old point
+// moves the new point by (sa, ca) dy, and bringing it back to the plane x'
+// along the track (slope tan phi' = s'/c' in y, t/c' in z, curvature kap in
+// s) gives
+//   dy'/dy = ca - (s'/c') sa,  dz'/dy = -(t/c') sa,  ds'/dy = -kap sa,
+//   ds'/ds = ca + sa s/c,  and 1 on the diagonal for z, t, k.
+template <class R>
+bool rotate_state(R& x, R p[5], R C[15], R ca, R sa, const Model<R>& m, R* Jout = nullptr) {
+  const R s = p[2];
+  const R c = Sqrt(R(1.0) - s * s);
+  const R s2 = s * ca - c * sa;
+  if (!(Abs(s2) < m.sin_max)) return false;
+  const R c2 = Sqrt(R(1.0) - s2 * s2);
+  const R kap = m.kfac * p[4];
+  const R x2 = x * ca + p[0] * sa;
+  const R y2 = -(x * sa) + p[0] * ca;
+  R J[25];
+  for (int i = 0; i < 25; ++i) J[i] = R(0.0);
+  J[0 * 5 + 0] = ca - (s2 / c2) * sa;
+  J[1 * 5 + 0] = -(p[3] / c2) * sa;
+  J[1 * 5 + 1] = R(1.0);
+  J[2 * 5 + 0] = -kap * sa;
+  J[2 * 5 + 2] = ca + sa * (s / c);
+  J[3 * 5 + 3] = R(1.0);
+  J[4 * 5 + 4] = R(1.0);
+  R T[25], Cn[15];
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j) {
+      R acc = R(0.0);
+      for (int k = 0; k < 5; ++k) acc = acc + J[i * 5 + k] * C[ix(k, j)];
+      T[i * 5 + j] = acc;
+    }
+  for (int i = 0; i < 5; ++i)
+    for (int j = i; j < 5; ++j) {
+      R acc = R(0.0);
+      for (int k = 0; k < 5; ++k) acc = acc + T[i * 5 + k] * J[j * 5 + k];
+      Cn[ix(i, j)] = acc;
+    }
+  for (int i = 0; i < 15; ++i) C[i] = Cn[i];
+  x = x2;
+  p[0] = y2;
+  p[2] = s2;
+  if (Jout) for (int i = 0; i < 25; ++i) Jout[i] = J[i];
+  return true;
+}
+
+// Centre angle of a sector's frame (R-1: wedge w = s mod 18 centred at
+// (w + 1/2) 20 degrees), and the turn from frame a to frame b in (-pi, pi].
+double sector_alpha(int s, int n_sectors) {
+  const int nw = n_sectors / 2;
+  return ((s % nw) + 0.5) * (2.0 * M_PI / nw);
+}
+double frame_turn(int sa, int sb, int n_sectors) {
+  double d = sector_alpha(sb, n_sectors) - sector_alpha(sa, n_sectors);
+  while (d > M_PI) d -= 2.0 * M_PI;
+  while (d <= -M_PI) d += 2.0 * M_PI;
+  return d;
+}
+
+// Match chi2 of two 5-vectors' difference under the covariance M (packed):
+// Delta^T M^-1 Delta by Cholesky decomposition.  Returns false if M is not
+// positive definite.
+bool match_chi2(const double d[5], const double M[15], double& chi2) {
+  double L[5][5] = {};
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double acc = M[ix(i, j)];
+      for (int k = 0; k < j; ++k) acc -= L[i][k] * L[j][k];
+      if (i == j) {
+        if (!(acc > 0.0)) return false;
+        L[i][i] = std::sqrt(acc);
+      } else {
+        L[i][j] = acc / L[j][j];
+      }
+    }
+  double w[5];
+  chi2 = 0.0;
+  for (int i = 0; i < 5; ++i) {
+    double acc = d[i];
+    for (int k = 0; k < i; ++k) acc -= L[i][k] * w[k];
+    w[i] = acc / L[i][i];
+    chi2 += w[i] * w[i];
+  }
+  return true;
+}
+
+// The merger on one event (FP64), in the order of the rules:
+//  1. exit state of every segment: its state at the innermost hit transported
+//     (in its own frame) to the plane of its outermost hit's x;
+//  2. a pair (a inner, b outer) is a candidate iff a and b lie in sectors of
+//     the same side whose wedges are adjacent, a's last pad row is below b's
+//     first, and a's outermost hit lies within merge_dist of b's innermost
+//     hit both in the transverse plane and in z;
+//  3. its match chi2: a's exit state rotated into b's frame and transported
+//     to b's reference plane, compared with b's state: Delta^T (C_a + C_b)^-1
+//     Delta over the five parameters; a candidate is valid iff the rotation
+//     and transport succeed and chi2 <= chi2_merge;
+//  4. every segment takes its best valid partner on each side (smallest
+//     chi2, ties by the smaller segment index); a link a -> b is kept iff b
+//     is a's best outer and a is b's best inner partner;
+//  5. links form chains (a segment has at most one inner and one outer
+//     partner, rows increase along a chain); each chain of two or more
+//     segments is refitted as one track (refit_chain); chains whose refit
+//     fails stay split into their segments.
+// Output in the order of the segments: a segment without an inner link
+// emits its chain (or, if unmerged, itself); the others are emitted with
+// their chain.
+template <class R>
+bool refit_chain(const orc_geometry& g, const orc_params& P, const Model<R>& m,
+                 const std::vector<int>& chain, const std::vector<int>& sec,
+                 const std::vector<std::vector<int64_t>>& hits, const double* x, const double* y,
+                 const double* z, R k0, R p[5], R C[15], R& chi2, R& xref);
+
+struct MergeOut {
+  std::vector<int> link, best_in, best_out;
+  std::vector<double> chi_in, chi_in2, chi_out, chi_out2;
+  // merged tracks
+  std::vector<int64_t> head;
+  std::vector<int32_t> sector, ndf;
+  std::vector<double> xref, p, cov, chi2;
+  std::vector<int64_t> hit_off, hit_ids;
+};
+
+MergeOut merge_segments(const orc_geometry& g, const orc_params& P, const double* x, const double* y,
+                        const double* z, const int16_t* row, int64_t nseg, const int32_t* ssec,
+                        const double* sxref, const double* sp, const double* scov, const double* schi2,
+                        const int64_t* soff, const int64_t* sids) {
+  const Model<double> m = make_model<double>(g, P);
+  const int S = g.n_sectors, NW = S / 2;
+  const double INF = std::numeric_limits<double>::infinity();
+  std::vector<std::vector<int64_t>> hits(nseg);
+  std::vector<int> sec(nseg), rlo(nseg), rhi(nseg);
+  std::vector<bool> has_exit(nseg, false);
+  std::vector<double> ex(nseg), ep((size_t)nseg * 5), ec((size_t)nseg * 15);
+  for (int64_t i = 0; i < nseg; ++i) {
+    hits[i].assign(sids + soff[i], sids + soff[i + 1]);
+    sec[i] = ssec[i];
+    rlo[i] = row[hits[i].front()];
+    rhi[i] = row[hits[i].back()];
+    // 1. exit state
+    double q[5], Q[15];
+    for (int k = 0; k < 5; ++k) q[k] = sp[i * 5 + k];
+    for (int k = 0; k < 15; ++k) Q[k] = scov[i * 15 + k];
+    const double xo = x[hits[i].back()];
+    if (transport(q, Q, sxref[i], xo, m)) {
+      has_exit[i] = true;
+      ex[i] = xo;
+      for (int k = 0; k < 5; ++k) ep[i * 5 + k] = q[k];
+      for (int k = 0; k < 15; ++k) ec[i * 15 + k] = Q[k];
+    }
+  }
+  MergeOut o;
+  o.link.assign(nseg, -1);
+  o.best_in.assign(nseg, -1); o.best_out.assign(nseg, -1);
+  o.chi_in.assign(nseg, INF); o.chi_in2.assign(nseg, INF);
+  o.chi_out.assign(nseg, INF); o.chi_out2.assign(nseg, INF);
+  auto offer = [&](int& best, double& bchi, double& bchi2, int cand, double chi) {
+    if (chi < bchi || (chi == bchi && cand < best)) {
+      bchi2 = bchi;
+      bchi = chi;
+      best = cand;
+    } else if (chi < bchi2) {
+      bchi2 = chi;
+    }
+  };
+  for (int64_t a = 0; a < nseg; ++a) {
+    if (!has_exit[a]) continue;
+    for (int64_t b = 0; b < nseg; ++b) {
+      // 2. candidate
+      const bool same_side = (sec[a] < NW) == (sec[b] < NW);
+      const int wa = sec[a] % NW, wb = sec[b] % NW;
+      const bool adjacent = (wb == (wa + 1) % NW) || (wa == (wb + 1) % NW);
+      if (!same_side || !adjacent || !(rhi[a] < rlo[b])) continue;
+      const double turn = frame_turn(sec[a], sec[b], S);
+      const double ca = std::cos(turn), sa = std::sin(turn);
+      const int64_t ha = hits[a].back(), hb = hits[b].front();
+      const double xa = x[ha] * ca + y[ha] * sa, ya = -(x[ha] * sa) + y[ha] * ca;
+      const double dr = std::sqrt((xa - x[hb]) * (xa - x[hb]) + (ya - y[hb]) * (ya - y[hb]));
+      if (!(dr <= P.merge_dist && std::fabs(z[ha] - z[hb]) <= P.merge_dist)) continue;
+      // 3. match chi2
+      double xx = ex[a], q[5], Q[15];
+      for (int k = 0; k < 5; ++k) q[k] = ep[a * 5 + k];
+      for (int k = 0; k < 15; ++k) Q[k] = ec[a * 15 + k];
+      if (!rotate_state(xx, q, Q, ca, sa, m)) continue;
+      if (!transport(q, Q, xx, sxref[b], m)) continue;
+      double d[5], M[15], chi;
+      for (int k = 0; k < 5; ++k) d[k] = q[k] - sp[b * 5 + k];
+      for (int k = 0; k < 15; ++k) M[k] = Q[k] + scov[b * 15 + k];
+      if (!match_chi2(d, M, chi) || !(chi <= P.chi2_merge)) continue;
+      // 4. best partners
+      offer(o.best_out[a], o.chi_out[a], o.chi_out2[a], (int)b, chi);
+      offer(o.best_in[b], o.chi_in[b], o.chi_in2[b], (int)a, chi);
+    }
+  }
+  std::vector<int> inner(nseg, -1);
+  for (int64_t a = 0; a < nseg; ++a) {
+    const int b = o.best_out[a];
+    if (b >= 0 && o.best_in[b] == a) { o.link[a] = b; inner[b] = (int)a; }
+  }
+  // 5. chains and their refit
+  o.hit_off.push_back(0);
+  auto emit_one = [&](int i) {
+    o.head.push_back(i);
+    o.sector.push_back(sec[i]);
+    o.xref.push_back(sxref[i]);
+    for (int k = 0; k < 5; ++k) o.p.push_back(sp[i * 5 + k]);
+    for (int k = 0; k < 15; ++k) o.cov.push_back(scov[i * 15 + k]);
+    o.chi2.push_back(schi2[i]);
+    o.ndf.push_back(2 * (int)hits[i].size() - 5);
+    for (int64_t h : hits[i]) o.hit_ids.push_back(h);
+    o.hit_off.push_back((int64_t)o.hit_ids.size());
+  };
+  for (int64_t i = 0; i < nseg; ++i) {
+    if (inner[i] >= 0) continue;
+    std::vector<int> chain{(int)i};
+    while (o.link[chain.back()] >= 0) chain.push_back(o.link[chain.back()]);
+    if (chain.size() == 1) { emit_one((int)i); continue; }
+    double p[5], C[15], chi2, xr;
+    const double k0 = sp[(size_t)chain.back() * 5 + 4];
+    if (!refit_chain(g, P, m, chain, sec, hits, x, y, z, k0, p, C, chi2, xr)) {
+      for (int c : chain) emit_one(c);
+      continue;
+    }
+    o.head.push_back(i);
+    o.sector.push_back(sec[i]);
+    o.xref.push_back(xr);
+    for (int k = 0; k < 5; ++k) o.p.push_back(p[k]);
+    for (int k = 0; k < 15; ++k) o.cov.push_back(C[k]);
+    o.chi2.push_back(chi2);
+    int64_t n = 0;
+    for (int c : chain) {
+      for (int64_t h : hits[c]) o.hit_ids.push_back(h);
+      n += (int64_t)hits[c].size();
+    }
+    o.ndf.push_back(2 * (int)n - 5);
+    o.hit_off.push_back((int64_t)o.hit_ids.size());
+  }
+  return o;
+}
+
+// Refit of a chain of segments (innermost first) as one track: the final fit
+// of the selection step over all its hits, outermost first (state at the
+// outermost hit, direction from the chord to the hit two positions inward,
+// q/pT prior k0, initial covariance as there), crossing each segment
+// boundary by rotating the state into the next inner segment's frame;
+// result at the innermost hit.
+template <class R>
+bool refit_chain(const orc_geometry& g, const orc_params& P, const Model<R>& m,
+                 const std::vector<int>& chain, const std::vector<int>& sec,
+                 const std::vector<std::vector<int64_t>>& hits, const double* x, const double* y,
+                 const double* z, R k0, R p[5], R C[15], R& chi2, R& xref) {
+  const int S = g.n_sectors;
+  // outermost segment's hits, outermost first
+  int ci = (int)chain.size() - 1;
+  const std::vector<int64_t>* hl = &hits[chain[ci]];
+  int hi = (int)hl->size() - 1;
+  if (hi < 2) return false;
+  auto X = [&](int64_t h) { return R(x[h]); };
+  auto Y = [&](int64_t h) { return R(y[h]); };
+  auto Z = [&](int64_t h) { return R(z[h]); };
+  const int64_t h0 = (*hl)[hi], h2 = (*hl)[hi - 2];
+  R s, t;
+  chord_dir(X(h2), Y(h2), Z(h2), X(h0), Y(h0), Z(h0), s, t);
+  p[0] = Y(h0); p[1] = Z(h0); p[2] = s; p[3] = t; p[4] = k0;
+  init_cov(C, P);
+  chi2 = R(0.0);
+  if (!(Abs(s) < m.sin_max)) return false;
+  R xc = X(h0);
+  --hi;
+  while (true) {
+    for (; hi >= 0; --hi) {
+      const int64_t h = (*hl)[hi];
+      if (!transport(p, C, xc, X(h), m)) return false;
+      kf_update(p, C, Y(h), Z(h), m.vy, m.vz, chi2);
+      xc = X(h);
+    }
+    if (ci == 0) break;
+    // into the frame of the next inner segment
+    const double turn = frame_turn(sec[chain[ci]], sec[chain[ci - 1]], S);
+    if (!rotate_state(xc, p, C, R(std::cos(turn)), R(std::sin(turn)), m)) return false;
+    --ci;
+    hl = &hits[chain[ci]];
+    hi = (int)hl->size() - 1;
+  }
+  xref = xc;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Calibration correction (applied to default-transformed clusters):
 //  drift: with side = +1 for A-side sectors (first half), -1 otherwise,
 //         side*z' = L - (1 + delta_s) * (L - side*z - tau_s);
@@ -749,6 +1049,8 @@ void orc_default_params(orc_params* p) {
   p->sigma_z = 0.15f;
   p->sigma_vertex = 0.01f;
   p->sigma_tgl = 1e-3f;
+  p->chi2_merge = 50.0f;
+  p->merge_dist = 20.0f;
 }
 
 int orc_transport(int precision, const double pin[5], const double Cin[15], double x0, double x1,
@@ -876,6 +1178,82 @@ void orc_calib_apply(const orc_geometry* g, int64_t n, const uint8_t* sector, co
                      const double* y, const double* z, const double* theta, double* xo,
                      double* zo) {
   for (int64_t i = 0; i < n; ++i) calib_point<double>(*g, sector[i], x[i], y[i], z[i], theta, xo[i], zo[i]);
+}
+
+int orc_rotate(int precision, double x, const double p[5], const double C[15], double dalpha, double bz,
+               double sin_max, double* out_x, double out_p[5], double out_C[15], double J[25]) {
+  orc_geometry g{};
+  g.bz = (float)bz;
+  orc_params P{};
+  orc_default_params(&P);
+  P.sin_max = (float)sin_max;
+  if (precision == 32) {
+    Model<float> m = make_model<float>(g, P);
+    m.sin_max = (float)sin_max;
+    float xx = (float)x, q[5], Q[15], Jf[25];
+    for (int i = 0; i < 5; ++i) q[i] = (float)p[i];
+    for (int i = 0; i < 15; ++i) Q[i] = (float)C[i];
+    if (!rotate_state(xx, q, Q, (float)std::cos(dalpha), (float)std::sin(dalpha), m, Jf)) return 0;
+    *out_x = xx;
+    for (int i = 0; i < 5; ++i) out_p[i] = q[i];
+    for (int i = 0; i < 15; ++i) out_C[i] = Q[i];
+    for (int i = 0; i < 25; ++i) J[i] = Jf[i];
+    return 1;
+  }
+  Model<double> m = make_model<double>(g, P);
+  m.sin_max = sin_max;
+  double xx = x, q[5], Q[15];
+  for (int i = 0; i < 5; ++i) q[i] = p[i];
+  for (int i = 0; i < 15; ++i) Q[i] = C[i];
+  if (!rotate_state(xx, q, Q, std::cos(dalpha), std::sin(dalpha), m, J)) return 0;
+  *out_x = xx;
+  for (int i = 0; i < 5; ++i) out_p[i] = q[i];
+  for (int i = 0; i < 15; ++i) out_C[i] = Q[i];
+  return 1;
+}
+
+int orc_merge(const orc_geometry* g, const orc_params* P, int64_t n_clusters, const double* x,
+              const double* y, const double* z, const int16_t* row, int64_t n_seg,
+              const int32_t* seg_sector, const double* seg_xref, const double* seg_p,
+              const double* seg_cov, const double* seg_chi2, const int64_t* seg_hit_off,
+              const int64_t* seg_hit_ids, int32_t* link, int32_t* best_in, double* chi_in, double* chi_in2,
+              int32_t* best_out, double* chi_out, double* chi_out2, orc_result** out) {
+  (void)n_clusters;
+  MergeOut o = merge_segments(*g, *P, x, y, z, row, n_seg, seg_sector, seg_xref, seg_p, seg_cov, seg_chi2,
+                              seg_hit_off, seg_hit_ids);
+  for (int64_t i = 0; i < n_seg; ++i) {
+    link[i] = o.link[i]; best_in[i] = o.best_in[i]; best_out[i] = o.best_out[i];
+    chi_in[i] = o.chi_in[i]; chi_in2[i] = o.chi_in2[i]; chi_out[i] = o.chi_out[i]; chi_out2[i] = o.chi_out2[i];
+  }
+  orc_result* r = (orc_result*)std::calloc(1, sizeof(orc_result));
+  const int64_t nt = (int64_t)o.head.size();
+  r->n_tracks = nt;
+  auto c64 = [](const std::vector<int64_t>& v) {
+    int64_t* q = (int64_t*)std::malloc(sizeof(int64_t) * std::max<size_t>(v.size(), 1));
+    std::memcpy(q, v.data(), sizeof(int64_t) * v.size());
+    return q;
+  };
+  auto cd = [](const std::vector<double>& v) {
+    double* q = (double*)std::malloc(sizeof(double) * std::max<size_t>(v.size(), 1));
+    std::memcpy(q, v.data(), sizeof(double) * v.size());
+    return q;
+  };
+  auto c32 = [](const std::vector<int32_t>& v) {
+    int32_t* q = (int32_t*)std::malloc(sizeof(int32_t) * std::max<size_t>(v.size(), 1));
+    std::memcpy(q, v.data(), sizeof(int32_t) * v.size());
+    return q;
+  };
+  r->trk_seed = c64(o.head);
+  r->trk_sector = c32(o.sector);
+  r->trk_xref = cd(o.xref);
+  r->trk_p = cd(o.p);
+  r->trk_cov = cd(o.cov);
+  r->trk_chi2 = cd(o.chi2);
+  r->trk_ndf = c32(o.ndf);
+  r->hit_off = c64(o.hit_off);
+  r->hit_ids = c64(o.hit_ids);
+  *out = r;
+  return 0;
 }
 
 void orc_calib_apply32(const orc_geometry* g, int64_t n, const uint8_t* sector, const float* x,

@@ -48,6 +48,9 @@ typedef struct {
   float sigma_y, sigma_z;    /* cluster errors, cm */
   float sigma_vertex;        /* vertex pseudo-measurement error, cm */
   float sigma_tgl;           /* external tan(lambda) error */
+  float chi2_merge;          /* segment merging: accept a pair iff its match chi2 <= chi2_merge */
+  float merge_dist;          /* segment merging: outer hit of the inner segment within this
+                                transverse and z distance (cm) of the inner hit of the outer one */
 } orc_params;
 
 void orc_default_params(orc_params* p);
@@ -104,6 +107,32 @@ int orc_track(int precision, const orc_geometry* g, const orc_params* P, int64_t
               const double* x, const double* y, const double* z, const int16_t* row,
               const uint8_t* sector, const uint8_t* sector_mask, orc_result** out);
 void orc_result_free(orc_result* r);
+
+/* ---- sector track merger (FP64) --------------------------------------------
+ * Joins the per-sector track segments of one event that continue each other
+ * across the boundary of two adjacent sectors on the same side (see
+ * merge_segments for the rules), and refits each joined chain.  Segments are
+ * given as the tracking output: sector, x_ref, p[5], cov[15] at the
+ * innermost hit, hit lists (cluster ids, ascending row) indexing the
+ * clusters (x, y, z, row).  Outputs: link[i] = the outer partner of segment
+ * i or -1; per segment the best inner / outer candidate, its match chi2 and
+ * the second-best chi2 (inf if none) -- what decides each link; and the
+ * merged tracks in out (trk_seed = the index of the chain's innermost
+ * segment, sector, x_ref, p, cov, chi2, ndf, hit lists innermost segment
+ * first).  Returns 0. */
+int orc_merge(const orc_geometry* g, const orc_params* P, int64_t n_clusters, const double* x,
+              const double* y, const double* z, const int16_t* row, int64_t n_seg,
+              const int32_t* seg_sector, const double* seg_xref, const double* seg_p,
+              const double* seg_cov, const double* seg_chi2, const int64_t* seg_hit_off,
+              const int64_t* seg_hit_ids, int32_t* link, int32_t* best_in, double* chi_in, double* chi_in2,
+              int32_t* best_out, double* chi_out, double* chi_out2, orc_result** out);
+
+/* Rotation of a state at plane x from the frame of one sector to a frame
+ * turned by dalpha (radians) about z: writes the new plane, state,
+ * covariance and the 5x5 Jacobian (row-major).  Returns 1 on success, 0 if
+ * |sin phi| in the new frame would reach sin_max.  precision 32 or 64. */
+int orc_rotate(int precision, double x, const double p[5], const double C[15], double dalpha, double bz,
+               double sin_max, double* out_x, double out_p[5], double out_C[15], double J[25]);
 
 /* ---- calibration (FP64) ---------------------------------------------------
  * theta layout: [0,36) drift scale delta, [36,72) time offset tau (cm),

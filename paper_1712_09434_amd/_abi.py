@@ -50,7 +50,7 @@ class tpcca_params(C.Structure):
                 ("max_gap", C.c_int32), ("min_seed_hits", C.c_int32), ("min_hits", C.c_int32),
                 ("owned_num", C.c_int32), ("owned_den", C.c_int32), ("sin_max", C.c_float),
                 ("sigma_y", C.c_float), ("sigma_z", C.c_float), ("sigma_vertex", C.c_float),
-                ("sigma_tgl", C.c_float)]
+                ("sigma_tgl", C.c_float), ("chi2_merge", C.c_float), ("merge_dist", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -266,7 +266,8 @@ int check_params(const tpcca_params* p) {
   if (!(p->win_y > 0 && p->win_z > 0 && p->inv_var_y > 0 && p->inv_var_z > 0 && p->link_cut > 0 &&
         p->chi2_ext > 0 && p->max_gap >= 0 && p->min_seed_hits >= 3 && p->min_hits >= 3 &&
         p->owned_num >= 0 && p->owned_den > 0 && p->sin_max > 0 && p->sin_max < 1 &&
-        p->sigma_y > 0 && p->sigma_z > 0 && p->sigma_vertex > 0 && p->sigma_tgl > 0))
+        p->sigma_y > 0 && p->sigma_z > 0 && p->sigma_vertex > 0 && p->sigma_tgl > 0 &&
+        p->chi2_merge > 0 && p->merge_dist > 0))
     return TPCCA_E_INVALID;
   return TPCCA_OK;
 }
@@ -299,6 +300,8 @@ void tpcca_default_params(tpcca_params* p) {
   p->sigma_z = 0.15f;
   p->sigma_vertex = 0.01f;
   p->sigma_tgl = 1e-3f;
+  p->chi2_merge = 50.0f;
+  p->merge_dist = 20.0f;
 }
 
 int tpcca_create(const tpcca_geometry* g, const tpcca_field* f, tpcca_ctx** out) {
