@@ -118,6 +118,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(ev, args)
 
+    merge = merge_leg(trk, (x, y, z, row, sec), out, args)
     batch = None if args.no_batch else batch_leg(args, Tracker, dev)
     grad = None if args.no_grad else grad_leg(Tracker, dev)
 
@@ -132,6 +133,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
+        "merge": merge,
         "batch": batch,
         "grad": grad,
     }
@@ -391,6 +393,25 @@ def batch_leg(args, Tracker, dev):
             "gain": t_seq / t_batch, "batched_clusters_per_s": n / t_batch,
             "batched_tuning": {"tracklet_grid": best["tracklet_grid"], "use_graph": best["use_graph"]},
             "sequential_tuning": {"tracklet_grid": seq_best[1], "use_graph": seq_best[2]}}
+
+
+def merge_leg(trk, cl, seg, args, reps=20):
+    """tpcca_merge on the segments of the timed event (the step after
+    tracking: segments joined across sector boundaries, chains refitted)."""
+    import torch
+    trk.set_phase_timing(False)
+    for _ in range(3):
+        m, links = trk.merge(seg, cl, links=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m = trk.merge(seg, cl)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    nl = int((links >= 0).sum())
+    log(f"merge: {seg.n_tracks} segments -> {m.n_tracks} tracks ({nl} links) in {dt * 1e3:.3f} ms")
+    return {"segments": seg.n_tracks, "tracks": m.n_tracks, "links": nl, "ms_per_call": dt * 1e3,
+            "segments_per_s": seg.n_tracks / dt}
 
 
 def grad_leg(Tracker, dev, n_events=20):

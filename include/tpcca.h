@@ -234,6 +234,36 @@ int tpcca_set_calib(tpcca_ctx* ctx, const tpcca_calib* calib);
 int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* events,
                       tpcca_tracks* out);
 
+/* Sector track merger (Sec. "Track reconstruction in the TPC": sectors are
+ * tracked independently and their segments merged afterwards; the refit of
+ * the merged tracks runs on the GPU).  segments: the output of tpcca_track
+ * for one event (n_tracks, sector, x_ref, p, cov, chi2, ndf, hit_off,
+ * hit_id) with segments->clusters the event's clusters (x, y, z, row);
+ * all device memory.  Two segments are joined when they continue each
+ * other across the boundary of adjacent wedges of one side: the inner one
+ * ends on a lower pad row than the outer one starts, its outermost hit lies
+ * within params.merge_dist (cm, transverse and z) of the outer one's
+ * innermost hit, and its state, transported to its outermost hit, rotated
+ * into the outer segment's frame and transported to that segment's
+ * reference plane, matches the outer segment's state with
+ * Delta^T (C_in + C_out)^-1 Delta <= params.chi2_merge; each segment keeps
+ * its best such partner on each side and a link needs both ends to agree.
+ * Each chain of linked segments is refitted as one track (outermost hit
+ * first, the state rotated into the next segment's frame at each boundary,
+ * q/pT prior = the outermost segment's, result at the innermost hit, ndf =
+ * 2 n - 5; FP32, the first TPCCA_GRAD_C2_UPDATES updates compensated); a
+ * chain whose refit fails stays split.  Output (merged, device memory):
+ * tracks in the order of the segments, a chain where its innermost segment
+ * was, sector = that segment's, hits innermost segment first (ascending pad
+ * row); unmerged segments are copied unchanged.  The output needs
+ * cap_tracks >= segments->n_tracks and cap_hits >= the segments' hits (else
+ * TPCCA_E_CAPACITY with those sizes in n_tracks / n_hits); on return
+ * n_tracks / n_hits hold the merged counts.  seg_link (optional, device,
+ * [segments->n_tracks]) receives each segment's outer partner or -1.
+ * TPCCA_E_INVALID for host memory, null arrays, a segment with fewer than
+ * 3 hits, a bad sector or hit id. */
+int tpcca_merge(tpcca_ctx* ctx, const tpcca_tracks* segments, tpcca_tracks* merged, int32_t* seg_link);
+
 /* Calibration objective and gradient (Sec. "Approach for online
  * calibration"; Sec. "Overview of HLT online calibration"): apply the
  * correction theta to the default-transformed clusters tracks->clusters,

@@ -32,7 +32,7 @@ EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_g
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
             "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc",
-            "tpcca_set_calib"]
+            "tpcca_set_calib", "tpcca_merge"]
 
 
 class tpcca_geometry(C.Structure):
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
     L.tpcca_set_params.argtypes = [C.c_void_p, P(tpcca_params)]
     L.tpcca_get_params.argtypes = [C.c_void_p, P(tpcca_params)]
     L.tpcca_track.argtypes = [C.c_void_p, P(tpcca_clusters), P(tpcca_tracks)]
+    L.tpcca_merge.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_tracks), C.c_void_p]
+    L.tpcca_merge.restype = C.c_int
     L.tpcca_set_calib.argtypes = [C.c_void_p, P(tpcca_calib)]
     L.tpcca_set_calib.restype = C.c_int
     L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]

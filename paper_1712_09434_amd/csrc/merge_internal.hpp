@@ -1,0 +1,58 @@
+// merge_internal.hpp -- workspace of the sector track merger (not ABI).
+#pragma once
+#include "internal.hpp"
+
+namespace tpcca {
+
+struct MergeWs {
+  int64_t T;               // segments
+  int64_t H;               // their hits (= hits of the merged output)
+  int S, NW, R;            // sectors, wedges per side, pad rows
+  Model m;                 // field, sin phi limit, cluster variances
+  float chi2_merge, merge_dist;
+  float ca, sa;            // cos and sin of the turn between adjacent wedges
+  // segments (the tracking output) and the clusters their hit ids index
+  const uint8_t* sector;
+  const float* x_ref;
+  const float* p;          // [T][5]
+  const float* cov;        // [T][15]
+  const float* chi2;
+  const int32_t* ndf;
+  const int32_t* hit_off;  // [T + 1]
+  const uint32_t* hit_id;
+  const float* cx;
+  const float* cy;
+  const float* cz;
+  const int16_t* crow;
+  int64_t NC;
+  // work
+  float* ex;               // [T][24]: exit plane, state, covariance (if the exit transport succeeded)
+  float4* first;           // [T] innermost hit (x, y, z, row bits)
+  float4* last;            // [T] outermost hit (x, y, z, row bits)
+  uint32_t* flags;         // [T] bit 0: exit state valid
+  uint32_t* sec_cnt;       // [S + 1] segments per sector, then offsets
+  uint32_t* sec_cur;       // [S] fill cursors
+  uint32_t* sec_list;      // [T] segment indices by sector
+  unsigned long long* best_in;   // [T] (chi2 bits << 32) | inner partner, or ~0
+  unsigned long long* best_out;  // [T] (chi2 bits << 32) | outer partner, or ~0
+  int32_t* link;           // [T] outer partner or -1
+  int32_t* inner;          // [T] inner partner or -1
+  uint32_t* emit;          // [T + 1] output tracks of the chain headed by a segment -> offsets
+  uint32_t* hemit;         // [T + 1] hits of those tracks -> offsets
+  float* rec;              // [T][24]: merged refit of a chain head (x_ref, p, cov, chi2)
+  uint32_t* err;           // [4]: error bits, output tracks
+  // outputs (device)
+  uint8_t* o_sector;
+  float* o_x_ref;
+  float* o_p;
+  float* o_cov;
+  float* o_chi2;
+  int32_t* o_ndf;
+  int32_t* o_hit_off;
+  uint32_t* o_hit_id;
+  int32_t* o_link;         // optional [T]
+};
+
+hipError_t run_merge(const MergeWs& w, hipStream_t st);
+
+}  // namespace tpcca

@@ -18,6 +18,7 @@
 
 #include "calib_internal.hpp"
 #include "internal.hpp"
+#include "merge_internal.hpp"
 
 using namespace tpcca;
 
@@ -81,6 +82,9 @@ struct tpcca_ctx {
   // refit_grad scratch
   char* gscratch = nullptr;
   size_t gscratch_bytes = 0;
+  // sector merger scratch
+  char* mscratch = nullptr;
+  size_t mscratch_bytes = 0;
   // installed calibration of the tracking input (device, 66 S floats), or off
   float* cal_d = nullptr;
   bool cal_on = false;
@@ -419,6 +423,7 @@ void tpcca_destroy(tpcca_ctx* c) {
   if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->gscratch) (void)hipFree(c->gscratch);
   if (c->cal_d) (void)hipFree(c->cal_d);
+  if (c->mscratch) (void)hipFree(c->mscratch);
   if (c->row_x_d) (void)hipFree(c->row_x_d);
   delete c;
 }
@@ -937,6 +942,93 @@ int tpcca_refit_grad(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal
       for (int q = 0; q < 64; ++q) g->d_map[(size_t)s * 64 + q] = out[s * kNPar + 2 + q];
     }
   }
+  return TPCCA_OK;
+}
+
+int tpcca_merge(tpcca_ctx* c, const tpcca_tracks* seg, tpcca_tracks* out, int32_t* seg_link) {
+  if (!c) return TPCCA_E_INVALID;
+  if (!seg || !out || !seg->clusters) return fail(c, TPCCA_E_INVALID, "null segments, output or clusters");
+  const tpcca_clusters& k = *seg->clusters;
+  const int64_t T = seg->n_tracks, NC = k.n;
+  if (T < 0 || NC < 0 || T >= ((int64_t)1 << 31)) return fail(c, TPCCA_E_INVALID, "bad sizes");
+  if (seg->mem != TPCCA_MEM_DEVICE || k.mem != TPCCA_MEM_DEVICE || out->mem != TPCCA_MEM_DEVICE)
+    return fail(c, TPCCA_E_INVALID, "the merger takes device memory only");
+  if (!seg->hit_off || (T > 0 && (!seg->sector || !seg->x_ref || !seg->p || !seg->cov || !seg->chi2 || !seg->ndf ||
+                                  !seg->hit_id)))
+    return fail(c, TPCCA_E_INVALID, "null segment array");
+  if (NC > 0 && (!k.x || !k.y || !k.z || !k.row)) return fail(c, TPCCA_E_INVALID, "null cluster array");
+  if (!out->hit_off || out->cap_tracks < 0 || out->cap_hits < 0) return fail(c, TPCCA_E_INVALID, "bad output");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+  hipStream_t st = (hipStream_t)k.stream;
+  int32_t ends[2] = {0, 0};
+  if (T > 0) {
+    he = hipMemcpyAsync(&ends[0], seg->hit_off, 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(&ends[1], seg->hit_off + T, 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
+    if (ends[0] != 0 || ends[1] < 0) return fail(c, TPCCA_E_INVALID, "hit_off must start at 0");
+  }
+  const int64_t H = ends[1];
+  // the merged output has at most as many tracks, and exactly as many hits
+  if (out->cap_tracks < T || out->cap_hits < H) {
+    out->n_tracks = T;
+    out->n_hits = H;
+    return fail(c, TPCCA_E_CAPACITY, "merged output needs n_tracks and n_hits of the segments");
+  }
+  if ((T > 0 && (!out->sector || !out->x_ref || !out->p || !out->cov || !out->chi2 || !out->ndf)) ||
+      (H > 0 && !out->hit_id))
+    return fail(c, TPCCA_E_INVALID, "null output array");
+  Layout L;
+  const size_t o_ex = L.take<float>(T * 24), o_first = L.take<float4>(T), o_last = L.take<float4>(T);
+  const size_t o_flags = L.take<uint32_t>(T), o_cnt = L.take<uint32_t>(c->S + 1), o_cur = L.take<uint32_t>(c->S);
+  const size_t o_list = L.take<uint32_t>(T), o_bi = L.take<unsigned long long>(T), o_bo = L.take<unsigned long long>(T);
+  const size_t o_link = L.take<int32_t>(T), o_inner = L.take<int32_t>(T), o_emit = L.take<uint32_t>(T + 1);
+  const size_t o_hemit = L.take<uint32_t>(T + 1), o_rec = L.take<float>(T * 24), o_err = L.take<uint32_t>(4);
+  if (L.off > c->mscratch_bytes) {
+    if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
+    he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
+    if (he != hipSuccess) { c->mscratch = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "merger scratch allocation failed"); }
+    c->mscratch_bytes = L.off + L.off / 4;
+  }
+  char* b = c->mscratch;
+  MergeWs w{};
+  w.T = T; w.H = H; w.S = c->S; w.NW = c->S / 2; w.R = c->R; w.NC = NC;
+  w.m = make_model(c->bz, c->P);
+  w.chi2_merge = c->P.chi2_merge;
+  w.merge_dist = c->P.merge_dist;
+  const double turn = 2.0 * M_PI / (double)w.NW;
+  w.ca = (float)std::cos(turn);
+  w.sa = (float)std::sin(turn);
+  w.sector = seg->sector; w.x_ref = seg->x_ref; w.p = seg->p; w.cov = seg->cov; w.chi2 = seg->chi2;
+  w.ndf = seg->ndf; w.hit_off = seg->hit_off; w.hit_id = seg->hit_id;
+  w.cx = k.x; w.cy = k.y; w.cz = k.z; w.crow = k.row;
+  w.ex = (float*)(b + o_ex); w.first = (float4*)(b + o_first); w.last = (float4*)(b + o_last);
+  w.flags = (uint32_t*)(b + o_flags); w.sec_cnt = (uint32_t*)(b + o_cnt); w.sec_cur = (uint32_t*)(b + o_cur);
+  w.sec_list = (uint32_t*)(b + o_list);
+  w.best_in = (unsigned long long*)(b + o_bi); w.best_out = (unsigned long long*)(b + o_bo);
+  w.link = (int32_t*)(b + o_link); w.inner = (int32_t*)(b + o_inner);
+  w.emit = (uint32_t*)(b + o_emit); w.hemit = (uint32_t*)(b + o_hemit);
+  w.rec = (float*)(b + o_rec); w.err = (uint32_t*)(b + o_err);
+  w.o_sector = out->sector; w.o_x_ref = out->x_ref; w.o_p = out->p; w.o_cov = out->cov; w.o_chi2 = out->chi2;
+  w.o_ndf = out->ndf; w.o_hit_off = out->hit_off; w.o_hit_id = out->hit_id; w.o_link = seg_link;
+  // an empty call still passes valid pointers to the kernels' checks
+  if (T == 0) {
+    w.sector = w.o_sector = (uint8_t*)b; w.x_ref = w.o_x_ref = (float*)b; w.p = w.o_p = (float*)b;
+    w.cov = w.o_cov = (float*)b; w.chi2 = w.o_chi2 = (float*)b; w.ndf = w.o_ndf = (int32_t*)b;
+    w.hit_id = w.o_hit_id = (uint32_t*)b;
+  }
+  if (NC == 0) { w.cx = w.cy = w.cz = (const float*)b; w.crow = (const int16_t*)b; }
+  he = run_merge(w, st);
+  if (he != hipSuccess) return hip_fail(c, he, "merger kernels");
+  uint32_t res[4] = {0, 0, 0, 0};
+  he = hipMemcpyAsync(res, w.err, sizeof(res), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "merger");
+  if (res[0] & 1u) return fail(c, TPCCA_E_INVALID, "a segment has fewer than 3 or more than n_rows hits, or a bad sector");
+  if (res[0] & 2u) return fail(c, TPCCA_E_INVALID, "hit id out of range");
+  out->n_tracks = res[1];
+  out->n_hits = res[2];
   return TPCCA_OK;
 }
 

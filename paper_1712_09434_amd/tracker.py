@@ -181,6 +181,41 @@ class Tracker:
         _check(self.L, self.ctx, self.L.tpcca_track(self.ctx, C.byref(cl), C.byref(st)))
         return self._slice(st, o, int(x.shape[0]))
 
+    def merge(self, seg: Tracks, clusters: tuple, links: bool = False):
+        """tpcca_merge: the sector merger on the tracks `seg` of one event
+        (device tensors, as returned by track) whose hit ids index
+        `clusters` (x, y, z, row, sector).  Returns the merged Tracks (their
+        k_prior is not set), and with links=True also each segment's outer
+        partner (int32, -1 for none)."""
+        cl = self.clusters_struct(*clusters)
+        T = seg.n_tracks
+        dev = seg.x_ref.device
+        st = A.tpcca_tracks()
+        st.n_tracks = T
+        keep = {k: getattr(seg, k).contiguous() for k in ("sector", "x_ref", "p", "cov", "chi2", "ndf",
+                                                          "hit_off", "hit_id")}
+        for k, v in keep.items():
+            setattr(st, k, _ptr(v))
+        st.clusters = C.pointer(cl)
+        st.mem = _mem(seg.hit_off)
+        H = int(seg.hit_id.numel())
+        f32 = dict(dtype=torch.float32, device=dev)
+        o = dict(sector=torch.empty(max(T, 1), dtype=torch.uint8, device=dev), x_ref=torch.empty(max(T, 1), **f32),
+                 p=torch.empty(max(T, 1), 5, **f32), cov=torch.empty(max(T, 1), 15, **f32),
+                 chi2=torch.empty(max(T, 1), **f32), ndf=torch.empty(max(T, 1), dtype=torch.int32, device=dev),
+                 k_prior=torch.zeros(max(T, 1), **f32),
+                 hit_off=torch.empty(T + 1, dtype=torch.int32, device=dev),
+                 hit_id=torch.empty(max(H, 1), dtype=torch.int32, device=dev))
+        out = A.tpcca_tracks()
+        out.cap_tracks, out.cap_hits = T, H
+        for k in ("sector", "x_ref", "p", "cov", "chi2", "ndf", "hit_off", "hit_id"):
+            setattr(out, k, _ptr(o[k]))
+        out.mem = _mem(o["hit_off"])
+        lk = torch.empty(max(T, 1), dtype=torch.int32, device=dev) if links else None
+        _check(self.L, self.ctx, self.L.tpcca_merge(self.ctx, C.byref(st), C.byref(out), _ptr(lk)))
+        m = self._slice(out, o, 0)
+        return (m, lk[:T]) if links else m
+
     def track_batch(self, events: Sequence[tuple], taps: bool = False) -> List[Tracks]:
         E = len(events)
         cls = (A.tpcca_clusters * E)()
