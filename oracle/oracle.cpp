@@ -238,6 +238,84 @@ void kf_update(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
   chi2 = chi2 + Fma(r1, Fma(I11, r1, I01 * r0), r0 * Fma(I01, r1, I00 * r0));
 }
 
+// The first Kalman updates of a fit, whose prior is nearly diffuse (q/pT
+// variance 100): there C - K H C cancels most of the digits of C, and in
+// FP32 the plain update leaves some tracks' covariance off by orders of
+// magnitude.  In FP32 this update computes S, its inverse, the gain and
+// C - K H C in compensated arithmetic: each value a pair hi + lo of floats
+// (|lo| at most half an ulp of hi), sums by Knuth's error-free two-sum,
+// products by one fused multiply-add for the rounding error, the inverse by
+// one Newton step on the pair residual 1 - a q; each covariance entry is
+// rounded once at the end, the state and chi2 take the rounded gain and
+// inverse.  In FP64 (and on the tape) it is the plain update.
+struct F2 { float hi, lo; };
+inline F2 f2_two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  return F2{s, (a - (s - bb)) + (b - bb)};
+}
+inline F2 f2_quick(float a, float b) {           // |a| >= |b| or a == 0
+  const float s = a + b;
+  return F2{s, b - (s - a)};
+}
+inline F2 f2_add(F2 a, F2 b) {
+  F2 s = f2_two_sum(a.hi, b.hi);
+  const F2 t = f2_two_sum(a.lo, b.lo);
+  s = f2_quick(s.hi, s.lo + t.hi);
+  return f2_quick(s.hi, s.lo + t.lo);
+}
+inline F2 f2_neg(F2 a) { return F2{-a.hi, -a.lo}; }
+inline F2 f2_mul(F2 a, F2 b) {
+  const float p = a.hi * b.hi;
+  const float e = std::fma(a.hi, b.hi, -p);
+  return f2_quick(p, std::fma(a.hi, b.lo, std::fma(a.lo, b.hi, e)));
+}
+inline F2 f2_mul(F2 a, float b) {
+  const float p = a.hi * b;
+  const float e = std::fma(a.hi, b, -p);
+  return f2_quick(p, std::fma(a.lo, b, e));
+}
+inline F2 f2_inv(F2 a) {
+  const float q = 1.0f / a.hi;
+  const F2 r = f2_add(F2{1.0f, 0.0f}, f2_neg(f2_mul(a, q)));
+  return f2_quick(q, r.hi * q);
+}
+
+template <class R>
+void kf_update_first(R p[5], R C[15], R my, R mz, R vy, R vz, R& chi2) {
+  kf_update(p, C, my, mz, vy, vz, chi2);
+}
+template <>
+void kf_update_first<float>(float p[5], float C[15], float my, float mz, float vy, float vz, float& chi2) {
+  const float r0 = my - p[0];
+  const float r1 = mz - p[1];
+  const F2 S00 = f2_two_sum(C[0], vy);
+  const F2 S01 = F2{C[1], 0.0f};
+  const F2 S11 = f2_two_sum(C[5], vz);
+  const F2 det = f2_add(f2_mul(S00, S11), f2_neg(f2_mul(S01, S01)));
+  const F2 idet = f2_inv(det);
+  const F2 I00 = f2_mul(S11, idet);
+  const F2 I01 = f2_neg(f2_mul(S01, idet));
+  const F2 I11 = f2_mul(S00, idet);
+  float row0[5], row1[5];
+  F2 K0[5], K1[5];
+  for (int j = 0; j < 5; ++j) { row0[j] = C[ix(0, j)]; row1[j] = C[ix(1, j)]; }
+  for (int i = 0; i < 5; ++i) {
+    K0[i] = f2_add(f2_mul(I00, row0[i]), f2_mul(I01, row1[i]));
+    K1[i] = f2_add(f2_mul(I01, row0[i]), f2_mul(I11, row1[i]));
+  }
+  for (int i = 0; i < 5; ++i) p[i] = p[i] + std::fma(K1[i].hi, r1, K0[i].hi * r0);
+  for (int i = 0; i < 5; ++i)
+    for (int j = i; j < 5; ++j) {
+      const F2 kr = f2_add(f2_mul(K0[i], row0[j]), f2_mul(K1[i], row1[j]));
+      const F2 cn = f2_add(F2{C[ix(i, j)], 0.0f}, f2_neg(kr));
+      C[ix(i, j)] = cn.hi + cn.lo;
+    }
+  chi2 = chi2 + std::fma(r1, std::fma(I11.hi, r1, I01.hi * r0), r0 * std::fma(I01.hi, r1, I00.hi * r0));
+}
+// Updates 1 .. kFirstUpdates of a fit take kf_update_first.
+constexpr int kFirstUpdates = 3;
+
 // Kalman update with a scalar measurement of state component q.
 template <class R>
 void kf_update1(R p[5], R C[15], int q, R m, R v, R& chi2) {
@@ -289,7 +367,8 @@ bool fit_hits(const Model<R>& m, const orc_params& P, int n, const R* x, const R
   xcur = x[0];
   for (int h = 1; h < n; ++h) {
     if (!transport(p, C, xcur, x[h], m)) return false;
-    kf_update(p, C, y[h], z[h], m.vy, m.vz, chi2);
+    if (h <= kFirstUpdates) kf_update_first(p, C, y[h], z[h], m.vy, m.vz, chi2);
+    else kf_update(p, C, y[h], z[h], m.vy, m.vz, chi2);
     xcur = x[h];
   }
   return true;
@@ -427,7 +506,8 @@ template <class R> struct Pipeline {
     for (size_t j = 1; j < chain.size(); ++j) {
       int64_t h = chain[j];
       if (!transport(p, C, xc, x[h], m)) { T.nhits = 0; T.hits.assign(g.n_rows, -1); return T; }
-      kf_update(p, C, y[h], z[h], m.vy, m.vz, dummy);
+      if ((int)j <= kFirstUpdates) kf_update_first(p, C, y[h], z[h], m.vy, m.vz, dummy);
+      else kf_update(p, C, y[h], z[h], m.vy, m.vz, dummy);
       T.hits[row[h]] = h;
       T.nhits++;
       xc = x[h];
