@@ -16,6 +16,7 @@
 //   a7 final fit  outermost-to-innermost Kalman refit of the owned hits,
 //                 ordered compaction into the caller's flat buffers
 #include "internal.hpp"
+#include "kf_c2.hpp"
 
 namespace tpcca {
 namespace {
@@ -1203,6 +1204,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   uint32_t rubase = 0;
   float p[5], C[15], xc = 0.f;
   uint32_t iters = 0;
+  int nupd = 0;   // Kalman updates of the current seed (the first three are compensated)
   // the record of the next chain cluster (nxt), loaded one step ahead
   float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
   // hit slots are written through a four-row buffer (rows are visited in
@@ -1291,6 +1293,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
             chord_dir(x0, y0, z0, a2.x, a2.y, a2.z, sdir, tdir);
             p[0] = y0; p[1] = z0; p[2] = sdir; p[3] = tdir; p[4] = 0.0f;
             init_cov(C, w.m.vy, w.m.vz);
+            nupd = 0;
             rlo = rhi = rstate = r0;
             xc = x0;
             if (fabsf(sdir) < w.m.sin_max) {
@@ -1364,7 +1367,9 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
     }
     if (upd) {
       float dummy = 0.0f;
-      update(p, C, my, mz, w.m, dummy);
+      if (nupd < TPCCA_GRAD_C2_UPDATES) update_c2(p, C, my, mz, w.m, dummy);
+      else update(p, C, my, mz, w.m, dummy);
+      ++nupd;
     }
     if (chain) {
       if (!go) {
@@ -1595,7 +1600,8 @@ __global__ __launch_bounds__(TB) void k_refit(Ws w) {
     auto step = [&](float4& q, int32_t& j, uint32_t k) {
       if (ok && k < cnt) {
         if (transport(p, C, xc, q.x, w.m)) {
-          update(p, C, q.y, q.z, w.m, chi2);
+          if (k <= (uint32_t)TPCCA_GRAD_C2_UPDATES) update_c2(p, C, q.y, q.z, w.m, chi2);
+          else update(p, C, q.y, q.z, w.m, chi2);
           xc = q.x;
         } else {
           ok = false;
