@@ -37,10 +37,16 @@ struct MergeWs {
   unsigned long long* best_out;  // [T] (chi2 bits << 32) | outer partner, or ~0
   int32_t* link;           // [T] outer partner or -1
   int32_t* inner;          // [T] inner partner or -1
+  float4* srec;            // [T] by sector: outermost hit (x, y, z), (last row << 1 | exit valid) bits
   uint32_t* emit;          // [T + 1] output tracks of the chain headed by a segment -> offsets
   uint32_t* hemit;         // [T + 1] hits of those tracks -> offsets
+  int32_t* head;           // [T] the head of each segment's chain
+  uint32_t* tpos;          // [T] a segment's place in its chain
+  uint32_t* hpos;          // [T] hits of the chain's segments before it
+  uint32_t* nseg;          // [T] segments of the chain (at its head)
+  uint32_t* rlist;         // [T] heads of chains of two or more segments
   float* rec;              // [T][24]: merged refit of a chain head (x_ref, p, cov, chi2)
-  uint32_t* err;           // [4]: error bits, output tracks
+  uint32_t* err;           // [4]: error bits, output tracks, output hits, chains to refit
   // outputs (device)
   uint8_t* o_sector;
   float* o_x_ref;

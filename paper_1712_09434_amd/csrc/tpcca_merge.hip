@@ -120,13 +120,16 @@ __device__ bool match_chi2(const float d[5], const float M[15], float& chi2) {
   return true;
 }
 
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << (threadIdx.x & 63)) - 1ull; }
+
 // Turn (sign of the adjacent-wedge angle) from the frame of wedge wa to that
 // of wedge wb: +1 if wb follows wa counter-clockwise.
 __device__ __forceinline__ float turn_sign(int wa, int wb, int NW) { return wb == (wa + 1) % NW ? 1.0f : -1.0f; }
 
-__global__ __launch_bounds__(TB) void k_mrg_exit(MergeWs w) {
+__global__ __launch_bounds__(TB) void k_mrg_init(MergeWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
   if (i < w.S) w.sec_cnt[i] = 0u;
+  if (i < 4) w.err[i] = 0u;
   if (i < w.T) {
     w.best_in[i] = kNone;
     w.best_out[i] = kNone;
@@ -136,37 +139,54 @@ __global__ __launch_bounds__(TB) void k_mrg_exit(MergeWs w) {
   }
 }
 
+// Sector histogram of a workgroup's segments in LDS, one global atomic per
+// non-empty sector (the segments of a workgroup share few sectors).
+constexpr int kSecBins = 256;
+
 __global__ __launch_bounds__(TB) void k_mrg_ends(MergeWs w) {
+  __shared__ uint32_t s_h[kSecBins];
+  s_h[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= w.T) return;
-  const int32_t b0 = w.hit_off[i], b1 = w.hit_off[i + 1];
-  const int s = w.sector[i];
-  if (b0 < 0 || b1 - b0 < 3 || b1 - b0 > w.R || (int64_t)b1 > w.H || s >= w.S) { atomicOr(&w.err[0], 1u); return; }
-  const uint32_t hf = w.hit_id[b0], hl = w.hit_id[b1 - 1];
-  if ((int64_t)hf >= w.NC || (int64_t)hl >= w.NC) { atomicOr(&w.err[0], 2u); return; }
-  w.flags[i] = 2u;                        // a well-formed segment
-  w.first[i] = make_float4(w.cx[hf], w.cy[hf], w.cz[hf], __int_as_float((int)w.crow[hf]));
-  w.last[i] = make_float4(w.cx[hl], w.cy[hl], w.cz[hl], __int_as_float((int)w.crow[hl]));
-  atomicAdd(&w.sec_cnt[s], 1u);
-  float p[5], C[15];
+  if (i < w.T) {
+    const int32_t b0 = w.hit_off[i], b1 = w.hit_off[i + 1];
+    const int s = w.sector[i];
+    bool good = !(b0 < 0 || b1 - b0 < 3 || b1 - b0 > w.R || (int64_t)b1 > w.H || s >= w.S);
+    if (!good) atomicOr(&w.err[0], 1u);
+    uint32_t hf = 0, hl = 0;
+    if (good) {
+      hf = w.hit_id[b0];
+      hl = w.hit_id[b1 - 1];
+      if ((int64_t)hf >= w.NC || (int64_t)hl >= w.NC) { atomicOr(&w.err[0], 2u); good = false; }
+    }
+    if (good) {
+      w.first[i] = make_float4(w.cx[hf], w.cy[hf], w.cz[hf], __int_as_float((int)w.crow[hf]));
+      const float xo = w.cx[hl];
+      w.last[i] = make_float4(xo, w.cy[hl], w.cz[hl], __int_as_float((int)w.crow[hl]));
+      atomicAdd(&s_h[s], 1u);
+      float p[5], C[15];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) p[k] = w.p[i * 5 + k];
+      for (int k = 0; k < 5; ++k) p[k] = w.p[i * 5 + k];
 #pragma unroll
-  for (int k = 0; k < 15; ++k) C[k] = w.cov[i * 15 + k];
-  const float xo = w.cx[hl];
-  if (transport(p, C, w.x_ref[i], xo, w.m)) {
-    float* e = w.ex + i * 24;
-    e[0] = xo;
+      for (int k = 0; k < 15; ++k) C[k] = w.cov[i * 15 + k];
+      uint32_t f = 2u;                      // a well-formed segment
+      if (transport(p, C, w.x_ref[i], xo, w.m)) {
+        float* e = w.ex + i * 24;
+        e[0] = xo;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) e[1 + k] = p[k];
+        for (int k = 0; k < 5; ++k) e[1 + k] = p[k];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) e[6 + k] = C[k];
-    w.flags[i] = 3u;                      // ... with an exit state
+        for (int k = 0; k < 15; ++k) e[6 + k] = C[k];
+        f = 3u;                             // ... with an exit state
+      }
+      w.flags[i] = f;
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < w.S && s_h[threadIdx.x]) atomicAdd(&w.sec_cnt[threadIdx.x], s_h[threadIdx.x]);
 }
 
-// Segments listed by sector: offsets (one thread; at most 254 sectors), then
-// every segment takes a slot of its sector.
+// Sector offsets (one thread; at most 254 sectors).
 __global__ void k_mrg_secscan(MergeWs w) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t acc = 0;
@@ -179,66 +199,123 @@ __global__ void k_mrg_secscan(MergeWs w) {
   w.sec_cnt[w.S] = acc;
 }
 
+// Every well-formed segment takes a slot of its sector's list (a range per
+// sector and workgroup, ranks in LDS) and writes there what the candidate
+// search tests first: its outermost hit, last row and exit flag.
 __global__ __launch_bounds__(TB) void k_mrg_secfill(MergeWs w) {
+  __shared__ uint32_t s_h[kSecBins];
+  s_h[threadIdx.x] = 0u;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= w.T) return;
-  const int s = w.sector[i];
-  if (s >= w.S) return;
-  w.sec_list[atomicAdd(&w.sec_cur[s], 1u)] = (uint32_t)i;
+  const bool good = i < w.T && (w.flags[i] & 2u);
+  const int s = good ? (int)w.sector[i] : 0;
+  uint32_t rank = 0;
+  if (good) rank = atomicAdd(&s_h[s], 1u);
+  __syncthreads();
+  if (threadIdx.x < w.S && s_h[threadIdx.x]) s_h[threadIdx.x] = atomicAdd(&w.sec_cur[threadIdx.x], s_h[threadIdx.x]);
+  __syncthreads();
+  if (good) {
+    const uint32_t pos = s_h[s] + rank;
+    const float4 l = w.last[i];
+    w.sec_list[pos] = (uint32_t)i;
+    w.srec[pos] = make_float4(l.x, l.y, l.z, __int_as_float((__float_as_int(l.w) << 1) | (int)(w.flags[i] & 1u)));
+  }
 }
 
-// Candidate search of outer segment b over the segments of the two
-// neighbouring wedges of its side.
+// Candidate search of outer segment b over the lists of the two
+// neighbouring wedges of its side: one wave per b, its lanes taking every
+// 64th record (the cheap tests on the record first), the best candidate the
+// minimum of the lanes' (chi2 bits, index) keys.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)(v & 0xFFFFFFFFull), d, 64);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
-  const int64_t b = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (b >= w.T || w.err[0] != 0u || !(w.flags[b] & 2u)) return;
+  // records that pass the cheap tests, collected per wave and then tested
+  // in full one per lane (the full test is long; survivors are few and
+  // scattered over the lanes)
+  __shared__ uint32_t s_cand[TB / 64][64];
+  const int wv = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * (TB / 64) + wv;
+  const int lane = threadIdx.x & 63;
+  if (b >= w.T || w.err[0] != 0u || !(w.flags[b] & 2u) || w.NW < 3) return;
   const int sb = w.sector[b];
-  if (w.NW < 3) return;
   const int wb = sb % w.NW, side0 = sb - wb;
   const float4 hb = w.first[b];
   const int rlo_b = __float_as_int(hb.w);
   const float xb = w.x_ref[b];
-  float pb[5], Cb[15];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) pb[k] = w.p[b * 5 + k];
-#pragma unroll
-  for (int k = 0; k < 15; ++k) Cb[k] = w.cov[b * 15 + k];
   unsigned long long best = kNone;
-  for (int dir = 0; dir < 2; ++dir) {
-    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : (wb + 1) % w.NW;
-    const int sa_ = side0 + wa;
-    const float sgn = turn_sign(wa, wb, w.NW);
-    const float sa = sgn * w.sa, ca = w.ca;
-    const uint32_t k0 = w.sec_cnt[sa_], k1 = w.sec_cnt[sa_ + 1];
-    for (uint32_t k = k0; k < k1; ++k) {
+  int cnt = 0;                        // wave-uniform
+  auto flush = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    if (lane < cnt) {
+      const uint32_t v = s_cand[wv][lane];
+      const uint32_t k = v & 0x7FFFFFFFu;
+      const int wa = (v >> 31) ? (wb + 1) % w.NW : (wb + w.NW - 1) % w.NW;
+      const float sa = turn_sign(wa, wb, w.NW) * w.sa, ca = w.ca;
       const uint32_t a = w.sec_list[k];
-      if (!(w.flags[a] & 1u)) continue;
-      const float4 ha = w.last[a];
-      if (!(__float_as_int(ha.w) < rlo_b)) continue;
-      const float xa = ha.x * ca + ha.y * sa, ya = -(ha.x * sa) + ha.y * ca;
-      const float dX = xa - hb.x, dY = ya - hb.y;
-      const float dr = sqrtf(dX * dX + dY * dY);
-      if (!(dr <= w.merge_dist && fabsf(ha.z - hb.z) <= w.merge_dist)) continue;
       const float* e = w.ex + (int64_t)a * 24;
       float x = e[0], q[5], Q[15];
 #pragma unroll
       for (int j = 0; j < 5; ++j) q[j] = e[1 + j];
 #pragma unroll
       for (int j = 0; j < 15; ++j) Q[j] = e[6 + j];
-      if (!rotate_state(x, q, Q, ca, sa, w.m)) continue;
-      if (!transport(q, Q, x, xb, w.m)) continue;
-      float d[5], M[15], chi;
+      float chi = 0.0f;
+      bool ok = rotate_state(x, q, Q, ca, sa, w.m);
+      if (ok) ok = transport(q, Q, x, xb, w.m);
+      if (ok) {
+        float d[5], M[15];
 #pragma unroll
-      for (int j = 0; j < 5; ++j) d[j] = q[j] - pb[j];
+        for (int j = 0; j < 5; ++j) d[j] = q[j] - w.p[b * 5 + j];
 #pragma unroll
-      for (int j = 0; j < 15; ++j) M[j] = Q[j] + Cb[j];
-      if (!match_chi2(d, M, chi) || !(chi <= w.chi2_merge)) continue;
-      const unsigned long long cb = (unsigned long long)__float_as_uint(chi) << 32;
-      best = min(best, cb | a);
-      atomicMin(&w.best_out[a], cb | (unsigned long long)b);
+        for (int j = 0; j < 15; ++j) M[j] = Q[j] + w.cov[b * 15 + j];
+        ok = match_chi2(d, M, chi) && chi <= w.chi2_merge;
+      }
+      if (ok) {
+        const unsigned long long cb = (unsigned long long)__float_as_uint(chi) << 32;
+        best = min(best, cb | a);
+        atomicMin(&w.best_out[a], cb | (unsigned long long)b);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    cnt = 0;
+  };
+  for (int dir = 0; dir < 2; ++dir) {
+    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : (wb + 1) % w.NW;
+    const int sa_ = side0 + wa;
+    const float sa = turn_sign(wa, wb, w.NW) * w.sa, ca = w.ca;
+    const uint32_t k0 = w.sec_cnt[sa_], k1 = w.sec_cnt[sa_ + 1];
+    for (uint32_t kb = k0; kb < k1; kb += 64) {
+      const uint32_t k = kb + (uint32_t)lane;
+      bool pass = false;
+      if (k < k1) {
+        const float4 ha = w.srec[k];
+        const int bits = __float_as_int(ha.w);
+        if ((bits & 1) && (bits >> 1) < rlo_b) {
+          const float xa = ha.x * ca + ha.y * sa, ya = -(ha.x * sa) + ha.y * ca;
+          const float dX = xa - hb.x, dY = ya - hb.y;
+          const float dr = sqrtf(dX * dX + dY * dY);
+          pass = dr <= w.merge_dist && fabsf(ha.z - hb.z) <= w.merge_dist;
+        }
+      }
+      const uint64_t mask = __ballot(pass);
+      const int np = __popcll(mask);
+      if (np == 0) continue;
+      if (cnt + np > 64) flush();
+      if (pass) s_cand[wv][cnt + __popcll(mask & lanemask_lt())] = k | ((uint32_t)dir << 31);
+      cnt += np;
     }
   }
-  w.best_in[b] = best;
+  if (cnt > 0) flush();
+  best = wave_min_u64(best);
+  if (lane == 0) w.best_in[b] = best;
 }
 
 __global__ __launch_bounds__(TB) void k_mrg_links(MergeWs w) {
@@ -258,176 +335,237 @@ __global__ __launch_bounds__(TB) void k_mrg_links(MergeWs w) {
   if (w.o_link) w.o_link[a] = l;
 }
 
-// Chain of head i (a segment without an inner partner): its output tracks
-// and hits, and for a chain of two or more segments the merged refit.
-__global__ __launch_bounds__(64) void k_mrg_chains(MergeWs w) {
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+// Chain of head i (a segment without an inner partner): every segment's
+// head, place and preceding hits; the head's counts (its segments as they
+// are, until the refit succeeds); chains of two or more listed for the refit.
+__global__ __launch_bounds__(TB) void k_mrg_chains(MergeWs w) {
+  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
   if (i >= w.T) return;
   if (w.inner[i] >= 0 || w.err[0] != 0u) { w.emit[i] = 0u; w.hemit[i] = 0u; return; }
-  int n = 1;
-  int32_t c = (int32_t)i;
-  uint32_t hits = (uint32_t)(w.hit_off[i + 1] - w.hit_off[i]);
-  while (w.link[c] >= 0 && n <= w.S) {
-    c = w.link[c];
+  uint32_t n = 0, hits = 0;
+  for (int32_t c = (int32_t)i; c >= 0 && n <= (uint32_t)w.S; c = w.link[c]) {
+    w.head[c] = (int32_t)i;
+    w.tpos[c] = n;
+    w.hpos[c] = hits;
     ++n;
     hits += (uint32_t)(w.hit_off[c + 1] - w.hit_off[c]);
   }
+  w.nseg[i] = n;
+  w.emit[i] = n;
   w.hemit[i] = hits;
-  if (n == 1) { w.emit[i] = 1u; return; }
-  // merged refit, from the outermost hit of the outermost segment c inward
+  if (n > 1) w.rlist[atomicAdd(&w.err[3], 1u)] = (uint32_t)i;
+}
+
+// Exclusive scan of v[0 .. T) in place, one workgroup: tiles of kScanT x 4
+// entries staged in LDS by coalesced loads, four consecutive entries per
+// thread, a block scan of the thread sums, a running offset across tiles;
+// the total at v[T] and in *tot.
+constexpr int kScanT = 1024;
+constexpr int kScanPer = 4;
+__global__ __launch_bounds__(kScanT) void k_mrg_scan(uint32_t* __restrict__ v, int64_t T, uint32_t* __restrict__ tot) {
+  __shared__ uint32_t tile[kScanT * kScanPer];
+  __shared__ uint32_t sums[kScanT];
+  uint32_t base = 0;
+  constexpr int64_t kTile = (int64_t)kScanT * kScanPer;
+  for (int64_t t0 = 0; t0 < T; t0 += kTile) {
+    for (int k = 0; k < kScanPer; ++k) {
+      const int64_t j = t0 + (int64_t)k * kScanT + threadIdx.x;
+      tile[k * kScanT + threadIdx.x] = j < T ? v[j] : 0u;
+    }
+    __syncthreads();
+    uint32_t a = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) a += tile[threadIdx.x * kScanPer + k];
+    // inclusive scan of the thread sums: within each wave by shuffles, then
+    // over the sixteen wave totals
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = a;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) sums[wv] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int q = 0; q < wv; ++q) wbase += sums[q];
+    uint32_t total = 0;
+    for (int q = 0; q < kScanT / 64; ++q) total += sums[q];
+    __syncthreads();
+    sums[threadIdx.x] = wbase + inc;
+    __syncthreads();
+    uint32_t o = base + (threadIdx.x ? sums[threadIdx.x - 1] : 0u);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const uint32_t e = tile[threadIdx.x * kScanPer + k];
+      tile[threadIdx.x * kScanPer + k] = o;
+      o += e;
+    }
+    base += total;
+    __syncthreads();
+    for (int k = 0; k < kScanPer; ++k) {
+      const int64_t j = t0 + (int64_t)k * kScanT + threadIdx.x;
+      if (j < T) v[j] = tile[k * kScanT + threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    v[T] = base;
+    *tot = base;
+  }
+}
+
+// One wave per segment: its hit ids copied to their place in the output
+// (the chain's hits, innermost segment first).
+__global__ __launch_bounds__(TB) void k_mrg_hits(MergeWs w) {
+  const int64_t c = (int64_t)blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= w.T || w.err[0] != 0u) return;
+  const uint32_t h = w.hemit[w.head[c]] + w.hpos[c];
+  const int32_t b0 = w.hit_off[c], nh = w.hit_off[c + 1] - b0;
+  for (int32_t k = lane; k < nh; k += 64) w.o_hit_id[h + (uint32_t)k] = w.hit_id[b0 + k];
+}
+
+// Merged refit of a listed chain, from its outermost hit inward over the
+// chain's hit ids as written to the output (innermost segment first, so read
+// backwards): ids are loaded eight steps ahead, coordinates four steps
+// ahead, a ring of four slots per kind (past the chain's first hit the
+// loads repeat it and are never used).  At each segment boundary the state
+// is rotated into the next inner segment's frame.
+__global__ __launch_bounds__(64) void k_mrg_refit(MergeWs w) {
+  const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (q >= (int64_t)w.err[3]) return;
+  const int32_t i = (int32_t)w.rlist[q];
+  const uint32_t* ids = w.o_hit_id + w.hemit[i];
+  int32_t c = i;
+  while (w.link[c] >= 0) c = w.link[c];
+  // the chain's hits at positions 0 .. n-1 (inner to outer); the outermost
+  // segment c covers the last nc of them
+  const int32_t n = (int32_t)(w.hemit[i + 1] - w.hemit[i]);
+  int32_t seg_lo = n - (w.hit_off[c + 1] - w.hit_off[c]);
   const Model& m = w.m;
-  int32_t b0 = w.hit_off[c], hi = w.hit_off[c + 1] - 1;
-  const uint32_t h0 = w.hit_id[hi], h2 = w.hit_id[hi - 2];
+  auto X = [&](uint32_t id) { return make_float4(w.cx[id], w.cy[id], w.cz[id], 0.0f); };
+  const float4 r0 = X(ids[n - 1]), r2 = X(ids[n - 3]);
   float p[5], C[15], s, t;
-  chord_dir(w.cx[h2], w.cy[h2], w.cz[h2], w.cx[h0], w.cy[h0], w.cz[h0], s, t);
-  p[0] = w.cy[h0]; p[1] = w.cz[h0]; p[2] = s; p[3] = t; p[4] = w.p[c * 5 + 4];
+  chord_dir(r2.x, r2.y, r2.z, r0.x, r0.y, r0.z, s, t);
+  p[0] = r0.y; p[1] = r0.z; p[2] = s; p[3] = t; p[4] = w.p[c * 5 + 4];
   init_cov(C, m.vy, m.vz);
-  float chi2 = 0.0f, xc = w.cx[h0];
+  float chi2 = 0.0f, xc = r0.x;
   bool ok = fabsf(s) < m.sin_max;
   int nupd = 0;
-  --hi;
-  while (ok) {
-    for (; hi >= b0; --hi) {
-      const uint32_t h = w.hit_id[hi];
-      const float hx = w.cx[h];
-      if (!transport(p, C, xc, hx, m)) { ok = false; break; }
-      if (nupd < TPCCA_GRAD_C2_UPDATES) update_c2(p, C, w.cy[h], w.cz[h], m, chi2);
-      else update(p, C, w.cy[h], w.cz[h], m, chi2);
-      ++nupd;
-      xc = hx;
+  auto at = [&](int32_t k) { return k >= 0 ? k : 0; };
+  // ring slots: coordinates of hits k, k-1, k-2, k-3; ids of hits k-4 .. k-7
+  int32_t k = n - 2;
+  float4 c0 = X(ids[at(k)]), c1 = X(ids[at(k - 1)]), c2 = X(ids[at(k - 2)]), c3 = X(ids[at(k - 3)]);
+  uint32_t j0 = ids[at(k - 4)], j1 = ids[at(k - 5)], j2 = ids[at(k - 6)], j3 = ids[at(k - 7)];
+  auto step = [&](float4& cs, uint32_t& js) {
+    if (ok && k >= 0) {
+      if (k < seg_lo) {
+        // entering the next inner segment
+        const int32_t a = w.inner[c];
+        const int wc = w.sector[c] % w.NW, wa = w.sector[a] % w.NW;
+        if (!rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m)) ok = false;
+        c = a;
+        seg_lo -= w.hit_off[c + 1] - w.hit_off[c];
+      }
+      if (ok && !transport(p, C, xc, cs.x, m)) ok = false;
+      if (ok) {
+        if (nupd < TPCCA_GRAD_C2_UPDATES) update_c2(p, C, cs.y, cs.z, m, chi2);
+        else update(p, C, cs.y, cs.z, m, chi2);
+        ++nupd;
+        xc = cs.x;
+      }
     }
-    if (!ok || c == (int32_t)i) break;
-    const int32_t a = w.inner[c];
-    const int wc = w.sector[c] % w.NW, wa = w.sector[a] % w.NW;
-    if (!rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m)) { ok = false; break; }
-    c = a;
-    b0 = w.hit_off[c];
-    hi = w.hit_off[c + 1] - 1;
+    cs = X(js);
+    js = ids[at(k - 8)];
+    --k;
+  };
+  while (ok && k >= 0) {
+    step(c0, j0);
+    step(c1, j1);
+    step(c2, j2);
+    step(c3, j3);
   }
-  w.emit[i] = ok ? 1u : (uint32_t)n;
   if (ok) {
-    float* r = w.rec + i * 24;
+    w.emit[i] = 1u;
+    float* r = w.rec + (int64_t)i * 24;
     r[0] = xc;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) r[1 + k] = p[k];
+    for (int kk = 0; kk < 5; ++kk) r[1 + kk] = p[kk];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) r[6 + k] = C[k];
+    for (int kk = 0; kk < 15; ++kk) r[6 + kk] = C[kk];
     r[21] = chi2;
   }
 }
 
-// Exclusive scans of emit and hemit over the segments (one workgroup of
-// 1024 threads, each a contiguous block); totals at [T]; the output's final
-// hit offset.
-constexpr int kScanT = 1024;
-__global__ __launch_bounds__(kScanT) void k_mrg_scan(MergeWs w) {
-  __shared__ uint32_t se[kScanT], sh[kScanT];
-  const int64_t per = (w.T + kScanT - 1) / kScanT;
-  const int64_t i0 = (int64_t)threadIdx.x * per, i1 = min<int64_t>(i0 + per, w.T);
-  uint32_t ae = 0, ah = 0;
-  for (int64_t i = i0; i < i1; ++i) { ae += w.emit[i]; ah += w.hemit[i]; }
-  se[threadIdx.x] = ae;
-  sh[threadIdx.x] = ah;
-  __syncthreads();
-  for (int d = 1; d < kScanT; d <<= 1) {
-    const uint32_t ve = threadIdx.x >= (unsigned)d ? se[threadIdx.x - d] : 0u;
-    const uint32_t vh = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0u;
-    __syncthreads();
-    se[threadIdx.x] += ve;
-    sh[threadIdx.x] += vh;
-    __syncthreads();
-  }
-  uint32_t oe = threadIdx.x ? se[threadIdx.x - 1] : 0u, oh = threadIdx.x ? sh[threadIdx.x - 1] : 0u;
-  for (int64_t i = i0; i < i1; ++i) {
-    const uint32_t e = w.emit[i], h = w.hemit[i];
-    w.emit[i] = oe;
-    w.hemit[i] = oh;
-    oe += e;
-    oh += h;
-  }
-  if (threadIdx.x == kScanT - 1) {
-    w.emit[w.T] = se[kScanT - 1];
-    w.hemit[w.T] = sh[kScanT - 1];
-    w.err[1] = se[kScanT - 1];
-    w.err[2] = sh[kScanT - 1];
-    w.o_hit_off[se[kScanT - 1]] = (int32_t)sh[kScanT - 1];
-  }
-}
-
-__device__ void copy_hits(const MergeWs& w, int32_t c, uint32_t h) {
-  const int32_t b0 = w.hit_off[c], b1 = w.hit_off[c + 1];
-  for (int32_t k = b0; k < b1; ++k) w.o_hit_id[h + (uint32_t)(k - b0)] = w.hit_id[k];
-}
-
-__global__ __launch_bounds__(64) void k_mrg_write(MergeWs w) {
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (i >= w.T || w.inner[i] >= 0 || w.err[0] != 0u) return;
-  uint32_t t = w.emit[i], h = w.hemit[i];
-  const uint32_t ne = w.emit[i + 1] - t;
-  if (ne == 1u && w.link[i] >= 0) {
-    // merged chain
-    const float* r = w.rec + i * 24;
-    w.o_sector[t] = w.sector[i];
-    w.o_x_ref[t] = r[0];
+// Lane per segment: the track records -- the segment's own, or, for the
+// head of a refitted chain, the merged track; the output's final offset.
+__global__ __launch_bounds__(TB) void k_mrg_tracks(MergeWs w) {
+  const int64_t c = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (c == 0) w.o_hit_off[w.emit[w.T]] = (int32_t)w.hemit[w.T];
+  if (c >= w.T || w.err[0] != 0u) return;
+  const int32_t i = w.head[c];
+  const uint32_t t0 = w.emit[i], ne = w.emit[i + 1] - t0;
+  const uint32_t h = w.hemit[i] + w.hpos[c];
+  if (ne == 1u && w.nseg[i] > 1u) {
+    if (c != i) return;
+    const float* r = w.rec + (int64_t)i * 24;
+    w.o_sector[t0] = w.sector[i];
+    w.o_x_ref[t0] = r[0];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w.o_p[t * 5 + k] = r[1 + k];
+    for (int k = 0; k < 5; ++k) w.o_p[t0 * 5 + k] = r[1 + k];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) w.o_cov[t * 15 + k] = r[6 + k];
-    w.o_chi2[t] = r[21];
-    w.o_ndf[t] = 2 * (int32_t)(w.hemit[i + 1] - h) - 5;
-    w.o_hit_off[t] = (int32_t)h;
-    for (int32_t c = (int32_t)i; c >= 0; c = w.link[c]) {
-      copy_hits(w, c, h);
-      h += (uint32_t)(w.hit_off[c + 1] - w.hit_off[c]);
-    }
+    for (int k = 0; k < 15; ++k) w.o_cov[t0 * 15 + k] = r[6 + k];
+    w.o_chi2[t0] = r[21];
+    w.o_ndf[t0] = 2 * (int32_t)(w.hemit[i + 1] - w.hemit[i]) - 5;
+    w.o_hit_off[t0] = (int32_t)h;
     return;
   }
-  // single segment, or a chain whose refit failed: its segments as they are
-  for (int32_t c = (int32_t)i; c >= 0; c = w.link[c]) {
-    w.o_sector[t] = w.sector[c];
-    w.o_x_ref[t] = w.x_ref[c];
+  const uint32_t t = t0 + w.tpos[c];
+  w.o_sector[t] = w.sector[c];
+  w.o_x_ref[t] = w.x_ref[c];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w.o_p[t * 5 + k] = w.p[c * 5 + k];
+  for (int k = 0; k < 5; ++k) w.o_p[t * 5 + k] = w.p[c * 5 + k];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) w.o_cov[t * 15 + k] = w.cov[c * 15 + k];
-    w.o_chi2[t] = w.chi2[c];
-    w.o_ndf[t] = w.ndf[c];
-    w.o_hit_off[t] = (int32_t)h;
-    copy_hits(w, c, h);
-    h += (uint32_t)(w.hit_off[c + 1] - w.hit_off[c]);
-    ++t;
-  }
-}
-
-__global__ void k_mrg_zero(MergeWs w) {
-  if (threadIdx.x < 4 && blockIdx.x == 0) w.err[threadIdx.x] = 0u;
+  for (int k = 0; k < 15; ++k) w.o_cov[t * 15 + k] = w.cov[c * 15 + k];
+  w.o_chi2[t] = w.chi2[c];
+  w.o_ndf[t] = w.ndf[c];
+  w.o_hit_off[t] = (int32_t)h;
 }
 
 }  // namespace
 
 hipError_t run_merge(const MergeWs& w, hipStream_t st) {
   const void* need[] = {w.sector, w.x_ref, w.p, w.cov, w.chi2, w.ndf, w.hit_off, w.hit_id, w.cx, w.cy, w.cz,
-                        w.crow, w.ex, w.first, w.last, w.flags, w.sec_cnt, w.sec_cur, w.sec_list, w.best_in,
-                        w.best_out, w.link, w.inner, w.emit, w.hemit, w.rec, w.err, w.o_sector, w.o_x_ref,
-                        w.o_p, w.o_cov, w.o_chi2, w.o_ndf, w.o_hit_off, w.o_hit_id};
+                        w.crow, w.ex, w.first, w.last, w.flags, w.sec_cnt, w.sec_cur, w.sec_list, w.srec,
+                        w.best_in, w.best_out, w.link, w.inner, w.emit, w.hemit, w.head, w.tpos, w.hpos, w.nseg,
+                        w.rlist, w.rec, w.err, w.o_sector, w.o_x_ref, w.o_p, w.o_cov, w.o_chi2, w.o_ndf,
+                        w.o_hit_off, w.o_hit_id};
   for (const void* q : need)
     if (!q) return hipErrorInvalidValue;
-  if (w.S > kMaxSectors || w.T >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  k_mrg_zero<<<1, 64, 0, st>>>(w);
-  const int64_t n0 = std::max<int64_t>(w.T, w.S);
-  const unsigned g0 = (unsigned)std::max<int64_t>((n0 + TB - 1) / TB, 1);
-  k_mrg_exit<<<g0, TB, 0, st>>>(w);
+  if (w.S > kMaxSectors || w.S > kSecBins || w.T >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int64_t n0 = std::max<int64_t>(std::max<int64_t>(w.T, w.S), 4);
+  k_mrg_init<<<(unsigned)((n0 + TB - 1) / TB), TB, 0, st>>>(w);
+  const unsigned g = (unsigned)std::max<int64_t>((w.T + TB - 1) / TB, 1);
+  const unsigned gw = (unsigned)std::max<int64_t>((w.T + TB / 64 - 1) / (TB / 64), 1);
   if (w.T > 0) {
-    const unsigned g = (unsigned)((w.T + TB - 1) / TB), g64 = (unsigned)((w.T + 63) / 64);
     k_mrg_ends<<<g, TB, 0, st>>>(w);
     k_mrg_secscan<<<1, 64, 0, st>>>(w);
     k_mrg_secfill<<<g, TB, 0, st>>>(w);
-    k_mrg_pairs<<<g, TB, 0, st>>>(w);
+    k_mrg_pairs<<<gw, TB, 0, st>>>(w);
     k_mrg_links<<<g, TB, 0, st>>>(w);
-    k_mrg_chains<<<g64, 64, 0, st>>>(w);
+    k_mrg_chains<<<g, TB, 0, st>>>(w);
   }
-  k_mrg_scan<<<1, kScanT, 0, st>>>(w);
-  if (w.T > 0) k_mrg_write<<<(unsigned)((w.T + 63) / 64), 64, 0, st>>>(w);
+  // hit offsets of the chains (they do not depend on the refit), the hits,
+  // the refit (one lane per listed chain: at most T / 2 of them), then the
+  // track offsets and records
+  k_mrg_scan<<<1, kScanT, 0, st>>>(w.hemit, w.T, w.err + 2);
+  if (w.T > 0) {
+    k_mrg_hits<<<gw, TB, 0, st>>>(w);
+    k_mrg_refit<<<(unsigned)((w.T / 2 + 64) / 64), 64, 0, st>>>(w);
+  }
+  k_mrg_scan<<<1, kScanT, 0, st>>>(w.emit, w.T, w.err + 1);
+  k_mrg_tracks<<<g, TB, 0, st>>>(w);
   return hipGetLastError();
 }
 

@@ -985,6 +985,8 @@ int tpcca_merge(tpcca_ctx* c, const tpcca_tracks* seg, tpcca_tracks* out, int32_
   const size_t o_list = L.take<uint32_t>(T), o_bi = L.take<unsigned long long>(T), o_bo = L.take<unsigned long long>(T);
   const size_t o_link = L.take<int32_t>(T), o_inner = L.take<int32_t>(T), o_emit = L.take<uint32_t>(T + 1);
   const size_t o_hemit = L.take<uint32_t>(T + 1), o_rec = L.take<float>(T * 24), o_err = L.take<uint32_t>(4);
+  const size_t o_srec = L.take<float4>(T), o_head = L.take<int32_t>(T), o_tpos = L.take<uint32_t>(T);
+  const size_t o_hpos = L.take<uint32_t>(T), o_nseg = L.take<uint32_t>(T), o_rlist = L.take<uint32_t>(T);
   if (L.off > c->mscratch_bytes) {
     if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
     he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
@@ -1010,6 +1012,8 @@ int tpcca_merge(tpcca_ctx* c, const tpcca_tracks* seg, tpcca_tracks* out, int32_
   w.link = (int32_t*)(b + o_link); w.inner = (int32_t*)(b + o_inner);
   w.emit = (uint32_t*)(b + o_emit); w.hemit = (uint32_t*)(b + o_hemit);
   w.rec = (float*)(b + o_rec); w.err = (uint32_t*)(b + o_err);
+  w.srec = (float4*)(b + o_srec); w.head = (int32_t*)(b + o_head); w.tpos = (uint32_t*)(b + o_tpos);
+  w.hpos = (uint32_t*)(b + o_hpos); w.nseg = (uint32_t*)(b + o_nseg); w.rlist = (uint32_t*)(b + o_rlist);
   w.o_sector = out->sector; w.o_x_ref = out->x_ref; w.o_p = out->p; w.o_cov = out->cov; w.o_chi2 = out->chi2;
   w.o_ndf = out->ndf; w.o_hit_off = out->hit_off; w.o_hit_id = out->hit_id; w.o_link = seg_link;
   // an empty call still passes valid pointers to the kernels' checks
