@@ -47,6 +47,8 @@ def main():
                     help="threads of the multi-threaded oracle sample (0: the usable cores, at most 16)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only run the calibration-gradient leg (for its kernel trace)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run device copies of this many MiB (calibrates PMC byte counters)")
@@ -58,6 +60,11 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.grad_only:
+        import torch
+        from paper_1712_09434_amd import Tracker
+        print(json.dumps({"grad": grad_leg(Tracker, torch.device("cuda:0"))}), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -111,7 +118,7 @@ def main():
                 "traffic": traffic, "kernel_ms": round(dom_ms, 4),
                 "traffic_gbs": None if traffic_gbs is None else round(traffic_gbs, 1),
                 "traffic_frac": None if traffic_gbs is None else round(traffic_gbs / HBM_PEAK_GBS, 4),
-                "valu_issue_frac": measured_valu_issue(f"k_{dom}"),
+                "sq": measured_valu_issue(f"k_{dom}"),
                 "algo_bytes_per_launch": algo_bytes}
 
     cpu = None
@@ -142,7 +149,9 @@ def main():
 
 
 KERNEL_SOURCES = ("paper_1712_09434_amd/csrc/tpcca_kernels.hip", "paper_1712_09434_amd/csrc/kf_device.hpp",
-                  "paper_1712_09434_amd/csrc/internal.hpp")
+                  "paper_1712_09434_amd/csrc/internal.hpp", "paper_1712_09434_amd/csrc/kf_c2.hpp",
+                  "paper_1712_09434_amd/csrc/calib_device.hpp", "paper_1712_09434_amd/csrc/tpcca_merge.hip",
+                  "paper_1712_09434_amd/csrc/merge_internal.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tracking_c3_traffic.md")
 PMC_BENCH_CMD = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-grad"
 
@@ -183,9 +192,10 @@ def measured_valu_issue(kernel: str):
         return None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if cells and cells[0] == kernel and len(cells) >= 7:
+        if cells and cells[0] == kernel and len(cells) >= 10:
             try:
-                return float(cells[6])
+                return {"valu_issue_frac": float(cells[5]), "waves_per_simd": float(cells[6]),
+                        "valu_busy": float(cells[7]), "valu_lanes": float(cells[8]), "wait_frac": float(cells[9])}
             except ValueError:
                 return None
     return None
@@ -279,6 +289,31 @@ sha256 `{kernel_source_hash()}`.
         print(text2)
         sq = defaultdict(lambda: defaultdict(float))
         ncalls = defaultdict(int)
+        grad_stats = glob.glob(os.path.join(folder, "prof_grad", "**", "*kernel_stats.csv"), recursive=True)
+        if grad_stats:
+            gl = []
+            for r in csv.DictReader(open(grad_stats[0])):
+                name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+                name = re.sub(r"^void ", "", name)
+                gl.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+            body_g = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in gl[:16])
+            text_g = f"""# Kernel trace, calibration workload (20 miscalibrated full events, ~82 k tracks, ~10.8 M hits)
+
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_grad -o grad -- python3 bench.py --grad-only
+    python3 bench.py --pmc-summary <out>
+
+One tpcca_refit_grad over all tracks per call: 11 timed calls, then the 50-step Adam calibration
+(132 + 50 calls) and the calibration-map tracking calls; average duration per dispatch.
+
+| Kernel | Calls | Average µs | % of GPU time |
+|---|---|---|---|
+{body_g}
+"""
+            with open(os.path.join(ROOT, "profiles", "refit_grad_c5x20_kernel_trace.md"), "w") as f:
+                f.write(text_g)
+            print(text_g)
         for fn in glob.glob(os.path.join(folder, "pmc_sq", "**", "*counter_collection*.csv"), recursive=True):
             for r in csv.DictReader(open(fn)):
                 name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("tpcca::(anonymous namespace)::", ""))
@@ -288,31 +323,47 @@ sha256 `{kernel_source_hash()}`.
                     ncalls[name] += 1
         if sq:
             avg_us = {n: a for n, _, a, _ in lines}
-            simds, clock_ghz = 256 * 4, 2.4
+            simds, cus, clock_ghz = 256 * 4, 256, 2.4
             rows3 = []
             for n in sorted(sq, key=lambda k: -avg_us.get(k, 0.0)):
                 c = ncalls[n] or 1
-                valu = sq[n]["SQ_INSTS_VALU"] / c
+                q = {k: v / c for k, v in sq[n].items()}
+                valu = q["SQ_INSTS_VALU"]
                 issue_us = valu * 4 / simds / (clock_ghz * 1e3)
                 d = avg_us.get(n, 0.0)
                 if d < 20.0:
                     continue
-                rows3.append(f"| {n} | {sq[n]['SQ_WAVES'] / c:,.0f} | {valu / 1e6:,.1f} | "
-                             f"{sq[n]['SQ_INSTS_LDS'] / c / 1e6:,.2f} | {issue_us:,.1f} | {d:,.1f} | {issue_us / d:.2f} |")
+                cycles = d * clock_ghz * 1e3
+                # SQ_WAVE_CYCLES, SQ_ACTIVE_INST_VALU and SQ_WAIT_ANY are quad-cycles summed over
+                # the SIMDs: mean resident waves per SIMD, VALU busy per CU (the VALUBusy
+                # metric's formula with the traced duration), lane utilisation (VALUUtilization's)
+                waves_simd = 4 * q["SQ_WAVE_CYCLES"] / (cycles * simds)
+                busy = q["SQ_ACTIVE_INST_VALU"] / (cus * cycles)
+                lanes = q["SQ_THREAD_CYCLES_VALU"] / max(q["SQ_ACTIVE_INST_VALU"] * 64, 1.0)
+                wait = q["SQ_WAIT_ANY"] / max(q["SQ_WAVE_CYCLES"], 1.0)
+                rows3.append(f"| {n} | {q['SQ_WAVES']:,.0f} | {valu / 1e6:,.1f} | {issue_us:,.1f} | {d:,.1f} | "
+                             f"{issue_us / d:.2f} | {waves_simd:.2f} | {busy:.2f} | {lanes:.2f} | {wait:.2f} |")
             text3 = f"""# SQ counters per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
 
 Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
-    rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS -f csv -d <out>/pmc_sq -o sq -- {PMC_BENCH_CMD}
+    rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_WAIT_ANY SQ_INSTS_VALU SQ_INSTS_LDS -f csv -d <out>/pmc_sq -o sq -- {PMC_BENCH_CMD}
     python3 bench.py --pmc-summary <out>
 
-Per dispatch (means over the profiled calls).  VALU issue time = wave-64 VALU instructions x 4
-cycles / (1,024 SIMDs x 2.4 GHz): the time the kernel would take if every SIMD issued one of its
-VALU instructions every 4 cycles.  Its ratio to the traced duration is the kernel's VALU issue
-utilisation.  Kernel sources sha256 `{kernel_source_hash()}`.
+Per dispatch (means over the profiled calls; the tracking call and the sector merger).  VALU issue
+time = wave-64 VALU instructions x 4 cycles / (1,024 SIMDs x 2.4 GHz): the time the kernel would
+take if every SIMD issued one of its VALU instructions every 4 cycles; its ratio to the traced
+duration is the kernel's VALU issue utilisation.  Waves/SIMD = 4 SQ_WAVE_CYCLES (quad-cycles
+summed over SIMDs) / (traced cycles x 1,024): the mean number of resident waves per SIMD (the
+occupancy; at most 8).  VALU busy = SQ_ACTIVE_INST_VALU / (256 CUs x traced cycles) (the
+VALUBusy metric's formula).  Lanes = SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU), the
+VALUUtilization metric: the fraction of a wave's 64 lanes active in its VALU instructions.  Wait
+= SQ_WAIT_ANY / SQ_WAVE_CYCLES: the fraction of resident wave time spent waiting (memory,
+dependencies, barriers).  Traced durations from the kernel trace of the same command.  Kernel
+sources sha256 `{kernel_source_hash()}`.
 
-| Kernel | Waves | VALU (M wave-instr.) | LDS (M wave-instr.) | VALU issue µs | Traced µs | Issue / traced |
-|---|---|---|---|---|---|---|
+| Kernel | Waves | VALU (M wave-instr.) | VALU issue µs | Traced µs | Issue / traced | Waves/SIMD | VALU busy | Lanes | Wait |
+|---|---|---|---|---|---|---|---|---|---|
 """ + "\n".join(rows3) + "\n"
             with open(os.path.join(ROOT, "profiles", "tracking_c3_sq_counters.md"), "w") as f:
                 f.write(text3)
