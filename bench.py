@@ -423,6 +423,14 @@ def batch_leg(args, Tracker, dev):
             return (time.perf_counter() - t0) / reps
 
         t_batch = timed(lambda: trk.track_batch(tens), args.batch_reps)
+        # per-phase times of the batched call (library HIP events between its kernels;
+        # timing runs the phases without graph replay)
+        trk.set_phase_timing(True)
+        for _ in range(args.batch_reps):
+            trk.track_batch(tens)
+        torch.cuda.synchronize()
+        batch_phases = trk.phase_times()[0]
+        trk.set_phase_timing(False)
 
         def seq():
             for e in tens:
@@ -439,9 +447,11 @@ def batch_leg(args, Tracker, dev):
         trk.close()
     t_seq = seq_best[0]
     log(f"batch: {n} clusters in 64 events: batched {t_batch * 1e3:.2f} ms, "
-        f"sequential {t_seq * 1e3:.2f} ms, gain {t_seq / t_batch:.2f}")
+        f"sequential {t_seq * 1e3:.2f} ms, gain {t_seq / t_batch:.2f}; phases "
+        + ", ".join(f"{k}={v:.3f}" for k, v in batch_phases.items()))
     return {"events": 64, "clusters": n, "batched_ms": t_batch * 1e3, "sequential_ms": t_seq * 1e3,
             "gain": t_seq / t_batch, "batched_clusters_per_s": n / t_batch,
+            "phase_ms": {k: round(v, 4) for k, v in batch_phases.items()},
             "batched_tuning": {"tracklet_grid": best["tracklet_grid"], "use_graph": best["use_graph"]},
             "sequential_tuning": {"tracklet_grid": seq_best[1], "use_graph": seq_best[2]}}
 

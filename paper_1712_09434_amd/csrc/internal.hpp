@@ -28,8 +28,13 @@ enum : int {
   F_NSEEDS = 1,     // number of seeds
   F_NSTARTS = 2,    // number of start hits
   F_FITS = 3,       // 1 if every event's outputs fit their capacities
+  F_LROWS1 = 4,     // list lengths of the row-unit size classes (many row units only):
+  F_LROWS2 = 5,     //   row kernels' wave, workgroup and large classes (also F_LROWS3),
+  F_LLINKS1 = 6,    //   link kernels' small-slab and slab classes
+  F_LLINKS2 = 7,
   F_SEEDCTR = 8,    // work counters of the tracklet kernel, one per seed range (8)
-  F_COUNT = 16
+  F_LROWS3 = 16,
+  F_COUNT = 20
 };
 enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u, ERR_STUCK = 4u };
 
@@ -112,6 +117,9 @@ struct Ws {
   uint32_t* cell_cap;   // [RU] cells + 1 per row unit, then scanned -> cell base [RU + 1]
   uint32_t* cell_base;  // [RU + 1]
   GridParams* grid;     // [RU]
+  uint32_t* ru_rows;    // [RU] row units of the wave row class from the front, workgroup class from the back
+  uint32_t* ru_big;     // [RU] row units of the large row class
+  uint32_t* ru_links;   // [RU] same for the small-slab and slab link classes
   float4* tmp4;         // [N] (x, y, z, event-local id bits), bucketed by row unit
   // canonical SoA: (event, sector, row, id) order
   float* cx;

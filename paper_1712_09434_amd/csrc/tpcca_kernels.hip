@@ -15,6 +15,8 @@
 //   a6 selection  64-bit atomicMax ownership per cluster
 //   a7 final fit  outermost-to-innermost Kalman refit of the owned hits,
 //                 ordered compaction into the caller's flat buffers
+#include <algorithm>
+
 #include "internal.hpp"
 #include "kf_c2.hpp"
 
@@ -86,6 +88,32 @@ __device__ __forceinline__ uint32_t scan_in(const ScanArgs& a, int y, uint32_t v
 }
 constexpr int kScanNT = 1024;                        // threads of a one-workgroup scan
 constexpr int64_t kScanSmall = 4 * 4 * kScanNT;      // at most four tiles of 4 x kScanNT
+
+// Size classes of row units.  The row and link kernels come in variants by
+// row size; with few row units (RU <= kScanSmall, e.g. one event) each
+// variant's launch covers every row unit and skips the others, with many
+// (batches of events) the binning builds one list per variant and the
+// variants other than the wave-per-unit ones run over their list only, so
+// that the hundreds of thousands of mostly tiny units of a batch do not
+// each cost a workgroup launch in every variant.
+constexpr uint32_t kTiny = 64;         // clusters of a row unit handled by one wave, one per lane
+constexpr uint32_t kWaveRow = 256;     // clusters of a row unit handled by one wave, four per lane
+constexpr uint32_t kSmallSlab = 256;   // neighbour rows staged in the small-LDS link variant
+constexpr uint32_t kSlab = 896;        // clusters of one row staged in LDS (3 workgroups per CU fit)
+__host__ __device__ inline bool ru_lists(int64_t RU) { return RU > kScanSmall; }
+// 0: k_rows_tiny (empty units too), 1: k_rows_wave, 2: k_rows<false>, 3: k_rows<true>
+__device__ __forceinline__ int rows_class(uint32_t n) {
+  return n <= kTiny ? 0 : n <= kWaveRow ? 1 : n <= 4u * TB ? 2 : 3;
+}
+// -1: nothing to do (empty), 0/1/2: k_links<kTiny>, <kSmallSlab>, <kSlab>
+// (the last also writes the no-link entries of edge rows and over-full units)
+__device__ __forceinline__ int links_class(uint32_t n, uint32_t nd, uint32_t nu, bool inner) {
+  if (n == 0) return -1;
+  if (!inner || n > (uint32_t)kMaxRow) return 2;
+  return (nd <= kTiny && nu <= kTiny) ? 0 : (nd <= kSmallSlab && nu <= kSmallSlab) ? 1 : 2;
+}
+// Workgroups of a list-driven launch (each loops over list entries).
+constexpr unsigned kListGrid = 2048, kListGridBig = 1024;
 
 // Exclusive scan over a kScanNT-thread block; *tot receives the block total.
 __device__ uint32_t block_excl_scan_big(uint32_t v, uint32_t* tot) {
@@ -330,10 +358,43 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
       if (s_h[b]) atomicAdd(&w.ru_count[rb + b], s_h[b]);
 }
 
-// cells + 1 offsets per row unit
+// Appends v to a list (forward from 0, or backward from cap - 1) for every
+// lane with p: one atomic per wave.  The order of the entries is not
+// defined; every consumer's results are independent of it.
+__device__ __forceinline__ void list_push(bool p, uint32_t v, uint32_t* ctr, uint32_t* list, bool backward,
+                                          int64_t cap) {
+  const uint64_t m = __ballot(p);
+  if (m == 0ull) return;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader, 64);
+  if (p) {
+    const uint32_t k = base + (uint32_t)__popcll(m & lanemask_lt());
+    list[backward ? cap - 1 - (int64_t)k : (int64_t)k] = v;
+  }
+}
+
+// cells + 1 offsets per row unit; with many row units also the lists of the
+// row and link variants (from the counts, before they are reused as cursors)
 __global__ void k_cell_caps(Ws w) {
-  for (int64_t ru = (int64_t)blockIdx.x * TB + threadIdx.x; ru < w.RU; ru += (int64_t)gridDim.x * TB)
-    w.cell_cap[ru] = grid_cells(w.ru_count[ru]) + 1u;
+  const bool lists = ru_lists(w.RU);
+  for (int64_t b0 = (int64_t)blockIdx.x * TB; b0 < w.RU; b0 += (int64_t)gridDim.x * TB) {
+    const int64_t ru = b0 + threadIdx.x;
+    const bool ok = ru < w.RU;
+    const uint32_t n = ok ? w.ru_count[ru] : 0u;
+    if (ok) w.cell_cap[ru] = grid_cells(n) + 1u;
+    if (!lists) continue;
+    const int r = ok ? (int)(ru % w.R) : 0;
+    const bool inner = r >= 1 && r <= w.R - 2;
+    const uint32_t nd = ok && inner ? w.ru_count[ru - 1] : 0u, nu = ok && inner ? w.ru_count[ru + 1] : 0u;
+    const int rc = rows_class(n), lc = links_class(n, nd, nu, inner);
+    list_push(ok && rc == 1, (uint32_t)ru, &w.flags[F_LROWS1], w.ru_rows, false, w.RU);
+    list_push(ok && rc == 2, (uint32_t)ru, &w.flags[F_LROWS2], w.ru_rows, true, w.RU);
+    list_push(ok && rc == 3, (uint32_t)ru, &w.flags[F_LROWS3], w.ru_big, false, w.RU);
+    list_push(ok && lc == 1, (uint32_t)ru, &w.flags[F_LLINKS1], w.ru_links, false, w.RU);
+    list_push(ok && lc == 2, (uint32_t)ru, &w.flags[F_LLINKS2], w.ru_links, true, w.RU);
+  }
 }
 
 // ru_count is reused as the global fill cursor (zeroed after the scans).
@@ -401,6 +462,28 @@ __device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float 
   return cell_coord(z, G.z0, G.inv_bz, G.nz) * G.ny + cell_coord(y, G.y0, G.inv_by, G.ny);
 }
 
+// Search grid of a row unit of n clusters with the given bounding box: about
+// grid_cells(n) cells of equal shape over the box (one cell if the box is
+// degenerate or n < 4).
+__device__ __forceinline__ GridParams make_grid(uint32_t n, uint32_t cbase, float ymin, float ymax, float zmin,
+                                                float zmax) {
+  const uint32_t cap = grid_cells(n);
+  uint32_t nz = 1, ny = 1;
+  float dz = zmax - zmin, dy = ymax - ymin;
+  if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
+  if (n >= 4 && dz > 0.0f && dy > 0.0f) {
+    const float a = sqrtf((dz * dy) / (float)cap);
+    nz = (uint32_t)fminf(fmaxf(dz / a, 1.0f), (float)cap);
+    ny = (uint32_t)fminf(fmaxf(dy / a, 1.0f), (float)(cap / nz));
+  }
+  GridParams G;
+  G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
+  G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
+  G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
+  G.pad = 0u;
+  return G;
+}
+
 // One block per row unit: the row unit's (x, y, z, id) entries sorted by id
 // in LDS (bitonic on the ids, carrying the entry's slot), canonical SoA
 // written in that order, then a uniform 2-D grid over the row's bounding box
@@ -419,8 +502,6 @@ __device__ __forceinline__ void wave_sync() {
 // entry: the ids are sorted by a bitonic network over lane shuffles, the
 // coordinates follow by a gather from the lane that held them; the grid is
 // built as in k_rows with a per-wave LDS histogram.  Same results as k_rows.
-constexpr uint32_t kTiny = 64;
-
 __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
   __shared__ uint32_t s_h[TB / 64][kCellsPerCluster * kTiny + 2];
   const int wv = threadIdx.x >> 6, lane = lane_id();
@@ -462,22 +543,9 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
     zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
   }
   // grid parameters: every lane computes the same values, lane 0 stores them
-  const uint32_t cap = grid_cells(n);
-  uint32_t nz = 1, ny = 1;
-  float dz = zmax - zmin, dy = ymax - ymin;
-  if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
-  if (n >= 4 && dz > 0.0f && dy > 0.0f) {
-    const float a = sqrtf((dz * dy) / (float)cap);
-    nz = (uint32_t)fminf(fmaxf(dz / a, 1.0f), (float)cap);
-    ny = (uint32_t)fminf(fmaxf(dy / a, 1.0f), (float)(cap / nz));
-  }
-  GridParams G;
-  G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
-  G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
-  G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
-  G.pad = 0u;
+  const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
   if (lane == 0) w.grid[ru] = G;
-  const uint32_t nc = nz * ny;
+  const uint32_t nc = G.nz * G.ny;
   for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
   wave_sync();
   const uint32_t cell = mine ? cell_of(G, y, z) : 0u;
@@ -499,9 +567,127 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
   }
 }
 
-// Two instantiations: row units of up to 4 TB clusters (small LDS, so many
-// workgroups share a CU) and larger ones (LDS for kMaxRow ids); each launch
-// covers every row unit and skips those of the other size.
+// Row units of kTiny < n <= kWaveRow clusters: one wave each, four per
+// workgroup, no workgroup barrier.  Lane l holds entries 4l .. 4l+3; the
+// bitonic sort on the ids swaps registers for partners in the same lane and
+// uses shuffles otherwise, then every sorted entry's coordinates are read
+// from its original slot; the grid is built with a per-wave LDS histogram.
+// Same results as k_rows.
+__global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
+  __shared__ uint32_t s_h[TB / 64][kCellsPerCluster * kWaveRow + 2];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  uint32_t* hist = s_h[wv];
+  auto unit = [&](const int64_t ru) {
+    const uint32_t off = w.ru_off[ru];
+    const uint32_t n = w.ru_off[ru + 1] - off;
+    if (rows_class(n) != 1) return;
+    const uint32_t cbase = w.cell_base[ru];
+    uint32_t K[4], V[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * lane + k;
+      K[k] = i < n ? __float_as_uint(w.tmp4[off + i].w) : 0xFFFFFFFFu;
+      V[k] = i;
+    }
+    auto cs = [&](int k0, int k1, uint32_t kk) {   // registers k0 < k1 of this lane
+      const bool asc = ((4u * lane + k0) & kk) == 0;
+      if (asc ? K[k0] > K[k1] : K[k0] < K[k1]) {
+        const uint32_t t = K[k0]; K[k0] = K[k1]; K[k1] = t;
+        const uint32_t u = V[k0]; V[k0] = V[k1]; V[k1] = u;
+      }
+    };
+    uint32_t npad = 2;
+    while (npad < n) npad <<= 1;
+    for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+      for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+        if (j == 1) {
+          cs(0, 1, kk); cs(2, 3, kk);
+        } else if (j == 2) {
+          cs(0, 2, kk); cs(1, 3, kk);
+        } else {
+          uint32_t O[4], OV[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            O[k] = (uint32_t)__shfl_xor((int)K[k], (int)(j >> 2), 64);
+            OV[k] = (uint32_t)__shfl_xor((int)V[k], (int)(j >> 2), 64);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t i = 4u * lane + k;
+            const bool lower = (i & j) == 0, asc = (i & kk) == 0;
+            const uint32_t lo = lower ? K[k] : O[k], hi = lower ? O[k] : K[k];
+            if (asc ? lo > hi : lo < hi) { K[k] = O[k]; V[k] = OV[k]; }
+          }
+        }
+      }
+    }
+    float px[4], py[4], pz[4];
+    float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * lane + k;
+      px[k] = py[k] = pz[k] = 0.f;
+      if (i < n) {
+        const float4 v = w.tmp4[off + V[k]];
+        px[k] = v.x; py[k] = v.y; pz[k] = v.z;
+        w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
+        w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
+        ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+      }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
+      zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
+    }
+    // every lane computes the same grid, lane 0 stores it
+    const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
+    if (lane == 0) w.grid[ru] = G;
+    const uint32_t nc = G.nz * G.ny;
+    for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
+    wave_sync();
+    uint32_t cell[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cell[k] = 4u * lane + k < n ? cell_of(G, py[k], pz[k]) : 0u;
+      if (4u * lane + k < n) atomicAdd(&hist[cell[k]], 1u);
+    }
+    wave_sync();
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nc; c0 += 64) {
+      const uint32_t c = c0 + lane;
+      const uint32_t v = c < nc ? hist[c] : 0u;
+      const uint32_t inc = wave_incl_scan(v);
+      if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = off + carry + inc - v; }
+      carry += (uint32_t)__shfl((int)inc, 63, 64);
+    }
+    if (lane == 0) w.cell_off[cbase + nc] = off + n;
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = 4u * lane + k;
+      if (i < n) {
+        const uint32_t pos = atomicAdd(&hist[cell[k]], 1u);
+        w.gbuf[off + pos] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
+      }
+    }
+  };
+  if (!ru_lists(w.RU)) {
+    const int64_t ru = (int64_t)blockIdx.x * (TB / 64) + wv;
+    if (ru < w.RU) unit(ru);
+    return;
+  }
+  const uint32_t cnt = w.flags[F_LROWS1];
+  for (uint32_t i = blockIdx.x * (TB / 64) + wv; i < cnt; i += gridDim.x * (TB / 64)) {
+    unit(w.ru_rows[i]);
+    wave_sync();   // the histogram is reused by the next unit
+  }
+}
+
+// Two instantiations: row units of kWaveRow < n <= 4 TB clusters (small LDS,
+// so many workgroups share a CU) and larger ones (LDS for kMaxRow ids).  With few row
+// units a launch covers every unit and skips those of the other sizes; with
+// many its workgroups loop over the class's list.
 template <bool kLarge>
 __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   constexpr uint32_t kIds = kLarge ? (uint32_t)kMaxRow : 4u * TB;
@@ -513,206 +699,204 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   __shared__ GridParams s_gp;
   uint16_t* s_slot = (uint16_t*)s_aux;
   uint32_t* s_hist = s_aux;
-  const int64_t ru = blockIdx.x;
-  const uint32_t off = w.ru_off[ru];
-  const uint32_t n = w.ru_off[ru + 1] - off;
-  const uint32_t cbase = w.cell_base[ru];
-  const int tid = threadIdx.x;
-  if (kLarge != (n > 4u * TB) || n <= kTiny) return;   // (k_rows_tiny takes units of <= kTiny)
-  if (n > (uint32_t)kMaxRow) {
-    if (tid == 0) {
-      atomicOr(&w.flags[F_ERR], ERR_LIMIT);
-      GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, 0u};
-      w.grid[ru] = G;
-      w.cell_off[cbase] = off;
-      w.cell_off[cbase + 1] = off;
-    }
-    // every per-position array still gets a defined entry (its own position
-    // in the grid copy), so later kernels stay in bounds until the error is
-    // reported
-    const float nan = __int_as_float(0x7fc00000);
-    for (uint32_t k = tid; k < n; k += TB) {
-      w.cx[off + k] = nan; w.cy[off + k] = nan; w.cz[off + k] = nan;
-      w.cid[off + k] = 0u; w.cru[off + k] = (uint32_t)ru;
-      w.gbuf[off + k] = make_float4(nan, nan, nan, __uint_as_float(off + k));
-    }
-    return;
-  }
-  // Rows of up to 4 TB clusters (all but extreme ones) are sorted in
-  // registers: thread t holds sorted positions 4t .. 4t+3; bitonic stages
-  // whose partner is in the same thread swap registers, partners in the
-  // same wave come by shuffles, and only the stages across waves (partner
-  // distance >= 256) go through LDS.  Their coordinates then stay in
-  // registers for the grid passes.
-  const bool fast = !kLarge;
-  uint32_t K[4], V[4];
-  float px[4], py[4], pz[4];
-  float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
-  if (fast) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t i = 4u * tid + k;
-      K[k] = i < n ? __float_as_uint(w.tmp4[off + i].w) : 0xFFFFFFFFu;
-      V[k] = i;
-    }
-    auto cs = [&](int k0, int k1, uint32_t kk) {   // registers k0 < k1 of this thread
-      const bool asc = ((4u * tid + k0) & kk) == 0;
-      if (asc ? K[k0] > K[k1] : K[k0] < K[k1]) {
-        const uint32_t t = K[k0]; K[k0] = K[k1]; K[k1] = t;
-        const uint32_t u = V[k0]; V[k0] = V[k1]; V[k1] = u;
+  // one row unit (workgroup-uniform); called once per unit of the launch
+  auto unit = [&](const int64_t ru) {
+    const uint32_t off = w.ru_off[ru];
+    const uint32_t n = w.ru_off[ru + 1] - off;
+    const uint32_t cbase = w.cell_base[ru];
+    const int tid = threadIdx.x;
+    if (rows_class(n) != (kLarge ? 3 : 2)) return;   // (smaller units: k_rows_tiny, k_rows_wave)
+    if (n > (uint32_t)kMaxRow) {
+      if (tid == 0) {
+        atomicOr(&w.flags[F_ERR], ERR_LIMIT);
+        GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, 0u};
+        w.grid[ru] = G;
+        w.cell_off[cbase] = off;
+        w.cell_off[cbase + 1] = off;
       }
-    };
-    // stages up to the row's power-of-two size only: the entries past it are
-    // all padding (equal maxima), already in order
-    uint32_t npad = 2;
-    while (npad < n) npad <<= 1;
-    for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
-      for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-        if (j == 1) {
-          cs(0, 1, kk); cs(2, 3, kk);
-        } else if (j == 2) {
-          cs(0, 2, kk); cs(1, 3, kk);
-        } else {
-          uint32_t O[4], OV[4];
-          if (j < 256) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              O[k] = (uint32_t)__shfl_xor((int)K[k], (int)(j >> 2), 64);
-              OV[k] = (uint32_t)__shfl_xor((int)V[k], (int)(j >> 2), 64);
-            }
+      // every per-position array still gets a defined entry (its own position
+      // in the grid copy), so later kernels stay in bounds until the error is
+      // reported
+      const float nan = __int_as_float(0x7fc00000);
+      for (uint32_t k = tid; k < n; k += TB) {
+        w.cx[off + k] = nan; w.cy[off + k] = nan; w.cz[off + k] = nan;
+        w.cid[off + k] = 0u; w.cru[off + k] = (uint32_t)ru;
+        w.gbuf[off + k] = make_float4(nan, nan, nan, __uint_as_float(off + k));
+      }
+      return;
+    }
+    // Rows of up to 4 TB clusters (all but extreme ones) are sorted in
+    // registers: thread t holds sorted positions 4t .. 4t+3; bitonic stages
+    // whose partner is in the same thread swap registers, partners in the
+    // same wave come by shuffles, and only the stages across waves (partner
+    // distance >= 256) go through LDS.  Their coordinates then stay in
+    // registers for the grid passes.
+    const bool fast = !kLarge;
+    uint32_t K[4], V[4];
+    float px[4], py[4], pz[4];
+    float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+    if (fast) {
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = 4u * tid + k;
+        K[k] = i < n ? __float_as_uint(w.tmp4[off + i].w) : 0xFFFFFFFFu;
+        V[k] = i;
+      }
+      auto cs = [&](int k0, int k1, uint32_t kk) {   // registers k0 < k1 of this thread
+        const bool asc = ((4u * tid + k0) & kk) == 0;
+        if (asc ? K[k0] > K[k1] : K[k0] < K[k1]) {
+          const uint32_t t = K[k0]; K[k0] = K[k1]; K[k1] = t;
+          const uint32_t u = V[k0]; V[k0] = V[k1]; V[k1] = u;
+        }
+      };
+      // stages up to the row's power-of-two size only: the entries past it are
+      // all padding (equal maxima), already in order
+      uint32_t npad = 2;
+      while (npad < n) npad <<= 1;
+      for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+          if (j == 1) {
+            cs(0, 1, kk); cs(2, 3, kk);
+          } else if (j == 2) {
+            cs(0, 2, kk); cs(1, 3, kk);
           } else {
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { s_ids[4u * tid + k] = K[k]; s_slot[4u * tid + k] = (uint16_t)V[k]; }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { O[k] = s_ids[(4u * tid + k) ^ j]; OV[k] = s_slot[(4u * tid + k) ^ j]; }
-          }
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const uint32_t i = 4u * tid + k;
-            const bool lower = (i & j) == 0, asc = (i & kk) == 0;
-            const uint32_t lo = lower ? K[k] : O[k], hi = lower ? O[k] : K[k];
-            if (asc ? lo > hi : lo < hi) { K[k] = O[k]; V[k] = OV[k]; }
+            uint32_t O[4], OV[4];
+            if (j < 256) {
+  #pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                O[k] = (uint32_t)__shfl_xor((int)K[k], (int)(j >> 2), 64);
+                OV[k] = (uint32_t)__shfl_xor((int)V[k], (int)(j >> 2), 64);
+              }
+            } else {
+              __syncthreads();
+  #pragma unroll
+              for (int k = 0; k < 4; ++k) { s_ids[4u * tid + k] = K[k]; s_slot[4u * tid + k] = (uint16_t)V[k]; }
+              __syncthreads();
+  #pragma unroll
+              for (int k = 0; k < 4; ++k) { O[k] = s_ids[(4u * tid + k) ^ j]; OV[k] = s_slot[(4u * tid + k) ^ j]; }
+            }
+  #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t i = 4u * tid + k;
+              const bool lower = (i & j) == 0, asc = (i & kk) == 0;
+              const uint32_t lo = lower ? K[k] : O[k], hi = lower ? O[k] : K[k];
+              if (asc ? lo > hi : lo < hi) { K[k] = O[k]; V[k] = OV[k]; }
+            }
           }
         }
       }
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t i = 4u * tid + k;
-      if (i < n) {
-        const float4 v = w.tmp4[off + V[k]];
-        px[k] = v.x; py[k] = v.y; pz[k] = v.z;
-        w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
-        w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
-        ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = 4u * tid + k;
+        if (i < n) {
+          const float4 v = w.tmp4[off + V[k]];
+          px[k] = v.x; py[k] = v.y; pz[k] = v.z;
+          w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
+          w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
+          ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+        }
+      }
+    } else {
+      uint32_t npad = 2;
+      while (npad < n) npad <<= 1;
+      for (uint32_t k = tid; k < npad; k += TB) {
+        s_ids[k] = k < n ? __float_as_uint(w.tmp4[off + k].w) : 0xFFFFFFFFu;
+        s_slot[k] = (uint16_t)k;
+      }
+      __syncthreads();
+      for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+          for (uint32_t i = tid; i < npad; i += TB) {
+            const uint32_t ixj = i ^ j;
+            if (ixj > i) {
+              const uint32_t a = s_ids[i], b = s_ids[ixj];
+              const bool asc = (i & kk) == 0;
+              if ((a > b) == asc) {
+                s_ids[i] = b; s_ids[ixj] = a;
+                const uint16_t t = s_slot[i]; s_slot[i] = s_slot[ixj]; s_slot[ixj] = t;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t k = tid; k < n; k += TB) {
+        const float4 v = w.tmp4[off + s_slot[k]];
+        const float x = v.x, y = v.y, z = v.z;
+        w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
+        w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
+        ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
       }
     }
-  } else {
-    uint32_t npad = 2;
-    while (npad < n) npad <<= 1;
-    for (uint32_t k = tid; k < npad; k += TB) {
-      s_ids[k] = k < n ? __float_as_uint(w.tmp4[off + k].w) : 0xFFFFFFFFu;
-      s_slot[k] = (uint16_t)k;
+  #pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
+      zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
+    }
+    if (lane_id() == 0) {
+      s_red[0][tid >> 6] = ymin; s_red[1][tid >> 6] = ymax; s_red[2][tid >> 6] = zmin; s_red[3][tid >> 6] = zmax;
     }
     __syncthreads();
-    for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
-      for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-        for (uint32_t i = tid; i < npad; i += TB) {
-          const uint32_t ixj = i ^ j;
-          if (ixj > i) {
-            const uint32_t a = s_ids[i], b = s_ids[ixj];
-            const bool asc = (i & kk) == 0;
-            if ((a > b) == asc) {
-              s_ids[i] = b; s_ids[ixj] = a;
-              const uint16_t t = s_slot[i]; s_slot[i] = s_slot[ixj]; s_slot[ixj] = t;
-            }
-          }
+    if (tid == 0) {
+      for (int i = 1; i < TB / 64; ++i) {
+        ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
+        zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
+      }
+      const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
+      s_gp = G;
+      w.grid[ru] = G;
+    }
+    __syncthreads();
+    const GridParams G = s_gp;
+    const uint32_t nc = G.nz * G.ny;
+    for (uint32_t c = tid; c <= nc; c += TB) s_hist[c] = 0u;
+    __syncthreads();
+    if (fast) {
+  #pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4u * tid + k < n) atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
+    } else {
+      // the canonical entries were written by this same thread (same k
+      // stride): re-read them, coalesced
+      for (uint32_t k = tid; k < n; k += TB) atomicAdd(&s_hist[cell_of(G, w.cy[off + k], w.cz[off + k])], 1u);
+    }
+    __syncthreads();
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nc; c0 += TB) {
+      const uint32_t c = c0 + tid;
+      const uint32_t v = c < nc ? s_hist[c] : 0u;
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan(v, &tot) + carry;
+      if (c < nc) { s_hist[c] = ex; w.cell_off[cbase + c] = off + ex; }
+      carry += tot;
+    }
+    if (tid == 0) w.cell_off[cbase + nc] = off + n;
+    __syncthreads();
+    if (fast) {
+  #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = 4u * tid + k;
+        if (i < n) {
+          const uint32_t slot = atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
+          w.gbuf[off + slot] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
         }
-        __syncthreads();
+      }
+    } else {
+      for (uint32_t k = tid; k < n; k += TB) {
+        const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
+        const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
+        w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
       }
     }
-    for (uint32_t k = tid; k < n; k += TB) {
-      const float4 v = w.tmp4[off + s_slot[k]];
-      const float x = v.x, y = v.y, z = v.z;
-      w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
-      w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
-      ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
-    }
+  };
+  if (!ru_lists(w.RU)) {
+    unit(blockIdx.x);
+    return;
   }
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
-    zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
-  }
-  if (lane_id() == 0) {
-    s_red[0][tid >> 6] = ymin; s_red[1][tid >> 6] = ymax; s_red[2][tid >> 6] = zmin; s_red[3][tid >> 6] = zmax;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 1; i < TB / 64; ++i) {
-      ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
-      zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
-    }
-    const uint32_t cap = grid_cells(n);
-    uint32_t nz = 1, ny = 1;
-    float dz = zmax - zmin, dy = ymax - ymin;
-    if (!(n > 0)) { zmin = 0.f; ymin = 0.f; dz = 0.f; dy = 0.f; }
-    if (n >= 4 && dz > 0.0f && dy > 0.0f) {
-      const float a = sqrtf((dz * dy) / (float)cap);
-      nz = (uint32_t)fminf(fmaxf(dz / a, 1.0f), (float)cap);
-      ny = (uint32_t)fminf(fmaxf(dy / a, 1.0f), (float)(cap / nz));
-    }
-    GridParams G;
-    G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
-    G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
-    G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
-    G.pad = 0u;
-    s_gp = G;
-    w.grid[ru] = G;
-  }
-  __syncthreads();
-  const GridParams G = s_gp;
-  const uint32_t nc = G.nz * G.ny;
-  for (uint32_t c = tid; c <= nc; c += TB) s_hist[c] = 0u;
-  __syncthreads();
-  if (fast) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (4u * tid + k < n) atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
-  } else {
-    // the canonical entries were written by this same thread (same k
-    // stride): re-read them, coalesced
-    for (uint32_t k = tid; k < n; k += TB) atomicAdd(&s_hist[cell_of(G, w.cy[off + k], w.cz[off + k])], 1u);
-  }
-  __syncthreads();
-  uint32_t carry = 0;
-  for (uint32_t c0 = 0; c0 < nc; c0 += TB) {
-    const uint32_t c = c0 + tid;
-    const uint32_t v = c < nc ? s_hist[c] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, &tot) + carry;
-    if (c < nc) { s_hist[c] = ex; w.cell_off[cbase + c] = off + ex; }
-    carry += tot;
-  }
-  if (tid == 0) w.cell_off[cbase + nc] = off + n;
-  __syncthreads();
-  if (fast) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t i = 4u * tid + k;
-      if (i < n) {
-        const uint32_t slot = atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
-        w.gbuf[off + slot] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
-      }
-    }
-  } else {
-    for (uint32_t k = tid; k < n; k += TB) {
-      const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
-      const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
-      w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
-    }
+  const uint32_t cnt = w.flags[kLarge ? F_LROWS3 : F_LROWS2];
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    unit(kLarge ? w.ru_big[i] : w.ru_rows[w.RU - 1 - (int64_t)i]);
+    __syncthreads();   // LDS is reused by the next unit
   }
 }
 
@@ -775,7 +959,6 @@ __device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float
   }
 }
 
-constexpr uint32_t kSlab = 896;    // clusters of one row staged in LDS (3 workgroups per CU fit)
 constexpr int kCand = 16;          // passing candidates per side kept per lane
 
 // Window scan of one row's box: indices (into D4) of the entries within the
@@ -886,10 +1069,9 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
 // Three instantiations by the size of the neighbour rows: up to kTiny
 // clusters (one wave per row unit, four per workgroup, wave-level ordering),
 // up to kSmallSlab (workgroup per row unit, half the LDS) and the rest
-// (896-cluster slab); each launch covers every row unit and skips those of
-// the other kinds.
-constexpr uint32_t kSmallSlab = 256;
-
+// (896-cluster slab).  With few row units each launch covers every unit and
+// skips those of the other kinds; with many the two workgroup variants loop
+// over their class's list.
 template <uint32_t kS, uint32_t kG>
 __global__ __launch_bounds__(TB) void k_links(Ws w) {
   constexpr uint32_t kNG = TB / kG;   // row units per workgroup
@@ -903,93 +1085,104 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   __shared__ uint16_t s_cd[kNG][kSpareC + 1], s_cu[kNG][kSpareC + 1];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
   const uint32_t g = threadIdx.x / kG, gt = threadIdx.x % kG;
-  const int64_t ru = (int64_t)blockIdx.x * kNG + g;
-  if (ru >= w.RU) return;
-  const int r = (int)(ru % w.R);
-  const bool inner = r >= 1 && r <= w.R - 2;
-  // every row offset and both neighbour grids in one round of loads
-  const int64_t rdn = inner ? ru - 1 : ru, rup = inner ? ru + 1 : ru;
-  const uint32_t offd = w.ru_off[rdn], off = w.ru_off[ru], offu = w.ru_off[ru + 1];
-  const uint32_t endu = w.ru_off[inner ? ru + 2 : ru + 1];
-  const GridParams Gd = w.grid[rdn], Gu = w.grid[rup];
-  const uint32_t n = offu - off;
-  if (n == 0) return;
-  // edge rows have no links; an over-full row unit (reported as an error) gets none either
-  if (!inner || n > (uint32_t)kMaxRow) {
-    if (kClass == 2)   // (written by one of the instantiations)
-      for (uint32_t k = gt; k < n; k += kG) { w.up[off + k] = -1; w.dn[off + k] = -1; }
+  // one row unit (uniform over its kG threads); called once per unit of the launch
+  auto unit = [&](const int64_t ru) {
+    if (ru >= w.RU) return;
+    const int r = (int)(ru % w.R);
+    const bool inner = r >= 1 && r <= w.R - 2;
+    // every row offset and both neighbour grids in one round of loads
+    const int64_t rdn = inner ? ru - 1 : ru, rup = inner ? ru + 1 : ru;
+    const uint32_t offd = w.ru_off[rdn], off = w.ru_off[ru], offu = w.ru_off[ru + 1];
+    const uint32_t endu = w.ru_off[inner ? ru + 2 : ru + 1];
+    const GridParams Gd = w.grid[rdn], Gu = w.grid[rup];
+    const uint32_t n = offu - off;
+    if (n == 0) return;
+    // edge rows have no links; an over-full row unit (reported as an error) gets none either
+    if (!inner || n > (uint32_t)kMaxRow) {
+      if (kClass == 2)   // (written by one of the instantiations)
+        for (uint32_t k = gt; k < n; k += kG) { w.up[off + k] = -1; w.dn[off + k] = -1; }
+      return;
+    }
+    const uint32_t nd = off - offd, nu = endu - offu;
+    const int cls = links_class(n, nd, nu, true);
+    if (cls != kClass) return;
+    const bool lds = nd <= kS && nu <= kS;
+    float4* sd = s_d[g];
+    float4* su = s_u[g];
+    uint16_t* scd = s_cd[g];
+    uint16_t* scu = s_cu[g];
+    // this thread's own clusters (grid order) for its first rounds, read now
+    // so that they arrive with the staged rows
+    constexpr int kOwn = 4;
+    float4 mine[kOwn];
+  #pragma unroll
+    for (int i = 0; i < kOwn; ++i) {
+      const uint32_t k = gt + kG * i;
+      mine[i] = w.gbuf[off + (k < n ? k : 0u)];   // (used only if k < n)
+    }
+    if (lds) {
+      // all of a thread's staging loads are issued before the first LDS store
+      // (one memory round trip instead of one per loop iteration); slots past
+      // a row's end load an entry known to exist (this row's first entry, the
+      // row's first cell offset) and store it to the spare slot, so that
+      // neither the loads nor the stores need a branch
+      constexpr int kE = (int)((kS + kG - 1) / kG);                          // entries per thread
+      constexpr int kC = (int)((kCellsPerCluster * kS + 1 + kG) / kG);      // cell offsets per thread
+      const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
+  #pragma unroll
+      for (int j = 0; j < kE; ++j) {
+        const uint32_t i = gt + kG * (uint32_t)j;
+        const float4 a = w.gbuf[i < nd ? offd + i : off];
+        const float4 b = w.gbuf[i < nu ? offu + i : off];
+        sd[i < nd ? i : kSpareE] = a;
+        su[i < nu ? i : kSpareE] = b;
+      }
+  #pragma unroll
+      for (int j = 0; j < kC; ++j) {
+        const uint32_t i = gt + kG * (uint32_t)j;
+        const uint32_t a = w.cell_off[Gd.cell_base + (i <= ncd ? i : 0u)];
+        const uint32_t b = w.cell_off[Gu.cell_base + (i <= ncu ? i : 0u)];
+        scd[i <= ncd ? i : kSpareC] = (uint16_t)(a - offd);
+        scu[i <= ncu ? i : kSpareC] = (uint16_t)(b - offu);
+      }
+      if (kG == TB) __syncthreads(); else wave_sync();
+    }
+    uint16_t* ld = s_ld + kCand * threadIdx.x;
+    uint16_t* lu = s_lu + kCand * threadIdx.x;
+    const float WY = w.P.win_y, WZ = w.P.win_z;
+    auto link = [&](const float4& me) {
+      const uint32_t p = __float_as_uint(me.w);
+      const float xi = me.z, yi = me.x, zi = me.y;
+      int32_t bu = -1, bd = -1;
+      if (lds) {
+        const int cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
+        const int cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
+        if (cd <= kCand && cu <= kCand)
+          best_pair(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
+        else
+          find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
+                    (const uint16_t*)scu, bu, bd);
+      } else {
+        find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
+                  w.cell_off + Gu.cell_base, bu, bd);
+      }
+      w.up[p] = bu;
+      w.dn[p] = bd;
+    };
+  #pragma unroll
+    for (int i = 0; i < kOwn; ++i)
+      if (gt + kG * i < n) link(mine[i]);
+    for (uint32_t k = gt + kG * kOwn; k < n; k += kG) link(w.gbuf[off + k]);
+  };
+  if (kNG != 1 || !ru_lists(w.RU)) {
+    unit((int64_t)blockIdx.x * kNG + g);
     return;
   }
-  const uint32_t nd = off - offd, nu = endu - offu;
-  const int cls = (nd <= kTiny && nu <= kTiny) ? 0 : (nd <= kSmallSlab && nu <= kSmallSlab) ? 1 : 2;
-  if (cls != kClass) return;
-  const bool lds = nd <= kS && nu <= kS;
-  float4* sd = s_d[g];
-  float4* su = s_u[g];
-  uint16_t* scd = s_cd[g];
-  uint16_t* scu = s_cu[g];
-  // this thread's own clusters (grid order) for its first rounds, read now
-  // so that they arrive with the staged rows
-  constexpr int kOwn = 4;
-  float4 mine[kOwn];
-#pragma unroll
-  for (int i = 0; i < kOwn; ++i) {
-    const uint32_t k = gt + kG * i;
-    mine[i] = w.gbuf[off + (k < n ? k : 0u)];   // (used only if k < n)
+  const uint32_t cnt = w.flags[kClass == 2 ? F_LLINKS2 : F_LLINKS1];
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    unit(kClass == 2 ? w.ru_links[w.RU - 1 - (int64_t)i] : w.ru_links[i]);
+    __syncthreads();   // LDS is reused by the next unit
   }
-  if (lds) {
-    // all of a thread's staging loads are issued before the first LDS store
-    // (one memory round trip instead of one per loop iteration); slots past
-    // a row's end load an entry known to exist (this row's first entry, the
-    // row's first cell offset) and store it to the spare slot, so that
-    // neither the loads nor the stores need a branch
-    constexpr int kE = (int)((kS + kG - 1) / kG);                          // entries per thread
-    constexpr int kC = (int)((kCellsPerCluster * kS + 1 + kG) / kG);      // cell offsets per thread
-    const uint32_t ncd = Gd.nz * Gd.ny, ncu = Gu.nz * Gu.ny;
-#pragma unroll
-    for (int j = 0; j < kE; ++j) {
-      const uint32_t i = gt + kG * (uint32_t)j;
-      const float4 a = w.gbuf[i < nd ? offd + i : off];
-      const float4 b = w.gbuf[i < nu ? offu + i : off];
-      sd[i < nd ? i : kSpareE] = a;
-      su[i < nu ? i : kSpareE] = b;
-    }
-#pragma unroll
-    for (int j = 0; j < kC; ++j) {
-      const uint32_t i = gt + kG * (uint32_t)j;
-      const uint32_t a = w.cell_off[Gd.cell_base + (i <= ncd ? i : 0u)];
-      const uint32_t b = w.cell_off[Gu.cell_base + (i <= ncu ? i : 0u)];
-      scd[i <= ncd ? i : kSpareC] = (uint16_t)(a - offd);
-      scu[i <= ncu ? i : kSpareC] = (uint16_t)(b - offu);
-    }
-    if (kG == TB) __syncthreads(); else wave_sync();
-  }
-  uint16_t* ld = s_ld + kCand * threadIdx.x;
-  uint16_t* lu = s_lu + kCand * threadIdx.x;
-  const float WY = w.P.win_y, WZ = w.P.win_z;
-  auto link = [&](const float4& me) {
-    const uint32_t p = __float_as_uint(me.w);
-    const float xi = me.z, yi = me.x, zi = me.y;
-    int32_t bu = -1, bd = -1;
-    if (lds) {
-      const int cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
-      const int cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
-      if (cd <= kCand && cu <= kCand)
-        best_pair(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
-      else
-        find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
-                  (const uint16_t*)scu, bu, bd);
-    } else {
-      find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
-                w.cell_off + Gu.cell_base, bu, bd);
-    }
-    w.up[p] = bu;
-    w.dn[p] = bd;
-  };
-#pragma unroll
-  for (int i = 0; i < kOwn; ++i)
-    if (gt + kG * i < n) link(mine[i]);
-  for (uint32_t k = gt + kG * kOwn; k < n; k += kG) link(w.gbuf[off + k]);
 }
 
 // ------------------------------------------------------- a3/a4: clean/start
@@ -1759,15 +1952,20 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_MARK(PH_SCATTER);
   k_scatter<<<nchunk, TB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
-  k_rows_tiny<<<(unsigned)((w.RU + TB / 64 - 1) / (TB / 64)), TB, 0, st>>>(w);
-  k_rows<false><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
-  k_rows<true><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  const bool lists = ru_lists(w.RU);
+  const unsigned g_all = (unsigned)w.RU;
+  const unsigned g_mid = lists ? std::min(g_all, kListGrid) : g_all, g_big = lists ? std::min(g_all, kListGridBig) : g_all;
+  const unsigned g_wave = (unsigned)((w.RU + TB / 64 - 1) / (TB / 64));
+  k_rows_tiny<<<g_wave, TB, 0, st>>>(w);
+  k_rows_wave<<<lists ? std::min(g_wave, kListGrid) : g_wave, TB, 0, st>>>(w);
+  k_rows<false><<<g_mid, TB, 0, st>>>(w);
+  k_rows<true><<<g_big, TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   const unsigned nbN = (unsigned)w.nb;
   TPCCA_MARK(PH_LINKS);
-  k_links<kTiny, 64><<<(unsigned)((w.RU + TB / 64 - 1) / (TB / 64)), TB, 0, st>>>(w);
-  k_links<kSmallSlab, TB><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
-  k_links<kSlab, TB><<<dim3((unsigned)w.RU), TB, 0, st>>>(w);
+  k_links<kTiny, 64><<<g_wave, TB, 0, st>>>(w);
+  k_links<kSmallSlab, TB><<<g_mid, TB, 0, st>>>(w);
+  k_links<kSlab, TB><<<g_big, TB, 0, st>>>(w);
   TPCCA_MARK(PH_CLEAN);
   k_clean<<<nbN, TB, 0, st>>>(w);
   TPCCA_MARK(PH_COMPACT);

@@ -165,6 +165,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_ruc = L.take<uint32_t>(RU), o_ruo = L.take<uint32_t>(RU + 1);
   size_t o_cc = L.take<uint32_t>(RU), o_cb = L.take<uint32_t>(RU + 1);
   size_t o_grid = L.take<GridParams>(RU);
+  size_t o_lr = L.take<uint32_t>(RU), o_ll = L.take<uint32_t>(RU), o_lb = L.take<uint32_t>(RU);
   size_t o_tmp = L.take<float4>(N);
   size_t o_cx = L.take<float>(N), o_cy = L.take<float>(N), o_cz = L.take<float>(N);
   size_t o_cid = L.take<uint32_t>(N), o_cru = L.take<uint32_t>(N);
@@ -195,6 +196,8 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.ru_count = (uint32_t*)(base + o_ruc); w.ru_off = (uint32_t*)(base + o_ruo);
     w.cell_cap = (uint32_t*)(base + o_cc); w.cell_base = (uint32_t*)(base + o_cb);
     w.grid = (GridParams*)(base + o_grid);
+    w.ru_rows = (uint32_t*)(base + o_lr); w.ru_links = (uint32_t*)(base + o_ll);
+    w.ru_big = (uint32_t*)(base + o_lb);
     w.tmp4 = (float4*)(base + o_tmp);
     w.cx = (float*)(base + o_cx); w.cy = (float*)(base + o_cy); w.cz = (float*)(base + o_cz);
     w.cid = (uint32_t*)(base + o_cid); w.cru = (uint32_t*)(base + o_cru);

@@ -314,6 +314,26 @@ def test_dense_rows_take_the_fallback_paths(tracker, orc):
     assert out.n_tracks > 0
 
 
+def test_batch_with_dense_rows_equals_single_events(tracker):
+    """A batch large enough for the row-unit class lists (more than 16,384 row
+    units), holding units of every row and link class (a dense event with
+    1600- and 650-cluster rows, a one-sector event of ~100 clusters per row,
+    a small event): each event's output equals its single-event call."""
+    dense = synth.make_event(seed=31, n_primaries=150, noise=0.01, single_sector=True)
+    patches = [(r, 1600, (-10.0, 10.0), (40.0, 120.0)) for r in (40, 41, 42, 43)]
+    patches += [(r, 650, (-6.0, 6.0), (150.0, 180.0)) for r in (80, 81, 82)]
+    evs = [_with_patches(dense, patches, seed=32), synth.make_config("C1"),
+           synth.make_event(seed=8, n_primaries=200, noise=0.02)]
+    assert len(evs) * evs[0].geom.n_sectors * evs[0].geom.n_rows > 16384
+    batch = tracker.track_batch([to_dev(e) for e in evs], taps=True)
+    for e, ev in enumerate(evs):
+        single = tracker.track(*to_dev(ev), taps=True)
+        for k in ("sector", "x_ref", "p", "cov", "chi2", "ndf", "k_prior", "hit_off", "hit_id"):
+            assert torch.equal(getattr(batch[e], k), getattr(single, k)), (e, k)
+        for k in ("up", "dn", "cup", "cdn", "start"):
+            assert torch.equal(batch[e].taps[k], single.taps[k]), (e, k)
+
+
 def test_batch_of_uneven_events_matches_oracle(tracker, orc):
     """Several events of the batching workload (lognormal multiplicity) in one
     call, each compared with the oracle in full."""
