@@ -92,7 +92,7 @@ def lib():
         L.orc_rotate.restype = C.c_int
         L.orc_merge.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
                                 C.POINTER(C.c_int16), C.c_int64, i32p, dp, dp, dp, dp, i64p, i64p,
-                                i32p, i32p, dp, dp, i32p, dp, dp, C.POINTER(C.POINTER(Result))]
+                                i32p, i32p, i32p, dp, dp, i32p, dp, dp, C.POINTER(C.POINTER(Result))]
         fp = C.POINTER(C.c_float)
         L.orc_calib_apply32.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), fp, fp, fp,
                                         fp, fp, fp]
@@ -225,11 +225,13 @@ def rotate(x, p, cov, dalpha, bz=0.5, sin_max=0.99, precision=64):
     return bool(ok), ox.value, op, oc, J.reshape(5, 5)
 
 
-def merge(ev, seg, params=None):
+def merge(ev, seg, params=None, slices=None):
     """The sector merger on the segments `seg` of event `ev` (a track()
     result: sector, x_ref, p, cov, chi2, hit_off, hit_ids).  Returns the
     links, the per-segment best candidates with their chi2 and second-best
-    chi2, and the merged tracks (head = index of the innermost segment)."""
+    chi2, and the merged tracks (head = index of the innermost segment).
+    `ev` needs geom, n, x, y, z (float32 or float64) and row.  slices: the
+    time-frame slice of every segment (None for one event)."""
     g = make_geometry(ev.geom)
     P = params or default_params()
     x = np.ascontiguousarray(ev.x, dtype=np.float64); y = np.ascontiguousarray(ev.y, dtype=np.float64)
@@ -248,8 +250,10 @@ def merge(ev, seg, params=None):
     out = C.POINTER(Result)()
     i32 = lambda a: _ptr(a, C.c_int32)
     f64 = lambda a: _ptr(a, C.c_double)
+    sl = None if slices is None else np.ascontiguousarray(slices, dtype=np.int32)
     lib().orc_merge(C.byref(g), C.byref(P), ev.n, f64(x), f64(y), f64(z), _ptr(row, C.c_int16), ns, i32(sec),
-                    f64(xr), f64(sp), f64(sc), f64(sx2), _ptr(so, C.c_int64), _ptr(si, C.c_int64), i32(link),
+                    f64(xr), f64(sp), f64(sc), f64(sx2), _ptr(so, C.c_int64), _ptr(si, C.c_int64),
+                    i32(sl) if sl is not None else None, i32(link),
                     i32(bi), f64(ci), f64(ci2), i32(bo), f64(co), f64(co2), C.byref(out))
     r = out.contents
     nt = r.n_tracks
@@ -261,6 +265,81 @@ def merge(ev, seg, params=None):
                hit_off=_arr(r.hit_off, nt + 1, np.int64), hit_ids=_arr(r.hit_ids, int(r.hit_off[nt]), np.int64))
     lib().orc_result_free(out)
     return res
+
+
+class _Clusters:
+    """Cluster arrays with a geometry, in the form track() and merge() read."""
+
+    def __init__(self, geom, x, y, z, row, sector):
+        self.geom, self.x, self.y, self.z, self.row, self.sector = geom, x, y, z, row, sector
+
+    @property
+    def n(self):
+        return int(self.x.shape[0])
+
+
+def timeframe_slices(geom, tau, sector, slice_len):
+    """Slicing of a continuous-readout time frame (reading R-25): slice s =
+    floor(tau / slice_len) with the quotient rounded to FP32, and the
+    pseudo-coordinate z' = side (L - (tau - s slice_len)) evaluated in FP32
+    in that order (side = +1 for the first half of the sectors, -1 for the
+    second; L = z_max).  Returns (s int64, z' float32)."""
+    L = np.float32(geom.z_max)
+    D = np.float32(slice_len)
+    tau = np.asarray(tau, dtype=np.float32)
+    s = np.floor(tau / D).astype(np.int64)
+    side = np.where(np.asarray(sector).astype(np.int64) < geom.n_sectors // 2, np.float32(1.0), np.float32(-1.0))
+    zp = side * (L - (tau - s.astype(np.float32) * D))
+    return s, zp.astype(np.float32)
+
+
+def timeframe(tf, slice_len, n_slices, params=None):
+    """Time-frame tracking (Sec. "Track reconstruction in the TPC": slices of
+    the frame along the time axis tracked individually, their segments
+    merged afterwards; reading R-25).
+      1. every cluster gets its slice and pseudo-coordinate (timeframe_slices);
+         0 <= slice < n_slices is required;
+      2. each slice is tracked as one event (track(), FP32) on its clusters
+         in ascending frame order (x, y, z', row, sector);
+      3. the segments are taken into frame coordinates: hit ids to frame
+         ids, the state's z shifted by -side s slice_len (FP64);
+      4. the sector merger (FP64) runs on all segments with their slice
+         indices, on the frame coordinates of the clusters, z = side (L - tau)
+         (FP64 from the FP32 tau).
+    Returns dict(seg=..., slice=..., merged=merge() result)."""
+    geom = tf.geom
+    P = params or default_params()
+    s, zp = timeframe_slices(geom, tf.tau, tf.sector, slice_len)
+    if s.size and (s.min() < 0 or s.max() >= n_slices):
+        raise ValueError("cluster outside the slices")
+    half = geom.n_sectors // 2
+    keys = ("sector", "x_ref", "p", "cov", "chi2", "ndf")
+    parts = {k: [] for k in keys}
+    offs, ids, sl = [0], [], []
+    for k in range(n_slices):
+        idx = np.nonzero(s == k)[0]
+        ev = _Clusters(geom, tf.x[idx], tf.y[idx], zp[idx], tf.row[idx], tf.sector[idx])
+        r = track(ev, precision=32, params=P)
+        nt = len(r["x_ref"])
+        side = np.where(r["sector"] < half, 1.0, -1.0)
+        p = r["p"].copy()
+        p[:, 1] = p[:, 1] - side * (float(k) * float(np.float32(slice_len)))
+        for key in keys:
+            parts[key].append(p if key == "p" else r[key])
+        for t in range(nt):
+            h = idx[r["hit_ids"][r["hit_off"][t]:r["hit_off"][t + 1]]]
+            ids.append(h)
+            offs.append(offs[-1] + len(h))
+        sl.append(np.full(nt, k, np.int32))
+    seg = {key: np.concatenate(v) if v else np.zeros(0) for key, v in parts.items()}
+    seg["hit_off"] = np.asarray(offs, np.int64)
+    seg["hit_ids"] = np.concatenate(ids).astype(np.int64) if ids else np.zeros(0, np.int64)
+    slices = np.concatenate(sl) if sl else np.zeros(0, np.int32)
+    side_c = np.where(tf.sector.astype(np.int64) < half, 1.0, -1.0)
+    ztf = side_c * (float(geom.z_max) - tf.tau.astype(np.float64))
+    frame = _Clusters(geom, tf.x.astype(np.float64), tf.y.astype(np.float64), ztf, tf.row, tf.sector)
+    merged = merge(frame, seg, params=P, slices=slices)
+    return dict(seg=seg, slice=slices, merged=merged, z_tf=ztf)
 
 
 def calib_apply(ev_or_geom, sector, x, y, z, theta):

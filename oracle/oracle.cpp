@@ -778,7 +778,9 @@ bool match_chi2(const double d[5], const double M[15], double& chi2) {
 //  2. a pair (a inner, b outer) is a candidate iff a and b lie in sectors of
 //     the same side whose wedges are adjacent, a's last pad row is below b's
 //     first, and a's outermost hit lies within merge_dist of b's innermost
-//     hit both in the transverse plane and in z;
+//     hit both in the transverse plane and in z; in a time frame (slice
+//     indices given) also a pair in the same sector whose slices are
+//     neighbours, under the same row and distance conditions (no rotation);
 //  3. its match chi2: a's exit state rotated into b's frame and transported
 //     to b's reference plane, compared with b's state: Delta^T (C_a + C_b)^-1
 //     Delta over the five parameters; a candidate is valid iff the rotation
@@ -812,7 +814,7 @@ struct MergeOut {
 MergeOut merge_segments(const orc_geometry& g, const orc_params& P, const double* x, const double* y,
                         const double* z, const int16_t* row, int64_t nseg, const int32_t* ssec,
                         const double* sxref, const double* sp, const double* scov, const double* schi2,
-                        const int64_t* soff, const int64_t* sids) {
+                        const int64_t* soff, const int64_t* sids, const int32_t* sslice) {
   const Model<double> m = make_model<double>(g, P);
   const int S = g.n_sectors, NW = S / 2;
   const double INF = std::numeric_limits<double>::infinity();
@@ -858,8 +860,9 @@ MergeOut merge_segments(const orc_geometry& g, const orc_params& P, const double
       const bool same_side = (sec[a] < NW) == (sec[b] < NW);
       const int wa = sec[a] % NW, wb = sec[b] % NW;
       const bool adjacent = (wb == (wa + 1) % NW) || (wa == (wb + 1) % NW);
-      if (!same_side || !adjacent || !(rhi[a] < rlo[b])) continue;
-      const double turn = frame_turn(sec[a], sec[b], S);
+      const bool slices = sec[a] == sec[b] && sslice != nullptr && std::abs(sslice[a] - sslice[b]) == 1;
+      if (!((same_side && adjacent) || slices) || !(rhi[a] < rlo[b])) continue;
+      const double turn = slices ? 0.0 : frame_turn(sec[a], sec[b], S);
       const double ca = std::cos(turn), sa = std::sin(turn);
       const int64_t ha = hits[a].back(), hb = hits[b].front();
       const double xa = x[ha] * ca + y[ha] * sa, ya = -(x[ha] * sa) + y[ha] * ca;
@@ -869,7 +872,7 @@ MergeOut merge_segments(const orc_geometry& g, const orc_params& P, const double
       double xx = ex[a], q[5], Q[15];
       for (int k = 0; k < 5; ++k) q[k] = ep[a * 5 + k];
       for (int k = 0; k < 15; ++k) Q[k] = ec[a * 15 + k];
-      if (!rotate_state(xx, q, Q, ca, sa, m)) continue;
+      if (!slices && !rotate_state(xx, q, Q, ca, sa, m)) continue;
       if (!transport(q, Q, xx, sxref[b], m)) continue;
       double d[5], M[15], chi;
       for (int k = 0; k < 5; ++k) d[k] = q[k] - sp[b * 5 + k];
@@ -964,8 +967,11 @@ bool refit_chain(const orc_geometry& g, const orc_params& P, const Model<R>& m,
     }
     if (ci == 0) break;
     // into the frame of the next inner segment
+    // (segments of one sector from neighbouring slices share the frame)
     const double turn = frame_turn(sec[chain[ci]], sec[chain[ci - 1]], S);
-    if (!rotate_state(xc, p, C, R(std::cos(turn)), R(std::sin(turn)), m)) return false;
+    if (sec[chain[ci]] != sec[chain[ci - 1]] &&
+        !rotate_state(xc, p, C, R(std::cos(turn)), R(std::sin(turn)), m))
+      return false;
     --ci;
     hl = &hits[chain[ci]];
     hi = (int)hl->size() - 1;
@@ -1296,11 +1302,12 @@ int orc_merge(const orc_geometry* g, const orc_params* P, int64_t n_clusters, co
               const double* y, const double* z, const int16_t* row, int64_t n_seg,
               const int32_t* seg_sector, const double* seg_xref, const double* seg_p,
               const double* seg_cov, const double* seg_chi2, const int64_t* seg_hit_off,
-              const int64_t* seg_hit_ids, int32_t* link, int32_t* best_in, double* chi_in, double* chi_in2,
-              int32_t* best_out, double* chi_out, double* chi_out2, orc_result** out) {
+              const int64_t* seg_hit_ids, const int32_t* seg_slice, int32_t* link, int32_t* best_in,
+              double* chi_in, double* chi_in2, int32_t* best_out, double* chi_out, double* chi_out2,
+              orc_result** out) {
   (void)n_clusters;
   MergeOut o = merge_segments(*g, *P, x, y, z, row, n_seg, seg_sector, seg_xref, seg_p, seg_cov, seg_chi2,
-                              seg_hit_off, seg_hit_ids);
+                              seg_hit_off, seg_hit_ids, seg_slice);
   for (int64_t i = 0; i < n_seg; ++i) {
     link[i] = o.link[i]; best_in[i] = o.best_in[i]; best_out[i] = o.best_out[i];
     chi_in[i] = o.chi_in[i]; chi_in2[i] = o.chi_in2[i]; chi_out[i] = o.chi_out[i]; chi_out2[i] = o.chi_out2[i];

@@ -119,13 +119,16 @@ void orc_result_free(orc_result* r);
  * the second-best chi2 (inf if none) -- what decides each link; and the
  * merged tracks in out (trk_seed = the index of the chain's innermost
  * segment, sector, x_ref, p, cov, chi2, ndf, hit lists innermost segment
- * first).  Returns 0. */
+ * first).  seg_slice (NULL for one event): the time-frame slice of each
+ * segment; then segments of one sector from neighbouring slices are
+ * candidates as well (same frame, no rotation).  Returns 0. */
 int orc_merge(const orc_geometry* g, const orc_params* P, int64_t n_clusters, const double* x,
               const double* y, const double* z, const int16_t* row, int64_t n_seg,
               const int32_t* seg_sector, const double* seg_xref, const double* seg_p,
               const double* seg_cov, const double* seg_chi2, const int64_t* seg_hit_off,
-              const int64_t* seg_hit_ids, int32_t* link, int32_t* best_in, double* chi_in, double* chi_in2,
-              int32_t* best_out, double* chi_out, double* chi_out2, orc_result** out);
+              const int64_t* seg_hit_ids, const int32_t* seg_slice, int32_t* link, int32_t* best_in,
+              double* chi_in, double* chi_in2, int32_t* best_out, double* chi_out, double* chi_out2,
+              orc_result** out);
 
 /* Rotation of a state at plane x from the frame of one sector to a frame
  * turned by dalpha (radians) about z: writes the new plane, state,

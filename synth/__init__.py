@@ -10,3 +10,4 @@ from .events import (  # noqa: F401
     Geometry, Event, CalibTheta, default_geometry, make_event, make_config, make_configs,
     bspline_basis, draw_theta, CONFIGS,
 )
+from .timeframe import TimeFrame, make_timeframe, make_tf_config, TF_CONFIGS, TF_SLICE  # noqa: F401
