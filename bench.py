@@ -47,8 +47,11 @@ def main():
                     help="threads of the multi-threaded oracle sample (0: the usable cores, at most 16)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
+    ap.add_argument("--no-timeframe", action="store_true", help="skip the time-frame leg")
     ap.add_argument("--grad-only", action="store_true",
                     help="only run the calibration-gradient leg (for its kernel trace)")
+    ap.add_argument("--timeframe-only", action="store_true",
+                    help="only run the time-frame leg (for its kernel trace)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run device copies of this many MiB (calibrates PMC byte counters)")
@@ -65,6 +68,14 @@ def main():
         import torch
         from paper_1712_09434_amd import Tracker
         print(json.dumps({"grad": grad_leg(Tracker, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.timeframe_only:
+        import torch
+        import synth
+        from paper_1712_09434_amd import Tracker
+        trk = Tracker.from_geometry(synth.default_geometry())
+        print(json.dumps({"timeframe": timeframe_leg(trk, torch.device("cuda:0"))}), flush=True)
+        trk.close()
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -127,6 +138,7 @@ def main():
 
     merge = merge_leg(trk, (x, y, z, row, sec), out, args)
     batch = None if args.no_batch else batch_leg(args, Tracker, dev)
+    timeframe = None if args.no_timeframe else timeframe_leg(trk, dev)
     grad = None if args.no_grad else grad_leg(Tracker, dev)
 
     line = {
@@ -142,6 +154,7 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
         "merge": merge,
         "batch": batch,
+        "timeframe": timeframe,
         "grad": grad,
     }
     trk.close()
@@ -219,47 +232,48 @@ def pmc_summary(folder: str):
 
     fetch, write = load("pmc_fetch"), load("pmc_write")
     cf, cw = load("pmc_copy_fetch"), load("pmc_copy_write")
-    big = lambda d: max(max(v) for v in d.values())
-    kib = 1024 * 1024
-    sf, sw = kib / big(cf), kib / big(cw)
-    mean = lambda v: sum(v) / len(v)
-    rows, rec = [], {}
-    for k in sorted(set(fetch) | set(write), key=lambda k: -mean(fetch.get(k, [0]))):
-        if not k.startswith("k_"):
-            continue
-        f, w = mean(fetch.get(k, [0.0])), mean(write.get(k, [0.0]))
-        b = (f * sf + w * sw) * 1024
-        rec[k] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": round(b)}
-        rows.append(f"| {k} | {f:,.0f} | {w:,.0f} | {b / 1e6:,.1f} |")
-    record = {"workload": "C3", "source_sha256": kernel_source_hash(), "fetch_scale": round(sf, 4),
-              "write_scale": round(sw, 4), "kernels": rec}
-    text = f"""# HBM traffic per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
+    if fetch and write and cf and cw:
+        big = lambda d: max(max(v) for v in d.values())
+        kib = 1024 * 1024
+        sf, sw = kib / big(cf), kib / big(cw)
+        mean = lambda v: sum(v) / len(v)
+        rows, rec = [], {}
+        for k in sorted(set(fetch) | set(write), key=lambda k: -mean(fetch.get(k, [0]))):
+            if not k.startswith("k_"):
+                continue
+            f, w = mean(fetch.get(k, [0.0])), mean(write.get(k, [0.0]))
+            b = (f * sf + w * sw) * 1024
+            rec[k] = {"fetch_kib": round(f, 1), "write_kib": round(w, 1), "bytes_per_launch": round(b)}
+            rows.append(f"| {k} | {f:,.0f} | {w:,.0f} | {b / 1e6:,.1f} |")
+        record = {"workload": "C3", "source_sha256": kernel_source_hash(), "fetch_scale": round(sf, 4),
+                  "write_scale": round(sw, 4), "kernels": rec}
+        text = f"""# HBM traffic per kernel, central-Pb-Pb-shaped event (3.81 M clusters)
 
-Commands (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+    Commands (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
-    rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_fetch -o fetch -- {PMC_BENCH_CMD}
-    rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_write -o write -- {PMC_BENCH_CMD}
-    rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_copy_fetch -o cfetch -- python3 bench.py --copy-probe-mib 1024
-    rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_copy_write -o cwrite -- python3 bench.py --copy-probe-mib 1024
-    python3 bench.py --pmc-summary <out>
+        rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_fetch -o fetch -- {PMC_BENCH_CMD}
+        rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_write -o write -- {PMC_BENCH_CMD}
+        rocprofv3 --pmc FETCH_SIZE -f csv -d <out>/pmc_copy_fetch -o cfetch -- python3 bench.py --copy-probe-mib 1024
+        rocprofv3 --pmc WRITE_SIZE -f csv -d <out>/pmc_copy_write -o cwrite -- python3 bench.py --copy-probe-mib 1024
+        python3 bench.py --pmc-summary <out>
 
-Scale: a plain 1 GiB device copy reads as {big(cf):,.0f} KiB of FETCH_SIZE and {big(cw):,.0f} KiB of
-WRITE_SIZE, so fetch counts are multiplied by {sf:.4f} and write counts by {sw:.4f}.  Values are
-means over the profiled dispatches (6 calls).
+    Scale: a plain 1 GiB device copy reads as {big(cf):,.0f} KiB of FETCH_SIZE and {big(cw):,.0f} KiB of
+    WRITE_SIZE, so fetch counts are multiplied by {sf:.4f} and write counts by {sw:.4f}.  Values are
+    means over the profiled dispatches (6 calls).
 
-| Kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled HBM MB/launch |
-|---|---|---|---|
-""" + "\n".join(rows) + f"""
+    | Kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled HBM MB/launch |
+    |---|---|---|---|
+    """ + "\n".join(rows) + f"""
 
-The record below is read by `bench.py` (roofline `traffic`) only while the kernel sources hash to
-`source_sha256`.
+    The record below is read by `bench.py` (roofline `traffic`) only while the kernel sources hash to
+    `source_sha256`.
 
-record: {json.dumps(record)}
-"""
-    os.makedirs(os.path.dirname(TRAFFIC_RECORD), exist_ok=True)
-    with open(TRAFFIC_RECORD, "w") as f:
-        f.write(text)
-    print(text)
+    record: {json.dumps(record)}
+    """
+        os.makedirs(os.path.dirname(TRAFFIC_RECORD), exist_ok=True)
+        with open(TRAFFIC_RECORD, "w") as f:
+            f.write(text)
+        print(text)
     stats = glob.glob(os.path.join(folder, "prof_c3", "**", "*kernel_stats.csv"), recursive=True)
     if stats:
         lines = []
@@ -368,6 +382,32 @@ sources sha256 `{kernel_source_hash()}`.
             with open(os.path.join(ROOT, "profiles", "tracking_c3_sq_counters.md"), "w") as f:
                 f.write(text3)
             print(text3)
+    tf_stats = glob.glob(os.path.join(folder, "prof_tf", "**", "*kernel_stats.csv"), recursive=True)
+    if tf_stats:
+        tl = []
+        for r in csv.DictReader(open(tf_stats[0])):
+            name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+            name = re.sub(r"^void ", "", name)
+            tl.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        body_t = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in tl[:28])
+        text_t = f"""# Kernel trace, continuous-readout time frame (24 collisions over 6 drift lengths, 5.77 M clusters)
+
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_tf -o tf -- python3 bench.py --timeframe-only
+python3 bench.py --pmc-summary <out>
+
+tpcca_track_timeframe with 6 slices of one drift length: 2 warm-up calls with the segment
+outputs, 5 timed calls; average duration per dispatch (the tracking kernels run once per call
+over the batch of 6 slices).
+
+| Kernel | Calls | Average µs | % of GPU time |
+|---|---|---|---|
+{body_t}
+"""
+        with open(os.path.join(ROOT, "profiles", "timeframe_tf24_kernel_trace.md"), "w") as f:
+            f.write(text_t)
+        print(text_t)
 
 
 def copy_probe(mib: int, reps: int = 5):
@@ -454,6 +494,42 @@ def batch_leg(args, Tracker, dev):
             "phase_ms": {k: round(v, 4) for k, v in batch_phases.items()},
             "batched_tuning": {"tracklet_grid": best["tracklet_grid"], "use_graph": best["use_graph"]},
             "sequential_tuning": {"tracklet_grid": seq_best[1], "use_graph": seq_best[2]}}
+
+
+def timeframe_leg(trk, dev, reps=5):
+    """One continuous-readout time frame (24 collisions of lognormal
+    multiplicity over 6 drift lengths, 5.8 M clusters) sliced per drift
+    length, tracked as one batch of slices and merged across slices and
+    sectors: tpcca_track_timeframe, inputs resident in HBM."""
+    import numpy as np
+    import torch
+
+    import synth
+    log("generating the time frame")
+    tf = synth.make_tf_config("TF")
+    D = synth.TF_SLICE
+    ns = int(np.ceil(tf.length / D))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    cl = (t(tf.x), t(tf.y), t(tf.tau), t(tf.row), t(tf.sector))
+    trk.set_phase_timing(False)
+    for _ in range(2):
+        merged, seg, sl, lk = trk.track_timeframe(*cl, D, ns, segments=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m = trk.track_timeframe(*cl, D, ns)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    lkn = lk.cpu().numpy()
+    s = seg.sector.cpu().numpy()
+    links = int((lkn >= 0).sum())
+    slice_links = int(sum(1 for a in np.nonzero(lkn >= 0)[0] if s[a] == s[lkn[a]]))
+    log(f"time frame: {tf.n} clusters, {ns} slices: {dt * 1e3:.2f} ms, {tf.n / dt:.3e} clusters/s; "
+        f"{seg.n_tracks} segments, {links} links ({slice_links} across slices), {m.n_tracks} tracks")
+    return {"workload": "24 collisions (lognormal multiplicity, 2% noise) over 6 drift lengths, seed 1006002, "
+                        "sliced per drift length", "clusters": tf.n, "slices": ns, "ms_per_frame": dt * 1e3,
+            "clusters_per_s": tf.n / dt, "segments": seg.n_tracks, "links": links, "slice_links": slice_links,
+            "tracks": m.n_tracks}
 
 
 def merge_leg(trk, cl, seg, args, reps=20):

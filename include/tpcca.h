@@ -264,6 +264,41 @@ int tpcca_track_batch(tpcca_ctx* ctx, int32_t n_events, const tpcca_clusters* ev
  * 3 hits, a bad sector or hit id. */
 int tpcca_merge(tpcca_ctx* ctx, const tpcca_tracks* segments, tpcca_tracks* merged, int32_t* seg_link);
 
+/* Time-frame tracking (Sec. "Track reconstruction in the TPC": with
+ * continuous readout the TPC delivers time frames of overlapping
+ * collisions; a frame is sliced along the time axis, the slices are tracked
+ * individually and their track segments merged afterwards).
+ * frame: the clusters of one time frame, device memory: x, y, row, sector
+ * as for tpcca_track; z holds tau, the readout time since the frame start
+ * in drift-length units (cm): for a cluster at z of a collision at time c,
+ * tau = c + z_max - side z (side = +1 in the first half of the sectors, -1
+ * in the second).  Cluster ids are frame indices.
+ * slice_len D (cm, 0 < D <= 2 z_max) and n_slices (1 .. TPCCA_TF_MAX_SLICES):
+ * the slice of a cluster is s = floor(tau / D) (FP32 quotient) and must lie
+ * in [0, n_slices); slices do not overlap.
+ * Each slice is tracked as one event of a batch (tpcca_track_batch) on its
+ * clusters in ascending frame order with z' = side (z_max - (tau - s D))
+ * (FP32, in that order) in place of z; the segments are taken to frame
+ * coordinates (hit ids = frame indices; the z of the state shifted by
+ * -side s D, so that a cluster's z is side (z_max - tau)) and merged as by
+ * tpcca_merge, where two segments of one sector from neighbouring slices are
+ * candidates too (same frame, no rotation).  The installed calibration is
+ * not applied (its drift terms need the collision time).
+ * Outputs, device memory: merged (required): the merged tracks in frame
+ * coordinates, as tpcca_merge writes them; segments (optional, NULL = not
+ * returned): the per-slice tracks in frame coordinates, slices ascending;
+ * seg_slice, seg_link (optional, [segments]): each segment's slice and outer
+ * merge partner (-1 if none).  Both track outputs need cap_tracks >= the
+ * number of segments and cap_hits >= their hits; at most n / min_hits +
+ * n_slices tracks and n hits.  Otherwise TPCCA_E_CAPACITY with the required
+ * counts in n_tracks / n_hits (the tracking was done; only the outputs are
+ * missing).  TPCCA_E_INVALID for host memory, null arrays, a bad slice
+ * length or count, a non-finite tau or one outside the slices; the errors
+ * of tpcca_track otherwise. */
+#define TPCCA_TF_MAX_SLICES 1024
+int tpcca_track_timeframe(tpcca_ctx* ctx, const tpcca_clusters* frame, float slice_len, int32_t n_slices,
+                          tpcca_tracks* merged, tpcca_tracks* segments, int32_t* seg_slice, int32_t* seg_link);
+
 /* Calibration objective and gradient (Sec. "Approach for online
  * calibration"; Sec. "Overview of HLT online calibration"): apply the
  * correction theta to the default-transformed clusters tracks->clusters,

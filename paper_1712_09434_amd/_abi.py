@@ -26,13 +26,14 @@ TPCCA_NOALLOC_SCRATCH_BYTES = 128 << 20
 TPCCA_TRK_NOT_FITTED, TPCCA_TRK_HITS, TPCCA_TRK_VERTEX, TPCCA_TRK_SHORT = 0, 1, 2, 4
 TPCCA_GRAD_MIN_HITS = 40
 TPCCA_GRAD_C2_UPDATES = 3
+TPCCA_TF_MAX_SLICES = 1024
 ERROR_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_CAPACITY", -3: "E_DEVICE", -4: "E_NOMEM", -5: "E_LIMIT"}
 
 EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_get_params",
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
             "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc",
-            "tpcca_set_calib", "tpcca_merge"]
+            "tpcca_set_calib", "tpcca_merge", "tpcca_track_timeframe"]
 
 
 class tpcca_geometry(C.Structure):
@@ -115,6 +116,9 @@ def load(path: str = LIB_PATH):
     L.tpcca_track.argtypes = [C.c_void_p, P(tpcca_clusters), P(tpcca_tracks)]
     L.tpcca_merge.argtypes = [C.c_void_p, P(tpcca_tracks), P(tpcca_tracks), C.c_void_p]
     L.tpcca_merge.restype = C.c_int
+    L.tpcca_track_timeframe.argtypes = [C.c_void_p, P(tpcca_clusters), C.c_float, C.c_int32, P(tpcca_tracks),
+                                        P(tpcca_tracks), C.c_void_p, C.c_void_p]
+    L.tpcca_track_timeframe.restype = C.c_int
     L.tpcca_set_calib.argtypes = [C.c_void_p, P(tpcca_calib)]
     L.tpcca_set_calib.restype = C.c_int
     L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]

@@ -181,6 +181,7 @@ struct PhaseEvents {
 // Host-side launchers (tpcca_kernels.hip).
 hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe = nullptr);
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st);
 hipError_t fp32_probe(int op, int64_t n, const float* a, const float* b, float* out, hipStream_t st);
 
 }  // namespace tpcca

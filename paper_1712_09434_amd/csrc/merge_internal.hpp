@@ -25,6 +25,7 @@ struct MergeWs {
   const float* cz;
   const int16_t* crow;
   int64_t NC;
+  const int32_t* slice;    // [T] time-frame slice of each segment, or null (one event)
   // work
   float* ex;               // [T][24]: exit plane, state, covariance (if the exit transport succeeded)
   float4* first;           // [T] innermost hit (x, y, z, row bits)
@@ -37,7 +38,7 @@ struct MergeWs {
   unsigned long long* best_out;  // [T] (chi2 bits << 32) | outer partner, or ~0
   int32_t* link;           // [T] outer partner or -1
   int32_t* inner;          // [T] inner partner or -1
-  float4* srec;            // [T] by sector: outermost hit (x, y, z), (last row << 1 | exit valid) bits
+  float4* srec;            // [T] by sector: outermost hit (x, y, z), (slice << 9 | last row << 1 | exit valid) bits
   uint32_t* emit;          // [T + 1] output tracks of the chain headed by a segment -> offsets
   uint32_t* hemit;         // [T + 1] hits of those tracks -> offsets
   int32_t* head;           // [T] the head of each segment's chain
@@ -47,6 +48,7 @@ struct MergeWs {
   uint32_t* rlist;         // [T] heads of chains of two or more segments
   float* rec;              // [T][24]: merged refit of a chain head (x_ref, p, cov, chi2)
   uint32_t* err;           // [4]: error bits, output tracks, output hits, chains to refit
+  uint32_t* scan_part;     // [2 (T / 1024 + 2)] partial sums of the offset scans
   // outputs (device)
   uint8_t* o_sector;
   float* o_x_ref;

@@ -1892,6 +1892,12 @@ __global__ __launch_bounds__(TB) void k_write(Ws w) {
 
 }  // namespace
 
+// Exclusive scan of n values into out[0 .. n] (out[n] = total); part holds
+// 2 (n / 1024 + 2) values.
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st) {
+  return scan_u32(in, out, n, part, st);
+}
+
 // Persistent grid of the tracklet kernel: one lane per possible seed (the
 // workgroups past the actual seed count leave at once), or the tuned value.
 unsigned tracklet_grid(const Ws& w) {

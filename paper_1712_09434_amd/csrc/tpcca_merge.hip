@@ -11,14 +11,18 @@
 // into b's frame and transported to b's reference plane, with b's state
 // under the summed covariance; links are mutual best pairs under
 // chi2_merge; chains of linked segments are refitted as one track, the
-// state rotated into the next inner segment's frame at each boundary.
+// state rotated into the next inner segment's frame at each boundary.  In
+// a time frame (slice indices given) two segments of one sector from
+// neighbouring slices are candidates too, under the same row and distance
+// conditions, and share the frame (no rotation).
 //
 // Kernels, one lane per segment unless noted: exit states and hit ends,
 // segments listed by sector, candidate search (each outer segment scans the
-// two neighbouring sectors' lists; keys (chi2 bits, index) taken by atomic
+// two neighbouring sectors' lists, and its own in a time frame; keys (chi2
+// bits, index) taken by atomic
 // minimum, so the result does not depend on the scan order), mutual links,
-// chain walk and merged refit (lane per chain head), output offsets (one
-// workgroup), output writing (lane per chain head).
+// chain walk and merged refit (lane per chain head), output offsets
+// (exclusive scans), output writing (lane per chain head).
 #include <algorithm>
 
 #include "kf_c2.hpp"
@@ -217,15 +221,18 @@ __global__ __launch_bounds__(TB) void k_mrg_secfill(MergeWs w) {
   if (good) {
     const uint32_t pos = s_h[s] + rank;
     const float4 l = w.last[i];
+    const int sl = w.slice ? w.slice[i] : 0;   // (0 <= slice < 2^22, checked by the caller)
     w.sec_list[pos] = (uint32_t)i;
-    w.srec[pos] = make_float4(l.x, l.y, l.z, __int_as_float((__float_as_int(l.w) << 1) | (int)(w.flags[i] & 1u)));
+    w.srec[pos] = make_float4(l.x, l.y, l.z,
+                              __int_as_float((sl << 9) | (__float_as_int(l.w) << 1) | (int)(w.flags[i] & 1u)));
   }
 }
 
 // Candidate search of outer segment b over the lists of the two
-// neighbouring wedges of its side: one wave per b, its lanes taking every
-// 64th record (the cheap tests on the record first), the best candidate the
-// minimum of the lanes' (chi2 bits, index) keys.
+// neighbouring wedges of its side (and, in a time frame, of its own sector
+// for segments of the neighbouring slices): one wave per b, its lanes taking
+// every 64th record (the cheap tests on the record first), the best
+// candidate the minimum of the lanes' (chi2 bits, index) keys.
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) {
@@ -242,6 +249,7 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
   // in full one per lane (the full test is long; survivors are few and
   // scattered over the lanes)
   __shared__ uint32_t s_cand[TB / 64][64];
+  __shared__ uint8_t s_dir[TB / 64][64];
   const int wv = threadIdx.x >> 6;
   const int64_t b = (int64_t)blockIdx.x * (TB / 64) + wv;
   const int lane = threadIdx.x & 63;
@@ -251,14 +259,15 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
   const float4 hb = w.first[b];
   const int rlo_b = __float_as_int(hb.w);
   const float xb = w.x_ref[b];
+  const int slb = w.slice ? w.slice[b] : 0;
   unsigned long long best = kNone;
   int cnt = 0;                        // wave-uniform
   auto flush = [&]() {
     __builtin_amdgcn_wave_barrier();
     if (lane < cnt) {
-      const uint32_t v = s_cand[wv][lane];
-      const uint32_t k = v & 0x7FFFFFFFu;
-      const int wa = (v >> 31) ? (wb + 1) % w.NW : (wb + w.NW - 1) % w.NW;
+      const uint32_t k = s_cand[wv][lane];
+      const int dir = s_dir[wv][lane];
+      const int wa = dir == 1 ? (wb + 1) % w.NW : (wb + w.NW - 1) % w.NW;
       const float sa = turn_sign(wa, wb, w.NW) * w.sa, ca = w.ca;
       const uint32_t a = w.sec_list[k];
       const float* e = w.ex + (int64_t)a * 24;
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
 #pragma unroll
       for (int j = 0; j < 15; ++j) Q[j] = e[6 + j];
       float chi = 0.0f;
-      bool ok = rotate_state(x, q, Q, ca, sa, w.m);
+      bool ok = dir == 2 || rotate_state(x, q, Q, ca, sa, w.m);   // (one frame within a sector)
       if (ok) ok = transport(q, Q, x, xb, w.m);
       if (ok) {
         float d[5], M[15];
@@ -287,10 +296,12 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
     __builtin_amdgcn_wave_barrier();
     cnt = 0;
   };
-  for (int dir = 0; dir < 2; ++dir) {
-    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : (wb + 1) % w.NW;
+  const int ndir = w.slice ? 3 : 2;
+  for (int dir = 0; dir < ndir; ++dir) {
+    // 0, 1: the preceding and following wedge of the side; 2: the own sector
+    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : dir == 1 ? (wb + 1) % w.NW : wb;
     const int sa_ = side0 + wa;
-    const float sa = turn_sign(wa, wb, w.NW) * w.sa, ca = w.ca;
+    const float sa = dir == 2 ? 0.0f : turn_sign(wa, wb, w.NW) * w.sa, ca = dir == 2 ? 1.0f : w.ca;
     const uint32_t k0 = w.sec_cnt[sa_], k1 = w.sec_cnt[sa_ + 1];
     for (uint32_t kb = k0; kb < k1; kb += 64) {
       const uint32_t k = kb + (uint32_t)lane;
@@ -298,7 +309,8 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
       if (k < k1) {
         const float4 ha = w.srec[k];
         const int bits = __float_as_int(ha.w);
-        if ((bits & 1) && (bits >> 1) < rlo_b) {
+        const int dsl = (bits >> 9) - slb;
+        if ((bits & 1) && ((bits >> 1) & 0xFF) < rlo_b && (dir < 2 || dsl == 1 || dsl == -1)) {
           const float xa = ha.x * ca + ha.y * sa, ya = -(ha.x * sa) + ha.y * ca;
           const float dX = xa - hb.x, dY = ya - hb.y;
           const float dr = sqrtf(dX * dX + dY * dY);
@@ -309,7 +321,11 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
       const int np = __popcll(mask);
       if (np == 0) continue;
       if (cnt + np > 64) flush();
-      if (pass) s_cand[wv][cnt + __popcll(mask & lanemask_lt())] = k | ((uint32_t)dir << 31);
+      if (pass) {
+        const int slot = cnt + __popcll(mask & lanemask_lt());
+        s_cand[wv][slot] = k;
+        s_dir[wv][slot] = (uint8_t)dir;
+      }
       cnt += np;
     }
   }
@@ -343,7 +359,8 @@ __global__ __launch_bounds__(TB) void k_mrg_chains(MergeWs w) {
   if (i >= w.T) return;
   if (w.inner[i] >= 0 || w.err[0] != 0u) { w.emit[i] = 0u; w.hemit[i] = 0u; return; }
   uint32_t n = 0, hits = 0;
-  for (int32_t c = (int32_t)i; c >= 0 && n <= (uint32_t)w.S; c = w.link[c]) {
+  // (rows increase strictly along a chain, so it has at most R segments)
+  for (int32_t c = (int32_t)i; c >= 0 && n <= (uint32_t)w.R; c = w.link[c]) {
     w.head[c] = (int32_t)i;
     w.tpos[c] = n;
     w.hpos[c] = hits;
@@ -356,63 +373,9 @@ __global__ __launch_bounds__(TB) void k_mrg_chains(MergeWs w) {
   if (n > 1) w.rlist[atomicAdd(&w.err[3], 1u)] = (uint32_t)i;
 }
 
-// Exclusive scan of v[0 .. T) in place, one workgroup: tiles of kScanT x 4
-// entries staged in LDS by coalesced loads, four consecutive entries per
-// thread, a block scan of the thread sums, a running offset across tiles;
-// the total at v[T] and in *tot.
-constexpr int kScanT = 1024;
-constexpr int kScanPer = 4;
-__global__ __launch_bounds__(kScanT) void k_mrg_scan(uint32_t* __restrict__ v, int64_t T, uint32_t* __restrict__ tot) {
-  __shared__ uint32_t tile[kScanT * kScanPer];
-  __shared__ uint32_t sums[kScanT];
-  uint32_t base = 0;
-  constexpr int64_t kTile = (int64_t)kScanT * kScanPer;
-  for (int64_t t0 = 0; t0 < T; t0 += kTile) {
-    for (int k = 0; k < kScanPer; ++k) {
-      const int64_t j = t0 + (int64_t)k * kScanT + threadIdx.x;
-      tile[k * kScanT + threadIdx.x] = j < T ? v[j] : 0u;
-    }
-    __syncthreads();
-    uint32_t a = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) a += tile[threadIdx.x * kScanPer + k];
-    // inclusive scan of the thread sums: within each wave by shuffles, then
-    // over the sixteen wave totals
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t inc = a;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t u = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += u;
-    }
-    if (lane == 63) sums[wv] = inc;
-    __syncthreads();
-    uint32_t wbase = 0;
-    for (int q = 0; q < wv; ++q) wbase += sums[q];
-    uint32_t total = 0;
-    for (int q = 0; q < kScanT / 64; ++q) total += sums[q];
-    __syncthreads();
-    sums[threadIdx.x] = wbase + inc;
-    __syncthreads();
-    uint32_t o = base + (threadIdx.x ? sums[threadIdx.x - 1] : 0u);
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      const uint32_t e = tile[threadIdx.x * kScanPer + k];
-      tile[threadIdx.x * kScanPer + k] = o;
-      o += e;
-    }
-    base += total;
-    __syncthreads();
-    for (int k = 0; k < kScanPer; ++k) {
-      const int64_t j = t0 + (int64_t)k * kScanT + threadIdx.x;
-      if (j < T) v[j] = tile[k * kScanT + threadIdx.x];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    v[T] = base;
-    *tot = base;
-  }
+// The total of a scanned count array (v[T]) into its result word.
+__global__ void k_mrg_total(const uint32_t* __restrict__ v, int64_t T, uint32_t* __restrict__ tot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *tot = v[T];
 }
 
 // One wave per segment: its hit ids copied to their place in the output
@@ -461,10 +424,12 @@ __global__ __launch_bounds__(64) void k_mrg_refit(MergeWs w) {
   auto step = [&](float4& cs, uint32_t& js) {
     if (ok && k >= 0) {
       if (k < seg_lo) {
-        // entering the next inner segment
+        // entering the next inner segment (its frame, unless it lies in the
+        // same sector: a neighbouring slice of a time frame)
         const int32_t a = w.inner[c];
         const int wc = w.sector[c] % w.NW, wa = w.sector[a] % w.NW;
-        if (!rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m)) ok = false;
+        if (w.sector[a] != w.sector[c] && !rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m))
+          ok = false;
         c = a;
         seg_lo -= w.hit_off[c + 1] - w.hit_off[c];
       }
@@ -539,7 +504,7 @@ hipError_t run_merge(const MergeWs& w, hipStream_t st) {
   const void* need[] = {w.sector, w.x_ref, w.p, w.cov, w.chi2, w.ndf, w.hit_off, w.hit_id, w.cx, w.cy, w.cz,
                         w.crow, w.ex, w.first, w.last, w.flags, w.sec_cnt, w.sec_cur, w.sec_list, w.srec,
                         w.best_in, w.best_out, w.link, w.inner, w.emit, w.hemit, w.head, w.tpos, w.hpos, w.nseg,
-                        w.rlist, w.rec, w.err, w.o_sector, w.o_x_ref, w.o_p, w.o_cov, w.o_chi2, w.o_ndf,
+                        w.rlist, w.rec, w.err, w.scan_part, w.o_sector, w.o_x_ref, w.o_p, w.o_cov, w.o_chi2, w.o_ndf,
                         w.o_hit_off, w.o_hit_id};
   for (const void* q : need)
     if (!q) return hipErrorInvalidValue;
@@ -559,12 +524,16 @@ hipError_t run_merge(const MergeWs& w, hipStream_t st) {
   // hit offsets of the chains (they do not depend on the refit), the hits,
   // the refit (one lane per listed chain: at most T / 2 of them), then the
   // track offsets and records
-  k_mrg_scan<<<1, kScanT, 0, st>>>(w.hemit, w.T, w.err + 2);
+  hipError_t e = scan_exclusive_u32(w.hemit, w.hemit, w.T, w.scan_part, st);
+  if (e != hipSuccess) return e;
+  k_mrg_total<<<1, 64, 0, st>>>(w.hemit, w.T, w.err + 2);
   if (w.T > 0) {
     k_mrg_hits<<<gw, TB, 0, st>>>(w);
     k_mrg_refit<<<(unsigned)((w.T / 2 + 64) / 64), 64, 0, st>>>(w);
   }
-  k_mrg_scan<<<1, kScanT, 0, st>>>(w.emit, w.T, w.err + 1);
+  e = scan_exclusive_u32(w.emit, w.emit, w.T, w.scan_part, st);
+  if (e != hipSuccess) return e;
+  k_mrg_total<<<1, 64, 0, st>>>(w.emit, w.T, w.err + 1);
   k_mrg_tracks<<<g, TB, 0, st>>>(w);
   return hipGetLastError();
 }

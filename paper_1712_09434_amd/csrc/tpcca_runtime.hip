@@ -19,6 +19,7 @@
 #include "calib_internal.hpp"
 #include "internal.hpp"
 #include "merge_internal.hpp"
+#include "timeframe_internal.hpp"
 
 using namespace tpcca;
 
@@ -85,6 +86,9 @@ struct tpcca_ctx {
   // sector merger scratch
   char* mscratch = nullptr;
   size_t mscratch_bytes = 0;
+  // time-frame workspace (slices, per-slice tracks, the segment set)
+  char* tfscratch = nullptr;
+  size_t tfscratch_bytes = 0;
   // installed calibration of the tracking input (device, 66 S floats), or off
   float* cal_d = nullptr;
   bool cal_on = false;
@@ -427,6 +431,7 @@ void tpcca_destroy(tpcca_ctx* c) {
   if (c->gscratch) (void)hipFree(c->gscratch);
   if (c->cal_d) (void)hipFree(c->cal_d);
   if (c->mscratch) (void)hipFree(c->mscratch);
+  if (c->tfscratch) (void)hipFree(c->tfscratch);
   if (c->row_x_d) (void)hipFree(c->row_x_d);
   delete c;
 }
@@ -862,6 +867,82 @@ int grad_err(tpcca_ctx* c, uint32_t err) {
   return TPCCA_OK;
 }
 
+// The merger on T segments with H hits (checked by the caller) whose hit
+// ids index NC clusters (cx, cy, cz, crow); slice: the segments' time-frame
+// slices or null.  Device memory throughout.
+int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const float* cy, const float* cz,
+               const int16_t* crow, int64_t NC, const int32_t* slice, int64_t H, tpcca_tracks* out,
+               int32_t* seg_link, hipStream_t st) {
+  const int64_t T = seg->n_tracks;
+  hipError_t he;
+  // the merged output has at most as many tracks, and exactly as many hits
+  if (out->cap_tracks < T || out->cap_hits < H) {
+    out->n_tracks = T;
+    out->n_hits = H;
+    return fail(c, TPCCA_E_CAPACITY, "merged output needs n_tracks and n_hits of the segments");
+  }
+  if ((T > 0 && (!out->sector || !out->x_ref || !out->p || !out->cov || !out->chi2 || !out->ndf)) ||
+      (H > 0 && !out->hit_id))
+    return fail(c, TPCCA_E_INVALID, "null output array");
+  Layout L;
+  const size_t o_ex = L.take<float>(T * 24), o_first = L.take<float4>(T), o_last = L.take<float4>(T);
+  const size_t o_flags = L.take<uint32_t>(T), o_cnt = L.take<uint32_t>(c->S + 1), o_cur = L.take<uint32_t>(c->S);
+  const size_t o_list = L.take<uint32_t>(T), o_bi = L.take<unsigned long long>(T), o_bo = L.take<unsigned long long>(T);
+  const size_t o_link = L.take<int32_t>(T), o_inner = L.take<int32_t>(T), o_emit = L.take<uint32_t>(T + 1);
+  const size_t o_hemit = L.take<uint32_t>(T + 1), o_rec = L.take<float>(T * 24), o_err = L.take<uint32_t>(4);
+  const size_t o_srec = L.take<float4>(T), o_head = L.take<int32_t>(T), o_tpos = L.take<uint32_t>(T);
+  const size_t o_hpos = L.take<uint32_t>(T), o_nseg = L.take<uint32_t>(T), o_rlist = L.take<uint32_t>(T);
+  const size_t o_part = L.take<uint32_t>(2 * (T / 1024 + 2));
+  if (L.off > c->mscratch_bytes) {
+    if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
+    he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
+    if (he != hipSuccess) { c->mscratch = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "merger scratch allocation failed"); }
+    c->mscratch_bytes = L.off + L.off / 4;
+  }
+  char* b = c->mscratch;
+  MergeWs w{};
+  w.T = T; w.H = H; w.S = c->S; w.NW = c->S / 2; w.R = c->R; w.NC = NC;
+  w.m = make_model(c->bz, c->P);
+  w.chi2_merge = c->P.chi2_merge;
+  w.merge_dist = c->P.merge_dist;
+  const double turn = 2.0 * M_PI / (double)w.NW;
+  w.ca = (float)std::cos(turn);
+  w.sa = (float)std::sin(turn);
+  w.sector = seg->sector; w.x_ref = seg->x_ref; w.p = seg->p; w.cov = seg->cov; w.chi2 = seg->chi2;
+  w.ndf = seg->ndf; w.hit_off = seg->hit_off; w.hit_id = seg->hit_id;
+  w.cx = cx; w.cy = cy; w.cz = cz; w.crow = crow; w.slice = slice;
+  w.ex = (float*)(b + o_ex); w.first = (float4*)(b + o_first); w.last = (float4*)(b + o_last);
+  w.flags = (uint32_t*)(b + o_flags); w.sec_cnt = (uint32_t*)(b + o_cnt); w.sec_cur = (uint32_t*)(b + o_cur);
+  w.sec_list = (uint32_t*)(b + o_list);
+  w.best_in = (unsigned long long*)(b + o_bi); w.best_out = (unsigned long long*)(b + o_bo);
+  w.link = (int32_t*)(b + o_link); w.inner = (int32_t*)(b + o_inner);
+  w.emit = (uint32_t*)(b + o_emit); w.hemit = (uint32_t*)(b + o_hemit);
+  w.rec = (float*)(b + o_rec); w.err = (uint32_t*)(b + o_err);
+  w.srec = (float4*)(b + o_srec); w.head = (int32_t*)(b + o_head); w.tpos = (uint32_t*)(b + o_tpos);
+  w.hpos = (uint32_t*)(b + o_hpos); w.nseg = (uint32_t*)(b + o_nseg); w.rlist = (uint32_t*)(b + o_rlist);
+  w.scan_part = (uint32_t*)(b + o_part);
+  w.o_sector = out->sector; w.o_x_ref = out->x_ref; w.o_p = out->p; w.o_cov = out->cov; w.o_chi2 = out->chi2;
+  w.o_ndf = out->ndf; w.o_hit_off = out->hit_off; w.o_hit_id = out->hit_id; w.o_link = seg_link;
+  // an empty call still passes valid pointers to the kernels' checks
+  if (T == 0) {
+    w.sector = w.o_sector = (uint8_t*)b; w.x_ref = w.o_x_ref = (float*)b; w.p = w.o_p = (float*)b;
+    w.cov = w.o_cov = (float*)b; w.chi2 = w.o_chi2 = (float*)b; w.ndf = w.o_ndf = (int32_t*)b;
+    w.hit_id = w.o_hit_id = (uint32_t*)b;
+  }
+  if (NC == 0) { w.cx = w.cy = w.cz = (const float*)b; w.crow = (const int16_t*)b; }
+  he = run_merge(w, st);
+  if (he != hipSuccess) return hip_fail(c, he, "merger kernels");
+  uint32_t res[4] = {0, 0, 0, 0};
+  he = hipMemcpyAsync(res, w.err, sizeof(res), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(c, he, "merger");
+  if (res[0] & 1u) return fail(c, TPCCA_E_INVALID, "a segment has fewer than 3 or more than n_rows hits, or a bad sector");
+  if (res[0] & 2u) return fail(c, TPCCA_E_INVALID, "hit id out of range");
+  out->n_tracks = res[1];
+  out->n_hits = res[2];
+  return TPCCA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -972,71 +1053,150 @@ int tpcca_merge(tpcca_ctx* c, const tpcca_tracks* seg, tpcca_tracks* out, int32_
     if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
     if (ends[0] != 0 || ends[1] < 0) return fail(c, TPCCA_E_INVALID, "hit_off must start at 0");
   }
-  const int64_t H = ends[1];
-  // the merged output has at most as many tracks, and exactly as many hits
-  if (out->cap_tracks < T || out->cap_hits < H) {
-    out->n_tracks = T;
-    out->n_hits = H;
-    return fail(c, TPCCA_E_CAPACITY, "merged output needs n_tracks and n_hits of the segments");
-  }
-  if ((T > 0 && (!out->sector || !out->x_ref || !out->p || !out->cov || !out->chi2 || !out->ndf)) ||
-      (H > 0 && !out->hit_id))
-    return fail(c, TPCCA_E_INVALID, "null output array");
+  return merge_core(c, seg, k.x, k.y, k.z, k.row, NC, nullptr, ends[1], out, seg_link, st);
+}
+
+int tpcca_track_timeframe(tpcca_ctx* c, const tpcca_clusters* fr, float slice_len, int32_t n_slices,
+                          tpcca_tracks* merged, tpcca_tracks* segs, int32_t* seg_slice, int32_t* seg_link) {
+  if (!c) return TPCCA_E_INVALID;
+  if (!fr || !merged) return fail(c, TPCCA_E_INVALID, "null frame or output");
+  const int64_t n = fr->n;
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(c, TPCCA_E_INVALID, "bad cluster count");
+  if (fr->mem != TPCCA_MEM_DEVICE || merged->mem != TPCCA_MEM_DEVICE || (segs && segs->mem != TPCCA_MEM_DEVICE))
+    return fail(c, TPCCA_E_INVALID, "time-frame tracking takes device memory only");
+  if (n > 0 && (!fr->x || !fr->y || !fr->z || !fr->row || !fr->sector))
+    return fail(c, TPCCA_E_INVALID, "null cluster array");
+  if (!(slice_len > 0.0f) || !(slice_len <= 2.0f * c->z_max))
+    return fail(c, TPCCA_E_INVALID, "slice length outside (0, 2 z_max]");
+  if (n_slices < 1 || n_slices > kTfMaxSlices) return fail(c, TPCCA_E_INVALID, "n_slices outside [1, 1024]");
+  if (!merged->hit_off || merged->cap_tracks < 0 || merged->cap_hits < 0 ||
+      (segs && (!segs->hit_off || segs->cap_tracks < 0 || segs->cap_hits < 0)))
+    return fail(c, TPCCA_E_INVALID, "bad output");
+  if (check_params(&c->P) != TPCCA_OK) return fail(c, TPCCA_E_INVALID, "invalid parameters");
+  hipError_t he = hipSetDevice(c->device);
+  if (he != hipSuccess) return hip_fail(c, he, "hipSetDevice");
+  hipStream_t st = (hipStream_t)fr->stream;
+  const int E = n_slices;
+  const int64_t nb = std::max<int64_t>((n + kTfBlock - 1) / kTfBlock, 1);
+  const int64_t TC = n / std::max(c->P.min_hits, 1) + E;     // tracks of all slices, at most
+  const int64_t ncnt = (int64_t)E * nb;
   Layout L;
-  const size_t o_ex = L.take<float>(T * 24), o_first = L.take<float4>(T), o_last = L.take<float4>(T);
-  const size_t o_flags = L.take<uint32_t>(T), o_cnt = L.take<uint32_t>(c->S + 1), o_cur = L.take<uint32_t>(c->S);
-  const size_t o_list = L.take<uint32_t>(T), o_bi = L.take<unsigned long long>(T), o_bo = L.take<unsigned long long>(T);
-  const size_t o_link = L.take<int32_t>(T), o_inner = L.take<int32_t>(T), o_emit = L.take<uint32_t>(T + 1);
-  const size_t o_hemit = L.take<uint32_t>(T + 1), o_rec = L.take<float>(T * 24), o_err = L.take<uint32_t>(4);
-  const size_t o_srec = L.take<float4>(T), o_head = L.take<int32_t>(T), o_tpos = L.take<uint32_t>(T);
-  const size_t o_hpos = L.take<uint32_t>(T), o_nseg = L.take<uint32_t>(T), o_rlist = L.take<uint32_t>(T);
-  if (L.off > c->mscratch_bytes) {
-    if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
-    he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
-    if (he != hipSuccess) { c->mscratch = nullptr; (void)hipGetLastError(); return fail(c, TPCCA_E_NOMEM, "merger scratch allocation failed"); }
-    c->mscratch_bytes = L.off + L.off / 4;
+  const size_t o_cnt = L.take<uint32_t>(ncnt + 1), o_part = L.take<uint32_t>(2 * (ncnt / 1024 + 2));
+  const size_t o_err = L.take<uint32_t>(4), o_soff = L.take<uint32_t>(E + 1);
+  const size_t o_sx = L.take<float>(n), o_sy = L.take<float>(n), o_sz = L.take<float>(n);
+  const size_t o_srow = L.take<int16_t>(n), o_ssec = L.take<uint8_t>(n), o_sid = L.take<uint32_t>(n);
+  const size_t o_ztf = L.take<float>(n);
+  const size_t o_isec = L.take<uint8_t>(TC), o_ixr = L.take<float>(TC), o_ip = L.take<float>(TC * 5);
+  const size_t o_icov = L.take<float>(TC * 15), o_ichi = L.take<float>(TC), o_indf = L.take<int32_t>(TC);
+  const size_t o_ihoff = L.take<int32_t>(TC + E), o_ihid = L.take<uint32_t>(n);
+  const size_t o_osec = L.take<uint8_t>(TC), o_oxr = L.take<float>(TC), o_op = L.take<float>(TC * 5);
+  const size_t o_ocov = L.take<float>(TC * 15), o_ochi = L.take<float>(TC), o_ondf = L.take<int32_t>(TC);
+  const size_t o_ohoff = L.take<int32_t>(TC + 1), o_ohid = L.take<uint32_t>(n), o_osl = L.take<int32_t>(TC);
+  const size_t o_tab = L.take<TfRange>(E + 1);
+  if (L.off > c->tfscratch_bytes) {
+    if (c->tfscratch) { (void)hipFree(c->tfscratch); c->tfscratch = nullptr; c->tfscratch_bytes = 0; }
+    he = hipMalloc((void**)&c->tfscratch, L.off + L.off / 4);
+    if (he != hipSuccess) {
+      c->tfscratch = nullptr;
+      (void)hipGetLastError();
+      return fail(c, TPCCA_E_NOMEM, "time-frame workspace allocation failed");
+    }
+    c->tfscratch_bytes = L.off + L.off / 4;
   }
-  char* b = c->mscratch;
-  MergeWs w{};
-  w.T = T; w.H = H; w.S = c->S; w.NW = c->S / 2; w.R = c->R; w.NC = NC;
-  w.m = make_model(c->bz, c->P);
-  w.chi2_merge = c->P.chi2_merge;
-  w.merge_dist = c->P.merge_dist;
-  const double turn = 2.0 * M_PI / (double)w.NW;
-  w.ca = (float)std::cos(turn);
-  w.sa = (float)std::sin(turn);
-  w.sector = seg->sector; w.x_ref = seg->x_ref; w.p = seg->p; w.cov = seg->cov; w.chi2 = seg->chi2;
-  w.ndf = seg->ndf; w.hit_off = seg->hit_off; w.hit_id = seg->hit_id;
-  w.cx = k.x; w.cy = k.y; w.cz = k.z; w.crow = k.row;
-  w.ex = (float*)(b + o_ex); w.first = (float4*)(b + o_first); w.last = (float4*)(b + o_last);
-  w.flags = (uint32_t*)(b + o_flags); w.sec_cnt = (uint32_t*)(b + o_cnt); w.sec_cur = (uint32_t*)(b + o_cur);
-  w.sec_list = (uint32_t*)(b + o_list);
-  w.best_in = (unsigned long long*)(b + o_bi); w.best_out = (unsigned long long*)(b + o_bo);
-  w.link = (int32_t*)(b + o_link); w.inner = (int32_t*)(b + o_inner);
-  w.emit = (uint32_t*)(b + o_emit); w.hemit = (uint32_t*)(b + o_hemit);
-  w.rec = (float*)(b + o_rec); w.err = (uint32_t*)(b + o_err);
-  w.srec = (float4*)(b + o_srec); w.head = (int32_t*)(b + o_head); w.tpos = (uint32_t*)(b + o_tpos);
-  w.hpos = (uint32_t*)(b + o_hpos); w.nseg = (uint32_t*)(b + o_nseg); w.rlist = (uint32_t*)(b + o_rlist);
-  w.o_sector = out->sector; w.o_x_ref = out->x_ref; w.o_p = out->p; w.o_cov = out->cov; w.o_chi2 = out->chi2;
-  w.o_ndf = out->ndf; w.o_hit_off = out->hit_off; w.o_hit_id = out->hit_id; w.o_link = seg_link;
-  // an empty call still passes valid pointers to the kernels' checks
-  if (T == 0) {
-    w.sector = w.o_sector = (uint8_t*)b; w.x_ref = w.o_x_ref = (float*)b; w.p = w.o_p = (float*)b;
-    w.cov = w.o_cov = (float*)b; w.chi2 = w.o_chi2 = (float*)b; w.ndf = w.o_ndf = (int32_t*)b;
-    w.hit_id = w.o_hit_id = (uint32_t*)b;
+  char* b = c->tfscratch;
+  // 1. slices (counts, scan, stable scatter, offsets)
+  TfSlice a{};
+  a.n = n; a.x = fr->x; a.y = fr->y; a.tau = fr->z; a.row = fr->row; a.sector = fr->sector;
+  a.D = slice_len; a.L = c->z_max; a.n_slices = E; a.half = c->S / 2; a.S = c->S; a.nb = nb;
+  a.cnt = (uint32_t*)(b + o_cnt); a.err = (uint32_t*)(b + o_err); a.soff = (uint32_t*)(b + o_soff);
+  a.sx = (float*)(b + o_sx); a.sy = (float*)(b + o_sy); a.sz = (float*)(b + o_sz);
+  a.srow = (int16_t*)(b + o_srow); a.ssec = (uint8_t*)(b + o_ssec); a.sid = (uint32_t*)(b + o_sid);
+  a.ztf = (float*)(b + o_ztf);
+  std::vector<uint32_t> soff(E + 1, 0u);
+  uint32_t terr = 0;
+  if (n > 0) {
+    he = fill_u32(a.err, 0u, 4, st);
+    if (he == hipSuccess) he = tf_slice(a, (uint32_t*)(b + o_part), st);
+    if (he == hipSuccess) he = hipMemcpyAsync(soff.data(), a.soff, sizeof(uint32_t) * (E + 1), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(&terr, a.err, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(c, he, "time-frame slicing");
+    if (terr) return fail(c, TPCCA_E_INVALID, "a readout time is not finite or lies outside the slices");
   }
-  if (NC == 0) { w.cx = w.cy = w.cz = (const float*)b; w.crow = (const int16_t*)b; }
-  he = run_merge(w, st);
-  if (he != hipSuccess) return hip_fail(c, he, "merger kernels");
-  uint32_t res[4] = {0, 0, 0, 0};
-  he = hipMemcpyAsync(res, w.err, sizeof(res), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipStreamSynchronize(st);
-  if (he != hipSuccess) return hip_fail(c, he, "merger");
-  if (res[0] & 1u) return fail(c, TPCCA_E_INVALID, "a segment has fewer than 3 or more than n_rows hits, or a bad sector");
-  if (res[0] & 2u) return fail(c, TPCCA_E_INVALID, "hit id out of range");
-  out->n_tracks = res[1];
-  out->n_hits = res[2];
-  return TPCCA_OK;
+  // 2. every slice tracked as one event of a batch (without the installed
+  // calibration: its drift terms need the collision time)
+  std::vector<tpcca_clusters> cls(E);
+  std::vector<tpcca_tracks> trs(E);
+  std::vector<int64_t> tcap(E + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int64_t ne = (int64_t)soff[e + 1] - soff[e], co = soff[e];
+    tcap[e + 1] = tcap[e] + ne / std::max(c->P.min_hits, 1) + 1;
+    tpcca_clusters& k = cls[e];
+    k = tpcca_clusters{};
+    k.n = ne; k.x = a.sx + co; k.y = a.sy + co; k.z = a.sz + co; k.row = a.srow + co; k.sector = a.ssec + co;
+    k.mem = TPCCA_MEM_DEVICE; k.stream = fr->stream;
+    tpcca_tracks& o = trs[e];
+    o = tpcca_tracks{};
+    o.cap_tracks = tcap[e + 1] - tcap[e]; o.cap_hits = ne;
+    o.sector = (uint8_t*)(b + o_isec) + tcap[e]; o.x_ref = (float*)(b + o_ixr) + tcap[e];
+    o.p = (float*)(b + o_ip) + tcap[e] * 5; o.cov = (float*)(b + o_icov) + tcap[e] * 15;
+    o.chi2 = (float*)(b + o_ichi) + tcap[e]; o.ndf = (int32_t*)(b + o_indf) + tcap[e];
+    o.hit_off = (int32_t*)(b + o_ihoff) + tcap[e] + e; o.hit_id = (uint32_t*)(b + o_ihid) + co;
+    o.mem = TPCCA_MEM_DEVICE;
+  }
+  const bool cal = c->cal_on;
+  c->cal_on = false;
+  int rc = tpcca_track_batch(c, E, cls.data(), trs.data());
+  c->cal_on = cal;
+  if (rc != TPCCA_OK) return rc;
+  // 3. the segment set in frame coordinates
+  std::vector<TfRange> tab(E + 1);
+  int64_t T = 0, H = 0;
+  for (int e = 0; e <= E; ++e) {
+    TfRange& r = tab[e];
+    r.tcap = tcap[std::min(e, E)]; r.hoff = r.tcap + e; r.hcap = soff[e]; r.coff = soff[e];
+    r.tout = T; r.hout = H;
+    if (e < E) { T += trs[e].n_tracks; H += trs[e].n_hits; }
+  }
+  if (merged->cap_tracks < T || merged->cap_hits < H || (segs && (segs->cap_tracks < T || segs->cap_hits < H))) {
+    merged->n_tracks = T; merged->n_hits = H;
+    if (segs) { segs->n_tracks = T; segs->n_hits = H; }
+    return fail(c, TPCCA_E_CAPACITY, "outputs need the segments' track and hit counts");
+  }
+  TfGather g{};
+  g.E = E; g.half = c->S / 2; g.D = slice_len; g.T = T; g.H = H;
+  g.tab = (const TfRange*)(b + o_tab);
+  g.isec = (const uint8_t*)(b + o_isec); g.ixref = (const float*)(b + o_ixr); g.ip = (const float*)(b + o_ip);
+  g.icov = (const float*)(b + o_icov); g.ichi2 = (const float*)(b + o_ichi); g.indf = (const int32_t*)(b + o_indf);
+  g.ihoff = (const int32_t*)(b + o_ihoff); g.ihid = (const uint32_t*)(b + o_ihid); g.sid = a.sid;
+  g.osec = (uint8_t*)(b + o_osec); g.oxref = (float*)(b + o_oxr); g.op = (float*)(b + o_op);
+  g.ocov = (float*)(b + o_ocov); g.ochi2 = (float*)(b + o_ochi); g.ondf = (int32_t*)(b + o_ondf);
+  g.ohoff = (int32_t*)(b + o_ohoff); g.ohid = (uint32_t*)(b + o_ohid); g.oslice = (int32_t*)(b + o_osl);
+  he = hipMemcpyAsync(b + o_tab, tab.data(), sizeof(TfRange) * (E + 1), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = tf_gather(g, st);
+  if (he == hipSuccess && segs) {
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+      if (he == hipSuccess && bytes) he = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+    };
+    if (T > 0 && (!segs->sector || !segs->x_ref || !segs->p || !segs->cov || !segs->chi2 || !segs->ndf))
+      return fail(c, TPCCA_E_INVALID, "null segment output array");
+    if (H > 0 && !segs->hit_id) return fail(c, TPCCA_E_INVALID, "null segment hit_id");
+    cp(segs->sector, g.osec, (size_t)T); cp(segs->x_ref, g.oxref, 4 * (size_t)T);
+    cp(segs->p, g.op, 20 * (size_t)T); cp(segs->cov, g.ocov, 60 * (size_t)T);
+    cp(segs->chi2, g.ochi2, 4 * (size_t)T); cp(segs->ndf, g.ondf, 4 * (size_t)T);
+    cp(segs->hit_off, g.ohoff, 4 * (size_t)(T + 1)); cp(segs->hit_id, g.ohid, 4 * (size_t)H);
+  }
+  if (he == hipSuccess && seg_slice && T > 0)
+    he = hipMemcpyAsync(seg_slice, g.oslice, 4 * (size_t)T, hipMemcpyDeviceToDevice, st);
+  if (he != hipSuccess) return hip_fail(c, he, "time-frame segment set");
+  if (segs) { segs->n_tracks = T; segs->n_hits = H; }
+  // 4. the merger over slices and sectors, on the frame coordinates
+  tpcca_tracks view{};
+  view.n_tracks = T; view.n_hits = H;
+  view.sector = g.osec; view.x_ref = g.oxref; view.p = g.op; view.cov = g.ocov; view.chi2 = g.ochi2;
+  view.ndf = g.ondf; view.hit_off = g.ohoff; view.hit_id = g.ohid; view.mem = TPCCA_MEM_DEVICE;
+  // (the tab upload above reads host memory that lives until here: the merger synchronises the stream)
+  return merge_core(c, &view, fr->x, fr->y, a.ztf, fr->row, n, g.oslice, H, merged, seg_link, st);
 }
 
 int tpcca_refit_grad_noalloc(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {

@@ -139,9 +139,9 @@ class Tracker:
         return A.tpcca_clusters(int(x.shape[0]), _ptr(x), _ptr(y), _ptr(z), _ptr(row), _ptr(sector),
                                 _mem(x), _stream_handle(x.device))
 
-    def _alloc_out(self, n: int, device, taps: bool, k_prior: bool = True):
+    def _alloc_out(self, n: int, device, taps: bool, k_prior: bool = True, cap_tracks: int = 0):
         p = self.get_params()
-        cap_t = n // max(p.min_hits, 1) + 1
+        cap_t = cap_tracks or n // max(p.min_hits, 1) + 1
         cap_h = max(n, 1)
         f32 = dict(dtype=torch.float32, device=device)
         o = dict(sector=torch.empty(cap_t, dtype=torch.uint8, device=device),
@@ -215,6 +215,35 @@ class Tracker:
         _check(self.L, self.ctx, self.L.tpcca_merge(self.ctx, C.byref(st), C.byref(out), _ptr(lk)))
         m = self._slice(out, o, 0)
         return (m, lk[:T]) if links else m
+
+    def track_timeframe(self, x, y, tau, row, sector, slice_len: float, n_slices: int, segments: bool = False):
+        """tpcca_track_timeframe: one continuous-readout time frame (device
+        tensors; tau = readout time in cm of drift since the frame start)
+        sliced every slice_len cm into n_slices slices, tracked and merged.
+        Returns the merged Tracks in frame coordinates; with segments=True
+        also (segment Tracks, their slices, their outer merge partners)."""
+        cl = self.clusters_struct(x, y, tau, row, sector)
+        n = int(x.shape[0])
+        cap_t = n // max(self.get_params().min_hits, 1) + int(n_slices)
+        m_st, m_o = self._alloc_out(n, x.device, False, cap_tracks=cap_t)
+        m_st.k_prior = None                   # (not produced for frames)
+        m_o["k_prior"].zero_()
+        s_st = s_o = sl = lk = None
+        if segments:
+            s_st, s_o = self._alloc_out(n, x.device, False, cap_tracks=cap_t)
+            s_st.k_prior = None
+            s_o["k_prior"].zero_()
+            sl = torch.empty(cap_t, dtype=torch.int32, device=x.device)
+            lk = torch.empty(cap_t, dtype=torch.int32, device=x.device)
+        _check(self.L, self.ctx, self.L.tpcca_track_timeframe(
+            self.ctx, C.byref(cl), float(slice_len), int(n_slices), C.byref(m_st),
+            C.byref(s_st) if segments else None, _ptr(sl), _ptr(lk)))
+        merged = self._slice(m_st, m_o, n)
+        if not segments:
+            return merged
+        seg = self._slice(s_st, s_o, n)
+        T = seg.n_tracks
+        return merged, seg, sl[:T], lk[:T]
 
     def track_batch(self, events: Sequence[tuple], taps: bool = False) -> List[Tracks]:
         E = len(events)
