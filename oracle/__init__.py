@@ -46,6 +46,20 @@ class Params(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ItsGeometry(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("radius", C.c_float * 6), ("half_z", C.c_float * 6),
+                ("x_over_x0", C.c_float * 6), ("sigma_y", C.c_float * 6), ("sigma_z", C.c_float * 6),
+                ("n_staves", C.c_int32 * 6), ("bz", C.c_float)]
+
+
+class ItsParams(C.Structure):
+    _fields_ = [("vtx_sin_phi", C.c_float), ("vtx_bin", C.c_float), ("vtx_range", C.c_float),
+                ("trk_sin_phi", C.c_float), ("trk_dtgl", C.c_float), ("chi2_cut", C.c_float),
+                ("sigma_vy", C.c_float), ("sigma_vz", C.c_float), ("sin_max", C.c_float),
+                ("min_clusters", C.c_int32), ("tukey_c", C.c_float), ("fit_iters", C.c_int32),
+                ("cov_scale_in", C.c_float)]
+
+
 class Result(C.Structure):
     P64 = C.POINTER(C.c_int64)
     _fields_ = [("n", C.c_int64), ("up", P64), ("dn", P64), ("cup", P64), ("cdn", P64),
@@ -94,6 +108,12 @@ def lib():
                                 C.POINTER(C.c_int16), C.c_int64, i32p, dp, dp, dp, dp, i64p, i64p,
                                 i32p, i32p, i32p, dp, dp, i32p, dp, dp, C.POINTER(C.POINTER(Result))]
         fp = C.POINTER(C.c_float)
+        L.orc_its_default_params.argtypes = [C.POINTER(ItsParams)]
+        L.orc_its_default_params.restype = None
+        L.orc_its.argtypes = [C.POINTER(ItsGeometry), C.POINTER(ItsParams), C.c_int64, fp, fp, fp,
+                              C.POINTER(C.c_int8), C.POINTER(C.c_int16), i64p, i64p, fp] + \
+            [i32p, i32p, i32p, i32p, i32p, fp, i32p, i32p, fp, fp, fp, i32p, i32p, fp, fp, dp, i32p]
+        L.orc_its_ms.argtypes = [C.POINTER(ItsGeometry), C.c_int, fp, fp]
         L.orc_calib_apply32.argtypes = [C.POINTER(Geometry), C.c_int64, C.POINTER(C.c_uint8), fp, fp, fp,
                                         fp, fp, fp]
         L.orc_calib_chi2.argtypes = [C.POINTER(Geometry), C.POINTER(Params), C.c_int64, dp, dp, dp,
@@ -340,6 +360,69 @@ def timeframe(tf, slice_len, n_slices, params=None):
     frame = _Clusters(geom, tf.x.astype(np.float64), tf.y.astype(np.float64), ztf, tf.row, tf.sector)
     merged = merge(frame, seg, params=P, slices=slices)
     return dict(seg=seg, slice=slices, merged=merged, z_tf=ztf)
+
+
+def make_its_geometry(g):
+    G = ItsGeometry()
+    G.n_layers = g.n_layers
+    for i in range(g.n_layers):
+        G.radius[i] = float(g.radius[i]); G.half_z[i] = float(g.half_z[i])
+        G.x_over_x0[i] = float(g.x_over_x0[i]); G.sigma_y[i] = float(g.sigma_y[i])
+        G.sigma_z[i] = float(g.sigma_z[i]); G.n_staves[i] = int(g.n_staves[i])
+    G.bz = float(g.bz)
+    return G
+
+
+def its_default_params() -> ItsParams:
+    P = ItsParams()
+    lib().orc_its_default_params(C.byref(P))
+    return P
+
+
+def its(ev, params=None):
+    """ITS standalone tracking of one event (reading R-26): the SPD vertexer,
+    tracklets, Kalman following and inward fit (FP32), the bi-square vertex
+    fit (FP64).  Returns a dict of numpy arrays (per tracklet: tl0, tl1, ok,
+    cls[6], ncls, chi2, outward layer/stave/x/p/cov, inward ok/stave/p/cov)
+    and the vertexer and fit results."""
+    G = make_its_geometry(ev.geom)
+    P = params or its_default_params()
+    n = ev.n
+    x = np.ascontiguousarray(ev.x, np.float32); y = np.ascontiguousarray(ev.y, np.float32)
+    z = np.ascontiguousarray(ev.z, np.float32)
+    lay = np.ascontiguousarray(ev.layer, np.int8); stv = np.ascontiguousarray(ev.stave, np.int16)
+    nb = int(round(2.0 * P.vtx_range / P.vtx_bin))
+    cap = max(int((ev.layer == 0).sum()), 1)
+    hist = np.zeros(nb, np.int64); meta = np.zeros(7, np.int64); vz = np.zeros(1, np.float32)
+    i32 = lambda k=1: np.zeros(cap * k, np.int32)
+    f32 = lambda k=1: np.zeros(cap * k, np.float32)
+    o = dict(tl0=i32(), tl1=i32(), ok=i32(), cls=i32(6), ncls=i32(), chi2=f32(), olayer=i32(), ostave=i32(),
+             ox=f32(), op=f32(5), oc=f32(15), iok=i32(), istave=i32(), ip=f32(5), ic=f32(15))
+    vfit = np.zeros(4); vn = np.zeros(1, np.int32)
+    fp = lambda a: _ptr(a, C.c_float)
+    ip = lambda a: _ptr(a, C.c_int32)
+    lib().orc_its(C.byref(G), C.byref(P), n, fp(x), fp(y), fp(z), _ptr(lay, C.c_int8), _ptr(stv, C.c_int16),
+                  _ptr(hist, C.c_int64), _ptr(meta, C.c_int64), fp(vz), ip(o["tl0"]), ip(o["tl1"]), ip(o["ok"]),
+                  ip(o["cls"]), ip(o["ncls"]), fp(o["chi2"]), ip(o["olayer"]), ip(o["ostave"]), fp(o["ox"]),
+                  fp(o["op"]), fp(o["oc"]), ip(o["iok"]), ip(o["istave"]), fp(o["ip"]), fp(o["ic"]),
+                  _ptr(vfit, C.c_double), ip(vn))
+    T = int(meta[4])
+    res = {k: v[:T * (len(v) // cap)] for k, v in o.items()}
+    res["cls"] = res["cls"].reshape(T, 6)
+    for k, w in (("op", 5), ("oc", 15), ("ip", 5), ("ic", 15)):
+        res[k] = res[k].reshape(T, w)
+    res.update(hist=hist, n_pairs=int(meta[0]), peak=int(meta[1]), vz_n=int(meta[2]), vz_qsum=int(meta[3]),
+               vz=float(vz[0]), vz_ok=bool(meta[5]), vfit_ok=bool(meta[6]), vertex=vfit[:3].copy(),
+               vfit_sumw=float(vfit[3]), vfit_n=int(vn[0]))
+    return res
+
+
+def its_ms(geom, layer, p, cov):
+    """The multiple-scattering covariance increment of one layer (FP32)."""
+    G = make_its_geometry(geom)
+    p = np.ascontiguousarray(p, np.float32); c = np.ascontiguousarray(cov, np.float32).copy()
+    lib().orc_its_ms(C.byref(G), int(layer), _ptr(p, C.c_float), _ptr(c, C.c_float))
+    return c
 
 
 def calib_apply(ev_or_geom, sector, x, y, z, theta):

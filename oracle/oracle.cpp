@@ -1113,6 +1113,370 @@ int track_objective(const orc_geometry& g, const orc_params& P, const Model<R>& 
   return 2;
 }
 
+
+// ===========================================================================
+// ITS standalone tracking (paper, Sec. "Fast ITS standalone tracking" and
+// Sec. "Luminous region estimation based on ITS tracking"; reading R-26).
+// Six layers of flat staves around the beam axis; every decision in FP32
+// with the expressions written here (the GPU library evaluates the same
+// ones), the vertex fit in FP64.
+
+struct ItsGeo {
+  int L = 0;
+  float r[6], hz[6], xx0[6], vy[6], vz[6], kms[6];
+  int ns[6];
+  std::vector<float> ca[6], sa[6];   // stave centre angle (k + 1/2) 2 pi / n
+  std::vector<float> bc[6], bs[6];   // wedge boundary angle j 2 pi / n, j = 0 .. n
+  Model<float> m;
+};
+
+ItsGeo its_geo(const orc_its_geometry& g, const orc_its_params& P) {
+  ItsGeo G;
+  G.L = g.n_layers;
+  for (int l = 0; l < G.L; ++l) {
+    G.r[l] = g.radius[l]; G.hz[l] = g.half_z[l]; G.xx0[l] = g.x_over_x0[l];
+    G.vy[l] = g.sigma_y[l] * g.sigma_y[l]; G.vz[l] = g.sigma_z[l] * g.sigma_z[l];
+    G.ns[l] = g.n_staves[l];
+    // Highland's logarithmic factor at normal incidence (a per-layer constant)
+    G.kms[l] = (float)(1.0 + 0.038 * std::log((double)g.x_over_x0[l]));
+    const double d = 2.0 * M_PI / (double)g.n_staves[l];
+    for (int k = 0; k < G.ns[l]; ++k) {
+      G.ca[l].push_back((float)std::cos((k + 0.5) * d));
+      G.sa[l].push_back((float)std::sin((k + 0.5) * d));
+    }
+    for (int j = 0; j <= G.ns[l]; ++j) {
+      G.bc[l].push_back((float)std::cos(j * d));
+      G.bs[l].push_back((float)std::sin(j * d));
+    }
+  }
+  G.m.kfac = -(float)((double)2.99792458e-3) * g.bz;
+  G.m.sin_max = P.sin_max;
+  G.m.vy = 0.0f;
+  G.m.vz = 0.0f;
+  return G;
+}
+
+// Multiple scattering in the average material of a layer (thin layer, no
+// energy loss): two independent small deflections of variance theta0^2
+// perpendicular to the direction change phi by d1 / cos(lambda) and lambda
+// by d2, hence var(sin phi) = theta0^2 cos^2 phi / cos^2 lambda, var(tan
+// lambda) = theta0^2 / cos^4 lambda, var(q/pT) = theta0^2 (q/pT)^2 tan^2
+// lambda, cov(tan lambda, q/pT) = theta0^2 (q/pT) tan lambda / cos^2 lambda.
+// theta0 by Highland's formula for beta = 1 with the path through the
+// stave, x/X0 / (cos lambda cos phi), the logarithmic factor taken at
+// normal incidence.
+void its_ms(float p[5], float C[15], float xx0, float kms) {
+  const float s = p[2], t = p[3], k = p[4];
+  const float t2 = 1.0f + t * t;
+  const float c2 = 1.0f - s * s;
+  const float path = xx0 * Sqrt(t2 / c2);
+  const float pin = (k * k) / t2;
+  const float hl = 0.0136f;
+  const float th2 = (((hl * hl) * pin) * path) * (kms * kms);
+  const float kt = k * t;
+  C[ix(2, 2)] = C[ix(2, 2)] + th2 * (c2 * t2);
+  C[ix(3, 3)] = C[ix(3, 3)] + th2 * (t2 * t2);
+  C[ix(3, 4)] = C[ix(3, 4)] + th2 * (t2 * kt);
+  C[ix(4, 4)] = C[ix(4, 4)] + th2 * (kt * kt);
+}
+
+struct ItsCl {
+  float x, y, z, X, Y, r;
+  int l, k;
+};
+
+struct ItsOut {
+  std::vector<int64_t> hist;
+  int64_t npairs = 0, qn = 0, qsum = 0;
+  int peak = -1, vz_ok = 0;
+  float vz = 0.0f;
+  std::vector<int32_t> tl0, tl1;
+  std::vector<int32_t> ok, cls, ncls, ostave, olayer, istave, iok;
+  std::vector<float> chi2, ox, op, oc, ip, ic;
+  double V[3] = {0, 0, 0};
+  double sumw = 0.0;
+  int nused = 0, vfit_ok = 0;
+};
+
+// SPD pair test (vertexer and tracklets): the two clusters lie within the
+// azimuth window seen from the beam axis (|sin dphi| <= sphi, same side).
+inline bool spd_pair(const ItsCl& a, const ItsCl& b, float sphi, float& cross) {
+  cross = a.X * b.Y - a.Y * b.X;
+  const float dot = a.X * b.X + a.Y * b.Y;
+  return dot > 0.0f && Abs(cross) <= sphi * (a.r * b.r);
+}
+
+ItsOut its_run(const orc_its_geometry& g, const orc_its_params& P, int64_t n, const float* x, const float* y,
+               const float* z, const int8_t* layer, const int16_t* stave) {
+  const ItsGeo G = its_geo(g, P);
+  ItsOut o;
+  std::vector<ItsCl> c(n);
+  std::vector<std::vector<int32_t>> lists(6 * 64);   // clusters per (layer, stave), ascending id
+  std::vector<int32_t> L0, L1;
+  for (int64_t i = 0; i < n; ++i) {
+    ItsCl& q = c[i];
+    q.x = x[i]; q.y = y[i]; q.z = z[i]; q.l = layer[i]; q.k = stave[i];
+    const float ca = G.ca[q.l][q.k], sa = G.sa[q.l][q.k];
+    q.X = q.x * ca - q.y * sa;
+    q.Y = q.x * sa + q.y * ca;
+    q.r = Sqrt(q.X * q.X + q.Y * q.Y);
+    lists[q.l * 64 + q.k].push_back((int32_t)i);
+    if (q.l == 0) L0.push_back((int32_t)i);
+    if (q.l == 1) L1.push_back((int32_t)i);
+  }
+  // 1. vertexer: z where the SPD pair lines cross the beam axis, histogram
+  // peak (ties: lower bin), then the mean over the peak bin and its two
+  // neighbours in fixed point (2^-16 cm)
+  const int nb = (int)std::lrint(2.0 * (double)P.vtx_range / (double)P.vtx_bin);
+  o.hist.assign(nb, 0);
+  auto zline = [&](const ItsCl& a, const ItsCl& b) { return a.z - a.r * ((b.z - a.z) / (b.r - a.r)); };
+  auto bin_of = [&](float zv) {
+    const float u = (zv + P.vtx_range) / P.vtx_bin;
+    if (!(u >= 0.0f) || !(u < (float)nb)) return -1;
+    return (int)std::floor(u);
+  };
+  for (int32_t i0 : L0)
+    for (int32_t i1 : L1) {
+      float cr;
+      if (!spd_pair(c[i0], c[i1], P.vtx_sin_phi, cr)) continue;
+      const int b = bin_of(zline(c[i0], c[i1]));
+      if (b < 0) continue;
+      ++o.hist[b];
+      ++o.npairs;
+    }
+  int64_t best = 0;
+  for (int b = 0; b < nb; ++b)
+    if (o.hist[b] > best) { best = o.hist[b]; o.peak = b; }
+  if (o.peak >= 0) {
+    for (int32_t i0 : L0)
+      for (int32_t i1 : L1) {
+        float cr;
+        if (!spd_pair(c[i0], c[i1], P.vtx_sin_phi, cr)) continue;
+        const float zv = zline(c[i0], c[i1]);
+        const int b = bin_of(zv);
+        if (b < 0 || b < o.peak - 1 || b > o.peak + 1) continue;
+        o.qsum += (int64_t)std::rint(zv * 65536.0f);
+        ++o.qn;
+      }
+    o.vz = (float)((double)o.qsum / (double)o.qn / 65536.0);
+    o.vz_ok = 1;
+  }
+  const float vz = o.vz;
+  // 2. tracklets: mutual best SPD pairs seen under nearly the same angles
+  // from the vertex (beam axis at the origin, z = vz)
+  const float itp2 = 1.0f / (P.trk_sin_phi * P.trk_sin_phi), itt2 = 1.0f / (P.trk_dtgl * P.trk_dtgl);
+  std::vector<std::pair<float, int32_t>> b0(n, {INFINITY, -1}), b1(n, {INFINITY, -1});
+  auto better = [](std::pair<float, int32_t>& cur, float sc, int32_t id) {
+    if (sc < cur.first || (sc == cur.first && id < cur.second)) cur = {sc, id};
+  };
+  for (int32_t i0 : L0)
+    for (int32_t i1 : L1) {
+      const ItsCl &a = c[i0], &b = c[i1];
+      float cr;
+      if (!spd_pair(a, b, P.trk_sin_phi, cr)) continue;
+      const float dt = (b.z - vz) / b.r - (a.z - vz) / a.r;
+      if (!(Abs(dt) <= P.trk_dtgl)) continue;
+      const float sp = cr / (a.r * b.r);
+      const float sc = (sp * sp) * itp2 + (dt * dt) * itt2;
+      better(b0[i0], sc, i1);
+      better(b1[i1], sc, i0);
+    }
+  for (int32_t i0 : L0) {   // (L0 in ascending id)
+    const int32_t i1 = b0[i0].second;
+    if (i1 >= 0 && b1[i1].second == i0) { o.tl0.push_back(i0); o.tl1.push_back(i1); }
+  }
+  // 3. following, one tracklet at a time
+  const int64_t T = (int64_t)o.tl0.size();
+  o.ok.assign(T, 0); o.cls.assign(T * 6, -1); o.ncls.assign(T, 0); o.ostave.assign(T, -1);
+  o.olayer.assign(T, -1); o.istave.assign(T, -1); o.iok.assign(T, 0);
+  o.chi2.assign(T, 0.0f); o.ox.assign(T, 0.0f); o.op.assign(T * 5, 0.0f); o.oc.assign(T * 15, 0.0f);
+  o.ip.assign(T * 5, 0.0f); o.ic.assign(T * 15, 0.0f);
+  const Model<float>& m = G.m;
+  for (int64_t t = 0; t < T; ++t) {
+    const ItsCl &a = c[o.tl0[t]], &b = c[o.tl1[t]];
+    // initial state at the beam axis (x = 0 in the frame of a's stave): the
+    // vertex as the measured point, direction and q/pT from the circle
+    // through the axis and the two SPD clusters
+    const float ca0 = G.ca[0][a.k], sa0 = G.sa[0][a.k];
+    const float bx = b.X * ca0 + b.Y * sa0, by = -(b.X * sa0) + b.Y * ca0;
+    const float la = Sqrt(a.x * a.x + a.y * a.y), lb = Sqrt(bx * bx + by * by);
+    const float ex = bx - a.x, ey = by - a.y, lab = Sqrt(ex * ex + ey * ey);
+    const float crs = a.x * by - a.y * bx;
+    const float kap = (2.0f * crs) / ((la * lb) * lab);
+    const float dl = (kap * la) * 0.5f;
+    const float cd = Sqrt(1.0f - dl * dl);
+    float p[5], C[15];
+    p[0] = 0.0f;
+    p[1] = vz;
+    p[2] = (a.y / la) * cd - (a.x / la) * dl;
+    p[3] = (b.z - a.z) / lab;
+    p[4] = kap / m.kfac;
+    for (int i = 0; i < 15; ++i) C[i] = 0.0f;
+    C[ix(0, 0)] = P.sigma_vy * P.sigma_vy;
+    C[ix(1, 1)] = P.sigma_vz * P.sigma_vz;
+    C[ix(2, 2)] = 1e-2f;
+    C[ix(3, 3)] = 1e-2f;
+    C[ix(4, 4)] = 1.0f;
+    float chi2 = 0.0f, xc = 0.0f;
+    int kst[6] = {-1, -1, -1, -1, -1, -1};
+    int32_t cl[6] = {-1, -1, -1, -1, -1, -1};
+    bool alive = Abs(p[2]) < m.sin_max;
+    int lc = -1, kc = -1, ncl = 0, miss = 0;
+    bool rejected = false;
+    // the tracklet's SPD clusters
+    for (int l = 0; l < 2 && alive; ++l) {
+      const ItsCl& h = l == 0 ? a : b;
+      if (l == 1) {
+        const float dca = G.ca[1][h.k] * G.ca[0][kc] + G.sa[1][h.k] * G.sa[0][kc];
+        const float dsa = G.sa[1][h.k] * G.ca[0][kc] - G.ca[1][h.k] * G.sa[0][kc];
+        if (!rotate_state(xc, p, C, dca, dsa, m)) { alive = false; break; }
+      }
+      if (!transport(p, C, xc, h.x, m)) { alive = false; break; }
+      xc = h.x;
+      kf_update(p, C, h.y, h.z, G.vy[l], G.vz[l], chi2);
+      its_ms(p, C, G.xx0[l], G.kms[l]);
+      cl[l] = l == 0 ? o.tl0[t] : o.tl1[t];
+      kst[l] = h.k;
+      lc = l; kc = h.k;
+      ++ncl;
+    }
+    for (int l = 2; l < G.L && alive; ++l) {
+      // the stave whose wedge holds the prediction on the plane at r_l
+      // parallel to the current stave
+      float pp[5], CC[15];
+      for (int i = 0; i < 5; ++i) pp[i] = p[i];
+      for (int i = 0; i < 15; ++i) CC[i] = C[i];
+      if (!transport(pp, CC, xc, G.r[l], m)) { alive = false; break; }
+      const float X = G.r[l] * G.ca[lc][kc] - pp[0] * G.sa[lc][kc];
+      const float Y = G.r[l] * G.sa[lc][kc] + pp[0] * G.ca[lc][kc];
+      const int ns = G.ns[l];
+      int k = ((2 * kc + 1) * ns) / (2 * G.ns[lc]);
+      for (int it = 0; it < 4; ++it) {
+        const bool lo = G.bc[l][k] * Y - G.bs[l][k] * X >= 0.0f;
+        const bool hi = G.bc[l][k + 1] * Y - G.bs[l][k + 1] * X < 0.0f;
+        if (lo && hi) break;
+        k = lo ? (k + 1) % ns : (k + ns - 1) % ns;
+      }
+      const float dca = G.ca[l][k] * G.ca[lc][kc] + G.sa[l][k] * G.sa[lc][kc];
+      const float dsa = G.sa[l][k] * G.ca[lc][kc] - G.ca[l][k] * G.sa[lc][kc];
+      if (!rotate_state(xc, p, C, dca, dsa, m)) { alive = false; break; }
+      if (!transport(p, C, xc, G.r[l], m)) { alive = false; break; }
+      xc = G.r[l];
+      lc = l; kc = k; kst[l] = k;
+      // closest cluster of the stave under the chi2 cut (ties: lower id)
+      const float isy = 1.0f / (C[0] + G.vy[l]), isz = 1.0f / (C[5] + G.vz[l]);
+      float bchi = P.chi2_cut;
+      int32_t bid = -1;
+      for (int32_t id : lists[l * 64 + k]) {
+        const float dy = c[id].y - p[0], dz = c[id].z - p[1];
+        const float ch = (dy * dy) * isy + (dz * dz) * isz;
+        if (ch < bchi || (ch == bchi && (bid < 0 || id < bid))) { bchi = ch; bid = id; }
+      }
+      if (bid >= 0) {
+        kf_update(p, C, c[bid].y, c[bid].z, G.vy[l], G.vz[l], chi2);
+        cl[l] = bid;
+        ++ncl;
+        miss = 0;
+      } else if (++miss >= 2) {
+        rejected = true;
+        break;
+      }
+      its_ms(p, C, G.xx0[l], G.kms[l]);
+    }
+    // layers not reached count as missing
+    const int missing_tail = G.L - 1 - lc;
+    if (lc < 1 || miss + missing_tail >= 2) rejected = true;
+    if (rejected || ncl < P.min_clusters) continue;
+    o.ok[t] = 1;
+    o.ncls[t] = ncl;
+    o.chi2[t] = chi2;
+    o.olayer[t] = lc;
+    o.ostave[t] = kc;
+    o.ox[t] = xc;
+    for (int i = 0; i < 6; ++i) o.cls[t * 6 + i] = cl[i];
+    for (int i = 0; i < 5; ++i) o.op[t * 5 + i] = p[i];
+    for (int i = 0; i < 15; ++i) o.oc[t * 15 + i] = C[i];
+    // 4. inward: from the outward state (covariance scaled up) back over
+    // the track's clusters to the beam axis, no vertex point
+    float q[5], Q[15], dummy = 0.0f;
+    for (int i = 0; i < 5; ++i) q[i] = p[i];
+    for (int i = 0; i < 15; ++i) Q[i] = C[i] * P.cov_scale_in;
+    float xq = xc;
+    bool iok = true;
+    for (int l = lc; l >= 0 && iok; --l) {
+      if (l < lc) {
+        const int kf = kst[l + 1], kt = kst[l];
+        const float dca = G.ca[l][kt] * G.ca[l + 1][kf] + G.sa[l][kt] * G.sa[l + 1][kf];
+        const float dsa = G.sa[l][kt] * G.ca[l + 1][kf] - G.ca[l][kt] * G.sa[l + 1][kf];
+        if (!rotate_state(xq, q, Q, dca, dsa, m)) { iok = false; break; }
+        if (!transport(q, Q, xq, G.r[l], m)) { iok = false; break; }
+        xq = G.r[l];
+      }
+      if (cl[l] >= 0) kf_update(q, Q, c[cl[l]].y, c[cl[l]].z, G.vy[l], G.vz[l], dummy);
+      its_ms(q, Q, G.xx0[l], G.kms[l]);
+    }
+    if (iok && transport(q, Q, xq, 0.0f, m)) {
+      o.iok[t] = 1;
+      o.istave[t] = kst[0];
+      for (int i = 0; i < 5; ++i) o.ip[t * 5 + i] = q[i];
+      for (int i = 0; i < 15; ++i) o.ic[t * 15 + i] = Q[i];
+    }
+  }
+  // 5. vertex: the point of least weighted squared distance to the tracks'
+  // straight-line extrapolations at the beam axis, Tukey bi-square weights
+  // on the normalised distance, fit_iters solves (FP64)
+  std::vector<double> PX, PY, PZ, DX, DY, DZ, S2, W;
+  for (int64_t t = 0; t < T; ++t) {
+    if (!o.ok[t] || !o.iok[t]) continue;
+    const double ca = G.ca[0][o.istave[t]], sa = G.sa[0][o.istave[t]];
+    const double yy = o.ip[t * 5 + 0], zz = o.ip[t * 5 + 1], s = o.ip[t * 5 + 2], tt = o.ip[t * 5 + 3];
+    const double cc = std::sqrt(1.0 - s * s), nn = std::sqrt(1.0 + tt * tt);
+    PX.push_back(-(yy * sa)); PY.push_back(yy * ca); PZ.push_back(zz);
+    DX.push_back((cc * ca - s * sa) / nn); DY.push_back((cc * sa + s * ca) / nn); DZ.push_back(tt / nn);
+    S2.push_back(0.5 * ((double)o.ic[t * 15 + 0] + (double)o.ic[t * 15 + 5]));
+    W.push_back(1.0);
+  }
+  const size_t nt = PX.size();
+  if (nt >= 2) {
+    bool good = true;
+    for (int it = 0; it < P.fit_iters && good; ++it) {
+      double A[6] = {0, 0, 0, 0, 0, 0}, bv[3] = {0, 0, 0};   // A: xx, xy, xz, yy, yz, zz
+      for (size_t i = 0; i < nt; ++i) {
+        const double f = W[i] / S2[i];
+        const double d[3] = {DX[i], DY[i], DZ[i]}, Pp[3] = {PX[i], PY[i], PZ[i]};
+        double M[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int cc2 = 0; cc2 < 3; ++cc2) M[r][cc2] = (r == cc2 ? 1.0 : 0.0) - d[r] * d[cc2];
+        A[0] += f * M[0][0]; A[1] += f * M[0][1]; A[2] += f * M[0][2];
+        A[3] += f * M[1][1]; A[4] += f * M[1][2]; A[5] += f * M[2][2];
+        for (int r = 0; r < 3; ++r) bv[r] += f * (M[r][0] * Pp[0] + M[r][1] * Pp[1] + M[r][2] * Pp[2]);
+      }
+      // 3x3 symmetric solve by Cramer's rule
+      const double a00 = A[0], a01 = A[1], a02 = A[2], a11 = A[3], a12 = A[4], a22 = A[5];
+      const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+      const double det = a00 * c00 + a01 * c01 + a02 * c02;
+      if (!(std::fabs(det) > 0.0)) { good = false; break; }
+      const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+      o.V[0] = (c00 * bv[0] + c01 * bv[1] + c02 * bv[2]) / det;
+      o.V[1] = (c01 * bv[0] + c11 * bv[1] + c12 * bv[2]) / det;
+      o.V[2] = (c02 * bv[0] + c12 * bv[1] + c22 * bv[2]) / det;
+      o.nused = 0;
+      o.sumw = 0.0;
+      for (size_t i = 0; i < nt; ++i) {
+        const double u[3] = {o.V[0] - PX[i], o.V[1] - PY[i], o.V[2] - PZ[i]};
+        const double pr = u[0] * DX[i] + u[1] * DY[i] + u[2] * DZ[i];
+        const double e0 = u[0] - pr * DX[i], e1 = u[1] - pr * DY[i], e2 = u[2] - pr * DZ[i];
+        const double D = std::sqrt((e0 * e0 + e1 * e1 + e2 * e2) / S2[i]) / (double)P.tukey_c;
+        W[i] = D < 1.0 ? (1.0 - D * D) * (1.0 - D * D) : 0.0;
+        if (W[i] > 0.0) ++o.nused;
+        o.sumw += W[i];
+      }
+    }
+    o.vfit_ok = good ? 1 : 0;
+  }
+  return o;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1423,6 +1787,56 @@ int orc_calib_chi2(const orc_geometry* g, const orc_params* P, int64_t n_cluster
   }
   *chi2_out = total;
   *ndf_out = ndf;
+  return 0;
+}
+
+
+void orc_its_default_params(orc_its_params* p) {
+  p->vtx_sin_phi = 0.03f;
+  p->vtx_bin = 0.1f;
+  p->vtx_range = 20.0f;
+  p->trk_sin_phi = 0.03f;
+  p->trk_dtgl = 0.025f;
+  p->chi2_cut = 12.0f;
+  p->sigma_vy = 0.005f;
+  p->sigma_vz = 0.02f;
+  p->sin_max = 0.99f;
+  p->min_clusters = 4;
+  p->tukey_c = 4.685f;
+  p->fit_iters = 8;
+  p->cov_scale_in = 100.0f;
+}
+
+int orc_its(const orc_its_geometry* g, const orc_its_params* P, int64_t n, const float* x, const float* y,
+            const float* z, const int8_t* layer, const int16_t* stave, int64_t* hist, int64_t* meta, float* vz,
+            int32_t* tl0, int32_t* tl1, int32_t* ok, int32_t* cls, int32_t* ncls, float* chi2,
+            int32_t* olayer, int32_t* ostave, float* ox, float* op, float* oc, int32_t* iok, int32_t* istave,
+            float* ip, float* ic, double* vfit, int32_t* vfit_n) {
+  ItsOut o = its_run(*g, *P, n, x, y, z, layer, stave);
+  for (size_t b = 0; b < o.hist.size(); ++b) hist[b] = o.hist[b];
+  meta[0] = o.npairs; meta[1] = o.peak; meta[2] = o.qn; meta[3] = o.qsum; meta[4] = (int64_t)o.tl0.size();
+  meta[5] = o.vz_ok; meta[6] = o.vfit_ok;
+  *vz = o.vz;
+  const size_t T = o.tl0.size();
+  for (size_t t = 0; t < T; ++t) {
+    tl0[t] = o.tl0[t]; tl1[t] = o.tl1[t]; ok[t] = o.ok[t]; ncls[t] = o.ncls[t]; chi2[t] = o.chi2[t];
+    olayer[t] = o.olayer[t]; ostave[t] = o.ostave[t]; ox[t] = o.ox[t]; iok[t] = o.iok[t]; istave[t] = o.istave[t];
+    for (int i = 0; i < 6; ++i) cls[t * 6 + i] = o.cls[t * 6 + i];
+    for (int i = 0; i < 5; ++i) { op[t * 5 + i] = o.op[t * 5 + i]; ip[t * 5 + i] = o.ip[t * 5 + i]; }
+    for (int i = 0; i < 15; ++i) { oc[t * 15 + i] = o.oc[t * 15 + i]; ic[t * 15 + i] = o.ic[t * 15 + i]; }
+  }
+  vfit[0] = o.V[0]; vfit[1] = o.V[1]; vfit[2] = o.V[2]; vfit[3] = o.sumw;
+  *vfit_n = o.nused;
+  return 0;
+}
+
+int orc_its_ms(const orc_its_geometry* g, int layer, const float p[5], float C[15]) {
+  orc_its_params P;
+  orc_its_default_params(&P);
+  const ItsGeo G = its_geo(*g, P);
+  float q[5];
+  for (int i = 0; i < 5; ++i) q[i] = p[i];
+  its_ms(q, C, G.xx0[layer], G.kms[layer]);
   return 0;
 }
 

@@ -167,6 +167,57 @@ int orc_calib_chi2(const orc_geometry* g, const orc_params* P, int64_t n_cluster
                    const double* theta, double* chi2, int64_t* ndf, double* trk_chi2,
                    double* grad);
 
+/* ---- ITS standalone tracking (paper, Sec. "Fast ITS standalone tracking"
+ * and Sec. "Luminous region estimation based on ITS tracking"; reading R-26)
+ * Six layers of flat staves around the beam axis (stave k of layer l: the
+ * plane at distance radius[l] whose normal points at (k + 1/2) 2 pi /
+ * n_staves[l]); clusters in stave-local (x, y, z).  Steps: SPD vertexer
+ * (z histogram of the lines through layer-0/layer-1 pairs, peak, fixed-point
+ * mean), tracklets (mutual best layer-0/layer-1 pairs in azimuth and dip
+ * from the vertex), Kalman following outward from the vertex as a measured
+ * point with multiple scattering per layer (closest cluster of the
+ * predicted stave under chi2_cut; at least min_clusters clusters, never two
+ * consecutive layers missing), inward Kalman fit to the beam axis, vertex
+ * fit with Tukey bi-square weights.  FP32 except the vertex fit (FP64). */
+typedef struct {
+  int32_t n_layers;          /* 6 */
+  float radius[6], half_z[6], x_over_x0[6], sigma_y[6], sigma_z[6];
+  int32_t n_staves[6];       /* at most 64 */
+  float bz;
+} orc_its_geometry;
+
+typedef struct {
+  float vtx_sin_phi;         /* SPD pair azimuth window |sin dphi| (vertexer) */
+  float vtx_bin, vtx_range;  /* z histogram bin and half range, cm */
+  float trk_sin_phi;         /* tracklet azimuth window */
+  float trk_dtgl;            /* tracklet dip window (dz/dr from the vertex) */
+  float chi2_cut;            /* track-to-cluster chi2 cut in following */
+  float sigma_vy, sigma_vz;  /* vertex measurement errors, cm */
+  float sin_max;
+  int32_t min_clusters;      /* clusters of an accepted track */
+  float tukey_c;             /* bi-square cut of the normalised distance */
+  int32_t fit_iters;         /* vertex-fit solves */
+  float cov_scale_in;        /* inward fit: outward covariance times this */
+} orc_its_params;
+
+void orc_its_default_params(orc_its_params* p);
+
+/* One event.  Outputs (caller-allocated): hist[bins], meta[7] = (SPD pairs,
+ * peak bin, pairs in the mean, their fixed-point sum, tracklets, vertex z
+ * found, vertex fit found), vz; per tracklet t (at most the layer-0
+ * clusters): tl0/tl1 (cluster ids), ok, cls[6] (id per layer or -1), ncls,
+ * chi2, outward layer/stave/x/p[5]/cov[15], inward ok/stave/p[5]/cov[15]
+ * at x = 0; vfit[4] = (x, y, z, sum of weights), vfit_n tracks with weight
+ * > 0.  Returns 0. */
+int orc_its(const orc_its_geometry* g, const orc_its_params* P, int64_t n, const float* x, const float* y,
+            const float* z, const int8_t* layer, const int16_t* stave, int64_t* hist, int64_t* meta, float* vz,
+            int32_t* tl0, int32_t* tl1, int32_t* ok, int32_t* cls, int32_t* ncls, float* chi2,
+            int32_t* olayer, int32_t* ostave, float* ox, float* op, float* oc, int32_t* iok, int32_t* istave,
+            float* ip, float* ic, double* vfit, int32_t* vfit_n);
+
+/* The multiple-scattering covariance increment of one layer (FP32). */
+int orc_its_ms(const orc_its_geometry* g, int layer, const float p[5], float C[15]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,3 +11,4 @@ from .events import (  # noqa: F401
     bspline_basis, draw_theta, CONFIGS,
 )
 from .timeframe import TimeFrame, make_timeframe, make_tf_config, TF_CONFIGS, TF_SLICE  # noqa: F401
+from .its import ItsGeometry, ItsEvent, default_its_geometry, make_its_event, make_its_config, ITS_CONFIGS  # noqa: F401
