@@ -48,6 +48,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-event batching leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the calibration-gradient leg")
     ap.add_argument("--no-timeframe", action="store_true", help="skip the time-frame leg")
+    ap.add_argument("--no-its", action="store_true", help="skip the ITS leg")
     ap.add_argument("--grad-only", action="store_true",
                     help="only run the calibration-gradient leg (for its kernel trace)")
     ap.add_argument("--timeframe-only", action="store_true",
@@ -139,6 +140,7 @@ def main():
     merge = merge_leg(trk, (x, y, z, row, sec), out, args)
     batch = None if args.no_batch else batch_leg(args, Tracker, dev)
     timeframe = None if args.no_timeframe else timeframe_leg(trk, dev)
+    its = None if args.no_its else its_leg(dev)
     grad = None if args.no_grad else grad_leg(Tracker, dev)
 
     line = {
@@ -155,6 +157,7 @@ def main():
         "merge": merge,
         "batch": batch,
         "timeframe": timeframe,
+        "its": its,
         "grad": grad,
     }
     trk.close()
@@ -530,6 +533,44 @@ def timeframe_leg(trk, dev, reps=5):
                         "sliced per drift length", "clusters": tf.n, "slices": ns, "ms_per_frame": dt * 1e3,
             "clusters_per_s": tf.n / dt, "segments": seg.n_tracks, "links": links, "slice_links": slice_links,
             "tracks": m.n_tracks}
+
+
+def its_leg(dev, n_events=20, reps=3):
+    """ITS standalone tracking (vertexer, tracklets, following, inward fit,
+    vertex fit) of 20 events per workload, one tpcca_its_track call per event
+    (inputs resident in HBM); plus the fitted vertices against the generated
+    ones over the minimum-bias-like events (the luminous-region input)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1712_09434_amd.its import ItsTracker
+    trk = ItsTracker(synth.default_its_geometry())
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    res = {}
+    for name in ("ITS-pp", "ITS-mb", "ITS-central"):
+        evs = [synth.make_its_config(name, i) for i in range(n_events)]
+        tens = [(t(e.x), t(e.y), t(e.z), t(e.layer), t(e.stave)) for e in evs]
+        outs = [trk.track(*c) for c in tens]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for c in tens:
+                trk.track(*c)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (reps * n_events)
+        ncl = sum(e.n for e in evs) / n_events
+        ntrk = sum(int(o.ok.sum()) for o in outs) / n_events
+        dv = np.array([np.array(o.vertex) - e.vertex for o, e in zip(outs, evs)])
+        res[name] = {"clusters_per_event": ncl, "tracks_per_event": ntrk, "ms_per_event": dt * 1e3,
+                     "events_per_s": 1.0 / dt,
+                     "vertex_residual_um": {"mean": [round(v, 2) for v in (dv.mean(0) * 1e4).tolist()],
+                                            "rms": [round(v, 2) for v in (dv.std(0) * 1e4).tolist()]}}
+        log(f"ITS {name}: {ncl:.0f} clusters, {ntrk:.0f} tracks per event: {dt * 1e3:.3f} ms per event "
+            f"({1.0 / dt:.0f} events/s); vertex residual rms (x, y, z) "
+            f"{res[name]['vertex_residual_um']['rms']} um")
+    trk.close()
+    return res
 
 
 def merge_leg(trk, cl, seg, args, reps=20):

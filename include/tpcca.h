@@ -391,6 +391,116 @@ int tpcca_phase_times(const tpcca_ctx* ctx, int32_t cap, const char** names, dou
 const char* tpcca_last_error(const tpcca_ctx* ctx);
 void tpcca_destroy(tpcca_ctx* ctx);
 
+/* ---- ITS standalone tracking (Sec. "Fast ITS standalone tracking" and
+ * Sec. "Luminous region estimation based on ITS tracking": a fast tracker
+ * of the six-layer inner silicon detector for calibration and for the
+ * luminous region, and a vertex fit with outlier rejection).
+ * Detector: layer l (0 .. 5, innermost first) is a polygon of n_staves[l]
+ * flat staves around the beam axis; stave k lies in the plane at distance
+ * radius[l] from the axis whose normal points at azimuth (k + 1/2) 2 pi /
+ * n_staves[l] and covers |y| <= radius tan(pi / n_staves), |z| <= half_z.
+ * Clusters are given in their stave's frame (x = radius, y across, z along
+ * the beam); the beam axis is x = y = 0.
+ * Steps of one event (all FP32, the vertex fit FP64; the integer decisions
+ * are reproducible from the written expressions):
+ *   1. SPD vertexer: every layer-0/layer-1 pair with |sin dphi| <=
+ *      vtx_sin_phi (same side) gives the z where its line crosses the axis;
+ *      histogram of vtx_bin bins over [-vtx_range, vtx_range); the vertex z
+ *      is the mean over the fullest bin (ties: lower) and its two
+ *      neighbours, summed in fixed point (2^-16 cm);
+ *   2. tracklets: layer-0/layer-1 pairs with |sin dphi| <= trk_sin_phi and
+ *      |d(dz/dr)| <= trk_dtgl seen from the vertex; a tracklet is a mutual
+ *      best pair by (sin dphi / trk_sin_phi)^2 + (d / trk_dtgl)^2 (ties:
+ *      lower cluster id), tracklets ordered by their layer-0 cluster id;
+ *   3. following: a Kalman filter from the vertex as a measured point
+ *      (sigma_vy, sigma_vz) through the tracklet's clusters, then on layers
+ *      2 .. 5 the closest cluster of the predicted stave with chi2 <=
+ *      chi2_cut; multiple scattering in each layer's average material
+ *      (x_over_x0, Highland); a track needs min_clusters clusters and never
+ *      two consecutive layers without one;
+ *   4. inward fit: from the outward state (covariance times cov_scale_in)
+ *      over the track's clusters to the beam axis (x = 0);
+ *   5. vertex: the point of least weighted squared distance to the tracks'
+ *      straight-line extrapolations at the axis, Tukey bi-square weights
+ *      with cut tukey_c on the distance over its error, fit_iters solves. */
+typedef struct {
+  int32_t n_layers;                  /* 6 */
+  float radius[6], half_z[6];        /* cm */
+  float x_over_x0[6];                /* average material per layer (radiation lengths) */
+  float sigma_y[6], sigma_z[6];      /* cluster resolution, cm */
+  int32_t n_staves[6];               /* 1 .. 64 */
+  float bz;                          /* tesla */
+} tpcca_its_geometry;
+
+typedef struct {
+  float vtx_sin_phi, vtx_bin, vtx_range;   /* 0.03, 0.1 cm, 20 cm */
+  float trk_sin_phi, trk_dtgl;             /* 0.03, 0.025 */
+  float chi2_cut;                          /* 12 */
+  float sigma_vy, sigma_vz;                /* 0.005, 0.02 cm */
+  float sin_max;                           /* 0.99 */
+  int32_t min_clusters;                    /* 4 */
+  float tukey_c;                           /* 4.685 */
+  int32_t fit_iters;                       /* 8 */
+  float cov_scale_in;                      /* 100 */
+} tpcca_its_params;
+
+/* One event's clusters, device memory only; ids are positions. */
+typedef struct {
+  int64_t n;
+  const float* x;
+  const float* y;
+  const float* z;
+  const int8_t* layer;
+  const int16_t* stave;
+  void* stream;
+} tpcca_its_clusters;
+
+/* Results of one event.  Arrays (device memory, caller-owned) hold one entry
+ * per tracklet (capacity cap; at most the layer-0 clusters); the scalars
+ * are written by the call. */
+typedef struct {
+  int64_t cap;                 /* in: entries of the arrays below */
+  int64_t n_tracklets;         /* out (required capacity on TPCCA_E_CAPACITY) */
+  int32_t* tl0;                /* [cap] layer-0 cluster id */
+  int32_t* tl1;                /* [cap] layer-1 cluster id */
+  int32_t* ok;                 /* [cap] 1: accepted track */
+  int32_t* cls;                /* [cap][6] cluster id per layer or -1 */
+  int32_t* ncls;               /* [cap] */
+  float* chi2;                 /* [cap] outward chi2 */
+  int32_t* out_layer;          /* [cap] last layer of the outward fit */
+  int32_t* out_stave;          /* [cap] its stave */
+  float* out_x;                /* [cap] its plane */
+  float* out_p;                /* [cap][5] outward state (for matching with the TPC) */
+  float* out_cov;              /* [cap][15] */
+  int32_t* in_ok;              /* [cap] 1: the inward fit reached the axis */
+  int32_t* in_stave;           /* [cap] layer-0 stave of the inward state's frame */
+  float* in_p;                 /* [cap][5] state at x = 0 */
+  float* in_cov;               /* [cap][15] */
+  uint32_t* hist;              /* optional [bins] vertexer histogram (NULL = not returned) */
+  /* out: vertexer and vertex fit */
+  int64_t n_pairs;             /* SPD pairs in the histogram */
+  int32_t peak;                /* fullest bin, -1 if none */
+  int32_t vz_ok;
+  float vz;
+  int32_t vfit_ok;
+  int32_t vfit_n;              /* tracks with non-zero weight */
+  double vertex[3];
+  double vfit_sumw;
+} tpcca_its_tracks;
+
+typedef struct tpcca_its_ctx tpcca_its_ctx;
+void tpcca_its_default_params(tpcca_its_params* p);
+/* TPCCA_E_INVALID for a bad geometry (n_layers != 6, staves outside 1 ..
+ * 64, non-positive sizes, radii not increasing). */
+int tpcca_its_create(const tpcca_its_geometry* geom, tpcca_its_ctx** out);
+int tpcca_its_set_params(tpcca_its_ctx* ctx, const tpcca_its_params* p);
+/* TPCCA_E_INVALID for null arrays, non-finite coordinates or a layer /
+ * stave out of range; TPCCA_E_CAPACITY (required count in n_tracklets)
+ * when the arrays hold fewer than the tracklets. */
+int tpcca_its_track(tpcca_its_ctx* ctx, const tpcca_its_clusters* cl, tpcca_its_tracks* out);
+const char* tpcca_its_last_error(const tpcca_its_ctx* ctx);
+void tpcca_its_destroy(tpcca_its_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,9 @@ EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_g
             "tpcca_track", "tpcca_track_batch", "tpcca_refit_grad", "tpcca_debug_tracklets",
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
             "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc",
-            "tpcca_set_calib", "tpcca_merge", "tpcca_track_timeframe"]
+            "tpcca_set_calib", "tpcca_merge", "tpcca_track_timeframe", "tpcca_its_default_params",
+            "tpcca_its_create", "tpcca_its_set_params", "tpcca_its_track", "tpcca_its_last_error",
+            "tpcca_its_destroy"]
 
 
 class tpcca_geometry(C.Structure):
@@ -78,6 +80,36 @@ class tpcca_tracks(C.Structure):
                 ("use_vertex", C.c_void_p), ("mem", C.c_int32)]
 
 
+class tpcca_its_geometry(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("radius", C.c_float * 6), ("half_z", C.c_float * 6),
+                ("x_over_x0", C.c_float * 6), ("sigma_y", C.c_float * 6), ("sigma_z", C.c_float * 6),
+                ("n_staves", C.c_int32 * 6), ("bz", C.c_float)]
+
+
+class tpcca_its_params(C.Structure):
+    _fields_ = [("vtx_sin_phi", C.c_float), ("vtx_bin", C.c_float), ("vtx_range", C.c_float),
+                ("trk_sin_phi", C.c_float), ("trk_dtgl", C.c_float), ("chi2_cut", C.c_float),
+                ("sigma_vy", C.c_float), ("sigma_vz", C.c_float), ("sin_max", C.c_float),
+                ("min_clusters", C.c_int32), ("tukey_c", C.c_float), ("fit_iters", C.c_int32),
+                ("cov_scale_in", C.c_float)]
+
+
+class tpcca_its_clusters(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("layer", C.c_void_p), ("stave", C.c_void_p), ("stream", C.c_void_p)]
+
+
+ITS_TRACK_ARRAYS = ("tl0", "tl1", "ok", "cls", "ncls", "chi2", "out_layer", "out_stave", "out_x", "out_p",
+                    "out_cov", "in_ok", "in_stave", "in_p", "in_cov")
+
+
+class tpcca_its_tracks(C.Structure):
+    _fields_ = ([("cap", C.c_int64), ("n_tracklets", C.c_int64)] + [(k, C.c_void_p) for k in ITS_TRACK_ARRAYS]
+                + [("hist", C.c_void_p), ("n_pairs", C.c_int64), ("peak", C.c_int32), ("vz_ok", C.c_int32),
+                   ("vz", C.c_float), ("vfit_ok", C.c_int32), ("vfit_n", C.c_int32),
+                   ("vertex", C.c_double * 3), ("vfit_sumw", C.c_double)])
+
+
 class tpcca_calib(C.Structure):
     _fields_ = [("drift_scale", C.c_void_p), ("time_offset", C.c_void_p), ("map", C.c_void_p),
                 ("mem", C.c_int32)]
@@ -119,6 +151,15 @@ def load(path: str = LIB_PATH):
     L.tpcca_track_timeframe.argtypes = [C.c_void_p, P(tpcca_clusters), C.c_float, C.c_int32, P(tpcca_tracks),
                                         P(tpcca_tracks), C.c_void_p, C.c_void_p]
     L.tpcca_track_timeframe.restype = C.c_int
+    L.tpcca_its_default_params.argtypes = [P(tpcca_its_params)]
+    L.tpcca_its_default_params.restype = None
+    L.tpcca_its_create.argtypes = [P(tpcca_its_geometry), P(C.c_void_p)]
+    L.tpcca_its_set_params.argtypes = [C.c_void_p, P(tpcca_its_params)]
+    L.tpcca_its_track.argtypes = [C.c_void_p, P(tpcca_its_clusters), P(tpcca_its_tracks)]
+    L.tpcca_its_last_error.argtypes = [C.c_void_p]
+    L.tpcca_its_last_error.restype = C.c_char_p
+    L.tpcca_its_destroy.argtypes = [C.c_void_p]
+    L.tpcca_its_destroy.restype = None
     L.tpcca_set_calib.argtypes = [C.c_void_p, P(tpcca_calib)]
     L.tpcca_set_calib.restype = C.c_int
     L.tpcca_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_clusters), P(tpcca_tracks)]

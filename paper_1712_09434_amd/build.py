@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpcca.so")
-SOURCES = ["tpcca_kernels.hip", "tpcca_runtime.hip", "tpcca_calib.hip", "tpcca_merge.hip", "tpcca_timeframe.hip"]
+SOURCES = ["tpcca_kernels.hip", "tpcca_runtime.hip", "tpcca_calib.hip", "tpcca_merge.hip", "tpcca_timeframe.hip", "tpcca_its.hip"]
 
 # FP32 decisions must be reproducible: no contraction into FMA, correctly
 # rounded division and square root, denormals kept, no fast-math.  Packed
