@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--no-its", action="store_true", help="skip the ITS leg")
     ap.add_argument("--grad-only", action="store_true",
                     help="only run the calibration-gradient leg (for its kernel trace)")
+    ap.add_argument("--its-only", action="store_true", help="only run the ITS leg (for its kernel trace)")
     ap.add_argument("--timeframe-only", action="store_true",
                     help="only run the time-frame leg (for its kernel trace)")
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -69,6 +70,10 @@ def main():
         import torch
         from paper_1712_09434_amd import Tracker
         print(json.dumps({"grad": grad_leg(Tracker, torch.device("cuda:0"))}), flush=True)
+        return
+    if args.its_only:
+        import torch
+        print(json.dumps({"its": its_leg(torch.device("cuda:0"))}), flush=True)
         return
     if args.timeframe_only:
         import torch
@@ -169,7 +174,8 @@ KERNEL_SOURCES = ("paper_1712_09434_amd/csrc/tpcca_kernels.hip", "paper_1712_094
                   "paper_1712_09434_amd/csrc/calib_device.hpp", "paper_1712_09434_amd/csrc/tpcca_merge.hip",
                   "paper_1712_09434_amd/csrc/merge_internal.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tracking_c3_traffic.md")
-PMC_BENCH_CMD = "python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-grad"
+PMC_BENCH_CMD = ("python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-grad --no-timeframe "
+                 "--no-its")
 
 
 def kernel_source_hash() -> str:
@@ -411,6 +417,32 @@ over the batch of 6 slices).
         with open(os.path.join(ROOT, "profiles", "timeframe_tf24_kernel_trace.md"), "w") as f:
             f.write(text_t)
         print(text_t)
+    its_stats = glob.glob(os.path.join(folder, "prof_its", "**", "*kernel_stats.csv"), recursive=True)
+    if its_stats:
+        il = []
+        for r in csv.DictReader(open(its_stats[0])):
+            name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+            name = re.sub(r"^void ", "", name)
+            il.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        body_i = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in il[:20])
+        text_i = f"""# Kernel trace, ITS standalone tracking (pp-like, minimum-bias-like and central-like events)
+
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_its -o its -- python3 bench.py --its-only
+    python3 bench.py --pmc-summary <out>
+
+One tpcca_its_track call per event: 20 events of each workload, 1 + 3 calls each (the averages
+mix the three event sizes: the per-kernel times of the central-like events are about twice
+these).
+
+| Kernel | Calls | Average µs | % of GPU time |
+|---|---|---|---|
+{body_i}
+"""
+        with open(os.path.join(ROOT, "profiles", "its_kernel_trace.md"), "w") as f:
+            f.write(text_i)
+        print(text_i)
 
 
 def copy_probe(mib: int, reps: int = 5):
@@ -535,11 +567,12 @@ def timeframe_leg(trk, dev, reps=5):
             "tracks": m.n_tracks}
 
 
-def its_leg(dev, n_events=20, reps=3):
+def its_leg(dev, n_events=20, reps=5):
     """ITS standalone tracking (vertexer, tracklets, following, inward fit,
-    vertex fit) of 20 events per workload, one tpcca_its_track call per event
-    (inputs resident in HBM); plus the fitted vertices against the generated
-    ones over the minimum-bias-like events (the luminous-region input)."""
+    vertex fit) of 20 events per workload (inputs resident in HBM, outputs
+    marshalled beforehand): one tpcca_its_track_batch call on all 20, and one
+    call per event; plus the fitted vertices against the generated ones (the
+    luminous-region input)."""
     import numpy as np
     import torch
 
@@ -548,27 +581,35 @@ def its_leg(dev, n_events=20, reps=3):
     trk = ItsTracker(synth.default_its_geometry())
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     res = {}
-    for name in ("ITS-pp", "ITS-mb", "ITS-central"):
-        evs = [synth.make_its_config(name, i) for i in range(n_events)]
-        tens = [(t(e.x), t(e.y), t(e.z), t(e.layer), t(e.stave)) for e in evs]
-        outs = [trk.track(*c) for c in tens]
+
+    def timed(fns):
+        for f in fns:
+            f(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            for c in tens:
-                trk.track(*c)
+            for f in fns:
+                f(False)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / (reps * n_events)
+        return (time.perf_counter() - t0) / (reps * n_events)
+
+    for name in ("ITS-pp", "ITS-mb", "ITS-central"):
+        evs = [synth.make_its_config(name, i) for i in range(n_events)]
+        tens = [(t(e.x), t(e.y), t(e.z), t(e.layer), t(e.stave)) for e in evs]
+        batch = trk.prepare_batch(tens)
+        outs = batch()
+        dt_b = timed([batch])
+        dt_s = timed([trk.prepare_batch([c]) for c in tens])
         ncl = sum(e.n for e in evs) / n_events
         ntrk = sum(int(o.ok.sum()) for o in outs) / n_events
         dv = np.array([np.array(o.vertex) - e.vertex for o, e in zip(outs, evs)])
-        res[name] = {"clusters_per_event": ncl, "tracks_per_event": ntrk, "ms_per_event": dt * 1e3,
-                     "events_per_s": 1.0 / dt,
+        res[name] = {"clusters_per_event": ncl, "tracks_per_event": ntrk, "ms_per_event": dt_b * 1e3,
+                     "events_per_s": 1.0 / dt_b, "ms_per_event_single_calls": dt_s * 1e3,
                      "vertex_residual_um": {"mean": [round(v, 2) for v in (dv.mean(0) * 1e4).tolist()],
                                             "rms": [round(v, 2) for v in (dv.std(0) * 1e4).tolist()]}}
-        log(f"ITS {name}: {ncl:.0f} clusters, {ntrk:.0f} tracks per event: {dt * 1e3:.3f} ms per event "
-            f"({1.0 / dt:.0f} events/s); vertex residual rms (x, y, z) "
-            f"{res[name]['vertex_residual_um']['rms']} um")
+        log(f"ITS {name}: {ncl:.0f} clusters, {ntrk:.0f} tracks per event: {dt_b * 1e3:.3f} ms per event in "
+            f"batches of {n_events} ({1.0 / dt_b:.0f} events/s), {dt_s * 1e3:.3f} ms in single calls; vertex "
+            f"residual rms (x, y, z) {res[name]['vertex_residual_um']['rms']} um")
     trk.close()
     return res
 

@@ -498,6 +498,16 @@ int tpcca_its_set_params(tpcca_its_ctx* ctx, const tpcca_its_params* p);
  * stave out of range; TPCCA_E_CAPACITY (required count in n_tracklets)
  * when the arrays hold fewer than the tracklets. */
 int tpcca_its_track(tpcca_its_ctx* ctx, const tpcca_its_clusters* cl, tpcca_its_tracks* out);
+/* n_events events in one pass over the chip (ITS events are small; the
+ * paper's data-parallel processing of many events at once): events[e] and
+ * outs[e] as in tpcca_its_track, ids local to each event, every event's
+ * results equal to those of tpcca_its_track on that event alone.  All
+ * events name the same stream (TPCCA_E_INVALID otherwise); the call returns
+ * after the stream has finished the work.  Fewer than 2^31 clusters in all.
+ * On TPCCA_E_CAPACITY every event's n_tracklets holds its required count;
+ * on any error no event's results are valid. */
+int tpcca_its_track_batch(tpcca_its_ctx* ctx, int32_t n_events, const tpcca_its_clusters* events,
+                          tpcca_its_tracks* outs);
 const char* tpcca_its_last_error(const tpcca_its_ctx* ctx);
 void tpcca_its_destroy(tpcca_its_ctx* ctx);
 

@@ -34,7 +34,8 @@ EXPORTED = ["tpcca_default_params", "tpcca_create", "tpcca_set_params", "tpcca_g
             "tpcca_set_tuning", "tpcca_get_tuning", "tpcca_set_phase_timing", "tpcca_phase_times",
             "tpcca_last_error", "tpcca_destroy", "tpcca_debug_fp32", "tpcca_refit_grad_noalloc",
             "tpcca_set_calib", "tpcca_merge", "tpcca_track_timeframe", "tpcca_its_default_params",
-            "tpcca_its_create", "tpcca_its_set_params", "tpcca_its_track", "tpcca_its_last_error",
+            "tpcca_its_create", "tpcca_its_set_params", "tpcca_its_track", "tpcca_its_track_batch",
+            "tpcca_its_last_error",
             "tpcca_its_destroy"]
 
 
@@ -156,6 +157,7 @@ def load(path: str = LIB_PATH):
     L.tpcca_its_create.argtypes = [P(tpcca_its_geometry), P(C.c_void_p)]
     L.tpcca_its_set_params.argtypes = [C.c_void_p, P(tpcca_its_params)]
     L.tpcca_its_track.argtypes = [C.c_void_p, P(tpcca_its_clusters), P(tpcca_its_tracks)]
+    L.tpcca_its_track_batch.argtypes = [C.c_void_p, C.c_int32, P(tpcca_its_clusters), P(tpcca_its_tracks)]
     L.tpcca_its_last_error.argtypes = [C.c_void_p]
     L.tpcca_its_last_error.restype = C.c_char_p
     L.tpcca_its_destroy.argtypes = [C.c_void_p]

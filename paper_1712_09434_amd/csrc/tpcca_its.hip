@@ -14,14 +14,20 @@
 // linear fit of the point of least distance, bi-square outlier weights.
 // The library's reading of the rules and constants is in tpcca.h.
 //
-// Kernels (one event per call; clusters are few, tens of thousands):
-// cluster preparation and per-stave counts, stave offsets, stave lists;
-// pair histogram (thread per layer-0 cluster over the three layer-1 staves
-// around its azimuth), peak, fixed-point mean; tracklet candidates (best of
-// each layer-0 cluster in registers, best of each layer-1 cluster by a
-// 64-bit atomic minimum of (score bits, id)), mutual pairs compacted in id
-// order; following and inward fit (lane per tracklet); vertex fit (one
-// workgroup, fixed-order FP64 reductions).
+// One call covers any number of events (ITS events are small: one event per
+// call would leave the chip idle and pay the launches per event).  Kernels:
+// gather of the events' clusters with their global positions and per-stave
+// counts; stave offsets; stave records (global x, y, radius, z for the pair
+// tests; local y, z, id for the cluster search) and the ordered layer-0
+// list; pair histogram per event (thread per layer-0 cluster over the three
+// layer-1 staves around its azimuth, loads eight records at a time, the
+// histogram privatised in LDS), peak, fixed-point mean; tracklet candidates
+// (best of each layer-0 cluster in registers, best of each layer-1 cluster
+// by a 64-bit atomic minimum of (score bits, id)); mutual pairs compacted in
+// id order; following and inward fit (eight lanes per tracklet sharing the
+// cluster search); vertex fit (one workgroup per event, fixed-order FP64
+// reductions).  Every event's results equal those of a call on that event
+// alone.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -46,6 +52,7 @@ constexpr int TB = 256;
 constexpr int kLayers = 6;
 constexpr int kStaves = 64;      // per layer, at most
 constexpr int kBins = 4096;      // vertexer histogram bins, at most
+constexpr int kPerEv = kLayers * kStaves;   // stave slots per event
 
 // Geometry tables in device memory (FP32 values of FP64 expressions):
 // stave centre cos/sin and wedge boundary cos/sin per layer.
@@ -54,55 +61,96 @@ struct ItsTab {
   float bc[kLayers][kStaves + 1], bs[kLayers][kStaves + 1];
 };
 
-struct ItsWs {
-  int64_t n, cap;
+struct ItsEvIn {
   const float* x;
   const float* y;
   const float* z;
   const int8_t* layer;
   const int16_t* stave;
+  int64_t off;             // first global cluster of the event
+};
+
+struct ItsWs {
+  int E;
+  int64_t n;               // clusters of all events
+  const ItsEvIn* ev;       // [E + 1] (off of entry E: n)
+  tpcca_its_tracks* out;   // [E] the callers' outputs (device copy of the structs)
   const ItsTab* tab;
-  float r[kLayers], hz[kLayers], xx0[kLayers], vy[kLayers], vz[kLayers], kms[kLayers];
+  float r[kLayers], xx0[kLayers], vy[kLayers], vz[kLayers], kms[kLayers];
   int ns[kLayers];
   Model m;
   tpcca_its_params P;
   int nbins;
-  // work
-  float* cX;                 // [n] global position and radius (FP32)
+  // clusters of all events (global order = event-major input order)
+  float* cx;
+  float* cy;
+  float* cz;
+  int8_t* cl;
+  int16_t* ck;
+  int32_t* cev;
+  float* cX;               // global position and radius (FP32)
   float* cY;
   float* cR;
-  uint32_t* scount;          // [6 * 64 + 1] clusters per stave -> offsets
-  uint32_t* scur;            // [6 * 64] fill cursors
-  uint32_t* slist;           // [n] cluster ids by stave
-  uint32_t* hist;            // [nbins]
-  unsigned long long* vsum;  // [4]: pairs, pairs in the mean, fixed-point sum, error bits
-  float* vzd;                // [2]: vertex z, found flag
-  int32_t* vpeak;            // [1]
-  unsigned long long* best0; // [n] (score bits << 32) | layer-1 id
-  unsigned long long* best1; // [n] (score bits << 32) | layer-0 id
-  uint32_t* tflag;           // [n + 1] mutual pair at a layer-0 cluster -> offsets
-  double* vw;                // [cap] vertex-fit weights
-  double* vres;              // [8]: vertex (3), sum of weights, tracks used, ok
-  // outputs
-  tpcca_its_tracks o;
+  uint32_t* err;           // [1] bit 0: a bad layer / stave or a non-finite coordinate
+  uint32_t* scnt;          // [E * kPerEv + 1] clusters per (event, layer, stave) -> offsets
+  uint32_t* scur;          // [E * kPerEv] fill cursors
+  uint32_t* slist;         // [n] cluster ids by stave
+  float4* sA;              // [n] by stave: global X, Y, radius, z (pair tests)
+  float4* sB;              // [n] by stave: local y, z, id bits (cluster search)
+  uint32_t* l0f;           // [n + 1] layer-0 indicator -> offsets
+  uint32_t* l0list;        // [n] layer-0 clusters in id order
+  uint32_t* hist;          // [E * nbins]
+  unsigned long long* vsum;   // [E * 4]: pairs, pairs in the mean, fixed-point sum
+  float* vzd;              // [E * 2]: vertex z, found flag
+  int32_t* vpeak;          // [E]
+  unsigned long long* best0;  // [n] (score bits << 32) | layer-1 id
+  unsigned long long* best1;  // [n] (score bits << 32) | layer-0 id
+  uint32_t* tflag;         // [n + 1] mutual pair at a layer-0 cluster -> offsets
+  int32_t* tl0;            // [n] global tracklet list: layer-0 id, layer-1 id, event
+  int32_t* tl1;
+  int32_t* tev;
+  uint32_t* toff;          // [E + 1] first tracklet of each event
+  double* vw;              // [n] vertex-fit weights
+  double* vres;            // [E * 8]: vertex (3), sum of weights, tracks used, ok
+  uint32_t* part;          // scan partial sums
 };
 
-__device__ __forceinline__ int sidx(int l, int k) { return l * kStaves + k; }
+__device__ __forceinline__ int sidx(int e, int l, int k) { return (e * kLayers + l) * kStaves + k; }
 
-__device__ __forceinline__ bool valid_cluster(const ItsWs& w, int64_t i) {
-  const int l = w.layer[i], k = w.stave[i];
-  return l >= 0 && l < kLayers && k >= 0 && k < w.ns[l] && isfinite(w.x[i]) && isfinite(w.y[i]) &&
-         isfinite(w.z[i]);
+// Largest e with ev[e].off <= i.
+__device__ __forceinline__ int event_of(const ItsWs& w, int64_t i) {
+  int lo = 0, hi = w.E - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.ev[mid].off <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
-__global__ __launch_bounds__(TB) void k_its_prep(ItsWs w) {
+__global__ __launch_bounds__(TB) void k_its_init(ItsWs w) {
+  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < (int64_t)w.E * kPerEv + 1) w.scnt[i] = 0u;
+  if (i < (int64_t)w.E * w.nbins) w.hist[i] = 0u;
+  if (i < (int64_t)w.E * 4) w.vsum[i] = 0ull;
+  if (i < w.n) w.best1[i] = ~0ull;
+  if (i == 0) w.err[0] = 0u;
+}
+
+__global__ __launch_bounds__(TB) void k_its_gather(ItsWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
   if (i >= w.n) return;
-  const int l = w.layer[i], k = w.stave[i];
-  const float x = w.x[i], y = w.y[i];
-  if (!valid_cluster(w, i)) {
-    atomicOr(&w.vsum[3], 1ull);
+  const int e = event_of(w, i);
+  const ItsEvIn& v = w.ev[e];
+  const int64_t j = i - v.off;
+  const int l = v.layer[j], k = v.stave[j];
+  const float x = v.x[j], y = v.y[j], z = v.z[j];
+  w.cx[i] = x; w.cy[i] = y; w.cz[i] = z; w.cl[i] = (int8_t)l; w.ck[i] = (int16_t)k; w.cev[i] = e;
+  const bool ok = l >= 0 && l < kLayers && k >= 0 && k < w.ns[l] && isfinite(x) && isfinite(y) && isfinite(z);
+  w.l0f[i] = ok && l == 0 ? 1u : 0u;
+  if (!ok) {
+    atomicOr(w.err, 1u);
     w.cX[i] = 0.0f; w.cY[i] = 0.0f; w.cR[i] = 0.0f;
+    w.cl[i] = -1;   // (skipped by the later kernels)
     return;
   }
   const float ca = w.tab->ca[l][k], sa = w.tab->sa[l][k];
@@ -111,37 +159,27 @@ __global__ __launch_bounds__(TB) void k_its_prep(ItsWs w) {
   w.cX[i] = X;
   w.cY[i] = Y;
   w.cR[i] = sqrtf(X * X + Y * Y);
-  atomicAdd(&w.scount[sidx(l, k)], 1u);
+  atomicAdd(&w.scnt[sidx(e, l, k)], 1u);
 }
 
-// stave offsets (one workgroup of 512 threads: 384 staves)
-__global__ __launch_bounds__(512) void k_its_soff(ItsWs w) {
-  __shared__ uint32_t s[kLayers * kStaves];
-  const int t = threadIdx.x;
-  if (t < kLayers * kStaves) s[t] = w.scount[t];
-  __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int j = 0; j < kLayers * kStaves; ++j) {
-      const uint32_t c = s[j];
-      s[j] = acc;
-      acc += c;
-    }
-    w.scount[kLayers * kStaves] = acc;
-  }
-  __syncthreads();
-  if (t < kLayers * kStaves) { w.scount[t] = s[t]; w.scur[t] = s[t]; }
+__global__ __launch_bounds__(TB) void k_its_cursors(ItsWs w) {
+  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < (int64_t)w.E * kPerEv) w.scur[i] = w.scnt[i];
 }
 
 __global__ __launch_bounds__(TB) void k_its_fill(ItsWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= w.n) return;
-  if (!valid_cluster(w, i)) return;
-  w.slist[atomicAdd(&w.scur[sidx(w.layer[i], w.stave[i])], 1u)] = (uint32_t)i;
+  if (i >= w.n || w.cl[i] < 0) return;
+  const int l = w.cl[i];
+  const uint32_t pos = atomicAdd(&w.scur[sidx(w.cev[i], l, w.ck[i])], 1u);
+  w.slist[pos] = (uint32_t)i;
+  w.sA[pos] = make_float4(w.cX[i], w.cY[i], w.cR[i], w.cz[i]);
+  w.sB[pos] = make_float4(w.cy[i], w.cz[i], __uint_as_float((uint32_t)i), 0.0f);
+  if (l == 0) w.l0list[w.l0f[i]] = (uint32_t)i;
 }
 
-// The layer-1 stave whose wedge holds the direction (X, Y), searched from a
-// stave of the same angular position on layer lf.
+// The stave of layer l whose wedge holds the direction (X, Y), searched
+// from the stave of the same angular position as stave kf of layer lf.
 __device__ __forceinline__ int wedge_of(const ItsWs& w, int l, int lf, int kf, float X, float Y) {
   const int ns = w.ns[l];
   int k = ((2 * kf + 1) * ns) / (2 * w.ns[lf]);
@@ -154,31 +192,55 @@ __device__ __forceinline__ int wedge_of(const ItsWs& w, int l, int lf, int kf, f
   return k;
 }
 
-// Visits every layer-1 cluster of the three staves around a layer-0
-// cluster's azimuth (every pair within a window narrower than a stave).
+// One layer-0 cluster per thread, in id order.
+struct L0 {
+  bool ok;
+  float X, Y, R, z;
+  int k, e;
+  uint32_t id;
+};
+__device__ __forceinline__ L0 l0_cluster(const ItsWs& w, int64_t t) {
+  L0 c{};
+  c.ok = t < (int64_t)w.l0f[w.n] && w.err[0] == 0u;
+  if (!c.ok) return c;
+  c.id = w.l0list[t];
+  c.X = w.cX[c.id]; c.Y = w.cY[c.id]; c.R = w.cR[c.id]; c.z = w.cz[c.id];
+  c.k = w.ck[c.id];
+  c.e = w.cev[c.id];
+  return c;
+}
+
+// Visits every layer-1 cluster record of the event's three staves around a
+// layer-0 cluster's azimuth (every pair within a window narrower than a
+// stave), the records of a chunk loaded together: f(record, list position).
+constexpr int kChunk = 8;
 template <class F>
-__device__ __forceinline__ void for_l1(const ItsWs& w, int64_t i0, F f) {
-  const int k0 = w.stave[i0];
-  const int kc = wedge_of(w, 1, 0, k0, w.cX[i0], w.cY[i0]);
+__device__ __forceinline__ void for_l1(const ItsWs& w, const L0& c, F f) {
+  const int kc = wedge_of(w, 1, 0, c.k, c.X, c.Y);
   const int ns = w.ns[1];
   for (int d = -1; d <= 1; ++d) {
     const int k = (kc + d + ns) % ns;
     if (d != 0 && (k == kc || (d == 1 && k == (kc + ns - 1) % ns))) continue;   // (fewer than 3 staves)
-    const uint32_t a = w.scount[sidx(1, k)], b = w.scount[sidx(1, k) + 1];
-    for (uint32_t j = a; j < b; ++j) f((int64_t)w.slist[j]);
+    const uint32_t a = w.scnt[sidx(c.e, 1, k)], b = w.scnt[sidx(c.e, 1, k) + 1];
+    for (uint32_t j0 = a; j0 < b; j0 += kChunk) {
+      float4 r[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) r[u] = w.sA[j0 + u < b ? j0 + u : a];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u)
+        if (j0 + u < b) f(r[u], j0 + u);
+    }
   }
 }
 
-__device__ __forceinline__ bool spd_pair(const ItsWs& w, int64_t a, int64_t b, float sphi, float& cross) {
-  const float Xa = w.cX[a], Ya = w.cY[a], Xb = w.cX[b], Yb = w.cY[b];
-  cross = Xa * Yb - Ya * Xb;
-  const float dot = Xa * Xb + Ya * Yb;
-  return dot > 0.0f && fabsf(cross) <= sphi * (w.cR[a] * w.cR[b]);
+__device__ __forceinline__ bool spd_pair(const L0& a, const float4& b, float sphi, float& cross) {
+  cross = a.X * b.y - a.Y * b.x;
+  const float dot = a.X * b.x + a.Y * b.y;
+  return dot > 0.0f && fabsf(cross) <= sphi * (a.R * b.z);
 }
 
-__device__ __forceinline__ float zline(const ItsWs& w, int64_t a, int64_t b) {
-  const float za = w.z[a], zb = w.z[b], ra = w.cR[a], rb = w.cR[b];
-  return za - ra * ((zb - za) / (rb - ra));
+__device__ __forceinline__ float zline(const L0& a, const float4& b) {
+  return a.z - a.R * ((b.w - a.z) / (b.z - a.R));
 }
 
 __device__ __forceinline__ int bin_of(const ItsWs& w, float zv) {
@@ -187,27 +249,47 @@ __device__ __forceinline__ int bin_of(const ItsWs& w, float zv) {
   return (int)floorf(u);
 }
 
+// Pair histogram.  The pairs of an event crowd into the few bins around its
+// vertex: the bins of the workgroup's first event are privatised in LDS
+// (one global atomic per non-empty bin), other events' go straight to the
+// global histogram.
 __global__ __launch_bounds__(TB) void k_its_vpairs(ItsWs w) {
-  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= w.n || w.layer[i] != 0 || w.vsum[3] != 0ull) return;
+  __shared__ uint32_t h[kBins];
+  __shared__ int e0;
+  for (int bb = threadIdx.x; bb < w.nbins; bb += TB) h[bb] = 0u;
+  const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
+  const L0 c = l0_cluster(w, t);
+  if (threadIdx.x == 0) {
+    const L0 f = l0_cluster(w, (int64_t)blockIdx.x * TB);
+    e0 = f.ok ? f.e : -1;
+  }
+  __syncthreads();
   uint32_t cnt = 0;
-  for_l1(w, i, [&](int64_t j) {
-    float cr;
-    if (!spd_pair(w, i, j, w.P.vtx_sin_phi, cr)) return;
-    const int b = bin_of(w, zline(w, i, j));
-    if (b < 0) return;
-    atomicAdd(&w.hist[b], 1u);
-    ++cnt;
-  });
-  if (cnt) atomicAdd(&w.vsum[0], (unsigned long long)cnt);
+  if (c.ok)
+    for_l1(w, c, [&](const float4& b, uint32_t) {
+      float cr;
+      if (!spd_pair(c, b, w.P.vtx_sin_phi, cr)) return;
+      const int bin = bin_of(w, zline(c, b));
+      if (bin < 0) return;
+      if (c.e == e0) atomicAdd(&h[bin], 1u);
+      else atomicAdd(&w.hist[(int64_t)c.e * w.nbins + bin], 1u);
+      ++cnt;
+    });
+  if (cnt) atomicAdd(&w.vsum[c.e * 4 + 0], (unsigned long long)cnt);
+  __syncthreads();
+  if (e0 >= 0)
+    for (int bb = threadIdx.x; bb < w.nbins; bb += TB)
+      if (h[bb]) atomicAdd(&w.hist[(int64_t)e0 * w.nbins + bb], h[bb]);
 }
 
-// fullest bin (ties: lower), one workgroup
+// fullest bin of each event (ties: lower), one workgroup per event
 __global__ __launch_bounds__(TB) void k_its_vpeak(ItsWs w) {
   __shared__ unsigned long long s[TB];
+  const int e = blockIdx.x;
+  const uint32_t* hist = w.hist + (int64_t)e * w.nbins;
   unsigned long long best = 0ull;
   for (int b = threadIdx.x; b < w.nbins; b += TB) {
-    const uint32_t c = w.hist[b];
+    const uint32_t c = hist[b];
     // key: count high, inverted bin low, so the maximum prefers the lower bin
     const unsigned long long key = c ? ((unsigned long long)c << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)b) : 0ull;
     best = key > best ? key : best;
@@ -218,70 +300,71 @@ __global__ __launch_bounds__(TB) void k_its_vpeak(ItsWs w) {
     if (threadIdx.x < d && s[threadIdx.x + d] > s[threadIdx.x]) s[threadIdx.x] = s[threadIdx.x + d];
     __syncthreads();
   }
-  if (threadIdx.x == 0) w.vpeak[0] = s[0] ? (int32_t)(0xFFFFFFFFu - (uint32_t)(s[0] & 0xFFFFFFFFull)) : -1;
+  if (threadIdx.x == 0) w.vpeak[e] = s[0] ? (int32_t)(0xFFFFFFFFu - (uint32_t)(s[0] & 0xFFFFFFFFull)) : -1;
 }
 
 __global__ __launch_bounds__(TB) void k_its_vsum(ItsWs w) {
-  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  const int pk = w.vpeak[0];
-  if (i >= w.n || w.layer[i] != 0 || pk < 0 || w.vsum[3] != 0ull) return;
+  const L0 c = l0_cluster(w, (int64_t)blockIdx.x * TB + threadIdx.x);
+  if (!c.ok) return;
+  const int pk = w.vpeak[c.e];
+  if (pk < 0) return;
   unsigned long long cnt = 0ull, q = 0ull;
-  for_l1(w, i, [&](int64_t j) {
+  for_l1(w, c, [&](const float4& b, uint32_t) {
     float cr;
-    if (!spd_pair(w, i, j, w.P.vtx_sin_phi, cr)) return;
-    const float zv = zline(w, i, j);
-    const int b = bin_of(w, zv);
-    if (b < 0 || b < pk - 1 || b > pk + 1) return;
+    if (!spd_pair(c, b, w.P.vtx_sin_phi, cr)) return;
+    const float zv = zline(c, b);
+    const int bin = bin_of(w, zv);
+    if (bin < 0 || bin < pk - 1 || bin > pk + 1) return;
     q += (unsigned long long)(long long)rintf(zv * 65536.0f);   // (two's complement sums)
     ++cnt;
   });
   if (cnt) {
-    atomicAdd(&w.vsum[1], cnt);
-    atomicAdd(&w.vsum[2], q);
+    atomicAdd(&w.vsum[c.e * 4 + 1], cnt);
+    atomicAdd(&w.vsum[c.e * 4 + 2], q);
   }
 }
 
-__global__ void k_its_vfinal(ItsWs w) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const unsigned long long n = w.vsum[1];
-  if (w.vpeak[0] >= 0 && n > 0ull) {
-    const long long q = (long long)w.vsum[2];
-    w.vzd[0] = (float)((double)q / (double)n / 65536.0);
-    w.vzd[1] = 1.0f;
+__global__ __launch_bounds__(TB) void k_its_vfinal(ItsWs w) {
+  const int e = blockIdx.x * TB + threadIdx.x;
+  if (e >= w.E) return;
+  const unsigned long long n = w.vsum[e * 4 + 1];
+  if (w.vpeak[e] >= 0 && n > 0ull) {
+    const long long q = (long long)w.vsum[e * 4 + 2];
+    w.vzd[e * 2] = (float)((double)q / (double)n / 65536.0);
+    w.vzd[e * 2 + 1] = 1.0f;
   } else {
-    w.vzd[0] = 0.0f;
-    w.vzd[1] = 0.0f;
+    w.vzd[e * 2] = 0.0f;
+    w.vzd[e * 2 + 1] = 0.0f;
   }
 }
 
 __global__ __launch_bounds__(TB) void k_its_tl(ItsWs w) {
-  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i >= w.n || w.layer[i] != 0 || w.vsum[3] != 0ull) return;
-  const float vz = w.vzd[0];
+  const L0 c = l0_cluster(w, (int64_t)blockIdx.x * TB + threadIdx.x);
+  if (!c.ok) return;
+  const float vz = w.vzd[c.e * 2];
   const float itp2 = 1.0f / (w.P.trk_sin_phi * w.P.trk_sin_phi);
   const float itt2 = 1.0f / (w.P.trk_dtgl * w.P.trk_dtgl);
-  const float ra = w.cR[i], za = w.z[i];
   unsigned long long best = ~0ull;
-  for_l1(w, i, [&](int64_t j) {
+  for_l1(w, c, [&](const float4& b, uint32_t pos) {
     float cr;
-    if (!spd_pair(w, i, j, w.P.trk_sin_phi, cr)) return;
-    const float rb = w.cR[j];
-    const float dt = (w.z[j] - vz) / rb - (za - vz) / ra;
+    if (!spd_pair(c, b, w.P.trk_sin_phi, cr)) return;
+    const float dt = (b.w - vz) / b.z - (c.z - vz) / c.R;
     if (!(fabsf(dt) <= w.P.trk_dtgl)) return;
-    const float sp = cr / (ra * rb);
+    const float sp = cr / (c.R * b.z);
     const float sc = (sp * sp) * itp2 + (dt * dt) * itt2;
     const unsigned long long hi = (unsigned long long)__float_as_uint(sc) << 32;
-    best = min(best, hi | (uint32_t)j);
-    atomicMin(&w.best1[j], hi | (uint32_t)i);
+    const uint32_t j = w.slist[pos];
+    best = min(best, hi | j);
+    atomicMin(&w.best1[j], hi | c.id);
   });
-  w.best0[i] = best;
+  w.best0[c.id] = best;
 }
 
 __global__ __launch_bounds__(TB) void k_its_tlflag(ItsWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
   if (i >= w.n) return;
   uint32_t f = 0u;
-  if (w.layer[i] == 0 && w.vsum[3] == 0ull) {
+  if (w.cl[i] == 0 && w.err[0] == 0u) {
     const unsigned long long b = w.best0[i];
     if (b != ~0ull) {
       const uint32_t j = (uint32_t)(b & 0xFFFFFFFFull);
@@ -291,13 +374,26 @@ __global__ __launch_bounds__(TB) void k_its_tlflag(ItsWs w) {
   w.tflag[i] = f;
 }
 
+// Tracklets in id order (events in order): the global list, the event's
+// first tracklet, and the callers' lists (event-local ids).
 __global__ __launch_bounds__(TB) void k_its_tlcompact(ItsWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+  if (i < w.E + 1) w.toff[i] = w.tflag[i < w.E ? w.ev[i].off : w.n];
   if (i >= w.n) return;
   const uint32_t a = w.tflag[i], b = w.tflag[i + 1];
-  if (b == a || (int64_t)a >= w.cap) return;
-  w.o.tl0[a] = (int32_t)i;
-  w.o.tl1[a] = (int32_t)(w.best0[i] & 0xFFFFFFFFull);
+  if (b == a) return;
+  const int e = w.cev[i];
+  const uint32_t j = (uint32_t)(w.best0[i] & 0xFFFFFFFFull);
+  w.tl0[a] = (int32_t)i;
+  w.tl1[a] = (int32_t)j;
+  w.tev[a] = e;
+  const int64_t off = w.ev[e].off;
+  const int64_t t = (int64_t)a - (int64_t)w.tflag[off];
+  const tpcca_its_tracks& o = w.out[e];
+  if (t < o.cap) {
+    o.tl0[t] = (int32_t)(i - off);
+    o.tl1[t] = (int32_t)((int64_t)j - off);
+  }
 }
 
 // Rotation of a state at plane x into a frame turned by the angle with
@@ -380,17 +476,38 @@ __device__ __forceinline__ void frame_turn(const ItsTab* tb, int lt, int kt, int
   dsa = tb->sa[lt][kt] * tb->ca[lf][kf] - tb->ca[lt][kt] * tb->sa[lf][kf];
 }
 
-// Following and inward fit of one tracklet (lane per tracklet).
+// Following and inward fit of one tracklet by a group of kGrp lanes: every
+// lane of the group evaluates the same state (the same expressions, so the
+// same values), the cluster search of a layer is split over the lanes and
+// its result is the group minimum of (chi2 bits, id); lane 0 writes.
+constexpr int kGrp = 8;
+
+__device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
+#pragma unroll
+  for (int d = 1; d < kGrp; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, kGrp);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kGrp);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
-  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const int64_t T = std::min<int64_t>((int64_t)w.tflag[w.n], w.cap);
-  if (t >= T) return;
+  const int64_t a = (int64_t)blockIdx.x * (64 / kGrp) + threadIdx.x / kGrp;
+  const int gl = threadIdx.x % kGrp;
+  if (a >= (int64_t)w.tflag[w.n]) return;   // (the whole group)
+  const int e = w.tev[a];
+  const int64_t t = a - (int64_t)w.toff[e];
+  const tpcca_its_tracks& o = w.out[e];
+  if (t >= o.cap) return;
+  const int64_t off = w.ev[e].off;
   const ItsTab* tb = w.tab;
-  const int64_t ia = w.o.tl0[t], ib = w.o.tl1[t];
-  const float vz = w.vzd[0];
+  const int64_t ia = w.tl0[a], ib = w.tl1[a];
+  const float vz = w.vzd[e * 2];
   Model m = w.m;
-  const float ax = w.x[ia], ay = w.y[ia], az = w.z[ia];
-  const int ka = w.stave[ia], kb = w.stave[ib];
+  const float ax = w.cx[ia], ay = w.cy[ia], az = w.cz[ia];
+  const int ka = w.ck[ia], kb = w.ck[ib];
   const float ca0 = tb->ca[0][ka], sa0 = tb->sa[0][ka];
   const float BX = w.cX[ib], BY = w.cY[ib];
   const float bx = BX * ca0 + BY * sa0, by = -(BX * sa0) + BY * ca0;
@@ -404,7 +521,7 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
   p[0] = 0.0f;
   p[1] = vz;
   p[2] = (ay / la) * cd - (ax / la) * dl;
-  p[3] = (w.z[ib] - az) / lab;
+  p[3] = (w.cz[ib] - az) / lab;
   p[4] = kap / m.kfac;
 #pragma unroll
   for (int i = 0; i < 15; ++i) C[i] = 0.0f;
@@ -427,11 +544,11 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
       frame_turn(tb, 1, kh, 0, kc, dca, dsa);
       if (!rotate_frame(xc, p, C, dca, dsa, m)) { alive = false; break; }
     }
-    const float hx = w.x[h];
+    const float hx = w.cx[h];
     if (!transport(p, C, xc, hx, m)) { alive = false; break; }
     xc = hx;
     m.vy = w.vy[l]; m.vz = w.vz[l];
-    update(p, C, w.y[h], w.z[h], m, chi2);
+    update(p, C, w.cy[h], w.cz[h], m, chi2);
     its_ms(p, C, w.xx0[l], w.kms[l]);
     cl[l] = (int32_t)h;
     kst[l] = kh;
@@ -455,18 +572,30 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
     xc = w.r[l];
     lc = l; kc = k; kst[l] = k;
     const float isy = 1.0f / (C[0] + w.vy[l]), isz = 1.0f / (C[5] + w.vz[l]);
-    float bchi = w.P.chi2_cut;
-    int32_t bid = -1;
-    const uint32_t a = w.scount[sidx(l, k)], b = w.scount[sidx(l, k) + 1];
-    for (uint32_t j = a; j < b; ++j) {
-      const int32_t id = (int32_t)w.slist[j];
-      const float dy = w.y[id] - p[0], dz = w.z[id] - p[1];
-      const float ch = (dy * dy) * isy + (dz * dz) * isz;
-      if (ch < bchi || (ch == bchi && (bid < 0 || id < bid))) { bchi = ch; bid = id; }
+    const float cut = w.P.chi2_cut;
+    unsigned long long best = ~0ull;
+    const uint32_t sa = w.scnt[sidx(e, l, k)], sb = w.scnt[sidx(e, l, k) + 1];
+    constexpr int kU = 4;
+    for (uint32_t j0 = sa + (uint32_t)gl; j0 < sb; j0 += kU * kGrp) {
+      float4 rc[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const uint32_t j = j0 + (uint32_t)(u * kGrp);
+        rc[u] = w.sB[j < sb ? j : sa];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (j0 + (uint32_t)(u * kGrp) >= sb) continue;
+        const float dy = rc[u].x - p[0], dz = rc[u].y - p[1];
+        const float ch = (dy * dy) * isy + (dz * dz) * isz;
+        if (ch <= cut) best = min(best, ((unsigned long long)__float_as_uint(ch) << 32) | __float_as_uint(rc[u].z));
+      }
     }
+    best = grp_min(best);
+    const int32_t bid = best == ~0ull ? -1 : (int32_t)(best & 0xFFFFFFFFull);
     if (bid >= 0) {
       m.vy = w.vy[l]; m.vz = w.vz[l];
-      update(p, C, w.y[bid], w.z[bid], m, chi2);
+      update(p, C, w.cy[bid], w.cz[bid], m, chi2);
       cl[l] = bid;
       ++ncl;
       miss = 0;
@@ -478,29 +607,30 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
   }
   const int missing_tail = kLayers - 1 - lc;
   if (lc < 1 || miss + missing_tail >= 2) rejected = true;
-  int32_t* cls = w.o.cls + t * 6;
+  if (gl != 0) return;   // (the group's results are identical; lane 0 writes)
+  int32_t* cls = o.cls + t * 6;
   if (rejected || ncl < w.P.min_clusters) {
-    w.o.ok[t] = 0;
-    w.o.in_ok[t] = 0;
-    w.o.ncls[t] = 0;
-    w.o.chi2[t] = 0.0f;
-    w.o.out_layer[t] = -1; w.o.out_stave[t] = -1; w.o.in_stave[t] = -1;
+    o.ok[t] = 0;
+    o.in_ok[t] = 0;
+    o.ncls[t] = 0;
+    o.chi2[t] = 0.0f;
+    o.out_layer[t] = -1; o.out_stave[t] = -1; o.in_stave[t] = -1;
 #pragma unroll
     for (int i = 0; i < 6; ++i) cls[i] = -1;
     return;
   }
-  w.o.ok[t] = 1;
-  w.o.ncls[t] = ncl;
-  w.o.chi2[t] = chi2;
-  w.o.out_layer[t] = lc;
-  w.o.out_stave[t] = kc;
-  w.o.out_x[t] = xc;
+  o.ok[t] = 1;
+  o.ncls[t] = ncl;
+  o.chi2[t] = chi2;
+  o.out_layer[t] = lc;
+  o.out_stave[t] = kc;
+  o.out_x[t] = xc;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) cls[i] = cl[i];
+  for (int i = 0; i < 6; ++i) cls[i] = cl[i] >= 0 ? (int32_t)(cl[i] - off) : -1;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) w.o.out_p[t * 5 + i] = p[i];
+  for (int i = 0; i < 5; ++i) o.out_p[t * 5 + i] = p[i];
 #pragma unroll
-  for (int i = 0; i < 15; ++i) w.o.out_cov[t * 15 + i] = C[i];
+  for (int i = 0; i < 15; ++i) o.out_cov[t * 15 + i] = C[i];
   // inward, no vertex point
   float q[5], Q[15], dummy = 0.0f;
 #pragma unroll
@@ -519,80 +649,76 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
     }
     if (cl[l] >= 0) {
       m.vy = w.vy[l]; m.vz = w.vz[l];
-      update(q, Q, w.y[cl[l]], w.z[cl[l]], m, dummy);
+      update(q, Q, w.cy[cl[l]], w.cz[cl[l]], m, dummy);
     }
     its_ms(q, Q, w.xx0[l], w.kms[l]);
   }
   if (iok && transport(q, Q, xq, 0.0f, m)) {
-    w.o.in_ok[t] = 1;
-    w.o.in_stave[t] = kst[0];
+    o.in_ok[t] = 1;
+    o.in_stave[t] = kst[0];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) w.o.in_p[t * 5 + i] = q[i];
+    for (int i = 0; i < 5; ++i) o.in_p[t * 5 + i] = q[i];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) w.o.in_cov[t * 15 + i] = Q[i];
+    for (int i = 0; i < 15; ++i) o.in_cov[t * 15 + i] = Q[i];
   } else {
-    w.o.in_ok[t] = 0;
-    w.o.in_stave[t] = -1;
+    o.in_ok[t] = 0;
+    o.in_stave[t] = -1;
   }
 }
 
-// Vertex fit: one workgroup; per solve, each thread sums its tracks (t =
-// tid, tid + TB, ...) and the partial sums are added by a fixed tree, so the
-// result does not depend on timing.
+// Vertex fit: one workgroup per event; per solve, each thread sums its
+// tracks (t = tid, tid + TB, ...) and the partial sums are added by a fixed
+// tree, so the result does not depend on timing.
 __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
-  __shared__ double s[10][TB];
+  __shared__ double s[9][TB];
   __shared__ double V[3];
   __shared__ int good;
+  const int e = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t T = std::min<int64_t>((int64_t)w.tflag[w.n], w.cap);
+  const tpcca_its_tracks& o = w.out[e];
+  const int64_t T = std::min<int64_t>((int64_t)(w.toff[e + 1] - w.toff[e]), o.cap);
+  double* vw = w.vw + w.toff[e];
   const ItsTab* tb = w.tab;
-  int64_t nt = 0;
+  int c = 0;
   for (int64_t t = tid; t < T; t += TB) {
-    const bool use = w.o.ok[t] && w.o.in_ok[t];
-    w.vw[t] = use ? 1.0 : 0.0;
+    const bool use = o.ok[t] && o.in_ok[t];
+    vw[t] = use ? 1.0 : 0.0;
+    c += use ? 1 : 0;
   }
-  // tracks entering the fit (block count)
-  {
-    int c = 0;
-    for (int64_t t = tid; t < T; t += TB) c += (w.o.ok[t] && w.o.in_ok[t]) ? 1 : 0;
-    s[0][tid] = (double)c;
-    __syncthreads();
-    for (int d = TB / 2; d > 0; d >>= 1) {
-      if (tid < d) s[0][tid] += s[0][tid + d];
-      __syncthreads();
-    }
-    nt = (int64_t)s[0][0];
+  s[0][tid] = (double)c;
+  __syncthreads();
+  for (int d = TB / 2; d > 0; d >>= 1) {
+    if (tid < d) s[0][tid] += s[0][tid + d];
     __syncthreads();
   }
-  if (tid == 0) { good = nt >= 2 ? 1 : 0; V[0] = V[1] = V[2] = 0.0; }
+  if (tid == 0) { good = s[0][0] >= 2.0 ? 1 : 0; V[0] = V[1] = V[2] = 0.0; }
   __syncthreads();
   double nused = 0.0, sumw = 0.0;
   auto line = [&](int64_t t, double Pp[3], double d[3], double& s2) {
-    const int k = w.o.in_stave[t];
+    const int k = o.in_stave[t];
     const double ca = tb->ca[0][k], sa = tb->sa[0][k];
-    const double yy = w.o.in_p[t * 5 + 0], zz = w.o.in_p[t * 5 + 1];
-    const double sn = w.o.in_p[t * 5 + 2], tt = w.o.in_p[t * 5 + 3];
+    const double yy = o.in_p[t * 5 + 0], zz = o.in_p[t * 5 + 1];
+    const double sn = o.in_p[t * 5 + 2], tt = o.in_p[t * 5 + 3];
     const double cc = sqrt(1.0 - sn * sn), nn = sqrt(1.0 + tt * tt);
     Pp[0] = -(yy * sa); Pp[1] = yy * ca; Pp[2] = zz;
     d[0] = (cc * ca - sn * sa) / nn; d[1] = (cc * sa + sn * ca) / nn; d[2] = tt / nn;
-    s2 = 0.5 * ((double)w.o.in_cov[t * 15 + 0] + (double)w.o.in_cov[t * 15 + 5]);
+    s2 = 0.5 * ((double)o.in_cov[t * 15 + 0] + (double)o.in_cov[t * 15 + 5]);
   };
   for (int it = 0; it < w.P.fit_iters && good; ++it) {
-    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // A (6) and b (3)
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // A (xx, xy, xz, yy, yz, zz) and b
     for (int64_t t = tid; t < T; t += TB) {
-      const double wt = w.vw[t];
-      if (!(w.o.ok[t] && w.o.in_ok[t])) continue;
+      if (!(o.ok[t] && o.in_ok[t])) continue;
       double Pp[3], d[3], s2;
       line(t, Pp, d, s2);
-      const double f = wt / s2;
+      const double f = vw[t] / s2;
       double M[3][3];
       for (int r = 0; r < 3; ++r)
         for (int c2 = 0; c2 < 3; ++c2) M[r][c2] = (r == c2 ? 1.0 : 0.0) - d[r] * d[c2];
-      a[0] += f * M[0][0]; a[1] += f * M[0][1]; a[2] += f * M[0][2];
-      a[3] += f * M[1][1]; a[4] += f * M[1][2]; a[5] += f * M[2][2];
-      for (int r = 0; r < 3; ++r) a[6 + r] += f * (M[r][0] * Pp[0] + M[r][1] * Pp[1] + M[r][2] * Pp[2]);
+      acc[0] += f * M[0][0]; acc[1] += f * M[0][1]; acc[2] += f * M[0][2];
+      acc[3] += f * M[1][1]; acc[4] += f * M[1][2]; acc[5] += f * M[2][2];
+      for (int r = 0; r < 3; ++r) acc[6 + r] += f * (M[r][0] * Pp[0] + M[r][1] * Pp[1] + M[r][2] * Pp[2]);
     }
-    for (int j = 0; j < 9; ++j) s[j][tid] = a[j];
+    for (int j = 0; j < 9; ++j) s[j][tid] = acc[j];
     __syncthreads();
     for (int d = TB / 2; d > 0; d >>= 1) {
       if (tid < d)
@@ -617,7 +743,7 @@ __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
     if (!good) break;
     double nu = 0.0, sw = 0.0;
     for (int64_t t = tid; t < T; t += TB) {
-      if (!(w.o.ok[t] && w.o.in_ok[t])) continue;
+      if (!(o.ok[t] && o.in_ok[t])) continue;
       double Pp[3], d[3], s2;
       line(t, Pp, d, s2);
       const double u0 = V[0] - Pp[0], u1 = V[1] - Pp[1], u2 = V[2] - Pp[2];
@@ -625,7 +751,7 @@ __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
       const double e0 = u0 - pr * d[0], e1 = u1 - pr * d[1], e2 = u2 - pr * d[2];
       const double D = sqrt((e0 * e0 + e1 * e1 + e2 * e2) / s2) / (double)w.P.tukey_c;
       const double wt = D < 1.0 ? (1.0 - D * D) * (1.0 - D * D) : 0.0;
-      w.vw[t] = wt;
+      vw[t] = wt;
       nu += wt > 0.0 ? 1.0 : 0.0;
       sw += wt;
     }
@@ -641,41 +767,41 @@ __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
     __syncthreads();
   }
   if (tid == 0) {
-    w.vres[0] = V[0]; w.vres[1] = V[1]; w.vres[2] = V[2];
-    w.vres[3] = sumw; w.vres[4] = nused; w.vres[5] = good ? 1.0 : 0.0;
+    double* r = w.vres + e * 8;
+    r[0] = V[0]; r[1] = V[1]; r[2] = V[2];
+    r[3] = sumw; r[4] = nused; r[5] = good ? 1.0 : 0.0;
   }
-}
-
-__global__ void k_its_init(ItsWs w) {
-  const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i < kLayers * kStaves + 1) w.scount[i] = 0u;
-  if (i < w.nbins) w.hist[i] = 0u;
-  if (i < 4) w.vsum[i] = 0ull;
-  if (i < w.n) w.best1[i] = ~0ull;
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>((n + TB - 1) / TB, 1); }
 
 hipError_t run_its(const ItsWs& w, hipStream_t st) {
   const unsigned g = grid_for(w.n);
-  const int64_t ninit = std::max<int64_t>(std::max<int64_t>(w.n, w.nbins), kLayers * kStaves + 1);
+  const int64_t ns = (int64_t)w.E * kPerEv;
+  const int64_t ninit = std::max<int64_t>(std::max<int64_t>(w.n, (int64_t)w.E * w.nbins), std::max<int64_t>(ns + 1, 4 * w.E));
   k_its_init<<<grid_for(ninit), TB, 0, st>>>(w);
-  k_its_prep<<<g, TB, 0, st>>>(w);
-  k_its_soff<<<1, 512, 0, st>>>(w);
-  k_its_fill<<<g, TB, 0, st>>>(w);
-  k_its_vpairs<<<g, TB, 0, st>>>(w);
-  k_its_vpeak<<<1, TB, 0, st>>>(w);
-  k_its_vsum<<<g, TB, 0, st>>>(w);
-  k_its_vfinal<<<1, 64, 0, st>>>(w);
-  k_its_tl<<<g, TB, 0, st>>>(w);
-  k_its_tlflag<<<g, TB, 0, st>>>(w);
+  k_its_gather<<<g, TB, 0, st>>>(w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan_exclusive_u32(w.tflag, w.tflag, w.n, (uint32_t*)(w.vres + 8), st);
+  e = scan_exclusive_u32(w.scnt, w.scnt, ns, w.part, st);
   if (e != hipSuccess) return e;
-  k_its_tlcompact<<<g, TB, 0, st>>>(w);
-  k_its_follow<<<(unsigned)std::max<int64_t>((w.cap + 63) / 64, 1), 64, 0, st>>>(w);
-  k_its_vfit<<<1, TB, 0, st>>>(w);
+  e = scan_exclusive_u32(w.l0f, w.l0f, w.n, w.part, st);
+  if (e != hipSuccess) return e;
+  k_its_cursors<<<grid_for(ns), TB, 0, st>>>(w);
+  k_its_fill<<<g, TB, 0, st>>>(w);
+  k_its_vpairs<<<g, TB, 0, st>>>(w);
+  k_its_vpeak<<<(unsigned)w.E, TB, 0, st>>>(w);
+  k_its_vsum<<<g, TB, 0, st>>>(w);
+  k_its_vfinal<<<grid_for(w.E), TB, 0, st>>>(w);
+  k_its_tl<<<g, TB, 0, st>>>(w);
+  k_its_tlflag<<<g, TB, 0, st>>>(w);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive_u32(w.tflag, w.tflag, w.n, w.part, st);
+  if (e != hipSuccess) return e;
+  k_its_tlcompact<<<grid_for(std::max<int64_t>(w.n, w.E + 1)), TB, 0, st>>>(w);
+  k_its_follow<<<(unsigned)std::max<int64_t>((w.n + 64 / kGrp - 1) / (64 / kGrp), 1), 64, 0, st>>>(w);
+  k_its_vfit<<<(unsigned)w.E, TB, 0, st>>>(w);
   return hipGetLastError();
 }
 
@@ -770,32 +896,42 @@ int tpcca_its_set_params(tpcca_its_ctx* c, const tpcca_its_params* p) {
   return TPCCA_OK;
 }
 
-int tpcca_its_track(tpcca_its_ctx* c, const tpcca_its_clusters* cl, tpcca_its_tracks* o) {
+int tpcca_its_track_batch(tpcca_its_ctx* c, int32_t E, const tpcca_its_clusters* ev, tpcca_its_tracks* outs) {
   if (!c) return TPCCA_E_INVALID;
-  if (!cl || !o) return its_fail(c, TPCCA_E_INVALID, "null clusters or output");
-  const int64_t n = cl->n;
-  if (n < 0 || n >= ((int64_t)1 << 31)) return its_fail(c, TPCCA_E_INVALID, "bad cluster count");
-  if (n > 0 && (!cl->x || !cl->y || !cl->z || !cl->layer || !cl->stave))
-    return its_fail(c, TPCCA_E_INVALID, "null cluster array");
-  if (o->cap < 0 || (o->cap > 0 && (!o->tl0 || !o->tl1 || !o->ok || !o->cls || !o->ncls || !o->chi2 ||
-                                    !o->out_layer || !o->out_stave || !o->out_x || !o->out_p ||
-                                    !o->out_cov || !o->in_ok || !o->in_stave || !o->in_p || !o->in_cov)))
-    return its_fail(c, TPCCA_E_INVALID, "null output array");
+  if (E < 1 || !ev || !outs) return its_fail(c, TPCCA_E_INVALID, "need events and outputs");
+  int64_t n = 0;
+  for (int e = 0; e < E; ++e) {
+    const tpcca_its_clusters& k = ev[e];
+    if (k.n < 0 || (k.n > 0 && (!k.x || !k.y || !k.z || !k.layer || !k.stave)))
+      return its_fail(c, TPCCA_E_INVALID, "event " + std::to_string(e) + ": null cluster array or bad size");
+    if (k.stream != ev[0].stream) return its_fail(c, TPCCA_E_INVALID, "all events must share one stream");
+    const tpcca_its_tracks& o = outs[e];
+    if (o.cap < 0 || (o.cap > 0 && (!o.tl0 || !o.tl1 || !o.ok || !o.cls || !o.ncls || !o.chi2 || !o.out_layer ||
+                                    !o.out_stave || !o.out_x || !o.out_p || !o.out_cov || !o.in_ok ||
+                                    !o.in_stave || !o.in_p || !o.in_cov)))
+      return its_fail(c, TPCCA_E_INVALID, "event " + std::to_string(e) + ": null output array");
+    n += k.n;
+  }
+  if (n >= ((int64_t)1 << 31)) return its_fail(c, TPCCA_E_INVALID, "more than 2^31 clusters in one call");
   hipError_t he = hipSetDevice(c->device);
   if (he != hipSuccess) return its_fail(c, TPCCA_E_DEVICE, "hipSetDevice");
-  hipStream_t st = (hipStream_t)cl->stream;
+  hipStream_t st = (hipStream_t)ev[0].stream;
   const int nbins = (int)std::lrint(2.0 * (double)c->P.vtx_range / (double)c->P.vtx_bin);
-  const int64_t cap = o->cap;
   // workspace
   size_t off = 0;
-  auto take = [&](size_t bytes) { const size_t at = off; off += (bytes + 255) & ~(size_t)255; return at; };
+  auto take = [&](size_t bytes) { const size_t at = off; off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255; return at; };
   const int64_t nn = std::max<int64_t>(n, 1);
-  const size_t oX = take(4 * nn), oY = take(4 * nn), oR = take(4 * nn);
-  const size_t ocnt = take(4 * (kLayers * kStaves + 1)), ocur = take(4 * kLayers * kStaves);
-  const size_t olist = take(4 * nn), ohist = take(4 * nbins), ovsum = take(8 * 4), ovz = take(8), opk = take(8);
-  const size_t ob0 = take(8 * nn), ob1 = take(8 * nn), oflag = take(4 * (nn + 1));
-  const size_t ovw = take(8 * std::max<int64_t>(cap, 1));
-  const size_t ovres = take(8 * 8 + 4 * (2 * (nn / 1024 + 2)) + 64);
+  const int64_t ns = (int64_t)E * kPerEv;
+  const size_t o_ev = take(sizeof(ItsEvIn) * (E + 1)), o_out = take(sizeof(tpcca_its_tracks) * E);
+  const size_t o_cx = take(4 * nn), o_cy = take(4 * nn), o_cz = take(4 * nn), o_cl = take(nn), o_ck = take(2 * nn);
+  const size_t o_cev = take(4 * nn), o_X = take(4 * nn), o_Y = take(4 * nn), o_R = take(4 * nn);
+  const size_t o_err = take(8), o_scnt = take(4 * (ns + 1)), o_scur = take(4 * ns), o_slist = take(4 * nn);
+  const size_t o_sA = take(16 * nn), o_sB = take(16 * nn), o_l0f = take(4 * (nn + 1)), o_l0l = take(4 * nn);
+  const size_t o_hist = take(4 * (int64_t)E * nbins), o_vsum = take(8 * 4 * (int64_t)E), o_vzd = take(8 * (int64_t)E);
+  const size_t o_pk = take(4 * (int64_t)E), o_b0 = take(8 * nn), o_b1 = take(8 * nn), o_tf = take(4 * (nn + 1));
+  const size_t o_tl0 = take(4 * nn), o_tl1 = take(4 * nn), o_tev = take(4 * nn), o_toff = take(4 * (E + 1));
+  const size_t o_vw = take(8 * nn), o_vres = take(8 * 8 * (int64_t)E);
+  const size_t o_part = take(4 * (2 * (std::max<int64_t>(nn, ns) / 1024 + 2)));
   if (off > c->arena_bytes) {
     if (c->arena) { (void)hipFree(c->arena); c->arena = nullptr; c->arena_bytes = 0; }
     if (hipMalloc((void**)&c->arena, off + off / 4) != hipSuccess) {
@@ -805,12 +941,30 @@ int tpcca_its_track(tpcca_its_ctx* c, const tpcca_its_clusters* cl, tpcca_its_tr
     c->arena_bytes = off + off / 4;
   }
   char* b = c->arena;
+  // per-event tables (the input pointers of an empty event still point at
+  // valid memory; they are never read)
+  std::vector<ItsEvIn> tin(E + 1);
+  std::vector<tpcca_its_tracks> tout(outs, outs + E);
+  int64_t acc = 0;
+  for (int e = 0; e < E; ++e) {
+    const tpcca_its_clusters& k = ev[e];
+    tin[e] = ItsEvIn{k.n ? k.x : (const float*)b, k.n ? k.y : (const float*)b, k.n ? k.z : (const float*)b,
+                     k.n ? k.layer : (const int8_t*)b, k.n ? k.stave : (const int16_t*)b, acc};
+    acc += k.n;
+    if (tout[e].cap == 0) {   // (valid pointers for the kernels' checks)
+      tpcca_its_tracks& o = tout[e];
+      o.tl0 = o.tl1 = o.ok = o.ncls = o.out_layer = o.out_stave = o.in_ok = o.in_stave = o.cls = (int32_t*)b;
+      o.chi2 = o.out_x = o.out_p = o.out_cov = o.in_p = o.in_cov = (float*)b;
+    }
+  }
+  tin[E] = ItsEvIn{nullptr, nullptr, nullptr, nullptr, nullptr, acc};
   ItsWs w{};
-  w.n = n; w.cap = cap;
-  w.x = cl->x; w.y = cl->y; w.z = cl->z; w.layer = cl->layer; w.stave = cl->stave;
+  w.E = E; w.n = n;
+  w.ev = (const ItsEvIn*)(b + o_ev);
+  w.out = (tpcca_its_tracks*)(b + o_out);
   w.tab = (const ItsTab*)c->tab;
   for (int l = 0; l < kLayers; ++l) {
-    w.r[l] = c->g.radius[l]; w.hz[l] = c->g.half_z[l]; w.xx0[l] = c->g.x_over_x0[l];
+    w.r[l] = c->g.radius[l]; w.xx0[l] = c->g.x_over_x0[l];
     w.vy[l] = c->g.sigma_y[l] * c->g.sigma_y[l]; w.vz[l] = c->g.sigma_z[l] * c->g.sigma_z[l];
     w.kms[l] = (float)(1.0 + 0.038 * std::log((double)c->g.x_over_x0[l]));
     w.ns[l] = c->g.n_staves[l];
@@ -820,50 +974,66 @@ int tpcca_its_track(tpcca_its_ctx* c, const tpcca_its_clusters* cl, tpcca_its_tr
   w.m.vy = 0.0f; w.m.vz = 0.0f;
   w.P = c->P;
   w.nbins = nbins;
-  w.cX = (float*)(b + oX); w.cY = (float*)(b + oY); w.cR = (float*)(b + oR);
-  w.scount = (uint32_t*)(b + ocnt); w.scur = (uint32_t*)(b + ocur); w.slist = (uint32_t*)(b + olist);
-  w.hist = (uint32_t*)(b + ohist); w.vsum = (unsigned long long*)(b + ovsum); w.vzd = (float*)(b + ovz);
-  w.vpeak = (int32_t*)(b + opk);
-  w.best0 = (unsigned long long*)(b + ob0); w.best1 = (unsigned long long*)(b + ob1);
-  w.tflag = (uint32_t*)(b + oflag); w.vw = (double*)(b + ovw); w.vres = (double*)(b + ovres);
-  w.o = *o;
-  // an empty capacity still hands the kernels valid pointers
-  if (cap == 0) {
-    w.o.tl0 = w.o.tl1 = w.o.ok = w.o.ncls = w.o.out_layer = w.o.out_stave = w.o.in_ok = w.o.in_stave = (int32_t*)b;
-    w.o.cls = (int32_t*)b;
-    w.o.chi2 = w.o.out_x = w.o.out_p = w.o.out_cov = w.o.in_p = w.o.in_cov = (float*)b;
+  w.cx = (float*)(b + o_cx); w.cy = (float*)(b + o_cy); w.cz = (float*)(b + o_cz);
+  w.cl = (int8_t*)(b + o_cl); w.ck = (int16_t*)(b + o_ck); w.cev = (int32_t*)(b + o_cev);
+  w.cX = (float*)(b + o_X); w.cY = (float*)(b + o_Y); w.cR = (float*)(b + o_R);
+  w.err = (uint32_t*)(b + o_err); w.scnt = (uint32_t*)(b + o_scnt); w.scur = (uint32_t*)(b + o_scur);
+  w.slist = (uint32_t*)(b + o_slist); w.sA = (float4*)(b + o_sA); w.sB = (float4*)(b + o_sB);
+  w.l0f = (uint32_t*)(b + o_l0f); w.l0list = (uint32_t*)(b + o_l0l);
+  w.hist = (uint32_t*)(b + o_hist); w.vsum = (unsigned long long*)(b + o_vsum); w.vzd = (float*)(b + o_vzd);
+  w.vpeak = (int32_t*)(b + o_pk);
+  w.best0 = (unsigned long long*)(b + o_b0); w.best1 = (unsigned long long*)(b + o_b1);
+  w.tflag = (uint32_t*)(b + o_tf); w.tl0 = (int32_t*)(b + o_tl0); w.tl1 = (int32_t*)(b + o_tl1);
+  w.tev = (int32_t*)(b + o_tev); w.toff = (uint32_t*)(b + o_toff);
+  w.vw = (double*)(b + o_vw); w.vres = (double*)(b + o_vres); w.part = (uint32_t*)(b + o_part);
+  he = hipMemcpyAsync(b + o_ev, tin.data(), sizeof(ItsEvIn) * (E + 1), hipMemcpyHostToDevice, st);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(b + o_out, tout.data(), sizeof(tpcca_its_tracks) * E, hipMemcpyHostToDevice, st);
+  if (he == hipSuccess) he = run_its(w, st);
+  if (he != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    return its_fail(c, TPCCA_E_DEVICE, std::string("ITS kernels: ") + hipGetErrorString(he));
   }
-  if (n == 0) {
-    w.x = w.y = w.z = (const float*)b; w.layer = (const int8_t*)b; w.stave = (const int16_t*)b;
-  }
-  he = run_its(w, st);
-  if (he != hipSuccess) return its_fail(c, TPCCA_E_DEVICE, std::string("ITS kernels: ") + hipGetErrorString(he));
-  unsigned long long vs[4] = {0, 0, 0, 0};
-  float vz[2] = {0, 0};
-  int32_t pk = -1;
-  uint32_t T = 0;
-  double vr[6] = {0, 0, 0, 0, 0, 0};
-  he = hipMemcpyAsync(vs, w.vsum, sizeof(vs), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(vz, w.vzd, sizeof(vz), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(&pk, w.vpeak, 4, hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(&T, w.tflag + n, 4, hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(vr, w.vres, sizeof(vr), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess && o->hist)
-    he = hipMemcpyAsync(o->hist, w.hist, 4 * (size_t)nbins, hipMemcpyDeviceToDevice, st);
+  std::vector<unsigned long long> vs(4 * (size_t)E);
+  std::vector<float> vz(2 * (size_t)E);
+  std::vector<int32_t> pk(E);
+  std::vector<uint32_t> toff(E + 1);
+  std::vector<double> vr(8 * (size_t)E);
+  uint32_t err = 0;
+  he = hipMemcpyAsync(vs.data(), w.vsum, 8 * vs.size(), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(vz.data(), w.vzd, 4 * vz.size(), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(pk.data(), w.vpeak, 4 * pk.size(), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(toff.data(), w.toff, 4 * toff.size(), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(vr.data(), w.vres, 8 * vr.size(), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(&err, w.err, 4, hipMemcpyDeviceToHost, st);
+  for (int e = 0; e < E && he == hipSuccess; ++e)
+    if (outs[e].hist)
+      he = hipMemcpyAsync(outs[e].hist, w.hist + (int64_t)e * nbins, 4 * (size_t)nbins, hipMemcpyDeviceToDevice, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return its_fail(c, TPCCA_E_DEVICE, std::string("ITS results: ") + hipGetErrorString(he));
-  if (vs[3]) return its_fail(c, TPCCA_E_INVALID, "a cluster has a bad layer or stave or a non-finite coordinate");
-  o->n_tracklets = n > 0 ? (int64_t)T : 0;
-  if (o->n_tracklets > cap) return its_fail(c, TPCCA_E_CAPACITY, "more tracklets than the output holds");
-  o->n_pairs = (int64_t)vs[0];
-  o->peak = pk;
-  o->vz = vz[0];
-  o->vz_ok = vz[1] != 0.0f ? 1 : 0;
-  o->vertex[0] = vr[0]; o->vertex[1] = vr[1]; o->vertex[2] = vr[2];
-  o->vfit_sumw = vr[3];
-  o->vfit_n = (int32_t)vr[4];
-  o->vfit_ok = vr[5] != 0.0 ? 1 : 0;
+  if (err) return its_fail(c, TPCCA_E_INVALID, "a cluster has a bad layer or stave or a non-finite coordinate");
+  bool fits = true;
+  for (int e = 0; e < E; ++e) {
+    tpcca_its_tracks& o = outs[e];
+    o.n_tracklets = (int64_t)(toff[e + 1] - toff[e]);
+    fits = fits && o.n_tracklets <= o.cap;
+    o.n_pairs = (int64_t)vs[4 * e];
+    o.peak = pk[e];
+    o.vz = vz[2 * e];
+    o.vz_ok = vz[2 * e + 1] != 0.0f ? 1 : 0;
+    o.vertex[0] = vr[8 * e]; o.vertex[1] = vr[8 * e + 1]; o.vertex[2] = vr[8 * e + 2];
+    o.vfit_sumw = vr[8 * e + 3];
+    o.vfit_n = (int32_t)vr[8 * e + 4];
+    o.vfit_ok = vr[8 * e + 5] != 0.0 ? 1 : 0;
+  }
+  if (!fits) return its_fail(c, TPCCA_E_CAPACITY, "more tracklets than an event's output holds");
   return TPCCA_OK;
+}
+
+int tpcca_its_track(tpcca_its_ctx* c, const tpcca_its_clusters* cl, tpcca_its_tracks* o) {
+  if (!c) return TPCCA_E_INVALID;
+  if (!cl || !o) return its_fail(c, TPCCA_E_INVALID, "null clusters or output");
+  return tpcca_its_track_batch(c, 1, cl, o);
 }
 
 const char* tpcca_its_last_error(const tpcca_its_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -80,11 +80,12 @@ class ItsTracker:
         _check(self.L, self.ctx, self.L.tpcca_its_set_params(self.ctx, C.byref(p)))
         self.nbins = int(round(2.0 * p.vtx_range / p.vtx_bin))
 
-    def track(self, x, y, z, layer, stave, hist: bool = False) -> ItsResult:
+    def _event(self, x, y, z, layer, stave, hist):
+        """Marshals one event: the cluster struct, the output struct and the
+        tensors behind both (kept alive by the caller until the call ends)."""
         dev = x.device
-        n = int(x.shape[0])
         cl = A.tpcca_its_clusters()
-        cl.n = n
+        cl.n = int(x.shape[0])
         keep = [t.contiguous() for t in (x, y, z, layer, stave)]
         cl.x, cl.y, cl.z, cl.layer, cl.stave = (_ptr(t) for t in keep)
         cl.stream = _stream_handle(dev)
@@ -103,12 +104,41 @@ class ItsTracker:
         for k in A.ITS_TRACK_ARRAYS:
             setattr(st, k, _ptr(o[k]))
         st.hist = _ptr(h)
-        _check(self.L, self.ctx, self.L.tpcca_its_track(self.ctx, C.byref(cl), C.byref(st)))
+        return cl, st, o, h, keep
+
+    @staticmethod
+    def _result(st, o, h) -> ItsResult:
         T = int(st.n_tracklets)
         sl = {k: v[:T] for k, v in o.items()}
         return ItsResult(**sl, hist=h, n_pairs=int(st.n_pairs), peak=int(st.peak), vz_ok=bool(st.vz_ok),
                          vz=float(st.vz), vfit_ok=bool(st.vfit_ok), vfit_n=int(st.vfit_n),
                          vertex=tuple(st.vertex), vfit_sumw=float(st.vfit_sumw))
+
+    def track(self, x, y, z, layer, stave, hist: bool = False) -> ItsResult:
+        cl, st, o, h, keep = self._event(x, y, z, layer, stave, hist)
+        _check(self.L, self.ctx, self.L.tpcca_its_track(self.ctx, C.byref(cl), C.byref(st)))
+        return self._result(st, o, h)
+
+    def prepare_batch(self, events, hist: bool = False):
+        """Marshals a batch once (output tensors, structs) and returns
+        run(results=True): one tpcca_its_track_batch call on it, for repeated
+        calls on the same inputs."""
+        ev = [self._event(*e, hist) for e in events]
+        n = len(ev)
+        cls = (A.tpcca_its_clusters * max(n, 1))(*[e[0] for e in ev])
+        sts = (A.tpcca_its_tracks * max(n, 1))(*[e[1] for e in ev])
+
+        def run(results: bool = True):
+            if n == 0:
+                return []
+            _check(self.L, self.ctx, self.L.tpcca_its_track_batch(self.ctx, n, cls, sts))
+            return [self._result(sts[i], e[2], e[3]) for i, e in enumerate(ev)] if results else None
+        return run
+
+    def track_batch(self, events, hist: bool = False) -> list:
+        """events: sequence of (x, y, z, layer, stave) device tensors, one
+        tuple per event, all on one device and stream; one library call."""
+        return self.prepare_batch(events, hist)()
 
     def close(self):
         if self.ctx:
