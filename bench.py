@@ -52,6 +52,10 @@ def main():
     ap.add_argument("--grad-only", action="store_true",
                     help="only run the calibration-gradient leg (for its kernel trace)")
     ap.add_argument("--its-only", action="store_true", help="only run the ITS leg (for its kernel trace)")
+    ap.add_argument("--its-workloads", default="ITS-pp,ITS-mb,ITS-central",
+                    help="ITS workloads of the ITS leg (comma-separated)")
+    ap.add_argument("--its-no-single", action="store_true",
+                    help="ITS leg: time the batches only, not the one-event calls")
     ap.add_argument("--timeframe-only", action="store_true",
                     help="only run the time-frame leg (for its kernel trace)")
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -73,7 +77,8 @@ def main():
         return
     if args.its_only:
         import torch
-        print(json.dumps({"its": its_leg(torch.device("cuda:0"))}), flush=True)
+        print(json.dumps({"its": its_leg(torch.device("cuda:0"), workloads=args.its_workloads.split(","),
+                                         single=not args.its_no_single)}), flush=True)
         return
     if args.timeframe_only:
         import torch
@@ -279,6 +284,7 @@ def pmc_summary(folder: str):
 
     record: {json.dumps(record)}
     """
+        text = "\n".join(l[4:] if l.startswith("    ") else l for l in text.split("\n"))
         os.makedirs(os.path.dirname(TRAFFIC_RECORD), exist_ok=True)
         with open(TRAFFIC_RECORD, "w") as f:
             f.write(text)
@@ -403,8 +409,8 @@ sources sha256 `{kernel_source_hash()}`.
 
 Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
-rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_tf -o tf -- python3 bench.py --timeframe-only
-python3 bench.py --pmc-summary <out>
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_tf -o tf -- python3 bench.py --timeframe-only
+    python3 bench.py --pmc-summary <out>
 
 tpcca_track_timeframe with 6 slices of one drift length: 2 warm-up calls with the segment
 outputs, 5 timed calls; average duration per dispatch (the tracking kernels run once per call
@@ -429,18 +435,18 @@ over the batch of 6 slices).
 
 Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
 
-    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_its -o its -- python3 bench.py --its-only
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_its -o its -- python3 bench.py --its-only --its-workloads ITS-central --its-no-single
     python3 bench.py --pmc-summary <out>
 
-One tpcca_its_track call per event: 20 events of each workload, 1 + 3 calls each (the averages
-mix the three event sizes: the per-kernel times of the central-like events are about twice
-these).
+One tpcca_its_track_batch call on 20 central-like events (about 18 k clusters and 2.6 k tracks
+each): 1 + 1 untimed and 5 timed calls; average duration per dispatch (one dispatch covers all
+20 events).
 
 | Kernel | Calls | Average µs | % of GPU time |
 |---|---|---|---|
 {body_i}
 """
-        with open(os.path.join(ROOT, "profiles", "its_kernel_trace.md"), "w") as f:
+        with open(os.path.join(ROOT, "profiles", "its_central_x20_kernel_trace.md"), "w") as f:
             f.write(text_i)
         print(text_i)
 
@@ -567,7 +573,7 @@ def timeframe_leg(trk, dev, reps=5):
             "tracks": m.n_tracks}
 
 
-def its_leg(dev, n_events=20, reps=5):
+def its_leg(dev, n_events=20, reps=5, workloads=("ITS-pp", "ITS-mb", "ITS-central"), single=True):
     """ITS standalone tracking (vertexer, tracklets, following, inward fit,
     vertex fit) of 20 events per workload (inputs resident in HBM, outputs
     marshalled beforehand): one tpcca_its_track_batch call on all 20, and one
@@ -593,13 +599,13 @@ def its_leg(dev, n_events=20, reps=5):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / (reps * n_events)
 
-    for name in ("ITS-pp", "ITS-mb", "ITS-central"):
+    for name in workloads:
         evs = [synth.make_its_config(name, i) for i in range(n_events)]
         tens = [(t(e.x), t(e.y), t(e.z), t(e.layer), t(e.stave)) for e in evs]
         batch = trk.prepare_batch(tens)
         outs = batch()
         dt_b = timed([batch])
-        dt_s = timed([trk.prepare_batch([c]) for c in tens])
+        dt_s = timed([trk.prepare_batch([c]) for c in tens]) if single else float("nan")
         ncl = sum(e.n for e in evs) / n_events
         ntrk = sum(int(o.ok.sum()) for o in outs) / n_events
         dv = np.array([np.array(o.vertex) - e.vertex for o, e in zip(outs, evs)])
