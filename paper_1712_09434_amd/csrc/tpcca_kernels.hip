@@ -305,22 +305,26 @@ __device__ __forceinline__ bool check_cluster(const Ws& w, const RawCl& c, int e
 }
 
 constexpr int kGroup = 4;
+// threads of the binning workgroups: a chunk's clusters and bins are spread
+// over sixteen waves, so the few hundred chunks of a large event still keep
+// several waves on every SIMD
+constexpr int TBB = 1024;
 
 // f(ok, ru, v) for every cluster of the chunk [c0, c1) of event e taken by
-// this thread (stride TB), kGroup at a time.
+// this thread (stride TBB), kGroup at a time.
 template <class F>
 __device__ __forceinline__ void for_chunk(const Ws& w, int64_t c0, int64_t c1, int e, F&& f) {
   const EventIn& E = w.ev[e];
-  for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += (int64_t)kGroup * TB) {
+  for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += (int64_t)kGroup * TBB) {
     RawCl c[kGroup];
 #pragma unroll
     for (int k = 0; k < kGroup; ++k) {
-      const int64_t g = g0 + (int64_t)k * TB;
+      const int64_t g = g0 + (int64_t)k * TBB;
       if (g < c1) c[k] = load_cluster(E, g - E.base);
     }
 #pragma unroll
     for (int k = 0; k < kGroup; ++k) {
-      const int64_t g = g0 + (int64_t)k * TB;
+      const int64_t g = g0 + (int64_t)k * TBB;
       if (g >= c1) continue;
       uint32_t ru = 0;
       float4 v;
@@ -336,7 +340,7 @@ __device__ __forceinline__ void for_chunk(const Ws& w, int64_t c0, int64_t c1, i
 // one global range reservation per non-empty bin, then LDS ranks.
 constexpr int kLdsBins = 8192;
 
-__global__ __launch_bounds__(TB) void k_count(Ws w) {
+__global__ __launch_bounds__(TBB) void k_count(Ws w) {
   __shared__ uint32_t s_h[kLdsBins];
   const ChunkIn ch = w.chunk[blockIdx.x];
   if (ch.c0 >= ch.c1) return;
@@ -345,7 +349,7 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
   const uint32_t per = (uint32_t)w.S * (uint32_t)w.R;
   const bool lds = per <= (uint32_t)kLdsBins;
   const uint32_t rb = (uint32_t)e * per;
-  if (lds) for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
+  if (lds) for (uint32_t b = threadIdx.x; b < per; b += TBB) s_h[b] = 0u;
   __syncthreads();
   for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4&) {
     if (!ok) { atomicOr(&w.flags[F_ERR], ERR_INVALID); return; }
@@ -354,7 +358,7 @@ __global__ __launch_bounds__(TB) void k_count(Ws w) {
   });
   __syncthreads();
   if (lds)
-    for (uint32_t b = threadIdx.x; b < per; b += TB)
+    for (uint32_t b = threadIdx.x; b < per; b += TBB)
       if (s_h[b]) atomicAdd(&w.ru_count[rb + b], s_h[b]);
 }
 
@@ -401,7 +405,7 @@ __global__ void k_cell_caps(Ws w) {
 // Each cluster travels with its coordinates and event-local id, so the row
 // kernel reads its row unit contiguously instead of gathering from the
 // (arbitrarily ordered) input.
-__global__ __launch_bounds__(TB) void k_scatter(Ws w) {
+__global__ __launch_bounds__(TBB) void k_scatter(Ws w) {
   __shared__ uint32_t s_h[kLdsBins];
   const ChunkIn ch = w.chunk[blockIdx.x];
   if (ch.c0 >= ch.c1) return;
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
   const bool lds = per <= (uint32_t)kLdsBins;
   const uint32_t rb = (uint32_t)e * per;
   if (lds) {
-    for (uint32_t b = threadIdx.x; b < per; b += TB) s_h[b] = 0u;
+    for (uint32_t b = threadIdx.x; b < per; b += TBB) s_h[b] = 0u;
     __syncthreads();
     for_chunk(w, c0, c1, e, [&](bool ok, uint32_t ru, const float4&) {
       if (ok && ru - rb < per) atomicAdd(&s_h[ru - rb], 1u);
@@ -419,17 +423,17 @@ __global__ __launch_bounds__(TB) void k_scatter(Ws w) {
     __syncthreads();
     // range reservations: the returning atomics of a thread's bins are all
     // issued before their results are stored
-    constexpr int kPer = kLdsBins / TB;
+    constexpr int kPer = kLdsBins / TBB;
     uint32_t got[kPer];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const uint32_t b = threadIdx.x + (uint32_t)i * TB;
+      const uint32_t b = threadIdx.x + (uint32_t)i * TBB;
       const uint32_t n = b < per ? s_h[b] : 0u;
       got[i] = n ? atomicAdd(&w.ru_count[rb + b], n) : 0u;
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-      const uint32_t b = threadIdx.x + (uint32_t)i * TB;
+      const uint32_t b = threadIdx.x + (uint32_t)i * TBB;
       if (b < per) s_h[b] = got[i];
     }
     __syncthreads();
@@ -1944,7 +1948,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_COUNT);
   const unsigned nchunk = (unsigned)chunk_cap(w.N, w.E);
-  k_count<<<nchunk, TB, 0, st>>>(w);
+  k_count<<<nchunk, TBB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_SCAN);
   if (w.RU <= kScanSmall) {
@@ -1956,7 +1960,7 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
     TPCCA_CHECK(fill_u32(w.ru_count, 0u, w.RU, st));
   }
   TPCCA_MARK(PH_SCATTER);
-  k_scatter<<<nchunk, TB, 0, st>>>(w);
+  k_scatter<<<nchunk, TBB, 0, st>>>(w);
   TPCCA_MARK(PH_ROWS);
   const bool lists = ru_lists(w.RU);
   const unsigned g_all = (unsigned)w.RU;
