@@ -141,6 +141,7 @@ def main():
                 "traffic_gbs": None if traffic_gbs is None else round(traffic_gbs, 1),
                 "traffic_frac": None if traffic_gbs is None else round(traffic_gbs / HBM_PEAK_GBS, 4),
                 "sq": measured_valu_issue(f"k_{dom}"),
+                "read_bytes_exact": measured_read_bytes(f"k_{dom}"),
                 "algo_bytes_per_launch": algo_bytes}
 
     cpu = None
@@ -204,6 +205,19 @@ def measured_traffic(kernel: str):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["bytes_per_launch"]
+
+
+def measured_read_bytes(kernel: str):
+    """Exact L2-miss read bytes per launch of `kernel` (request sizes
+    resolved) from the committed counter summary, or None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "tracking_c3_read_requests.md")) as f:
+            rec = next(json.loads(l[len("record: "):]) for l in f if l.startswith("record: "))
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("read_bytes_per_launch", {}).get(kernel)
 
 
 def measured_valu_issue(kernel: str):
@@ -289,6 +303,68 @@ def pmc_summary(folder: str):
         with open(TRAFFIC_RECORD, "w") as f:
             f.write(text)
         print(text)
+    def load_multi(sub):
+        vals, calls = defaultdict(lambda: defaultdict(float)), defaultdict(int)
+        for fn in glob.glob(os.path.join(folder, sub, "**", "*counter_collection*.csv"), recursive=True):
+            for r in csv.DictReader(open(fn)):
+                name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("tpcca::(anonymous namespace)::", ""))
+                name = re.sub(r"^void ", "", name)
+                vals[name][r["Counter_Name"]] += float(r["Counter_Value"])
+                if r["Counter_Name"] == "TCC_EA0_RDREQ_sum":
+                    calls[name] += 1
+        return vals, calls
+
+    rq, rqn = load_multi("pmc_req")
+    cq, cqn = load_multi("pmc_req_copy")
+    if rq and cq:
+        def split(v, c):
+            q = {k: x / max(c, 1) for k, x in v.items()}
+            n, n32 = q.get("TCC_EA0_RDREQ_sum", 0.0), q.get("TCC_EA0_RDREQ_32B_sum", 0.0)
+            n64, n128 = q.get("TCC_EA0_RDREQ_64B_sum", 0.0), q.get("TCC_EA0_RDREQ_128B_sum", 0.0)
+            exact = 32 * n32 + 64 * n64 + 128 * n128
+            fetch = 32 * n32 + 64 * (n - n32)          # FETCH_SIZE's reading (no 128-byte term seen)
+            return n, n32, n64, n128, exact, fetch
+        copy_name = max(cq, key=lambda k: cq[k].get("TCC_EA0_RDREQ_sum", 0.0))
+        cn, c32, c64, c128, cexact, cfetch = split(cq[copy_name], cqn[copy_name])
+        rows_r, rec_r = [], {}
+        for k in sorted(rq, key=lambda k: -split(rq[k], rqn[k])[4]):
+            if not k.startswith("k_"):
+                continue
+            n, n32, n64, n128, exact, fetch = split(rq[k], rqn[k])
+            if exact < 1e6:
+                continue
+            rec_r[k] = round(exact)
+            rows_r.append(f"| {k} | {n / 1e6:,.2f} | {100 * n32 / max(n, 1):.0f} / {100 * n64 / max(n, 1):.0f} / "
+                          f"{100 * n128 / max(n, 1):.0f} | {exact / 1e6:,.1f} | {fetch / 1e6:,.1f} | "
+                          f"{2 * fetch / 1e6:,.1f} |")
+        record_r = {"workload": "C3", "source_sha256": kernel_source_hash(), "read_bytes_per_launch": rec_r}
+        text_r = f"""# L2 read requests by size, central-Pb-Pb-shaped event (3.81 M clusters)
+
+Commands (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+    rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d <out>/pmc_req -o req -- {PMC_BENCH_CMD}
+    rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum -f csv -d <out>/pmc_req_copy -o reqc -- python3 bench.py --copy-probe-mib 1024
+    python3 bench.py --pmc-summary <out>
+
+Read requests from the L2 to the memory side (all XCDs), per dispatch, split by request size.
+Exact bytes = 32 n(32 B) + 64 n(64 B) + 128 n(128 B).  FETCH_SIZE's expression counts every
+request that is not a 32-byte one as 64 bytes (its 128-byte term reads zero here), so a plain copy,
+made of 128-byte requests, reads as half its size and the copy-scaled traffic doubles FETCH_SIZE.
+The plain 1 GiB copy: {cn / 1e6:,.2f} M requests, {100 * c32 / max(cn, 1):.0f} / {100 * c64 / max(cn, 1):.0f} /
+{100 * c128 / max(cn, 1):.0f} % of 32 / 64 / 128 bytes, {cexact / 2**20:,.0f} MiB exact against
+{cfetch / 2**20:,.0f} MiB by FETCH_SIZE's expression.  These are L2 misses: on this chip they are
+served by the 256 MB Infinity Cache or by HBM, which the L2 counters do not tell apart.  Kernel
+sources sha256 `{kernel_source_hash()}`.
+
+| Kernel | Read requests (M) | 32 / 64 / 128 B (%) | Exact MB | FETCH_SIZE MB | Copy-scaled MB |
+|---|---|---|---|---|---|
+""" + "\n".join(rows_r) + f"""
+
+record: {json.dumps(record_r)}
+"""
+        with open(os.path.join(ROOT, "profiles", "tracking_c3_read_requests.md"), "w") as f:
+            f.write(text_r)
+        print(text_r)
     stats = glob.glob(os.path.join(folder, "prof_c3", "**", "*kernel_stats.csv"), recursive=True)
     if stats:
         lines = []
@@ -743,7 +819,7 @@ def cpu_baseline(ev, args):
     sample of the same event: (i) single-threaded on a few sectors, (ii) one
     sector per thread on T threads at once (sectors are independent, so the
     event's work splits over them without change).  The reported value is
-    (ii); cores = T."""
+    the median of three runs of (ii); cores = T."""
     import concurrent.futures
     import numpy as np
     import oracle
@@ -770,16 +846,20 @@ def cpu_baseline(ev, args):
     T = min(T, ns)
     secsT = sorted({int(round(v)) for v in np.linspace(0, ns - 1, T)})
     nT = int(np.isin(ev.sector, secsT).sum())
-    log(f"oracle (FP32, {len(secsT)} threads, one sector each) on sectors {secsT}: {nT} clusters")
-    tT = time.perf_counter()
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(secsT)) as pool:
-        list(pool.map(lambda s: one([s]), secsT))
-    cT = time.perf_counter() - tT
-    log(f"oracle {len(secsT)} threads {nT / cT:.3e} clusters/s")
+    log(f"oracle (FP32, {len(secsT)} threads, one sector each) on sectors {secsT}: {nT} clusters, 3 runs")
+    walls = []
+    for _ in range(3):
+        tT = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(max_workers=len(secsT)) as pool:
+            list(pool.map(lambda s: one([s]), secsT))
+        walls.append(time.perf_counter() - tT)
+        log(f"oracle {len(secsT)} threads {nT / walls[-1]:.3e} clusters/s")
+    cT = sorted(walls)[1]
     return {"value": nT / cT, "unit": "clusters/s", "cores": len(secsT), "kind": "oracle",
             "sample": (f"C3 event: sectors {secsT} ({nT} clusters), one sector per thread on "
-                       f"{len(secsT)} threads, {cT:.1f} s wall; single-threaded on sectors {secs1} "
-                       f"({n1} clusters) {c1:.1f} s"),
+                       f"{len(secsT)} threads, median of 3 runs ({', '.join(f'{v:.2f}' for v in walls)} s "
+                       f"wall); single-threaded on sectors {secs1} ({n1} clusters) {c1:.1f} s"),
+            "runs_s": [round(v, 3) for v in walls],
             "single_thread_value": n1 / c1, "host_cpu": _cpu_model()}
 
 def _cpu_model():
