@@ -26,19 +26,22 @@ struct MergeWs {
   const int16_t* crow;
   int64_t NC;
   const int32_t* slice;    // [T] time-frame slice of each segment, or null (one event)
+  int nsl;                 // slices of the frame (1 for one event): the lists are by (sector, slice)
+  int prune;               // 1: the window is shorter than half a slice, so only segments of the
+                           // same or a neighbouring slice can pass it
   // work
   float* ex;               // [T][24]: exit plane, state, covariance (if the exit transport succeeded)
   float4* first;           // [T] innermost hit (x, y, z, row bits)
   float4* last;            // [T] outermost hit (x, y, z, row bits)
   uint32_t* flags;         // [T] bit 0: exit state valid
-  uint32_t* sec_cnt;       // [S + 1] segments per sector, then offsets
-  uint32_t* sec_cur;       // [S] fill cursors
-  uint32_t* sec_list;      // [T] segment indices by sector
+  uint32_t* sec_cnt;       // [S nsl + 1] segments per (sector, slice), then offsets
+  uint32_t* sec_cur;       // [S nsl] fill counts (from zero)
+  uint32_t* sec_list;      // [T] segment indices by (sector, slice)
   unsigned long long* best_in;   // [T] (chi2 bits << 32) | inner partner, or ~0
   unsigned long long* best_out;  // [T] (chi2 bits << 32) | outer partner, or ~0
   int32_t* link;           // [T] outer partner or -1
   int32_t* inner;          // [T] inner partner or -1
-  float4* srec;            // [T] by sector: outermost hit (x, y, z), (slice << 9 | last row << 1 | exit valid) bits
+  float4* srec;            // [T] by (sector, slice): outermost hit (x, y, z), (slice << 9 | last row << 1 | exit valid) bits
   uint32_t* emit;          // [T + 1] output tracks of the chain headed by a segment -> offsets
   uint32_t* hemit;         // [T + 1] hits of those tracks -> offsets
   int32_t* head;           // [T] the head of each segment's chain

@@ -132,7 +132,7 @@ __device__ __forceinline__ float turn_sign(int wa, int wb, int NW) { return wb =
 
 __global__ __launch_bounds__(TB) void k_mrg_init(MergeWs w) {
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
-  if (i < w.S) w.sec_cnt[i] = 0u;
+  if (i < (int64_t)w.S * w.nsl) { w.sec_cnt[i] = 0u; w.sec_cur[i] = 0u; }
   if (i < 4) w.err[i] = 0u;
   if (i < w.T) {
     w.best_in[i] = kNone;
@@ -143,9 +143,14 @@ __global__ __launch_bounds__(TB) void k_mrg_init(MergeWs w) {
   }
 }
 
-// Sector histogram of a workgroup's segments in LDS, one global atomic per
-// non-empty sector (the segments of a workgroup share few sectors).
+// (Sector, slice) histogram of a workgroup's segments in LDS, one global
+// atomic per non-empty bin (the segments of a workgroup share few bins);
+// with more bins than kSecBins, global atomics per segment.
 constexpr int kSecBins = 256;
+
+__device__ __forceinline__ uint32_t sec_bin(const MergeWs& w, int64_t i, int s) {
+  return (uint32_t)s * (uint32_t)w.nsl + (uint32_t)(w.slice ? w.slice[i] : 0);
+}
 
 __global__ __launch_bounds__(TB) void k_mrg_ends(MergeWs w) {
   __shared__ uint32_t s_h[kSecBins];
@@ -167,7 +172,9 @@ __global__ __launch_bounds__(TB) void k_mrg_ends(MergeWs w) {
       w.first[i] = make_float4(w.cx[hf], w.cy[hf], w.cz[hf], __int_as_float((int)w.crow[hf]));
       const float xo = w.cx[hl];
       w.last[i] = make_float4(xo, w.cy[hl], w.cz[hl], __int_as_float((int)w.crow[hl]));
-      atomicAdd(&s_h[s], 1u);
+      const uint32_t bin = sec_bin(w, i, s);
+      if (w.S * w.nsl <= kSecBins) atomicAdd(&s_h[bin], 1u);
+      else atomicAdd(&w.sec_cnt[bin], 1u);
       float p[5], C[15];
 #pragma unroll
       for (int k = 0; k < 5; ++k) p[k] = w.p[i * 5 + k];
@@ -187,39 +194,30 @@ __global__ __launch_bounds__(TB) void k_mrg_ends(MergeWs w) {
     }
   }
   __syncthreads();
-  if (threadIdx.x < w.S && s_h[threadIdx.x]) atomicAdd(&w.sec_cnt[threadIdx.x], s_h[threadIdx.x]);
+  if (threadIdx.x < w.S * w.nsl && w.S * w.nsl <= kSecBins && s_h[threadIdx.x])
+    atomicAdd(&w.sec_cnt[threadIdx.x], s_h[threadIdx.x]);
 }
 
-// Sector offsets (one thread; at most 254 sectors).
-__global__ void k_mrg_secscan(MergeWs w) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t acc = 0;
-  for (int s = 0; s < w.S; ++s) {
-    const uint32_t n = w.sec_cnt[s];
-    w.sec_cnt[s] = acc;
-    w.sec_cur[s] = acc;
-    acc += n;
-  }
-  w.sec_cnt[w.S] = acc;
-}
-
-// Every well-formed segment takes a slot of its sector's list (a range per
-// sector and workgroup, ranks in LDS) and writes there what the candidate
-// search tests first: its outermost hit, last row and exit flag.
+// Every well-formed segment takes a slot of its (sector, slice) list (the
+// bins' offsets are the exclusive scan of the counts; a range per bin and
+// workgroup, ranks in LDS) and writes there what the candidate search tests
+// first: its outermost hit, last row and exit flag.
 __global__ __launch_bounds__(TB) void k_mrg_secfill(MergeWs w) {
   __shared__ uint32_t s_h[kSecBins];
+  const bool lds = w.S * w.nsl <= kSecBins;
   s_h[threadIdx.x] = 0u;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
   const bool good = i < w.T && (w.flags[i] & 2u);
-  const int s = good ? (int)w.sector[i] : 0;
+  const uint32_t bin = good ? sec_bin(w, i, (int)w.sector[i]) : 0u;
   uint32_t rank = 0;
-  if (good) rank = atomicAdd(&s_h[s], 1u);
+  if (good) rank = lds ? atomicAdd(&s_h[bin], 1u) : atomicAdd(&w.sec_cur[bin], 1u);
   __syncthreads();
-  if (threadIdx.x < w.S && s_h[threadIdx.x]) s_h[threadIdx.x] = atomicAdd(&w.sec_cur[threadIdx.x], s_h[threadIdx.x]);
+  if (lds && threadIdx.x < w.S * w.nsl && s_h[threadIdx.x])
+    s_h[threadIdx.x] = atomicAdd(&w.sec_cur[threadIdx.x], s_h[threadIdx.x]);
   __syncthreads();
   if (good) {
-    const uint32_t pos = s_h[s] + rank;
+    const uint32_t pos = w.sec_cnt[bin] + (lds ? s_h[bin] : 0u) + rank;
     const float4 l = w.last[i];
     const int sl = w.slice ? w.slice[i] : 0;   // (0 <= slice < 2^22, checked by the caller)
     w.sec_list[pos] = (uint32_t)i;
@@ -297,12 +295,8 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
     cnt = 0;
   };
   const int ndir = w.slice ? 3 : 2;
-  for (int dir = 0; dir < ndir; ++dir) {
-    // 0, 1: the preceding and following wedge of the side; 2: the own sector
-    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : dir == 1 ? (wb + 1) % w.NW : wb;
-    const int sa_ = side0 + wa;
-    const float sa = dir == 2 ? 0.0f : turn_sign(wa, wb, w.NW) * w.sa, ca = dir == 2 ? 1.0f : w.ca;
-    const uint32_t k0 = w.sec_cnt[sa_], k1 = w.sec_cnt[sa_ + 1];
+  // the list part [k0, k1) of direction dir
+  auto scan = [&](int dir, float ca, float sa, uint32_t k0, uint32_t k1) {
     for (uint32_t kb = k0; kb < k1; kb += 64) {
       const uint32_t k = kb + (uint32_t)lane;
       bool pass = false;
@@ -327,6 +321,24 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
         s_dir[wv][slot] = (uint8_t)dir;
       }
       cnt += np;
+    }
+  };
+  for (int dir = 0; dir < ndir; ++dir) {
+    // 0, 1: the preceding and following wedge of the side; 2: the own sector
+    const int wa = dir == 0 ? (wb + w.NW - 1) % w.NW : dir == 1 ? (wb + 1) % w.NW : wb;
+    const uint32_t s0 = (uint32_t)(side0 + wa) * (uint32_t)w.nsl;
+    const float sa = dir == 2 ? 0.0f : turn_sign(wa, wb, w.NW) * w.sa, ca = dir == 2 ? 1.0f : w.ca;
+    if (!w.prune) {
+      scan(dir, ca, sa, w.sec_cnt[s0], w.sec_cnt[s0 + (uint32_t)w.nsl]);
+      continue;
+    }
+    // hit ends two or more slices apart are more than a slice length apart
+    // in the frame's z, outside the window: only the neighbouring slices
+    // (and, across wedges, the own one) are scanned
+    for (int ds = -1; ds <= 1; ++ds) {
+      const int sl = slb + ds;
+      if ((dir == 2 && ds == 0) || sl < 0 || sl >= w.nsl) continue;
+      scan(dir, ca, sa, w.sec_cnt[s0 + (uint32_t)sl], w.sec_cnt[s0 + (uint32_t)sl + 1]);
     }
   }
   if (cnt > 0) flush();
@@ -508,14 +520,16 @@ hipError_t run_merge(const MergeWs& w, hipStream_t st) {
                         w.o_hit_off, w.o_hit_id};
   for (const void* q : need)
     if (!q) return hipErrorInvalidValue;
-  if (w.S > kMaxSectors || w.S > kSecBins || w.T >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  const int64_t n0 = std::max<int64_t>(std::max<int64_t>(w.T, w.S), 4);
+  if (w.S > kMaxSectors || w.S > kSecBins || w.nsl < 1 || w.T >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int64_t nbin = (int64_t)w.S * w.nsl;
+  const int64_t n0 = std::max<int64_t>(std::max<int64_t>(w.T, nbin), 4);
   k_mrg_init<<<(unsigned)((n0 + TB - 1) / TB), TB, 0, st>>>(w);
   const unsigned g = (unsigned)std::max<int64_t>((w.T + TB - 1) / TB, 1);
   const unsigned gw = (unsigned)std::max<int64_t>((w.T + TB / 64 - 1) / (TB / 64), 1);
   if (w.T > 0) {
     k_mrg_ends<<<g, TB, 0, st>>>(w);
-    k_mrg_secscan<<<1, 64, 0, st>>>(w);
+    const hipError_t es = scan_exclusive_u32(w.sec_cnt, w.sec_cnt, nbin, w.scan_part, st);
+    if (es != hipSuccess) return es;
     k_mrg_secfill<<<g, TB, 0, st>>>(w);
     k_mrg_pairs<<<gw, TB, 0, st>>>(w);
     k_mrg_links<<<g, TB, 0, st>>>(w);

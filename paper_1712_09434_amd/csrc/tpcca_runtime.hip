@@ -870,9 +870,11 @@ int grad_err(tpcca_ctx* c, uint32_t err) {
 // The merger on T segments with H hits (checked by the caller) whose hit
 // ids index NC clusters (cx, cy, cz, crow); slice: the segments' time-frame
 // slices or null.  Device memory throughout.
+// slice: each segment's time-frame slice (null for one event); nsl slices
+// of length slice_len along the readout time.
 int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const float* cy, const float* cz,
-               const int16_t* crow, int64_t NC, const int32_t* slice, int64_t H, tpcca_tracks* out,
-               int32_t* seg_link, hipStream_t st) {
+               const int16_t* crow, int64_t NC, const int32_t* slice, int nsl, float slice_len, int64_t H,
+               tpcca_tracks* out, int32_t* seg_link, hipStream_t st) {
   const int64_t T = seg->n_tracks;
   hipError_t he;
   // the merged output has at most as many tracks, and exactly as many hits
@@ -886,13 +888,14 @@ int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const flo
     return fail(c, TPCCA_E_INVALID, "null output array");
   Layout L;
   const size_t o_ex = L.take<float>(T * 24), o_first = L.take<float4>(T), o_last = L.take<float4>(T);
-  const size_t o_flags = L.take<uint32_t>(T), o_cnt = L.take<uint32_t>(c->S + 1), o_cur = L.take<uint32_t>(c->S);
+  const int64_t nbin = (int64_t)c->S * (slice ? nsl : 1);
+  const size_t o_flags = L.take<uint32_t>(T), o_cnt = L.take<uint32_t>(nbin + 1), o_cur = L.take<uint32_t>(nbin);
   const size_t o_list = L.take<uint32_t>(T), o_bi = L.take<unsigned long long>(T), o_bo = L.take<unsigned long long>(T);
   const size_t o_link = L.take<int32_t>(T), o_inner = L.take<int32_t>(T), o_emit = L.take<uint32_t>(T + 1);
   const size_t o_hemit = L.take<uint32_t>(T + 1), o_rec = L.take<float>(T * 24), o_err = L.take<uint32_t>(4);
   const size_t o_srec = L.take<float4>(T), o_head = L.take<int32_t>(T), o_tpos = L.take<uint32_t>(T);
   const size_t o_hpos = L.take<uint32_t>(T), o_nseg = L.take<uint32_t>(T), o_rlist = L.take<uint32_t>(T);
-  const size_t o_part = L.take<uint32_t>(2 * (T / 1024 + 2));
+  const size_t o_part = L.take<uint32_t>(2 * (std::max<int64_t>(T, nbin) / 1024 + 2));
   if (L.off > c->mscratch_bytes) {
     if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
     he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
@@ -911,6 +914,8 @@ int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const flo
   w.sector = seg->sector; w.x_ref = seg->x_ref; w.p = seg->p; w.cov = seg->cov; w.chi2 = seg->chi2;
   w.ndf = seg->ndf; w.hit_off = seg->hit_off; w.hit_id = seg->hit_id;
   w.cx = cx; w.cy = cy; w.cz = cz; w.crow = crow; w.slice = slice;
+  w.nsl = slice ? nsl : 1;
+  w.prune = slice && nsl > 1 && w.merge_dist < 0.5f * slice_len ? 1 : 0;
   w.ex = (float*)(b + o_ex); w.first = (float4*)(b + o_first); w.last = (float4*)(b + o_last);
   w.flags = (uint32_t*)(b + o_flags); w.sec_cnt = (uint32_t*)(b + o_cnt); w.sec_cur = (uint32_t*)(b + o_cur);
   w.sec_list = (uint32_t*)(b + o_list);
@@ -1053,7 +1058,7 @@ int tpcca_merge(tpcca_ctx* c, const tpcca_tracks* seg, tpcca_tracks* out, int32_
     if (he != hipSuccess) return hip_fail(c, he, "hit_off read");
     if (ends[0] != 0 || ends[1] < 0) return fail(c, TPCCA_E_INVALID, "hit_off must start at 0");
   }
-  return merge_core(c, seg, k.x, k.y, k.z, k.row, NC, nullptr, ends[1], out, seg_link, st);
+  return merge_core(c, seg, k.x, k.y, k.z, k.row, NC, nullptr, 1, 0.0f, ends[1], out, seg_link, st);
 }
 
 int tpcca_track_timeframe(tpcca_ctx* c, const tpcca_clusters* fr, float slice_len, int32_t n_slices,
@@ -1196,7 +1201,7 @@ int tpcca_track_timeframe(tpcca_ctx* c, const tpcca_clusters* fr, float slice_le
   view.sector = g.osec; view.x_ref = g.oxref; view.p = g.op; view.cov = g.ocov; view.chi2 = g.ochi2;
   view.ndf = g.ondf; view.hit_off = g.ohoff; view.hit_id = g.ohid; view.mem = TPCCA_MEM_DEVICE;
   // (the tab upload above reads host memory that lives until here: the merger synchronises the stream)
-  return merge_core(c, &view, fr->x, fr->y, a.ztf, fr->row, n, g.oslice, H, merged, seg_link, st);
+  return merge_core(c, &view, fr->x, fr->y, a.ztf, fr->row, n, g.oslice, E, slice_len, H, merged, seg_link, st);
 }
 
 int tpcca_refit_grad_noalloc(tpcca_ctx* c, const tpcca_tracks* t, const tpcca_calib* cal, tpcca_grad* g) {
