@@ -41,6 +41,9 @@ struct MergeWs {
   unsigned long long* best_out;  // [T] (chi2 bits << 32) | outer partner, or ~0
   int32_t* link;           // [T] outer partner or -1
   int32_t* inner;          // [T] inner partner or -1
+  float4* zrec;            // [T] srec with every list of at most kZSort records sorted by z
+  uint32_t* zlist;         // [T] sec_list in the same order
+  uint8_t* zsorted;        // [S nsl] 1: the list is sorted by z
   float4* srec;            // [T] by (sector, slice): outermost hit (x, y, z), (slice << 9 | last row << 1 | exit valid) bits
   uint32_t* emit;          // [T + 1] output tracks of the chain headed by a segment -> offsets
   uint32_t* hemit;         // [T + 1] hits of those tracks -> offsets

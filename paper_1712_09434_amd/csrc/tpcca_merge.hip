@@ -242,6 +242,59 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
   return v;
 }
 
+// Each (sector, slice) list of at most kZSort records sorted by the z of the
+// outermost hit (bitonic in LDS on (z order bits, slot)), so that the
+// candidate search reads only the part inside the z window; longer lists
+// are copied as they are and scanned whole.
+constexpr int kZSort = 2048;
+constexpr int TBZ = 1024;
+
+__global__ __launch_bounds__(TBZ) void k_mrg_zsort(MergeWs w) {
+  __shared__ unsigned long long s_k[kZSort];
+  const uint32_t bin = blockIdx.x;
+  const uint32_t k0 = w.sec_cnt[bin], n = w.sec_cnt[bin + 1] - k0;
+  if (n > (uint32_t)kZSort) {
+    for (uint32_t i = threadIdx.x; i < n; i += TBZ) {
+      w.zrec[k0 + i] = w.srec[k0 + i];
+      w.zlist[k0 + i] = w.sec_list[k0 + i];
+    }
+    if (threadIdx.x == 0) w.zsorted[bin] = 0;
+    return;
+  }
+  if (threadIdx.x == 0) w.zsorted[bin] = 1;
+  if (n == 0) return;
+  uint32_t npad = 1;
+  while (npad < n) npad <<= 1;
+  for (uint32_t i = threadIdx.x; i < npad; i += TBZ) {
+    unsigned long long key = ~0ull;
+    if (i < n) {
+      // order-preserving bits of the float (negatives reversed below positives)
+      const uint32_t u = __float_as_uint(w.srec[k0 + i].z);
+      const uint32_t m = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+      key = ((unsigned long long)m << 32) | i;
+    }
+    s_k[i] = key;
+  }
+  __syncthreads();
+  for (uint32_t kk = 2; kk <= npad; kk <<= 1) {
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < npad; i += TBZ) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned long long x = s_k[i], y = s_k[ixj];
+          if ((x > y) == ((i & kk) == 0)) { s_k[i] = y; s_k[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += TBZ) {
+    const uint32_t src = (uint32_t)(s_k[i] & 0xFFFFFFFFull);
+    w.zrec[k0 + i] = w.srec[k0 + src];
+    w.zlist[k0 + i] = w.sec_list[k0 + src];
+  }
+}
+
 __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
   // records that pass the cheap tests, collected per wave and then tested
   // in full one per lane (the full test is long; survivors are few and
@@ -267,7 +320,7 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
       const int dir = s_dir[wv][lane];
       const int wa = dir == 1 ? (wb + 1) % w.NW : (wb + w.NW - 1) % w.NW;
       const float sa = turn_sign(wa, wb, w.NW) * w.sa, ca = w.ca;
-      const uint32_t a = w.sec_list[k];
+      const uint32_t a = w.zlist[k];
       const float* e = w.ex + (int64_t)a * 24;
       float x = e[0], q[5], Q[15];
 #pragma unroll
@@ -295,13 +348,28 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
     cnt = 0;
   };
   const int ndir = w.slice ? 3 : 2;
-  // the list part [k0, k1) of direction dir
-  auto scan = [&](int dir, float ca, float sa, uint32_t k0, uint32_t k1) {
+  // hit ends outside [zlo, zhi] fail the window test (the margin covers the
+  // rounding of the bounds and of the test's difference)
+  const float zlo = (hb.z - w.merge_dist) - 0.01f, zhi = (hb.z + w.merge_dist) + 0.01f;
+  // the list of bin for direction dir: in a z-sorted list, from the last of
+  // 64 evenly spaced probes below zlo up to the first chunk wholly above zhi
+  auto scan = [&](int dir, float ca, float sa, uint32_t bin) {
+    uint32_t k0 = w.sec_cnt[bin];
+    const uint32_t k1 = w.sec_cnt[bin + 1];
+    if (k0 >= k1) return;
+    const bool zs = w.zsorted[bin] != 0;
+    if (zs) {
+      const uint32_t step = (k1 - k0 + 63) / 64;
+      const uint32_t at = k0 + (uint32_t)lane * step;
+      const int c = __popcll(__ballot(at < k1 && w.zrec[at].z < zlo));
+      if (c > 0) k0 += (uint32_t)(c - 1) * step;
+    }
     for (uint32_t kb = k0; kb < k1; kb += 64) {
       const uint32_t k = kb + (uint32_t)lane;
-      bool pass = false;
+      bool pass = false, inside = false;
       if (k < k1) {
-        const float4 ha = w.srec[k];
+        const float4 ha = w.zrec[k];
+        inside = !(ha.z > zhi);
         const int bits = __float_as_int(ha.w);
         const int dsl = (bits >> 9) - slb;
         if ((bits & 1) && ((bits >> 1) & 0xFF) < rlo_b && (dir < 2 || dsl == 1 || dsl == -1)) {
@@ -312,15 +380,18 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
         }
       }
       const uint64_t mask = __ballot(pass);
+      const bool stop = zs && __ballot(inside) == 0ull;   // (sorted: all later records lie above)
       const int np = __popcll(mask);
-      if (np == 0) continue;
-      if (cnt + np > 64) flush();
-      if (pass) {
-        const int slot = cnt + __popcll(mask & lanemask_lt());
-        s_cand[wv][slot] = k;
-        s_dir[wv][slot] = (uint8_t)dir;
+      if (np > 0) {
+        if (cnt + np > 64) flush();
+        if (pass) {
+          const int slot = cnt + __popcll(mask & lanemask_lt());
+          s_cand[wv][slot] = k;
+          s_dir[wv][slot] = (uint8_t)dir;
+        }
+        cnt += np;
       }
-      cnt += np;
+      if (stop) break;
     }
   };
   for (int dir = 0; dir < ndir; ++dir) {
@@ -329,7 +400,7 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
     const uint32_t s0 = (uint32_t)(side0 + wa) * (uint32_t)w.nsl;
     const float sa = dir == 2 ? 0.0f : turn_sign(wa, wb, w.NW) * w.sa, ca = dir == 2 ? 1.0f : w.ca;
     if (!w.prune) {
-      scan(dir, ca, sa, w.sec_cnt[s0], w.sec_cnt[s0 + (uint32_t)w.nsl]);
+      for (int sl = 0; sl < w.nsl; ++sl) scan(dir, ca, sa, s0 + (uint32_t)sl);
       continue;
     }
     // hit ends two or more slices apart are more than a slice length apart
@@ -338,7 +409,7 @@ __global__ __launch_bounds__(TB) void k_mrg_pairs(MergeWs w) {
     for (int ds = -1; ds <= 1; ++ds) {
       const int sl = slb + ds;
       if ((dir == 2 && ds == 0) || sl < 0 || sl >= w.nsl) continue;
-      scan(dir, ca, sa, w.sec_cnt[s0 + (uint32_t)sl], w.sec_cnt[s0 + (uint32_t)sl + 1]);
+      scan(dir, ca, sa, s0 + (uint32_t)sl);
     }
   }
   if (cnt > 0) flush();
@@ -514,7 +585,7 @@ __global__ __launch_bounds__(TB) void k_mrg_tracks(MergeWs w) {
 
 hipError_t run_merge(const MergeWs& w, hipStream_t st) {
   const void* need[] = {w.sector, w.x_ref, w.p, w.cov, w.chi2, w.ndf, w.hit_off, w.hit_id, w.cx, w.cy, w.cz,
-                        w.crow, w.ex, w.first, w.last, w.flags, w.sec_cnt, w.sec_cur, w.sec_list, w.srec,
+                        w.crow, w.ex, w.first, w.last, w.flags, w.sec_cnt, w.sec_cur, w.sec_list, w.srec, w.zrec, w.zlist, w.zsorted,
                         w.best_in, w.best_out, w.link, w.inner, w.emit, w.hemit, w.head, w.tpos, w.hpos, w.nseg,
                         w.rlist, w.rec, w.err, w.scan_part, w.o_sector, w.o_x_ref, w.o_p, w.o_cov, w.o_chi2, w.o_ndf,
                         w.o_hit_off, w.o_hit_id};
@@ -531,6 +602,7 @@ hipError_t run_merge(const MergeWs& w, hipStream_t st) {
     const hipError_t es = scan_exclusive_u32(w.sec_cnt, w.sec_cnt, nbin, w.scan_part, st);
     if (es != hipSuccess) return es;
     k_mrg_secfill<<<g, TB, 0, st>>>(w);
+    k_mrg_zsort<<<(unsigned)nbin, TBZ, 0, st>>>(w);
     k_mrg_pairs<<<gw, TB, 0, st>>>(w);
     k_mrg_links<<<g, TB, 0, st>>>(w);
     k_mrg_chains<<<g, TB, 0, st>>>(w);

@@ -896,6 +896,7 @@ int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const flo
   const size_t o_srec = L.take<float4>(T), o_head = L.take<int32_t>(T), o_tpos = L.take<uint32_t>(T);
   const size_t o_hpos = L.take<uint32_t>(T), o_nseg = L.take<uint32_t>(T), o_rlist = L.take<uint32_t>(T);
   const size_t o_part = L.take<uint32_t>(2 * (std::max<int64_t>(T, nbin) / 1024 + 2));
+  const size_t o_zrec = L.take<float4>(T), o_zlist = L.take<uint32_t>(T), o_zs = L.take<uint8_t>(nbin);
   if (L.off > c->mscratch_bytes) {
     if (c->mscratch) { (void)hipFree(c->mscratch); c->mscratch = nullptr; c->mscratch_bytes = 0; }
     he = hipMalloc((void**)&c->mscratch, L.off + L.off / 4);
@@ -926,6 +927,7 @@ int merge_core(tpcca_ctx* c, const tpcca_tracks* seg, const float* cx, const flo
   w.srec = (float4*)(b + o_srec); w.head = (int32_t*)(b + o_head); w.tpos = (uint32_t*)(b + o_tpos);
   w.hpos = (uint32_t*)(b + o_hpos); w.nseg = (uint32_t*)(b + o_nseg); w.rlist = (uint32_t*)(b + o_rlist);
   w.scan_part = (uint32_t*)(b + o_part);
+  w.zrec = (float4*)(b + o_zrec); w.zlist = (uint32_t*)(b + o_zlist); w.zsorted = (uint8_t*)(b + o_zs);
   w.o_sector = out->sector; w.o_x_ref = out->x_ref; w.o_p = out->p; w.o_cov = out->cov; w.o_chi2 = out->chi2;
   w.o_ndf = out->ndf; w.o_hit_off = out->hit_off; w.o_hit_id = out->hit_id; w.o_link = seg_link;
   // an empty call still passes valid pointers to the kernels' checks
