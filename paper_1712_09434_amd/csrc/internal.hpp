@@ -44,7 +44,7 @@ struct alignas(32) GridParams {
   uint32_t cell_base;
   uint32_t nz, ny;
   float z0, y0, inv_bz, inv_by;
-  uint32_t pad;
+  uint32_t base;        // the row unit's first entry in the grid-ordered arrays
 };
 
 struct EventIn {
@@ -129,7 +129,8 @@ struct Ws {
   uint32_t* cru;        // row unit
   // grid-ordered copy for window searches: (y, z, x, canonical position)
   float4* gbuf;         // [N]
-  uint32_t* cell_off;   // [kCellsPerCluster N + 2 RU + 1] (grid_cells + 1 per row unit)
+  uint16_t* cell_off;   // [kCellsPerCluster N + 2 RU + 1] (grid_cells + 1 per row unit), relative to the
+                        // row unit's first entry (rows hold at most TPCCA_MAX_ROW_CLUSTERS < 2^16)
   // links (canonical positions)
   int32_t* up;
   int32_t* dn;

@@ -469,8 +469,8 @@ __device__ __forceinline__ uint32_t cell_of(const GridParams& G, float y, float 
 // Search grid of a row unit of n clusters with the given bounding box: about
 // grid_cells(n) cells of equal shape over the box (one cell if the box is
 // degenerate or n < 4).
-__device__ __forceinline__ GridParams make_grid(uint32_t n, uint32_t cbase, float ymin, float ymax, float zmin,
-                                                float zmax) {
+__device__ __forceinline__ GridParams make_grid(uint32_t n, uint32_t cbase, uint32_t off, float ymin, float ymax,
+                                                float zmin, float zmax) {
   const uint32_t cap = grid_cells(n);
   uint32_t nz = 1, ny = 1;
   float dz = zmax - zmin, dy = ymax - ymin;
@@ -484,7 +484,7 @@ __device__ __forceinline__ GridParams make_grid(uint32_t n, uint32_t cbase, floa
   G.cell_base = cbase; G.nz = nz; G.ny = ny; G.z0 = zmin; G.y0 = ymin;
   G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
   G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
-  G.pad = 0u;
+  G.base = off;
   return G;
 }
 
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
     zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
   }
   // grid parameters: every lane computes the same values, lane 0 stores them
-  const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
+  const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
   if (lane == 0) w.grid[ru] = G;
   const uint32_t nc = G.nz * G.ny;
   for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
@@ -560,10 +560,10 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
     const uint32_t c = c0 + lane;
     const uint32_t v = c < nc ? hist[c] : 0u;
     const uint32_t inc = wave_incl_scan(v);
-    if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = off + carry + inc - v; }
+    if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = (uint16_t)(carry + inc - v); }
     carry += (uint32_t)__shfl((int)inc, 63, 64);
   }
-  if (lane == 0) w.cell_off[cbase + nc] = off + n;
+  if (lane == 0) w.cell_off[cbase + nc] = (uint16_t)n;
   wave_sync();
   if (mine) {
     const uint32_t pos = atomicAdd(&hist[cell], 1u);
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
       zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
     }
     // every lane computes the same grid, lane 0 stores it
-    const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
+    const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
     if (lane == 0) w.grid[ru] = G;
     const uint32_t nc = G.nz * G.ny;
     for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
@@ -662,10 +662,10 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
       const uint32_t c = c0 + lane;
       const uint32_t v = c < nc ? hist[c] : 0u;
       const uint32_t inc = wave_incl_scan(v);
-      if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = off + carry + inc - v; }
+      if (c < nc) { hist[c] = carry + inc - v; w.cell_off[cbase + c] = (uint16_t)(carry + inc - v); }
       carry += (uint32_t)__shfl((int)inc, 63, 64);
     }
-    if (lane == 0) w.cell_off[cbase + nc] = off + n;
+    if (lane == 0) w.cell_off[cbase + nc] = (uint16_t)n;
     wave_sync();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -713,10 +713,10 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
     if (n > (uint32_t)kMaxRow) {
       if (tid == 0) {
         atomicOr(&w.flags[F_ERR], ERR_LIMIT);
-        GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, 0u};
+        GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, off};
         w.grid[ru] = G;
-        w.cell_off[cbase] = off;
-        w.cell_off[cbase + 1] = off;
+        w.cell_off[cbase] = 0;
+        w.cell_off[cbase + 1] = 0;
       }
       // every per-position array still gets a defined entry (its own position
       // in the grid copy), so later kernels stay in bounds until the error is
@@ -846,7 +846,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
         zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
       }
-      const GridParams G = make_grid(n, cbase, ymin, ymax, zmin, zmax);
+      const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
       s_gp = G;
       w.grid[ru] = G;
     }
@@ -871,10 +871,10 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
       const uint32_t v = c < nc ? s_hist[c] : 0u;
       uint32_t tot;
       const uint32_t ex = block_excl_scan(v, &tot) + carry;
-      if (c < nc) { s_hist[c] = ex; w.cell_off[cbase + c] = off + ex; }
+      if (c < nc) { s_hist[c] = ex; w.cell_off[cbase + c] = (uint16_t)ex; }
       carry += tot;
     }
-    if (tid == 0) w.cell_off[cbase + nc] = off + n;
+    if (tid == 0) w.cell_off[cbase + nc] = (uint16_t)n;
     __syncthreads();
     if (fast) {
   #pragma unroll
@@ -1144,10 +1144,10 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   #pragma unroll
       for (int j = 0; j < kC; ++j) {
         const uint32_t i = gt + kG * (uint32_t)j;
-        const uint32_t a = w.cell_off[Gd.cell_base + (i <= ncd ? i : 0u)];
-        const uint32_t b = w.cell_off[Gu.cell_base + (i <= ncu ? i : 0u)];
-        scd[i <= ncd ? i : kSpareC] = (uint16_t)(a - offd);
-        scu[i <= ncu ? i : kSpareC] = (uint16_t)(b - offu);
+        const uint16_t a = w.cell_off[Gd.cell_base + (i <= ncd ? i : 0u)];
+        const uint16_t b = w.cell_off[Gu.cell_base + (i <= ncu ? i : 0u)];
+        scd[i <= ncd ? i : kSpareC] = a;
+        scu[i <= ncu ? i : kSpareC] = b;
       }
       if (kG == TB) __syncthreads(); else wave_sync();
     }
@@ -1167,7 +1167,7 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
           find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
                     (const uint16_t*)scu, bu, bd);
       } else {
-        find_pair(w, xi, yi, zi, Gd, w.gbuf, w.cell_off + Gd.cell_base, Gu, w.gbuf,
+        find_pair(w, xi, yi, zi, Gd, w.gbuf + offd, w.cell_off + Gd.cell_base, Gu, w.gbuf + offu,
                   w.cell_off + Gu.cell_base, bu, bd);
       }
       w.up[p] = bu;
@@ -1328,9 +1328,9 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   const uint32_t nzr = b.iz1 - b.iz0 + 1;
   const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
   const uint32_t c0b = c0a + G.ny;
-  const uint32_t ka0 = w.cell_off[c0a + b.iy0], ka1 = w.cell_off[c0a + b.iy1 + 1];
+  const uint32_t ka0 = G.base + w.cell_off[c0a + b.iy0], ka1 = G.base + w.cell_off[c0a + b.iy1 + 1];
   uint32_t kb0 = 0, kb1 = 0;
-  if (nzr > 1) { kb0 = w.cell_off[c0b + b.iy0]; kb1 = w.cell_off[c0b + b.iy1 + 1]; }
+  if (nzr > 1) { kb0 = G.base + w.cell_off[c0b + b.iy0]; kb1 = G.base + w.cell_off[c0b + b.iy1 + 1]; }
   // entries of the two ranges as one sequence t = 0 .. na + nb - 1
   const uint32_t na = ka1 - ka0, nt = na + (kb1 - kb0);
   constexpr uint32_t kChunk = 8;
@@ -1347,7 +1347,7 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   }
   for (uint32_t iz = 2; iz < nzr; ++iz) {
     const uint32_t cz = G.cell_base + (b.iz0 + iz) * G.ny;
-    const uint32_t k0 = w.cell_off[cz + b.iy0], k1 = w.cell_off[cz + b.iy1 + 1];
+    const uint32_t k0 = G.base + w.cell_off[cz + b.iy0], k1 = G.base + w.cell_off[cz + b.iy1 + 1];
     for (uint32_t k = k0; k < k1; k += 4) {
       float4 c[4];
 #pragma unroll
