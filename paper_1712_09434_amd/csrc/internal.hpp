@@ -40,11 +40,18 @@ enum : uint32_t { ERR_INVALID = 1u, ERR_LIMIT = 2u, ERR_STUCK = 4u };
 
 // Per-(event, sector, row) search grid: cells of a uniform 2-D (z, y) grid
 // over the row's bounding box; cell (iz, iy) = cell_base + iz * ny + iy.
-struct alignas(32) GridParams {
+struct alignas(16) GridParams {
   uint32_t cell_base;
   uint32_t nz, ny;
   float z0, y0, inv_bz, inv_by;
   uint32_t base;        // the row unit's first entry in the grid-ordered arrays
+  uint32_t off_plane;   // 1: some cluster of the row unit has x other than the row's plane
+};
+
+// Grid-ordered record of the tracklet search: (y, z, canonical position).
+struct SearchRec {
+  float y, z;
+  uint32_t pos;
 };
 
 struct EventIn {
@@ -129,6 +136,7 @@ struct Ws {
   uint32_t* cru;        // row unit
   // grid-ordered copy for window searches: (y, z, x, canonical position)
   float4* gbuf;         // [N]
+  SearchRec* grec;      // [N] the same entries without x (the tracklet search's records)
   uint16_t* cell_off;   // [kCellsPerCluster N + 2 RU + 1] (grid_cells + 1 per row unit), relative to the
                         // row unit's first entry (rows hold at most TPCCA_MAX_ROW_CLUSTERS < 2^16)
   // links (canonical positions)

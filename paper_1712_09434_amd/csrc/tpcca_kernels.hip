@@ -485,6 +485,7 @@ __device__ __forceinline__ GridParams make_grid(uint32_t n, uint32_t cbase, uint
   G.inv_bz = dz > 0.0f ? (float)nz / dz : 0.0f;
   G.inv_by = dy > 0.0f ? (float)ny / dy : 0.0f;
   G.base = off;
+  G.off_plane = 0u;
   return G;
 }
 
@@ -547,7 +548,8 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
     zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
   }
   // grid parameters: every lane computes the same values, lane 0 stores them
-  const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+  GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+  G.off_plane = __ballot(mine && x != w.row_x[ru % w.R]) ? 1u : 0u;
   if (lane == 0) w.grid[ru] = G;
   const uint32_t nc = G.nz * G.ny;
   for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
@@ -568,6 +570,7 @@ __global__ __launch_bounds__(TB) void k_rows_tiny(Ws w) {
   if (mine) {
     const uint32_t pos = atomicAdd(&hist[cell], 1u);
     w.gbuf[off + pos] = make_float4(y, z, x, __uint_as_float(off + lane));
+    w.grec[off + pos] = SearchRec{y, z, off + lane};
   }
 }
 
@@ -627,6 +630,8 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
     }
     float px[4], py[4], pz[4];
     float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+    const float xr = w.row_x[ru % w.R];
+    bool offp = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t i = 4u * lane + k;
@@ -637,6 +642,7 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
         w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
         w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
         ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+        offp = offp || v.x != xr;
       }
     }
 #pragma unroll
@@ -645,7 +651,8 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
       zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
     }
     // every lane computes the same grid, lane 0 stores it
-    const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+    GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+    G.off_plane = __ballot(offp) ? 1u : 0u;
     if (lane == 0) w.grid[ru] = G;
     const uint32_t nc = G.nz * G.ny;
     for (uint32_t c = lane; c <= nc; c += 64) hist[c] = 0u;
@@ -673,6 +680,7 @@ __global__ __launch_bounds__(TB) void k_rows_wave(Ws w) {
       if (i < n) {
         const uint32_t pos = atomicAdd(&hist[cell[k]], 1u);
         w.gbuf[off + pos] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
+        w.grec[off + pos] = SearchRec{py[k], pz[k], off + i};
       }
     }
   };
@@ -700,6 +708,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
   // slots (16 bit) during the sort, then the cell histogram
   __shared__ uint32_t s_aux[(kCells + 1) > kIds / 2 ? (kCells + 1) : kIds / 2];
   __shared__ float s_red[4][TB / 64];
+  __shared__ uint32_t s_off[TB / 64];
   __shared__ GridParams s_gp;
   uint16_t* s_slot = (uint16_t*)s_aux;
   uint32_t* s_hist = s_aux;
@@ -713,7 +722,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
     if (n > (uint32_t)kMaxRow) {
       if (tid == 0) {
         atomicOr(&w.flags[F_ERR], ERR_LIMIT);
-        GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, off};
+        GridParams G{cbase, 1u, 1u, 0.f, 0.f, 0.f, 0.f, off, 1u};
         w.grid[ru] = G;
         w.cell_off[cbase] = 0;
         w.cell_off[cbase + 1] = 0;
@@ -726,6 +735,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         w.cx[off + k] = nan; w.cy[off + k] = nan; w.cz[off + k] = nan;
         w.cid[off + k] = 0u; w.cru[off + k] = (uint32_t)ru;
         w.gbuf[off + k] = make_float4(nan, nan, nan, __uint_as_float(off + k));
+        w.grec[off + k] = SearchRec{nan, nan, off + k};
       }
       return;
     }
@@ -739,6 +749,8 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
     uint32_t K[4], V[4];
     float px[4], py[4], pz[4];
     float ymin = INFINITY, ymax = -INFINITY, zmin = INFINITY, zmax = -INFINITY;
+    const float xr = w.row_x[ru % w.R];
+    bool offp = false;
     if (fast) {
   #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -798,6 +810,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
           w.cx[off + i] = v.x; w.cy[off + i] = v.y; w.cz[off + i] = v.z;
           w.cid[off + i] = K[k]; w.cru[off + i] = (uint32_t)ru;
           ymin = fminf(ymin, v.y); ymax = fmaxf(ymax, v.y); zmin = fminf(zmin, v.z); zmax = fmaxf(zmax, v.z);
+          offp = offp || v.x != xr;
         }
       }
     } else {
@@ -830,6 +843,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         w.cx[off + k] = x; w.cy[off + k] = y; w.cz[off + k] = z;
         w.cid[off + k] = s_ids[k]; w.cru[off + k] = (uint32_t)ru;
         ymin = fminf(ymin, y); ymax = fmaxf(ymax, y); zmin = fminf(zmin, z); zmax = fmaxf(zmax, z);
+        offp = offp || x != xr;
       }
     }
   #pragma unroll
@@ -837,16 +851,21 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
       ymin = fminf(ymin, __shfl_xor(ymin, d, 64)); ymax = fmaxf(ymax, __shfl_xor(ymax, d, 64));
       zmin = fminf(zmin, __shfl_xor(zmin, d, 64)); zmax = fmaxf(zmax, __shfl_xor(zmax, d, 64));
     }
+    const bool offw = __ballot(offp) != 0ull;
     if (lane_id() == 0) {
       s_red[0][tid >> 6] = ymin; s_red[1][tid >> 6] = ymax; s_red[2][tid >> 6] = zmin; s_red[3][tid >> 6] = zmax;
+      s_off[tid >> 6] = offw ? 1u : 0u;
     }
     __syncthreads();
     if (tid == 0) {
+      uint32_t o = s_off[0];
       for (int i = 1; i < TB / 64; ++i) {
         ymin = fminf(ymin, s_red[0][i]); ymax = fmaxf(ymax, s_red[1][i]);
         zmin = fminf(zmin, s_red[2][i]); zmax = fmaxf(zmax, s_red[3][i]);
+        o |= s_off[i];
       }
-      const GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+      GridParams G = make_grid(n, cbase, off, ymin, ymax, zmin, zmax);
+      G.off_plane = o;
       s_gp = G;
       w.grid[ru] = G;
     }
@@ -883,6 +902,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         if (i < n) {
           const uint32_t slot = atomicAdd(&s_hist[cell_of(G, py[k], pz[k])], 1u);
           w.gbuf[off + slot] = make_float4(py[k], pz[k], px[k], __uint_as_float(off + i));
+          w.grec[off + slot] = SearchRec{py[k], pz[k], off + i};
         }
       }
     } else {
@@ -890,6 +910,7 @@ __global__ __launch_bounds__(TB) void k_rows(Ws w) {
         const float x = w.cx[off + k], y = w.cy[off + k], z = w.cz[off + k];
         const uint32_t slot = atomicAdd(&s_hist[cell_of(G, y, z)], 1u);
         w.gbuf[off + slot] = make_float4(y, z, x, __uint_as_float(off + k));
+        w.grec[off + slot] = SearchRec{y, z, off + k};
       }
     }
   };
@@ -1295,14 +1316,17 @@ __global__ __launch_bounds__(TB) void k_start_tap(Ws w) {
 }
 
 // ----------------------------------------------------------- a5: tracklets
-struct Found { int32_t pos; float x, y, z; };
+struct Found { int32_t pos; uint32_t slot; float y, z; };
 
 // Closest cluster of row unit ru to the predicted (y, z):
 // d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
-// The cell ranges of the box's first two z rows are read together, then
-// their entries in chunks of eight loads issued before any is tested, so a
-// step waits for memory twice rather than once per candidate.  The result
-// does not depend on the order the candidates are visited in.
+// The candidates are the 12-byte (y, z, canonical position) search records;
+// the winner's grid slot comes back too (its x is read from the full record
+// only in row units with clusters off the row plane).  The cell ranges of
+// the box's first two z rows are read together, then their entries in
+// chunks of eight loads issued before any is tested, so a step waits for
+// memory twice rather than once per candidate.  The result does not depend
+// on the order the candidates are visited in.
 __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, const float p[5],
                                             const float C[15]) {
   const float sy2 = C[0] + w.m.vy, sz2 = C[5] + w.m.vz;
@@ -1317,13 +1341,13 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   // (bd, pos) starts at (CUT, INT32_MAX): the first candidate with d <= CUT
   // replaces it, later ones must beat the best so far, so no separate test
   // of the cut (a NaN distance fails every comparison)
-  Found best{INT32_MAX, 0.f, 0.f, 0.f};
+  Found best{INT32_MAX, 0u, 0.f, 0.f};
   float bd = CUT;
-  auto consider = [&](const float4& c) {
-    const float dY = c.x - p[0], dZ = c.y - p[1];
+  auto consider = [&](const SearchRec& c, uint32_t k) {
+    const float dY = c.y - p[0], dZ = c.z - p[1];
     const float d = fmaf(dZ * dZ, isz, (dY * dY) * isy);
-    const int32_t pos = (int32_t)__float_as_uint(c.w);
-    if (d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.z, c.x, c.y}; bd = d; }
+    const int32_t pos = (int32_t)c.pos;
+    if (d < bd || (d == bd && pos < best.pos)) { best = Found{pos, k, c.y, c.z}; bd = d; }
   };
   const uint32_t nzr = b.iz1 - b.iz0 + 1;
   const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
@@ -1335,27 +1359,29 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   const uint32_t na = ka1 - ka0, nt = na + (kb1 - kb0);
   constexpr uint32_t kChunk = 8;
   for (uint32_t t0 = 0; t0 < nt; t0 += kChunk) {
-    float4 c[kChunk];
+    SearchRec c[kChunk];
+    uint32_t kk[kChunk];
 #pragma unroll
     for (uint32_t j = 0; j < kChunk; ++j) {
       const uint32_t t = t0 + j;
-      if (t < nt) c[j] = w.gbuf[t < na ? ka0 + t : kb0 + (t - na)];
+      kk[j] = t < na ? ka0 + t : kb0 + (t - na);
+      if (t < nt) c[j] = w.grec[kk[j]];
     }
 #pragma unroll
     for (uint32_t j = 0; j < kChunk; ++j)
-      if (t0 + j < nt) consider(c[j]);
+      if (t0 + j < nt) consider(c[j], kk[j]);
   }
   for (uint32_t iz = 2; iz < nzr; ++iz) {
     const uint32_t cz = G.cell_base + (b.iz0 + iz) * G.ny;
     const uint32_t k0 = G.base + w.cell_off[cz + b.iy0], k1 = G.base + w.cell_off[cz + b.iy1 + 1];
     for (uint32_t k = k0; k < k1; k += 4) {
-      float4 c[4];
+      SearchRec c[4];
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if (k + j < k1) c[j] = w.gbuf[k + j];
+        if (k + j < k1) c[j] = w.grec[k + j];
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if (k + j < k1) consider(c[j]);
+        if (k + j < k1) consider(c[j], k + j);
     }
   }
   if (best.pos == INT32_MAX) best.pos = -1;
@@ -1542,9 +1568,11 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
       if (go) {
         const Found h = search_row(w, G, p, C);
         if (h.pos >= 0) {
-          if (h.x != X) {
-            go = transport(p, C, X, h.x, w.m);
-            if (go) xc = h.x;
+          float hx = X;
+          if (G.off_plane) hx = w.gbuf[h.slot].z;
+          if (hx != X) {
+            go = transport(p, C, X, hx, w.m);
+            if (go) xc = hx;
           }
           if (go) {
             my = h.y; mz = h.z;

@@ -173,7 +173,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_tmp = L.take<float4>(N);
   size_t o_cx = L.take<float>(N), o_cy = L.take<float>(N), o_cz = L.take<float>(N);
   size_t o_cid = L.take<uint32_t>(N), o_cru = L.take<uint32_t>(N);
-  size_t o_gbuf = L.take<float4>(N);
+  size_t o_gbuf = L.take<float4>(N), o_grec = L.take<SearchRec>(N);
   size_t o_coff = L.take<uint16_t>(kCellsPerCluster * N + 2 * RU + 1);
   size_t o_up = L.take<int32_t>(N), o_dn = L.take<int32_t>(N), o_cup = L.take<int32_t>(N), o_cdn = L.take<int32_t>(N);
   size_t o_cpk = L.take<float4>(N);
@@ -205,7 +205,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.tmp4 = (float4*)(base + o_tmp);
     w.cx = (float*)(base + o_cx); w.cy = (float*)(base + o_cy); w.cz = (float*)(base + o_cz);
     w.cid = (uint32_t*)(base + o_cid); w.cru = (uint32_t*)(base + o_cru);
-    w.gbuf = (float4*)(base + o_gbuf); w.cell_off = (uint16_t*)(base + o_coff);
+    w.gbuf = (float4*)(base + o_gbuf); w.grec = (SearchRec*)(base + o_grec); w.cell_off = (uint16_t*)(base + o_coff);
     w.up = (int32_t*)(base + o_up); w.dn = (int32_t*)(base + o_dn);
     w.cup = (int32_t*)(base + o_cup); w.cdn = (int32_t*)(base + o_cdn);
     w.cpk = (float4*)(base + o_cpk);
