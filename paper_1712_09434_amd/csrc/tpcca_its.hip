@@ -19,11 +19,11 @@
 // gather of the events' clusters with their global positions and per-stave
 // counts; stave offsets; stave records (global x, y, radius, z for the pair
 // tests; local y, z, id for the cluster search) and the ordered layer-0
-// list; pair histogram per event (thread per layer-0 cluster over the three
-// layer-1 staves around its azimuth, loads eight records at a time, the
-// histogram privatised in LDS), peak, fixed-point mean; tracklet candidates
-// (best of each layer-0 cluster in registers, best of each layer-1 cluster
-// by a 64-bit atomic minimum of (score bits, id)); mutual pairs compacted in
+// list; pair histogram per event (eight lanes per layer-0 cluster share the
+// records of the three layer-1 staves around its azimuth, each loading eight
+// at a time; the histogram privatised in LDS), peak, fixed-point mean;
+// tracklet candidates (best of each layer-0 cluster by a group minimum, best
+// of each layer-1 cluster by a 64-bit atomic minimum of (score bits, id)); mutual pairs compacted in
 // id order; following and inward fit (eight lanes per tracklet sharing the
 // cluster search); vertex fit (one workgroup per event, fixed-order FP64
 // reductions).  Every event's results equal those of a call on that event
@@ -192,7 +192,33 @@ __device__ __forceinline__ int wedge_of(const ItsWs& w, int l, int lf, int kf, f
   return k;
 }
 
-// One layer-0 cluster per thread, in id order.
+// Lanes per layer-0 cluster in the pair kernels and per tracklet in the
+// following: the records a cluster or tracklet visits are split over them.
+constexpr int kGrp = 8;
+
+__device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
+#pragma unroll
+  for (int d = 1; d < kGrp; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, kGrp);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kGrp);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Sum over the group (integers: any order gives the same result).
+__device__ __forceinline__ unsigned long long grp_sum(unsigned long long v) {
+#pragma unroll
+  for (int d = 1; d < kGrp; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, kGrp);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kGrp);
+    v += ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+// One layer-0 cluster per group of kGrp lanes, in id order.
 struct L0 {
   bool ok;
   float X, Y, R, z;
@@ -212,26 +238,35 @@ __device__ __forceinline__ L0 l0_cluster(const ItsWs& w, int64_t t) {
 
 // Visits every layer-1 cluster record of the event's three staves around a
 // layer-0 cluster's azimuth (every pair within a window narrower than a
-// stave), the records of a chunk loaded together: f(record, list position).
+// stave), lane gl of the group taking every kGrp-th record, the records of
+// a chunk loaded together: f(record, list position).
 constexpr int kChunk = 8;
 template <class F>
-__device__ __forceinline__ void for_l1(const ItsWs& w, const L0& c, F f) {
+__device__ __forceinline__ void for_l1(const ItsWs& w, const L0& c, int gl, F f) {
   const int kc = wedge_of(w, 1, 0, c.k, c.X, c.Y);
   const int ns = w.ns[1];
   for (int d = -1; d <= 1; ++d) {
     const int k = (kc + d + ns) % ns;
     if (d != 0 && (k == kc || (d == 1 && k == (kc + ns - 1) % ns))) continue;   // (fewer than 3 staves)
     const uint32_t a = w.scnt[sidx(c.e, 1, k)], b = w.scnt[sidx(c.e, 1, k) + 1];
-    for (uint32_t j0 = a; j0 < b; j0 += kChunk) {
+    for (uint32_t j0 = a + (uint32_t)gl; j0 < b; j0 += kChunk * kGrp) {
       float4 r[kChunk];
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) r[u] = w.sA[j0 + u < b ? j0 + u : a];
+      for (int u = 0; u < kChunk; ++u) {
+        const uint32_t j = j0 + (uint32_t)(u * kGrp);
+        r[u] = w.sA[j < b ? j : a];
+      }
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u)
-        if (j0 + u < b) f(r[u], j0 + u);
+      for (int u = 0; u < kChunk; ++u) {
+        const uint32_t j = j0 + (uint32_t)(u * kGrp);
+        if (j < b) f(r[u], j);
+      }
     }
   }
 }
+
+// Layer-0 clusters per workgroup of the pair kernels.
+constexpr int kPerWg = TB / kGrp;
 
 __device__ __forceinline__ bool spd_pair(const L0& a, const float4& b, float sphi, float& cross) {
   cross = a.X * b.y - a.Y * b.x;
@@ -255,18 +290,19 @@ __device__ __forceinline__ int bin_of(const ItsWs& w, float zv) {
 // global histogram.
 __global__ __launch_bounds__(TB) void k_its_vpairs(ItsWs w) {
   __shared__ uint32_t h[kBins];
-  __shared__ int e0;
+  __shared__ unsigned long long s_n;
+  const int64_t t0 = (int64_t)blockIdx.x * kPerWg;
+  const L0 f = l0_cluster(w, t0);
+  if (!f.ok) return;   // (workgroup-uniform: no layer-0 cluster from here on)
+  const int e0 = f.e;
   for (int bb = threadIdx.x; bb < w.nbins; bb += TB) h[bb] = 0u;
-  const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-  const L0 c = l0_cluster(w, t);
-  if (threadIdx.x == 0) {
-    const L0 f = l0_cluster(w, (int64_t)blockIdx.x * TB);
-    e0 = f.ok ? f.e : -1;
-  }
+  if (threadIdx.x == 0) s_n = 0ull;
+  const int gl = threadIdx.x % kGrp;
+  const L0 c = l0_cluster(w, t0 + threadIdx.x / kGrp);
   __syncthreads();
-  uint32_t cnt = 0;
-  if (c.ok)
-    for_l1(w, c, [&](const float4& b, uint32_t) {
+  if (c.ok) {
+    unsigned long long cnt = 0ull;
+    for_l1(w, c, gl, [&](const float4& b, uint32_t) {
       float cr;
       if (!spd_pair(c, b, w.P.vtx_sin_phi, cr)) return;
       const int bin = bin_of(w, zline(c, b));
@@ -275,11 +311,17 @@ __global__ __launch_bounds__(TB) void k_its_vpairs(ItsWs w) {
       else atomicAdd(&w.hist[(int64_t)c.e * w.nbins + bin], 1u);
       ++cnt;
     });
-  if (cnt) atomicAdd(&w.vsum[c.e * 4 + 0], (unsigned long long)cnt);
+    cnt = grp_sum(cnt);
+    // the pair count of the workgroup's first event is summed in LDS first
+    if (gl == 0 && cnt) {
+      if (c.e == e0) atomicAdd(&s_n, cnt);
+      else atomicAdd(&w.vsum[c.e * 4 + 0], cnt);
+    }
+  }
   __syncthreads();
-  if (e0 >= 0)
-    for (int bb = threadIdx.x; bb < w.nbins; bb += TB)
-      if (h[bb]) atomicAdd(&w.hist[(int64_t)e0 * w.nbins + bb], h[bb]);
+  for (int bb = threadIdx.x; bb < w.nbins; bb += TB)
+    if (h[bb]) atomicAdd(&w.hist[(int64_t)e0 * w.nbins + bb], h[bb]);
+  if (threadIdx.x == 0 && s_n) atomicAdd(&w.vsum[e0 * 4 + 0], s_n);
 }
 
 // fullest bin of each event (ties: lower), one workgroup per event
@@ -303,24 +345,47 @@ __global__ __launch_bounds__(TB) void k_its_vpeak(ItsWs w) {
   if (threadIdx.x == 0) w.vpeak[e] = s[0] ? (int32_t)(0xFFFFFFFFu - (uint32_t)(s[0] & 0xFFFFFFFFull)) : -1;
 }
 
+// Pairs in the peak's three bins: count and fixed-point sum of their z, the
+// workgroup's first event summed in LDS first (one global atomic each per
+// workgroup; the event counters of a batch share a few cache lines).
 __global__ __launch_bounds__(TB) void k_its_vsum(ItsWs w) {
-  const L0 c = l0_cluster(w, (int64_t)blockIdx.x * TB + threadIdx.x);
-  if (!c.ok) return;
-  const int pk = w.vpeak[c.e];
-  if (pk < 0) return;
-  unsigned long long cnt = 0ull, q = 0ull;
-  for_l1(w, c, [&](const float4& b, uint32_t) {
-    float cr;
-    if (!spd_pair(c, b, w.P.vtx_sin_phi, cr)) return;
-    const float zv = zline(c, b);
-    const int bin = bin_of(w, zv);
-    if (bin < 0 || bin < pk - 1 || bin > pk + 1) return;
-    q += (unsigned long long)(long long)rintf(zv * 65536.0f);   // (two's complement sums)
-    ++cnt;
-  });
-  if (cnt) {
-    atomicAdd(&w.vsum[c.e * 4 + 1], cnt);
-    atomicAdd(&w.vsum[c.e * 4 + 2], q);
+  __shared__ unsigned long long s_n, s_q;
+  const int64_t t0 = (int64_t)blockIdx.x * kPerWg;
+  const L0 f = l0_cluster(w, t0);
+  if (!f.ok) return;   // (workgroup-uniform)
+  const int e0 = f.e;
+  if (threadIdx.x == 0) { s_n = 0ull; s_q = 0ull; }
+  __syncthreads();
+  const L0 c = l0_cluster(w, t0 + threadIdx.x / kGrp);
+  const int gl = threadIdx.x % kGrp;
+  const int pk = c.ok ? w.vpeak[c.e] : -1;
+  if (pk >= 0) {   // (group-uniform)
+    unsigned long long cnt = 0ull, q = 0ull;
+    for_l1(w, c, gl, [&](const float4& b, uint32_t) {
+      float cr;
+      if (!spd_pair(c, b, w.P.vtx_sin_phi, cr)) return;
+      const float zv = zline(c, b);
+      const int bin = bin_of(w, zv);
+      if (bin < 0 || bin < pk - 1 || bin > pk + 1) return;
+      q += (unsigned long long)(long long)rintf(zv * 65536.0f);   // (two's complement sums)
+      ++cnt;
+    });
+    cnt = grp_sum(cnt);
+    q = grp_sum(q);
+    if (gl == 0 && cnt) {
+      if (c.e == e0) {
+        atomicAdd(&s_n, cnt);
+        atomicAdd(&s_q, q);
+      } else {
+        atomicAdd(&w.vsum[c.e * 4 + 1], cnt);
+        atomicAdd(&w.vsum[c.e * 4 + 2], q);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_n) {
+    atomicAdd(&w.vsum[e0 * 4 + 1], s_n);
+    atomicAdd(&w.vsum[e0 * 4 + 2], s_q);
   }
 }
 
@@ -339,13 +404,14 @@ __global__ __launch_bounds__(TB) void k_its_vfinal(ItsWs w) {
 }
 
 __global__ __launch_bounds__(TB) void k_its_tl(ItsWs w) {
-  const L0 c = l0_cluster(w, (int64_t)blockIdx.x * TB + threadIdx.x);
-  if (!c.ok) return;
+  const L0 c = l0_cluster(w, (int64_t)blockIdx.x * kPerWg + threadIdx.x / kGrp);
+  const int gl = threadIdx.x % kGrp;
+  if (!c.ok) return;   // (group-uniform)
   const float vz = w.vzd[c.e * 2];
   const float itp2 = 1.0f / (w.P.trk_sin_phi * w.P.trk_sin_phi);
   const float itt2 = 1.0f / (w.P.trk_dtgl * w.P.trk_dtgl);
   unsigned long long best = ~0ull;
-  for_l1(w, c, [&](const float4& b, uint32_t pos) {
+  for_l1(w, c, gl, [&](const float4& b, uint32_t pos) {
     float cr;
     if (!spd_pair(c, b, w.P.trk_sin_phi, cr)) return;
     const float dt = (b.w - vz) / b.z - (c.z - vz) / c.R;
@@ -357,7 +423,8 @@ __global__ __launch_bounds__(TB) void k_its_tl(ItsWs w) {
     best = min(best, hi | j);
     atomicMin(&w.best1[j], hi | c.id);
   });
-  w.best0[c.id] = best;
+  best = grp_min(best);
+  if (gl == 0) w.best0[c.id] = best;
 }
 
 __global__ __launch_bounds__(TB) void k_its_tlflag(ItsWs w) {
@@ -480,18 +547,6 @@ __device__ __forceinline__ void frame_turn(const ItsTab* tb, int lt, int kt, int
 // lane of the group evaluates the same state (the same expressions, so the
 // same values), the cluster search of a layer is split over the lanes and
 // its result is the group minimum of (chi2 bits, id); lane 0 writes.
-constexpr int kGrp = 8;
-
-__device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
-#pragma unroll
-  for (int d = 1; d < kGrp; d <<= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, kGrp);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kGrp);
-    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-    v = o < v ? o : v;
-  }
-  return v;
-}
 
 __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
   const int64_t a = (int64_t)blockIdx.x * (64 / kGrp) + threadIdx.x / kGrp;
@@ -666,11 +721,88 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
   }
 }
 
-// Vertex fit: one workgroup per event; per solve, each thread sums its
-// tracks (t = tid, tid + TB, ...) and the partial sums are added by a fixed
-// tree, so the result does not depend on timing.
-__global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
-  __shared__ double s[9][TB];
+// Vertex fit: one 512-thread workgroup per event.  Thread tid owns tracks
+// tid + k * TBV (k < kVReg) and keeps their lines (point, direction,
+// variance) and weights in registers for all solves; tracks past kVReg TBV
+// are recomputed from memory in each pass.  Per solve each thread sums its
+// tracks in order, the waves sum their lanes by a fixed butterfly and thread
+// 0 adds the waves in order, so the result does not depend on timing.
+constexpr int TBV = 512;
+constexpr int kVReg = 4;
+
+struct VLine { double P[3], d[3], s2; };
+
+__device__ __forceinline__ VLine its_line(const ItsTab* tb, const tpcca_its_tracks& o, int64_t t) {
+  VLine L;
+  const int k = o.in_stave[t];
+  const double ca = tb->ca[0][k], sa = tb->sa[0][k];
+  const double yy = o.in_p[t * 5 + 0], zz = o.in_p[t * 5 + 1];
+  const double sn = o.in_p[t * 5 + 2], tt = o.in_p[t * 5 + 3];
+  const double cc = sqrt(1.0 - sn * sn), nn = sqrt(1.0 + tt * tt);
+  L.P[0] = -(yy * sa); L.P[1] = yy * ca; L.P[2] = zz;
+  L.d[0] = (cc * ca - sn * sa) / nn; L.d[1] = (cc * sa + sn * ca) / nn; L.d[2] = tt / nn;
+  L.s2 = 0.5 * ((double)o.in_cov[t * 15 + 0] + (double)o.in_cov[t * 15 + 5]);
+  return L;
+}
+
+// A[0..5] (xx, xy, xz, yy, yz, zz) and b[0..2] += the track's weighted terms
+__device__ __forceinline__ void vfit_acc(const VLine& L, double wgt, double acc[9]) {
+  const double f = wgt / L.s2;
+  double M[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c2 = 0; c2 < 3; ++c2) M[r][c2] = (r == c2 ? 1.0 : 0.0) - L.d[r] * L.d[c2];
+  acc[0] += f * M[0][0]; acc[1] += f * M[0][1]; acc[2] += f * M[0][2];
+  acc[3] += f * M[1][1]; acc[4] += f * M[1][2]; acc[5] += f * M[2][2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) acc[6 + r] += f * (M[r][0] * L.P[0] + M[r][1] * L.P[1] + M[r][2] * L.P[2]);
+}
+
+__device__ __forceinline__ double bisquare(const VLine& L, const double V[3], double c) {
+  const double u0 = V[0] - L.P[0], u1 = V[1] - L.P[1], u2 = V[2] - L.P[2];
+  const double pr = u0 * L.d[0] + u1 * L.d[1] + u2 * L.d[2];
+  const double e0 = u0 - pr * L.d[0], e1 = u1 - pr * L.d[1], e2 = u2 - pr * L.d[2];
+  const double D = sqrt((e0 * e0 + e1 * e1 + e2 * e2) / L.s2) / c;
+  return D < 1.0 ? (1.0 - D * D) * (1.0 - D * D) : 0.0;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(u & 0xFFFFFFFFull), m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(u >> 32), m, 64);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sums of n values over the workgroup, returned to every thread (s: LDS of
+// n * TBV / 64 doubles, out: LDS of n doubles).
+template <int N>
+__device__ __forceinline__ void vfit_sum(double v[N], double* s, double* out) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1)
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += shfl_xor_d(v[j], m);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j * (TBV / 64) + wv] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double a = 0.0;
+      for (int q = 0; q < TBV / 64; ++q) a += s[j * (TBV / 64) + q];
+      out[j] = a;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = out[j];
+  __syncthreads();   // (s and out are reused by the next sum)
+}
+
+__global__ __launch_bounds__(TBV) void k_its_vfit(ItsWs w) {
+  __shared__ double s[9 * (TBV / 64)];
+  __shared__ double out[9];
   __shared__ double V[3];
   __shared__ int good;
   const int e = blockIdx.x;
@@ -679,55 +811,38 @@ __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
   const int64_t T = std::min<int64_t>((int64_t)(w.toff[e + 1] - w.toff[e]), o.cap);
   double* vw = w.vw + w.toff[e];
   const ItsTab* tb = w.tab;
-  int c = 0;
-  for (int64_t t = tid; t < T; t += TB) {
-    const bool use = o.ok[t] && o.in_ok[t];
-    vw[t] = use ? 1.0 : 0.0;
-    c += use ? 1 : 0;
+  VLine L[kVReg];
+  double wr[kVReg];
+  bool use[kVReg];
+  double c1[1] = {0.0};
+#pragma unroll
+  for (int k = 0; k < kVReg; ++k) {
+    const int64_t t = tid + (int64_t)k * TBV;
+    use[k] = t < T && o.ok[t] && o.in_ok[t];
+    if (use[k]) L[k] = its_line(tb, o, t);
+    wr[k] = use[k] ? 1.0 : 0.0;
+    c1[0] += use[k] ? 1.0 : 0.0;
   }
-  s[0][tid] = (double)c;
-  __syncthreads();
-  for (int d = TB / 2; d > 0; d >>= 1) {
-    if (tid < d) s[0][tid] += s[0][tid + d];
-    __syncthreads();
+  for (int64_t t = tid + (int64_t)kVReg * TBV; t < T; t += TBV) {
+    const bool u = o.ok[t] && o.in_ok[t];
+    vw[t] = u ? 1.0 : 0.0;
+    c1[0] += u ? 1.0 : 0.0;
   }
-  if (tid == 0) { good = s[0][0] >= 2.0 ? 1 : 0; V[0] = V[1] = V[2] = 0.0; }
+  vfit_sum<1>(c1, s, out);
+  if (tid == 0) { good = c1[0] >= 2.0 ? 1 : 0; V[0] = V[1] = V[2] = 0.0; }
   __syncthreads();
   double nused = 0.0, sumw = 0.0;
-  auto line = [&](int64_t t, double Pp[3], double d[3], double& s2) {
-    const int k = o.in_stave[t];
-    const double ca = tb->ca[0][k], sa = tb->sa[0][k];
-    const double yy = o.in_p[t * 5 + 0], zz = o.in_p[t * 5 + 1];
-    const double sn = o.in_p[t * 5 + 2], tt = o.in_p[t * 5 + 3];
-    const double cc = sqrt(1.0 - sn * sn), nn = sqrt(1.0 + tt * tt);
-    Pp[0] = -(yy * sa); Pp[1] = yy * ca; Pp[2] = zz;
-    d[0] = (cc * ca - sn * sa) / nn; d[1] = (cc * sa + sn * ca) / nn; d[2] = tt / nn;
-    s2 = 0.5 * ((double)o.in_cov[t * 15 + 0] + (double)o.in_cov[t * 15 + 5]);
-  };
   for (int it = 0; it < w.P.fit_iters && good; ++it) {
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // A (xx, xy, xz, yy, yz, zz) and b
-    for (int64_t t = tid; t < T; t += TB) {
-      if (!(o.ok[t] && o.in_ok[t])) continue;
-      double Pp[3], d[3], s2;
-      line(t, Pp, d, s2);
-      const double f = vw[t] / s2;
-      double M[3][3];
-      for (int r = 0; r < 3; ++r)
-        for (int c2 = 0; c2 < 3; ++c2) M[r][c2] = (r == c2 ? 1.0 : 0.0) - d[r] * d[c2];
-      acc[0] += f * M[0][0]; acc[1] += f * M[0][1]; acc[2] += f * M[0][2];
-      acc[3] += f * M[1][1]; acc[4] += f * M[1][2]; acc[5] += f * M[2][2];
-      for (int r = 0; r < 3; ++r) acc[6 + r] += f * (M[r][0] * Pp[0] + M[r][1] * Pp[1] + M[r][2] * Pp[2]);
-    }
-    for (int j = 0; j < 9; ++j) s[j][tid] = acc[j];
-    __syncthreads();
-    for (int d = TB / 2; d > 0; d >>= 1) {
-      if (tid < d)
-        for (int j = 0; j < 9; ++j) s[j][tid] += s[j][tid + d];
-      __syncthreads();
-    }
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kVReg; ++k)
+      if (use[k]) vfit_acc(L[k], wr[k], acc);
+    for (int64_t t = tid + (int64_t)kVReg * TBV; t < T; t += TBV)
+      if (o.ok[t] && o.in_ok[t]) vfit_acc(its_line(tb, o, t), vw[t], acc);
+    vfit_sum<9>(acc, s, out);
     if (tid == 0) {
-      const double a00 = s[0][0], a01 = s[1][0], a02 = s[2][0], a11 = s[3][0], a12 = s[4][0], a22 = s[5][0];
-      const double b0 = s[6][0], b1 = s[7][0], b2 = s[8][0];
+      const double a00 = acc[0], a01 = acc[1], a02 = acc[2], a11 = acc[3], a12 = acc[4], a22 = acc[5];
+      const double b0 = acc[6], b1 = acc[7], b2 = acc[8];
       const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
       const double det = a00 * c00 + a01 * c01 + a02 * c02;
       if (!(fabs(det) > 0.0)) {
@@ -741,30 +856,25 @@ __global__ __launch_bounds__(TB) void k_its_vfit(ItsWs w) {
     }
     __syncthreads();
     if (!good) break;
-    double nu = 0.0, sw = 0.0;
-    for (int64_t t = tid; t < T; t += TB) {
-      if (!(o.ok[t] && o.in_ok[t])) continue;
-      double Pp[3], d[3], s2;
-      line(t, Pp, d, s2);
-      const double u0 = V[0] - Pp[0], u1 = V[1] - Pp[1], u2 = V[2] - Pp[2];
-      const double pr = u0 * d[0] + u1 * d[1] + u2 * d[2];
-      const double e0 = u0 - pr * d[0], e1 = u1 - pr * d[1], e2 = u2 - pr * d[2];
-      const double D = sqrt((e0 * e0 + e1 * e1 + e2 * e2) / s2) / (double)w.P.tukey_c;
-      const double wt = D < 1.0 ? (1.0 - D * D) * (1.0 - D * D) : 0.0;
-      vw[t] = wt;
-      nu += wt > 0.0 ? 1.0 : 0.0;
-      sw += wt;
-    }
-    s[0][tid] = nu;
-    s[1][tid] = sw;
-    __syncthreads();
-    for (int d = TB / 2; d > 0; d >>= 1) {
-      if (tid < d) { s[0][tid] += s[0][tid + d]; s[1][tid] += s[1][tid + d]; }
-      __syncthreads();
-    }
-    nused = s[0][0];
-    sumw = s[1][0];
-    __syncthreads();
+    const double Vl[3] = {V[0], V[1], V[2]};
+    double nw[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kVReg; ++k)
+      if (use[k]) {
+        wr[k] = bisquare(L[k], Vl, (double)w.P.tukey_c);
+        nw[0] += wr[k] > 0.0 ? 1.0 : 0.0;
+        nw[1] += wr[k];
+      }
+    for (int64_t t = tid + (int64_t)kVReg * TBV; t < T; t += TBV)
+      if (o.ok[t] && o.in_ok[t]) {
+        const double wt = bisquare(its_line(tb, o, t), Vl, (double)w.P.tukey_c);
+        vw[t] = wt;
+        nw[0] += wt > 0.0 ? 1.0 : 0.0;
+        nw[1] += wt;
+      }
+    vfit_sum<2>(nw, s, out);
+    nused = nw[0];
+    sumw = nw[1];
   }
   if (tid == 0) {
     double* r = w.vres + e * 8;
@@ -789,11 +899,12 @@ hipError_t run_its(const ItsWs& w, hipStream_t st) {
   if (e != hipSuccess) return e;
   k_its_cursors<<<grid_for(ns), TB, 0, st>>>(w);
   k_its_fill<<<g, TB, 0, st>>>(w);
-  k_its_vpairs<<<g, TB, 0, st>>>(w);
+  const unsigned gg = grid_for(w.n * kGrp);   // (kGrp lanes per layer-0 cluster)
+  k_its_vpairs<<<gg, TB, 0, st>>>(w);
   k_its_vpeak<<<(unsigned)w.E, TB, 0, st>>>(w);
-  k_its_vsum<<<g, TB, 0, st>>>(w);
+  k_its_vsum<<<gg, TB, 0, st>>>(w);
   k_its_vfinal<<<grid_for(w.E), TB, 0, st>>>(w);
-  k_its_tl<<<g, TB, 0, st>>>(w);
+  k_its_tl<<<gg, TB, 0, st>>>(w);
   k_its_tlflag<<<g, TB, 0, st>>>(w);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -801,7 +912,7 @@ hipError_t run_its(const ItsWs& w, hipStream_t st) {
   if (e != hipSuccess) return e;
   k_its_tlcompact<<<grid_for(std::max<int64_t>(w.n, w.E + 1)), TB, 0, st>>>(w);
   k_its_follow<<<(unsigned)std::max<int64_t>((w.n + 64 / kGrp - 1) / (64 / kGrp), 1), 64, 0, st>>>(w);
-  k_its_vfit<<<(unsigned)w.E, TB, 0, st>>>(w);
+  k_its_vfit<<<(unsigned)w.E, TBV, 0, st>>>(w);
   return hipGetLastError();
 }
 
