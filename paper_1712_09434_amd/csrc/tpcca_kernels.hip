@@ -1316,13 +1316,13 @@ __global__ __launch_bounds__(TB) void k_start_tap(Ws w) {
 }
 
 // ----------------------------------------------------------- a5: tracklets
-struct Found { int32_t pos; uint32_t slot; float y, z; };
+struct Found { int32_t pos; float y, z; };
 
 // Closest cluster of row unit ru to the predicted (y, z):
 // d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
-// The candidates are the 12-byte (y, z, canonical position) search records;
-// the winner's grid slot comes back too (its x is read from the full record
-// only in row units with clusters off the row plane).  The cell ranges of
+// The candidates are the 12-byte (y, z, canonical position) search records
+// (the winner's x is read from the canonical arrays only in row units with
+// clusters off the row plane).  The cell ranges of
 // the box's first two z rows are read together, then their entries in
 // chunks of eight loads issued before any is tested, so a step waits for
 // memory twice rather than once per candidate.  The result does not depend
@@ -1341,13 +1341,13 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   // (bd, pos) starts at (CUT, INT32_MAX): the first candidate with d <= CUT
   // replaces it, later ones must beat the best so far, so no separate test
   // of the cut (a NaN distance fails every comparison)
-  Found best{INT32_MAX, 0u, 0.f, 0.f};
+  Found best{INT32_MAX, 0.f, 0.f};
   float bd = CUT;
-  auto consider = [&](const SearchRec& c, uint32_t k) {
+  auto consider = [&](const SearchRec& c) {
     const float dY = c.y - p[0], dZ = c.z - p[1];
     const float d = fmaf(dZ * dZ, isz, (dY * dY) * isy);
     const int32_t pos = (int32_t)c.pos;
-    if (d < bd || (d == bd && pos < best.pos)) { best = Found{pos, k, c.y, c.z}; bd = d; }
+    if (d < bd || (d == bd && pos < best.pos)) { best = Found{pos, c.y, c.z}; bd = d; }
   };
   const uint32_t nzr = b.iz1 - b.iz0 + 1;
   const uint32_t c0a = G.cell_base + b.iz0 * G.ny;
@@ -1360,16 +1360,14 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
   constexpr uint32_t kChunk = 8;
   for (uint32_t t0 = 0; t0 < nt; t0 += kChunk) {
     SearchRec c[kChunk];
-    uint32_t kk[kChunk];
 #pragma unroll
     for (uint32_t j = 0; j < kChunk; ++j) {
       const uint32_t t = t0 + j;
-      kk[j] = t < na ? ka0 + t : kb0 + (t - na);
-      if (t < nt) c[j] = w.grec[kk[j]];
+      if (t < nt) c[j] = w.grec[t < na ? ka0 + t : kb0 + (t - na)];
     }
 #pragma unroll
     for (uint32_t j = 0; j < kChunk; ++j)
-      if (t0 + j < nt) consider(c[j], kk[j]);
+      if (t0 + j < nt) consider(c[j]);
   }
   for (uint32_t iz = 2; iz < nzr; ++iz) {
     const uint32_t cz = G.cell_base + (b.iz0 + iz) * G.ny;
@@ -1381,7 +1379,7 @@ __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, co
         if (k + j < k1) c[j] = w.grec[k + j];
 #pragma unroll
       for (uint32_t j = 0; j < 4; ++j)
-        if (k + j < k1) consider(c[j], k + j);
+        if (k + j < k1) consider(c[j]);
     }
   }
   if (best.pos == INT32_MAX) best.pos = -1;
@@ -1569,7 +1567,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
         const Found h = search_row(w, G, p, C);
         if (h.pos >= 0) {
           float hx = X;
-          if (G.off_plane) hx = w.gbuf[h.slot].z;
+          if (G.off_plane) hx = w.cx[h.pos];
           if (hx != X) {
             go = transport(p, C, X, hx, w.m);
             if (go) xc = hx;
