@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--timeframe-only", action="store_true",
                     help="only run the time-frame leg (for its kernel trace)")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 64-event batch calls (default tuning, for their kernel trace)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run device copies of this many MiB (calibrates PMC byte counters)")
     ap.add_argument("--pmc-summary", default="",
@@ -79,6 +81,11 @@ def main():
         import torch
         print(json.dumps({"its": its_leg(torch.device("cuda:0"), workloads=args.its_workloads.split(","),
                                          single=not args.its_no_single)}), flush=True)
+        return
+    if args.batch_only:
+        import torch
+        from paper_1712_09434_amd import Tracker
+        print(json.dumps({"batch": batch_trace_leg(args, Tracker, torch.device("cuda:0"))}), flush=True)
         return
     if args.timeframe_only:
         import torch
@@ -549,6 +556,28 @@ def _to_dev(ev, dev):
     import torch
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     return t(ev.x), t(ev.y), t(ev.z), t(ev.row), t(ev.sector)
+
+
+def batch_trace_leg(args, Tracker, dev, reps=5):
+    """The 64-event batch alone: one warm-up and `reps` timed
+    tpcca_track_batch calls with the default launch setting."""
+    import torch
+
+    import synth
+    evs = [synth.make_config("C4", e) for e in range(64)]
+    n = sum(e.n for e in evs)
+    tens = [_to_dev(e, dev) for e in evs]
+    trk = Tracker.from_geometry(evs[0].geom)
+    trk.track_batch(tens)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        trk.track_batch(tens)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    trk.close()
+    log(f"batch only: {n} clusters in 64 events, {dt * 1e3:.2f} ms per call")
+    return {"events": 64, "clusters": n, "ms_per_call": dt * 1e3}
 
 
 def batch_leg(args, Tracker, dev):

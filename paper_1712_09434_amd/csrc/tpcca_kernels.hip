@@ -1015,25 +1015,19 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
 }
 
 // Pairs from the two candidate lists, same arithmetic and tie-break as
-// find_pair.  The up candidates are read into registers once (kCand slots,
-// LDS occupancy leaves room for them), so the pair loop touches LDS only for
-// the down candidates; the interpolation weight depends only on the two x
-// coordinates, so the quotient of the previous pair is reused when they
-// repeat (clusters on their row planes).
-template <class F4>
+// find_pair.  With kRegU the up candidates are read into registers once
+// (kCand slots), so the pair loop touches LDS only for the down candidates;
+// without it (the one-wave and small-slab variants, which gain occupancy from the freed
+// registers) every pair reads its up candidate from LDS.  The interpolation
+// weight depends only on the two x coordinates, so the quotient of the
+// previous pair is reused when they repeat (clusters on their row planes).
+template <bool kRegU, class F4>
 __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
                                           int32_t& bd) {
   const float IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z, CUT = w.P.link_cut;
   bu = -1; bd = -1;
   if (nu == 0) return;
-  uint32_t ui[kCand];
-#pragma unroll
-  for (int j = 0; j < kCand; ++j) ui[j] = j < nu ? lu[j] : 0u;
-  float4 U[kCand];
-#pragma unroll
-  for (int j = 0; j < kCand; ++j)
-    if (j < nu) U[j] = U4[ui[j]];
   // (bs, bu, bd) starts at (CUT, INT32_MAX, INT32_MAX): the first pair with
   // score <= CUT replaces it, later ones must beat the best so far (a NaN
   // score fails every comparison)
@@ -1045,38 +1039,62 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
   // the interpolation quotient (xi - xd)/(xu - xd) only changes with the x
   // coordinates: when all up candidates share one x it is taken once per
   // down x, else per pair whenever either x differs from the last quotient's
-  bool same_xu = true;
-#pragma unroll
-  for (int j = 1; j < kCand; ++j)
-    if (j < nu && U[j].z != U[0].z) same_xu = false;
   float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
   bool wk = false;
-  for (int i = 0; i < nd; ++i) {
-    const float4 D = D4[ld[i]];
-    const int32_t pd = (int32_t)__float_as_uint(D.w);
-    if (same_xu) {
-      if (!(wk && D.z == wx_d)) {
-        wq = (xi - D.z) / (U[0].z - D.z);
-        wx_d = D.z; wx_u = U[0].z; wk = true;
-      }
+  if constexpr (kRegU) {
+    uint32_t ui[kCand];
 #pragma unroll
-      for (int j = 0; j < kCand; ++j) {
-        if (j >= nu) continue;
-        const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
-        const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
-        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
-      }
-    } else {
+    for (int j = 0; j < kCand; ++j) ui[j] = j < nu ? lu[j] : 0u;
+    float4 U[kCand];
 #pragma unroll
-      for (int j = 0; j < kCand; ++j) {
-        if (j >= nu) continue;
-        if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
-          wq = (xi - D.z) / (U[j].z - D.z);
-          wx_d = D.z; wx_u = U[j].z; wk = true;
+    for (int j = 0; j < kCand; ++j)
+      if (j < nu) U[j] = U4[ui[j]];
+    bool same_xu = true;
+#pragma unroll
+    for (int j = 1; j < kCand; ++j)
+      if (j < nu && U[j].z != U[0].z) same_xu = false;
+    for (int i = 0; i < nd; ++i) {
+      const float4 D = D4[ld[i]];
+      const int32_t pd = (int32_t)__float_as_uint(D.w);
+      if (same_xu) {
+        if (!(wk && D.z == wx_d)) {
+          wq = (xi - D.z) / (U[0].z - D.z);
+          wx_d = D.z; wx_u = U[0].z; wk = true;
         }
-        const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
-        const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
-        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
+#pragma unroll
+        for (int j = 0; j < kCand; ++j) {
+          if (j >= nu) continue;
+          const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
+          const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
+          take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kCand; ++j) {
+          if (j >= nu) continue;
+          if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
+            wq = (xi - D.z) / (U[j].z - D.z);
+            wx_d = D.z; wx_u = U[j].z; wk = true;
+          }
+          const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
+          const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
+          take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
+        }
+      }
+    }
+  } else {
+    for (int i = 0; i < nd; ++i) {
+      const float4 D = D4[ld[i]];
+      const int32_t pd = (int32_t)__float_as_uint(D.w);
+      for (int j = 0; j < nu; ++j) {
+        const float4 U = U4[lu[j]];
+        if (!(wk && D.z == wx_d && U.z == wx_u)) {
+          wq = (xi - D.z) / (U.z - D.z);
+          wx_d = D.z; wx_u = U.z; wk = true;
+        }
+        const float ey = yi - fmaf(U.x - D.x, wq, D.x);
+        const float ez = zi - fmaf(U.y - D.y, wq, D.y);
+        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U.w), pd);
       }
     }
   }
@@ -1183,7 +1201,7 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
         const int cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
         const int cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
         if (cd <= kCand && cu <= kCand)
-          best_pair(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
+          best_pair<kClass == 2>(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
         else
           find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
                     (const uint16_t*)scu, bu, bd);
