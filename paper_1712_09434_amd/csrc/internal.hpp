@@ -100,7 +100,7 @@ constexpr int kTl = 20;
 struct Ws {
   // sizes
   int E, S, R;          // events, sectors per event, rows
-  int Rh;               // stride of a tracklet's hit slots: R rounded up to 4 (16-byte groups)
+  int Rh;               // hit-slot rows of a tracklet: R rounded up to a band of 8
   int64_t N;            // clusters (all events)
   int64_t RU;           // row units = E * S * R
   int64_t seed_cap;     // capacity of seed arrays (>= N / min_seed_hits)
@@ -159,7 +159,7 @@ struct Ws {
   int32_t* tl_range;    // [seed_cap] rlo | rhi << 16
   uint64_t* tl_key;     // [seed_cap]
   float* tl_state;      // [seed_cap * kTl]
-  int32_t* tl_hits;     // [seed_cap * R]
+  int32_t* tl_hits;     // [Rh / 8][seed_cap][8]: band-major hit slots (hit_slot())
   uint64_t* owner;      // [N]
   int32_t* tl_own;      // [seed_cap * R] owned hits of accepted tracklets, outermost first
   uint32_t* acc_flag;   // [seed_cap + 1]
@@ -190,6 +190,13 @@ struct PhaseEvents {
 // Host-side launchers (tpcca_kernels.hip).
 hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe = nullptr);
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// Hit slot of seed s at pad row r: rows in bands of 8, each band holding
+// the 8 slots of every seed in turn (a band's slots of consecutive seeds are
+// contiguous; four rows of one band are one aligned 16-byte group).
+__host__ __device__ inline int64_t hit_slot(int64_t seed_cap, int64_t s, int r) {
+  return ((int64_t)(r >> 3) * seed_cap + s) * 8 + (r & 7);
+}
+
 hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* part, hipStream_t st);
 hipError_t fp32_probe(int op, int64_t n, const float* a, const float* b, float* out, hipStream_t st);
 

@@ -1451,14 +1451,16 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
   int32_t wb0 = 0, wb1 = 0, wb2 = 0, wb3 = 0;
   int wbase = -1;
   uint32_t wmask = 0;
+  const int64_t bstride = (int64_t)w.seed_cap * 8;   // between the bands of one seed
   auto flush = [&]() {
+    int32_t* q = hits + (int64_t)(wbase >> 3) * bstride + (wbase & 7);
     if (wmask == 0xFu) {
-      *(int4*)(hits + wbase) = make_int4(wb0, wb1, wb2, wb3);
+      *(int4*)q = make_int4(wb0, wb1, wb2, wb3);
     } else if (wmask) {
-      if (wmask & 1u) hits[wbase] = wb0;
-      if (wmask & 2u) hits[wbase + 1] = wb1;
-      if (wmask & 4u) hits[wbase + 2] = wb2;
-      if (wmask & 8u) hits[wbase + 3] = wb3;
+      if (wmask & 1u) q[0] = wb0;
+      if (wmask & 2u) q[1] = wb1;
+      if (wmask & 4u) q[2] = wb2;
+      if (wmask & 8u) q[3] = wb3;
     }
     wmask = 0;
   };
@@ -1521,7 +1523,7 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
             const uint32_t ru0 = w.cru[h0];
             r0 = (int)(ru0 % (uint32_t)R);
             rubase = ru0 - (uint32_t)r0;
-            hits = w.tl_hits + s * w.Rh;
+            hits = w.tl_hits + s * 8;
             const float4 a0 = w.cpk[h0];
             const int32_t h1 = __float_as_int(a0.w);
             const float4 a1 = w.cpk[h1];
@@ -1694,7 +1696,8 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
     for (uint32_t i = threadIdx.x; i < nc; i += TB) w.owner[c0 + i] = 0ull;
   __syncthreads();
   // one thread per tracklet: the band's eight hit slots are two aligned
-  // 16-byte loads (the slot stride is a multiple of four rows)
+  // 16-byte loads, and the band's slots of consecutive tracklets are
+  // contiguous (hit_slot), so a wave reads them in whole lines
   static_assert(kBandRows == 8, "two int4 of hit slots per band");
   const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
   constexpr int kUn = 2;   // passes whose loads are issued together
@@ -1710,8 +1713,9 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
       const uint32_t sc = ok[u] ? s : s0;
       rg[u] = w.tl_range[sc];
       nh[u] = w.tl_nhits[sc];
-      hh[u] = *(const int4*)(w.tl_hits + (int64_t)sc * w.Rh + r_lo);
-      hh2[u] = r_lo + 4 < w.Rh ? *(const int4*)(w.tl_hits + (int64_t)sc * w.Rh + r_lo + 4) : make_int4(-1, -1, -1, -1);
+      const int32_t* hb = w.tl_hits + hit_slot(w.seed_cap, sc, r_lo);   // (r_lo: a band's first row)
+      hh[u] = *(const int4*)hb;
+      hh2[u] = *(const int4*)(hb + 4);
       key[u] = w.tl_key[sc];
     }
 #pragma unroll
@@ -1759,7 +1763,8 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
     const int32_t rg = w.tl_range[s];
     const bool ok = nh >= w.P.min_hits;
     const int rlo = rg & 0xFFFF, rhi = rg >> 16;
-    const int32_t* hits = w.tl_hits + s * w.Rh;
+    const int32_t* hits = w.tl_hits + s * 8;
+    const int64_t bstride = (int64_t)w.seed_cap * 8;
     int32_t* own = w.tl_own + s * w.R;
     // a list spans at most eight passes of 32 rows (<= 255 rows): read all
     // hit slots, then all their owners, then compact pass by pass
@@ -1769,7 +1774,7 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
 #pragma unroll
     for (int c = 0; c < kPass; ++c) {
       const int r = rhi - hl - 32 * c;
-      h[c] = (ok && r >= rlo) ? hits[r] : -1;
+      h[c] = (ok && r >= rlo) ? hits[(int64_t)(r >> 3) * bstride + (r & 7)] : -1;
     }
 #pragma unroll
     for (int c = 0; c < kPass; ++c) o[c] = h[c] >= 0 ? w.owner[h[c]] : 0ull;

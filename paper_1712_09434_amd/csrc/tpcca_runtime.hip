@@ -156,7 +156,7 @@ struct Layout {
 size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed) {
   Layout L;
   w.E = E; w.S = S; w.R = R; w.N = N;
-  w.Rh = (R + 3) & ~3;
+  w.Rh = (R + 7) & ~7;
   w.RU = (int64_t)E * S * R;
   w.seed_cap = N / std::max(min_seed, 1) + 1;
   w.nb = std::max<int64_t>(1, (N + 255) / 256);
@@ -184,7 +184,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_seo = L.take<uint32_t>(E + 1), o_steo = L.take<uint32_t>(E + 1);
   size_t o_ssu = L.take<uint32_t>((int64_t)E * S + 1);
   size_t o_tln = L.take<int32_t>(SC), o_tlr = L.take<int32_t>(SC);
-  size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * ((R + 3) & ~3));
+  size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * ((R + 7) & ~7));
   size_t o_own = L.take<uint64_t>(N);
   size_t o_tlo = L.take<int32_t>(SC * R);
   size_t o_acf = L.take<uint32_t>(SC + 1), o_aco = L.take<uint32_t>(SC + 1);
@@ -673,12 +673,14 @@ int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t*
   if (cap < ns) return fail(c, TPCCA_E_CAPACITY, "seed capacity too small");
   if (ns == 0) return TPCCA_OK;
   std::vector<uint32_t> seeds(ns), cid(w.N);
-  std::vector<int32_t> nh(ns), hits((size_t)ns * w.Rh);
+  std::vector<int32_t> nh(ns), hits((size_t)ns * w.Rh);   // [band][seed][8] for the first ns seeds
   std::vector<float> state((size_t)ns * kTl);
   hipError_t he = hipMemcpy(seeds.data(), w.seeds, 4 * ns, hipMemcpyDeviceToHost);
   if (he == hipSuccess) he = hipMemcpy(cid.data(), w.cid, 4 * w.N, hipMemcpyDeviceToHost);
   if (he == hipSuccess) he = hipMemcpy(nh.data(), w.tl_nhits, 4 * ns, hipMemcpyDeviceToHost);
-  if (he == hipSuccess) he = hipMemcpy(hits.data(), w.tl_hits, 4 * (size_t)ns * w.Rh, hipMemcpyDeviceToHost);
+  if (he == hipSuccess)
+    he = hipMemcpy2D(hits.data(), 32 * (size_t)ns, w.tl_hits, 32 * (size_t)w.seed_cap, 32 * (size_t)ns,
+                     (size_t)(w.Rh / 8), hipMemcpyDeviceToHost);
   if (he == hipSuccess) he = hipMemcpy(state.data(), w.tl_state, 4 * (size_t)ns * kTl, hipMemcpyDeviceToHost);
   std::vector<int32_t> rng(ns);
   if (he == hipSuccess) he = hipMemcpy(rng.data(), w.tl_range, 4 * ns, hipMemcpyDeviceToHost);
@@ -689,7 +691,7 @@ int tpcca_debug_tracklets(tpcca_ctx* c, int64_t cap, int64_t* n_seeds, uint32_t*
     if (seed_hits) {
       const int rlo = rng[s] & 0xFFFF, rhi = rng[s] >> 16;
       for (int r = 0; r < w.R; ++r) {
-        const int32_t h = hits[(size_t)s * w.Rh + r];
+        const int32_t h = hits[(size_t)hit_slot(ns, s, r)];
         seed_hits[(size_t)s * w.R + r] = (nh[s] > 0 && r >= rlo && r <= rhi && h >= 0) ? (int32_t)cid[h] : -1;
       }
     }
