@@ -160,7 +160,8 @@ struct Ws {
   uint64_t* tl_key;     // [seed_cap]
   float* tl_state;      // [seed_cap * kTl]
   int32_t* tl_hits;     // [Rh / 8][seed_cap][8]: band-major hit slots (hit_slot())
-  uint64_t* owner;      // [N]
+  uint64_t* owner;      // [N] (bands above the LDS capacity only)
+  uint8_t* own_mask;    // [Rh / 8][seed_cap]: rows of a band whose hit the tracklet owns
   int32_t* tl_own;      // [seed_cap * R] owned hits of accepted tracklets, outermost first
   uint32_t* acc_flag;   // [seed_cap + 1]
   uint32_t* acc_off;    // [seed_cap + 1] scanned acc_flag

@@ -1687,9 +1687,9 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   const uint32_t c0 = w.ru_off[su * w.R + r_lo], c1 = w.ru_off[su * w.R + r_hi + 1];
   const uint32_t nc = c1 - c0;
   const bool lds = nc <= (uint32_t)kBandCap;
-  // every cluster lies in one band, whose workgroup alone writes its owner
-  // entries: here (LDS maxima copied out at the end) or, for bands above
-  // the LDS capacity, by global atomics on entries this workgroup clears
+  // every cluster lies in one band, whose workgroup alone takes its
+  // maxima: in LDS or, for bands above the LDS capacity, by global atomics
+  // on entries this workgroup clears
   if (lds)
     for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
   else
@@ -1733,9 +1733,34 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
       }
     }
   }
-  if (lds) {
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nc; i += TB) w.owner[c0 + i] = s_own[i];
+  __syncthreads();
+  // the band's maxima are final: every tracklet of the sector gets the mask
+  // of the band's rows whose hit it owns (its key is the maximum there),
+  // written beside those of the neighbouring tracklets
+  uint8_t* mk = w.own_mask + (int64_t)(r_lo >> 3) * w.seed_cap;
+  for (uint32_t s = s0 + threadIdx.x; s < s1; s += TB) {
+    const int32_t rg = w.tl_range[s];
+    const int nh = w.tl_nhits[s];
+    const int32_t* hb = w.tl_hits + hit_slot(w.seed_cap, s, r_lo);
+    const int4 a = *(const int4*)hb, b = *(const int4*)(hb + 4);
+    const unsigned long long key = w.tl_key[s];
+    uint32_t m = 0;
+    if (nh >= w.P.min_hits) {
+      const int rlo = rg & 0xFFFF, rhi = rg >> 16;
+      const int32_t hq[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = r_lo + q;
+        const int32_t h = hq[q];
+        if (r > r_hi || r < rlo || r > rhi || h < 0) continue;
+        // (bands above the LDS capacity: the maxima are this workgroup's
+        // atomics, read past the compute unit's cache)
+        const unsigned long long mx =
+            lds ? s_own[(uint32_t)h - c0] : __hip_atomic_load(&w.owner[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (mx == key) m |= 1u << q;
+      }
+    }
+    mk[s] = (uint8_t)m;
   }
 }
 
@@ -1756,31 +1781,32 @@ __global__ __launch_bounds__(TB) void k_accept(Ws w) {
   const int64_t stride = (int64_t)(gridDim.x / kXcd) * (TB / 32);
   for (int64_t s = first; s < hi; s += stride) {
     uint32_t acc = 0, cnt = 0;
-    // the three are loaded together (one memory round trip): no branch
+    // the two are loaded together (one memory round trip): no branch
     // around the rest, whose loads and stores are predicated on ok instead
     const int nh = w.tl_nhits[s];
-    const uint64_t key = w.tl_key[s];
     const int32_t rg = w.tl_range[s];
     const bool ok = nh >= w.P.min_hits;
     const int rlo = rg & 0xFFFF, rhi = rg >> 16;
     const int32_t* hits = w.tl_hits + s * 8;
     const int64_t bstride = (int64_t)w.seed_cap * 8;
+    const uint8_t* mk = w.own_mask + s;
     int32_t* own = w.tl_own + s * w.R;
     // a list spans at most eight passes of 32 rows (<= 255 rows): read all
-    // hit slots, then all their owners, then compact pass by pass
+    // hit slots and the owned-row masks of their bands, then compact pass
+    // by pass
     constexpr int kPass = 8;
     int32_t h[kPass];
-    uint64_t o[kPass];
+    uint32_t mb[kPass];
 #pragma unroll
     for (int c = 0; c < kPass; ++c) {
       const int r = rhi - hl - 32 * c;
-      h[c] = (ok && r >= rlo) ? hits[(int64_t)(r >> 3) * bstride + (r & 7)] : -1;
+      const bool in = ok && r >= rlo;
+      h[c] = in ? hits[(int64_t)(r >> 3) * bstride + (r & 7)] : -1;
+      mb[c] = in ? ((uint32_t)mk[(int64_t)(r >> 3) * w.seed_cap] >> (r & 7)) & 1u : 0u;
     }
 #pragma unroll
-    for (int c = 0; c < kPass; ++c) o[c] = h[c] >= 0 ? w.owner[h[c]] : 0ull;
-#pragma unroll
     for (int c = 0; c < kPass; ++c) {
-      const bool mine = h[c] >= 0 && o[c] == key;
+      const bool mine = h[c] >= 0 && mb[c] != 0u;
       const uint64_t m = __ballot(mine) & half;
       if (mine) own[cnt + (uint32_t)__popcll(m & lanemask_lt())] = h[c];
       cnt += (uint32_t)__popcll(m);

@@ -185,7 +185,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
   size_t o_ssu = L.take<uint32_t>((int64_t)E * S + 1);
   size_t o_tln = L.take<int32_t>(SC), o_tlr = L.take<int32_t>(SC);
   size_t o_tlk = L.take<uint64_t>(SC), o_tls = L.take<float>(SC * kTl), o_tlh = L.take<int32_t>(SC * ((R + 7) & ~7));
-  size_t o_own = L.take<uint64_t>(N);
+  size_t o_own = L.take<uint64_t>(N), o_omask = L.take<uint8_t>(SC * ((R + 7) / 8));
   size_t o_tlo = L.take<int32_t>(SC * R);
   size_t o_acf = L.take<uint32_t>(SC + 1), o_aco = L.take<uint32_t>(SC + 1);
   size_t o_acl = L.take<uint32_t>(SC), o_occ = L.take<uint32_t>(SC + 1);
@@ -218,7 +218,7 @@ size_t layout_ws(Ws& w, char* base, int64_t N, int E, int S, int R, int min_seed
     w.tl_nhits = (int32_t*)(base + o_tln); w.tl_range = (int32_t*)(base + o_tlr);
     w.tl_key = (uint64_t*)(base + o_tlk); w.tl_state = (float*)(base + o_tls);
     w.tl_hits = (int32_t*)(base + o_tlh);
-    w.owner = (uint64_t*)(base + o_own);
+    w.owner = (uint64_t*)(base + o_own); w.own_mask = (uint8_t*)(base + o_omask);
     w.tl_own = (int32_t*)(base + o_tlo);
     w.acc_flag = (uint32_t*)(base + o_acf); w.acc_off = (uint32_t*)(base + o_aco);
     w.acc_list = (uint32_t*)(base + o_acl); w.own_cnt = (uint32_t*)(base + o_occ);
