@@ -506,6 +506,32 @@ over the batch of 6 slices).
         with open(os.path.join(ROOT, "profiles", "timeframe_tf24_kernel_trace.md"), "w") as f:
             f.write(text_t)
         print(text_t)
+    b_stats = glob.glob(os.path.join(folder, "prof_batch", "**", "*kernel_stats.csv"), recursive=True)
+    if b_stats:
+        bl = []
+        for r in csv.DictReader(open(b_stats[0])):
+            name = re.sub(r"\(.*", "", r["Name"].replace("tpcca::(anonymous namespace)::", ""))
+            name = re.sub(r"^void ", "", name)
+            bl.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+        body_b = "\n".join(f"| {n} | {c} | {a:,.1f} | {p:.1f} |" for n, c, a, p in bl[:20])
+        text_b = f"""# Kernel trace, batch of 64 events of lognormal multiplicity (12.0 M clusters)
+
+Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
+
+    rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_batch -o batch -- python3 bench.py --batch-only
+    python3 bench.py --pmc-summary <out>
+
+One tpcca_track_batch call over all 64 events per step (default launch setting): 1 warm-up and
+5 timed calls; average duration per dispatch.  Row units: 366,336, of which 321,195 hold at most
+64 clusters and 44,470 between 65 and 256.
+
+| Kernel | Calls | Average µs | % of GPU time |
+|---|---|---|---|
+{body_b}
+"""
+        with open(os.path.join(ROOT, "profiles", "batch_c4x64_kernel_trace.md"), "w") as f:
+            f.write(text_b)
+        print(text_b)
     its_stats = glob.glob(os.path.join(folder, "prof_its", "**", "*kernel_stats.csv"), recursive=True)
     if its_stats:
         il = []
