@@ -1677,8 +1677,13 @@ __global__ __launch_bounds__(TB) void k_tracklets(Ws w) {
 // kBandCap clusters uses global atomics on the (zeroed) owner array instead.
 constexpr int kBandRows = 8;
 constexpr int kBandCap = 6144;
+// threads of an ownership workgroup: 1024 where the sectors hold many
+// tracklets (short chains of dependent loads per thread), TB for batches of
+// small events (few tracklets per band, many workgroups)
+constexpr int TBO = 1024;
 
-__global__ __launch_bounds__(TB) void k_owner(Ws w) {
+__global__ __launch_bounds__(TBO) void k_owner(Ws w) {
+  const uint32_t nt = blockDim.x;   // (TBO for events of many tracklets, TB otherwise)
   __shared__ unsigned long long s_own[kBandCap];
   const int nband = (w.R + kBandRows - 1) / kBandRows;
   const int64_t su = blockIdx.x / nband;
@@ -1691,9 +1696,9 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   // maxima: in LDS or, for bands above the LDS capacity, by global atomics
   // on entries this workgroup clears
   if (lds)
-    for (uint32_t i = threadIdx.x; i < nc; i += TB) s_own[i] = 0ull;
+    for (uint32_t i = threadIdx.x; i < nc; i += nt) s_own[i] = 0ull;
   else
-    for (uint32_t i = threadIdx.x; i < nc; i += TB) w.owner[c0 + i] = 0ull;
+    for (uint32_t i = threadIdx.x; i < nc; i += nt) w.owner[c0 + i] = 0ull;
   __syncthreads();
   // one thread per tracklet: the band's eight hit slots are two aligned
   // 16-byte loads, and the band's slots of consecutive tracklets are
@@ -1701,14 +1706,14 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   static_assert(kBandRows == 8, "two int4 of hit slots per band");
   const uint32_t s0 = w.seed_su_off[su], s1 = w.seed_su_off[su + 1];
   constexpr int kUn = 2;   // passes whose loads are issued together
-  for (uint32_t sb = s0; sb < s1; sb += TB * kUn) {
+  for (uint32_t sb = s0; sb < s1; sb += nt * kUn) {
     int32_t rg[kUn], nh[kUn];
     int4 hh[kUn], hh2[kUn];
     unsigned long long key[kUn];
     bool ok[kUn];
 #pragma unroll
     for (int u = 0; u < kUn; ++u) {
-      const uint32_t s = sb + u * TB + threadIdx.x;
+      const uint32_t s = sb + u * nt + threadIdx.x;
       ok[u] = s < s1;
       const uint32_t sc = ok[u] ? s : s0;
       rg[u] = w.tl_range[sc];
@@ -1738,7 +1743,7 @@ __global__ __launch_bounds__(TB) void k_owner(Ws w) {
   // of the band's rows whose hit it owns (its key is the maximum there),
   // written beside those of the neighbouring tracklets
   uint8_t* mk = w.own_mask + (int64_t)(r_lo >> 3) * w.seed_cap;
-  for (uint32_t s = s0 + threadIdx.x; s < s1; s += TB) {
+  for (uint32_t s = s0 + threadIdx.x; s < s1; s += nt) {
     const int32_t rg = w.tl_range[s];
     const int nh = w.tl_nhits[s];
     const int32_t* hb = w.tl_hits + hit_slot(w.seed_cap, s, r_lo);
@@ -2063,7 +2068,8 @@ hipError_t run_pipeline(const Ws& w, hipStream_t st, const PhaseEvents* pe) {
   k_tracklets<<<tracklet_grid(w), TB, 0, st>>>(w);
   TPCCA_CHECK(hipGetLastError());
   TPCCA_MARK(PH_OWNER);
-  k_owner<<<(unsigned)((int64_t)w.E * w.S * ((w.R + kBandRows - 1) / kBandRows)), TB, 0, st>>>(w);
+  k_owner<<<(unsigned)((int64_t)w.E * w.S * ((w.R + kBandRows - 1) / kBandRows)),
+             w.N / std::max(w.E, 1) >= ((int64_t)1 << 20) ? TBO : TB, 0, st>>>(w);
   TPCCA_MARK(PH_REFIT);
   k_accept<<<xcd_blocks(w.seed_cap * 32), TB, 0, st>>>(w);
   TPCCA_CHECK(scan_u32(w.acc_flag, w.acc_off, w.seed_cap, w.scan_tmp, st));
