@@ -43,6 +43,8 @@ struct tpcca_its_ctx {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   float* tab = nullptr;          // device stave tables
+  char* hpin = nullptr;          // pinned staging of the per-call tables and results
+  size_t hpin_bytes = 0;
 };
 
 namespace tpcca {
@@ -1033,15 +1035,21 @@ int tpcca_its_track_batch(tpcca_its_ctx* c, int32_t E, const tpcca_its_clusters*
   auto take = [&](size_t bytes) { const size_t at = off; off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255; return at; };
   const int64_t nn = std::max<int64_t>(n, 1);
   const int64_t ns = (int64_t)E * kPerEv;
-  const size_t o_ev = take(sizeof(ItsEvIn) * (E + 1)), o_out = take(sizeof(tpcca_its_tracks) * E);
+  // the event and output tables back to back (one upload), the per-event
+  // results back to back (one download)
+  const size_t up_ev = sizeof(ItsEvIn) * (E + 1), up_bytes = up_ev + sizeof(tpcca_its_tracks) * E;
+  const size_t r_vsum = 0, r_vres = r_vsum + 8 * 4 * (size_t)E, r_vzd = r_vres + 8 * 8 * (size_t)E;
+  const size_t r_pk = r_vzd + 8 * (size_t)E, r_toff = r_pk + 4 * (size_t)E, r_err = r_toff + 4 * ((size_t)E + 1);
+  const size_t res_bytes = r_err + 8;
+  const size_t o_up = take(up_bytes), o_res = take(res_bytes);
   const size_t o_cx = take(4 * nn), o_cy = take(4 * nn), o_cz = take(4 * nn), o_cl = take(nn), o_ck = take(2 * nn);
   const size_t o_cev = take(4 * nn), o_X = take(4 * nn), o_Y = take(4 * nn), o_R = take(4 * nn);
-  const size_t o_err = take(8), o_scnt = take(4 * (ns + 1)), o_scur = take(4 * ns), o_slist = take(4 * nn);
+  const size_t o_scnt = take(4 * (ns + 1)), o_scur = take(4 * ns), o_slist = take(4 * nn);
   const size_t o_sA = take(16 * nn), o_sB = take(16 * nn), o_l0f = take(4 * (nn + 1)), o_l0l = take(4 * nn);
-  const size_t o_hist = take(4 * (int64_t)E * nbins), o_vsum = take(8 * 4 * (int64_t)E), o_vzd = take(8 * (int64_t)E);
-  const size_t o_pk = take(4 * (int64_t)E), o_b0 = take(8 * nn), o_b1 = take(8 * nn), o_tf = take(4 * (nn + 1));
-  const size_t o_tl0 = take(4 * nn), o_tl1 = take(4 * nn), o_tev = take(4 * nn), o_toff = take(4 * (E + 1));
-  const size_t o_vw = take(8 * nn), o_vres = take(8 * 8 * (int64_t)E);
+  const size_t o_hist = take(4 * (int64_t)E * nbins);
+  const size_t o_b0 = take(8 * nn), o_b1 = take(8 * nn), o_tf = take(4 * (nn + 1));
+  const size_t o_tl0 = take(4 * nn), o_tl1 = take(4 * nn), o_tev = take(4 * nn);
+  const size_t o_vw = take(8 * nn);
   const size_t o_part = take(4 * (2 * (std::max<int64_t>(nn, ns) / 1024 + 2)));
   if (off > c->arena_bytes) {
     if (c->arena) { (void)hipFree(c->arena); c->arena = nullptr; c->arena_bytes = 0; }
@@ -1051,11 +1059,22 @@ int tpcca_its_track_batch(tpcca_its_ctx* c, int32_t E, const tpcca_its_clusters*
     }
     c->arena_bytes = off + off / 4;
   }
+  if (std::max(up_bytes, res_bytes) > c->hpin_bytes) {
+    if (c->hpin) { (void)hipHostFree(c->hpin); c->hpin = nullptr; c->hpin_bytes = 0; }
+    const size_t hb = std::max(up_bytes, res_bytes) * 2;
+    if (hipHostMalloc((void**)&c->hpin, hb) != hipSuccess) {
+      (void)hipGetLastError();
+      c->hpin = nullptr;
+      return its_fail(c, TPCCA_E_NOMEM, "ITS staging allocation failed");
+    }
+    c->hpin_bytes = hb;
+  }
   char* b = c->arena;
   // per-event tables (the input pointers of an empty event still point at
   // valid memory; they are never read)
-  std::vector<ItsEvIn> tin(E + 1);
-  std::vector<tpcca_its_tracks> tout(outs, outs + E);
+  ItsEvIn* tin = (ItsEvIn*)c->hpin;
+  tpcca_its_tracks* tout = (tpcca_its_tracks*)(c->hpin + up_ev);
+  std::copy(outs, outs + E, tout);
   int64_t acc = 0;
   for (int e = 0; e < E; ++e) {
     const tpcca_its_clusters& k = ev[e];
@@ -1071,8 +1090,8 @@ int tpcca_its_track_batch(tpcca_its_ctx* c, int32_t E, const tpcca_its_clusters*
   tin[E] = ItsEvIn{nullptr, nullptr, nullptr, nullptr, nullptr, acc};
   ItsWs w{};
   w.E = E; w.n = n;
-  w.ev = (const ItsEvIn*)(b + o_ev);
-  w.out = (tpcca_its_tracks*)(b + o_out);
+  w.ev = (const ItsEvIn*)(b + o_up);
+  w.out = (tpcca_its_tracks*)(b + o_up + up_ev);
   w.tab = (const ItsTab*)c->tab;
   for (int l = 0; l < kLayers; ++l) {
     w.r[l] = c->g.radius[l]; w.xx0[l] = c->g.x_over_x0[l];
@@ -1088,40 +1107,35 @@ int tpcca_its_track_batch(tpcca_its_ctx* c, int32_t E, const tpcca_its_clusters*
   w.cx = (float*)(b + o_cx); w.cy = (float*)(b + o_cy); w.cz = (float*)(b + o_cz);
   w.cl = (int8_t*)(b + o_cl); w.ck = (int16_t*)(b + o_ck); w.cev = (int32_t*)(b + o_cev);
   w.cX = (float*)(b + o_X); w.cY = (float*)(b + o_Y); w.cR = (float*)(b + o_R);
-  w.err = (uint32_t*)(b + o_err); w.scnt = (uint32_t*)(b + o_scnt); w.scur = (uint32_t*)(b + o_scur);
+  w.err = (uint32_t*)(b + o_res + r_err); w.scnt = (uint32_t*)(b + o_scnt); w.scur = (uint32_t*)(b + o_scur);
   w.slist = (uint32_t*)(b + o_slist); w.sA = (float4*)(b + o_sA); w.sB = (float4*)(b + o_sB);
   w.l0f = (uint32_t*)(b + o_l0f); w.l0list = (uint32_t*)(b + o_l0l);
-  w.hist = (uint32_t*)(b + o_hist); w.vsum = (unsigned long long*)(b + o_vsum); w.vzd = (float*)(b + o_vzd);
-  w.vpeak = (int32_t*)(b + o_pk);
+  w.hist = (uint32_t*)(b + o_hist); w.vsum = (unsigned long long*)(b + o_res + r_vsum);
+  w.vzd = (float*)(b + o_res + r_vzd); w.vpeak = (int32_t*)(b + o_res + r_pk);
   w.best0 = (unsigned long long*)(b + o_b0); w.best1 = (unsigned long long*)(b + o_b1);
   w.tflag = (uint32_t*)(b + o_tf); w.tl0 = (int32_t*)(b + o_tl0); w.tl1 = (int32_t*)(b + o_tl1);
-  w.tev = (int32_t*)(b + o_tev); w.toff = (uint32_t*)(b + o_toff);
-  w.vw = (double*)(b + o_vw); w.vres = (double*)(b + o_vres); w.part = (uint32_t*)(b + o_part);
-  he = hipMemcpyAsync(b + o_ev, tin.data(), sizeof(ItsEvIn) * (E + 1), hipMemcpyHostToDevice, st);
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(b + o_out, tout.data(), sizeof(tpcca_its_tracks) * E, hipMemcpyHostToDevice, st);
+  w.tev = (int32_t*)(b + o_tev); w.toff = (uint32_t*)(b + o_res + r_toff);
+  w.vw = (double*)(b + o_vw); w.vres = (double*)(b + o_res + r_vres); w.part = (uint32_t*)(b + o_part);
+  he = hipMemcpyAsync(b + o_up, c->hpin, up_bytes, hipMemcpyHostToDevice, st);
   if (he == hipSuccess) he = run_its(w, st);
   if (he != hipSuccess) {
     (void)hipStreamSynchronize(st);
     return its_fail(c, TPCCA_E_DEVICE, std::string("ITS kernels: ") + hipGetErrorString(he));
   }
-  std::vector<unsigned long long> vs(4 * (size_t)E);
-  std::vector<float> vz(2 * (size_t)E);
-  std::vector<int32_t> pk(E);
-  std::vector<uint32_t> toff(E + 1);
-  std::vector<double> vr(8 * (size_t)E);
-  uint32_t err = 0;
-  he = hipMemcpyAsync(vs.data(), w.vsum, 8 * vs.size(), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(vz.data(), w.vzd, 4 * vz.size(), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(pk.data(), w.vpeak, 4 * pk.size(), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(toff.data(), w.toff, 4 * toff.size(), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(vr.data(), w.vres, 8 * vr.size(), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipMemcpyAsync(&err, w.err, 4, hipMemcpyDeviceToHost, st);
+  // (the upload has been read by the kernels once the stream passes them:
+  // the staging buffer takes the results now)
+  he = hipMemcpyAsync(c->hpin, b + o_res, res_bytes, hipMemcpyDeviceToHost, st);
   for (int e = 0; e < E && he == hipSuccess; ++e)
     if (outs[e].hist)
       he = hipMemcpyAsync(outs[e].hist, w.hist + (int64_t)e * nbins, 4 * (size_t)nbins, hipMemcpyDeviceToDevice, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) return its_fail(c, TPCCA_E_DEVICE, std::string("ITS results: ") + hipGetErrorString(he));
+  const unsigned long long* vs = (const unsigned long long*)(c->hpin + r_vsum);
+  const double* vr = (const double*)(c->hpin + r_vres);
+  const float* vz = (const float*)(c->hpin + r_vzd);
+  const int32_t* pk = (const int32_t*)(c->hpin + r_pk);
+  const uint32_t* toff = (const uint32_t*)(c->hpin + r_toff);
+  const uint32_t err = *(const uint32_t*)(c->hpin + r_err);
   if (err) return its_fail(c, TPCCA_E_INVALID, "a cluster has a bad layer or stave or a non-finite coordinate");
   bool fits = true;
   for (int e = 0; e < E; ++e) {
@@ -1153,6 +1167,7 @@ void tpcca_its_destroy(tpcca_its_ctx* c) {
   if (!c) return;
   if (c->arena) (void)hipFree(c->arena);
   if (c->tab) (void)hipFree(c->tab);
+  if (c->hpin) (void)hipHostFree(c->hpin);
   delete c;
 }
 
