@@ -195,14 +195,17 @@ __device__ __forceinline__ int wedge_of(const ItsWs& w, int l, int lf, int kf, f
 }
 
 // Lanes per layer-0 cluster in the pair kernels and per tracklet in the
-// following: the records a cluster or tracklet visits are split over them.
+// following (fewer: each lane also repeats the tracklet's Kalman steps): the
+// records a cluster or tracklet visits are split over them.
 constexpr int kGrp = 8;
+constexpr int kGrpF = 4;   // lanes per tracklet in the following
 
+template <int G = kGrp>
 __device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
 #pragma unroll
-  for (int d = 1; d < kGrp; d <<= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, kGrp);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kGrp);
+  for (int d = 1; d < G; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(v & 0xFFFFFFFFull), d, G);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, G);
     const unsigned long long o = ((unsigned long long)hi << 32) | lo;
     v = o < v ? o : v;
   }
@@ -545,14 +548,14 @@ __device__ __forceinline__ void frame_turn(const ItsTab* tb, int lt, int kt, int
   dsa = tb->sa[lt][kt] * tb->ca[lf][kf] - tb->ca[lt][kt] * tb->sa[lf][kf];
 }
 
-// Following and inward fit of one tracklet by a group of kGrp lanes: every
+// Following and inward fit of one tracklet by a group of kGrpF lanes: every
 // lane of the group evaluates the same state (the same expressions, so the
 // same values), the cluster search of a layer is split over the lanes and
 // its result is the group minimum of (chi2 bits, id); lane 0 writes.
 
 __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
-  const int64_t a = (int64_t)blockIdx.x * (64 / kGrp) + threadIdx.x / kGrp;
-  const int gl = threadIdx.x % kGrp;
+  const int64_t a = (int64_t)blockIdx.x * (64 / kGrpF) + threadIdx.x / kGrpF;
+  const int gl = threadIdx.x % kGrpF;
   if (a >= (int64_t)w.tflag[w.n]) return;   // (the whole group)
   const int e = w.tev[a];
   const int64_t t = a - (int64_t)w.toff[e];
@@ -633,22 +636,22 @@ __global__ __launch_bounds__(64) void k_its_follow(ItsWs w) {
     unsigned long long best = ~0ull;
     const uint32_t sa = w.scnt[sidx(e, l, k)], sb = w.scnt[sidx(e, l, k) + 1];
     constexpr int kU = 4;
-    for (uint32_t j0 = sa + (uint32_t)gl; j0 < sb; j0 += kU * kGrp) {
+    for (uint32_t j0 = sa + (uint32_t)gl; j0 < sb; j0 += kU * kGrpF) {
       float4 rc[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const uint32_t j = j0 + (uint32_t)(u * kGrp);
+        const uint32_t j = j0 + (uint32_t)(u * kGrpF);
         rc[u] = w.sB[j < sb ? j : sa];
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (j0 + (uint32_t)(u * kGrp) >= sb) continue;
+        if (j0 + (uint32_t)(u * kGrpF) >= sb) continue;
         const float dy = rc[u].x - p[0], dz = rc[u].y - p[1];
         const float ch = (dy * dy) * isy + (dz * dz) * isz;
         if (ch <= cut) best = min(best, ((unsigned long long)__float_as_uint(ch) << 32) | __float_as_uint(rc[u].z));
       }
     }
-    best = grp_min(best);
+    best = grp_min<kGrpF>(best);
     const int32_t bid = best == ~0ull ? -1 : (int32_t)(best & 0xFFFFFFFFull);
     if (bid >= 0) {
       m.vy = w.vy[l]; m.vz = w.vz[l];
@@ -913,7 +916,7 @@ hipError_t run_its(const ItsWs& w, hipStream_t st) {
   e = scan_exclusive_u32(w.tflag, w.tflag, w.n, w.part, st);
   if (e != hipSuccess) return e;
   k_its_tlcompact<<<grid_for(std::max<int64_t>(w.n, w.E + 1)), TB, 0, st>>>(w);
-  k_its_follow<<<(unsigned)std::max<int64_t>((w.n + 64 / kGrp - 1) / (64 / kGrp), 1), 64, 0, st>>>(w);
+  k_its_follow<<<(unsigned)std::max<int64_t>((w.n + 64 / kGrpF - 1) / (64 / kGrpF), 1), 64, 0, st>>>(w);
   k_its_vfit<<<(unsigned)w.E, TBV, 0, st>>>(w);
   return hipGetLastError();
 }
