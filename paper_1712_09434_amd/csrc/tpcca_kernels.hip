@@ -1017,10 +1017,11 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
 // Pairs from the two candidate lists, same arithmetic and tie-break as
 // find_pair.  With kRegU the up candidates are read into registers once
 // (kCand slots), so the pair loop touches LDS only for the down candidates;
-// without it (the one-wave and small-slab variants, which gain occupancy from the freed
-// registers) every pair reads its up candidate from LDS.  The interpolation
-// weight depends only on the two x coordinates, so the quotient of the
-// previous pair is reused when they repeat (clusters on their row planes).
+// without it (the one-wave and small-slab variants, which gain occupancy
+// from the freed registers) every pair reads its up candidate from LDS.
+// The interpolation weight depends only on the two x coordinates, so the
+// quotient of the previous pair is reused when they repeat (clusters on
+// their row planes).
 template <bool kRegU, class F4>
 __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
@@ -1340,11 +1341,11 @@ struct Found { int32_t pos; float y, z; };
 // d = dy^2/(Cyy + sy^2) + dz^2/(Czz + sz^2) <= chi2_ext, minimum (d, id).
 // The candidates are the 12-byte (y, z, canonical position) search records
 // (the winner's x is read from the canonical arrays only in row units with
-// clusters off the row plane).  The cell ranges of
-// the box's first two z rows are read together, then their entries in
-// chunks of eight loads issued before any is tested, so a step waits for
-// memory twice rather than once per candidate.  The result does not depend
-// on the order the candidates are visited in.
+// clusters off the row plane).  The cell ranges of the box's first two z
+// rows are read together, then their entries in chunks of eight loads issued
+// before any is tested, so a step waits for memory twice rather than once
+// per candidate.  The result does not depend on the order the candidates
+// are visited in.
 __device__ __forceinline__ Found search_row(const Ws& w, const GridParams& G, const float p[5],
                                             const float C[15]) {
   const float sy2 = C[0] + w.m.vy, sz2 = C[5] + w.m.vz;
