@@ -24,7 +24,7 @@
 // at a time; the histogram privatised in LDS), peak, fixed-point mean;
 // tracklet candidates (best of each layer-0 cluster by a group minimum, best
 // of each layer-1 cluster by a 64-bit atomic minimum of (score bits, id)); mutual pairs compacted in
-// id order; following and inward fit (eight lanes per tracklet sharing the
+// id order; following and inward fit (four lanes per tracklet sharing the
 // cluster search); vertex fit (one workgroup per event, fixed-order FP64
 // reductions).  Every event's results equal those of a call on that event
 // alone.
