@@ -984,7 +984,7 @@ __device__ __forceinline__ void find_pair(const Ws& w, float xi, float yi, float
   }
 }
 
-constexpr int kCand = 16;          // passing candidates per side kept per lane
+constexpr int kCand = 15;          // passing candidates per side kept per lane
 
 // Window scan of one row's box: indices (into D4) of the entries within the
 // windows, at most kCand; returns the count, or kCand + 1 on overflow.
@@ -1102,6 +1102,109 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
   if (ku != INT32_MAX) { bu = ku; bd = kd; }
 }
 
+// The pairs of a wave's lanes scored by all 64 lanes, same arithmetic and
+// tie-break as find_pair.  Lane l (has: a cluster whose lists fit) owns
+// cd_l cu_l pairs, listed in lane order and, within a lane, down-major; the
+// list is cut into 64 contiguous ranges, one per lane, so a wave runs about
+// its mean pair count instead of its lanes' largest candidate counts.  A lane
+// keeps the least key of the pairs it scored for the current owner and folds
+// it into the owner's LDS word (atomic minimum) when it moves on.  The key
+// is (score bits, up offset, down offset) in 32 + 10 + 10 bits: a score that
+// passes the cut is >= 0, so its bits order like its value, and the offsets
+// of the neighbour rows' canonical positions (rows of at most kSlab entries)
+// order like the positions, so the least key is find_pair's choice.  Called
+// by all lanes of the wave; ld_w/lu_w/key_w: the wave's slices of the
+// candidate lists and of the key words.
+constexpr unsigned long long kNoKey = ~0ull;
+static_assert(kSlab <= 1024u, "row offsets in the pair key take 10 bits");
+
+__device__ __forceinline__ void wave_pairs(const Ws& w, bool has, float xi, float yi, float zi, uint32_t cd,
+                                           uint32_t cu, const float4* D4, const float4* U4, const uint16_t* ld_w,
+                                           const uint16_t* lu_w, unsigned long long* key_w, uint32_t offd,
+                                           uint32_t offu, int32_t& bu, int32_t& bd) {
+  const float IWY = w.P.inv_var_y, IWZ = w.P.inv_var_z, CUT = w.P.link_cut;
+  const int lane = lane_id();
+  const uint32_t cnt = has ? cd * cu : 0u;
+  const uint32_t incl = wave_incl_scan(cnt);
+  const uint32_t P = (uint32_t)__shfl((int)incl, 63, 64);
+  bu = -1; bd = -1;
+  if (P == 0u) return;   // (uniform)
+  key_w[lane] = kNoKey;
+  wave_sync();
+  const uint64_t owners = __ballot(cnt > 0u);
+  uint32_t t = (uint32_t)(((uint64_t)lane * P) >> 6);
+  const uint32_t t1 = (uint32_t)(((uint64_t)(lane + 1) * P) >> 6);
+  // owner of pair t (< P): the lowest lane whose inclusive count exceeds t
+  int o = 0;
+#pragma unroll
+  for (int st = 32; st > 0; st >>= 1) {
+    const uint32_t v = (uint32_t)__shfl((int)incl, o + st - 1, 64);
+    if (v <= t) o += st;
+  }
+  // the owner's cluster, up count and pair range (shuffles by every lane)
+  float oxi, oyi, ozi;
+  uint32_t ocu, oend;
+  auto fetch = [&](int src) {
+    oxi = __shfl(xi, src, 64);
+    oyi = __shfl(yi, src, 64);
+    ozi = __shfl(zi, src, 64);
+    ocu = (uint32_t)__shfl((int)cu, src, 64);
+    oend = (uint32_t)__shfl((int)incl, src, 64);
+  };
+  fetch(o);
+  const uint32_t ocnt = (uint32_t)__shfl((int)cnt, o, 64);
+  uint32_t i = 0, j = 0;
+  if (t < t1) {
+    const uint32_t rel = t - (oend - ocnt);
+    i = rel / ocu;
+    j = rel - i * ocu;
+  }
+  unsigned long long best = kNoKey;
+  // the interpolation quotient of the last pair, reused while the three x
+  // coordinates repeat (clusters on their row planes)
+  float wx_i = 0.0f, wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
+  bool wk = false;
+  const uint32_t steps = (P + 63u) >> 6;   // the longest range
+  for (uint32_t k = 0; k < steps; ++k) {
+    const bool act = t < t1;
+    if (act) {
+      const float4 D = D4[ld_w[kCand * o + (int)i]];
+      const float4 U = U4[lu_w[kCand * o + (int)j]];
+      if (!(wk && oxi == wx_i && D.z == wx_d && U.z == wx_u)) {
+        wq = (oxi - D.z) / (U.z - D.z);
+        wx_i = oxi; wx_d = D.z; wx_u = U.z; wk = true;
+      }
+      const float ey = oyi - fmaf(U.x - D.x, wq, D.x);
+      const float ez = ozi - fmaf(U.y - D.y, wq, D.y);
+      const float score = fmaf(ez * ez, IWZ, (ey * ey) * IWY);
+      if (score <= CUT) {
+        const unsigned long long key = ((unsigned long long)__float_as_uint(score) << 20) |
+                                       ((unsigned long long)(__float_as_uint(U.w) - offu) << 10) |
+                                       (unsigned long long)(__float_as_uint(D.w) - offd);
+        best = key < best ? key : best;
+      }
+      ++t;
+      if (++j == ocu) { j = 0; ++i; }
+    }
+    const bool fold = act && (t == oend || t == t1);
+    if (fold && best != kNoKey) atomicMin(&key_w[o], best);
+    if (fold) best = kNoKey;
+    // the range goes on into the next owner (a later lane with pairs)
+    const bool next = act && t == oend && t < t1;
+    if (__ballot(next) != 0ull) {
+      const int on = next ? __ffsll((unsigned long long)(owners & ~((2ull << o) - 1ull))) - 1 : o;
+      fetch(on);
+      if (next) { o = on; i = 0; j = 0; }
+    }
+  }
+  wave_sync();
+  const unsigned long long b = key_w[lane];
+  if (has && b != kNoKey) {
+    bu = (int32_t)(offu + (uint32_t)((b >> 10) & 1023ull));
+    bd = (int32_t)(offd + (uint32_t)(b & 1023ull));
+  }
+}
+
 // One block per row unit: the grids of rows r-1 and r+1 (entries and cell
 // offsets) are staged in LDS when each holds at most kSlab clusters.  Lanes
 // take the row's clusters in grid (cell) order, so the lanes of a wave are
@@ -1128,6 +1231,8 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
   // clusters has at most kCellsPerCluster kS + 1 cells
   __shared__ uint16_t s_cd[kNG][kSpareC + 1], s_cu[kNG][kSpareC + 1];
   __shared__ uint16_t s_ld[kCand * TB], s_lu[kCand * TB];
+  // per-lane best pair keys of the wave-level pair scoring (slab variant)
+  __shared__ unsigned long long s_key[kClass == 2 ? TB : 1];
   const uint32_t g = threadIdx.x / kG, gt = threadIdx.x % kG;
   // one row unit (uniform over its kG threads); called once per unit of the launch
   auto unit = [&](const int64_t ru) {
@@ -1157,7 +1262,7 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
     uint16_t* scu = s_cu[g];
     // this thread's own clusters (grid order) for its first rounds, read now
     // so that they arrive with the staged rows
-    constexpr int kOwn = 4;
+    constexpr int kOwn = 4;   // (the slab variant's rounds shift through four)
     float4 mine[kOwn];
   #pragma unroll
     for (int i = 0; i < kOwn; ++i) {
@@ -1213,6 +1318,46 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
       w.up[p] = bu;
       w.dn[p] = bd;
     };
+    if constexpr (kClass == 2) {
+      if (lds) {
+        // rounds of the wave's 64 clusters: candidate lists per lane, then
+        // the wave's pairs scored by all its lanes; a lane whose lists
+        // overflow takes find_pair afterwards
+        const uint32_t wb = gt & ~63u;
+        const uint16_t* ld_w = s_ld + kCand * (threadIdx.x & ~63u);
+        const uint16_t* lu_w = s_lu + kCand * (threadIdx.x & ~63u);
+        unsigned long long* key_w = s_key + (threadIdx.x & ~63u);
+        // the prefetched clusters move down one slot per round (an array
+        // indexed by the round would be placed in scratch memory)
+        float4 m0 = mine[0], m1 = mine[1], m2 = mine[2], m3 = mine[3];
+        for (uint32_t i = 0; wb + kG * i < n; ++i) {
+          const uint32_t k = gt + kG * i;
+          const bool has = k < n;
+          float4 me = m0;
+          if (i >= (uint32_t)kOwn) me = w.gbuf[off + (has ? k : 0u)];
+          m0 = m1; m1 = m2; m2 = m3;
+          const float xi = me.z, yi = me.x, zi = me.y;
+          int cd = 0, cu = 0;
+          if (has) {
+            cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
+            cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
+          }
+          const bool fb = has && (cd > kCand || cu > kCand);
+          int32_t bu, bd;
+          wave_pairs(w, has && !fb, xi, yi, zi, (uint32_t)cd, (uint32_t)cu, (const float4*)sd, (const float4*)su,
+                     ld_w, lu_w, key_w, offd, offu, bu, bd);
+          if (fb)
+            find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
+                      (const uint16_t*)scu, bu, bd);
+          if (has) {
+            const uint32_t p = __float_as_uint(me.w);
+            w.up[p] = bu;
+            w.dn[p] = bd;
+          }
+        }
+        return;
+      }
+    }
   #pragma unroll
     for (int i = 0; i < kOwn; ++i)
       if (gt + kG * i < n) link(mine[i]);
