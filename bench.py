@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--phase-steps", type=int, default=5,
+                    help="tracking calls with phase events after the timed ones (per-phase times)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sectors", default="0,13,18",
                     help="sectors of the single-threaded oracle sample")
@@ -119,7 +121,6 @@ def main():
     for _ in range(args.warmup):
         out = trk.track(x, y, z, row, sec)
     torch.cuda.synchronize()
-    trk.set_phase_timing(True)
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,7 +128,14 @@ def main():
         out = trk.track(x, y, z, row, sec)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # per-phase times from separate calls: the library's HIP events between
+    # the phases add about 30 us to a call, so they stay out of the timed ones
+    trk.set_phase_timing(True)
+    for _ in range(args.phase_steps):
+        trk.track(x, y, z, row, sec)
+    torch.cuda.synchronize()
     phases, calls = trk.phase_times()
+    trk.set_phase_timing(False)
     ms = dt / args.steps * 1e3
     value = n / (dt / args.steps)
     n_tracks, n_hits = out.n_tracks, int(out.hit_id.numel())
@@ -389,7 +397,7 @@ Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
     rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_c3 -o c3 -- {PMC_BENCH_CMD}
     python3 bench.py --pmc-summary <out>
 
-6 tracking calls (1 warm-up + 5 timed); average duration per dispatch.  Kernel sources
+11 tracking calls (1 warm-up, 5 timed, 5 with phase events); average duration per dispatch.  Kernel sources
 sha256 `{kernel_source_hash()}`.
 
 | Kernel | Calls | Average µs | % of GPU time |
