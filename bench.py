@@ -195,7 +195,7 @@ KERNEL_SOURCES = ("paper_1712_09434_amd/csrc/tpcca_kernels.hip", "paper_1712_094
                   "paper_1712_09434_amd/csrc/calib_device.hpp", "paper_1712_09434_amd/csrc/tpcca_merge.hip",
                   "paper_1712_09434_amd/csrc/merge_internal.hpp")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tracking_c3_traffic.md")
-PMC_BENCH_CMD = ("python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-grad --no-timeframe "
+PMC_BENCH_CMD = ("python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batch --no-grad --no-timeframe "
                  "--no-its")
 
 
@@ -302,7 +302,7 @@ def pmc_summary(folder: str):
 
     Scale: a plain 1 GiB device copy reads as {big(cf):,.0f} KiB of FETCH_SIZE and {big(cw):,.0f} KiB of
     WRITE_SIZE, so fetch counts are multiplied by {sf:.4f} and write counts by {sw:.4f}.  Values are
-    means over the profiled dispatches (6 calls).
+    means over the profiled dispatches (28 calls: 3 warm-up, 20 timed, 5 with phase events).
 
     | Kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | scaled HBM MB/launch |
     |---|---|---|---|
@@ -397,7 +397,7 @@ Command (from the repository root on a machine with the GPU, `TMPDIR=/tmp`):
     rocprofv3 --kernel-trace --stats -f csv -d <out>/prof_c3 -o c3 -- {PMC_BENCH_CMD}
     python3 bench.py --pmc-summary <out>
 
-11 tracking calls (1 warm-up, 5 timed, 5 with phase events); average duration per dispatch.  Kernel sources
+28 tracking calls (3 warm-up, 20 timed, 5 with phase events); average duration per dispatch.  Kernel sources
 sha256 `{kernel_source_hash()}`.
 
 | Kernel | Calls | Average µs | % of GPU time |
