@@ -477,7 +477,9 @@ __global__ __launch_bounds__(TB) void k_mrg_hits(MergeWs w) {
 // backwards): ids are loaded eight steps ahead, coordinates four steps
 // ahead, a ring of four slots per kind (past the chain's first hit the
 // loads repeat it and are never used).  At each segment boundary the state
-// is rotated into the next inner segment's frame.
+// is rotated into the next inner segment's frame; that segment's sector and
+// hit count, and the index of the one inside it, are loaded a segment ahead,
+// so a lane crossing a boundary does not stop its wave for dependent loads.
 __global__ __launch_bounds__(64) void k_mrg_refit(MergeWs w) {
   const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (q >= (int64_t)w.err[3]) return;
@@ -489,6 +491,15 @@ __global__ __launch_bounds__(64) void k_mrg_refit(MergeWs w) {
   // segment c covers the last nc of them
   const int32_t n = (int32_t)(w.hemit[i + 1] - w.hemit[i]);
   int32_t seg_lo = n - (w.hit_off[c + 1] - w.hit_off[c]);
+  // the current segment's sector; the next inner segment (na), its sector and
+  // hit count, and the segment inside it (nna); past the chain's innermost
+  // segment the loads repeat the current one and are never used
+  int sec_c = w.sector[c];
+  int32_t na = w.inner[c];
+  int32_t sa = na >= 0 ? na : c;
+  int sec_a = w.sector[sa];
+  int32_t len_a = w.hit_off[sa + 1] - w.hit_off[sa];
+  int32_t nna = w.inner[sa];
   const Model& m = w.m;
   auto X = [&](uint32_t id) { return make_float4(w.cx[id], w.cy[id], w.cz[id], 0.0f); };
   const float4 r0 = X(ids[n - 1]), r2 = X(ids[n - 3]);
@@ -509,12 +520,17 @@ __global__ __launch_bounds__(64) void k_mrg_refit(MergeWs w) {
       if (k < seg_lo) {
         // entering the next inner segment (its frame, unless it lies in the
         // same sector: a neighbouring slice of a time frame)
-        const int32_t a = w.inner[c];
-        const int wc = w.sector[c] % w.NW, wa = w.sector[a] % w.NW;
-        if (w.sector[a] != w.sector[c] && !rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m))
+        const int wc = sec_c % w.NW, wa = sec_a % w.NW;
+        if (sec_a != sec_c && !rotate_state(xc, p, C, w.ca, turn_sign(wc, wa, w.NW) * w.sa, m))
           ok = false;
-        c = a;
-        seg_lo -= w.hit_off[c + 1] - w.hit_off[c];
+        c = na;
+        sec_c = sec_a;
+        seg_lo -= len_a;
+        na = nna;
+        sa = na >= 0 ? na : c;
+        sec_a = w.sector[sa];
+        len_a = w.hit_off[sa + 1] - w.hit_off[sa];
+        nna = w.inner[sa];
       }
       if (ok && !transport(p, C, xc, cs.x, m)) ok = false;
       if (ok) {
