@@ -569,17 +569,11 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     const float dl = c.dl[s];
     const int a = l >> 3, b = l & 7;
     // this lane's basis product at each hit from the four non-zero values
-    // of each direction stored per hit (the same floats as the full basis);
-    // the hit's records are the same for every lane of the track and are
-    // all read before any is used, the sums take their terms by selects
-    // component k of v (0 outside 0..3) as a sum of products with 0 / 1:
-    // exact for the finite, non-negative basis values, and every component
-    // is read, so the record's loads are not split across branches
-    auto pick = [](const float4& v, int k) {
-      const float e0 = k == 0 ? 1.f : 0.f, e1 = k == 1 ? 1.f : 0.f;
-      const float e2 = k == 2 ? 1.f : 0.f, e3 = k == 3 ? 1.f : 0.f;
-      return ((e0 * v.x + e1 * v.y) + e2 * v.z) + e3 * v.w;
-    };
+    // of each direction stored per hit (the same floats as the full basis):
+    // each lane loads its own component of the hit's two records (0 where
+    // its coefficient lies outside the hit's support; such lanes load the
+    // first component, all lanes then read one cache line), the hit's other
+    // values are the same for every lane of the track
     const float kd = l == 0 ? -side : side * (1.0f + dl);
     // basis product at hit i+1 (the next hit outward), carried down the loop
     float w_next = 0.f;
@@ -587,9 +581,12 @@ __host__ __device__ inline void partials_lane(const CalWs& c, int64_t t, int l) 
     for (int i = nh - 1; i >= 0; --i) {
       const int64_t j = b0 + i;
       const int32_t sp = c.bsp[j];
-      const float4 va = c.bva[j], vb = c.bvb[j];
+      const int ka = a - (sp & 0xFF), kb = b - ((sp >> 8) & 0xFF);
+      const bool ina = (unsigned)ka < 4u, inb = (unsigned)kb < 4u;
+      const float xa = ((const float*)(c.bva + j))[ina ? ka : 0];
+      const float xb = ((const float*)(c.bvb + j))[inb ? kb : 0];
       const float gxj = c.gx[j], gpj = c.gpt[j], gzj = c.gz[j], dz = c.dzt[j];
-      const float wj = pick(va, a - (sp & 0xFF)) * pick(vb, b - ((sp >> 8) & 0xFF));
+      const float wj = (ina ? xa : 0.0f) * (inb ? xb : 0.0f);
       // drift scale (lane 0) and time offset (lane 1), valid hits only
       const float td = l == 0 ? dz : 1.0f;
       if (l < 2 && (sp >> 16) != 0) accd += gzj * (kd * td);
