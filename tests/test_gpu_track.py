@@ -300,8 +300,8 @@ def _with_patches(ev, patches, seed):
 def test_dense_rows_take_the_fallback_paths(tracker, orc):
     """Rows above the register-sort size (1024), above the neighbour slab
     (896), a 4-row band above the LDS ownership capacity (6144), and windows
-    with more than 16 candidates per side in an LDS-staged row: every
-    fallback path still matches the oracle."""
+    with more than the 15 kept candidates per side in an LDS-staged row:
+    every fallback path still matches the oracle."""
     ev = synth.make_event(seed=31, n_primaries=150, noise=0.01, single_sector=True)
     patches = [(r, 1600, (-10.0, 10.0), (40.0, 120.0)) for r in (40, 41, 42, 43)]
     patches += [(r, 650, (-6.0, 6.0), (150.0, 180.0)) for r in (80, 81, 82)]
@@ -312,6 +312,45 @@ def test_dense_rows_take_the_fallback_paths(tracker, orc):
     ref = orc.track(ev, precision=32)
     compare(ev, out, tl, ref)
     assert out.n_tracks > 0
+
+
+def test_lattice_ties_in_slab_rows(tracker, orc):
+    """Rows of 300 to 800 clusters (the 896-cluster slab variant of the link
+    kernel, which scores a wave's candidate pairs with all of its lanes) on
+    a 0.5 cm lattice, a fifth of each row duplicating other clusters of the
+    row: equal scores from different pairs are common, and the tie rule
+    (smaller up position, then smaller down position) decides.  Links and
+    everything after them equal the oracle."""
+    import dataclasses
+    ev = synth.make_event(seed=33, n_primaries=60, noise=0.0, single_sector=True)
+    rng = np.random.default_rng(34)
+    xs, ys, zs, rows = [ev.x], [ev.y], [ev.z], [ev.row]
+    for r, n in ((60, 500), (61, 700), (62, 600), (63, 800), (64, 300)):
+        y = (rng.integers(-20, 21, n) * 0.5).astype(np.float32)
+        z = (rng.integers(40, 241, n) * 0.5).astype(np.float32)
+        src = rng.integers(n // 5, n, n // 5)
+        y[: n // 5] = y[src]
+        z[: n // 5] = z[src]
+        xs.append(np.full(n, ev.geom.row_x[r], np.float32))
+        ys.append(y)
+        zs.append(z)
+        rows.append(np.full(n, r, np.int16))
+    extra = sum(len(a) for a in rows[1:])
+    cat = np.concatenate
+    ev = dataclasses.replace(
+        ev, x=cat(xs), y=cat(ys), z=cat(zs), row=cat(rows), sector=cat([ev.sector, np.zeros(extra, np.uint8)]),
+        x64=cat(xs).astype(np.float64), y64=cat(ys).astype(np.float64), z64=cat(zs).astype(np.float64),
+        truth_track=cat([ev.truth_track, np.full(extra, -1, np.int32)]),
+        truth_double=cat([ev.truth_double, np.zeros(extra, bool)]))
+    print(f"[gpu] lattice rows n={ev.n}", flush=True)
+    out = tracker.track(*to_dev(ev), taps=True)
+    tl = tracker.debug_tracklets()
+    ref = orc.track(ev, precision=32)
+    compare(ev, out, tl, ref)
+    # the patch rows' links are many, so the pair scoring ran on them
+    up = out.taps["up"].cpu().numpy()
+    patch = (ev.sector == 0) & (ev.row >= 61) & (ev.row <= 63)
+    assert (up[patch] >= 0).sum() > 500
 
 
 def test_batch_with_dense_rows_equals_single_events(tracker):
