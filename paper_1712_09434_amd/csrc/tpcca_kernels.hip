@@ -1014,15 +1014,12 @@ __device__ __forceinline__ int collect(const GridParams& G, F4 D4, U32 Dc, float
   return n <= kCand ? n : kCand + 1;
 }
 
-// Pairs from the two candidate lists, same arithmetic and tie-break as
-// find_pair.  With kRegU the up candidates are read into registers once
-// (kCand slots), so the pair loop touches LDS only for the down candidates;
-// without it (the one-wave and small-slab variants, which gain occupancy
-// from the freed registers) every pair reads its up candidate from LDS.
-// The interpolation weight depends only on the two x coordinates, so the
-// quotient of the previous pair is reused when they repeat (clusters on
-// their row planes).
-template <bool kRegU, class F4>
+// Pairs of one lane's two candidate lists, same arithmetic and tie-break as
+// find_pair (the one-wave and small-slab variants; every pair reads its up
+// candidate from LDS).  The interpolation weight depends only on the two x
+// coordinates, so the quotient of the previous pair is reused when they
+// repeat (clusters on their row planes).
+template <class F4>
 __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float zi, F4 D4, const uint16_t* ld,
                                           int nd, F4 U4, const uint16_t* lu, int nu, int32_t& bu,
                                           int32_t& bd) {
@@ -1037,66 +1034,21 @@ __device__ __forceinline__ void best_pair(const Ws& w, float xi, float yi, float
   auto take = [&](float score, int32_t pu, int32_t pd) {
     if (score < bs || (score == bs && (pu < ku || (pu == ku && pd < kd)))) { bs = score; ku = pu; kd = pd; }
   };
-  // the interpolation quotient (xi - xd)/(xu - xd) only changes with the x
-  // coordinates: when all up candidates share one x it is taken once per
-  // down x, else per pair whenever either x differs from the last quotient's
+  // the last quotient and the x coordinates it was taken for
   float wx_d = 0.0f, wx_u = 0.0f, wq = 0.0f;
   bool wk = false;
-  if constexpr (kRegU) {
-    uint32_t ui[kCand];
-#pragma unroll
-    for (int j = 0; j < kCand; ++j) ui[j] = j < nu ? lu[j] : 0u;
-    float4 U[kCand];
-#pragma unroll
-    for (int j = 0; j < kCand; ++j)
-      if (j < nu) U[j] = U4[ui[j]];
-    bool same_xu = true;
-#pragma unroll
-    for (int j = 1; j < kCand; ++j)
-      if (j < nu && U[j].z != U[0].z) same_xu = false;
-    for (int i = 0; i < nd; ++i) {
-      const float4 D = D4[ld[i]];
-      const int32_t pd = (int32_t)__float_as_uint(D.w);
-      if (same_xu) {
-        if (!(wk && D.z == wx_d)) {
-          wq = (xi - D.z) / (U[0].z - D.z);
-          wx_d = D.z; wx_u = U[0].z; wk = true;
-        }
-#pragma unroll
-        for (int j = 0; j < kCand; ++j) {
-          if (j >= nu) continue;
-          const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
-          const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
-          take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < kCand; ++j) {
-          if (j >= nu) continue;
-          if (!(wk && D.z == wx_d && U[j].z == wx_u)) {
-            wq = (xi - D.z) / (U[j].z - D.z);
-            wx_d = D.z; wx_u = U[j].z; wk = true;
-          }
-          const float ey = yi - fmaf(U[j].x - D.x, wq, D.x);
-          const float ez = zi - fmaf(U[j].y - D.y, wq, D.y);
-          take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U[j].w), pd);
-        }
+  for (int i = 0; i < nd; ++i) {
+    const float4 D = D4[ld[i]];
+    const int32_t pd = (int32_t)__float_as_uint(D.w);
+    for (int j = 0; j < nu; ++j) {
+      const float4 U = U4[lu[j]];
+      if (!(wk && D.z == wx_d && U.z == wx_u)) {
+        wq = (xi - D.z) / (U.z - D.z);
+        wx_d = D.z; wx_u = U.z; wk = true;
       }
-    }
-  } else {
-    for (int i = 0; i < nd; ++i) {
-      const float4 D = D4[ld[i]];
-      const int32_t pd = (int32_t)__float_as_uint(D.w);
-      for (int j = 0; j < nu; ++j) {
-        const float4 U = U4[lu[j]];
-        if (!(wk && D.z == wx_d && U.z == wx_u)) {
-          wq = (xi - D.z) / (U.z - D.z);
-          wx_d = D.z; wx_u = U.z; wk = true;
-        }
-        const float ey = yi - fmaf(U.x - D.x, wq, D.x);
-        const float ez = zi - fmaf(U.y - D.y, wq, D.y);
-        take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U.w), pd);
-      }
+      const float ey = yi - fmaf(U.x - D.x, wq, D.x);
+      const float ez = zi - fmaf(U.y - D.y, wq, D.y);
+      take(fmaf(ez * ez, IWZ, (ey * ey) * IWY), (int32_t)__float_as_uint(U.w), pd);
     }
   }
   if (ku != INT32_MAX) { bu = ku; bd = kd; }
@@ -1209,9 +1161,11 @@ __device__ __forceinline__ void wave_pairs(const Ws& w, bool has, float xi, floa
 // offsets) are staged in LDS when each holds at most kSlab clusters.  Lanes
 // take the row's clusters in grid (cell) order, so the lanes of a wave are
 // spatial neighbours with similar candidate counts.  A lane first collects
-// the down and up candidates inside the windows (two flat scans), then
-// scores the pairs; nested scanning would make a wave run the product of its
-// lanes' largest candidate counts.  Results do not depend on the order.
+// the down and up candidates inside the windows (two flat scans), then the
+// pairs are scored: by the lane itself in the two smaller variants, by all
+// lanes of the wave in the slab variant (wave_pairs); nested scanning would
+// make a wave run the product of its lanes' largest candidate counts.
+// Results do not depend on the order.
 //
 // Three instantiations by the size of the neighbour rows: up to kTiny
 // clusters (one wave per row unit, four per workgroup, wave-level ordering),
@@ -1307,7 +1261,7 @@ __global__ __launch_bounds__(TB) void k_links(Ws w) {
         const int cd = collect(Gd, (const float4*)sd, (const uint16_t*)scd, yi, zi, WY, WZ, ld);
         const int cu = cd > 0 ? collect(Gu, (const float4*)su, (const uint16_t*)scu, yi, zi, WY, WZ, lu) : 0;
         if (cd <= kCand && cu <= kCand)
-          best_pair<kClass == 2>(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
+          best_pair(w, xi, yi, zi, (const float4*)sd, ld, cd, (const float4*)su, lu, cu, bu, bd);
         else
           find_pair(w, xi, yi, zi, Gd, (const float4*)sd, (const uint16_t*)scd, Gu, (const float4*)su,
                     (const uint16_t*)scu, bu, bd);
