@@ -190,10 +190,14 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+# every file holding kernels of the profiled workloads (tracking, merger,
+# calibration gradient, time frame, ITS)
 KERNEL_SOURCES = ("paper_1712_09434_amd/csrc/tpcca_kernels.hip", "paper_1712_09434_amd/csrc/kf_device.hpp",
                   "paper_1712_09434_amd/csrc/internal.hpp", "paper_1712_09434_amd/csrc/kf_c2.hpp",
                   "paper_1712_09434_amd/csrc/calib_device.hpp", "paper_1712_09434_amd/csrc/tpcca_merge.hip",
-                  "paper_1712_09434_amd/csrc/merge_internal.hpp")
+                  "paper_1712_09434_amd/csrc/merge_internal.hpp", "paper_1712_09434_amd/csrc/tpcca_calib.hip",
+                  "paper_1712_09434_amd/csrc/calib_internal.hpp", "paper_1712_09434_amd/csrc/tpcca_timeframe.hip",
+                  "paper_1712_09434_amd/csrc/timeframe_internal.hpp", "paper_1712_09434_amd/csrc/tpcca_its.hip")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tracking_c3_traffic.md")
 PMC_BENCH_CMD = ("python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --no-batch --no-grad --no-timeframe "
                  "--no-its")
